@@ -1,0 +1,932 @@
+/*
+ * ora.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY; see ora.h).
+ *
+ * What it computes, in the paper's order (Wang, Tian & Lai, Sec. 2):
+ *   1. the conservative compressible NS system dQ/dt + div(F,G,H) - div(F_v,G_v,H_v) = S
+ *      (Sec. 2, Eqs. (2)-(6)) with the ideal-gas closure p = (gamma-1)(E - rho|u|^2/2);
+ *   2. convective terms by conservative point-value finite differences with global
+ *      Lax-Friedrichs flux splitting and fifth-order reconstruction: WENO5-JS (Jiang & Shu
+ *      1996) or TENO5 (Fu, Hu & Adams 2016), the two schemes Sec. 2 names;
+ *   3. viscous terms by the fourth-order central difference applied twice
+ *      (velocity gradients at cells, then the divergence of the stress), no heat flux
+ *      (Sec. 2, Eq. (5)-(6): b = u . tau);
+ *   4. the penalty immersed boundary: interpolation of velocity to the markers (Eq. (8)),
+ *      the feedback force F_f = alpha int(U_ib - U) dt + beta (U_ib - U) (Eq. (7)), and
+ *      spreading of -F_f to the grid (Eq. (9)) with the tensor-product four-point
+ *      delta function (Eqs. (10)-(11));
+ *   5. a cubic sponge toward the far-field state;
+ *   6. the third-order TVD (SSP) Runge-Kutta update (Shu & Osher 1988, cited in Sec. 2),
+ *      the penalty integral advancing in lockstep with Q.
+ *
+ * The code is written to be read against the paper, not to be fast: every face flux is
+ * computed from the six cells around it, every stress from the velocities around it.
+ * Built with -O2 -fno-fast-math -ffp-contract=off; OpenMP only over loops with disjoint
+ * writes; every sum runs in a fixed order.
+ */
+#include "ora.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+struct ora_ctx {
+    ora_desc d;
+    int nq;            /* dim + 2 conserved components */
+    long nx, ny, nz;
+    long ncell;
+    double q_inf[5];   /* far-field conserved state */
+    /* markers */
+    int nm;
+    double* X;         /* [dim][nm] */
+    double* dV;        /* [nm] */
+    double* U;         /* [dim][nm] */
+    int motion;
+    double omega;
+    double* xi;        /* penalty integral [dim][nm] */
+    double* F;         /* penalty force of the last right-hand side [dim][nm] */
+    double* dxi;       /* U_ib - U of the last right-hand side [dim][nm] */
+    /* probes */
+    int np;
+    double* Xp;
+    double t;
+    int64_t step;
+};
+
+/* ------------------------------------------------------------------------------------ */
+/* Small helpers                                                                          */
+/* ------------------------------------------------------------------------------------ */
+
+static long cell_index(const ora_ctx* c, long i, long j, long k) { return (k * c->ny + j) * c->nx + i; }
+
+static long n_of(const ora_ctx* c, int d) { return d == 0 ? c->nx : (d == 1 ? c->ny : c->nz); }
+
+uint64_t ora_splitmix64(uint64_t seed, uint64_t ctr)
+{
+    /* Steele, Lea & Flood (2014) SplitMix64: the state advances by the golden-ratio
+     * increment, output number ctr is the finaliser applied to seed + (ctr+1) * increment. */
+    uint64_t z = seed + (ctr + 1u) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Uniform value in [0,1) from the top 53 bits. */
+static double unit_uniform(uint64_t r) { return (double)(r >> 11) * (1.0 / 9007199254740992.0); }
+
+/* Far-field primitive state (rho, u_1..u_dim, p) -> conserved state. */
+static void prim_to_cons(const ora_ctx* c, double rho, const double* u, double p, double* q)
+{
+    int dim = c->d.dim;
+    double ke = 0.0;
+    q[0] = rho;
+    for (int a = 0; a < dim; ++a) {
+        q[1 + a] = rho * u[a];
+        ke += u[a] * u[a];
+    }
+    q[dim + 1] = p / (c->d.gamma - 1.0) + 0.5 * rho * ke;
+}
+
+/* Ideal-gas primitives of a conserved state: velocity u_a = m_a / rho, pressure
+ * p = (gamma - 1)(E - 1/2 sum_a m_a u_a). */
+static void primitives(const ora_ctx* c, const double* q, double* u, double* p)
+{
+    int dim = c->d.dim;
+    double rho = q[0];
+    double ke = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        u[a] = q[1 + a] / rho;
+        ke += q[1 + a] * u[a];
+    }
+    *p = (c->d.gamma - 1.0) * (q[dim + 1] - 0.5 * ke);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Boundary handling: the state at any (possibly out-of-range) cell index                */
+/* ------------------------------------------------------------------------------------ */
+
+/* Out-of-range indices are resolved direction by direction (x, then y, then z):
+ * PERIODIC wraps, EXTRAP takes the nearest interior cell, INFLOW also clamps but marks the
+ * cell as an inflow ghost.  An inflow ghost holds the far-field state with each velocity
+ * component perturbed by inflow_amp * (2 r - 1), r uniform from SplitMix64 at counter
+ * ((((step * 6 + side) * 8 + depth) * ncell + cell) * 3 + component), where side = 2 d + s
+ * and depth >= 1 are those of the first inflow direction and cell is the clamped index. */
+static void fetch(const ora_ctx* c, const double* Q, long i, long j, long k, double* q)
+{
+    long idx[3] = {i, j, k};
+    int inflow = 0, side = 0;
+    long depth = 0;
+    for (int d = 0; d < c->d.dim; ++d) {
+        long n = n_of(c, d);
+        if (idx[d] < 0) {
+            int bc = c->d.bc[d][0];
+            long g = -idx[d];
+            if (bc == ORA_BC_PERIODIC) {
+                idx[d] = ((idx[d] % n) + n) % n;
+            } else {
+                idx[d] = 0;
+                if (bc == ORA_BC_INFLOW && !inflow) { inflow = 1; side = 2 * d; depth = g; }
+            }
+        } else if (idx[d] >= n) {
+            int bc = c->d.bc[d][1];
+            long g = idx[d] - n + 1;
+            if (bc == ORA_BC_PERIODIC) {
+                idx[d] = idx[d] % n;
+            } else {
+                idx[d] = n - 1;
+                if (bc == ORA_BC_INFLOW && !inflow) { inflow = 1; side = 2 * d + 1; depth = g; }
+            }
+        }
+    }
+    long lin = cell_index(c, idx[0], idx[1], idx[2]);
+    if (!inflow) {
+        for (int m = 0; m < c->nq; ++m) q[m] = Q[(long)m * c->ncell + lin];
+        return;
+    }
+    double u[3];
+    for (int a = 0; a < c->d.dim; ++a) {
+        u[a] = c->d.prim_inf[1 + a];
+        if (c->d.inflow_amp != 0.0) {
+            uint64_t ctr = ((((uint64_t)c->step * 6u + (uint64_t)side) * 8u + (uint64_t)depth)
+                                * (uint64_t)c->ncell + (uint64_t)lin) * 3u + (uint64_t)a;
+            double r = unit_uniform(ora_splitmix64(c->d.seed, ctr));
+            u[a] += c->d.inflow_amp * (2.0 * r - 1.0);
+        }
+    }
+    prim_to_cons(c, c->d.prim_inf[0], u, c->d.prim_inf[4], q);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Global Lax-Friedrichs wave speeds                                                      */
+/* ------------------------------------------------------------------------------------ */
+
+/* max that keeps a NaN once one has been seen */
+static double nan_max(double m, double v)
+{
+    if (isnan(m)) return m;
+    if (isnan(v)) return v;
+    return v > m ? v : m;
+}
+
+int ora_alpha(const ora_ctx* c, const double* Q, double* alpha)
+{
+    int dim = c->d.dim;
+    double amax[3] = {0.0, 0.0, 0.0};
+    for (long n = 0; n < c->ncell; ++n) {
+        double q[5], u[3], p;
+        for (int m = 0; m < c->nq; ++m) q[m] = Q[(long)m * c->ncell + n];
+        primitives(c, q, u, &p);
+        double snd = sqrt(c->d.gamma * p / q[0]);
+        for (int a = 0; a < dim; ++a) amax[a] = nan_max(amax[a], fabs(u[a]) + snd);
+    }
+    for (int a = 0; a < 3; ++a) alpha[a] = a < dim ? amax[a] : 0.0;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Fifth-order reconstruction                                                             */
+/* ------------------------------------------------------------------------------------ */
+
+/* Three third-order candidate values at the face from the five upwind-ordered values
+ * (a,b,cc,d,e) = (v_{i-2}, v_{i-1}, v_i, v_{i+1}, v_{i+2}), and their Jiang-Shu smoothness
+ * indicators. */
+static void candidates(double a, double b, double cc, double d, double e, double q[3], double beta[3])
+{
+    q[0] = (2.0 * a - 7.0 * b + 11.0 * cc) / 6.0;
+    q[1] = (-b + 5.0 * cc + 2.0 * d) / 6.0;
+    q[2] = (2.0 * cc + 5.0 * d - e) / 6.0;
+    double s0 = a - 2.0 * b + cc, t0 = a - 4.0 * b + 3.0 * cc;
+    double s1 = b - 2.0 * cc + d, t1 = b - d;
+    double s2 = cc - 2.0 * d + e, t2 = 3.0 * cc - 4.0 * d + e;
+    beta[0] = 13.0 / 12.0 * s0 * s0 + 0.25 * t0 * t0;
+    beta[1] = 13.0 / 12.0 * s1 * s1 + 0.25 * t1 * t1;
+    beta[2] = 13.0 / 12.0 * s2 * s2 + 0.25 * t2 * t2;
+}
+
+static const double lin_w[3] = {0.1, 0.6, 0.3}; /* optimal linear weights d_k */
+
+/* TENO5 sharp cut-off: gamma_k = (C + tau5 / (beta_k + eps))^q with C = 1, q = 6,
+ * tau5 = |beta_0 - beta_2|; chi_k = gamma_k / sum gamma; sub-stencil k is kept unless
+ * chi_k < C_T. */
+static int teno_keep(const double beta[3], double ct, double eps)
+{
+    double tau = fabs(beta[0] - beta[2]);
+    double g[3], sum = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double x = 1.0 + tau / (beta[k] + eps);
+        double x3 = x * x * x;
+        g[k] = x3 * x3;
+        sum += g[k];
+    }
+    int flags = 0;
+    for (int k = 0; k < 3; ++k) {
+        double chi = g[k] / sum;
+        if (!(chi < ct)) flags |= 1 << k;
+    }
+    return flags;
+}
+
+int ora_teno_flags(double a, double b, double cc, double d, double e, double teno_ct, double teno_eps)
+{
+    double q[3], beta[3];
+    candidates(a, b, cc, d, e, q, beta);
+    return teno_keep(beta, teno_ct, teno_eps);
+}
+
+double ora_recon5(double a, double b, double cc, double d, double e, int scheme,
+                  double weno_eps, double teno_ct, double teno_eps)
+{
+    double q[3], beta[3], w[3];
+    candidates(a, b, cc, d, e, q, beta);
+    if (scheme == ORA_WENO5JS) {
+        double al[3], sum = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double s = weno_eps + beta[k];
+            al[k] = lin_w[k] / (s * s);
+            sum += al[k];
+        }
+        for (int k = 0; k < 3; ++k) w[k] = al[k] / sum;
+    } else {
+        int flags = teno_keep(beta, teno_ct, teno_eps);
+        double dd[3], sum = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            dd[k] = ((flags >> k) & 1) ? lin_w[k] : 0.0;
+            sum += dd[k];
+        }
+        for (int k = 0; k < 3; ++k) w[k] = dd[k] / sum;
+    }
+    return w[0] * q[0] + w[1] * q[1] + w[2] * q[2];
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Convective flux with global Lax-Friedrichs splitting                                   */
+/* ------------------------------------------------------------------------------------ */
+
+/* Physical flux along direction dir (Sec. 2, Eqs. (3)-(4)):
+ * [m_dir, m_a u_dir + p delta_{a,dir}, (E + p) u_dir]. */
+static void phys_flux(const ora_ctx* c, const double* q, int dir, double* f)
+{
+    int dim = c->d.dim;
+    double u[3], p;
+    primitives(c, q, u, &p);
+    f[0] = q[1 + dir];
+    for (int a = 0; a < dim; ++a) f[1 + a] = q[1 + a] * u[dir] + (a == dir ? p : 0.0);
+    f[dim + 1] = (q[dim + 1] + p) * u[dir];
+}
+
+/* Numerical flux at the face between cell idx and idx + e_dir:
+ * F_hat = rec+(f+_{i-2..i+2}) + rec-(f-_{i+3..i-1}), f+- = (F +- alpha Q)/2. */
+static void face_flux(const ora_ctx* c, const double* Q, int dir, const long* idx, double alpha, double* Fh)
+{
+    int nq = c->nq;
+    double fp[6][5], fm[6][5];
+    for (int s = 0; s < 6; ++s) {
+        long id[3] = {idx[0], idx[1], idx[2]};
+        id[dir] += s - 2;
+        double q[5], f[5];
+        fetch(c, Q, id[0], id[1], id[2], q);
+        phys_flux(c, q, dir, f);
+        for (int m = 0; m < nq; ++m) {
+            fp[s][m] = 0.5 * (f[m] + alpha * q[m]);
+            fm[s][m] = 0.5 * (f[m] - alpha * q[m]);
+        }
+    }
+    const ora_desc* dd = &c->d;
+    for (int m = 0; m < nq; ++m) {
+        double plus = ora_recon5(fp[0][m], fp[1][m], fp[2][m], fp[3][m], fp[4][m], dd->scheme,
+                                 dd->weno_eps, dd->teno_ct, dd->teno_eps);
+        double minus = ora_recon5(fm[5][m], fm[4][m], fm[3][m], fm[2][m], fm[1][m], dd->scheme,
+                                  dd->weno_eps, dd->teno_ct, dd->teno_eps);
+        Fh[m] = plus + minus;
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Viscous terms                                                                          */
+/* ------------------------------------------------------------------------------------ */
+
+/* Fourth-order central first derivative on the cell values g_{i-2..i+2} (g[0..4]). */
+static double d1c4(const double* g, double h)
+{
+    return (8.0 * (g[3] - g[1]) - (g[4] - g[0])) / (12.0 * h);
+}
+
+static void velocity_at(const ora_ctx* c, const double* Q, const long* idx, double* u)
+{
+    double q[5], p;
+    fetch(c, Q, idx[0], idx[1], idx[2], q);
+    primitives(c, q, u, &p);
+}
+
+/* Stress tau_ab = mu (G_ab + G_ba - 2/3 delta_ab div u) with G_ab = D_b u_a, and the
+ * viscous work b_a = sum_b u_b tau_ab (Sec. 2, Eqs. (5)-(6); no heat flux). */
+static void stress_at(const ora_ctx* c, const double* Q, const long* idx, double tau[3][3], double* bw)
+{
+    int dim = c->d.dim;
+    double G[3][3], u0[3];
+    velocity_at(c, Q, idx, u0);
+    for (int b = 0; b < dim; ++b) {
+        double ub[5][3];
+        for (int s = 0; s < 5; ++s) {
+            long id[3] = {idx[0], idx[1], idx[2]};
+            id[b] += s - 2;
+            velocity_at(c, Q, id, ub[s]);
+        }
+        for (int a = 0; a < dim; ++a) {
+            double g[5];
+            for (int s = 0; s < 5; ++s) g[s] = ub[s][a];
+            G[a][b] = d1c4(g, c->d.h);
+        }
+    }
+    double div = 0.0;
+    for (int a = 0; a < dim; ++a) div += G[a][a];
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) {
+            double t = G[a][b] + G[b][a];
+            if (a == b) t -= 2.0 / 3.0 * div;
+            tau[a][b] = c->d.mu * t;
+        }
+    for (int a = 0; a < dim; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < dim; ++b) s += u0[b] * tau[a][b];
+        bw[a] = s;
+    }
+}
+
+/* Viscous term at one cell from the stresses of the cells around it:
+ * momentum a: sum_b D_b tau_ab; energy: sum_b D_b b_b.  tau_nb[b][s] holds the stress at
+ * idx + (s-2) e_b. */
+static void visc_from_stresses(const ora_ctx* c, double tau_nb[3][5][3][3], double bw_nb[3][5][3], double* out)
+{
+    int dim = c->d.dim;
+    out[0] = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < dim; ++b) {
+            double g[5];
+            for (int m = 0; m < 5; ++m) g[m] = tau_nb[b][m][a][b];
+            s += d1c4(g, c->d.h);
+        }
+        out[1 + a] = s;
+    }
+    double e = 0.0;
+    for (int b = 0; b < dim; ++b) {
+        double g[5];
+        for (int m = 0; m < 5; ++m) g[m] = bw_nb[b][m][b];
+        e += d1c4(g, c->d.h);
+    }
+    out[dim + 1] = e;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Immersed boundary                                                                      */
+/* ------------------------------------------------------------------------------------ */
+
+/* Peskin's four-point function lambda(r) (Sec. 2, Eq. (11)). */
+double ora_delta4(double r)
+{
+    double x = fabs(r);
+    if (x < 1.0) return 0.125 * (3.0 - 2.0 * x + sqrt(1.0 + 4.0 * x - 4.0 * x * x));
+    if (x < 2.0) return 0.125 * (5.0 - 2.0 * x - sqrt(-7.0 + 12.0 * x - 4.0 * x * x));
+    return 0.0;
+}
+
+/* Support of the tensor-product delta at position X (Sec. 2, Eq. (10)) in direction d:
+ * the four cells j0 .. j0+3 around X and their one-dimensional weights lambda((X - x_j)/h). */
+static void support_1d(const ora_ctx* c, int d, double X, long* j0, double* w)
+{
+    double r0 = (X - c->d.lo[d]) / c->d.h - 0.5; /* X in cell-index units */
+    long j = (long)floor(r0) - 1;
+    *j0 = j;
+    for (int m = 0; m < 4; ++m) w[m] = ora_delta4(r0 - (double)(j + m));
+}
+
+/* Check that every point's four-point support lies inside the grid. */
+static int supports_inside(const ora_ctx* c, int n, const double* X)
+{
+    for (int k = 0; k < n; ++k)
+        for (int d = 0; d < c->d.dim; ++d) {
+            long j0;
+            double w[4];
+            double x = X[(long)d * n + k];
+            if (!isfinite(x)) return 0;
+            support_1d(c, d, x, &j0, w);
+            if (j0 < 0 || j0 + 3 >= n_of(c, d)) return 0;
+        }
+    return 1;
+}
+
+/* Loop helper over the 4^dim support of point k of a point set: weight W = w_x w_y (w_z),
+ * visited in z-major, x-fastest order. */
+typedef struct {
+    long j0[3];
+    double w[3][4];
+} support_t;
+
+static void support_of(const ora_ctx* c, const double* X, int n, int k, support_t* s)
+{
+    for (int d = 0; d < 3; ++d) {
+        if (d < c->d.dim) {
+            support_1d(c, d, X[(long)d * n + k], &s->j0[d], s->w[d]);
+        } else {
+            s->j0[d] = 0;
+            s->w[d][0] = 1.0;
+            s->w[d][1] = s->w[d][2] = s->w[d][3] = 0.0;
+        }
+    }
+}
+
+/* Interpolation U_ib(X_k) = sum over the support of u(x) lambda lambda (lambda), the
+ * discrete form of Eq. (8) with h^dim delta_h = prod lambda. */
+static void interp_point(const ora_ctx* c, const support_t* s, const double* field, int ncomp, double* out)
+{
+    int mzn = c->d.dim == 3 ? 4 : 1;
+    for (int a = 0; a < ncomp; ++a) out[a] = 0.0;
+    for (int mz = 0; mz < mzn; ++mz)
+        for (int my = 0; my < 4; ++my)
+            for (int mx = 0; mx < 4; ++mx) {
+                double W = s->w[0][mx] * s->w[1][my];
+                if (c->d.dim == 3) W = W * s->w[2][mz];
+                long lin = cell_index(c, s->j0[0] + mx, s->j0[1] + my, s->j0[2] + mz);
+                for (int a = 0; a < ncomp; ++a) out[a] += field[(long)a * c->ncell + lin] * W;
+            }
+}
+
+int ora_ib_interp(const ora_ctx* c, const double* field, int ncomp, double* out)
+{
+    if (ncomp < 1) return -1;
+    for (int k = 0; k < c->nm; ++k) {
+        support_t s;
+        double v[8];
+        support_of(c, c->X, c->nm, k, &s);
+        interp_point(c, &s, field, ncomp, v);
+        for (int a = 0; a < ncomp && a < 8; ++a) out[(long)a * c->nm + k] = v[a];
+    }
+    return 0;
+}
+
+/* Spreading f(x) = - sum_k F_k prod lambda dV_k / h^dim (Eq. (9)); contributions are added
+ * to each cell in marker order. */
+static void spread_add(const ora_ctx* c, const double* F, int ncomp, double* field, double scale)
+{
+    double hd = c->d.dim == 3 ? c->d.h * c->d.h * c->d.h : c->d.h * c->d.h;
+    int mzn = c->d.dim == 3 ? 4 : 1;
+    for (int k = 0; k < c->nm; ++k) {
+        support_t s;
+        support_of(c, c->X, c->nm, k, &s);
+        for (int mz = 0; mz < mzn; ++mz)
+            for (int my = 0; my < 4; ++my)
+                for (int mx = 0; mx < 4; ++mx) {
+                    double W = s.w[0][mx] * s.w[1][my];
+                    if (c->d.dim == 3) W = W * s.w[2][mz];
+                    long lin = cell_index(c, s.j0[0] + mx, s.j0[1] + my, s.j0[2] + mz);
+                    for (int a = 0; a < ncomp; ++a) {
+                        double fk = -(F[(long)a * c->nm + k] * W * c->dV[k]) / hd;
+                        field[(long)a * c->ncell + lin] += scale * fk;
+                    }
+                }
+    }
+}
+
+int ora_ib_spread(const ora_ctx* c, const double* F, int ncomp, double* field, double scale)
+{
+    if (ncomp < 1) return -1;
+    spread_add(c, F, ncomp, field, scale);
+    return 0;
+}
+
+/* Marker velocity at time t: STATIC and EXTERNAL markers carry the stored U; ROTATING
+ * markers U = omega e_z x X. */
+static void marker_velocity(const ora_ctx* c, int k, double t, double* U)
+{
+    (void)t;
+    int dim = c->d.dim;
+    if (c->motion == ORA_ROTATING) {
+        double x = c->X[k], y = c->X[(long)c->nm + k];
+        U[0] = -c->omega * y;
+        U[1] = c->omega * x;
+        if (dim == 3) U[2] = 0.0;
+    } else {
+        for (int a = 0; a < dim; ++a) U[a] = c->U[(long)a * c->nm + k];
+    }
+}
+
+/* Penalty step (Eq. (7)): interpolate u = m / rho, form F_f and dxi/dt = U_ib - U.
+ * Returns the force density on the grid, f = S(F_f), as a dense [dim][ncell] array. */
+static double* ib_force(ora_ctx* c, const double* Q, double t)
+{
+    int dim = c->d.dim;
+    long nc = c->ncell;
+    double* vel = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)nc);
+    #pragma omp parallel for
+    for (long n = 0; n < nc; ++n)
+        for (int a = 0; a < dim; ++a) vel[(long)a * nc + n] = Q[(long)(1 + a) * nc + n] / Q[n];
+    for (int k = 0; k < c->nm; ++k) {
+        support_t s;
+        double uib[3], U[3];
+        support_of(c, c->X, c->nm, k, &s);
+        interp_point(c, &s, vel, dim, uib);
+        marker_velocity(c, k, t, U);
+        for (int a = 0; a < dim; ++a) {
+            long o = (long)a * c->nm + k;
+            c->dxi[o] = uib[a] - U[a];
+            c->F[o] = c->d.ib_alpha * c->xi[o] + c->d.ib_beta * (uib[a] - U[a]);
+        }
+    }
+    free(vel);
+    double* f = (double*)calloc((size_t)dim * (size_t)nc, sizeof(double));
+    spread_add(c, c->F, dim, f, 1.0);
+    return f;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Sponge                                                                                 */
+/* ------------------------------------------------------------------------------------ */
+
+/* sigma(x) = sigma_max * eta^3, eta = max over directions of the depth into the layer
+ * divided by the layer width (0 outside every layer). */
+static double sponge_sigma_at(const ora_ctx* c, const long* idx)
+{
+    double eta = 0.0;
+    for (int d = 0; d < c->d.dim; ++d) {
+        double x = c->d.lo[d] + ((double)idx[d] + 0.5) * c->d.h;
+        double lo = c->d.lo[d], hi = c->d.lo[d] + (double)n_of(c, d) * c->d.h;
+        double wl = c->d.sponge_width[d][0], wh = c->d.sponge_width[d][1];
+        if (wl > 0.0 && x < lo + wl) {
+            double r = (lo + wl - x) / wl;
+            if (r > eta) eta = r;
+        }
+        if (wh > 0.0 && x > hi - wh) {
+            double r = (x - (hi - wh)) / wh;
+            if (r > eta) eta = r;
+        }
+    }
+    if (eta > 1.0) eta = 1.0;
+    return c->d.sponge_sigma * eta * eta * eta;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Right-hand side                                                                        */
+/* ------------------------------------------------------------------------------------ */
+
+static void idx_of(const ora_ctx* c, long n, long* idx)
+{
+    idx[0] = n % c->nx;
+    idx[1] = (n / c->nx) % c->ny;
+    idx[2] = n / (c->nx * c->ny);
+}
+
+/* Add the IB source S = [0, f, f . u] (f the spread force density, u the fluid velocity)
+ * and the sponge -sigma (Q - Q_inf) at one cell. */
+static void sources_at(const ora_ctx* c, const double* Q, const double* fib, long n, double* out)
+{
+    int dim = c->d.dim, nq = c->nq;
+    long nc = c->ncell;
+    if ((c->d.terms & ORA_IB) && fib) {
+        double rho = Q[n], fu = 0.0;
+        for (int a = 0; a < dim; ++a) {
+            double fa = fib[(long)a * nc + n];
+            out[1 + a] += fa;
+            fu += fa * (Q[(long)(1 + a) * nc + n] / rho);
+        }
+        out[dim + 1] += fu;
+    }
+    if ((c->d.terms & ORA_SPONGE) && c->d.sponge_sigma != 0.0) {
+        long idx[3];
+        idx_of(c, n, idx);
+        double sg = sponge_sigma_at(c, idx);
+        for (int m = 0; m < nq; ++m) out[m] += -sg * (Q[(long)m * nc + n] - c->q_inf[m]);
+    }
+}
+
+static int conv_on(const ora_ctx* c, int d) { return (c->d.terms >> d) & 1; }
+static int visc_on(const ora_ctx* c) { return (c->d.terms & ORA_VISC) && c->d.mu != 0.0; }
+
+int ora_rhs(ora_ctx* c, const double* Q, double* L)
+{
+    int dim = c->d.dim, nq = c->nq;
+    long nc = c->ncell;
+    double alpha[3];
+    ora_alpha(c, Q, alpha);
+    memset(L, 0, sizeof(double) * (size_t)nq * (size_t)nc);
+
+    /* convective terms: -(F_hat_{i+1/2} - F_hat_{i-1/2}) / h, one line of faces at a time */
+    for (int d = 0; d < dim; ++d) {
+        if (!conv_on(c, d)) continue;
+        long nd = n_of(c, d);
+        long nlines = nc / nd;
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (long ln = 0; ln < nlines; ++ln) {
+            long base[3];
+            /* enumerate lines: the index along d is 0, the others run over the grid */
+            long rest = ln;
+            for (int e = 0; e < 3; ++e) {
+                if (e == d) { base[e] = 0; continue; }
+                long ne = (e < dim) ? n_of(c, e) : 1;
+                base[e] = rest % ne;
+                rest /= ne;
+            }
+            double* Fh = (double*)malloc(sizeof(double) * (size_t)(nd + 1) * (size_t)nq);
+            for (long f = -1; f < nd; ++f) {
+                long idx[3] = {base[0], base[1], base[2]};
+                idx[d] = f;
+                face_flux(c, Q, d, idx, alpha[d], &Fh[(f + 1) * nq]);
+            }
+            for (long i = 0; i < nd; ++i) {
+                long idx[3] = {base[0], base[1], base[2]};
+                idx[d] = i;
+                long n = cell_index(c, idx[0], idx[1], idx[2]);
+                for (int m = 0; m < nq; ++m)
+                    L[(long)m * nc + n] += -(Fh[(i + 1) * nq + m] - Fh[i * nq + m]) / c->d.h;
+            }
+            free(Fh);
+        }
+    }
+
+    /* viscous terms: stresses on the grid plus a two-cell ring, then their divergence */
+    if (visc_on(c)) {
+        long ex = c->nx + 4, ey = c->ny + 4, ez = dim == 3 ? c->nz + 4 : 1;
+        long ne = ex * ey * ez;
+        int ntau = 9, nbw = 3;
+        double* tau = (double*)malloc(sizeof(double) * (size_t)ne * (size_t)ntau);
+        double* bw = (double*)malloc(sizeof(double) * (size_t)ne * (size_t)nbw);
+        long zoff = dim == 3 ? 2 : 0;
+        #pragma omp parallel for schedule(dynamic, 64)
+        for (long e = 0; e < ne; ++e) {
+            long idx[3] = {e % ex - 2, (e / ex) % ey - 2, e / (ex * ey) - zoff};
+            double t3[3][3] = {{0}}, b3[3] = {0};
+            stress_at(c, Q, idx, t3, b3);
+            for (int a = 0; a < 3; ++a) {
+                for (int b = 0; b < 3; ++b) tau[e * ntau + a * 3 + b] = t3[a][b];
+                bw[e * nbw + a] = b3[a];
+            }
+        }
+        #pragma omp parallel for schedule(dynamic, 64)
+        for (long n = 0; n < nc; ++n) {
+            long idx[3];
+            idx_of(c, n, idx);
+            double tnb[3][5][3][3], bnb[3][5][3], v[5];
+            for (int b = 0; b < dim; ++b)
+                for (int s = 0; s < 5; ++s) {
+                    long id[3] = {idx[0] + 2, idx[1] + 2, idx[2] + zoff};
+                    id[b] += s - 2;
+                    long e = (id[2] * ey + id[1]) * ex + id[0];
+                    for (int a = 0; a < 3; ++a) {
+                        for (int bb = 0; bb < 3; ++bb) tnb[b][s][a][bb] = tau[e * ntau + a * 3 + bb];
+                        bnb[b][s][a] = bw[e * nbw + a];
+                    }
+                }
+            visc_from_stresses(c, tnb, bnb, v);
+            for (int m = 0; m < nq; ++m) L[(long)m * nc + n] += v[m];
+        }
+        free(tau);
+        free(bw);
+    }
+
+    /* immersed-boundary source and sponge */
+    double* fib = NULL;
+    if ((c->d.terms & ORA_IB) && c->nm > 0) fib = ib_force(c, Q, c->t);
+    #pragma omp parallel for
+    for (long n = 0; n < nc; ++n) {
+        double s[5] = {0, 0, 0, 0, 0};
+        sources_at(c, Q, fib, n, s);
+        for (int m = 0; m < nq; ++m) L[(long)m * nc + n] += s[m];
+    }
+    free(fib);
+    return 0;
+}
+
+int ora_rhs_cells(ora_ctx* c, const double* Q, int64_t nlist, const int64_t* cells, double* out)
+{
+    int dim = c->d.dim, nq = c->nq;
+    long nc = c->ncell;
+    for (int64_t l = 0; l < nlist; ++l)
+        if (cells[l] < 0 || cells[l] >= nc) return -1;
+    double alpha[3];
+    ora_alpha(c, Q, alpha);
+    /* IB force only at the requested cells: contributions in marker order */
+    double* fl = (double*)calloc((size_t)dim * (size_t)(nlist > 0 ? nlist : 1), sizeof(double));
+    if ((c->d.terms & ORA_IB) && c->nm > 0) {
+        double* f = ib_force(c, Q, c->t);
+        for (int64_t l = 0; l < nlist; ++l)
+            for (int a = 0; a < dim; ++a) fl[(long)a * nlist + l] = f[(long)a * nc + cells[l]];
+        free(f);
+    }
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t l = 0; l < nlist; ++l) {
+        long n = cells[l];
+        long idx[3];
+        idx_of(c, n, idx);
+        double acc[5] = {0, 0, 0, 0, 0};
+        for (int d = 0; d < dim; ++d) {
+            if (!conv_on(c, d)) continue;
+            double Fr[5], Fl[5];
+            long id[3] = {idx[0], idx[1], idx[2]};
+            face_flux(c, Q, d, id, alpha[d], Fr);
+            id[d] -= 1;
+            face_flux(c, Q, d, id, alpha[d], Fl);
+            for (int m = 0; m < nq; ++m) acc[m] += -(Fr[m] - Fl[m]) / c->d.h;
+        }
+        if (visc_on(c)) {
+            double tnb[3][5][3][3], bnb[3][5][3], v[5];
+            memset(tnb, 0, sizeof tnb);
+            memset(bnb, 0, sizeof bnb);
+            for (int b = 0; b < dim; ++b)
+                for (int s = 0; s < 5; ++s) {
+                    long id[3] = {idx[0], idx[1], idx[2]};
+                    id[b] += s - 2;
+                    stress_at(c, Q, id, tnb[b][s], bnb[b][s]);
+                }
+            visc_from_stresses(c, tnb, bnb, v);
+            for (int m = 0; m < nq; ++m) acc[m] += v[m];
+        }
+        /* sources: reuse the per-cell routine with the requested cells' force values */
+        double s[5] = {0, 0, 0, 0, 0};
+        if ((c->d.terms & ORA_IB) && c->nm > 0) {
+            double rho = Q[n], fu = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                double fa = fl[(long)a * nlist + l];
+                s[1 + a] += fa;
+                fu += fa * (Q[(long)(1 + a) * nc + n] / rho);
+            }
+            s[dim + 1] += fu;
+        }
+        if ((c->d.terms & ORA_SPONGE) && c->d.sponge_sigma != 0.0) {
+            double sg = sponge_sigma_at(c, idx);
+            for (int m = 0; m < nq; ++m) s[m] += -sg * (Q[(long)m * nc + n] - c->q_inf[m]);
+        }
+        for (int m = 0; m < nq; ++m) out[(long)m * nlist + l] = acc[m] + s[m];
+    }
+    free(fl);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* SSP-RK3 (Shu & Osher 1988)                                                             */
+/* ------------------------------------------------------------------------------------ */
+
+/* Q1 = Qn + dt L(Qn);  Q2 = 3/4 Qn + 1/4 (Q1 + dt L(Q1));  Qn+1 = 1/3 Qn + 2/3 (Q2 + dt L(Q2)),
+ * with the penalty integral xi advanced by the same three stages using dxi/dt = U_ib - U. */
+int ora_rk3_step(ora_ctx* c, double* Q, double dt)
+{
+    long len = (long)c->nq * c->ncell;
+    long lm = (long)c->d.dim * c->nm;
+    double* Qn = (double*)malloc(sizeof(double) * (size_t)len);
+    double* Qs = (double*)malloc(sizeof(double) * (size_t)len);
+    double* L = (double*)malloc(sizeof(double) * (size_t)len);
+    double* xin = (double*)malloc(sizeof(double) * (size_t)(lm > 0 ? lm : 1));
+    memcpy(Qn, Q, sizeof(double) * (size_t)len);
+    if (lm > 0) memcpy(xin, c->xi, sizeof(double) * (size_t)lm);
+    double t0 = c->t;
+    int ib = (c->d.terms & ORA_IB) && c->nm > 0;
+
+    /* stage 1 at time t */
+    c->t = t0;
+    ora_rhs(c, Qn, L);
+    #pragma omp parallel for
+    for (long i = 0; i < len; ++i) Qs[i] = Qn[i] + dt * L[i];
+    if (ib)
+        for (long i = 0; i < lm; ++i) c->xi[i] = xin[i] + dt * c->dxi[i];
+
+    /* stage 2 at time t + dt */
+    c->t = t0 + dt;
+    ora_rhs(c, Qs, L);
+    #pragma omp parallel for
+    for (long i = 0; i < len; ++i) Qs[i] = 0.75 * Qn[i] + 0.25 * (Qs[i] + dt * L[i]);
+    if (ib)
+        for (long i = 0; i < lm; ++i) c->xi[i] = 0.75 * xin[i] + 0.25 * (c->xi[i] + dt * c->dxi[i]);
+
+    /* stage 3 at time t + dt/2 */
+    c->t = t0 + 0.5 * dt;
+    ora_rhs(c, Qs, L);
+    #pragma omp parallel for
+    for (long i = 0; i < len; ++i) Q[i] = (1.0 / 3.0) * Qn[i] + (2.0 / 3.0) * (Qs[i] + dt * L[i]);
+    if (ib)
+        for (long i = 0; i < lm; ++i)
+            c->xi[i] = (1.0 / 3.0) * xin[i] + (2.0 / 3.0) * (c->xi[i] + dt * c->dxi[i]);
+
+    c->t = t0 + dt;
+    c->step += 1;
+    free(Qn);
+    free(Qs);
+    free(L);
+    free(xin);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Probes, state, life cycle                                                              */
+/* ------------------------------------------------------------------------------------ */
+
+int ora_probe_dp(const ora_ctx* c, const double* Q, double* dp)
+{
+    long nc = c->ncell;
+    double* p = (double*)malloc(sizeof(double) * (size_t)nc);
+    for (long n = 0; n < nc; ++n) {
+        double q[5], u[3];
+        for (int m = 0; m < c->nq; ++m) q[m] = Q[(long)m * nc + n];
+        primitives(c, q, u, &p[n]);
+    }
+    for (int k = 0; k < c->np; ++k) {
+        support_t s;
+        double v;
+        support_of(c, c->Xp, c->np, k, &s);
+        interp_point(c, &s, p, 1, &v);
+        dp[k] = v - c->d.prim_inf[4];
+    }
+    free(p);
+    return 0;
+}
+
+int ora_marker_force(const ora_ctx* c, double* F)
+{
+    memcpy(F, c->F, sizeof(double) * (size_t)c->d.dim * (size_t)c->nm);
+    return 0;
+}
+
+int ora_get_state(const ora_ctx* c, double* xi, double* t, int64_t* step)
+{
+    if (xi && c->nm > 0) memcpy(xi, c->xi, sizeof(double) * (size_t)c->d.dim * (size_t)c->nm);
+    if (t) *t = c->t;
+    if (step) *step = c->step;
+    return 0;
+}
+
+int ora_set_state(ora_ctx* c, const double* xi, double t, int64_t step)
+{
+    if (xi && c->nm > 0) memcpy(c->xi, xi, sizeof(double) * (size_t)c->d.dim * (size_t)c->nm);
+    c->t = t;
+    c->step = step;
+    return 0;
+}
+
+static void free_markers(ora_ctx* c)
+{
+    free(c->X); free(c->dV); free(c->U); free(c->xi); free(c->F); free(c->dxi);
+    c->X = c->dV = c->U = c->xi = c->F = c->dxi = NULL;
+    c->nm = 0;
+}
+
+int ora_set_markers(ora_ctx* c, int n, const double* X, const double* dV, const double* U,
+                    int motion, double omega)
+{
+    int dim = c->d.dim;
+    if (n < 0 || (n > 0 && (!X || !dV))) return -1;
+    if (motion < ORA_STATIC || motion > ORA_EXTERNAL) return -1;
+    if (n > 0 && !supports_inside(c, n, X)) return -1;
+    free_markers(c);
+    c->nm = n;
+    c->motion = motion;
+    c->omega = omega;
+    size_t lm = (size_t)dim * (size_t)(n > 0 ? n : 1);
+    c->X = (double*)calloc(lm, sizeof(double));
+    c->dV = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    c->U = (double*)calloc(lm, sizeof(double));
+    c->xi = (double*)calloc(lm, sizeof(double));
+    c->F = (double*)calloc(lm, sizeof(double));
+    c->dxi = (double*)calloc(lm, sizeof(double));
+    if (n > 0) {
+        memcpy(c->X, X, sizeof(double) * (size_t)dim * (size_t)n);
+        memcpy(c->dV, dV, sizeof(double) * (size_t)n);
+        if (U) memcpy(c->U, U, sizeof(double) * (size_t)dim * (size_t)n);
+    }
+    return 0;
+}
+
+int ora_set_probes(ora_ctx* c, int n, const double* Xp)
+{
+    if (n < 0 || (n > 0 && !Xp)) return -1;
+    if (n > 0 && !supports_inside(c, n, Xp)) return -1;
+    free(c->Xp);
+    c->np = n;
+    c->Xp = (double*)calloc((size_t)c->d.dim * (size_t)(n > 0 ? n : 1), sizeof(double));
+    if (n > 0) memcpy(c->Xp, Xp, sizeof(double) * (size_t)c->d.dim * (size_t)n);
+    return 0;
+}
+
+ora_ctx* ora_create(const ora_desc* desc)
+{
+    if (!desc || (desc->dim != 2 && desc->dim != 3)) return NULL;
+    for (int d = 0; d < desc->dim; ++d)
+        if (desc->n[d] < 1) return NULL;
+    if (desc->dim == 2 && desc->n[2] != 1) return NULL;
+    if (!(desc->h > 0.0)) return NULL;
+    ora_ctx* c = (ora_ctx*)calloc(1, sizeof(ora_ctx));
+    c->d = *desc;
+    c->nq = desc->dim + 2;
+    c->nx = desc->n[0];
+    c->ny = desc->n[1];
+    c->nz = desc->dim == 3 ? desc->n[2] : 1;
+    c->ncell = c->nx * c->ny * c->nz;
+    double u[3] = {desc->prim_inf[1], desc->prim_inf[2], desc->prim_inf[3]};
+    prim_to_cons(c, desc->prim_inf[0], u, desc->prim_inf[4], c->q_inf);
+    ora_set_markers(c, 0, NULL, NULL, NULL, ORA_STATIC, 0.0);
+    return c;
+}
+
+void ora_destroy(ora_ctx* c)
+{
+    if (!c) return;
+    free_markers(c);
+    free(c->Xp);
+    free(c);
+}

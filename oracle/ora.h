@@ -1,0 +1,104 @@
+/*
+ * ora.h -- plain FP64 CPU oracle for the immersed-boundary compressible Navier-Stokes
+ * right-hand side and its SSP-RK3 update (Wang, Tian & Lai, "An immersed boundary method
+ * for fluid-structure-acoustics interactions involving large deformations and complex
+ * geometries", Sec. 2).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This header and ora.c are the reference the GPU library is
+ * checked against.  Only the test suite, the smoke check and the benchmark's CPU-baseline
+ * leg may load this code.  It shares no source, header, table or constant with the GPU
+ * library; every constant below is stated here on its own.
+ *
+ * Conventions
+ *   - Uniform cell-centred grid: x_i = lo + (i + 1/2) h, i = 0..n-1, same h in every direction.
+ *   - Conserved state Q = [rho, m_1 .. m_dim, E] (Sec. 2, the conservative NS system), stored
+ *     structure-of-arrays, component-major: Q[c * ncell + (k * ny + j) * nx + i].
+ *     nq = dim + 2 components.  In 2D n[2] must be 1.
+ *   - Marker arrays are [dim][nm], also component-major.
+ *   - All functions return 0 on success and a negative code on a bad argument.
+ */
+#ifndef ORA_H
+#define ORA_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORA_BC_PERIODIC = 0, ORA_BC_EXTRAP = 1, ORA_BC_INFLOW = 2 };
+enum { ORA_WENO5JS = 0, ORA_TENO5 = 1 };
+enum { ORA_STATIC = 0, ORA_ROTATING = 1, ORA_EXTERNAL = 2 };
+/* Terms of the right-hand side that are evaluated (bit mask). */
+enum {
+    ORA_CONV_X = 1, ORA_CONV_Y = 2, ORA_CONV_Z = 4, ORA_VISC = 8,
+    ORA_IB = 16, ORA_SPONGE = 32, ORA_ALL = 63
+};
+
+typedef struct ora_desc {
+    int32_t  dim;              /* 2 or 3 */
+    int32_t  n[3];             /* cells per direction (n[2] = 1 in 2D) */
+    double   lo[3];            /* lower domain corner */
+    double   h;                /* uniform grid spacing */
+    int32_t  bc[3][2];         /* boundary type per direction and side (0 = low, 1 = high) */
+    double   gamma;            /* ratio of specific heats */
+    double   mu;               /* dynamic viscosity (1/Re folded in) */
+    int32_t  scheme;           /* ORA_WENO5JS or ORA_TENO5 */
+    int32_t  terms;            /* ORA_* bit mask */
+    double   weno_eps;         /* WENO5-JS epsilon */
+    double   teno_ct;          /* TENO5 cut-off C_T */
+    double   teno_eps;         /* TENO5 epsilon */
+    double   prim_inf[5];      /* far-field primitive state rho, u, v, w, p */
+    double   inflow_amp;       /* amplitude of the seeded inflow velocity perturbation */
+    uint64_t seed;             /* seed of that perturbation */
+    double   sponge_width[3][2];
+    double   sponge_sigma;     /* sigma_max of the cubic sponge */
+    double   ib_alpha;         /* penalty constant on the integral term */
+    double   ib_beta;          /* penalty constant on the proportional term */
+} ora_desc;
+
+typedef struct ora_ctx ora_ctx;
+
+ora_ctx* ora_create(const ora_desc* desc);
+void     ora_destroy(ora_ctx* c);
+
+/* Markers: positions X[dim][n], quadrature weights dV[n], velocities U[dim][n] (NULL = 0).
+ * ROTATING markers move with U = omega e_z x X (rotation about the origin).
+ * Resets the penalty integral xi to zero. */
+int ora_set_markers(ora_ctx* c, int n, const double* X, const double* dV, const double* U,
+                    int motion, double omega);
+int ora_set_probes(ora_ctx* c, int n, const double* Xp);
+
+/* Global Lax-Friedrichs speeds alpha[d] = max over cells of |u_d| + c. */
+int ora_alpha(const ora_ctx* c, const double* Q, double* alpha);
+/* L(Q) at the context's current time, step and penalty integral. */
+int ora_rhs(ora_ctx* c, const double* Q, double* L);
+/* L(Q) at a list of cells only (linear cell indices); out[nq][ncell_list]. */
+int ora_rhs_cells(ora_ctx* c, const double* Q, int64_t nlist, const int64_t* cells, double* out);
+/* One SSP-RK3 step in place; advances xi, t and step. */
+int ora_rk3_step(ora_ctx* c, double* Q, double dt);
+/* Interpolate ncomp cell fields (component-major) to the markers: out[ncomp][nm]. */
+int ora_ib_interp(const ora_ctx* c, const double* field, int ncomp, double* out);
+/* field[a] += scale * S_a(F), S the spreading operator with the paper's minus sign. */
+int ora_ib_spread(const ora_ctx* c, const double* F, int ncomp, double* field, double scale);
+/* Acoustic pressure p - p_inf interpolated to the probes. */
+int ora_probe_dp(const ora_ctx* c, const double* Q, double* dp);
+/* Penalty force of the most recent right-hand-side evaluation, [dim][nm]. */
+int ora_marker_force(const ora_ctx* c, double* F);
+int ora_get_state(const ora_ctx* c, double* xi, double* t, int64_t* step);
+int ora_set_state(ora_ctx* c, const double* xi, double t, int64_t step);
+
+/* Scalar building blocks exposed for the pins. */
+double ora_delta4(double r);
+/* Reconstruction at a face from five upwind-ordered values. */
+double ora_recon5(double a, double b, double cc, double d, double e, int scheme,
+                  double weno_eps, double teno_ct, double teno_eps);
+/* TENO5 keep flags of one stencil (bit k set = sub-stencil k kept). */
+int ora_teno_flags(double a, double b, double cc, double d, double e,
+                   double teno_ct, double teno_eps);
+/* Counter-based SplitMix64: output number ctr of the generator seeded with seed. */
+uint64_t ora_splitmix64(uint64_t seed, uint64_t ctr);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
