@@ -110,3 +110,70 @@ def test_spread_accumulates_scale(oracle_mod):
     f2 = np.full((2,) + case.shape, 3.0)
     o.ib_spread(F, f2, -2.0)
     np.testing.assert_allclose(f2, 3.0 - 2.0 * f1, rtol=1e-15, atol=1e-15)
+
+
+def _uniform_flow_case(u0, omega=0.3, alpha=7.0, beta=2.5, terms=W.TERM["ib"]):
+    case = W.periodic_box(dim=2, n=32, terms=terms, prim_inf=(1.2, u0[0], u0[1], 0.0, 0.8))
+    X, dV = W.circle_markers(16, 0.2, (0.0, 0.0))
+    X = X + 0.5
+    return case.with_(ib_alpha=alpha, ib_beta=beta,
+                      markers={"X": X, "dV": dV, "U": None, "motion": "rotating", "omega": omega})
+
+
+def test_penalty_force_law(oracle_mod):
+    """Eq. (7): F = alpha xi + beta (U_ib - U); rotating markers move anticlockwise,
+    U = omega (-(y - 0), x - 0) about the origin."""
+    u0 = (0.13, -0.07)
+    case = _uniform_flow_case(u0)
+    o = oracle_mod.Oracle(case)
+    X = case.markers["X"]
+    U = 0.3 * np.stack([-X[1], X[0]])
+    xi = np.random.default_rng(3).normal(size=(2, o.nm))
+    o.set_state(xi, 0.0, 0)
+    o.rhs(W.uniform_state(case))
+    F = o.marker_force()
+    # U_ib of a uniform field is exactly the field value (zeroth moment)
+    want = 7.0 * xi + 2.5 * (np.array(u0)[:, None] - U)
+    np.testing.assert_allclose(F, want, rtol=1e-13, atol=1e-14)
+
+
+def test_ib_energy_source_is_force_work(oracle_mod):
+    u0 = (0.11, 0.04)
+    case = _uniform_flow_case(u0)
+    o = oracle_mod.Oracle(case)
+    L = o.rhs(W.uniform_state(case))
+    assert np.all(L[0] == 0.0)
+    np.testing.assert_allclose(L[3], L[1] * u0[0] + L[2] * u0[1], rtol=1e-13, atol=1e-18)
+    assert np.abs(L[1]).max() > 0
+
+
+def test_penalty_integral_advances_with_rk3(oracle_mod):
+    """With alpha = beta = 0 the fluid is untouched, so U_ib - U is constant over the step
+    and the SSP-RK3 stages must integrate it exactly: xi(dt) = xi(0) + dt (u0 - U)."""
+    u0 = (0.09, 0.02)
+    case = _uniform_flow_case(u0, omega=0.4, alpha=0.0, beta=0.0)
+    o = oracle_mod.Oracle(case)
+    xi0 = np.random.default_rng(4).normal(size=(2, o.nm))
+    o.set_state(xi0, 0.0, 0)
+    Q = W.uniform_state(case)
+    dt = 0.05
+    o.rk3_step(Q, dt)
+    xi, t, step = o.get_state()
+    X = case.markers["X"]
+    U = 0.4 * np.stack([-X[1], X[0]])
+    np.testing.assert_allclose(xi, xi0 + dt * (np.array(u0)[:, None] - U), rtol=1e-13, atol=1e-15)
+    assert t == dt and step == 1
+    # anticlockwise: the marker with the largest x moves in +y
+    k = int(np.argmax(X[0]))
+    assert U[1, k] > 0
+
+
+def test_sponge_profile_hand_values(oracle_mod):
+    rows = np.loadtxt(os.path.join(GOLDEN, "sponge_profile.txt"))
+    case = W.periodic_box(dim=2, n=8, terms=W.TERM["sponge"])
+    case = case.with_(sponge_width=((0.25, 0.0), (0.0, 0.0), (0.0, 0.0)), sponge_sigma=8.0)
+    Q = W.uniform_state(case)
+    Q[0] += 1e-3
+    L = oracle_mod.Oracle(case).rhs(Q)
+    for i, sg in rows:
+        np.testing.assert_allclose(L[0][:, int(i)], -sg * 1e-3, rtol=1e-12, atol=1e-18)

@@ -49,7 +49,7 @@ def test_teno_worked_example(oracle_mod):
     for row in rows:
         v, flags, val = row[:5], int(row[5]), row[6]
         assert oracle_mod.teno_flags(v) == flags
-        assert oracle_mod.recon5(v, "teno5") == val
+        assert oracle_mod.recon5(v, "teno5") == pytest.approx(val, rel=1e-15, abs=0)
 
 
 def test_weno_step_is_essentially_non_oscillatory(oracle_mod):
@@ -123,3 +123,10 @@ def test_convective_term_fifth_order(oracle_mod, scheme):
         errs.append(max(np.abs(L[m] + dF[m]).max() for m in range(4)))
     slopes = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert slopes[-1] > 4.7, (errs, slopes)
+
+
+def test_weno_js_rational_examples(oracle_mod):
+    rows = np.loadtxt(os.path.join(GOLDEN, "weno_js_examples.txt"))
+    for row in rows:
+        got = oracle_mod.recon5(row[:5], "weno5js")
+        assert got == pytest.approx(row[5], rel=1e-13)
