@@ -1,0 +1,173 @@
+"""Benchmark: SSP-RK3 steps of the 2048^2 TENO5 rotating-cylinder case on one MI355X.
+
+A step is one pass of the whole hot path: for each of the three stages, the global
+Lax-Friedrichs wave-speed reduction, the penalty immersed-boundary step (interpolation,
+feedback force, spreading) and the fused stencil/update kernel (flux splitting, TENO5
+reconstruction in x and y, fourth-order viscous terms, IB and sponge sources, RK3 update).
+Inputs are synthetic (seeded free stream with the inflow perturbation) and resident in HBM
+before the timed region.
+
+Prints one JSON line.  Metric: cell-stage updates per second (cells x 3 stages x steps /
+wall time).  roofline: the fused stage kernel, whose launches are bracketed by HIP events on
+the library's stream inside the timed region; its algorithmic FP64 operation count per
+cell-stage is stated in ALGO_FLOPS below.  cpu_baseline: the FP64 CPU oracle on a few steps
+of the same case on this host's cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
+PEAK_HBM_GBPS = 8000.0
+# Algorithmic FP64 operations per cell-stage of the 2D path (one op = one add, mul, div,
+# sqrt or compare of the method's plain formulation; see the design notes for the count).
+ALGO_FLOPS_2D = {"teno5": 1638, "weno5js": 1350}
+ALGO_BYTES_2D = 256.0 / 3.0  # FP64 state: read Qs (+ Qn in stages 2-3), write Q_{s+1}
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_stage2d_teno5_2048_pmc.txt")
+KERNEL_SOURCES = ["paper_1905_00182_amd/csrc/k_stage2d.hip", "paper_1905_00182_amd/csrc/fsa_dev.hpp"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(launch_cells):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or None when the
+    summary is missing or was taken on a different kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(PMC_SUMMARY):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(case, steps):
+    from oracle import oracle as ora
+    from paper_1905_00182_amd import workloads as W
+
+    Q = W.config2_state(case)
+    o = ora.Oracle(case)
+    o.rk3_step(Q, case.dt)            # warm-up step (page-in, thread start)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.rk3_step(Q, case.dt)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": case.ncell * 3 * steps / dt / 1e6,
+        "unit": "Mcell-stage/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{steps} SSP-RK3 steps of the same {case.n[0]}x{case.n[1]} case after one warm-up step "
+                  f"({dt:.1f} s, FP64 C oracle, OpenMP)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--scheme", default="teno5", choices=["teno5", "weno5js"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "decomposition is a design note, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1905_00182_amd import fsa, workloads as W
+
+    torch.cuda.set_device(0)
+    case = W.config2()
+    if args.scheme != case.scheme:
+        case = case.with_(scheme=args.scheme)
+    Q = torch.from_numpy(W.config2_state(case)).cuda()
+    s = fsa.Solver(case)
+    for _ in range(args.warmup):
+        s.rk3_step(Q, case.dt)
+    s.sync()
+    s.timing(True)
+    s.timing_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.rk3_step(Q, case.dt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches = s.timing_read()
+    s.timing(False)
+    s.sync()
+
+    cell_stages = case.ncell * 3 * args.steps
+    value = cell_stages / wall / 1e6
+    per_launch_ms = kms / max(launches, 1)
+    flops_launch = ALGO_FLOPS_2D[case.scheme] * case.ncell
+    achieved = flops_launch / (per_launch_ms * 1e-3) / 1e12
+    traffic = traffic_from_profile(case.ncell)
+    out = {
+        "metric": "Mcell-stage updates/s (2D FP64 TENO5 + IB, SSP-RK3)",
+        "value": round(value, 3),
+        "unit": "Mcell-stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"c2_rotating_cylinder_{case.n[0]}x{case.n[1]}_{case.scheme}_ib_fp64",
+            "grid": [case.n[0], case.n[1]],
+            "scheme": case.scheme,
+            "markers": int(case.markers["X"].shape[1]),
+            "re": 150,
+            "mach": 0.2,
+            "dt": case.dt,
+        },
+        "hbm_gbps_algorithmic": round(value * 1e6 * ALGO_BYTES_2D / 1e9, 1),
+        "hbm_frac_algorithmic": round(value * 1e6 * ALGO_BYTES_2D / 1e9 / PEAK_HBM_GBPS, 4),
+        "roofline": {
+            "bound": "alu",
+            "kernel": f"k_stage2d<{case.scheme.upper()}>",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+            "traffic": traffic,
+            "kernel_ms_per_launch": round(per_launch_ms, 4),
+            "launches": launches,
+            "algo_flops_per_cell_stage": ALGO_FLOPS_2D[case.scheme],
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu and args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * fsa.h -- C ABI of the MI355X (gfx950) immersed-boundary compressible Navier-Stokes library.
+ *
+ * The library computes the fluid hot path of the immersed-boundary method of Wang, Tian &
+ * Lai (fluid-structure-acoustics interactions, Sec. 2):
+ *   - the right-hand side L(Q) of the conservative compressible NS system (Sec. 2,
+ *     Eqs. (2)-(6)): convective fluxes by global Lax-Friedrichs splitting and fifth-order
+ *     WENO5-JS or TENO5 reconstruction per direction, viscous fluxes by fourth-order
+ *     central differences, the penalty immersed-boundary source and a sponge;
+ *   - the penalty immersed boundary: interpolation of velocity to Lagrangian markers
+ *     (Eq. (8)), the feedback force F_f = alpha int (U_ib - U) dt + beta (U_ib - U)
+ *     (Eq. (7)), spreading of -F_f to the grid (Eq. (9)) with the four-point delta function
+ *     (Eqs. (10)-(11));
+ *   - the third-order TVD (SSP) Runge-Kutta update the paper uses for time integration.
+ *
+ * Conventions
+ *   - Grid: uniform, cell-centred, x_i = lo + (i + 1/2) h, the same h in every direction.
+ *   - Field arrays are DEVICE pointers to FP64 structure-of-arrays, component-major:
+ *     Q[c * ncell + (k * ny + j) * nx + i], components [rho, m_1..m_dim, E] (nq = dim + 2),
+ *     interior cells only (ghost values are generated from the boundary conditions).
+ *   - Marker and probe arrays passed in are HOST pointers, [dim][n] component-major; they are
+ *     copied before the call returns, so the caller may free them at once.
+ *   - Every call that takes device pointers is enqueued on the context's HIP stream and
+ *     returns without waiting; the buffers must stay alive until the stream has passed the
+ *     call.  Calls documented as synchronising wait for the stream.
+ *   - A context belongs to one host thread at a time.
+ *   - Ownership: the library allocates and frees its own internal device memory (stage
+ *     buffers, marker and window arrays); it never frees a caller's buffer.
+ *
+ * Errors: every function returns FSA_OK (0) or a negative status.  Argument and shape errors
+ * are reported synchronously as FSA_EINVAL with a message from fsa_last_error.  Device
+ * errors surface as FSA_EDEVICE.  With nan_check set, a NaN or Inf seen by the global
+ * wave-speed reduction makes the next fsa_rk3_step / fsa_sync return FSA_ENONFINITE (the
+ * state is not rolled back).  No C++ exception crosses this interface.
+ */
+#ifndef FSA_H
+#define FSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSA_ABI_VERSION 1
+
+enum {
+    FSA_OK = 0,
+    FSA_EINVAL = -1,
+    FSA_ENOMEM = -2,
+    FSA_EDEVICE = -3,
+    FSA_ENONFINITE = -4,
+    FSA_ESTATE = -5,
+    FSA_EUNSUPPORTED = -6
+};
+
+/* Boundary conditions per direction and side. */
+enum { FSA_BC_PERIODIC = 0, FSA_BC_EXTRAP = 1, FSA_BC_INFLOW = 2 };
+/* Convective reconstruction. */
+enum { FSA_WENO5JS = 0, FSA_TENO5 = 1 };
+/* Arithmetic of the face reconstruction and viscous fluxes (the state is always FP64). */
+enum { FSA_FP64 = 0, FSA_MIXED32 = 1 };
+/* Marker motion. */
+enum { FSA_STATIC = 0, FSA_ROTATING = 1, FSA_EXTERNAL = 2 };
+/* Right-hand-side terms (bit mask). */
+enum {
+    FSA_TERM_CONV_X = 1, FSA_TERM_CONV_Y = 2, FSA_TERM_CONV_Z = 4, FSA_TERM_VISC = 8,
+    FSA_TERM_IB = 16, FSA_TERM_SPONGE = 32, FSA_TERM_ALL = 63
+};
+
+/* Problem description (Sec. 2 problem statement plus the readings the paper leaves open).
+ *
+ * Boundary ghosts: PERIODIC wraps, EXTRAP copies the nearest interior cell, INFLOW holds the
+ * far-field state prim_inf with each velocity component perturbed by
+ * inflow_amp * (2 r - 1), r uniform in [0,1) from the counter-based SplitMix64 stream of
+ * seed at counter ((((step * 6 + side) * 8 + depth) * ncell + cell) * 3 + component),
+ * side = 2 * direction + (0 low | 1 high), depth >= 1 the ghost layer, cell the linear index
+ * of the nearest interior cell.  Directions are resolved in the order x, y, z.
+ *
+ * Sponge: S = -sigma(x) (Q - Q_inf), sigma = sponge_sigma * eta^3, eta = max over
+ * directions of (depth into the layer) / (layer width), clipped to 1. */
+typedef struct fsa_desc {
+    int32_t  dim;                 /* 2 or 3 */
+    int32_t  n[3];                /* cells per direction; n[2] = 1 in 2D */
+    double   lo[3];               /* lower corner of the domain */
+    double   h;                   /* uniform grid spacing */
+    int32_t  bc[3][2];            /* FSA_BC_* per direction and side */
+    double   gamma;               /* ratio of specific heats (ideal gas) */
+    double   mu;                  /* dynamic viscosity, 1/Re folded in; 0 disables viscosity */
+    int32_t  scheme;              /* FSA_WENO5JS or FSA_TENO5 */
+    int32_t  precision;           /* FSA_FP64 or FSA_MIXED32 */
+    int32_t  terms;               /* FSA_TERM_* mask */
+    int32_t  nan_check;           /* 1: report non-finite wave speeds as FSA_ENONFINITE */
+    double   weno_eps;            /* WENO5-JS epsilon (1e-6) */
+    double   teno_ct;             /* TENO5 cut-off C_T (1e-6) */
+    double   teno_eps;            /* TENO5 epsilon (1e-40) */
+    double   prim_inf[5];         /* far-field rho, u, v, w, p */
+    double   inflow_amp;          /* inflow velocity perturbation amplitude */
+    uint64_t seed;                /* its seed */
+    double   sponge_width[3][2];  /* sponge layer widths per direction and side */
+    double   sponge_sigma;        /* sigma_max */
+    double   ib_alpha;            /* penalty constant on the integral term, Eq. (7) */
+    double   ib_beta;             /* penalty constant on the proportional term, Eq. (7) */
+} fsa_desc;
+
+typedef struct fsa_ctx fsa_ctx;
+
+/* Run statistics.  Synchronising. */
+typedef struct fsa_stats {
+    double   alpha[3];            /* last global Lax-Friedrichs speeds max(|u_d| + c) */
+    double   t;                   /* current time */
+    int64_t  step;                /* completed RK3 steps */
+    int32_t  nonfinite;           /* 1 if a NaN/Inf reached the wave-speed reduction */
+    int32_t  n_markers;
+    int32_t  n_probes;
+    int32_t  window_cells;        /* cells of the box that holds every marker's support */
+} fsa_stats;
+
+int32_t     fsa_abi_version(void);
+const char* fsa_status_str(int32_t status);
+/* Message of the last error on ctx (owned by ctx, valid until the next call on ctx). */
+const char* fsa_last_error(const fsa_ctx* ctx);
+
+/* Create a context on the current HIP device, enqueuing on hip_stream (a hipStream_t; NULL
+ * is the null stream).  Validates desc (FSA_EINVAL) and allocates the two RK stage buffers
+ * and the reduction slots (FSA_ENOMEM). */
+int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out);
+/* Free everything the context owns.  Synchronising.  NULL is accepted. */
+int32_t fsa_destroy(fsa_ctx* ctx);
+
+/* Lagrangian markers (Sec. 2, Eqs. (7)-(9)): positions X[dim][n], quadrature weights
+ * dV[n] (arc length in 2D, area in 3D), velocities U[dim][n] (NULL = 0; ignored for
+ * ROTATING, where U = omega e_z x X about the origin).  Every marker's four-point support
+ * must lie inside the grid (FSA_EINVAL otherwise).  Resets the penalty integral to zero.
+ * n = 0 removes the markers.  Synchronising. */
+int32_t fsa_set_markers(fsa_ctx* ctx, int32_t n, const double* X, const double* dV,
+                        const double* U, int32_t motion, double omega);
+/* New positions and velocities for EXTERNAL markers (same count), e.g. from a structure
+ * solver; keeps the penalty integral.  Synchronising. */
+int32_t fsa_set_marker_kinematics(fsa_ctx* ctx, const double* X, const double* U);
+/* Probe points Xp[dim][n] for fsa_probe_dp; supports must lie inside the grid. */
+int32_t fsa_set_probes(fsa_ctx* ctx, int32_t n, const double* Xp);
+
+/* Global Lax-Friedrichs speeds alpha[d] = max over cells of |u_d| + c of d_Q, written to the
+ * host array alpha[3] (NaN-propagating).  Synchronising. */
+int32_t fsa_alpha(fsa_ctx* ctx, const double* d_Q, double* alpha);
+/* d_L = L(d_Q) at the context's time, step and penalty integral (Sec. 2, Eq. (2) with the
+ * IB source of Eqs. (7)-(9)).  d_L must not alias d_Q.  Also records the penalty force. */
+int32_t fsa_rhs(fsa_ctx* ctx, const double* d_Q, double* d_L);
+/* One SSP-RK3 step of size dt in place on d_Q:
+ *   Q1 = Qn + dt L(Qn);  Q2 = 3/4 Qn + 1/4 (Q1 + dt L(Q1));  Qn+1 = 1/3 Qn + 2/3 (Q2 + dt L(Q2)),
+ * the penalty integral advancing through the same stages; then t += dt, step += 1. */
+int32_t fsa_rk3_step(fsa_ctx* ctx, double* d_Q, double dt);
+/* Interpolate ncomp fields d_field[ncomp][ncell] to the markers (Eq. (8)):
+ * d_out[a][k] = sum over the support of field_a * prod lambda. */
+int32_t fsa_ib_interp(fsa_ctx* ctx, const double* d_field, int32_t ncomp, double* d_out);
+/* d_field[a] += scale * f_a with f = -sum_k F_k prod lambda dV_k / h^dim (Eq. (9)), F given
+ * on the markers as d_F[ncomp][n].  Each cell sums its markers in index order. */
+int32_t fsa_ib_spread(fsa_ctx* ctx, const double* d_F, int32_t ncomp, double* d_field,
+                      double scale);
+/* Acoustic pressure p - p_inf interpolated to the probes, d_dp[np]. */
+int32_t fsa_probe_dp(fsa_ctx* ctx, const double* d_Q, double* d_dp);
+/* Penalty force on the structure from the most recent right-hand side, host h_F[dim][n]
+ * (the force on the fluid is its negative, Sec. 2).  Synchronising. */
+int32_t fsa_marker_force(fsa_ctx* ctx, double* h_F);
+/* Checkpoint: penalty integral h_xi[dim][n], time and step.  Synchronising. */
+int32_t fsa_get_state(fsa_ctx* ctx, double* h_xi, double* t, int64_t* step);
+int32_t fsa_set_state(fsa_ctx* ctx, const double* h_xi, double t, int64_t step);
+/* Measurement: with timing on, a pair of HIP events on the context's stream brackets every
+ * launch of the fused stencil/update kernel.  fsa_timing_read (synchronising) returns the
+ * summed kernel milliseconds and the number of launches since the previous read. */
+int32_t fsa_timing_enable(fsa_ctx* ctx, int32_t on);
+int32_t fsa_timing_read(fsa_ctx* ctx, double* ms, int64_t* launches);
+/* Wait for the stream; returns FSA_ENONFINITE if nan_check saw a NaN/Inf. */
+int32_t fsa_sync(fsa_ctx* ctx);
+int32_t fsa_stats_get(fsa_ctx* ctx, fsa_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSA_H */

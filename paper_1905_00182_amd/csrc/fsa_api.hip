@@ -1,0 +1,662 @@
+// C-ABI entry points (include/fsa.h): argument checking, device buffers, and the enqueue
+// order of the kernels for one right-hand side and one SSP-RK3 step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fsa.h"
+#include "fsa_impl.hpp"
+
+using namespace fsa;
+
+struct fsa_ctx {
+    fsa_desc d;
+    Grid G;
+    Phys P;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int nq = 0;
+    long long ncell = 0;
+    int ty = 16;                         // rows per wave segment of the 2D stage kernel
+    double* Qa = nullptr;                // RK stage buffers
+    double* Qb = nullptr;
+    unsigned long long* abits = nullptr; // alpha slots: [4][3]
+    unsigned long long* h_abits = nullptr;  // pinned mirror of the last step's slots
+    hipEvent_t ev_alpha = nullptr;
+    bool alpha_pending = false;
+    int nonfinite = 0;
+    // markers
+    int nm = 0;
+    int motion = 0;
+    double omega = 0.0;
+    double *X = nullptr, *dV = nullptr, *U = nullptr, *xi = nullptr, *xi_n = nullptr, *F = nullptr;
+    std::vector<double> hX;
+    int wlo[3] = {0, 0, 0}, wn[3] = {0, 0, 0};
+    long long wcells = 0;
+    double* fwin = nullptr;
+    int* cell_start = nullptr;
+    int* cell_marker = nullptr;
+    // probes
+    int np = 0;
+    double* Xp = nullptr;
+    double t = 0.0;
+    long long step = 0;
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> tev;   // pairs (start, stop) per timed launch
+    size_t tused = 0;
+    std::string err;
+};
+
+namespace {
+
+int fail(fsa_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+int hipcheck(fsa_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return FSA_OK;
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    return fail(c, FSA_EDEVICE, buf);
+}
+
+#define HIPCHK(ctx, expr)                                          \
+    do {                                                           \
+        int rc_ = hipcheck((ctx), (expr), #expr);                  \
+        if (rc_ != FSA_OK) return rc_;                             \
+    } while (0)
+
+template <class T>
+void dfree(T*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <class T>
+int dalloc(fsa_ctx* c, T*& p, size_t count)
+{
+    dfree(p);
+    if (count == 0) count = 1;
+    if (hipMalloc((void**)&p, count * sizeof(T)) != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, FSA_ENOMEM, "device allocation failed");
+    }
+    return FSA_OK;
+}
+
+int validate(const fsa_desc* d, std::string& why)
+{
+    if (!d) { why = "desc is NULL"; return FSA_EINVAL; }
+    if (d->dim != 2 && d->dim != 3) { why = "dim must be 2 or 3"; return FSA_EINVAL; }
+    for (int k = 0; k < d->dim; ++k)
+        if (d->n[k] < 1) { why = "n must be positive"; return FSA_EINVAL; }
+    if (d->dim == 2 && d->n[2] != 1) { why = "n[2] must be 1 in 2D"; return FSA_EINVAL; }
+    const double nc = (double)d->n[0] * d->n[1] * (d->dim == 3 ? d->n[2] : 1);
+    if (nc * (d->dim + 2) > 9.0e18 || nc > 2.0e9) { why = "grid too large"; return FSA_EINVAL; }
+    if (!(d->h > 0.0) || !std::isfinite(d->h)) { why = "h must be positive"; return FSA_EINVAL; }
+    for (int k = 0; k < 3; ++k)
+        for (int s = 0; s < 2; ++s) {
+            if (k >= d->dim) continue;
+            if (d->bc[k][s] < FSA_BC_PERIODIC || d->bc[k][s] > FSA_BC_INFLOW) { why = "bad bc"; return FSA_EINVAL; }
+            if ((d->bc[k][0] == FSA_BC_PERIODIC) != (d->bc[k][1] == FSA_BC_PERIODIC)) {
+                why = "periodic must be set on both sides";
+                return FSA_EINVAL;
+            }
+            if (d->sponge_width[k][s] < 0.0) { why = "negative sponge width"; return FSA_EINVAL; }
+        }
+    if (!(d->gamma > 1.0)) { why = "gamma must exceed 1"; return FSA_EINVAL; }
+    if (d->mu < 0.0) { why = "mu must be non-negative"; return FSA_EINVAL; }
+    if (d->scheme != FSA_WENO5JS && d->scheme != FSA_TENO5) { why = "bad scheme"; return FSA_EINVAL; }
+    if (d->precision != FSA_FP64) { why = "only FP64 is built"; return FSA_EUNSUPPORTED; }
+    if (d->dim == 3) { why = "3D path not built"; return FSA_EUNSUPPORTED; }
+    if (!(d->prim_inf[0] > 0.0) || !(d->prim_inf[4] > 0.0)) { why = "far field must have rho, p > 0"; return FSA_EINVAL; }
+    return FSA_OK;
+}
+
+void build_consts(fsa_ctx* c)
+{
+#pragma clang fp contract(off)
+    const fsa_desc& d = c->d;
+    Grid& G = c->G;
+    G.dim = d.dim;
+    for (int k = 0; k < 3; ++k) {
+        G.n[k] = k < d.dim ? d.n[k] : 1;
+        G.lo[k] = d.lo[k];
+        G.bc[k][0] = d.bc[k][0];
+        G.bc[k][1] = d.bc[k][1];
+    }
+    G.ncell = (long long)G.n[0] * G.n[1] * G.n[2];
+    G.h = d.h;
+    G.inv_h = 1.0 / d.h;
+    Phys& P = c->P;
+    P.gamma = d.gamma;
+    P.gm1 = d.gamma - 1.0;
+    P.inv_gm1 = 1.0 / (d.gamma - 1.0);
+    P.mu = d.mu;
+    for (int k = 0; k < 5; ++k) P.prim_inf[k] = d.prim_inf[k];
+    {
+        const double rho = d.prim_inf[0];
+        double ke = 0.0;
+        P.q_inf[0] = rho;
+        for (int a = 0; a < d.dim; ++a) {
+            P.q_inf[1 + a] = rho * d.prim_inf[1 + a];
+            ke += d.prim_inf[1 + a] * d.prim_inf[1 + a];
+        }
+        P.q_inf[d.dim + 1] = d.prim_inf[4] / (d.gamma - 1.0) + 0.5 * rho * ke;
+        for (int a = d.dim + 2; a < 5; ++a) P.q_inf[a] = 0.0;
+    }
+    P.inflow_amp = d.inflow_amp;
+    P.seed = d.seed;
+    P.step = 0;
+    for (int k = 0; k < 3; ++k)
+        for (int s = 0; s < 2; ++s) P.sw[k][s] = k < d.dim ? d.sponge_width[k][s] : 0.0;
+    P.sigma = d.sponge_sigma;
+    P.weno_eps = d.weno_eps;
+    P.teno_ct = d.teno_ct;
+    P.teno_eps = d.teno_eps;
+    P.terms = d.terms;
+}
+
+// Rows per wave segment: fill the device in whole rounds of resident waves, preferring
+// long segments (each segment recomputes one y face and eight halo rows).
+int choose_ty(const Grid& G)
+{
+    int dev = 0, cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        cus = prop.multiProcessorCount;
+    const long long slots = (long long)cus * 8;   // resident waves at two per SIMD
+    const long long ncol = stage2d_ncolx(G.n[0]);
+    int best = 16;
+    double best_cost = 1e300;
+    for (int ty = 8; ty <= 64; ++ty) {
+        const long long tiles = ncol * ((G.n[1] + ty - 1) / ty);
+        const long long rounds = (tiles + slots - 1) / slots;
+        const double cost = (double)rounds * (ty + 3.0);
+        if (cost < best_cost - 1e-9) { best_cost = cost; best = ty; }
+    }
+    return best;
+}
+
+bool support_inside(const fsa_ctx* c, int n, const double* X)
+{
+    for (int k = 0; k < n; ++k)
+        for (int d = 0; d < c->d.dim; ++d) {
+            const double x = X[(size_t)d * n + k];
+            if (!std::isfinite(x)) return false;
+            const double r0 = (x - c->d.lo[d]) / c->d.h - 0.5;
+            const double j0 = std::floor(r0) - 1.0;
+            if (j0 < 0.0 || j0 + 3.0 > (double)(c->G.n[d] - 1)) return false;
+        }
+    return true;
+}
+
+// Window box over all marker supports and the CSR list window cell -> markers (in marker
+// order).  Index bookkeeping only; the weights are computed on the device.
+int build_window(fsa_ctx* c)
+{
+    const int dim = c->d.dim, n = c->nm;
+    dfree(c->fwin);
+    dfree(c->cell_start);
+    dfree(c->cell_marker);
+    c->wcells = 0;
+    for (int k = 0; k < 3; ++k) { c->wlo[k] = 0; c->wn[k] = 1; }
+    if (n == 0) { c->wn[0] = c->wn[1] = c->wn[2] = 0; return FSA_OK; }
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    std::vector<int> j0((size_t)n * 3, 0);
+    for (int d = 0; d < dim; ++d) {
+        lo[d] = 1 << 30;
+        hi[d] = -(1 << 30);
+        for (int k = 0; k < n; ++k) {
+            const double r0 = (c->hX[(size_t)d * n + k] - c->d.lo[d]) / c->d.h - 0.5;
+            const int j = (int)std::floor(r0) - 1;
+            j0[(size_t)k * 3 + d] = j;
+            lo[d] = std::min(lo[d], j);
+            hi[d] = std::max(hi[d], j + 3);
+        }
+        c->wlo[d] = lo[d];
+        c->wn[d] = hi[d] - lo[d] + 1;
+    }
+    const long long wcells = (long long)c->wn[0] * c->wn[1] * c->wn[2];
+    if (wcells > (1ll << 26)) return fail(c, FSA_EINVAL, "marker supports span too large a box");
+    c->wcells = wcells;
+    std::vector<int> count((size_t)wcells + 1, 0);
+    const int mz = dim == 3 ? 4 : 1;
+    auto cell_of = [&](int k, int dx, int dy, int dz) {
+        const long long i = j0[(size_t)k * 3] + dx - c->wlo[0];
+        const long long j = j0[(size_t)k * 3 + 1] + dy - c->wlo[1];
+        const long long l = dim == 3 ? j0[(size_t)k * 3 + 2] + dz - c->wlo[2] : 0;
+        return (l * c->wn[1] + j) * c->wn[0] + i;
+    };
+    for (int k = 0; k < n; ++k)
+        for (int dz = 0; dz < mz; ++dz)
+            for (int dy = 0; dy < 4; ++dy)
+                for (int dx = 0; dx < 4; ++dx) count[(size_t)cell_of(k, dx, dy, dz) + 1]++;
+    for (long long w = 0; w < wcells; ++w) count[(size_t)w + 1] += count[(size_t)w];
+    std::vector<int> fillp(count.begin(), count.end() - 1);
+    std::vector<int> marker((size_t)count[(size_t)wcells]);
+    for (int k = 0; k < n; ++k)
+        for (int dz = 0; dz < mz; ++dz)
+            for (int dy = 0; dy < 4; ++dy)
+                for (int dx = 0; dx < 4; ++dx) marker[(size_t)fillp[(size_t)cell_of(k, dx, dy, dz)]++] = k;
+    int rc;
+    if ((rc = dalloc(c, c->fwin, (size_t)dim * wcells)) != FSA_OK) return rc;
+    if ((rc = dalloc(c, c->cell_start, (size_t)wcells + 1)) != FSA_OK) return rc;
+    if ((rc = dalloc(c, c->cell_marker, marker.size())) != FSA_OK) return rc;
+    HIPCHK(c, hipMemcpy(c->cell_start, count.data(), sizeof(int) * count.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->cell_marker, marker.data(), sizeof(int) * marker.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemset(c->fwin, 0, sizeof(double) * (size_t)dim * wcells));
+    return FSA_OK;
+}
+
+IBArgs ib_args(const fsa_ctx* c)
+{
+    IBArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.nm = c->nm;
+    A.X = c->X;
+    A.dV = c->dV;
+    A.U = c->U;
+    A.motion = c->motion;
+    A.omega = c->omega;
+    A.xi = c->xi;
+    A.xi_n = c->xi_n;
+    A.F = c->F;
+    A.alpha = c->d.ib_alpha;
+    A.beta = c->d.ib_beta;
+    A.fwin = c->fwin;
+    for (int k = 0; k < 3; ++k) {
+        A.wlo[k] = c->wlo[k];
+        A.wn[k] = c->wn[k];
+    }
+    A.cell_start = c->cell_start;
+    A.cell_marker = c->cell_marker;
+    return A;
+}
+
+bool ib_active(const fsa_ctx* c) { return (c->d.terms & FSA_TERM_IB) && c->nm > 0; }
+
+// One right-hand-side evaluation on Qs into the stage kernel: alpha reduction, penalty
+// step, fused stencil/update kernel.
+int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, int slot, int stage, double ca,
+                  double cb, double dt, int mode_rhs)
+{
+    unsigned long long* bits = c->abits + 3 * slot;
+    int e = launch_alpha(c->G, c->P, Qs, bits, c->stream);
+    if (e) return hipcheck(c, (hipError_t)e, "alpha reduction launch");
+    if (ib_active(c)) {
+        IBArgs A = ib_args(c);
+        A.Qs = Qs;
+        A.stage = stage;
+        A.ca = ca;
+        A.cb = cb;
+        A.dt = dt;
+        e = launch_ib_stage(c->G, c->P, A, c->stream);
+        if (e) return hipcheck(c, (hipError_t)e, "IB stage launch");
+    }
+    StageArgs S;
+    std::memset(&S, 0, sizeof S);
+    S.Qs = Qs;
+    S.Qn = Qn;
+    S.out = out;
+    S.alpha_bits = bits;
+    S.fwin = ib_active(c) ? c->fwin : nullptr;
+    for (int k = 0; k < 3; ++k) {
+        S.wlo[k] = c->wlo[k];
+        S.wn[k] = c->wn[k];
+    }
+    S.ca = ca;
+    S.cb = cb;
+    S.dt = dt;
+    S.mode_rhs = mode_rhs;
+    S.ty = c->ty;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (c->timing) {
+        if (c->tused + 2 > c->tev.size()) {
+            for (int k = 0; k < 2; ++k) {
+                hipEvent_t ev;
+                HIPCHK(c, hipEventCreate(&ev));
+                c->tev.push_back(ev);
+            }
+        }
+        t0 = c->tev[c->tused];
+        t1 = c->tev[c->tused + 1];
+        c->tused += 2;
+        HIPCHK(c, hipEventRecord(t0, c->stream));
+    }
+    e = launch_stage2d(c->G, c->P, c->d.scheme, S, c->stream);
+    if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch");
+    if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
+    return FSA_OK;
+}
+
+bool bits_finite(unsigned long long b)
+{
+    double v;
+    std::memcpy(&v, &b, sizeof v);
+    return std::isfinite(v);
+}
+
+// Check the wave speeds of the previous step (nan_check only).
+int check_previous(fsa_ctx* c)
+{
+    if (!c->d.nan_check || !c->alpha_pending) return c->nonfinite ? FSA_ENONFINITE : FSA_OK;
+    HIPCHK(c, hipEventSynchronize(c->ev_alpha));
+    c->alpha_pending = false;
+    for (int k = 0; k < 9; ++k) {
+        const int d = k % 3;
+        if (d < c->d.dim && !bits_finite(c->h_abits[k])) c->nonfinite = 1;
+    }
+    if (c->nonfinite) return fail(c, FSA_ENONFINITE, "non-finite wave speed in the state");
+    return FSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fsa_abi_version(void) { return FSA_ABI_VERSION; }
+
+const char* fsa_status_str(int32_t s)
+{
+    switch (s) {
+        case FSA_OK: return "ok";
+        case FSA_EINVAL: return "invalid argument";
+        case FSA_ENOMEM: return "out of device memory";
+        case FSA_EDEVICE: return "device error";
+        case FSA_ENONFINITE: return "non-finite state";
+        case FSA_ESTATE: return "bad state";
+        case FSA_EUNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+const char* fsa_last_error(const fsa_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
+{
+    if (!out) return FSA_EINVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = validate(desc, why);
+    if (rc != FSA_OK) {
+        std::fprintf(stderr, "fsa_init: %s\n", why.c_str());
+        return rc;
+    }
+    fsa_ctx* c = new (std::nothrow) fsa_ctx();
+    if (!c) return FSA_ENOMEM;
+    c->d = *desc;
+    c->stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&c->device);
+    c->nq = desc->dim + 2;
+    build_consts(c);
+    c->ncell = c->G.ncell;
+    c->ty = choose_ty(c->G);
+    if ((rc = dalloc(c, c->Qa, (size_t)c->nq * c->ncell)) != FSA_OK ||
+        (rc = dalloc(c, c->Qb, (size_t)c->nq * c->ncell)) != FSA_OK ||
+        (rc = dalloc(c, c->abits, 12)) != FSA_OK) {
+        fsa_destroy(c);
+        return rc;
+    }
+    if (hipHostMalloc((void**)&c->h_abits, 12 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_alpha, hipEventDisableTiming) != hipSuccess) {
+        fsa_destroy(c);
+        return FSA_ENOMEM;
+    }
+    if (hipMemset(c->abits, 0, 12 * sizeof(unsigned long long)) != hipSuccess) {
+        fsa_destroy(c);
+        return FSA_EDEVICE;
+    }
+    *out = c;
+    return FSA_OK;
+}
+
+int32_t fsa_destroy(fsa_ctx* c)
+{
+    if (!c) return FSA_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    dfree(c->Qa);
+    dfree(c->Qb);
+    dfree(c->abits);
+    dfree(c->X);
+    dfree(c->dV);
+    dfree(c->U);
+    dfree(c->xi);
+    dfree(c->xi_n);
+    dfree(c->F);
+    dfree(c->fwin);
+    dfree(c->cell_start);
+    dfree(c->cell_marker);
+    dfree(c->Xp);
+    if (c->h_abits) (void)hipHostFree(c->h_abits);
+    for (hipEvent_t ev : c->tev) (void)hipEventDestroy(ev);
+    if (c->ev_alpha) (void)hipEventDestroy(c->ev_alpha);
+    delete c;
+    return FSA_OK;
+}
+
+int32_t fsa_set_markers(fsa_ctx* c, int32_t n, const double* X, const double* dV, const double* U, int32_t motion,
+                        double omega)
+{
+    if (!c) return FSA_EINVAL;
+    if (n < 0 || (n > 0 && (!X || !dV))) return fail(c, FSA_EINVAL, "bad marker arrays");
+    if (motion < FSA_STATIC || motion > FSA_EXTERNAL) return fail(c, FSA_EINVAL, "bad motion");
+    if (n > 0 && !support_inside(c, n, X)) return fail(c, FSA_EINVAL, "a marker support leaves the grid");
+    HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+    const int dim = c->d.dim;
+    c->nm = n;
+    c->motion = motion;
+    c->omega = omega;
+    c->hX.assign(X ? X : nullptr, X ? X + (size_t)dim * n : nullptr);
+    const size_t ln = (size_t)dim * (n > 0 ? n : 1);
+    int rc;
+    if ((rc = dalloc(c, c->X, ln)) != FSA_OK || (rc = dalloc(c, c->dV, (size_t)(n > 0 ? n : 1))) != FSA_OK ||
+        (rc = dalloc(c, c->U, ln)) != FSA_OK || (rc = dalloc(c, c->xi, ln)) != FSA_OK ||
+        (rc = dalloc(c, c->xi_n, ln)) != FSA_OK || (rc = dalloc(c, c->F, ln)) != FSA_OK)
+        return rc;
+    HIPCHK(c, hipMemset(c->U, 0, sizeof(double) * ln));
+    HIPCHK(c, hipMemset(c->xi, 0, sizeof(double) * ln));
+    HIPCHK(c, hipMemset(c->xi_n, 0, sizeof(double) * ln));
+    HIPCHK(c, hipMemset(c->F, 0, sizeof(double) * ln));
+    if (n > 0) {
+        HIPCHK(c, hipMemcpy(c->X, X, sizeof(double) * dim * n, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->dV, dV, sizeof(double) * n, hipMemcpyHostToDevice));
+        if (U) HIPCHK(c, hipMemcpy(c->U, U, sizeof(double) * dim * n, hipMemcpyHostToDevice));
+    }
+    return build_window(c);
+}
+
+int32_t fsa_set_marker_kinematics(fsa_ctx* c, const double* X, const double* U)
+{
+    if (!c) return FSA_EINVAL;
+    if (c->nm == 0 || c->motion != FSA_EXTERNAL) return fail(c, FSA_ESTATE, "markers are not EXTERNAL");
+    if (!X) return fail(c, FSA_EINVAL, "X is NULL");
+    if (!support_inside(c, c->nm, X)) return fail(c, FSA_EINVAL, "a marker support leaves the grid");
+    HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+    const int dim = c->d.dim, n = c->nm;
+    c->hX.assign(X, X + (size_t)dim * n);
+    HIPCHK(c, hipMemcpy(c->X, X, sizeof(double) * dim * n, hipMemcpyHostToDevice));
+    if (U) HIPCHK(c, hipMemcpy(c->U, U, sizeof(double) * dim * n, hipMemcpyHostToDevice));
+    else HIPCHK(c, hipMemset(c->U, 0, sizeof(double) * dim * n));
+    return build_window(c);
+}
+
+int32_t fsa_set_probes(fsa_ctx* c, int32_t n, const double* Xp)
+{
+    if (!c) return FSA_EINVAL;
+    if (n < 0 || (n > 0 && !Xp)) return fail(c, FSA_EINVAL, "bad probe array");
+    if (n > 0 && !support_inside(c, n, Xp)) return fail(c, FSA_EINVAL, "a probe support leaves the grid");
+    HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+    c->np = n;
+    int rc = dalloc(c, c->Xp, (size_t)c->d.dim * (n > 0 ? n : 1));
+    if (rc != FSA_OK) return rc;
+    if (n > 0) HIPCHK(c, hipMemcpy(c->Xp, Xp, sizeof(double) * c->d.dim * n, hipMemcpyHostToDevice));
+    return FSA_OK;
+}
+
+int32_t fsa_alpha(fsa_ctx* c, const double* d_Q, double* alpha)
+{
+    if (!c || !d_Q || !alpha) return FSA_EINVAL;
+    unsigned long long* bits = c->abits + 9;
+    int e = launch_alpha(c->G, c->P, d_Q, bits, c->stream);
+    if (e) return hipcheck(c, (hipError_t)e, "alpha launch");
+    unsigned long long hb[3];
+    HIPCHK(c, hipMemcpyAsync(hb, bits, sizeof hb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int d = 0; d < 3; ++d) {
+        if (d < c->d.dim) std::memcpy(&alpha[d], &hb[d], sizeof(double));
+        else alpha[d] = 0.0;
+    }
+    return FSA_OK;
+}
+
+int32_t fsa_rhs(fsa_ctx* c, const double* d_Q, double* d_L)
+{
+    if (!c || !d_Q || !d_L) return FSA_EINVAL;
+    if ((const void*)d_Q == (const void*)d_L) return fail(c, FSA_EINVAL, "d_L aliases d_Q");
+    c->P.step = c->step;
+    return enqueue_stage(c, d_Q, nullptr, d_L, 0, 0, 0.0, 1.0, 0.0, 1);
+}
+
+int32_t fsa_rk3_step(fsa_ctx* c, double* d_Q, double dt)
+{
+    if (!c || !d_Q) return FSA_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, FSA_EINVAL, "dt must be positive");
+    int rc = check_previous(c);
+    if (rc != FSA_OK) return rc;
+    c->P.step = c->step;
+    if ((rc = enqueue_stage(c, d_Q, nullptr, c->Qa, 0, 1, 0.0, 1.0, dt, 0)) != FSA_OK) return rc;
+    if ((rc = enqueue_stage(c, c->Qa, d_Q, c->Qb, 1, 2, 0.75, 0.25, dt, 0)) != FSA_OK) return rc;
+    if ((rc = enqueue_stage(c, c->Qb, d_Q, d_Q, 2, 3, 1.0 / 3.0, 2.0 / 3.0, dt, 0)) != FSA_OK) return rc;
+    if (c->d.nan_check) {
+        HIPCHK(c, hipMemcpyAsync(c->h_abits, c->abits, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipEventRecord(c->ev_alpha, c->stream));
+        c->alpha_pending = true;
+    }
+    c->t += dt;
+    c->step += 1;
+    return FSA_OK;
+}
+
+int32_t fsa_ib_interp(fsa_ctx* c, const double* d_field, int32_t ncomp, double* d_out)
+{
+    if (!c || !d_field || !d_out || ncomp < 1) return FSA_EINVAL;
+    int e = launch_interp(c->G, c->nm, c->X, d_field, ncomp, d_out, c->stream);
+    return e ? hipcheck(c, (hipError_t)e, "interp launch") : FSA_OK;
+}
+
+int32_t fsa_ib_spread(fsa_ctx* c, const double* d_F, int32_t ncomp, double* d_field, double scale)
+{
+    if (!c || !d_F || !d_field || ncomp < 1) return FSA_EINVAL;
+    if (c->nm == 0) return FSA_OK;
+    IBArgs A = ib_args(c);
+    int e = launch_spread(c->G, A, d_F, ncomp, d_field, scale, c->stream);
+    return e ? hipcheck(c, (hipError_t)e, "spread launch") : FSA_OK;
+}
+
+int32_t fsa_probe_dp(fsa_ctx* c, const double* d_Q, double* d_dp)
+{
+    if (!c || !d_Q || !d_dp) return FSA_EINVAL;
+    int e = launch_probe_dp(c->G, c->P, c->np, c->Xp, d_Q, d_dp, c->stream);
+    return e ? hipcheck(c, (hipError_t)e, "probe launch") : FSA_OK;
+}
+
+int32_t fsa_marker_force(fsa_ctx* c, double* h_F)
+{
+    if (!c || !h_F) return FSA_EINVAL;
+    if (c->nm == 0) return FSA_OK;
+    HIPCHK(c, hipMemcpyAsync(h_F, c->F, sizeof(double) * c->d.dim * c->nm, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FSA_OK;
+}
+
+int32_t fsa_get_state(fsa_ctx* c, double* h_xi, double* t, int64_t* step)
+{
+    if (!c) return FSA_EINVAL;
+    if (h_xi && c->nm > 0) {
+        HIPCHK(c, hipMemcpyAsync(h_xi, c->xi, sizeof(double) * c->d.dim * c->nm, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (t) *t = c->t;
+    if (step) *step = c->step;
+    return FSA_OK;
+}
+
+int32_t fsa_set_state(fsa_ctx* c, const double* h_xi, double t, int64_t step)
+{
+    if (!c) return FSA_EINVAL;
+    if (step < 0) return fail(c, FSA_EINVAL, "negative step");
+    if (h_xi && c->nm > 0) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpy(c->xi, h_xi, sizeof(double) * c->d.dim * c->nm, hipMemcpyHostToDevice));
+    }
+    c->t = t;
+    c->step = step;
+    return FSA_OK;
+}
+
+int32_t fsa_timing_enable(fsa_ctx* c, int32_t on)
+{
+    if (!c) return FSA_EINVAL;
+    c->timing = on != 0;
+    return FSA_OK;
+}
+
+int32_t fsa_timing_read(fsa_ctx* c, double* ms, int64_t* launches)
+{
+    if (!c || !ms || !launches) return FSA_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double total = 0.0;
+    for (size_t k = 0; k + 1 < c->tused; k += 2) {
+        float e = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&e, c->tev[k], c->tev[k + 1]));
+        total += e;
+    }
+    *ms = total;
+    *launches = (int64_t)(c->tused / 2);
+    c->tused = 0;
+    return FSA_OK;
+}
+
+int32_t fsa_sync(fsa_ctx* c)
+{
+    if (!c) return FSA_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return check_previous(c);
+}
+
+int32_t fsa_stats_get(fsa_ctx* c, fsa_stats* out)
+{
+    if (!c || !out) return FSA_EINVAL;
+    unsigned long long hb[3];
+    HIPCHK(c, hipMemcpyAsync(hb, c->abits + 6, sizeof hb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::memset(out, 0, sizeof *out);
+    for (int d = 0; d < 3; ++d) {
+        if (d < c->d.dim) std::memcpy(&out->alpha[d], &hb[d], sizeof(double));
+        if (d < c->d.dim && !bits_finite(hb[d])) c->nonfinite = 1;
+    }
+    out->t = c->t;
+    out->step = c->step;
+    out->nonfinite = c->nonfinite;
+    out->n_markers = c->nm;
+    out->n_probes = c->np;
+    out->window_cells = (int32_t)c->wcells;
+    return FSA_OK;
+}
+
+}  // extern "C"

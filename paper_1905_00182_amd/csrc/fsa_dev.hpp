@@ -1,0 +1,215 @@
+// Device-side building blocks of the gfx950 solver: grid/physics descriptors passed to the
+// kernels by value, boundary ghosts, the ideal-gas closure, the fifth-order reconstructions,
+// the four-point delta and the sponge profile.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fsa {
+
+enum : int { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_INFLOW = 2 };
+enum : int { WENO5JS = 0, TENO5 = 1 };
+enum : int { T_CONVX = 1, T_CONVY = 2, T_CONVZ = 4, T_VISC = 8, T_IB = 16, T_SPONGE = 32 };
+
+// Grid and physics constants, copied into every kernel's argument block.
+struct Grid {
+    int dim;
+    int n[3];
+    long long ncell;
+    double lo[3];
+    double h, inv_h;
+    int bc[3][2];
+};
+
+struct Phys {
+    double gamma, gm1, inv_gm1;
+    double mu;
+    double prim_inf[5];
+    double q_inf[5];          // conserved far-field state
+    double inflow_amp;
+    unsigned long long seed;
+    long long step;           // step counter used as the inflow-noise counter
+    double sw[3][2];          // sponge widths
+    double sigma;             // sponge sigma_max
+    double weno_eps, teno_ct, teno_eps;
+    int terms;
+};
+
+// ---------------------------------------------------------------------------------------
+// Counter-based SplitMix64 (Steele, Lea & Flood 2014): output number ctr of the generator
+// seeded with seed is the finaliser applied to seed + (ctr + 1) * golden increment.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t ctr)
+{
+    uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double u01(uint64_t r) { return (double)(r >> 11) * 0x1.0p-53; }
+
+// Resolve one direction's index against its boundary; records the first inflow side.
+__device__ __forceinline__ int resolve_index(int i, int n, int bclo, int bchi, int dir, int& inflow,
+                                             int& side, int& depth)
+{
+    if (i < 0) {
+        if (bclo == BC_PERIODIC) return ((i % n) + n) % n;
+        if (bclo == BC_INFLOW && !inflow) { inflow = 1; side = 2 * dir; depth = -i; }
+        return 0;
+    }
+    if (i >= n) {
+        if (bchi == BC_PERIODIC) return i % n;
+        if (bchi == BC_INFLOW && !inflow) { inflow = 1; side = 2 * dir + 1; depth = i - n + 1; }
+        return n - 1;
+    }
+    return i;
+}
+
+// Conserved inflow ghost state: far field with the seeded velocity perturbation.  Evaluated
+// without contraction, one rounding per operation, so that an unperturbed ghost equals the
+// far-field state exactly (a uniform free stream then has an exactly zero right-hand side).
+template <int DIM>
+__device__ __forceinline__ void inflow_state(const Phys& P, long long ncell, long long lin, int side, int depth,
+                                             double* q)
+{
+#pragma clang fp contract(off)
+    const double rho = P.prim_inf[0];
+    double ke = 0.0;
+    q[0] = rho;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double u = P.prim_inf[1 + a];
+        if (P.inflow_amp != 0.0) {
+            const uint64_t ctr = ((((uint64_t)P.step * 6ull + (uint64_t)side) * 8ull + (uint64_t)depth)
+                                      * (uint64_t)ncell + (uint64_t)lin) * 3ull + (uint64_t)a;
+            u += P.inflow_amp * (2.0 * u01(splitmix64(P.seed, ctr)) - 1.0);
+        }
+        q[1 + a] = rho * u;
+        ke += u * u;
+    }
+    q[DIM + 1] = P.prim_inf[4] / P.gm1 + 0.5 * rho * ke;
+}
+
+// State at a possibly out-of-range cell (i, j, k): boundary ghosts resolved x, then y, then z.
+template <int DIM>
+__device__ __forceinline__ void fetch_state(const double* __restrict__ Q, const Grid& G, const Phys& P, int i,
+                                            int j, int k, double* q)
+{
+    int inflow = 0, side = 0, depth = 0;
+    i = resolve_index(i, G.n[0], G.bc[0][0], G.bc[0][1], 0, inflow, side, depth);
+    j = resolve_index(j, G.n[1], G.bc[1][0], G.bc[1][1], 1, inflow, side, depth);
+    if (DIM == 3) k = resolve_index(k, G.n[2], G.bc[2][0], G.bc[2][1], 2, inflow, side, depth);
+    else k = 0;
+    const long long lin = ((long long)k * G.n[1] + j) * G.n[0] + i;
+    if (!inflow) {
+#pragma unroll
+        for (int c = 0; c < DIM + 2; ++c) q[c] = Q[c * G.ncell + lin];
+        return;
+    }
+    inflow_state<DIM>(P, G.ncell, lin, side, depth, q);
+}
+
+// ---------------------------------------------------------------------------------------
+// Fifth-order reconstruction at a face from five upwind-ordered values (a..e) =
+// (v_{i-2}, ..., v_{i+2}): three third-order candidates with Jiang-Shu smoothness indicators,
+// weighted WENO5-JS (alpha_k = d_k / (eps + beta_k)^2) or TENO5 (sharp cut-off of
+// gamma_k = (1 + tau5 / (beta_k + eps))^6 at C_T, kept stencils weighted by d_k).
+// Both are evaluated with a single division.
+// ---------------------------------------------------------------------------------------
+struct Recon {
+    double eps;   // WENO epsilon or TENO epsilon
+    double ct;    // TENO cut-off
+};
+
+template <int SCHEME>
+__device__ __forceinline__ double recon5(double a, double b, double c, double d, double e, const Recon& R)
+{
+    const double q0 = fma(11.0 / 6.0, c, fma(-7.0 / 6.0, b, (1.0 / 3.0) * a));
+    const double q1 = fma(1.0 / 3.0, d, fma(5.0 / 6.0, c, (-1.0 / 6.0) * b));
+    const double q2 = fma(-1.0 / 6.0, e, fma(5.0 / 6.0, d, (1.0 / 3.0) * c));
+    const double s0 = fma(-2.0, b, a) + c, t0 = fma(-4.0, b, a) + 3.0 * c;
+    const double s1 = fma(-2.0, c, b) + d, t1 = b - d;
+    const double s2 = fma(-2.0, d, c) + e, t2 = fma(-4.0, d, 3.0 * c) + e;
+    const double b0 = fma(13.0 / 12.0 * s0, s0, 0.25 * t0 * t0);
+    const double b1 = fma(13.0 / 12.0 * s1, s1, 0.25 * t1 * t1);
+    const double b2 = fma(13.0 / 12.0 * s2, s2, 0.25 * t2 * t2);
+    if (SCHEME == WENO5JS) {
+        const double e0 = R.eps + b0, e1 = R.eps + b1, e2 = R.eps + b2;
+        const double p0 = e0 * e0, p1 = e1 * e1, p2 = e2 * e2;
+        // alpha_k proportional to d_k * prod_{j != k} (eps + beta_j)^2
+        const double w0 = 0.1 * (p1 * p2), w1 = 0.6 * (p0 * p2), w2 = 0.3 * (p0 * p1);
+        const double num = fma(w0, q0, fma(w1, q1, w2 * q2));
+        return num / (w0 + w1 + w2);
+    } else {
+        const double tau = fabs(b0 - b2);
+        const double e0 = b0 + R.eps, e1 = b1 + R.eps, e2 = b2 + R.eps;
+        const double e01 = e0 * e1;
+        const double inv = 1.0 / (e01 * e2);
+        const double r0 = (e1 * e2) * inv, r1 = (e0 * e2) * inv, r2 = e01 * inv;  // 1 / e_k
+        const double x0 = fma(tau, r0, 1.0), x1 = fma(tau, r1, 1.0), x2 = fma(tau, r2, 1.0);
+        const double c0 = x0 * x0 * x0, c1 = x1 * x1 * x1, c2 = x2 * x2 * x2;
+        const double g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2;
+        const double lim = R.ct * (g0 + g1 + g2);
+        const double d0 = g0 < lim ? 0.0 : 0.1;
+        const double d1 = g1 < lim ? 0.0 : 0.6;
+        const double d2 = g2 < lim ? 0.0 : 0.3;
+        const double num = fma(d0, q0, fma(d1, q1, d2 * q2));
+        return num / (d0 + d1 + d2);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Peskin four-point function (piecewise on |r| < 1, 1 <= |r| < 2).
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double delta4(double r)
+{
+    const double x = fabs(r);
+    if (x < 1.0) return 0.125 * (3.0 - 2.0 * x + sqrt(fma(-4.0 * x, x, fma(4.0, x, 1.0))));
+    if (x < 2.0) return 0.125 * (5.0 - 2.0 * x - sqrt(fma(-4.0 * x, x, fma(12.0, x, -7.0))));
+    return 0.0;
+}
+
+// Position in cell-index units along one direction: (X - lo) / h - 1/2.
+__device__ __forceinline__ double cell_coord(double X, double lo, double h) { return (X - lo) / h - 0.5; }
+
+// Four-point support along one direction: first cell j0 and the weights lambda(r0 - j) of
+// cells j = j0..j0+3.
+__device__ __forceinline__ void support4(double X, double lo, double h, int& j0, double* w)
+{
+    const double r0 = cell_coord(X, lo, h);
+    j0 = (int)floor(r0) - 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) w[m] = delta4(r0 - (double)(j0 + m));
+}
+
+// ---------------------------------------------------------------------------------------
+// Cubic sponge rate at cell (i, j, k).
+// ---------------------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ double sponge_rate(const Grid& G, const Phys& P, int i, int j, int k)
+{
+    double eta = 0.0;
+    const int idx[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double x = G.lo[d] + ((double)idx[d] + 0.5) * G.h;
+        const double lo = G.lo[d], hi = G.lo[d] + (double)G.n[d] * G.h;
+        const double wl = P.sw[d][0], wh = P.sw[d][1];
+        if (wl > 0.0 && x < lo + wl) eta = fmax(eta, (lo + wl - x) / wl);
+        if (wh > 0.0 && x > hi - wh) eta = fmax(eta, (x - (hi - wh)) / wh);
+    }
+    eta = fmin(eta, 1.0);
+    return P.sigma * (eta * eta * eta);
+}
+
+// NaN-propagating maximum of non-negative doubles through their bit patterns: for x >= 0
+// the unsigned order of the bits is the numeric order, and every NaN pattern sorts above
+// +Inf.
+__device__ __forceinline__ unsigned long long max_bits(unsigned long long a, unsigned long long b)
+{
+    return a > b ? a : b;
+}
+
+}  // namespace fsa

@@ -1,0 +1,54 @@
+// Internal interfaces between the C-ABI layer (fsa_api.hip) and the kernel launchers.
+#pragma once
+
+#include "fsa_dev.hpp"
+
+namespace fsa {
+
+// Arguments of the fused right-hand-side / stage kernels.
+struct StageArgs {
+    const double* Qs;                      // state the right-hand side is evaluated on
+    const double* Qn;                      // step-start state (read only when ca != 0)
+    double* out;                           // L (mode_rhs) or ca Qn + cb (Qs + dt L)
+    const unsigned long long* alpha_bits;  // global LF speeds of Qs, as bit patterns [3]
+    const double* fwin;                    // IB force density on the window box [dim][cells]
+    int wlo[3];                            // window box origin (cell indices)
+    int wn[3];                             // window box extent
+    double ca, cb, dt;
+    int mode_rhs;
+    int ty;                                // rows (2D) per wave segment
+};
+
+// Arguments of the per-stage immersed-boundary kernel.
+struct IBArgs {
+    const double* Qs;
+    int nm;
+    const double* X;       // [dim][nm]
+    const double* dV;      // [nm]
+    const double* U;       // [dim][nm]
+    int motion;            // 0 static, 1 rotating, 2 external
+    double omega;
+    double* xi;            // penalty integral (stage value, updated in place)
+    double* xi_n;          // penalty integral at the step start
+    double* F;             // penalty force [dim][nm]
+    int stage;             // 0: right-hand side only; 1..3: SSP-RK3 stage
+    double ca, cb, dt;
+    double alpha, beta;    // penalty constants
+    double* fwin;          // out: spread force density on the window box
+    int wlo[3], wn[3];
+    const int* cell_start; // CSR window cell -> markers (increasing marker index)
+    const int* cell_marker;
+};
+
+int launch_stage2d(const Grid& G, const Phys& P, int scheme, const StageArgs& A, hipStream_t s);
+int stage2d_ncolx(int nx);
+int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* bits, hipStream_t s);
+int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s);
+int launch_interp(const Grid& G, int npts, const double* X, const double* field, int ncomp, double* out,
+                  hipStream_t s);
+int launch_spread(const Grid& G, const IBArgs& A, const double* F, int ncomp, double* field, double scale,
+                  hipStream_t s);
+int launch_probe_dp(const Grid& G, const Phys& P, int np, const double* Xp, const double* Q, double* dp,
+                    hipStream_t s);
+
+}  // namespace fsa

@@ -1,0 +1,296 @@
+// Immersed-boundary kernels (Sec. 2, Eqs. (7)-(11)), probes and the global Lax-Friedrichs
+// wave-speed reduction.
+//
+// The penalty step runs in one workgroup per stage: every thread takes markers, gathers the
+// fluid velocity m / rho over the 4^dim support with the tensor-product four-point weights,
+// forms F_f = alpha xi + beta (U_ib - U) and advances the penalty integral with the stage's
+// SSP-RK3 combination; after a barrier every thread takes cells of the window box (the
+// bounding box of all supports) and sums the spread force -F_k W_k dV_k / h^dim over that
+// cell's markers in increasing marker index (a deterministic gather).
+#include "fsa_impl.hpp"
+
+namespace fsa {
+
+namespace {
+
+constexpr int IB_THREADS = 1024;
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ unsigned long long wave_max_bits(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(v, off, 64);
+        v = max_bits(v, o);
+    }
+    return v;
+}
+
+// alpha_d = max over cells of |u_d| + c, NaN-propagating (bits of non-negative doubles).
+template <int DIM>
+__global__ __launch_bounds__(RED_THREADS) void k_alpha(Grid G, Phys P, const double* __restrict__ Q,
+                                                       unsigned long long* __restrict__ bits)
+{
+    __shared__ unsigned long long part[RED_THREADS / 64][DIM];
+    unsigned long long m[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) m[d] = 0ull;
+    const long long nc = G.ncell;
+    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < nc;
+         n += (long long)gridDim.x * blockDim.x) {
+        const double rho = Q[n];
+        const double inv = 1.0 / rho;
+        double u[DIM], ke = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            u[d] = Q[(1 + d) * nc + n] * inv;
+            ke = fma(Q[(1 + d) * nc + n], u[d], ke);
+        }
+        const double p = P.gm1 * (Q[(DIM + 1) * nc + n] - 0.5 * ke);
+        const double c = sqrt(P.gamma * p * inv);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            m[d] = max_bits(m[d], (unsigned long long)__double_as_longlong(fabs(u[d]) + c));
+    }
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const unsigned long long w = wave_max_bits(m[d]);
+        if (lane == 0) part[wid][d] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < DIM) {
+        unsigned long long v = 0ull;
+        for (int w = 0; w < RED_THREADS / 64; ++w) v = max_bits(v, part[w][threadIdx.x]);
+        atomicMax(&bits[threadIdx.x], v);
+    }
+}
+
+__global__ void k_zero_bits(unsigned long long* bits, int n)
+{
+    if (threadIdx.x < n) bits[threadIdx.x] = 0ull;
+}
+
+// Marker support: first cell and four weights per direction.
+template <int DIM>
+__device__ __forceinline__ void marker_support(const Grid& G, const double* X, int n, int k, int* j0,
+                                               double (*w)[4])
+{
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) support4(X[(long long)d * n + k], G.lo[d], G.h, j0[d], w[d]);
+}
+
+// Tensor-product weight of cell (ci, cj, ck) for point k.
+template <int DIM>
+__device__ __forceinline__ double cell_weight(const Grid& G, const double* X, int n, int k, int ci, int cj, int ck)
+{
+    double W = delta4(cell_coord(X[k], G.lo[0], G.h) - (double)ci) *
+               delta4(cell_coord(X[(long long)n + k], G.lo[1], G.h) - (double)cj);
+    if (DIM == 3) W = W * delta4(cell_coord(X[2ll * n + k], G.lo[2], G.h) - (double)ck);
+    return W;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(IB_THREADS) void k_ib_stage(Grid G, Phys P, IBArgs A)
+{
+    const long long nc = G.ncell;
+    for (int k = threadIdx.x; k < A.nm; k += blockDim.x) {
+        int j0[3];
+        double w[3][4];
+        marker_support<DIM>(G, A.X, A.nm, k, j0, w);
+        double uib[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) uib[a] = 0.0;
+        for (int mz = 0; mz < (DIM == 3 ? 4 : 1); ++mz)
+            for (int my = 0; my < 4; ++my)
+#pragma unroll
+                for (int mx = 0; mx < 4; ++mx) {
+                    double W = w[0][mx] * w[1][my];
+                    if (DIM == 3) W = W * w[2][mz];
+                    const long long lin =
+                        ((long long)(DIM == 3 ? j0[2] + mz : 0) * G.n[1] + (j0[1] + my)) * G.n[0] + (j0[0] + mx);
+                    const double rho = A.Qs[lin];
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) uib[a] = fma(A.Qs[(1 + a) * nc + lin] / rho, W, uib[a]);
+                }
+        double U[DIM];
+        if (A.motion == 1) {
+            const double x = A.X[k], y = A.X[(long long)A.nm + k];
+            U[0] = -A.omega * y;
+            U[1] = A.omega * x;
+            if (DIM == 3) U[DIM - 1] = 0.0;
+        } else {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) U[a] = A.U[(long long)a * A.nm + k];
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const long long o = (long long)a * A.nm + k;
+            const double d = uib[a] - U[a];
+            double xs, xn;
+            if (A.stage <= 1) {
+                xs = A.xi[o];
+                xn = xs;
+                if (A.stage == 1) A.xi_n[o] = xs;
+            } else {
+                xs = A.xi[o];
+                xn = A.xi_n[o];
+            }
+            A.F[o] = fma(A.alpha, xs, A.beta * d);
+            if (A.stage == 1) A.xi[o] = fma(A.dt, d, xn);
+            else if (A.stage > 1) A.xi[o] = fma(A.ca, xn, A.cb * fma(A.dt, d, xs));
+        }
+    }
+    __syncthreads();
+    const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
+    const double hd = DIM == 3 ? G.h * G.h * G.h : G.h * G.h;
+    for (long long c = threadIdx.x; c < wcells; c += blockDim.x) {
+        const int ci = A.wlo[0] + (int)(c % A.wn[0]);
+        const int cj = A.wlo[1] + (int)((c / A.wn[0]) % A.wn[1]);
+        const int ck = A.wlo[2] + (int)(c / ((long long)A.wn[0] * A.wn[1]));
+        double f[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) f[a] = 0.0;
+        for (int e = A.cell_start[c]; e < A.cell_start[c + 1]; ++e) {
+            const int k = A.cell_marker[e];
+            const double s = cell_weight<DIM>(G, A.X, A.nm, k, ci, cj, ck) * A.dV[k];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) f[a] += -(A.F[(long long)a * A.nm + k] * s) / hd;
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) A.fwin[a * wcells + c] = f[a];
+    }
+}
+
+// Interpolation of ncomp fields to points (one thread per point).
+template <int DIM>
+__global__ void k_interp(Grid G, int npts, const double* __restrict__ X, const double* __restrict__ field,
+                         int ncomp, double* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npts) return;
+    int j0[3];
+    double w[3][4];
+    marker_support<DIM>(G, X, npts, k, j0, w);
+    for (int a = 0; a < ncomp; ++a) {
+        double acc = 0.0;
+        for (int mz = 0; mz < (DIM == 3 ? 4 : 1); ++mz)
+            for (int my = 0; my < 4; ++my)
+                for (int mx = 0; mx < 4; ++mx) {
+                    double W = w[0][mx] * w[1][my];
+                    if (DIM == 3) W = W * w[2][mz];
+                    const long long lin =
+                        ((long long)(DIM == 3 ? j0[2] + mz : 0) * G.n[1] + (j0[1] + my)) * G.n[0] + (j0[0] + mx);
+                    acc = fma(field[(long long)a * G.ncell + lin], W, acc);
+                }
+        out[(long long)a * npts + k] = acc;
+    }
+}
+
+// field[a] += scale * (-sum_k F_k W_k dV_k / h^dim) on the window cells (gather per cell).
+template <int DIM>
+__global__ void k_spread(Grid G, IBArgs A, const double* __restrict__ F, int ncomp, double* __restrict__ field,
+                         double scale)
+{
+    const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= wcells) return;
+    const int ci = A.wlo[0] + (int)(c % A.wn[0]);
+    const int cj = A.wlo[1] + (int)((c / A.wn[0]) % A.wn[1]);
+    const int ck = A.wlo[2] + (int)(c / ((long long)A.wn[0] * A.wn[1]));
+    const double hd = DIM == 3 ? G.h * G.h * G.h : G.h * G.h;
+    const long long lin = ((long long)(DIM == 3 ? ck : 0) * G.n[1] + cj) * G.n[0] + ci;
+    for (int a = 0; a < ncomp; ++a) {
+        double f = 0.0;
+        for (int e = A.cell_start[c]; e < A.cell_start[c + 1]; ++e) {
+            const int k = A.cell_marker[e];
+            const double W = cell_weight<DIM>(G, A.X, A.nm, k, ci, cj, ck);
+            f += -(F[(long long)a * A.nm + k] * (W * A.dV[k])) / hd;
+        }
+        field[(long long)a * G.ncell + lin] += scale * f;
+    }
+}
+
+// p - p_inf at probe points.
+template <int DIM>
+__global__ void k_probe_dp(Grid G, Phys P, int np, const double* __restrict__ Xp, const double* __restrict__ Q,
+                           double* __restrict__ dp)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    int j0[3];
+    double w[3][4];
+    marker_support<DIM>(G, Xp, np, k, j0, w);
+    const long long nc = G.ncell;
+    double acc = 0.0;
+    for (int mz = 0; mz < (DIM == 3 ? 4 : 1); ++mz)
+        for (int my = 0; my < 4; ++my)
+            for (int mx = 0; mx < 4; ++mx) {
+                double W = w[0][mx] * w[1][my];
+                if (DIM == 3) W = W * w[2][mz];
+                const long long lin =
+                    ((long long)(DIM == 3 ? j0[2] + mz : 0) * G.n[1] + (j0[1] + my)) * G.n[0] + (j0[0] + mx);
+                const double rho = Q[lin];
+                double ke = 0.0;
+                for (int a = 0; a < DIM; ++a) {
+                    const double m = Q[(1 + a) * nc + lin];
+                    ke = fma(m, m / rho, ke);
+                }
+                const double p = P.gm1 * (Q[(DIM + 1) * nc + lin] - 0.5 * ke);
+                acc = fma(p, W, acc);
+            }
+    dp[k] = acc - P.prim_inf[4];
+}
+
+}  // namespace
+
+int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* bits, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, s, bits, 3);
+    long long blocks = (G.ncell + RED_THREADS - 1) / RED_THREADS;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    if (G.dim == 3) hipLaunchKernelGGL(k_alpha<3>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, bits);
+    else hipLaunchKernelGGL(k_alpha<2>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, bits);
+    return (int)hipGetLastError();
+}
+
+int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s)
+{
+    if (G.dim == 3) hipLaunchKernelGGL(k_ib_stage<3>, dim3(1), dim3(IB_THREADS), 0, s, G, P, A);
+    else hipLaunchKernelGGL(k_ib_stage<2>, dim3(1), dim3(IB_THREADS), 0, s, G, P, A);
+    return (int)hipGetLastError();
+}
+
+int launch_interp(const Grid& G, int npts, const double* X, const double* field, int ncomp, double* out,
+                  hipStream_t s)
+{
+    if (npts <= 0) return 0;
+    const int blocks = (npts + 127) / 128;
+    if (G.dim == 3) hipLaunchKernelGGL(k_interp<3>, dim3(blocks), dim3(128), 0, s, G, npts, X, field, ncomp, out);
+    else hipLaunchKernelGGL(k_interp<2>, dim3(blocks), dim3(128), 0, s, G, npts, X, field, ncomp, out);
+    return (int)hipGetLastError();
+}
+
+int launch_spread(const Grid& G, const IBArgs& A, const double* F, int ncomp, double* field, double scale,
+                  hipStream_t s)
+{
+    const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
+    if (wcells <= 0) return 0;
+    const unsigned blocks = (unsigned)((wcells + 127) / 128);
+    if (G.dim == 3) hipLaunchKernelGGL(k_spread<3>, dim3(blocks), dim3(128), 0, s, G, A, F, ncomp, field, scale);
+    else hipLaunchKernelGGL(k_spread<2>, dim3(blocks), dim3(128), 0, s, G, A, F, ncomp, field, scale);
+    return (int)hipGetLastError();
+}
+
+int launch_probe_dp(const Grid& G, const Phys& P, int np, const double* Xp, const double* Q, double* dp,
+                    hipStream_t s)
+{
+    if (np <= 0) return 0;
+    const int blocks = (np + 127) / 128;
+    if (G.dim == 3) hipLaunchKernelGGL(k_probe_dp<3>, dim3(blocks), dim3(128), 0, s, G, P, np, Xp, Q, dp);
+    else hipLaunchKernelGGL(k_probe_dp<2>, dim3(blocks), dim3(128), 0, s, G, P, np, Xp, Q, dp);
+    return (int)hipGetLastError();
+}
+
+}  // namespace fsa

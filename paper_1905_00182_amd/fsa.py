@@ -1,0 +1,277 @@
+"""Thin ctypes binding of libfsa.so (the C ABI declared in include/fsa.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP kernels.
+Torch tensors provide device memory (their data pointers) and the HIP stream.  The library
+must have been built (``python -m paper_1905_00182_amd.build`` or ``__graft_entry__.build``);
+``lib()`` raises if it is missing rather than falling back to anything else.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsa.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+BC = {"periodic": 0, "extrap": 1, "inflow": 2}
+SCHEME = {"weno5js": 0, "teno5": 1}
+PRECISION = {"fp64": 0, "mixed32": 1}
+MOTION = {"static": 0, "rotating": 1, "external": 2}
+TERM = {"conv_x": 1, "conv_y": 2, "conv_z": 4, "visc": 8, "ib": 16, "sponge": 32, "all": 63}
+
+
+class FsaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class FsaDesc(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32),
+        ("n", C.c_int32 * 3),
+        ("lo", C.c_double * 3),
+        ("h", C.c_double),
+        ("bc", (C.c_int32 * 2) * 3),
+        ("gamma", C.c_double),
+        ("mu", C.c_double),
+        ("scheme", C.c_int32),
+        ("precision", C.c_int32),
+        ("terms", C.c_int32),
+        ("nan_check", C.c_int32),
+        ("weno_eps", C.c_double),
+        ("teno_ct", C.c_double),
+        ("teno_eps", C.c_double),
+        ("prim_inf", C.c_double * 5),
+        ("inflow_amp", C.c_double),
+        ("seed", C.c_uint64),
+        ("sponge_width", (C.c_double * 2) * 3),
+        ("sponge_sigma", C.c_double),
+        ("ib_alpha", C.c_double),
+        ("ib_beta", C.c_double),
+    ]
+
+
+class FsaStats(C.Structure):
+    _fields_ = [
+        ("alpha", C.c_double * 3),
+        ("t", C.c_double),
+        ("step", C.c_int64),
+        ("nonfinite", C.c_int32),
+        ("n_markers", C.c_int32),
+        ("n_probes", C.c_int32),
+        ("window_cells", C.c_int32),
+    ]
+
+
+_lib = None
+
+_SIGS = {
+    "fsa_abi_version": (C.c_int32, []),
+    "fsa_status_str": (C.c_char_p, [C.c_int32]),
+    "fsa_last_error": (C.c_char_p, [C.c_void_p]),
+    "fsa_init": (C.c_int32, [C.POINTER(FsaDesc), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "fsa_destroy": (C.c_int32, [C.c_void_p]),
+    "fsa_set_markers": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                    C.c_double]),
+    "fsa_set_marker_kinematics": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsa_set_probes": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "fsa_alpha": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsa_rhs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsa_rk3_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double]),
+    "fsa_ib_interp": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "fsa_ib_spread": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double]),
+    "fsa_probe_dp": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsa_marker_force": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fsa_get_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "fsa_set_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]),
+    "fsa_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "fsa_timing_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "fsa_sync": (C.c_int32, [C.c_void_p]),
+    "fsa_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(FsaStats)]),
+}
+
+
+def lib():
+    """Load libfsa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def make_desc(case, nan_check=False) -> FsaDesc:
+    d = FsaDesc()
+    d.dim = case.dim
+    for k in range(3):
+        d.n[k] = case.n[k]
+        d.lo[k] = case.lo[k]
+        for s in range(2):
+            d.bc[k][s] = BC[case.bc[k][s]]
+            d.sponge_width[k][s] = case.sponge_width[k][s]
+    d.h = case.h
+    d.gamma = case.gamma
+    d.mu = case.mu
+    d.scheme = SCHEME[case.scheme]
+    d.precision = PRECISION[case.precision]
+    d.terms = case.terms
+    d.nan_check = 1 if nan_check else 0
+    d.weno_eps = case.weno_eps
+    d.teno_ct = case.teno_ct
+    d.teno_eps = case.teno_eps
+    for k in range(5):
+        d.prim_inf[k] = case.prim_inf[k]
+    d.inflow_amp = case.inflow_amp
+    d.seed = case.seed
+    d.sponge_sigma = case.sponge_sigma
+    d.ib_alpha = case.ib_alpha
+    d.ib_beta = case.ib_beta
+    return d
+
+
+def _host(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One library context on the current HIP device and torch's current stream."""
+
+    def __init__(self, case, nan_check=False, stream=None):
+        import torch
+
+        self.torch = torch
+        self.case = case
+        self.dim = case.dim
+        self.nq = case.dim + 2
+        self.shape = (self.nq,) + case.shape
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.desc = make_desc(case, nan_check)
+        ctx = C.c_void_p()
+        self._check(lib().fsa_init(C.byref(self.desc), C.c_void_p(self.stream.cuda_stream), C.byref(ctx)), None)
+        self.ctx = ctx
+        self.nm = 0
+        self.np = 0
+        if case.markers is not None:
+            m = case.markers
+            self.set_markers(m["X"], m["dV"], m.get("U"), m.get("motion", "static"), m.get("omega", 0.0))
+        if case.probes is not None:
+            self.set_probes(case.probes)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().fsa_destroy(self.ctx)
+            self.ctx = None
+
+    __del__ = close
+
+    def _check(self, rc, ctx="self"):
+        if rc != OK:
+            c = self.ctx if ctx == "self" else None
+            msg = lib().fsa_last_error(c).decode() if c else lib().fsa_status_str(rc).decode()
+            raise FsaError(rc, msg)
+
+    def _state(self, Q):
+        t = self.torch
+        assert Q.dtype == t.float64 and Q.is_cuda and Q.is_contiguous(), "Q must be contiguous float64 on the GPU"
+        assert tuple(Q.shape) == self.shape, (tuple(Q.shape), self.shape)
+        return Q
+
+    # -- set-up
+    def set_markers(self, X, dV, U=None, motion="static", omega=0.0):
+        X, dV = _host(X), _host(dV)
+        Ua = _host(U) if U is not None else None
+        n = dV.shape[0]
+        self._check(lib().fsa_set_markers(self.ctx, n, X.ctypes.data, dV.ctypes.data,
+                                          Ua.ctypes.data if Ua is not None else None, MOTION[motion], omega))
+        self.nm = n
+
+    def set_marker_kinematics(self, X, U=None):
+        X = _host(X)
+        Ua = _host(U) if U is not None else None
+        self._check(lib().fsa_set_marker_kinematics(self.ctx, X.ctypes.data,
+                                                    Ua.ctypes.data if Ua is not None else None))
+
+    def set_probes(self, Xp):
+        Xp = _host(Xp)
+        n = Xp.shape[1] if Xp.ndim == 2 else 0
+        self._check(lib().fsa_set_probes(self.ctx, n, Xp.ctypes.data))
+        self.np = n
+
+    # -- field operations (asynchronous on the stream)
+    def alpha(self, Q):
+        out = np.zeros(3)
+        self._check(lib().fsa_alpha(self.ctx, _ptr(self._state(Q)), out.ctypes.data))
+        return out
+
+    def rhs(self, Q, out=None):
+        Q = self._state(Q)
+        L = out if out is not None else self.torch.empty_like(Q)
+        self._check(lib().fsa_rhs(self.ctx, _ptr(Q), _ptr(L)))
+        return L
+
+    def rk3_step(self, Q, dt):
+        self._check(lib().fsa_rk3_step(self.ctx, _ptr(self._state(Q)), dt))
+        return Q
+
+    def ib_interp(self, field):
+        ncomp = field.shape[0]
+        out = self.torch.empty((ncomp, self.nm), dtype=self.torch.float64, device=field.device)
+        self._check(lib().fsa_ib_interp(self.ctx, _ptr(field.contiguous()), ncomp, _ptr(out)))
+        return out
+
+    def ib_spread(self, F, field, scale=1.0):
+        assert field.is_contiguous()
+        self._check(lib().fsa_ib_spread(self.ctx, _ptr(F.contiguous()), F.shape[0], _ptr(field), scale))
+        return field
+
+    def probe_dp(self, Q, out=None):
+        dp = out if out is not None else self.torch.empty(self.np, dtype=self.torch.float64, device=Q.device)
+        self._check(lib().fsa_probe_dp(self.ctx, _ptr(self._state(Q)), _ptr(dp)))
+        return dp
+
+    # -- synchronising calls
+    def marker_force(self):
+        out = np.zeros((self.dim, self.nm))
+        self._check(lib().fsa_marker_force(self.ctx, out.ctypes.data))
+        return out
+
+    def get_state(self):
+        xi = np.zeros((self.dim, max(self.nm, 1)))
+        t = C.c_double()
+        step = C.c_int64()
+        self._check(lib().fsa_get_state(self.ctx, xi.ctypes.data, C.byref(t), C.byref(step)))
+        return xi[:, : self.nm], t.value, step.value
+
+    def set_state(self, xi, t, step):
+        xa = _host(xi) if xi is not None else None
+        self._check(lib().fsa_set_state(self.ctx, xa.ctypes.data if xa is not None else None, t, step))
+
+    def timing(self, on=True):
+        self._check(lib().fsa_timing_enable(self.ctx, 1 if on else 0))
+
+    def timing_read(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(lib().fsa_timing_read(self.ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def sync(self):
+        self._check(lib().fsa_sync(self.ctx))
+
+    def stats(self):
+        s = FsaStats()
+        self._check(lib().fsa_stats_get(self.ctx, C.byref(s)))
+        return s
