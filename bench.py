@@ -86,9 +86,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--scheme", default="teno5", choices=["teno5", "weno5js"])
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -100,20 +102,28 @@ def main():
     from paper_1905_00182_amd import fsa, workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": b.numel() * 8,
+                          "launches": 3}), flush=True)
+        return
     case = W.config2()
     if args.scheme != case.scheme:
         case = case.with_(scheme=args.scheme)
     Q = torch.from_numpy(W.config2_state(case)).cuda()
     s = fsa.Solver(case)
-    for _ in range(args.warmup):
-        s.rk3_step(Q, case.dt)
+    if args.warmup > 0:
+        s.rk3_steps(Q, case.dt, args.warmup)
     s.sync()
     s.timing(True)
     s.timing_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s.rk3_step(Q, case.dt)
+    s.rk3_steps(Q, case.dt, args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kms, launches = s.timing_read()

@@ -115,6 +115,7 @@ typedef struct fsa_stats {
     int32_t  n_markers;
     int32_t  n_probes;
     int32_t  window_cells;        /* cells of the box that holds every marker's support */
+    int32_t  rows_per_wave;       /* segment height the 2D stage kernel runs with (0 = not tuned yet) */
 } fsa_stats;
 
 int32_t     fsa_abi_version(void);
@@ -152,6 +153,10 @@ int32_t fsa_rhs(fsa_ctx* ctx, const double* d_Q, double* d_L);
  *   Q1 = Qn + dt L(Qn);  Q2 = 3/4 Qn + 1/4 (Q1 + dt L(Q1));  Qn+1 = 1/3 Qn + 2/3 (Q2 + dt L(Q2)),
  * the penalty integral advancing through the same stages; then t += dt, step += 1. */
 int32_t fsa_rk3_step(fsa_ctx* ctx, double* d_Q, double dt);
+/* nsteps consecutive fsa_rk3_step calls in one enqueue: the global Lax-Friedrichs speeds of
+ * each stage input are taken from the kernel that wrote that state, so only the first stage
+ * reduces d_Q on its own. */
+int32_t fsa_rk3_steps(fsa_ctx* ctx, double* d_Q, double dt, int32_t nsteps);
 /* Interpolate ncomp fields d_field[ncomp][ncell] to the markers (Eq. (8)):
  * d_out[a][k] = sum over the support of field_a * prod lambda. */
 int32_t fsa_ib_interp(fsa_ctx* ctx, const double* d_field, int32_t ncomp, double* d_out);

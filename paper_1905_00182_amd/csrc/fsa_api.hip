@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -15,10 +16,18 @@
 
 using namespace fsa;
 
+namespace {
+__global__ void k_clear_slots(unsigned long long* bits, int n)
+{
+    if ((int)threadIdx.x < n) bits[threadIdx.x] = 0ull;
+}
+}  // namespace
+
 struct fsa_ctx {
     fsa_desc d;
     Grid G;
     Phys P;
+    KConst* dK = nullptr;                // device copy of the constants
     hipStream_t stream = nullptr;
     int device = 0;
     int nq = 0;
@@ -31,6 +40,7 @@ struct fsa_ctx {
     hipEvent_t ev_alpha = nullptr;
     bool alpha_pending = false;
     int nonfinite = 0;
+    int last_slot = 0;                   // slot holding the wave speeds of the last state
     // markers
     int nm = 0;
     int motion = 0;
@@ -42,6 +52,9 @@ struct fsa_ctx {
     double* fwin = nullptr;
     int* cell_start = nullptr;
     int* cell_marker = nullptr;
+    double* cell_w = nullptr;            // per CSR entry spreading weight
+    int* mj0 = nullptr;                  // per marker support origin
+    double* mw = nullptr;                // per marker one-dimensional weights
     // probes
     int np = 0;
     double* Xp = nullptr;
@@ -159,7 +172,6 @@ void build_consts(fsa_ctx* c)
     }
     P.inflow_amp = d.inflow_amp;
     P.seed = d.seed;
-    P.step = 0;
     for (int k = 0; k < 3; ++k)
         for (int s = 0; s < 2; ++s) P.sw[k][s] = k < d.dim ? d.sponge_width[k][s] : 0.0;
     P.sigma = d.sponge_sigma;
@@ -169,25 +181,19 @@ void build_consts(fsa_ctx* c)
     P.terms = d.terms;
 }
 
-// Rows per wave segment: fill the device in whole rounds of resident waves, preferring
-// long segments (each segment recomputes one y face and eight halo rows).
-int choose_ty(const Grid& G)
+// Rows per wave segment of the 2D stage kernel.  The best value depends on how the waves
+// fill the chip (occupancy, tail of the last wave round), which no simple model predicts, so
+// it is measured: on the first launch of a context every candidate is timed on the caller's
+// data in right-hand-side mode into a scratch buffer, and the fastest is kept.  The
+// segmentation changes no result: every face is computed from the same inputs whichever
+// segment computes it.  FSA_STAGE_TY fixes the value instead (tuning runs, tests).
+int env_ty()
 {
-    int dev = 0, cus = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-        cus = prop.multiProcessorCount;
-    const long long slots = (long long)cus * 8;   // resident waves at two per SIMD
-    const long long ncol = stage2d_ncolx(G.n[0]);
-    int best = 16;
-    double best_cost = 1e300;
-    for (int ty = 8; ty <= 64; ++ty) {
-        const long long tiles = ncol * ((G.n[1] + ty - 1) / ty);
-        const long long rounds = (tiles + slots - 1) / slots;
-        const double cost = (double)rounds * (ty + 3.0);
-        if (cost < best_cost - 1e-9) { best_cost = cost; best = ty; }
+    if (const char* e = std::getenv("FSA_STAGE_TY")) {
+        const int v = std::atoi(e);
+        if (v >= 4 && v <= 4096) return v;
     }
-    return best;
+    return 0;
 }
 
 bool support_inside(const fsa_ctx* c, int n, const double* X)
@@ -203,6 +209,9 @@ bool support_inside(const fsa_ctx* c, int n, const double* X)
     return true;
 }
 
+IBArgs ib_args(const fsa_ctx* c);
+int tune_ty(fsa_ctx* c, const StageArgs& S0);
+
 // Window box over all marker supports and the CSR list window cell -> markers (in marker
 // order).  Index bookkeeping only; the weights are computed on the device.
 int build_window(fsa_ctx* c)
@@ -211,6 +220,9 @@ int build_window(fsa_ctx* c)
     dfree(c->fwin);
     dfree(c->cell_start);
     dfree(c->cell_marker);
+    dfree(c->cell_w);
+    dfree(c->mj0);
+    dfree(c->mw);
     c->wcells = 0;
     for (int k = 0; k < 3; ++k) { c->wlo[k] = 0; c->wn[k] = 1; }
     if (n == 0) { c->wn[0] = c->wn[1] = c->wn[2] = 0; return FSA_OK; }
@@ -255,9 +267,16 @@ int build_window(fsa_ctx* c)
     if ((rc = dalloc(c, c->fwin, (size_t)dim * wcells)) != FSA_OK) return rc;
     if ((rc = dalloc(c, c->cell_start, (size_t)wcells + 1)) != FSA_OK) return rc;
     if ((rc = dalloc(c, c->cell_marker, marker.size())) != FSA_OK) return rc;
+    if ((rc = dalloc(c, c->cell_w, marker.size())) != FSA_OK) return rc;
+    if ((rc = dalloc(c, c->mj0, (size_t)n * 3)) != FSA_OK) return rc;
+    if ((rc = dalloc(c, c->mw, (size_t)n * dim * 4)) != FSA_OK) return rc;
     HIPCHK(c, hipMemcpy(c->cell_start, count.data(), sizeof(int) * count.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->cell_marker, marker.data(), sizeof(int) * marker.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemset(c->fwin, 0, sizeof(double) * (size_t)dim * wcells));
+    IBArgs A = ib_args(c);
+    int e = launch_ib_weights(c->G, A, c->mj0, c->mw, c->cell_w, nullptr);
+    if (e) return hipcheck(c, (hipError_t)e, "IB weight launch");
+    HIPCHK(c, hipDeviceSynchronize());
     return FSA_OK;
 }
 
@@ -283,19 +302,27 @@ IBArgs ib_args(const fsa_ctx* c)
     }
     A.cell_start = c->cell_start;
     A.cell_marker = c->cell_marker;
+    A.cell_w = c->cell_w;
+    A.mj0 = c->mj0;
+    A.mw = c->mw;
     return A;
 }
 
 bool ib_active(const fsa_ctx* c) { return (c->d.terms & FSA_TERM_IB) && c->nm > 0; }
 
-// One right-hand-side evaluation on Qs into the stage kernel: alpha reduction, penalty
-// step, fused stencil/update kernel.
-int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, int slot, int stage, double ca,
-                  double cb, double dt, int mode_rhs)
+// One right-hand-side evaluation on Qs: (optionally) the wave-speed reduction of Qs into
+// slot `in`, the penalty step, and the fused stencil/update kernel, which reads slot `in`,
+// accumulates the wave speeds of its output into slot `acc` and clears slot `clr` (slots of
+// three doubles in abits; -1 = none).
+int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, int in, int acc, int clr,
+                  bool reduce, int stage, double ca, double cb, double dt, int mode_rhs)
 {
-    unsigned long long* bits = c->abits + 3 * slot;
-    int e = launch_alpha(c->G, c->P, Qs, bits, c->stream);
-    if (e) return hipcheck(c, (hipError_t)e, "alpha reduction launch");
+    unsigned long long* bits = c->abits + 3 * in;
+    int e;
+    if (reduce) {
+        e = launch_alpha(c->G, c->P, Qs, bits, c->stream);
+        if (e) return hipcheck(c, (hipError_t)e, "alpha reduction launch");
+    }
     if (ib_active(c)) {
         IBArgs A = ib_args(c);
         A.Qs = Qs;
@@ -312,6 +339,8 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     S.Qn = Qn;
     S.out = out;
     S.alpha_bits = bits;
+    S.alpha_out = acc >= 0 ? c->abits + 3 * acc : nullptr;
+    S.alpha_zero = clr >= 0 ? c->abits + 3 * clr : nullptr;
     S.fwin = ib_active(c) ? c->fwin : nullptr;
     for (int k = 0; k < 3; ++k) {
         S.wlo[k] = c->wlo[k];
@@ -321,6 +350,11 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     S.cb = cb;
     S.dt = dt;
     S.mode_rhs = mode_rhs;
+    S.step = c->step;
+    if (c->ty == 0) {
+        int rc = tune_ty(c, S);
+        if (rc != FSA_OK) return rc;
+    }
     S.ty = c->ty;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (c->timing) {
@@ -336,9 +370,48 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         c->tused += 2;
         HIPCHK(c, hipEventRecord(t0, c->stream));
     }
-    e = launch_stage2d(c->G, c->P, c->d.scheme, S, c->stream);
+    e = launch_stage2d(c->dK, c->G, c->d.scheme, S, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch");
     if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
+    return FSA_OK;
+}
+
+// Time the candidate segment heights on this launch's inputs (right-hand-side mode into the
+// second stage buffer, which no caller-visible state lives in at this point) and keep the
+// fastest.
+int tune_ty(fsa_ctx* c, const StageArgs& S0)
+{
+    static const int cand[] = {8, 10, 12, 14, 16, 19, 22, 25, 28, 32, 37, 44, 52, 64};
+    StageArgs S = S0;
+    S.mode_rhs = 1;
+    S.out = c->Qb;
+    S.Qn = nullptr;
+    S.alpha_out = nullptr;
+    S.alpha_zero = nullptr;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    int best = 16;
+    float best_ms = 1e30f;
+    for (int rep = 0; rep < 2; ++rep)
+        for (int ty : cand) {
+            if (ty > 2 * c->G.n[1] && ty != cand[0]) continue;
+            S.ty = ty;
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            int e = launch_stage2d(c->dK, c->G, c->d.scheme, S, c->stream);
+            if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch (tuning)");
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (rep == 1 && ms < best_ms) {   // the first pass warms caches and clocks
+                best_ms = ms;
+                best = ty;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->ty = best;
     return FSA_OK;
 }
 
@@ -403,12 +476,23 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
     c->nq = desc->dim + 2;
     build_consts(c);
     c->ncell = c->G.ncell;
-    c->ty = choose_ty(c->G);
+    c->ty = env_ty();
     if ((rc = dalloc(c, c->Qa, (size_t)c->nq * c->ncell)) != FSA_OK ||
         (rc = dalloc(c, c->Qb, (size_t)c->nq * c->ncell)) != FSA_OK ||
-        (rc = dalloc(c, c->abits, 12)) != FSA_OK) {
+        (rc = dalloc(c, c->abits, 12)) != FSA_OK || (rc = dalloc(c, c->dK, 1)) != FSA_OK) {
         fsa_destroy(c);
         return rc;
+    }
+    {
+        KConst hk;
+        std::memset(&hk, 0, sizeof hk);
+        hk.G = c->G;
+        hk.P = c->P;
+        hk.inv12h = 1.0 / (12.0 * c->G.h);
+        if (hipMemcpy(c->dK, &hk, sizeof hk, hipMemcpyHostToDevice) != hipSuccess) {
+            fsa_destroy(c);
+            return FSA_EDEVICE;
+        }
     }
     if (hipHostMalloc((void**)&c->h_abits, 12 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_alpha, hipEventDisableTiming) != hipSuccess) {
@@ -430,6 +514,7 @@ int32_t fsa_destroy(fsa_ctx* c)
     else (void)hipDeviceSynchronize();
     dfree(c->Qa);
     dfree(c->Qb);
+    dfree(c->dK);
     dfree(c->abits);
     dfree(c->X);
     dfree(c->dV);
@@ -440,6 +525,9 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->fwin);
     dfree(c->cell_start);
     dfree(c->cell_marker);
+    dfree(c->cell_w);
+    dfree(c->mj0);
+    dfree(c->mw);
     dfree(c->Xp);
     if (c->h_abits) (void)hipHostFree(c->h_abits);
     for (hipEvent_t ev : c->tev) (void)hipEventDestroy(ev);
@@ -527,30 +615,44 @@ int32_t fsa_rhs(fsa_ctx* c, const double* d_Q, double* d_L)
 {
     if (!c || !d_Q || !d_L) return FSA_EINVAL;
     if ((const void*)d_Q == (const void*)d_L) return fail(c, FSA_EINVAL, "d_L aliases d_Q");
-    c->P.step = c->step;
-    return enqueue_stage(c, d_Q, nullptr, d_L, 0, 0, 0.0, 1.0, 0.0, 1);
+    return enqueue_stage(c, d_Q, nullptr, d_L, 0, -1, -1, true, 0, 0.0, 1.0, 0.0, 1);
 }
 
-int32_t fsa_rk3_step(fsa_ctx* c, double* d_Q, double dt)
+int32_t fsa_rk3_steps(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps)
 {
     if (!c || !d_Q) return FSA_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, FSA_EINVAL, "dt must be positive");
+    if (nsteps < 1) return fail(c, FSA_EINVAL, "nsteps must be positive");
     int rc = check_previous(c);
     if (rc != FSA_OK) return rc;
-    c->P.step = c->step;
-    if ((rc = enqueue_stage(c, d_Q, nullptr, c->Qa, 0, 1, 0.0, 1.0, dt, 0)) != FSA_OK) return rc;
-    if ((rc = enqueue_stage(c, c->Qa, d_Q, c->Qb, 1, 2, 0.75, 0.25, dt, 0)) != FSA_OK) return rc;
-    if ((rc = enqueue_stage(c, c->Qb, d_Q, d_Q, 2, 3, 1.0 / 3.0, 2.0 / 3.0, dt, 0)) != FSA_OK) return rc;
+    static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
+    static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
+    // the wave speeds of every stage input come from the kernel that wrote it, except for
+    // the first stage of the call, which reduces d_Q (slot 0) after clearing slots 0 and 1
+    hipLaunchKernelGGL(k_clear_slots, dim3(1), dim3(64), 0, c->stream, c->abits, 6);
+    for (int n = 0; n < nsteps; ++n) {
+        for (int s = 0; s < 3; ++s) {
+            const int g = 3 * n + s;
+            const double* Qs = s == 0 ? d_Q : (s == 1 ? c->Qa : c->Qb);
+            double* out = s == 0 ? c->Qa : (s == 1 ? c->Qb : d_Q);
+            if ((rc = enqueue_stage(c, Qs, d_Q, out, g % 3, (g + 1) % 3, (g + 2) % 3, g == 0, s + 1, CA[s], CB[s],
+                                    dt, 0)) != FSA_OK)
+                return rc;
+        }
+        c->t += dt;
+        c->step += 1;
+    }
+    c->last_slot = (3 * nsteps) % 3;
     if (c->d.nan_check) {
         HIPCHK(c, hipMemcpyAsync(c->h_abits, c->abits, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                  c->stream));
         HIPCHK(c, hipEventRecord(c->ev_alpha, c->stream));
         c->alpha_pending = true;
     }
-    c->t += dt;
-    c->step += 1;
     return FSA_OK;
 }
+
+int32_t fsa_rk3_step(fsa_ctx* c, double* d_Q, double dt) { return fsa_rk3_steps(c, d_Q, dt, 1); }
 
 int32_t fsa_ib_interp(fsa_ctx* c, const double* d_field, int32_t ncomp, double* d_out)
 {
@@ -643,7 +745,7 @@ int32_t fsa_stats_get(fsa_ctx* c, fsa_stats* out)
 {
     if (!c || !out) return FSA_EINVAL;
     unsigned long long hb[3];
-    HIPCHK(c, hipMemcpyAsync(hb, c->abits + 6, sizeof hb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(hb, c->abits + 3 * c->last_slot, sizeof hb, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::memset(out, 0, sizeof *out);
     for (int d = 0; d < 3; ++d) {
@@ -656,6 +758,7 @@ int32_t fsa_stats_get(fsa_ctx* c, fsa_stats* out)
     out->n_markers = c->nm;
     out->n_probes = c->np;
     out->window_cells = (int32_t)c->wcells;
+    out->rows_per_wave = c->ty;
     return FSA_OK;
 }
 

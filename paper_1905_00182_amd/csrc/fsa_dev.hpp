@@ -29,7 +29,6 @@ struct Phys {
     double q_inf[5];          // conserved far-field state
     double inflow_amp;
     unsigned long long seed;
-    long long step;           // step counter used as the inflow-noise counter
     double sw[3][2];          // sponge widths
     double sigma;             // sponge sigma_max
     double weno_eps, teno_ct, teno_eps;
@@ -71,8 +70,8 @@ __device__ __forceinline__ int resolve_index(int i, int n, int bclo, int bchi, i
 // without contraction, one rounding per operation, so that an unperturbed ghost equals the
 // far-field state exactly (a uniform free stream then has an exactly zero right-hand side).
 template <int DIM>
-__device__ __forceinline__ void inflow_state(const Phys& P, long long ncell, long long lin, int side, int depth,
-                                             double* q)
+__device__ __forceinline__ void inflow_state(const Phys& P, long long step, long long ncell, long long lin, int side,
+                                             int depth, double* q)
 {
 #pragma clang fp contract(off)
     const double rho = P.prim_inf[0];
@@ -82,7 +81,7 @@ __device__ __forceinline__ void inflow_state(const Phys& P, long long ncell, lon
     for (int a = 0; a < DIM; ++a) {
         double u = P.prim_inf[1 + a];
         if (P.inflow_amp != 0.0) {
-            const uint64_t ctr = ((((uint64_t)P.step * 6ull + (uint64_t)side) * 8ull + (uint64_t)depth)
+            const uint64_t ctr = ((((uint64_t)step * 6ull + (uint64_t)side) * 8ull + (uint64_t)depth)
                                       * (uint64_t)ncell + (uint64_t)lin) * 3ull + (uint64_t)a;
             u += P.inflow_amp * (2.0 * u01(splitmix64(P.seed, ctr)) - 1.0);
         }
@@ -94,8 +93,8 @@ __device__ __forceinline__ void inflow_state(const Phys& P, long long ncell, lon
 
 // State at a possibly out-of-range cell (i, j, k): boundary ghosts resolved x, then y, then z.
 template <int DIM>
-__device__ __forceinline__ void fetch_state(const double* __restrict__ Q, const Grid& G, const Phys& P, int i,
-                                            int j, int k, double* q)
+__device__ __forceinline__ void fetch_state(const double* __restrict__ Q, const Grid& G, const Phys& P, long long step,
+                                            int i, int j, int k, double* q)
 {
     int inflow = 0, side = 0, depth = 0;
     i = resolve_index(i, G.n[0], G.bc[0][0], G.bc[0][1], 0, inflow, side, depth);
@@ -108,7 +107,18 @@ __device__ __forceinline__ void fetch_state(const double* __restrict__ Q, const 
         for (int c = 0; c < DIM + 2; ++c) q[c] = Q[c * G.ncell + lin];
         return;
     }
-    inflow_state<DIM>(P, G.ncell, lin, side, depth, q);
+    inflow_state<DIM>(P, step, G.ncell, lin, side, depth, q);
+}
+
+// Reciprocal from the hardware estimate refined by two Newton steps (within an ulp or two of
+// the correctly rounded 1/x for normal x), a quarter of the cost of an IEEE division.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -116,7 +126,7 @@ __device__ __forceinline__ void fetch_state(const double* __restrict__ Q, const 
 // (v_{i-2}, ..., v_{i+2}): three third-order candidates with Jiang-Shu smoothness indicators,
 // weighted WENO5-JS (alpha_k = d_k / (eps + beta_k)^2) or TENO5 (sharp cut-off of
 // gamma_k = (1 + tau5 / (beta_k + eps))^6 at C_T, kept stencils weighted by d_k).
-// Both are evaluated with a single division.
+// Both are evaluated with reciprocals instead of divisions.
 // ---------------------------------------------------------------------------------------
 struct Recon {
     double eps;   // WENO epsilon or TENO epsilon
@@ -141,12 +151,12 @@ __device__ __forceinline__ double recon5(double a, double b, double c, double d,
         // alpha_k proportional to d_k * prod_{j != k} (eps + beta_j)^2
         const double w0 = 0.1 * (p1 * p2), w1 = 0.6 * (p0 * p2), w2 = 0.3 * (p0 * p1);
         const double num = fma(w0, q0, fma(w1, q1, w2 * q2));
-        return num / (w0 + w1 + w2);
+        return num * rcp_nr(w0 + w1 + w2);
     } else {
         const double tau = fabs(b0 - b2);
         const double e0 = b0 + R.eps, e1 = b1 + R.eps, e2 = b2 + R.eps;
         const double e01 = e0 * e1;
-        const double inv = 1.0 / (e01 * e2);
+        const double inv = rcp_nr(e01 * e2);
         const double r0 = (e1 * e2) * inv, r1 = (e0 * e2) * inv, r2 = e01 * inv;  // 1 / e_k
         const double x0 = fma(tau, r0, 1.0), x1 = fma(tau, r1, 1.0), x2 = fma(tau, r2, 1.0);
         const double c0 = x0 * x0 * x0, c1 = x1 * x1 * x1, c2 = x2 * x2 * x2;
@@ -156,7 +166,7 @@ __device__ __forceinline__ double recon5(double a, double b, double c, double d,
         const double d1 = g1 < lim ? 0.0 : 0.6;
         const double d2 = g2 < lim ? 0.0 : 0.3;
         const double num = fma(d0, q0, fma(d1, q1, d2 * q2));
-        return num / (d0 + d1 + d2);
+        return num * rcp_nr(d0 + d1 + d2);
     }
 }
 
@@ -185,24 +195,30 @@ __device__ __forceinline__ void support4(double X, double lo, double h, int& j0,
 }
 
 // ---------------------------------------------------------------------------------------
-// Cubic sponge rate at cell (i, j, k).
+// Cubic sponge: depth ratio into the layers along one direction, clipped to [0, 1]; the
+// rate is sigma_max * (max over directions of the ratio)^3.
 // ---------------------------------------------------------------------------------------
-template <int DIM>
-__device__ __forceinline__ double sponge_rate(const Grid& G, const Phys& P, int i, int j, int k)
+__device__ __forceinline__ double sponge_eta(double x, double lo, double hi, double wl, double wh)
 {
     double eta = 0.0;
-    const int idx[3] = {i, j, k};
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        const double x = G.lo[d] + ((double)idx[d] + 0.5) * G.h;
-        const double lo = G.lo[d], hi = G.lo[d] + (double)G.n[d] * G.h;
-        const double wl = P.sw[d][0], wh = P.sw[d][1];
-        if (wl > 0.0 && x < lo + wl) eta = fmax(eta, (lo + wl - x) / wl);
-        if (wh > 0.0 && x > hi - wh) eta = fmax(eta, (x - (hi - wh)) / wh);
-    }
-    eta = fmin(eta, 1.0);
-    return P.sigma * (eta * eta * eta);
+    if (wl > 0.0 && x < lo + wl) eta = fmax(eta, (lo + wl - x) / wl);
+    if (wh > 0.0 && x > hi - wh) eta = fmax(eta, (x - (hi - wh)) / wh);
+    return fmin(eta, 1.0);
 }
+
+// Grid and physics constants as the kernels read them: one block in device memory, so that
+// rarely used fields are fetched with scalar loads where they are needed.
+struct KConst {
+    Grid G;
+    Phys P;
+    double inv12h;
+
+    __device__ __forceinline__ double eta_dir(int d, int i) const
+    {
+        const double x = G.lo[d] + ((double)i + 0.5) * G.h;
+        return sponge_eta(x, G.lo[d], G.lo[d] + (double)G.n[d] * G.h, P.sw[d][0], P.sw[d][1]);
+    }
+};
 
 // NaN-propagating maximum of non-negative doubles through their bit patterns: for x >= 0
 // the unsigned order of the bits is the numeric order, and every NaN pattern sorts above

@@ -17,6 +17,9 @@ struct StageArgs {
     double ca, cb, dt;
     int mode_rhs;
     int ty;                                // rows (2D) per wave segment
+    unsigned long long* alpha_out;         // if set: NaN-propagating max of |u_d| + c of the output
+    unsigned long long* alpha_zero;        // if set: slot cleared by the first lane of the grid
+    long long step;                        // step counter (inflow-noise counter)
 };
 
 // Arguments of the per-stage immersed-boundary kernel.
@@ -38,12 +41,16 @@ struct IBArgs {
     int wlo[3], wn[3];
     const int* cell_start; // CSR window cell -> markers (increasing marker index)
     const int* cell_marker;
+    const double* cell_w;  // per CSR entry: W(cell) dV_k / h^dim
+    const int* mj0;        // per marker: first support cell per direction [nm][3]
+    const double* mw;      // per marker: one-dimensional weights [nm][dim][4]
 };
 
-int launch_stage2d(const Grid& G, const Phys& P, int scheme, const StageArgs& A, hipStream_t s);
+int launch_stage2d(const KConst* K, const Grid& G, int scheme, const StageArgs& A, hipStream_t s);
 int stage2d_ncolx(int nx);
 int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* bits, hipStream_t s);
 int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s);
+int launch_ib_weights(const Grid& G, const IBArgs& A, int* mj0, double* mw, double* cell_w, hipStream_t s);
 int launch_interp(const Grid& G, int npts, const double* X, const double* field, int ncomp, double* out,
                   hipStream_t s);
 int launch_spread(const Grid& G, const IBArgs& A, const double* F, int ncomp, double* field, double scale,

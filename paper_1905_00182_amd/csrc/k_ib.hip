@@ -1,19 +1,19 @@
 // Immersed-boundary kernels (Sec. 2, Eqs. (7)-(11)), probes and the global Lax-Friedrichs
 // wave-speed reduction.
 //
-// The penalty step runs in one workgroup per stage: every thread takes markers, gathers the
-// fluid velocity m / rho over the 4^dim support with the tensor-product four-point weights,
-// forms F_f = alpha xi + beta (U_ib - U) and advances the penalty integral with the stage's
-// SSP-RK3 combination; after a barrier every thread takes cells of the window box (the
-// bounding box of all supports) and sums the spread force -F_k W_k dV_k / h^dim over that
-// cell's markers in increasing marker index (a deterministic gather).
+// The penalty step per stage is two small launches: one thread per marker gathers the fluid
+// velocity m / rho over the 4^dim support with the tensor-product four-point weights, forms
+// F_f = alpha xi + beta (U_ib - U) and advances the penalty integral with the stage's SSP-RK3
+// combination; then one thread per cell of the window box (the bounding box of all supports)
+// sums the spread force -F_k W_k dV_k / h^dim over that cell's markers in increasing marker
+// index (a deterministic gather).  The weights depend only on the marker positions and are
+// computed once per position update.
 #include "fsa_impl.hpp"
 
 namespace fsa {
 
 namespace {
 
-constexpr int IB_THREADS = 1024;
 constexpr int RED_THREADS = 256;
 
 __device__ __forceinline__ unsigned long long wave_max_bits(unsigned long long v)
@@ -90,73 +90,122 @@ __device__ __forceinline__ double cell_weight(const Grid& G, const double* X, in
     return W;
 }
 
+// Set-up for static marker positions: per marker the first support cell and the
+// one-dimensional weights per direction; per CSR entry (window cell, marker) the spreading
+// weight W(cell) dV_k / h^dim.
 template <int DIM>
-__global__ __launch_bounds__(IB_THREADS) void k_ib_stage(Grid G, Phys P, IBArgs A)
+__global__ void k_ib_weights(Grid G, IBArgs A, int* __restrict__ mj0, double* __restrict__ mw,
+                             double* __restrict__ cell_w)
 {
-    const long long nc = G.ncell;
-    for (int k = threadIdx.x; k < A.nm; k += blockDim.x) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < A.nm) {
+        const int k = (int)t;
         int j0[3];
         double w[3][4];
         marker_support<DIM>(G, A.X, A.nm, k, j0, w);
-        double uib[DIM];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) uib[a] = 0.0;
-        for (int mz = 0; mz < (DIM == 3 ? 4 : 1); ++mz)
-            for (int my = 0; my < 4; ++my)
+        for (int d = 0; d < DIM; ++d) {
+            mj0[k * 3 + d] = j0[d];
 #pragma unroll
-                for (int mx = 0; mx < 4; ++mx) {
-                    double W = w[0][mx] * w[1][my];
-                    if (DIM == 3) W = W * w[2][mz];
-                    const long long lin =
-                        ((long long)(DIM == 3 ? j0[2] + mz : 0) * G.n[1] + (j0[1] + my)) * G.n[0] + (j0[0] + mx);
-                    const double rho = A.Qs[lin];
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) uib[a] = fma(A.Qs[(1 + a) * nc + lin] / rho, W, uib[a]);
-                }
-        double U[DIM];
-        if (A.motion == 1) {
-            const double x = A.X[k], y = A.X[(long long)A.nm + k];
-            U[0] = -A.omega * y;
-            U[1] = A.omega * x;
-            if (DIM == 3) U[DIM - 1] = 0.0;
-        } else {
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) U[a] = A.U[(long long)a * A.nm + k];
-        }
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const long long o = (long long)a * A.nm + k;
-            const double d = uib[a] - U[a];
-            double xs, xn;
-            if (A.stage <= 1) {
-                xs = A.xi[o];
-                xn = xs;
-                if (A.stage == 1) A.xi_n[o] = xs;
-            } else {
-                xs = A.xi[o];
-                xn = A.xi_n[o];
-            }
-            A.F[o] = fma(A.alpha, xs, A.beta * d);
-            if (A.stage == 1) A.xi[o] = fma(A.dt, d, xn);
-            else if (A.stage > 1) A.xi[o] = fma(A.ca, xn, A.cb * fma(A.dt, d, xs));
+            for (int m = 0; m < 4; ++m) mw[(k * DIM + d) * 4 + m] = w[d][m];
         }
     }
-    __syncthreads();
     const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
-    const double hd = DIM == 3 ? G.h * G.h * G.h : G.h * G.h;
-    for (long long c = threadIdx.x; c < wcells; c += blockDim.x) {
+    if (t < wcells) {
+        const long long c = t;
         const int ci = A.wlo[0] + (int)(c % A.wn[0]);
         const int cj = A.wlo[1] + (int)((c / A.wn[0]) % A.wn[1]);
         const int ck = A.wlo[2] + (int)(c / ((long long)A.wn[0] * A.wn[1]));
-        double f[DIM];
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) f[a] = 0.0;
+        const double hd = DIM == 3 ? G.h * G.h * G.h : G.h * G.h;
         for (int e = A.cell_start[c]; e < A.cell_start[c + 1]; ++e) {
             const int k = A.cell_marker[e];
-            const double s = cell_weight<DIM>(G, A.X, A.nm, k, ci, cj, ck) * A.dV[k];
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) f[a] += -(A.F[(long long)a * A.nm + k] * s) / hd;
+            cell_w[e] = (cell_weight<DIM>(G, A.X, A.nm, k, ci, cj, ck) * A.dV[k]) / hd;
         }
+    }
+}
+
+// Penalty step per marker: U_ib = sum over the support of (m / rho) W, F_f = alpha xi +
+// beta (U_ib - U), and the stage's update of the penalty integral xi.
+template <int DIM>
+__global__ __launch_bounds__(64) void k_ib_markers(Grid G, IBArgs A)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.nm) return;
+    const long long nc = G.ncell;
+    int j0[3];
+    double w[3][4];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        j0[d] = A.mj0[k * 3 + d];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) w[d][m] = A.mw[(k * DIM + d) * 4 + m];
+    }
+    double uib[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) uib[a] = 0.0;
+#pragma unroll
+    for (int mz = 0; mz < (DIM == 3 ? 4 : 1); ++mz)
+#pragma unroll
+        for (int my = 0; my < 4; ++my)
+#pragma unroll
+            for (int mx = 0; mx < 4; ++mx) {
+                double W = w[0][mx] * w[1][my];
+                if (DIM == 3) W = W * w[2][mz];
+                const long long lin =
+                    ((long long)(DIM == 3 ? j0[2] + mz : 0) * G.n[1] + (j0[1] + my)) * G.n[0] + (j0[0] + mx);
+                const double rho = A.Qs[lin];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) uib[a] = fma(A.Qs[(1 + a) * nc + lin] / rho, W, uib[a]);
+            }
+    double U[DIM];
+    if (A.motion == 1) {
+        const double x = A.X[k], y = A.X[(long long)A.nm + k];
+        U[0] = -A.omega * y;
+        U[1] = A.omega * x;
+        if (DIM == 3) U[DIM - 1] = 0.0;
+    } else {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) U[a] = A.U[(long long)a * A.nm + k];
+    }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const long long o = (long long)a * A.nm + k;
+        const double d = uib[a] - U[a];
+        const double xs = A.xi[o];
+        double xn = xs;
+        if (A.stage == 1) A.xi_n[o] = xs;
+        else if (A.stage > 1) xn = A.xi_n[o];
+        A.F[o] = fma(A.alpha, xs, A.beta * d);
+        if (A.stage == 1) A.xi[o] = fma(A.dt, d, xn);
+        else if (A.stage > 1) A.xi[o] = fma(A.ca, xn, A.cb * fma(A.dt, d, xs));
+    }
+}
+
+// Spread force density on the window box: one wave per window cell; lane l sums the cell's
+// CSR entries l, l+64, ... in increasing marker index, then the wave adds the lane sums in a
+// fixed butterfly order, so the result is the same on every run.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_ib_window(IBArgs A)
+{
+    const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
+    const long long c = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (c >= wcells) return;
+    double f[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) f[a] = 0.0;
+    const int e1 = A.cell_start[c + 1];
+    for (int e = A.cell_start[c] + lane; e < e1; e += 64) {
+        const int k = A.cell_marker[e];
+        const double we = A.cell_w[e];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) f[a] = fma(-A.F[(long long)a * A.nm + k], we, f[a]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) f[a] += __shfl_xor(f[a], off, 64);
+    if (lane == 0) {
 #pragma unroll
         for (int a = 0; a < DIM; ++a) A.fwin[a * wcells + c] = f[a];
     }
@@ -198,15 +247,11 @@ __global__ void k_spread(Grid G, IBArgs A, const double* __restrict__ F, int nco
     const int ci = A.wlo[0] + (int)(c % A.wn[0]);
     const int cj = A.wlo[1] + (int)((c / A.wn[0]) % A.wn[1]);
     const int ck = A.wlo[2] + (int)(c / ((long long)A.wn[0] * A.wn[1]));
-    const double hd = DIM == 3 ? G.h * G.h * G.h : G.h * G.h;
     const long long lin = ((long long)(DIM == 3 ? ck : 0) * G.n[1] + cj) * G.n[0] + ci;
     for (int a = 0; a < ncomp; ++a) {
         double f = 0.0;
-        for (int e = A.cell_start[c]; e < A.cell_start[c + 1]; ++e) {
-            const int k = A.cell_marker[e];
-            const double W = cell_weight<DIM>(G, A.X, A.nm, k, ci, cj, ck);
-            f += -(F[(long long)a * A.nm + k] * (W * A.dV[k])) / hd;
-        }
+        for (int e = A.cell_start[c]; e < A.cell_start[c + 1]; ++e)
+            f = fma(-F[(long long)a * A.nm + A.cell_marker[e]], A.cell_w[e], f);
         field[(long long)a * G.ncell + lin] += scale * f;
     }
 }
@@ -257,8 +302,29 @@ int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long lo
 
 int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s)
 {
-    if (G.dim == 3) hipLaunchKernelGGL(k_ib_stage<3>, dim3(1), dim3(IB_THREADS), 0, s, G, P, A);
-    else hipLaunchKernelGGL(k_ib_stage<2>, dim3(1), dim3(IB_THREADS), 0, s, G, P, A);
+    (void)P;
+    if (A.nm <= 0) return 0;
+    const unsigned mb = (unsigned)((A.nm + 63) / 64);
+    const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
+    const unsigned wb = (unsigned)((wcells + 3) / 4);   // four waves (cells) per block
+    if (G.dim == 3) {
+        hipLaunchKernelGGL(k_ib_markers<3>, dim3(mb), dim3(64), 0, s, G, A);
+        hipLaunchKernelGGL(k_ib_window<3>, dim3(wb), dim3(256), 0, s, A);
+    } else {
+        hipLaunchKernelGGL(k_ib_markers<2>, dim3(mb), dim3(64), 0, s, G, A);
+        hipLaunchKernelGGL(k_ib_window<2>, dim3(wb), dim3(256), 0, s, A);
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_ib_weights(const Grid& G, const IBArgs& A, int* mj0, double* mw, double* cell_w, hipStream_t s)
+{
+    const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
+    const long long n = wcells > A.nm ? wcells : A.nm;
+    if (n <= 0) return 0;
+    const unsigned b = (unsigned)((n + 127) / 128);
+    if (G.dim == 3) hipLaunchKernelGGL(k_ib_weights<3>, dim3(b), dim3(128), 0, s, G, A, mj0, mw, cell_w);
+    else hipLaunchKernelGGL(k_ib_weights<2>, dim3(b), dim3(128), 0, s, G, A, mj0, mw, cell_w);
     return (int)hipGetLastError();
 }
 

@@ -5,11 +5,18 @@
 // state once, forms the y-split fluxes f+-_y and the velocities, and keeps them in register
 // windows (five rows, slot = row mod 5 fixed at compile time by unrolling the march by 5),
 // so every y-face is reconstructed exactly once.  x-neighbours come from the neighbouring
-// lanes of the same wave.  The viscous stress (Sec. 2, Eqs. (5)-(6), fourth-order central
-// differences applied twice) lags the front by two rows, the output row by four.  The
-// output row combines, in this order, the x and y convective terms, the viscous term and
-// the sources (penalty-IB force from the window array, sponge), and writes either L(Q) or
-// the SSP-RK3 combination a Qn + b (Qs + dt L).
+// lanes of the same wave through DPP wave shifts.  The viscous stress (Sec. 2, Eqs. (5)-(6),
+// fourth-order central differences applied twice) lags the front by two rows, the output
+// row by four.  The output row combines, in this order, the x and y convective terms, the
+// viscous term and the sources (penalty-IB force from the window array, sponge), and
+// writes either L(Q) or the SSP-RK3 combination a Qn + b (Qs + dt L); it also accumulates
+// the global Lax-Friedrichs speeds of what it writes for the next stage.
+//
+// Boundary ghosts are resolved once per lane for x and once per row (a wave-uniform value)
+// for y; only inflow ghosts take the slow path.  Each state value is loaded from memory once
+// per wave: the output row is read back from a lane-private LDS ring of the last five front
+// rows.  Constants live in a device-side block and
+// are read where they are used, which keeps the scalar registers for the hot loop.
 #include "fsa_impl.hpp"
 
 namespace fsa {
@@ -20,8 +27,21 @@ constexpr int HALO = 4;
 constexpr int WAVE = 64;
 constexpr int OUTW = WAVE - 2 * HALO;   // 56 output columns per wave
 
-__device__ __forceinline__ double from_lower(double x, int k) { return __shfl_up(x, (unsigned)k, WAVE); }
-__device__ __forceinline__ double from_upper(double x, int k) { return __shfl_down(x, (unsigned)k, WAVE); }
+// Lane shifts across the whole wave with DPP: wave_shr:1 gives lane i the value of lane i-1,
+// wave_shl:1 the value of lane i+1 (lanes without a source read 0; only halo lanes do).
+constexpr int DPP_WAVE_SHR1 = 0x138;
+constexpr int DPP_WAVE_SHL1 = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double lo1(double x) { return dpp64<DPP_WAVE_SHR1>(x); }
+__device__ __forceinline__ double up1(double x) { return dpp64<DPP_WAVE_SHL1>(x); }
 
 // Fourth-order central first derivative from the values at offsets -2..+2 (times 1/(12h)).
 __device__ __forceinline__ double d1(double gm2, double gm1, double gp1, double gp2, double inv12h)
@@ -31,45 +51,83 @@ __device__ __forceinline__ double d1(double gm2, double gm1, double gp1, double 
 
 __device__ __forceinline__ double d1_lanes(double g, double inv12h)
 {
-    return d1(from_lower(g, 2), from_lower(g, 1), from_upper(g, 1), from_upper(g, 2), inv12h);
+    const double l1 = lo1(g), u1 = up1(g);
+    return d1(lo1(l1), l1, u1, up1(u1), inv12h);
 }
 
 template <int SCHEME>
 struct Column2D {
-    // problem
-    Grid G;
-    Phys P;
-    Recon R;
+    const KConst* __restrict__ K;   // grid and physics constants (device memory)
     const double* __restrict__ Qs;
-    const double* Qn;    // may alias out (last stage writes in place)
+    const double* Qn;               // may alias out (last stage writes in place)
     double* out;
     const double* __restrict__ fwin;
+    long long ncell;
+    int nx;
     int wlo0, wlo1, wn0, wn1;
-    double ax, ay, inv_h, inv12h, ca, cb, dt;
-    int mode_rhs;
-    int j0, j1, ic, i;
+    double ax, ay, inv_h, inv12h, mu, gm1, ca, cb, dt;
+    Recon R;
+    int mode_rhs, terms;
+    int j0, j1;
+    int xr;                         // resolved x index of this lane
+    int i;                          // x index of this lane (a ghost index in the halo)
+    bool x_inflow;                  // this lane is an inflow ghost column
     bool out_lane;
+    bool want_alpha;
+    double eta_x;                   // sponge depth ratio of this lane's column
+    unsigned long long amax_x, amax_y;
+    long long step;
     // register windows, slot = (row - first front row) mod 5
     double fp[5][4], fm[5][4];
     double uw[5], vw[5];
     double txx[5], txy[5], tyy[5], bx[5], by[5];
-    double fy_prev[4], cy_queue[4], cy_new[4];
+    double fy_prev[4], cy_queue[4];
+    double qf[4];                   // prefetched state of the next front row
+    double (*ring)[4][WAVE];        // LDS: the last five front rows of this wave, [slot][comp][lane]
+    int lane;
 
-    template <int K>
-    __device__ __forceinline__ void step(int Rw)
+    // State of (this lane, row j): interior and periodic/zero-gradient ghosts are loads;
+    // inflow ghosts are built from the far field and the seeded perturbation.
+    __device__ __forceinline__ void load_row(int j, double* q) const
     {
-        constexpr int S0 = K % 5;          // row Rw (and row Rw-5 before it is overwritten)
-        constexpr int S1 = (K + 4) % 5;    // row Rw-1
-        constexpr int S2 = (K + 3) % 5;    // row Rw-2
-        constexpr int S3 = (K + 2) % 5;    // row Rw-3
-        constexpr int S4 = (K + 1) % 5;    // row Rw-4
+        int inflow = 0, side = 0, depth = 0;
+        const int jr = resolve_index(j, K->G.n[1], K->G.bc[1][0], K->G.bc[1][1], 1, inflow, side, depth);
+        if (!x_inflow && !inflow) {
+            const double* p = Qs + (long long)jr * nx + xr;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) q[c] = p[c * ncell];
+        } else {
+            fetch_state<2>(Qs, K->G, K->P, step, i, j, 0, q);
+        }
+    }
 
-        // ---- front row: state, velocity, y-split fluxes
-        double q[4];
-        fetch_state<2>(Qs, G, P, ic, Rw, 0, q);
-        const double inv_rho = 1.0 / q[0];
+    template <int K5>
+    __device__ __forceinline__ void step_row(int Rw)
+    {
+        constexpr int S0 = K5 % 5;          // row Rw (and row Rw-5 before it is overwritten)
+        constexpr int S1 = (K5 + 4) % 5;    // row Rw-1
+        constexpr int S2 = (K5 + 3) % 5;    // row Rw-2
+        constexpr int S3 = (K5 + 2) % 5;    // row Rw-3
+        constexpr int S4 = (K5 + 1) % 5;    // row Rw-4
+        const bool do_out = Rw >= j0 + 4;
+        const int r = Rw - 4;
+
+        // state of the output row, kept in LDS since it was the front row four steps ago
+        // (each lane reads back only what it wrote, so no barrier is involved)
+        double qr[4] = {0.0, 0.0, 0.0, 0.0};
+        if (do_out) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) qr[c] = ring[S4][c][lane];
+        }
+
+        // ---- front row Rw (prefetched in the previous step): velocity and y-split fluxes
+        const double q[4] = {qf[0], qf[1], qf[2], qf[3]};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ring[S0][c][lane] = q[c];
+        load_row(Rw + 1, qf);
+        const double inv_rho = rcp_nr(q[0]);
         const double u = q[1] * inv_rho, v = q[2] * inv_rho;
-        const double p = P.gm1 * (q[3] - 0.5 * fma(q[1], u, q[2] * v));
+        const double p = gm1 * (q[3] - 0.5 * fma(q[1], u, q[2] * v));
         double fpr[4];
         {
             const double F[4] = {q[2], q[1] * v, fma(q[2], v, p), (q[3] + p) * v};
@@ -83,7 +141,8 @@ struct Column2D {
         vw[S0] = v;
 
         // ---- y face (Rw-3)+1/2: f+ rows Rw-5..Rw-1, f- rows Rw..Rw-4
-        if ((P.terms & T_CONVY) && Rw >= j0 + 2 && Rw <= j1 + 3) {
+        double cy_new[4] = {0.0, 0.0, 0.0, 0.0};
+        if ((terms & T_CONVY) && Rw >= j0 + 2 && Rw <= j1 + 3) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const double fh = recon5<SCHEME>(fp[S0][c], fp[S4][c], fp[S3][c], fp[S2][c], fp[S1][c], R)
@@ -96,15 +155,15 @@ struct Column2D {
         for (int c = 0; c < 4; ++c) fp[S0][c] = fpr[c];
 
         // ---- stress at row Rw-2 (velocities of rows Rw-4..Rw in the window)
-        if ((P.terms & T_VISC) && Rw >= j0) {
+        if ((terms & T_VISC) && Rw >= j0) {
             const double uc = uw[S2], vc = vw[S2];
             const double dudx = d1_lanes(uc, inv12h), dvdx = d1_lanes(vc, inv12h);
             const double dudy = d1(uw[S4], uw[S3], uw[S1], uw[S0], inv12h);
             const double dvdy = d1(vw[S4], vw[S3], vw[S1], vw[S0], inv12h);
             const double div = dudx + dvdy;
-            const double sxx = P.mu * fma(-2.0 / 3.0, div, dudx + dudx);
-            const double syy = P.mu * fma(-2.0 / 3.0, div, dvdy + dvdy);
-            const double sxy = P.mu * (dudy + dvdx);
+            const double sxx = mu * fma(-2.0 / 3.0, div, dudx + dudx);
+            const double syy = mu * fma(-2.0 / 3.0, div, dvdy + dvdy);
+            const double sxy = mu * (dudy + dvdx);
             txx[S2] = sxx;
             txy[S2] = sxy;
             tyy[S2] = syy;
@@ -113,33 +172,28 @@ struct Column2D {
         }
 
         // ---- output row r = Rw-4
-        if (Rw >= j0 + 4) {
-            const int r = Rw - 4;
+        if (do_out) {
             double L[4] = {0.0, 0.0, 0.0, 0.0};
-            // x convection: state of row r, velocities from the window
-            double qr[4];
-            fetch_state<2>(Qs, G, P, ic, r, 0, qr);
-            if (P.terms & T_CONVX) {
+            if (terms & T_CONVX) {
                 const double ur = uw[S4], vr = vw[S4];
-                const double pr = P.gm1 * (qr[3] - 0.5 * fma(qr[1], ur, qr[2] * vr));
+                const double pr = gm1 * (qr[3] - 0.5 * fma(qr[1], ur, qr[2] * vr));
                 const double F[4] = {qr[1], fma(qr[1], ur, pr), qr[2] * ur, (qr[3] + pr) * ur};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const double fpx = 0.5 * fma(ax, qr[c], F[c]);
                     const double fmx = 0.5 * fma(-ax, qr[c], F[c]);
-                    const double fh =
-                        recon5<SCHEME>(from_lower(fpx, 2), from_lower(fpx, 1), fpx, from_upper(fpx, 1),
-                                       from_upper(fpx, 2), R) +
-                        recon5<SCHEME>(from_upper(fmx, 3), from_upper(fmx, 2), from_upper(fmx, 1), fmx,
-                                       from_lower(fmx, 1), R);
-                    L[c] = -(fh - from_lower(fh, 1)) * inv_h;
+                    const double pl1 = lo1(fpx), pu1 = up1(fpx);
+                    const double ml1 = lo1(fmx), mu1 = up1(fmx), mu2 = up1(mu1);
+                    const double fh = recon5<SCHEME>(lo1(pl1), pl1, fpx, pu1, up1(pu1), R) +
+                                      recon5<SCHEME>(up1(mu2), mu2, mu1, fmx, ml1, R);
+                    L[c] = -(fh - lo1(fh)) * inv_h;
                 }
             }
-            if (P.terms & T_CONVY) {
+            if (terms & T_CONVY) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) L[c] += cy_queue[c];
             }
-            if (P.terms & T_VISC) {
+            if (terms & T_VISC) {
                 // rows r-2..r+2 sit in slots S1, S0, S4, S3, S2
                 const double vx = d1_lanes(txx[S4], inv12h) + d1(txy[S1], txy[S0], txy[S3], txy[S2], inv12h);
                 const double vy = d1_lanes(txy[S4], inv12h) + d1(tyy[S1], tyy[S0], tyy[S3], tyy[S2], inv12h);
@@ -150,7 +204,7 @@ struct Column2D {
             }
             if (out_lane) {
                 double s[4] = {0.0, 0.0, 0.0, 0.0};
-                if ((P.terms & T_IB) && fwin) {
+                if ((terms & T_IB) && fwin) {
                     const int wi = i - wlo0, wj = r - wlo1;
                     if (wi >= 0 && wi < wn0 && wj >= 0 && wj < wn1) {
                         const long long wc = (long long)wj * wn0 + wi;
@@ -161,29 +215,38 @@ struct Column2D {
                         s[3] = fma(f0, uw[S4], f1 * vw[S4]);
                     }
                 }
-                if ((P.terms & T_SPONGE) && P.sigma != 0.0) {
-                    const double sg = sponge_rate<2>(G, P, i, r, 0);
-                    if (sg != 0.0) {
+                if (terms & T_SPONGE) {
+                    const double eta = fmax(eta_x, K->eta_dir(1, r));
+                    if (eta > 0.0) {
+                        const double sg = K->P.sigma * (eta * eta * eta);
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) s[c] = fma(-sg, qr[c] - P.q_inf[c], s[c]);
+                        for (int c = 0; c < 4; ++c) s[c] = fma(-sg, qr[c] - K->P.q_inf[c], s[c]);
                     }
                 }
-                const long long o = (long long)r * G.n[0] + i;
+                const long long o = (long long)r * nx + i;
+                double val[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const double l = L[c] + s[c];
-                    double val;
                     if (mode_rhs) {
-                        val = l;
+                        val[c] = l;
                     } else {
                         const double stage = fma(dt, l, qr[c]);
-                        val = (ca == 0.0) ? stage : fma(ca, Qn[c * G.ncell + o], cb * stage);
+                        val[c] = (ca == 0.0) ? stage : fma(ca, Qn[c * ncell + o], cb * stage);
                     }
-                    out[c * G.ncell + o] = val;
+                    out[c * ncell + o] = val[c];
+                }
+                if (want_alpha) {
+                    const double ir = rcp_nr(val[0]);
+                    const double un = val[1] * ir, vn = val[2] * ir;
+                    const double pn = gm1 * (val[3] - 0.5 * fma(val[1], un, val[2] * vn));
+                    const double cn = sqrt(K->P.gamma * pn * ir);
+                    amax_x = max_bits(amax_x, (unsigned long long)__double_as_longlong(fabs(un) + cn));
+                    amax_y = max_bits(amax_y, (unsigned long long)__double_as_longlong(fabs(vn) + cn));
                 }
             }
         }
-        if ((P.terms & T_CONVY) && Rw >= j0 + 3 && Rw <= j1 + 3) {
+        if ((terms & T_CONVY) && Rw >= j0 + 3 && Rw <= j1 + 3) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) cy_queue[c] = cy_new[c];
         }
@@ -191,43 +254,54 @@ struct Column2D {
 };
 
 template <int SCHEME>
-__global__ __launch_bounds__(64) void k_stage2d(Grid G, Phys P, StageArgs A)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_stage2d(
+    const KConst* __restrict__ K, StageArgs A)
 {
     Column2D<SCHEME> C;
-    C.G = G;
-    C.P = P;
-    C.R.eps = SCHEME == WENO5JS ? P.weno_eps : P.teno_eps;
-    C.R.ct = P.teno_ct;
+    C.K = K;
     C.Qs = A.Qs;
     C.Qn = A.Qn;
     C.out = A.out;
     C.fwin = A.fwin;
+    C.ncell = K->G.ncell;
+    C.nx = K->G.n[0];
     C.wlo0 = A.wlo[0];
     C.wlo1 = A.wlo[1];
     C.wn0 = A.wn[0];
     C.wn1 = A.wn[1];
     C.ax = __longlong_as_double((long long)A.alpha_bits[0]);
     C.ay = __longlong_as_double((long long)A.alpha_bits[1]);
-    C.inv_h = G.inv_h;
-    C.inv12h = 1.0 / (12.0 * G.h);
+    C.inv_h = K->G.inv_h;
+    C.inv12h = K->inv12h;
+    C.mu = K->P.mu;
+    C.gm1 = K->P.gm1;
+    C.R.eps = SCHEME == WENO5JS ? K->P.weno_eps : K->P.teno_eps;
+    C.R.ct = K->P.teno_ct;
     C.ca = A.ca;
     C.cb = A.cb;
     C.dt = A.dt;
     C.mode_rhs = A.mode_rhs;
+    C.terms = K->P.terms;
+    C.step = A.step;
 
+    __shared__ double ring[5][4][WAVE];
     const int lane = threadIdx.x;
-    const int nx = G.n[0], ny = G.n[1];
-    C.i = blockIdx.x * OUTW - HALO + lane;
-    C.ic = min(max(C.i, -HALO), nx + HALO - 1);
-    C.out_lane = lane >= HALO && lane < WAVE - HALO && C.i < nx;
+    C.ring = ring;
+    C.lane = lane;
+    const int nx = C.nx, ny = K->G.n[1];
+    {
+        const int i = blockIdx.x * OUTW - HALO + lane;
+        C.i = min(max(i, -HALO), nx + HALO - 1);
+        int inflow = 0, side = 0, depth = 0;
+        C.xr = resolve_index(C.i, nx, K->G.bc[0][0], K->G.bc[0][1], 0, inflow, side, depth);
+        C.x_inflow = inflow != 0;
+        C.out_lane = lane >= HALO && lane < WAVE - HALO && i < nx;
+    }
+    C.eta_x = C.out_lane ? K->eta_dir(0, C.i) : 0.0;
     C.j0 = blockIdx.y * A.ty;
     C.j1 = min(C.j0 + A.ty, ny) - 1;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        C.fy_prev[c] = 0.0;
-        C.cy_queue[c] = 0.0;
-        C.cy_new[c] = 0.0;
-    }
+    for (int c = 0; c < 4; ++c) C.fy_prev[c] = C.cy_queue[c] = 0.0;
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
 #pragma unroll
@@ -235,29 +309,45 @@ __global__ __launch_bounds__(64) void k_stage2d(Grid G, Phys P, StageArgs A)
         C.uw[s] = C.vw[s] = 0.0;
         C.txx[s] = C.txy[s] = C.tyy[s] = C.bx[s] = C.by[s] = 0.0;
     }
+    C.want_alpha = A.alpha_out != nullptr;
+    C.amax_x = C.amax_y = 0ull;
+    if (A.alpha_zero && blockIdx.x == 0 && blockIdx.y == 0 && lane < 3) A.alpha_zero[lane] = 0ull;
     const int Rend = C.j1 + HALO;
+    C.load_row(C.j0 - HALO, C.qf);
     for (int Rw = C.j0 - HALO; Rw <= Rend; Rw += 5) {
-        C.template step<0>(Rw);
+        C.template step_row<0>(Rw);
         if (Rw + 1 > Rend) break;
-        C.template step<1>(Rw + 1);
+        C.template step_row<1>(Rw + 1);
         if (Rw + 2 > Rend) break;
-        C.template step<2>(Rw + 2);
+        C.template step_row<2>(Rw + 2);
         if (Rw + 3 > Rend) break;
-        C.template step<3>(Rw + 3);
+        C.template step_row<3>(Rw + 3);
         if (Rw + 4 > Rend) break;
-        C.template step<4>(Rw + 4);
+        C.template step_row<4>(Rw + 4);
+    }
+    if (C.want_alpha) {
+        unsigned long long mx = C.amax_x, my = C.amax_y;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            mx = max_bits(mx, __shfl_xor(mx, off, WAVE));
+            my = max_bits(my, __shfl_xor(my, off, WAVE));
+        }
+        if (lane == 0) {
+            atomicMax(&A.alpha_out[0], mx);
+            atomicMax(&A.alpha_out[1], my);
+        }
     }
 }
 
 }  // namespace
 
-int launch_stage2d(const Grid& G, const Phys& P, int scheme, const StageArgs& A, hipStream_t s)
+int launch_stage2d(const KConst* K, const Grid& G, int scheme, const StageArgs& A, hipStream_t s)
 {
     const int ncolx = (G.n[0] + OUTW - 1) / OUTW;
     const int nseg = (G.n[1] + A.ty - 1) / A.ty;
     dim3 grid(ncolx, nseg), block(WAVE);
-    if (scheme == TENO5) hipLaunchKernelGGL(k_stage2d<TENO5>, grid, block, 0, s, G, P, A);
-    else hipLaunchKernelGGL(k_stage2d<WENO5JS>, grid, block, 0, s, G, P, A);
+    if (scheme == TENO5) hipLaunchKernelGGL(k_stage2d<TENO5>, grid, block, 0, s, K, A);
+    else hipLaunchKernelGGL(k_stage2d<WENO5JS>, grid, block, 0, s, K, A);
     return (int)hipGetLastError();
 }
 

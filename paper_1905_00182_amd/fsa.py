@@ -62,6 +62,7 @@ class FsaStats(C.Structure):
         ("n_markers", C.c_int32),
         ("n_probes", C.c_int32),
         ("window_cells", C.c_int32),
+        ("rows_per_wave", C.c_int32),
     ]
 
 
@@ -80,6 +81,7 @@ _SIGS = {
     "fsa_alpha": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fsa_rhs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fsa_rk3_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double]),
+    "fsa_rk3_steps": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32]),
     "fsa_ib_interp": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "fsa_ib_spread": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double]),
     "fsa_probe_dp": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -224,6 +226,10 @@ class Solver:
 
     def rk3_step(self, Q, dt):
         self._check(lib().fsa_rk3_step(self.ctx, _ptr(self._state(Q)), dt))
+        return Q
+
+    def rk3_steps(self, Q, dt, nsteps):
+        self._check(lib().fsa_rk3_steps(self.ctx, _ptr(self._state(Q)), dt, nsteps))
         return Q
 
     def ib_interp(self, field):

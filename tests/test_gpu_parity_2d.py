@@ -4,7 +4,10 @@ Tolerances (derived in the design notes):
   * one right-hand side: max |L_gpu - L_oracle| <= 1e-13 * S, S = 2 max|Q| alpha_max / h the
     size of a single face flux over h (face fluxes round to ~30 eps of that; FMA contraction
     and operation order differ between the two sides);
-  * after time steps: per conserved component ||Q_gpu - Q_ora||_2 / ||Q_ora||_2 <= 1e-12.
+  * after time steps: ||Q_gpu - Q_ora||_2 / ||Q_ora||_2 <= 1e-12 over the whole state, and per
+    conserved component relative to that component's natural size (rho_inf, rho_inf c_inf for
+    momentum, E_inf), since a quiescent case has a momentum field that is itself only the
+    acoustic fluctuation.
 """
 import numpy as np
 import pytest
@@ -136,9 +139,25 @@ def _steps_both(torch, case, Q0, nsteps):
     return s, o, Qg.cpu().numpy(), Qo
 
 
-def _assert_q_close(Qg, Qo, Q0, tol=1e-12):
+def natural_scale(case):
+    """Per-component size of the conserved state: rho_inf, rho_inf c_inf (+|m_inf|), E_inf."""
+    import math
+
+    rho, p = case.prim_inf[0], case.prim_inf[4]
+    c = math.sqrt(case.gamma * p / rho)
+    u = case.prim_inf[1:1 + case.dim]
+    E = p / (case.gamma - 1) + 0.5 * rho * sum(x * x for x in u)
+    return [rho] + [rho * (c + abs(x)) for x in u] + [E]
+
+
+def _assert_q_close(Qg, Qo, Q0, case, tol=1e-12):
+    whole = np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo)
+    _say(f"  whole state: rel L2 {whole:.3e}")
+    assert whole <= tol
+    scale = natural_scale(case)
     for c in range(Qo.shape[0]):
-        rel = np.linalg.norm(Qg[c] - Qo[c]) / np.linalg.norm(Qo[c])
+        ref = max(np.linalg.norm(Qo[c]), scale[c] * np.sqrt(Qo[c].size))
+        rel = np.linalg.norm(Qg[c] - Qo[c]) / ref
         dev = np.abs(Qo[c] - Q0[c]).max()
         _say(f"  comp {c}: rel L2 {rel:.3e}; max|dQ| {np.abs(Qg[c] - Qo[c]).max():.3e} of change {dev:.3e}")
         assert rel <= tol, (c, rel)
@@ -148,7 +167,7 @@ def test_rk3_config1_full(torch_cuda):
     case = W.config1(n=128)
     Q0 = W.config1_state(case)
     s, o, Qg, Qo = _steps_both(torch_cuda, case, Q0, case.steps)
-    _assert_q_close(Qg, Qo, Q0)
+    _assert_q_close(Qg, Qo, Q0, case)
     np.testing.assert_allclose(s.marker_force(), o.marker_force(), rtol=1e-9, atol=1e-12)
     xg, tg, kg = s.get_state()
     xo, to, ko = o.get_state()
@@ -164,7 +183,7 @@ def test_rk3_config2_small(torch_cuda):
     case = _c2_small(n=256)
     Q0 = W.config2_state(case)
     s, o, Qg, Qo = _steps_both(torch_cuda, case, Q0, 20)
-    _assert_q_close(Qg, Qo, Q0)
+    _assert_q_close(Qg, Qo, Q0, case)
     np.testing.assert_allclose(s.marker_force(), o.marker_force(), rtol=1e-9, atol=1e-12)
 
 
@@ -236,8 +255,31 @@ def test_config2_full_size(torch_cuda, nsteps):
     case = W.config2()
     Q0 = W.config2_state(case)
     s, o, Qg, Qo = _steps_both(torch_cuda, case, Q0, nsteps)
-    _assert_q_close(Qg, Qo, Q0)
+    _assert_q_close(Qg, Qo, Q0, case)
     # deviation from the initial state near the cylinder, where the IB acts
     dev = np.abs(Qg - Qo).max() / max(np.abs(Qo - Q0).max(), 1e-300)
     _say("  max |Q_gpu - Q_ora| / max |Q_ora - Q0| =", dev)
     assert dev < 1e-8
+
+
+def test_segmentation_does_not_change_results(torch_cuda, monkeypatch):
+    """The rows-per-wave segmentation is a launch parameter only: every face is computed
+    from the same inputs whatever segment computes it, so results are bitwise equal."""
+    case = _c2_small(n=150, nprobe=0)
+    Q0 = W.config2_state(case)
+    Q0[0, 40:70, 30:90] *= 1.03
+    outs = []
+    for ty in ("5", "13", "64", None):
+        if ty is None:
+            monkeypatch.delenv("FSA_STAGE_TY", raising=False)
+        else:
+            monkeypatch.setenv("FSA_STAGE_TY", ty)
+        s = _solver(case)
+        Q = torch_cuda.from_numpy(Q0.copy()).cuda()
+        L = s.rhs(Q)
+        s.rk3_steps(Q, case.dt, 2)
+        s.sync()
+        outs.append((L.cpu().numpy(), Q.cpu().numpy(), s.stats().rows_per_wave))
+    for L, Q, ty in outs[1:]:
+        assert np.array_equal(L, outs[0][0]) and np.array_equal(Q, outs[0][1]), ty
+    assert outs[-1][2] >= 8
