@@ -27,7 +27,7 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 fl
 PEAK_HBM_GBPS = 8000.0
 # Algorithmic FP64 operations per cell-stage of the 2D path (one op = one add, mul, div,
 # sqrt or compare of the method's plain formulation; see the design notes for the count).
-ALGO_FLOPS_2D = {"teno5": 1638, "weno5js": 1350}
+ALGO_FLOPS_2D = {"teno5": 1591, "weno5js": 1303}
 ALGO_BYTES_2D = 256.0 / 3.0  # FP64 state: read Qs (+ Qn in stages 2-3), write Q_{s+1}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_stage2d_teno5_2048_pmc.txt")
 KERNEL_SOURCES = ["paper_1905_00182_amd/csrc/k_stage2d.hip", "paper_1905_00182_amd/csrc/fsa_dev.hpp"]
