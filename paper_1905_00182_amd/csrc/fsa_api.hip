@@ -132,7 +132,7 @@ int validate(const fsa_desc* d, std::string& why)
     if (!(d->gamma > 1.0)) { why = "gamma must exceed 1"; return FSA_EINVAL; }
     if (d->mu < 0.0) { why = "mu must be non-negative"; return FSA_EINVAL; }
     if (d->scheme != FSA_WENO5JS && d->scheme != FSA_TENO5) { why = "bad scheme"; return FSA_EINVAL; }
-    if (d->precision != FSA_FP64) { why = "only FP64 is built"; return FSA_EUNSUPPORTED; }
+    if (d->precision != FSA_FP64 && d->precision != FSA_MIXED32) { why = "bad precision"; return FSA_EINVAL; }
     if (d->dim == 3) { why = "3D path not built"; return FSA_EUNSUPPORTED; }
     if (!(d->prim_inf[0] > 0.0) || !(d->prim_inf[4] > 0.0)) { why = "far field must have rho, p > 0"; return FSA_EINVAL; }
     return FSA_OK;
@@ -179,6 +179,25 @@ void build_consts(fsa_ctx* c)
     P.teno_ct = d.teno_ct;
     P.teno_eps = d.teno_eps;
     P.terms = d.terms;
+}
+
+// Physical fluxes of the far-field state per direction (the precision form stores split
+// fluxes relative to these).
+void far_field_fluxes(const fsa_ctx* c, KConst& k)
+{
+#pragma clang fp contract(off)
+    const int dim = c->d.dim;
+    const double* q = c->P.q_inf;
+    const double rho = c->d.prim_inf[0], p = c->d.prim_inf[4];
+    double* F[3] = {k.Fx_inf, k.Fy_inf, k.Fz_inf};
+    for (int d = 0; d < 3; ++d) {
+        for (int m = 0; m < 5; ++m) F[d][m] = 0.0;
+        if (d >= dim) continue;
+        const double ud = q[1 + d] / rho;
+        F[d][0] = q[1 + d];
+        for (int a = 0; a < dim; ++a) F[d][1 + a] = q[1 + a] * ud + (a == d ? p : 0.0);
+        F[d][dim + 1] = (q[dim + 1] + p) * ud;
+    }
 }
 
 // Rows per wave segment of the 2D stage kernel.  The best value depends on how the waves
@@ -370,7 +389,7 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         c->tused += 2;
         HIPCHK(c, hipEventRecord(t0, c->stream));
     }
-    e = launch_stage2d(c->dK, c->G, c->d.scheme, S, c->stream);
+    e = launch_stage2d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch");
     if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
     return FSA_OK;
@@ -398,7 +417,7 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
             if (ty > 2 * c->G.n[1] && ty != cand[0]) continue;
             S.ty = ty;
             HIPCHK(c, hipEventRecord(e0, c->stream));
-            int e = launch_stage2d(c->dK, c->G, c->d.scheme, S, c->stream);
+            int e = launch_stage2d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stream);
             if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch (tuning)");
             HIPCHK(c, hipEventRecord(e1, c->stream));
             HIPCHK(c, hipEventSynchronize(e1));
@@ -489,6 +508,7 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
         hk.G = c->G;
         hk.P = c->P;
         hk.inv12h = 1.0 / (12.0 * c->G.h);
+        far_field_fluxes(c, hk);
         if (hipMemcpy(c->dK, &hk, sizeof hk, hipMemcpyHostToDevice) != hipSuccess) {
             fsa_destroy(c);
             return FSA_EDEVICE;

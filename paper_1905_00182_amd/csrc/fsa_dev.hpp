@@ -170,6 +170,52 @@ __device__ __forceinline__ double recon5(double a, double b, double c, double d,
     }
 }
 
+// FP32 reconstruction of the precision form.  Same candidates and indicators; WENO5-JS as in
+// FP64; TENO5 in the normalised form gamma_k / gamma_max = ((1 + a_k) / (1 + a_max))^6,
+// a_k = tau5 / (beta_k + eps32), which cannot overflow in FP32 (eps32 = 1e-30 replaces the
+// FP64 1e-40, a subnormal in FP32); the cut-off test is the same ratio test.
+struct Recon32 {
+    float eps;
+    float ct;
+};
+
+template <int SCHEME>
+__device__ __forceinline__ float recon5f(float a, float b, float c, float d, float e, const Recon32& R)
+{
+    const float q0 = fmaf(11.0f / 6.0f, c, fmaf(-7.0f / 6.0f, b, (1.0f / 3.0f) * a));
+    const float q1 = fmaf(1.0f / 3.0f, d, fmaf(5.0f / 6.0f, c, (-1.0f / 6.0f) * b));
+    const float q2 = fmaf(-1.0f / 6.0f, e, fmaf(5.0f / 6.0f, d, (1.0f / 3.0f) * c));
+    const float s0 = fmaf(-2.0f, b, a) + c, t0 = fmaf(-4.0f, b, a) + 3.0f * c;
+    const float s1 = fmaf(-2.0f, c, b) + d, t1 = b - d;
+    const float s2 = fmaf(-2.0f, d, c) + e, t2 = fmaf(-4.0f, d, 3.0f * c) + e;
+    const float b0 = fmaf(13.0f / 12.0f * s0, s0, 0.25f * t0 * t0);
+    const float b1 = fmaf(13.0f / 12.0f * s1, s1, 0.25f * t1 * t1);
+    const float b2 = fmaf(13.0f / 12.0f * s2, s2, 0.25f * t2 * t2);
+    if (SCHEME == WENO5JS) {
+        const float e0 = R.eps + b0, e1 = R.eps + b1, e2 = R.eps + b2;
+        const float w0 = 0.1f * __builtin_amdgcn_rcpf(e0 * e0);
+        const float w1 = 0.6f * __builtin_amdgcn_rcpf(e1 * e1);
+        const float w2 = 0.3f * __builtin_amdgcn_rcpf(e2 * e2);
+        const float num = fmaf(w0, q0, fmaf(w1, q1, w2 * q2));
+        return num * __builtin_amdgcn_rcpf(w0 + w1 + w2);
+    } else {
+        const float tau = fabsf(b0 - b2);
+        const float a0 = tau * __builtin_amdgcn_rcpf(b0 + R.eps);
+        const float a1 = tau * __builtin_amdgcn_rcpf(b1 + R.eps);
+        const float a2 = tau * __builtin_amdgcn_rcpf(b2 + R.eps);
+        const float inv = __builtin_amdgcn_rcpf(1.0f + fmaxf(a0, fmaxf(a1, a2)));
+        const float x0 = (1.0f + a0) * inv, x1 = (1.0f + a1) * inv, x2 = (1.0f + a2) * inv;
+        const float c0 = x0 * x0 * x0, c1 = x1 * x1 * x1, c2 = x2 * x2 * x2;
+        const float g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2;
+        const float lim = R.ct * (g0 + g1 + g2);
+        const float d0 = g0 < lim ? 0.0f : 1.0f;
+        const float d1 = g1 < lim ? 0.0f : 6.0f;
+        const float d2 = g2 < lim ? 0.0f : 3.0f;
+        const float num = fmaf(d0, q0, fmaf(d1, q1, d2 * q2));
+        return num * __builtin_amdgcn_rcpf(d0 + d1 + d2);
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // Peskin four-point function (piecewise on |r| < 1, 1 <= |r| < 2).
 // ---------------------------------------------------------------------------------------
@@ -212,6 +258,7 @@ struct KConst {
     Grid G;
     Phys P;
     double inv12h;
+    double Fx_inf[5], Fy_inf[5], Fz_inf[5];   // physical fluxes of the far-field state
 
     __device__ __forceinline__ double eta_dir(int d, int i) const
     {

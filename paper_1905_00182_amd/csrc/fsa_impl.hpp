@@ -46,7 +46,7 @@ struct IBArgs {
     const double* mw;      // per marker: one-dimensional weights [nm][dim][4]
 };
 
-int launch_stage2d(const KConst* K, const Grid& G, int scheme, const StageArgs& A, hipStream_t s);
+int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, hipStream_t s);
 int stage2d_ncolx(int nx);
 int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* bits, hipStream_t s);
 int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s);

@@ -15,8 +15,15 @@
 // Boundary ghosts are resolved once per lane for x and once per row (a wave-uniform value)
 // for y; only inflow ghosts take the slow path.  Each state value is loaded from memory once
 // per wave: the output row is read back from a lane-private LDS ring of the last five front
-// rows.  Constants live in a device-side block and
-// are read where they are used, which keeps the scalar registers for the hot loop.
+// rows.  Constants live in a device-side block and are read where they are used.
+//
+// Arithmetic type T of the reconstruction and viscous fluxes: double (the FP64 method) or
+// float (the precision form).  In the precision form the windows hold, in FP32, the split
+// fluxes minus those of the far-field state, formed in FP64 before rounding; the far-field
+// part cancels exactly in the flux difference, so FP32 only ever carries deviations.  The
+// state, the sources, the RK3 combination and the wave speeds stay FP64.
+#include <type_traits>
+
 #include "fsa_impl.hpp"
 
 namespace fsa {
@@ -33,30 +40,52 @@ constexpr int DPP_WAVE_SHR1 = 0x138;
 constexpr int DPP_WAVE_SHL1 = 0x130;
 
 template <int CTRL>
-__device__ __forceinline__ double dpp64(double x)
+__device__ __forceinline__ double dpp(double x)
 {
     const long long b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
-__device__ __forceinline__ double lo1(double x) { return dpp64<DPP_WAVE_SHR1>(x); }
-__device__ __forceinline__ double up1(double x) { return dpp64<DPP_WAVE_SHL1>(x); }
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+template <class T>
+__device__ __forceinline__ T lo1(T x) { return dpp<DPP_WAVE_SHR1>(x); }
+template <class T>
+__device__ __forceinline__ T up1(T x) { return dpp<DPP_WAVE_SHL1>(x); }
 
 // Fourth-order central first derivative from the values at offsets -2..+2 (times 1/(12h)).
-__device__ __forceinline__ double d1(double gm2, double gm1, double gp1, double gp2, double inv12h)
+template <class T>
+__device__ __forceinline__ T d1(T gm2, T gm1, T gp1, T gp2, T inv12h)
 {
-    return (8.0 * (gp1 - gm1) - (gp2 - gm2)) * inv12h;
+    return (T(8) * (gp1 - gm1) - (gp2 - gm2)) * inv12h;
 }
 
-__device__ __forceinline__ double d1_lanes(double g, double inv12h)
+template <class T>
+__device__ __forceinline__ T d1_lanes(T g, T inv12h)
 {
-    const double l1 = lo1(g), u1 = up1(g);
+    const T l1 = lo1(g), u1 = up1(g);
     return d1(lo1(l1), l1, u1, up1(u1), inv12h);
 }
 
 template <int SCHEME>
+__device__ __forceinline__ double recon(double a, double b, double c, double d, double e, const Recon& R,
+                                        const Recon32&)
+{
+    return recon5<SCHEME>(a, b, c, d, e, R);
+}
+template <int SCHEME>
+__device__ __forceinline__ float recon(float a, float b, float c, float d, float e, const Recon&, const Recon32& R)
+{
+    return recon5f<SCHEME>(a, b, c, d, e, R);
+}
+
+template <int SCHEME, class T>
 struct Column2D {
+    static constexpr bool F64 = std::is_same<T, double>::value;
     const KConst* __restrict__ K;   // grid and physics constants (device memory)
     const double* __restrict__ Qs;
     const double* Qn;               // may alias out (last stage writes in place)
@@ -65,8 +94,10 @@ struct Column2D {
     long long ncell;
     int nx;
     int wlo0, wlo1, wn0, wn1;
-    double ax, ay, inv_h, inv12h, mu, gm1, ca, cb, dt;
+    double ax, ay, inv_h, gm1, ca, cb, dt;
+    T inv_hT, inv12h, mu;
     Recon R;
+    Recon32 R32;
     int mode_rhs, terms;
     int j0, j1;
     int xr;                         // resolved x index of this lane
@@ -78,10 +109,10 @@ struct Column2D {
     unsigned long long amax_x, amax_y;
     long long step;
     // register windows, slot = (row - first front row) mod 5
-    double fp[5][4], fm[5][4];
-    double uw[5], vw[5];
-    double txx[5], txy[5], tyy[5], bx[5], by[5];
-    double fy_prev[4], cy_queue[4];
+    T fp[5][4], fm[5][4];
+    T uw[5], vw[5];                 // velocities (minus the far-field velocity in FP32)
+    T txx[5], txy[5], tyy[5], bx[5], by[5];
+    T fy_prev[4], cy_queue[4];
     double qf[4];                   // prefetched state of the next front row
     double (*ring)[4][WAVE];        // LDS: the last five front rows of this wave, [slot][comp][lane]
     int lane;
@@ -98,6 +129,21 @@ struct Column2D {
             for (int c = 0; c < 4; ++c) q[c] = p[c * ncell];
         } else {
             fetch_state<2>(Qs, K->G, K->P, step, i, j, 0, q);
+        }
+    }
+
+    // Split fluxes f+- = (F +- alpha Q)/2 of component c of one direction, as stored in the
+    // windows (relative to the far field in FP32).
+    __device__ __forceinline__ void split(int c, double q, double F, double Finf, double alpha, T& fplus,
+                                          T& fminus) const
+    {
+        if (F64) {
+            fminus = (T)(0.5 * fma(-alpha, q, F));
+            fplus = (T)(0.5 * fma(alpha, q, F));
+        } else {
+            const double dq = q - K->P.q_inf[c], dF = F - Finf;
+            fminus = (T)(0.5 * fma(-alpha, dq, dF));
+            fplus = (T)(0.5 * fma(alpha, dq, dF));
         }
     }
 
@@ -128,26 +174,28 @@ struct Column2D {
         const double inv_rho = rcp_nr(q[0]);
         const double u = q[1] * inv_rho, v = q[2] * inv_rho;
         const double p = gm1 * (q[3] - 0.5 * fma(q[1], u, q[2] * v));
-        double fpr[4];
+        T fpr[4];
         {
             const double F[4] = {q[2], q[1] * v, fma(q[2], v, p), (q[3] + p) * v};
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                fm[S0][c] = 0.5 * fma(-ay, q[c], F[c]);
-                fpr[c] = 0.5 * fma(ay, q[c], F[c]);
-            }
+            for (int c = 0; c < 4; ++c) split(c, q[c], F[c], K->Fy_inf[c], ay, fpr[c], fm[S0][c]);
         }
-        uw[S0] = u;
-        vw[S0] = v;
+        if (F64) {
+            uw[S0] = (T)u;
+            vw[S0] = (T)v;
+        } else {
+            uw[S0] = (T)(u - K->P.prim_inf[1]);
+            vw[S0] = (T)(v - K->P.prim_inf[2]);
+        }
 
         // ---- y face (Rw-3)+1/2: f+ rows Rw-5..Rw-1, f- rows Rw..Rw-4
-        double cy_new[4] = {0.0, 0.0, 0.0, 0.0};
+        T cy_new[4] = {T(0), T(0), T(0), T(0)};
         if ((terms & T_CONVY) && Rw >= j0 + 2 && Rw <= j1 + 3) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const double fh = recon5<SCHEME>(fp[S0][c], fp[S4][c], fp[S3][c], fp[S2][c], fp[S1][c], R)
-                                + recon5<SCHEME>(fm[S0][c], fm[S1][c], fm[S2][c], fm[S3][c], fm[S4][c], R);
-                cy_new[c] = -(fh - fy_prev[c]) * inv_h;
+                const T fh = recon<SCHEME>(fp[S0][c], fp[S4][c], fp[S3][c], fp[S2][c], fp[S1][c], R, R32) +
+                             recon<SCHEME>(fm[S0][c], fm[S1][c], fm[S2][c], fm[S3][c], fm[S4][c], R, R32);
+                cy_new[c] = -(fh - fy_prev[c]) * inv_hT;
                 fy_prev[c] = fh;
             }
         }
@@ -156,51 +204,61 @@ struct Column2D {
 
         // ---- stress at row Rw-2 (velocities of rows Rw-4..Rw in the window)
         if ((terms & T_VISC) && Rw >= j0) {
-            const double uc = uw[S2], vc = vw[S2];
-            const double dudx = d1_lanes(uc, inv12h), dvdx = d1_lanes(vc, inv12h);
-            const double dudy = d1(uw[S4], uw[S3], uw[S1], uw[S0], inv12h);
-            const double dvdy = d1(vw[S4], vw[S3], vw[S1], vw[S0], inv12h);
-            const double div = dudx + dvdy;
-            const double sxx = mu * fma(-2.0 / 3.0, div, dudx + dudx);
-            const double syy = mu * fma(-2.0 / 3.0, div, dvdy + dvdy);
-            const double sxy = mu * (dudy + dvdx);
+            const T uc = uw[S2], vc = vw[S2];
+            const T dudx = d1_lanes(uc, inv12h), dvdx = d1_lanes(vc, inv12h);
+            const T dudy = d1(uw[S4], uw[S3], uw[S1], uw[S0], inv12h);
+            const T dvdy = d1(vw[S4], vw[S3], vw[S1], vw[S0], inv12h);
+            const T div = dudx + dvdy;
+            const T sxx = mu * fma(T(-2.0 / 3.0), div, dudx + dudx);
+            const T syy = mu * fma(T(-2.0 / 3.0), div, dvdy + dvdy);
+            const T sxy = mu * (dudy + dvdx);
             txx[S2] = sxx;
             txy[S2] = sxy;
             tyy[S2] = syy;
-            bx[S2] = fma(uc, sxx, vc * sxy);
-            by[S2] = fma(uc, sxy, vc * syy);
+            const T uf = F64 ? uc : uc + (T)K->P.prim_inf[1];
+            const T vf = F64 ? vc : vc + (T)K->P.prim_inf[2];
+            bx[S2] = fma(uf, sxx, vf * sxy);
+            by[S2] = fma(uf, sxy, vf * syy);
         }
 
         // ---- output row r = Rw-4
         if (do_out) {
+            double ur, vr;
+            if (F64) {
+                ur = (double)uw[S4];
+                vr = (double)vw[S4];
+            } else {
+                const double ir = rcp_nr(qr[0]);
+                ur = qr[1] * ir;
+                vr = qr[2] * ir;
+            }
             double L[4] = {0.0, 0.0, 0.0, 0.0};
             if (terms & T_CONVX) {
-                const double ur = uw[S4], vr = vw[S4];
                 const double pr = gm1 * (qr[3] - 0.5 * fma(qr[1], ur, qr[2] * vr));
                 const double F[4] = {qr[1], fma(qr[1], ur, pr), qr[2] * ur, (qr[3] + pr) * ur};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const double fpx = 0.5 * fma(ax, qr[c], F[c]);
-                    const double fmx = 0.5 * fma(-ax, qr[c], F[c]);
-                    const double pl1 = lo1(fpx), pu1 = up1(fpx);
-                    const double ml1 = lo1(fmx), mu1 = up1(fmx), mu2 = up1(mu1);
-                    const double fh = recon5<SCHEME>(lo1(pl1), pl1, fpx, pu1, up1(pu1), R) +
-                                      recon5<SCHEME>(up1(mu2), mu2, mu1, fmx, ml1, R);
-                    L[c] = -(fh - lo1(fh)) * inv_h;
+                    T fpx, fmx;
+                    split(c, qr[c], F[c], K->Fx_inf[c], ax, fpx, fmx);
+                    const T pl1 = lo1(fpx), pu1 = up1(fpx);
+                    const T ml1 = lo1(fmx), mu1 = up1(fmx), mu2 = up1(mu1);
+                    const T fh = recon<SCHEME>(lo1(pl1), pl1, fpx, pu1, up1(pu1), R, R32) +
+                                 recon<SCHEME>(up1(mu2), mu2, mu1, fmx, ml1, R, R32);
+                    L[c] = (double)(-(fh - lo1(fh)) * inv_hT);
                 }
             }
             if (terms & T_CONVY) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) L[c] += cy_queue[c];
+                for (int c = 0; c < 4; ++c) L[c] += (double)cy_queue[c];
             }
             if (terms & T_VISC) {
                 // rows r-2..r+2 sit in slots S1, S0, S4, S3, S2
-                const double vx = d1_lanes(txx[S4], inv12h) + d1(txy[S1], txy[S0], txy[S3], txy[S2], inv12h);
-                const double vy = d1_lanes(txy[S4], inv12h) + d1(tyy[S1], tyy[S0], tyy[S3], tyy[S2], inv12h);
-                const double ve = d1_lanes(bx[S4], inv12h) + d1(by[S1], by[S0], by[S3], by[S2], inv12h);
-                L[1] += vx;
-                L[2] += vy;
-                L[3] += ve;
+                const T vx = d1_lanes(txx[S4], inv12h) + d1(txy[S1], txy[S0], txy[S3], txy[S2], inv12h);
+                const T vy = d1_lanes(txy[S4], inv12h) + d1(tyy[S1], tyy[S0], tyy[S3], tyy[S2], inv12h);
+                const T ve = d1_lanes(bx[S4], inv12h) + d1(by[S1], by[S0], by[S3], by[S2], inv12h);
+                L[1] += (double)vx;
+                L[2] += (double)vy;
+                L[3] += (double)ve;
             }
             if (out_lane) {
                 double s[4] = {0.0, 0.0, 0.0, 0.0};
@@ -212,7 +270,7 @@ struct Column2D {
                         const double f0 = fwin[wc], f1 = fwin[wcells + wc];
                         s[1] = f0;
                         s[2] = f1;
-                        s[3] = fma(f0, uw[S4], f1 * vw[S4]);
+                        s[3] = fma(f0, ur, f1 * vr);
                     }
                 }
                 if (terms & T_SPONGE) {
@@ -253,11 +311,11 @@ struct Column2D {
     }
 };
 
-template <int SCHEME>
+template <int SCHEME, class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_stage2d(
     const KConst* __restrict__ K, StageArgs A)
 {
-    Column2D<SCHEME> C;
+    Column2D<SCHEME, T> C;
     C.K = K;
     C.Qs = A.Qs;
     C.Qn = A.Qn;
@@ -272,11 +330,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.ax = __longlong_as_double((long long)A.alpha_bits[0]);
     C.ay = __longlong_as_double((long long)A.alpha_bits[1]);
     C.inv_h = K->G.inv_h;
-    C.inv12h = K->inv12h;
-    C.mu = K->P.mu;
+    C.inv_hT = (T)K->G.inv_h;
+    C.inv12h = (T)K->inv12h;
+    C.mu = (T)K->P.mu;
     C.gm1 = K->P.gm1;
     C.R.eps = SCHEME == WENO5JS ? K->P.weno_eps : K->P.teno_eps;
     C.R.ct = K->P.teno_ct;
+    C.R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;
+    C.R32.ct = (float)K->P.teno_ct;
     C.ca = A.ca;
     C.cb = A.cb;
     C.dt = A.dt;
@@ -301,13 +362,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.j0 = blockIdx.y * A.ty;
     C.j1 = min(C.j0 + A.ty, ny) - 1;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) C.fy_prev[c] = C.cy_queue[c] = 0.0;
+    for (int c = 0; c < 4; ++c) C.fy_prev[c] = C.cy_queue[c] = T(0);
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) C.fp[s][c] = C.fm[s][c] = 0.0;
-        C.uw[s] = C.vw[s] = 0.0;
-        C.txx[s] = C.txy[s] = C.tyy[s] = C.bx[s] = C.by[s] = 0.0;
+        for (int c = 0; c < 4; ++c) C.fp[s][c] = C.fm[s][c] = T(0);
+        C.uw[s] = C.vw[s] = T(0);
+        C.txx[s] = C.txy[s] = C.tyy[s] = C.bx[s] = C.by[s] = T(0);
     }
     C.want_alpha = A.alpha_out != nullptr;
     C.amax_x = C.amax_y = 0ull;
@@ -341,13 +402,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
 }  // namespace
 
-int launch_stage2d(const KConst* K, const Grid& G, int scheme, const StageArgs& A, hipStream_t s)
+int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, hipStream_t s)
 {
     const int ncolx = (G.n[0] + OUTW - 1) / OUTW;
     const int nseg = (G.n[1] + A.ty - 1) / A.ty;
     dim3 grid(ncolx, nseg), block(WAVE);
-    if (scheme == TENO5) hipLaunchKernelGGL(k_stage2d<TENO5>, grid, block, 0, s, K, A);
-    else hipLaunchKernelGGL(k_stage2d<WENO5JS>, grid, block, 0, s, K, A);
+    if (precision == 1) {
+        if (scheme == TENO5) hipLaunchKernelGGL((k_stage2d<TENO5, float>), grid, block, 0, s, K, A);
+        else hipLaunchKernelGGL((k_stage2d<WENO5JS, float>), grid, block, 0, s, K, A);
+    } else {
+        if (scheme == TENO5) hipLaunchKernelGGL((k_stage2d<TENO5, double>), grid, block, 0, s, K, A);
+        else hipLaunchKernelGGL((k_stage2d<WENO5JS, double>), grid, block, 0, s, K, A);
+    }
     return (int)hipGetLastError();
 }
 
