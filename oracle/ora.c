@@ -761,6 +761,81 @@ int ora_rhs_cells(ora_ctx* c, const double* Q, int64_t nlist, const int64_t* cel
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Learned-weight inputs and labels (not in the paper: this library's definitions)        */
+/* ------------------------------------------------------------------------------------ */
+
+/* The five cells of one face side in upwind order: side 0 ("+") uses cells i-2..i+2 of the
+ * face between i and i+1 along dir; side 1 ("-") uses i+3..i-1.  Centre = position 2. */
+static void side_cells(int dir, const long* idx, int side, long cells[5][3])
+{
+    for (int s = 0; s < 5; ++s) {
+        long off = side == 0 ? (long)s - 2 : 3 - (long)s;
+        cells[s][0] = idx[0];
+        cells[s][1] = idx[1];
+        cells[s][2] = idx[2];
+        cells[s][dir] += off;
+    }
+}
+
+/* Features: for rho, the normal velocity (negated on side 1, so that both sides see the
+ * stencil in their upwind orientation) and p at the five cells, each variable's deviations
+ * from the centre divided by their largest magnitude (+1e-30): 15 values in [-1, 1]. */
+int ora_face_features(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side, double* out)
+{
+    if (dir < 0 || dir >= c->d.dim || side < 0 || side > 1) return -1;
+    long idx[3] = {i, j, k}, cells[5][3];
+    side_cells(dir, idx, side, cells);
+    double v[3][5];
+    for (int s = 0; s < 5; ++s) {
+        double q[5], u[3], p;
+        fetch(c, Q, cells[s][0], cells[s][1], cells[s][2], q);
+        primitives(c, q, u, &p);
+        v[0][s] = q[0];
+        v[1][s] = side == 0 ? u[dir] : -u[dir];
+        v[2][s] = p;
+    }
+    for (int m = 0; m < 3; ++m) {
+        double mx = 0.0;
+        for (int s = 0; s < 5; ++s) {
+            double dv = fabs(v[m][s] - v[m][2]);
+            if (dv > mx) mx = dv;
+        }
+        for (int s = 0; s < 5; ++s) out[m * 5 + s] = (v[m][s] - v[m][2]) / (mx + 1e-30);
+    }
+    return 0;
+}
+
+/* Label: bit k set when TENO5 keeps sub-stencil k for every conserved component of this
+ * face side's split flux (f+ on side 0, f- on side 1) at wave speed alpha.  A component
+ * whose five values agree to 1e-12 of their magnitude counts as keeping every sub-stencil:
+ * its TENO decision is then set by rounding noise and cannot change its face value. */
+int ora_face_label(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side, double alpha)
+{
+    if (dir < 0 || dir >= c->d.dim || side < 0 || side > 1) return -1;
+    long idx[3] = {i, j, k}, cells[5][3];
+    side_cells(dir, idx, side, cells);
+    double f[5][5];
+    for (int s = 0; s < 5; ++s) {
+        double q[5], F[5];
+        fetch(c, Q, cells[s][0], cells[s][1], cells[s][2], q);
+        phys_flux(c, q, dir, F);
+        for (int m = 0; m < c->nq; ++m) f[s][m] = 0.5 * (F[m] + (side == 0 ? alpha : -alpha) * q[m]);
+    }
+    int all = 7;
+    for (int m = 0; m < c->nq; ++m) {
+        double lo = f[0][m], hi = f[0][m], mag = 0.0;
+        for (int s = 0; s < 5; ++s) {
+            if (f[s][m] < lo) lo = f[s][m];
+            if (f[s][m] > hi) hi = f[s][m];
+            if (fabs(f[s][m]) > mag) mag = fabs(f[s][m]);
+        }
+        if (hi - lo <= 1e-12 * mag) continue;
+        all &= ora_teno_flags(f[0][m], f[1][m], f[2][m], f[3][m], f[4][m], c->d.teno_ct, c->d.teno_eps);
+    }
+    return all;
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* SSP-RK3 (Shu & Osher 1988)                                                             */
 /* ------------------------------------------------------------------------------------ */
 

@@ -87,6 +87,11 @@ int ora_marker_force(const ora_ctx* c, double* F);
 int ora_get_state(const ora_ctx* c, double* xi, double* t, int64_t* step);
 int ora_set_state(ora_ctx* c, const double* xi, double t, int64_t step);
 
+/* Learned-weight inputs and label of one face side (side 0 = f+ stencil i-2..i+2 of the face
+ * between cell idx and idx + e_dir, side 1 = f- stencil i+3..i-1); see ora.c. */
+int ora_face_features(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side, double* out);
+int ora_face_label(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side, double alpha);
+
 /* Scalar building blocks exposed for the pins. */
 double ora_delta4(double r);
 /* Reconstruction at a face from five upwind-ordered values. */

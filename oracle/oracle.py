@@ -77,6 +77,10 @@ def lib():
         _lib.ora_recon5.argtypes = [d, d, d, d, d, C.c_int, d, d, d]
         _lib.ora_teno_flags.restype = C.c_int
         _lib.ora_teno_flags.argtypes = [d, d, d, d, d, d, d]
+        _lib.ora_face_features.argtypes = [vp, dp, C.c_int, C.c_long, C.c_long, C.c_long, C.c_int, dp]
+        _lib.ora_face_features.restype = C.c_int
+        _lib.ora_face_label.argtypes = [vp, dp, C.c_int, C.c_long, C.c_long, C.c_long, C.c_int, d]
+        _lib.ora_face_label.restype = C.c_int
         _lib.ora_splitmix64.restype = C.c_uint64
         _lib.ora_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         for name in ("ora_set_markers", "ora_set_probes", "ora_alpha", "ora_rhs", "ora_rhs_cells",
@@ -234,6 +238,24 @@ class Oracle:
         out = np.empty(self.np)
         self._check(lib().ora_probe_dp(self.ctx, _ptr(Q), _ptr(out)), "probe_dp")
         return out
+
+    def face_features(self, Q, d, idx, side):
+        """15 features of one face side; idx = (i, j[, k]) of the cell left of the face."""
+        Q = self._state(Q)
+        out = np.empty(15)
+        i, j = idx[0], idx[1]
+        k = idx[2] if len(idx) > 2 else 0
+        self._check(lib().ora_face_features(self.ctx, _ptr(Q), d, i, j, k, side, _ptr(out)), "face_features")
+        return out
+
+    def face_label(self, Q, d, idx, side, alpha):
+        Q = self._state(Q)
+        i, j = idx[0], idx[1]
+        k = idx[2] if len(idx) > 2 else 0
+        r = lib().ora_face_label(self.ctx, _ptr(Q), d, i, j, k, side, alpha)
+        if r < 0:
+            raise ValueError("face_label failed")
+        return r
 
     def marker_force(self):
         out = np.empty((self.dim, self.nm))
