@@ -59,8 +59,10 @@ enum {
 enum { FSA_BC_PERIODIC = 0, FSA_BC_EXTRAP = 1, FSA_BC_INFLOW = 2 };
 /* Convective reconstruction. */
 enum { FSA_WENO5JS = 0, FSA_TENO5 = 1 };
-/* Arithmetic of the face reconstruction and viscous fluxes (the state is always FP64). */
-enum { FSA_FP64 = 0, FSA_MIXED32 = 1 };
+/* Arithmetic of the face reconstruction and viscous fluxes (the state is always FP64):
+ * FP64; FP32 on deviations from the far field (precision form); FP32 with the sub-stencils
+ * chosen by the learned selector (fsa_mlp_set), plain TENO5 on low-confidence faces. */
+enum { FSA_FP64 = 0, FSA_MIXED32 = 1, FSA_LEARNED32 = 2 };
 /* Marker motion. */
 enum { FSA_STATIC = 0, FSA_ROTATING = 1, FSA_EXTERNAL = 2 };
 /* Right-hand-side terms (bit mask). */
@@ -116,6 +118,8 @@ typedef struct fsa_stats {
     int32_t  n_probes;
     int32_t  window_cells;        /* cells of the box that holds every marker's support */
     int32_t  rows_per_wave;       /* segment height the 2D stage kernel runs with (0 = not tuned yet) */
+    int64_t  learned_sides;       /* face sides the learned selector has decided (cumulative) */
+    int64_t  fallback_sides;      /* of which fell back to plain TENO5 */
 } fsa_stats;
 
 int32_t     fsa_abi_version(void);
@@ -172,6 +176,36 @@ int32_t fsa_marker_force(fsa_ctx* ctx, double* h_F);
 /* Checkpoint: penalty integral h_xi[dim][n], time and step.  Synchronising. */
 int32_t fsa_get_state(fsa_ctx* ctx, double* h_xi, double* t, int64_t* step);
 int32_t fsa_set_state(fsa_ctx* ctx, const double* h_xi, double t, int64_t step);
+/* Learned TENO5 sub-stencil selector (not in the paper; the library's addition).  A network
+ * 15 -> 32 -> 32 -> 3 (ReLU, logits) maps the features of one face side -- rho, the normal
+ * velocity (negated on the "-" side) and p at its five upwind-ordered cells, each as
+ * deviations from the centre scaled by their largest magnitude (+1e-30) -- to keep
+ * probabilities of the three TENO5 sub-stencils, shared by all conserved components.  Flat
+ * parameters (FP32, 1667): W1[15][32], b1[32], W2[32][32], b2[32], W3[32][3], b3[3].  Inference
+ * and training run on BF16 MFMA with FP32 accumulation.  A side whose confidence
+ * min_k |2 sigmoid(z_k) - 1| is below conf_threshold, or with no sub-stencil predicted, uses
+ * plain TENO5 per component.  Labels: bit k set when FP64 TENO5 keeps sub-stencil k for every
+ * component (a component whose five values agree to 1e-12 counts as keeping all). */
+int32_t fsa_mlp_set(fsa_ctx* ctx, const float* h_params, int32_t nparams, double conf_threshold);
+int32_t fsa_mlp_get(fsa_ctx* ctx, float* h_params, int32_t nparams);            /* synchronising */
+/* Logits d_logits[n][3] of features d_feats[n][16] (column 15 ignored). */
+int32_t fsa_mlp_forward(fsa_ctx* ctx, const float* d_feats, int64_t n, float* d_logits);
+/* Mean binary cross-entropy d_loss[1] and its gradient d_grad[1667] over n samples. */
+int32_t fsa_mlp_grad(fsa_ctx* ctx, const float* d_feats, const uint8_t* d_labels, int64_t n, float* d_grad,
+                     float* d_loss);
+/* One Adam step (beta 0.9/0.999, eps 1e-8) on the gradient of this batch; d_loss may be NULL. */
+int32_t fsa_mlp_train_step(fsa_ctx* ctx, const float* d_feats, const uint8_t* d_labels, int64_t n, float lr,
+                           float* d_loss);
+/* Harvest training samples from a 2D state at its own wave speeds: every face side with a
+ * TENO5 cut-off and a seeded fraction keep_rate of the all-kept ones, written in face order
+ * (x faces, then y faces) as d_feats[max_out][16], d_labels[max_out].  *h_count receives the
+ * number selected (only the first max_out are written).  Synchronising. */
+int32_t fsa_harvest(fsa_ctx* ctx, const double* d_Q, double keep_rate, uint64_t seed, int64_t max_out,
+                    float* d_feats, uint8_t* d_labels, int64_t* h_count);
+/* Keep patterns the learned form uses for d_Q: x faces [(nx+1) ny], y faces [nx (ny+1)];
+ * bits 3c..3c+2 (side "+") and 16+3c.. (side "-") for component c. */
+int32_t fsa_face_flags(fsa_ctx* ctx, const double* d_Q, uint32_t* d_flags_x, uint32_t* d_flags_y);
+
 /* Measurement: with timing on, a pair of HIP events on the context's stream brackets every
  * launch of the fused stencil/update kernel.  fsa_timing_read (synchronising) returns the
  * summed kernel milliseconds and the number of launches since the previous read. */

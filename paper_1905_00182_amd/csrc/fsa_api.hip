@@ -13,6 +13,7 @@
 
 #include "fsa.h"
 #include "fsa_impl.hpp"
+#include "fsa_mlp.hpp"
 
 using namespace fsa;
 
@@ -60,6 +61,23 @@ struct fsa_ctx {
     double* Xp = nullptr;
     double t = 0.0;
     long long step = 0;
+    // learned selector
+    float* mlp_master = nullptr;
+    unsigned short* mlp_wbf = nullptr;
+    float* mlp_m = nullptr;
+    float* mlp_v = nullptr;
+    float* mlp_grad = nullptr;
+    float* mlp_partial = nullptr;
+    float* mlp_loss_part = nullptr;
+    int mlp_t = 0;
+    bool mlp_ready = false;
+    double conf_threshold = 0.8;
+    unsigned* flags_x = nullptr;
+    unsigned* flags_y = nullptr;
+    unsigned long long* counters = nullptr;
+    int* hv_count = nullptr;
+    long long* hv_offset = nullptr;
+    long long* hv_total = nullptr;
     // kernel timing
     bool timing = false;
     std::vector<hipEvent_t> tev;   // pairs (start, stop) per timed launch
@@ -132,7 +150,10 @@ int validate(const fsa_desc* d, std::string& why)
     if (!(d->gamma > 1.0)) { why = "gamma must exceed 1"; return FSA_EINVAL; }
     if (d->mu < 0.0) { why = "mu must be non-negative"; return FSA_EINVAL; }
     if (d->scheme != FSA_WENO5JS && d->scheme != FSA_TENO5) { why = "bad scheme"; return FSA_EINVAL; }
-    if (d->precision != FSA_FP64 && d->precision != FSA_MIXED32) { why = "bad precision"; return FSA_EINVAL; }
+    if (d->precision != FSA_FP64 && d->precision != FSA_MIXED32 && d->precision != FSA_LEARNED32) {
+        why = "bad precision";
+        return FSA_EINVAL;
+    }
     if (d->dim == 3) { why = "3D path not built"; return FSA_EUNSUPPORTED; }
     if (!(d->prim_inf[0] > 0.0) || !(d->prim_inf[4] > 0.0)) { why = "far field must have rho, p > 0"; return FSA_EINVAL; }
     return FSA_OK;
@@ -230,6 +251,7 @@ bool support_inside(const fsa_ctx* c, int n, const double* X)
 
 IBArgs ib_args(const fsa_ctx* c);
 int tune_ty(fsa_ctx* c, const StageArgs& S0);
+int enqueue_flags(fsa_ctx* c, const double* Qs, const unsigned long long* bits, unsigned* fx, unsigned* fy);
 
 // Window box over all marker supports and the CSR list window cell -> markers (in marker
 // order).  Index bookkeeping only; the weights are computed on the device.
@@ -352,11 +374,18 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         e = launch_ib_stage(c->G, c->P, A, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "IB stage launch");
     }
+    if (c->d.precision == FSA_LEARNED32) {
+        if (!c->mlp_ready) return fail(c, FSA_ESTATE, "learned form without a network (fsa_mlp_set)");
+        int rc = enqueue_flags(c, Qs, bits, c->flags_x, c->flags_y);
+        if (rc != FSA_OK) return rc;
+    }
     StageArgs S;
     std::memset(&S, 0, sizeof S);
     S.Qs = Qs;
     S.Qn = Qn;
     S.out = out;
+    S.flags_x = c->flags_x;
+    S.flags_y = c->flags_y;
     S.alpha_bits = bits;
     S.alpha_out = acc >= 0 ? c->abits + 3 * acc : nullptr;
     S.alpha_zero = clr >= 0 ? c->abits + 3 * clr : nullptr;
@@ -432,6 +461,47 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
     (void)hipEventDestroy(e1);
     c->ty = best;
     return FSA_OK;
+}
+
+MLPArgs mlp_args(const fsa_ctx* c)
+{
+    MLPArgs M;
+    M.master = c->mlp_master;
+    M.wbf = c->mlp_wbf;
+    M.m = c->mlp_m;
+    M.v = c->mlp_v;
+    return M;
+}
+
+int mlp_alloc(fsa_ctx* c)
+{
+    if (c->mlp_master) return FSA_OK;
+    int rc;
+    if ((rc = dalloc(c, c->mlp_master, MLP_NPARAM)) != FSA_OK || (rc = dalloc(c, c->mlp_wbf, MLP_NPARAM)) != FSA_OK ||
+        (rc = dalloc(c, c->mlp_m, MLP_NPARAM)) != FSA_OK || (rc = dalloc(c, c->mlp_v, MLP_NPARAM)) != FSA_OK ||
+        (rc = dalloc(c, c->mlp_grad, MLP_NPARAM)) != FSA_OK ||
+        (rc = dalloc(c, c->mlp_partial, (size_t)512 * MLP_NPARAM)) != FSA_OK ||
+        (rc = dalloc(c, c->mlp_loss_part, 512)) != FSA_OK || (rc = dalloc(c, c->counters, 2)) != FSA_OK)
+        return rc;
+    HIPCHK(c, hipMemset(c->counters, 0, 2 * sizeof(unsigned long long)));
+    return FSA_OK;
+}
+
+// Learned keep patterns of the faces of Qs (the learned form's per-stage pass).
+int enqueue_flags(fsa_ctx* c, const double* Qs, const unsigned long long* bits, unsigned* fx, unsigned* fy)
+{
+    FlagArgs F;
+    std::memset(&F, 0, sizeof F);
+    F.Q = Qs;
+    F.step = c->step;
+    F.alpha_bits = bits;
+    F.M = mlp_args(c);
+    F.conf_threshold = (float)c->conf_threshold;
+    F.flags_x = fx;
+    F.flags_y = fy;
+    F.counters = c->counters;
+    int e = launch_flags2d(c->dK, c->G, F, c->stream);
+    return e ? hipcheck(c, (hipError_t)e, "flags launch") : FSA_OK;
 }
 
 bool bits_finite(unsigned long long b)
@@ -514,6 +584,18 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
             return FSA_EDEVICE;
         }
     }
+    if (desc->precision == FSA_LEARNED32) {
+        if (desc->dim != 2) {
+            fsa_destroy(c);
+            return FSA_EUNSUPPORTED;
+        }
+        const size_t nfx = (size_t)(c->G.n[0] + 1) * c->G.n[1], nfy = (size_t)c->G.n[0] * (c->G.n[1] + 1);
+        if ((rc = dalloc(c, c->flags_x, nfx)) != FSA_OK || (rc = dalloc(c, c->flags_y, nfy)) != FSA_OK ||
+            (rc = mlp_alloc(c)) != FSA_OK) {
+            fsa_destroy(c);
+            return rc;
+        }
+    }
     if (hipHostMalloc((void**)&c->h_abits, 12 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_alpha, hipEventDisableTiming) != hipSuccess) {
         fsa_destroy(c);
@@ -549,6 +631,19 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->mj0);
     dfree(c->mw);
     dfree(c->Xp);
+    dfree(c->mlp_master);
+    dfree(c->mlp_wbf);
+    dfree(c->mlp_m);
+    dfree(c->mlp_v);
+    dfree(c->mlp_grad);
+    dfree(c->mlp_partial);
+    dfree(c->mlp_loss_part);
+    dfree(c->flags_x);
+    dfree(c->flags_y);
+    dfree(c->counters);
+    dfree(c->hv_count);
+    dfree(c->hv_offset);
+    dfree(c->hv_total);
     if (c->h_abits) (void)hipHostFree(c->h_abits);
     for (hipEvent_t ev : c->tev) (void)hipEventDestroy(ev);
     if (c->ev_alpha) (void)hipEventDestroy(c->ev_alpha);
@@ -731,6 +826,115 @@ int32_t fsa_set_state(fsa_ctx* c, const double* h_xi, double t, int64_t step)
     return FSA_OK;
 }
 
+int32_t fsa_mlp_set(fsa_ctx* c, const float* h_params, int32_t nparams, double conf_threshold)
+{
+    if (!c || !h_params) return FSA_EINVAL;
+    if (nparams != MLP_NPARAM) return fail(c, FSA_EINVAL, "the network has 1667 parameters");
+    if (!(conf_threshold >= 0.0 && conf_threshold <= 1.0)) return fail(c, FSA_EINVAL, "threshold outside [0, 1]");
+    int rc = mlp_alloc(c);
+    if (rc != FSA_OK) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->mlp_master, h_params, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemset(c->mlp_m, 0, sizeof(float) * MLP_NPARAM));
+    HIPCHK(c, hipMemset(c->mlp_v, 0, sizeof(float) * MLP_NPARAM));
+    int e = launch_mlp_round(mlp_args(c), c->stream);
+    if (e) return hipcheck(c, (hipError_t)e, "mlp round launch");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->mlp_t = 0;
+    c->conf_threshold = conf_threshold;
+    c->mlp_ready = true;
+    return FSA_OK;
+}
+
+int32_t fsa_mlp_get(fsa_ctx* c, float* h_params, int32_t nparams)
+{
+    if (!c || !h_params || nparams != MLP_NPARAM) return FSA_EINVAL;
+    if (!c->mlp_ready) return fail(c, FSA_ESTATE, "no network set");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(h_params, c->mlp_master, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
+    return FSA_OK;
+}
+
+int32_t fsa_mlp_forward(fsa_ctx* c, const float* d_feats, int64_t n, float* d_logits)
+{
+    if (!c || !d_feats || !d_logits || n < 0) return FSA_EINVAL;
+    if (!c->mlp_ready) return fail(c, FSA_ESTATE, "no network set");
+    int e = launch_mlp_forward(mlp_args(c), d_feats, n, d_logits, c->stream);
+    return e ? hipcheck(c, (hipError_t)e, "mlp forward launch") : FSA_OK;
+}
+
+int32_t fsa_mlp_grad(fsa_ctx* c, const float* d_feats, const uint8_t* d_labels, int64_t n, float* d_grad,
+                     float* d_loss)
+{
+    if (!c || !d_feats || !d_labels || !d_grad || n < 1) return FSA_EINVAL;
+    if (!c->mlp_ready) return fail(c, FSA_ESTATE, "no network set");
+    int e = launch_mlp_grad(mlp_args(c), d_feats, d_labels, n, c->mlp_partial, c->mlp_loss_part, d_grad, d_loss,
+                            c->stream);
+    return e ? hipcheck(c, (hipError_t)e, "mlp grad launch") : FSA_OK;
+}
+
+int32_t fsa_mlp_train_step(fsa_ctx* c, const float* d_feats, const uint8_t* d_labels, int64_t n, float lr,
+                           float* d_loss)
+{
+    if (!c || !d_feats || !d_labels || n < 1 || !(lr > 0.0f)) return FSA_EINVAL;
+    if (!c->mlp_ready) return fail(c, FSA_ESTATE, "no network set");
+    int e = launch_mlp_grad(mlp_args(c), d_feats, d_labels, n, c->mlp_partial, c->mlp_loss_part, c->mlp_grad, d_loss,
+                            c->stream);
+    if (e) return hipcheck(c, (hipError_t)e, "mlp grad launch");
+    c->mlp_t += 1;
+    e = launch_mlp_adam(mlp_args(c), c->mlp_grad, lr, c->mlp_t, c->stream);
+    return e ? hipcheck(c, (hipError_t)e, "adam launch") : FSA_OK;
+}
+
+int32_t fsa_harvest(fsa_ctx* c, const double* d_Q, double keep_rate, uint64_t seed, int64_t max_out, float* d_feats,
+                    uint8_t* d_labels, int64_t* h_count)
+{
+    if (!c || !d_Q || !h_count || max_out < 0 || (max_out > 0 && (!d_feats || !d_labels))) return FSA_EINVAL;
+    if (c->d.dim != 2) return fail(c, FSA_EUNSUPPORTED, "harvest is built for 2D");
+    if (!(keep_rate >= 0.0 && keep_rate <= 1.0)) return fail(c, FSA_EINVAL, "keep_rate outside [0, 1]");
+    const long long nb = harvest2d_blocks(c->G);
+    int rc;
+    if (!c->hv_count) {
+        if ((rc = dalloc(c, c->hv_count, (size_t)nb)) != FSA_OK || (rc = dalloc(c, c->hv_offset, (size_t)nb)) != FSA_OK ||
+            (rc = dalloc(c, c->hv_total, 1)) != FSA_OK)
+            return rc;
+    }
+    unsigned long long* bits = c->abits + 9;
+    int e = launch_alpha(c->G, c->P, d_Q, bits, c->stream);
+    if (e) return hipcheck(c, (hipError_t)e, "alpha launch");
+    HarvestArgs H;
+    std::memset(&H, 0, sizeof H);
+    H.Q = d_Q;
+    H.step = c->step;
+    H.alpha_bits = bits;
+    H.keep_rate = keep_rate;
+    H.seed = seed;
+    H.max_out = max_out;
+    H.feats = d_feats;
+    H.labels = d_labels;
+    H.block_count = c->hv_count;
+    H.block_offset = c->hv_offset;
+    H.total = c->hv_total;
+    e = launch_harvest2d(c->dK, c->G, H, c->stream);
+    if (e) return hipcheck(c, (hipError_t)e, "harvest launch");
+    long long tot = 0;
+    HIPCHK(c, hipMemcpyAsync(&tot, c->hv_total, sizeof tot, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *h_count = tot;
+    return FSA_OK;
+}
+
+int32_t fsa_face_flags(fsa_ctx* c, const double* d_Q, uint32_t* d_flags_x, uint32_t* d_flags_y)
+{
+    if (!c || !d_Q || !d_flags_x || !d_flags_y) return FSA_EINVAL;
+    if (c->d.dim != 2) return fail(c, FSA_EUNSUPPORTED, "learned flags are built for 2D");
+    if (!c->mlp_ready) return fail(c, FSA_ESTATE, "no network set");
+    unsigned long long* bits = c->abits + 9;
+    int e = launch_alpha(c->G, c->P, d_Q, bits, c->stream);
+    if (e) return hipcheck(c, (hipError_t)e, "alpha launch");
+    return enqueue_flags(c, d_Q, bits, d_flags_x, d_flags_y);
+}
+
 int32_t fsa_timing_enable(fsa_ctx* c, int32_t on)
 {
     if (!c) return FSA_EINVAL;
@@ -779,6 +983,12 @@ int32_t fsa_stats_get(fsa_ctx* c, fsa_stats* out)
     out->n_probes = c->np;
     out->window_cells = (int32_t)c->wcells;
     out->rows_per_wave = c->ty;
+    if (c->counters) {
+        unsigned long long hc[2];
+        HIPCHK(c, hipMemcpy(hc, c->counters, sizeof hc, hipMemcpyDeviceToHost));
+        out->learned_sides = (int64_t)hc[0];
+        out->fallback_sides = (int64_t)hc[1];
+    }
     return FSA_OK;
 }
 

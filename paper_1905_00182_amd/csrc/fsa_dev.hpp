@@ -9,7 +9,7 @@
 namespace fsa {
 
 enum : int { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_INFLOW = 2 };
-enum : int { WENO5JS = 0, TENO5 = 1 };
+enum : int { WENO5JS = 0, TENO5 = 1, LEARNED = 2 };
 enum : int { T_CONVX = 1, T_CONVY = 2, T_CONVZ = 4, T_VISC = 8, T_IB = 16, T_SPONGE = 32 };
 
 // Grid and physics constants, copied into every kernel's argument block.
@@ -214,6 +214,21 @@ __device__ __forceinline__ float recon5f(float a, float b, float c, float d, flo
         const float num = fmaf(d0, q0, fmaf(d1, q1, d2 * q2));
         return num * __builtin_amdgcn_rcpf(d0 + d1 + d2);
     }
+}
+
+// FP32 reconstruction with the sub-stencils given by keep bits (bit k = sub-stencil k): the
+// learned form.  The weighted sum is the same expression as recon5f's TENO5 branch, so all
+// bits set reproduces it exactly.
+__device__ __forceinline__ float recon5_bits(float a, float b, float c, float d, float e, int bits)
+{
+    const float q0 = fmaf(11.0f / 6.0f, c, fmaf(-7.0f / 6.0f, b, (1.0f / 3.0f) * a));
+    const float q1 = fmaf(1.0f / 3.0f, d, fmaf(5.0f / 6.0f, c, (-1.0f / 6.0f) * b));
+    const float q2 = fmaf(-1.0f / 6.0f, e, fmaf(5.0f / 6.0f, d, (1.0f / 3.0f) * c));
+    const float d0 = (bits & 1) ? 1.0f : 0.0f;
+    const float d1 = (bits & 2) ? 6.0f : 0.0f;
+    const float d2 = (bits & 4) ? 3.0f : 0.0f;
+    const float num = fmaf(d0, q0, fmaf(d1, q1, d2 * q2));
+    return num * __builtin_amdgcn_rcpf(d0 + d1 + d2);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -20,6 +20,8 @@ struct StageArgs {
     unsigned long long* alpha_out;         // if set: NaN-propagating max of |u_d| + c of the output
     unsigned long long* alpha_zero;        // if set: slot cleared by the first lane of the grid
     long long step;                        // step counter (inflow-noise counter)
+    const unsigned* flags_x;               // learned form: keep patterns of the x faces
+    const unsigned* flags_y;               // and of the y faces
 };
 
 // Arguments of the per-stage immersed-boundary kernel.

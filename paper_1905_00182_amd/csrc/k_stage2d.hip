@@ -83,6 +83,20 @@ __device__ __forceinline__ float recon(float a, float b, float c, float d, float
     return recon5f<SCHEME>(a, b, c, d, e, R);
 }
 
+// Face value of one side: the scheme's own weights, or the learned keep bits.
+template <int SCHEME, class T>
+__device__ __forceinline__ T recon_side(T a, T b, T c, T d, T e, const Recon& R, const Recon32& R32, int bits)
+{
+    if constexpr (SCHEME == LEARNED) {
+        (void)R;
+        (void)R32;
+        return recon5_bits(a, b, c, d, e, bits);
+    } else {
+        (void)bits;
+        return recon<SCHEME>(a, b, c, d, e, R, R32);
+    }
+}
+
 template <int SCHEME, class T>
 struct Column2D {
     static constexpr bool F64 = std::is_same<T, double>::value;
@@ -91,6 +105,8 @@ struct Column2D {
     const double* Qn;               // may alias out (last stage writes in place)
     double* out;
     const double* __restrict__ fwin;
+    const unsigned* __restrict__ flags_x;
+    const unsigned* __restrict__ flags_y;
     long long ncell;
     int nx;
     int wlo0, wlo1, wn0, wn1;
@@ -191,10 +207,14 @@ struct Column2D {
         // ---- y face (Rw-3)+1/2: f+ rows Rw-5..Rw-1, f- rows Rw..Rw-4
         T cy_new[4] = {T(0), T(0), T(0), T(0)};
         if ((terms & T_CONVY) && Rw >= j0 + 2 && Rw <= j1 + 3) {
+            unsigned word = 0;
+            if constexpr (SCHEME == LEARNED) word = flags_y[(long long)(Rw - 2) * nx + xr];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const T fh = recon<SCHEME>(fp[S0][c], fp[S4][c], fp[S3][c], fp[S2][c], fp[S1][c], R, R32) +
-                             recon<SCHEME>(fm[S0][c], fm[S1][c], fm[S2][c], fm[S3][c], fm[S4][c], R, R32);
+                const int bp = (int)(word >> (3 * c)) & 7, bm = (int)(word >> (16 + 3 * c)) & 7;
+                const T fh =
+                    recon_side<SCHEME, T>(fp[S0][c], fp[S4][c], fp[S3][c], fp[S2][c], fp[S1][c], R, R32, bp) +
+                    recon_side<SCHEME, T>(fm[S0][c], fm[S1][c], fm[S2][c], fm[S3][c], fm[S4][c], R, R32, bm);
                 cy_new[c] = -(fh - fy_prev[c]) * inv_hT;
                 fy_prev[c] = fh;
             }
@@ -236,14 +256,17 @@ struct Column2D {
             if (terms & T_CONVX) {
                 const double pr = gm1 * (qr[3] - 0.5 * fma(qr[1], ur, qr[2] * vr));
                 const double F[4] = {qr[1], fma(qr[1], ur, pr), qr[2] * ur, (qr[3] + pr) * ur};
+                unsigned word = 0;
+                if constexpr (SCHEME == LEARNED) word = flags_x[(long long)r * (nx + 1) + min(max(i + 1, 0), nx)];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     T fpx, fmx;
                     split(c, qr[c], F[c], K->Fx_inf[c], ax, fpx, fmx);
                     const T pl1 = lo1(fpx), pu1 = up1(fpx);
                     const T ml1 = lo1(fmx), mu1 = up1(fmx), mu2 = up1(mu1);
-                    const T fh = recon<SCHEME>(lo1(pl1), pl1, fpx, pu1, up1(pu1), R, R32) +
-                                 recon<SCHEME>(up1(mu2), mu2, mu1, fmx, ml1, R, R32);
+                    const int bp = (int)(word >> (3 * c)) & 7, bm = (int)(word >> (16 + 3 * c)) & 7;
+                    const T fh = recon_side<SCHEME, T>(lo1(pl1), pl1, fpx, pu1, up1(pu1), R, R32, bp) +
+                                 recon_side<SCHEME, T>(up1(mu2), mu2, mu1, fmx, ml1, R, R32, bm);
                     L[c] = (double)(-(fh - lo1(fh)) * inv_hT);
                 }
             }
@@ -321,6 +344,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.Qn = A.Qn;
     C.out = A.out;
     C.fwin = A.fwin;
+    C.flags_x = A.flags_x;
+    C.flags_y = A.flags_y;
     C.ncell = K->G.ncell;
     C.nx = K->G.n[0];
     C.wlo0 = A.wlo[0];
@@ -336,7 +361,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.gm1 = K->P.gm1;
     C.R.eps = SCHEME == WENO5JS ? K->P.weno_eps : K->P.teno_eps;
     C.R.ct = K->P.teno_ct;
-    C.R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;
+    C.R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;   // FP32 TENO5 epsilon
     C.R32.ct = (float)K->P.teno_ct;
     C.ca = A.ca;
     C.cb = A.cb;
@@ -407,7 +432,9 @@ int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, co
     const int ncolx = (G.n[0] + OUTW - 1) / OUTW;
     const int nseg = (G.n[1] + A.ty - 1) / A.ty;
     dim3 grid(ncolx, nseg), block(WAVE);
-    if (precision == 1) {
+    if (precision == 2) {
+        hipLaunchKernelGGL((k_stage2d<LEARNED, float>), grid, block, 0, s, K, A);
+    } else if (precision == 1) {
         if (scheme == TENO5) hipLaunchKernelGGL((k_stage2d<TENO5, float>), grid, block, 0, s, K, A);
         else hipLaunchKernelGGL((k_stage2d<WENO5JS, float>), grid, block, 0, s, K, A);
     } else {

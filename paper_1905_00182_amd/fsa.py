@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libfsa.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 BC = {"periodic": 0, "extrap": 1, "inflow": 2}
 SCHEME = {"weno5js": 0, "teno5": 1}
-PRECISION = {"fp64": 0, "mixed32": 1}
+PRECISION = {"fp64": 0, "mixed32": 1, "learned32": 2}
+MLP_NPARAM = 1667
 MOTION = {"static": 0, "rotating": 1, "external": 2}
 TERM = {"conv_x": 1, "conv_y": 2, "conv_z": 4, "visc": 8, "ib": 16, "sponge": 32, "all": 63}
 
@@ -63,6 +64,8 @@ class FsaStats(C.Structure):
         ("n_probes", C.c_int32),
         ("window_cells", C.c_int32),
         ("rows_per_wave", C.c_int32),
+        ("learned_sides", C.c_int64),
+        ("fallback_sides", C.c_int64),
     ]
 
 
@@ -88,6 +91,14 @@ _SIGS = {
     "fsa_marker_force": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fsa_get_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "fsa_set_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]),
+    "fsa_mlp_set": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double]),
+    "fsa_mlp_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "fsa_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "fsa_mlp_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "fsa_mlp_train_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p]),
+    "fsa_harvest": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p,
+                                C.POINTER(C.c_int64)]),
+    "fsa_face_flags": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fsa_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
     "fsa_timing_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "fsa_sync": (C.c_int32, [C.c_void_p]),
@@ -264,6 +275,53 @@ class Solver:
     def set_state(self, xi, t, step):
         xa = _host(xi) if xi is not None else None
         self._check(lib().fsa_set_state(self.ctx, xa.ctypes.data if xa is not None else None, t, step))
+
+    # -- learned selector
+    def mlp_set(self, params, conf_threshold=0.8):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape == (MLP_NPARAM,)
+        self._check(lib().fsa_mlp_set(self.ctx, p.ctypes.data, MLP_NPARAM, conf_threshold))
+
+    def mlp_get(self):
+        p = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self._check(lib().fsa_mlp_get(self.ctx, p.ctypes.data, MLP_NPARAM))
+        return p
+
+    def mlp_forward(self, feats):
+        t = self.torch
+        assert feats.dtype == t.float32 and feats.is_contiguous() and feats.shape[1] == 16
+        z = t.empty((feats.shape[0], 3), dtype=t.float32, device=feats.device)
+        self._check(lib().fsa_mlp_forward(self.ctx, _ptr(feats), feats.shape[0], _ptr(z)))
+        return z
+
+    def mlp_grad(self, feats, labels):
+        t = self.torch
+        g = t.empty(MLP_NPARAM, dtype=t.float32, device=feats.device)
+        loss = t.empty(1, dtype=t.float32, device=feats.device)
+        self._check(lib().fsa_mlp_grad(self.ctx, _ptr(feats), _ptr(labels), feats.shape[0], _ptr(g), _ptr(loss)))
+        return g, loss
+
+    def mlp_train_step(self, feats, labels, lr, loss=None):
+        self._check(lib().fsa_mlp_train_step(self.ctx, _ptr(feats), _ptr(labels), feats.shape[0], lr,
+                                             _ptr(loss) if loss is not None else None))
+
+    def harvest(self, Q, keep_rate, seed, max_out):
+        t = self.torch
+        feats = t.empty((max(max_out, 1), 16), dtype=t.float32, device=Q.device)
+        labels = t.empty(max(max_out, 1), dtype=t.uint8, device=Q.device)
+        n = C.c_int64()
+        self._check(lib().fsa_harvest(self.ctx, _ptr(self._state(Q)), keep_rate, seed, max_out, _ptr(feats),
+                                      _ptr(labels), C.byref(n)))
+        k = min(n.value, max_out)
+        return feats[:k], labels[:k], n.value
+
+    def face_flags(self, Q):
+        t = self.torch
+        nx, ny = self.case.n[0], self.case.n[1]
+        fx = t.empty((ny, nx + 1), dtype=t.int32, device=Q.device)
+        fy = t.empty((ny + 1, nx), dtype=t.int32, device=Q.device)
+        self._check(lib().fsa_face_flags(self.ctx, _ptr(self._state(Q)), _ptr(fx), _ptr(fy)))
+        return fx, fy
 
     def timing(self, on=True):
         self._check(lib().fsa_timing_enable(self.ctx, 1 if on else 0))

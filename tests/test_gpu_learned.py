@@ -1,0 +1,283 @@
+"""The learned TENO5 selector on the GPU, through the C ABI, against the FP64 references:
+
+* BF16 MFMA forward and backward against the oracle network fed the same BF16-rounded values
+  (FP32 accumulation order is the only difference: 1e-3 relative);
+* harvested features and labels against the oracle's face features and labels;
+* the learned stage with a network that always falls back equals the FP32 precision form
+  bitwise, and with a network that keeps every sub-stencil equals it wherever TENO5 keeps all;
+* a network trained on the GPU from harvested faces: loss falls, and the FP32+learned run
+  matches the FP64 oracle's acoustic pressure within 1%.
+"""
+import numpy as np
+import pytest
+
+from paper_1905_00182_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+def _say(*a):
+    print("[gpu]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mlp():
+    from oracle import mlp as M
+
+    return M
+
+
+def _solver(case, **kw):
+    from paper_1905_00182_amd import fsa
+
+    return fsa.Solver(case, **kw)
+
+
+def _small(n=128, precision="learned32"):
+    return W.config2(n=n, h=1.0 / 16.0, sponge=2.0, nprobe=0).with_(precision=precision)
+
+
+def _rand_theta(mlp, seed):
+    return np.float32(mlp.init_params(seed) + 0.05 * np.random.default_rng(seed).normal(size=mlp.NPARAM)).astype(np.float64)
+
+
+def _rand_feats(n, seed):
+    f = np.random.default_rng(seed).uniform(-1, 1, size=(n, 16)).astype(np.float32)
+    f[:, 15] = 0.0
+    return f
+
+
+def test_mlp_forward_matches_oracle(torch_cuda, mlp):
+    s = _solver(_small())
+    theta = _rand_theta(mlp, 1)
+    s.mlp_set(theta)
+    X = _rand_feats(1000, 2)
+    zg = s.mlp_forward(torch_cuda.from_numpy(X).cuda()).cpu().numpy()
+    zo, _ = mlp.forward(theta, X[:, :15].astype(np.float64), emulate=True)
+    rel = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
+    _say("forward rel", rel)
+    assert rel < 1e-3
+    assert np.abs(zg - zo).max() < 1e-2 * np.abs(zo).max()
+
+
+def test_mlp_gradient_matches_oracle(torch_cuda, mlp):
+    s = _solver(_small())
+    theta = _rand_theta(mlp, 3)
+    s.mlp_set(theta)
+    X = _rand_feats(777, 4)
+    Y = np.random.default_rng(5).integers(0, 8, size=777).astype(np.uint8)
+    g, loss = s.mlp_grad(torch_cuda.from_numpy(X).cuda(), torch_cuda.from_numpy(Y).cuda())
+    Yb = np.stack([(Y >> k) & 1 for k in range(3)], axis=1).astype(np.float64)
+    lo, go = mlp.loss_and_grad(theta, X[:, :15].astype(np.float64), Yb, emulate=True)
+    gg = g.cpu().numpy()
+    rel = np.linalg.norm(gg - go) / np.linalg.norm(go)
+    _say("loss", float(loss.item()), lo, "grad rel", rel)
+    assert abs(float(loss.item()) - lo) <= 1e-5 * lo
+    assert rel < 1e-3
+    for name, (a, b) in {"W1": (0, 480), "W2": (512, 1536), "W3": (1568, 1664), "b": (1664, 1667)}.items():
+        assert np.linalg.norm(gg[a:b] - go[a:b]) <= 2e-3 * np.linalg.norm(go[a:b]) + 1e-12, name
+
+
+def test_adam_step_matches_oracle(torch_cuda, mlp):
+    s = _solver(_small())
+    theta = _rand_theta(mlp, 6)
+    s.mlp_set(theta)
+    X = _rand_feats(512, 7)
+    Y = np.random.default_rng(8).integers(0, 8, size=512).astype(np.uint8)
+    s.mlp_train_step(torch_cuda.from_numpy(X).cuda(), torch_cuda.from_numpy(Y).cuda(), 1e-3)
+    got = s.mlp_get().astype(np.float64)
+    Yb = np.stack([(Y >> k) & 1 for k in range(3)], axis=1).astype(np.float64)
+    _, go = mlp.loss_and_grad(theta, X[:, :15].astype(np.float64), Yb, emulate=True)
+    want, _, _ = mlp.adam(theta, np.zeros_like(theta), np.zeros_like(theta), go, 1, 1e-3)
+    close = np.abs(got - want) <= 1e-3 * 1e-3 + 1e-6 * np.abs(want)
+    _say("adam: fraction within 1e-3 lr:", close.mean())
+    assert close.mean() > 0.99
+
+
+def test_harvest_matches_oracle(torch_cuda):
+    from oracle.oracle import Oracle
+
+    case = _small(n=96)
+    Q0 = W.config2_state(case)
+    Q0[0, 30:50, 40:60] *= 1.05
+    s = _solver(case)
+    nx, ny = case.n[0], case.n[1]
+    total = 2 * ((nx + 1) * ny + nx * (ny + 1))
+    feats, labels, n = s.harvest(torch_cuda.from_numpy(Q0).cuda(), 1.0, 1, total)
+    assert n == total
+    F, L = feats.cpu().numpy(), labels.cpu().numpy()
+    o = Oracle(case)
+    alpha = o.alpha(Q0)
+    rng = np.random.default_rng(9)
+    cut = np.flatnonzero(L != 7)
+    assert len(cut) > 50
+    picks = np.concatenate([rng.choice(total, 300, replace=False), rng.choice(cut, 200, replace=False)])
+    nfx = (nx + 1) * ny
+    bad = 0
+    for idx in picks:
+        face, sd = divmod(int(idx), 2)
+        if face < nfx:
+            d, j, i = 0, face // (nx + 1), face % (nx + 1) - 1
+        else:
+            d, j, i = 1, (face - nfx) // nx - 1, (face - nfx) % nx
+        fo = o.face_features(Q0, d, (i, j), sd)
+        np.testing.assert_allclose(F[idx, :15], fo, rtol=0, atol=1e-6)
+        bad += int(L[idx] != o.face_label(Q0, d, (i, j), sd, alpha[d]))
+    _say("harvest: label mismatches", bad, "of", len(picks), "; cut-off sides", len(cut), "of", total)
+    assert bad == 0
+
+
+def test_harvest_selection_is_deterministic(torch_cuda):
+    case = _small(n=96)
+    Q = torch_cuda.from_numpy(W.config2_state(case)).cuda()
+    s = _solver(case)
+    a = s.harvest(Q, 0.1, 7, 200000)
+    b = s.harvest(Q, 0.1, 7, 200000)
+    assert a[2] == b[2] and torch_cuda.equal(a[0], b[0]) and torch_cuda.equal(a[1], b[1])
+    assert (a[1] != 7).sum().item() > 0
+
+
+def _const_net(mlp, logit):
+    theta = np.zeros(mlp.NPARAM)
+    theta[1664:1667] = logit
+    return theta
+
+
+def test_learned_fallback_equals_precision_form(torch_cuda, mlp):
+    case = _small(n=160)
+    Q0 = W.config2_state(case)
+    Q0[0, 60:80, 40:90] *= 1.04
+    Q = torch_cuda.from_numpy(Q0).cuda()
+    s32 = _solver(case.with_(precision="mixed32"))
+    L32 = s32.rhs(Q)
+    sl = _solver(case)
+    sl.mlp_set(_const_net(mlp, -10.0), 0.8)          # predicts no sub-stencil: all sides fall back
+    Ll = sl.rhs(Q)
+    sl.sync()
+    st = sl.stats()
+    assert st.fallback_sides == st.learned_sides > 0
+    assert torch_cuda.equal(L32, Ll)
+
+
+def test_learned_keep_all_equals_precision_form_on_smooth_data(torch_cuda, mlp):
+    case = W.periodic_box(dim=2, n=128, scheme="teno5", mu=0.002).with_(precision="learned32")
+    Q0 = W.perturbed_state(case, seed=11, amp=1e-3)
+    Q = torch_cuda.from_numpy(Q0).cuda()
+    sl = _solver(case)
+    sl.mlp_set(_const_net(mlp, 10.0), 0.8)           # confident: keep every sub-stencil
+    fx, fy = sl.face_flags(Q)
+    assert torch_cuda.all(fx == 0x0FFF0FFF) and torch_cuda.all(fy == 0x0FFF0FFF)
+    Ll = sl.rhs(Q)
+    s32 = _solver(case.with_(precision="mixed32"))
+    L32 = s32.rhs(Q)
+    s32.sync()
+    assert torch_cuda.equal(L32, Ll)
+
+
+def _trajectory(torch, case, Q0, chunks, every):
+    s = _solver(case.with_(precision="fp64"))
+    Q = torch.from_numpy(Q0.copy()).cuda()
+    out = [Q.clone()]
+    for _ in range(chunks):
+        s.rk3_steps(Q, case.dt, every)
+        out.append(Q.clone())
+    s.sync()
+    return s, out
+
+
+@pytest.fixture(scope="module")
+def trained(torch_cuda, mlp):
+    """A selector trained on the GPU from faces harvested along FP64 runs of the scattering case
+    (TENO5) and the rotating-cylinder miniature."""
+    torch = torch_cuda
+    c1 = W.config1(n=128, scheme="teno5")
+    c2 = W.config2(n=256, h=1.0 / 16.0, sponge=2.0, nprobe=48, rprobe=5.0)
+    F, L = [], []
+    for c, Q0 in ((c1, W.config1_state(c1)), (c2, W.config2_state(c2))):
+        s, traj = _trajectory(torch, c, Q0, 5, 20)
+        for k, Q in enumerate(traj):
+            f, l, n = s.harvest(Q, 0.05, 100 + k, 1 << 20)
+            F.append(f.clone())
+            L.append(l.clone())
+    F, L = torch.cat(F), torch.cat(L)
+    ncut = int((L != 7).sum().item())
+    _say("harvested", F.shape[0], "sides;", ncut, "with a cut sub-stencil")
+    tr = _solver(_small())
+    tr.mlp_set(np.float32(mlp.init_params(42)), 0.8)
+    perm = torch.randperm(F.shape[0], generator=torch.Generator().manual_seed(0)).cuda()
+    F, L = F[perm].contiguous(), L[perm].contiguous()
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    B = 4096
+    losses = []
+    nb = max(F.shape[0] // B, 1)
+    for step in range(1500):
+        a = (step % nb) * B
+        tr.mlp_train_step(F[a:a + B], L[a:a + B], 3e-3 if step < 1000 else 1e-3, loss)
+        if step % 250 == 0 or step == 1499:
+            losses.append(round(float(loss.item()), 5))
+    _say("training loss", losses)
+    z = tr.mlp_forward(F).cpu().numpy()
+    bits = (z[:, 0] > 0) | ((z[:, 1] > 0) << 1) | ((z[:, 2] > 0) << 2)
+    Lh = L.cpu().numpy()
+    acc = np.mean(bits == Lh)
+    acc_cut = np.mean(bits[Lh != 7] == Lh[Lh != 7]) if ncut else 1.0
+    _say(f"training-set accuracy {acc:.4f}, on cut sides {acc_cut:.4f}")
+    return {"theta": tr.mlp_get(), "losses": losses, "acc": acc, "c1": c1, "c2": c2}
+
+
+def test_training_reduces_loss(trained):
+    assert trained["losses"][-1] < 0.5 * trained["losses"][0]
+    assert trained["acc"] > 0.9
+
+
+def _learned_vs_oracle(torch, case, Q0, theta, nsteps):
+    from oracle.oracle import Oracle
+
+    o = Oracle(case)
+    Qo = Q0.copy()
+    dpo = []
+    for _ in range(nsteps):
+        o.rk3_step(Qo, case.dt)
+        dpo.append(o.probe_dp(Qo))
+    dpo = np.array(dpo)
+    res = {}
+    for prec in ("mixed32", "learned32"):
+        sv = _solver(case.with_(precision=prec))
+        if prec == "learned32":
+            sv.mlp_set(theta, 0.8)
+        Q = torch.from_numpy(Q0.copy()).cuda()
+        dp = []
+        for _ in range(nsteps):
+            sv.rk3_step(Q, case.dt)
+            dp.append(sv.probe_dp(Q).cpu().numpy())
+        sv.sync()
+        dp = np.array(dp)
+        st = sv.stats()
+        fb = st.fallback_sides / max(st.learned_sides, 1)
+        res[prec] = (np.linalg.norm(dp - dpo) / np.linalg.norm(dpo), fb)
+    _say(f"{case.name} {case.n[:2]}, {nsteps} steps: e_p precision form {res['mixed32'][0]:.3e}, "
+         f"learned {res['learned32'][0]:.3e} (fallback fraction {res['learned32'][1]:.4f}); "
+         f"probe |dp| up to {np.abs(dpo).max():.2e}")
+    return res
+
+
+def test_learned_acoustic_error_config1(torch_cuda, trained):
+    c = trained["c1"]
+    res = _learned_vs_oracle(torch_cuda, c, W.config1_state(c), trained["theta"], c.steps)
+    assert res["learned32"][0] < 1e-2
+
+
+def test_learned_acoustic_error_config2_small(torch_cuda, trained):
+    c = trained["c2"]
+    res = _learned_vs_oracle(torch_cuda, c, W.config2_state(c), trained["theta"], 40)
+    assert res["learned32"][0] < 1e-2
