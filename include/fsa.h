@@ -120,6 +120,7 @@ typedef struct fsa_stats {
     int32_t  rows_per_wave;       /* segment height the 2D stage kernel runs with (0 = not tuned yet) */
     int64_t  learned_sides;       /* face sides the learned selector has decided (cumulative) */
     int64_t  fallback_sides;      /* of which fell back to plain TENO5 */
+    int64_t  significant_sides;   /* of which were significant (evaluated by the network) */
 } fsa_stats;
 
 int32_t     fsa_abi_version(void);
@@ -176,16 +177,19 @@ int32_t fsa_marker_force(fsa_ctx* ctx, double* h_F);
 /* Checkpoint: penalty integral h_xi[dim][n], time and step.  Synchronising. */
 int32_t fsa_get_state(fsa_ctx* ctx, double* h_xi, double* t, int64_t* step);
 int32_t fsa_set_state(fsa_ctx* ctx, const double* h_xi, double t, int64_t step);
-/* Learned TENO5 sub-stencil selector (not in the paper; the library's addition).  A network
- * 15 -> 32 -> 32 -> 3 (ReLU, logits) maps the features of one face side -- rho, the normal
- * velocity (negated on the "-" side) and p at its five upwind-ordered cells, each as
- * deviations from the centre scaled by their largest magnitude (+1e-30) -- to keep
- * probabilities of the three TENO5 sub-stencils, shared by all conserved components.  Flat
- * parameters (FP32, 1667): W1[15][32], b1[32], W2[32][32], b2[32], W3[32][3], b3[3].  Inference
- * and training run on BF16 MFMA with FP32 accumulation.  A side whose confidence
- * min_k |2 sigmoid(z_k) - 1| is below conf_threshold, or with no sub-stencil predicted, uses
- * plain TENO5 per component.  Labels: bit k set when FP64 TENO5 keeps sub-stencil k for every
- * component (a component whose five values agree to 1e-12 counts as keeping all). */
+/* Learned TENO5 sub-stencil selector (not in the paper; the library's addition).  A face side
+ * is significant when rho, a velocity component or p varies over its five cells by more than
+ * 1e-8 of its natural scale (rho_inf, c_inf, rho_inf c_inf^2); an insignificant side keeps
+ * every sub-stencil.  For significant sides a network 15 -> 32 -> 32 -> 3 (ReLU, logits) maps
+ * the features -- rho, the normal velocity (negated on the "-" side) and p at the five
+ * upwind-ordered cells, each as deviations from the centre over (their largest magnitude +
+ * 1e-8 of the natural scale) -- to keep probabilities of the three TENO5 sub-stencils, shared
+ * by all conserved components.  Flat parameters (FP32, 1667): W1[15][32], b1[32], W2[32][32],
+ * b2[32], W3[32][3], b3[3].  Inference and training run on BF16 MFMA with FP32 accumulation.
+ * A side whose confidence min_k |2 sigmoid(z_k) - 1| is below conf_threshold, or with no
+ * sub-stencil predicted, uses plain TENO5 per component.  Labels: bit k set when FP64 TENO5
+ * keeps sub-stencil k for every component (a component whose five values agree to 1e-12
+ * counts as keeping all). */
 int32_t fsa_mlp_set(fsa_ctx* ctx, const float* h_params, int32_t nparams, double conf_threshold);
 int32_t fsa_mlp_get(fsa_ctx* ctx, float* h_params, int32_t nparams);            /* synchronising */
 /* Logits d_logits[n][3] of features d_feats[n][16] (column 15 ignored). */
@@ -196,8 +200,10 @@ int32_t fsa_mlp_grad(fsa_ctx* ctx, const float* d_feats, const uint8_t* d_labels
 /* One Adam step (beta 0.9/0.999, eps 1e-8) on the gradient of this batch; d_loss may be NULL. */
 int32_t fsa_mlp_train_step(fsa_ctx* ctx, const float* d_feats, const uint8_t* d_labels, int64_t n, float lr,
                            float* d_loss);
-/* Harvest training samples from a 2D state at its own wave speeds: every face side with a
- * TENO5 cut-off and a seeded fraction keep_rate of the all-kept ones, written in face order
+/* Harvest training samples from a 2D state at its own wave speeds: every significant face
+ * side with a TENO5 cut-off and a seeded fraction keep_rate of the significant all-kept ones
+ * (side s of face f is kept when the SplitMix64 number 2 f' + s of seed, as a uniform in
+ * [0, 1), is below keep_rate; f' counts x faces first, then y faces), written in face order
  * (x faces, then y faces) as d_feats[max_out][16], d_labels[max_out].  *h_count receives the
  * number selected (only the first max_out are written).  Synchronising. */
 int32_t fsa_harvest(fsa_ctx* ctx, const double* d_Q, double keep_rate, uint64_t seed, int64_t max_out,

@@ -777,15 +777,26 @@ static void side_cells(int dir, const long* idx, int side, long cells[5][3])
     }
 }
 
+/* Natural scales of rho, velocity and p: rho_inf, c_inf and rho_inf c_inf^2 of the far field. */
+static void natural_scales(const ora_ctx* c, double* srho, double* svel, double* sp)
+{
+    const double cinf = sqrt(c->d.gamma * c->d.prim_inf[4] / c->d.prim_inf[0]);
+    *srho = c->d.prim_inf[0];
+    *svel = cinf;
+    *sp = c->d.prim_inf[0] * cinf * cinf;
+}
+
 /* Features: for rho, the normal velocity (negated on side 1, so that both sides see the
  * stencil in their upwind orientation) and p at the five cells, each variable's deviations
- * from the centre divided by their largest magnitude (+1e-30): 15 values in [-1, 1]. */
+ * from the centre divided by (their largest magnitude + 1e-8 times the variable's natural
+ * scale): 15 values in [-1, 1].  The floor maps variations at rounding level to ~0. */
 int ora_face_features(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side, double* out)
 {
     if (dir < 0 || dir >= c->d.dim || side < 0 || side > 1) return -1;
     long idx[3] = {i, j, k}, cells[5][3];
     side_cells(dir, idx, side, cells);
-    double v[3][5];
+    double v[3][5], sc[3];
+    natural_scales(c, &sc[0], &sc[1], &sc[2]);
     for (int s = 0; s < 5; ++s) {
         double q[5], u[3], p;
         fetch(c, Q, cells[s][0], cells[s][1], cells[s][2], q);
@@ -800,7 +811,39 @@ int ora_face_features(const ora_ctx* c, const double* Q, int dir, long i, long j
             double dv = fabs(v[m][s] - v[m][2]);
             if (dv > mx) mx = dv;
         }
-        for (int s = 0; s < 5; ++s) out[m * 5 + s] = (v[m][s] - v[m][2]) / (mx + 1e-30);
+        for (int s = 0; s < 5; ++s) out[m * 5 + s] = (v[m][s] - v[m][2]) / (mx + 1e-8 * sc[m]);
+    }
+    return 0;
+}
+
+/* Significance: 1 when rho, some velocity component or p varies over the five cells of the
+ * side by more than 1e-8 of its natural scale, else 0.  Every split-flux component of an
+ * insignificant side is constant to O(1e-8) of its scale, so its sub-stencil choice moves
+ * the face value by no more than that. */
+int ora_face_significant(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side)
+{
+    if (dir < 0 || dir >= c->d.dim || side < 0 || side > 1) return -1;
+    long idx[3] = {i, j, k}, cells[5][3];
+    side_cells(dir, idx, side, cells);
+    double sc[3];
+    natural_scales(c, &sc[0], &sc[1], &sc[2]);
+    const int nv = c->d.dim + 2;   /* rho, velocity components, p */
+    double lo[5], hi[5];
+    for (int s = 0; s < 5; ++s) {
+        double q[5], u[3], p, v[5];
+        fetch(c, Q, cells[s][0], cells[s][1], cells[s][2], q);
+        primitives(c, q, u, &p);
+        v[0] = q[0];
+        for (int a = 0; a < c->d.dim; ++a) v[1 + a] = u[a];
+        v[nv - 1] = p;
+        for (int m = 0; m < nv; ++m) {
+            lo[m] = s == 0 || v[m] < lo[m] ? v[m] : lo[m];
+            hi[m] = s == 0 || v[m] > hi[m] ? v[m] : hi[m];
+        }
+    }
+    for (int m = 0; m < nv; ++m) {
+        const double scale = m == 0 ? sc[0] : (m == nv - 1 ? sc[2] : sc[1]);
+        if (hi[m] - lo[m] > 1e-8 * scale) return 1;
     }
     return 0;
 }

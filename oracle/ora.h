@@ -91,6 +91,7 @@ int ora_set_state(ora_ctx* c, const double* xi, double t, int64_t step);
  * between cell idx and idx + e_dir, side 1 = f- stencil i+3..i-1); see ora.c. */
 int ora_face_features(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side, double* out);
 int ora_face_label(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side, double alpha);
+int ora_face_significant(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side);
 
 /* Scalar building blocks exposed for the pins. */
 double ora_delta4(double r);

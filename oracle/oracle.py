@@ -81,6 +81,8 @@ def lib():
         _lib.ora_face_features.restype = C.c_int
         _lib.ora_face_label.argtypes = [vp, dp, C.c_int, C.c_long, C.c_long, C.c_long, C.c_int, d]
         _lib.ora_face_label.restype = C.c_int
+        _lib.ora_face_significant.argtypes = [vp, dp, C.c_int, C.c_long, C.c_long, C.c_long, C.c_int]
+        _lib.ora_face_significant.restype = C.c_int
         _lib.ora_splitmix64.restype = C.c_uint64
         _lib.ora_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         for name in ("ora_set_markers", "ora_set_probes", "ora_alpha", "ora_rhs", "ora_rhs_cells",
@@ -256,6 +258,17 @@ class Oracle:
         if r < 0:
             raise ValueError("face_label failed")
         return r
+
+    def face_significant(self, Q, d, idx, side):
+        """True when some primitive variable of the side's five cells varies by more than
+        1e-8 of its natural scale."""
+        Q = self._state(Q)
+        i, j = idx[0], idx[1]
+        k = idx[2] if len(idx) > 2 else 0
+        r = lib().ora_face_significant(self.ctx, _ptr(Q), d, i, j, k, side)
+        if r < 0:
+            raise ValueError("face_significant failed")
+        return bool(r)
 
     def marker_force(self):
         out = np.empty((self.dim, self.nm))

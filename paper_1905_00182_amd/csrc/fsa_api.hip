@@ -17,13 +17,6 @@
 
 using namespace fsa;
 
-namespace {
-__global__ void k_clear_slots(unsigned long long* bits, int n)
-{
-    if ((int)threadIdx.x < n) bits[threadIdx.x] = 0ull;
-}
-}  // namespace
-
 struct fsa_ctx {
     fsa_desc d;
     Grid G;
@@ -37,6 +30,8 @@ struct fsa_ctx {
     double* Qa = nullptr;                // RK stage buffers
     double* Qb = nullptr;
     unsigned long long* abits = nullptr; // alpha slots: [4][3]
+    unsigned long long* apart = nullptr; // per-block / per-wave partial maxima [apart_n][3]
+    long long apart_n = 0;
     unsigned long long* h_abits = nullptr;  // pinned mirror of the last step's slots
     hipEvent_t ev_alpha = nullptr;
     bool alpha_pending = false;
@@ -219,6 +214,10 @@ void far_field_fluxes(const fsa_ctx* c, KConst& k)
         for (int a = 0; a < dim; ++a) F[d][1 + a] = q[1 + a] * ud + (a == d ? p : 0.0);
         F[d][dim + 1] = (q[dim + 1] + p) * ud;
     }
+    const double cinf = std::sqrt(c->d.gamma * p / rho);
+    k.sig[0] = 1e-8 * rho;
+    k.sig[1] = 1e-8 * cinf;
+    k.sig[2] = 1e-8 * rho * cinf * cinf;
 }
 
 // Rows per wave segment of the 2D stage kernel.  The best value depends on how the waves
@@ -353,15 +352,15 @@ bool ib_active(const fsa_ctx* c) { return (c->d.terms & FSA_TERM_IB) && c->nm > 
 
 // One right-hand-side evaluation on Qs: (optionally) the wave-speed reduction of Qs into
 // slot `in`, the penalty step, and the fused stencil/update kernel, which reads slot `in`,
-// accumulates the wave speeds of its output into slot `acc` and clears slot `clr` (slots of
-// three doubles in abits; -1 = none).
-int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, int in, int acc, int clr,
-                  bool reduce, int stage, double ca, double cb, double dt, int mode_rhs)
+// writes the wave speeds of its output into slot `acc` (per-wave partials, then a one-block
+// reduction; slots of three doubles in abits; -1 = none).
+int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, int in, int acc, bool reduce,
+                  int stage, double ca, double cb, double dt, int mode_rhs)
 {
     unsigned long long* bits = c->abits + 3 * in;
     int e;
     if (reduce) {
-        e = launch_alpha(c->G, c->P, Qs, bits, c->stream);
+        e = launch_alpha(c->G, c->P, Qs, c->apart, bits, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "alpha reduction launch");
     }
     if (ib_active(c)) {
@@ -387,8 +386,7 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     S.flags_x = c->flags_x;
     S.flags_y = c->flags_y;
     S.alpha_bits = bits;
-    S.alpha_out = acc >= 0 ? c->abits + 3 * acc : nullptr;
-    S.alpha_zero = clr >= 0 ? c->abits + 3 * clr : nullptr;
+    S.alpha_part = acc >= 0 ? c->apart : nullptr;
     S.fwin = ib_active(c) ? c->fwin : nullptr;
     for (int k = 0; k < 3; ++k) {
         S.wlo[k] = c->wlo[k];
@@ -421,6 +419,10 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     e = launch_stage2d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch");
     if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
+    if (acc >= 0) {
+        e = launch_alpha_final(c->apart, stage2d_waves(c->G, S.ty), c->abits + 3 * acc, c->stream);
+        if (e) return hipcheck(c, (hipError_t)e, "wave-speed reduction launch");
+    }
     return FSA_OK;
 }
 
@@ -434,8 +436,7 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
     S.mode_rhs = 1;
     S.out = c->Qb;
     S.Qn = nullptr;
-    S.alpha_out = nullptr;
-    S.alpha_zero = nullptr;
+    S.alpha_part = nullptr;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -481,9 +482,9 @@ int mlp_alloc(fsa_ctx* c)
         (rc = dalloc(c, c->mlp_m, MLP_NPARAM)) != FSA_OK || (rc = dalloc(c, c->mlp_v, MLP_NPARAM)) != FSA_OK ||
         (rc = dalloc(c, c->mlp_grad, MLP_NPARAM)) != FSA_OK ||
         (rc = dalloc(c, c->mlp_partial, (size_t)512 * MLP_NPARAM)) != FSA_OK ||
-        (rc = dalloc(c, c->mlp_loss_part, 512)) != FSA_OK || (rc = dalloc(c, c->counters, 2)) != FSA_OK)
+        (rc = dalloc(c, c->mlp_loss_part, 512)) != FSA_OK || (rc = dalloc(c, c->counters, 3 * (size_t)flags2d_blocks(c->G))) != FSA_OK)
         return rc;
-    HIPCHK(c, hipMemset(c->counters, 0, 2 * sizeof(unsigned long long)));
+    HIPCHK(c, hipMemset(c->counters, 0, 3 * (size_t)flags2d_blocks(c->G) * sizeof(unsigned long long)));
     return FSA_OK;
 }
 
@@ -496,7 +497,8 @@ int enqueue_flags(fsa_ctx* c, const double* Qs, const unsigned long long* bits, 
     F.step = c->step;
     F.alpha_bits = bits;
     F.M = mlp_args(c);
-    F.conf_threshold = (float)c->conf_threshold;
+    // min_k |2 sigma(z_k) - 1| >= c  <=>  min_k |z_k| >= 2 atanh(c) = ln((1 + c) / (1 - c))
+    F.zthr = c->conf_threshold >= 1.0 ? INFINITY : (float)std::log((1.0 + c->conf_threshold) / (1.0 - c->conf_threshold));
     F.flags_x = fx;
     F.flags_y = fy;
     F.counters = c->counters;
@@ -568,7 +570,9 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
     c->ty = env_ty();
     if ((rc = dalloc(c, c->Qa, (size_t)c->nq * c->ncell)) != FSA_OK ||
         (rc = dalloc(c, c->Qb, (size_t)c->nq * c->ncell)) != FSA_OK ||
-        (rc = dalloc(c, c->abits, 12)) != FSA_OK || (rc = dalloc(c, c->dK, 1)) != FSA_OK) {
+        (rc = dalloc(c, c->abits, 12)) != FSA_OK || (rc = dalloc(c, c->dK, 1)) != FSA_OK ||
+        (rc = dalloc(c, c->apart, 3 * (size_t)(c->apart_n = std::max<long long>(ALPHA_MAX_BLOCKS,
+                                                                                stage2d_waves(c->G, 4))))) != FSA_OK) {
         fsa_destroy(c);
         return rc;
     }
@@ -618,6 +622,7 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->Qb);
     dfree(c->dK);
     dfree(c->abits);
+    dfree(c->apart);
     dfree(c->X);
     dfree(c->dV);
     dfree(c->U);
@@ -714,7 +719,7 @@ int32_t fsa_alpha(fsa_ctx* c, const double* d_Q, double* alpha)
 {
     if (!c || !d_Q || !alpha) return FSA_EINVAL;
     unsigned long long* bits = c->abits + 9;
-    int e = launch_alpha(c->G, c->P, d_Q, bits, c->stream);
+    int e = launch_alpha(c->G, c->P, d_Q, c->apart, bits, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "alpha launch");
     unsigned long long hb[3];
     HIPCHK(c, hipMemcpyAsync(hb, bits, sizeof hb, hipMemcpyDeviceToHost, c->stream));
@@ -730,7 +735,7 @@ int32_t fsa_rhs(fsa_ctx* c, const double* d_Q, double* d_L)
 {
     if (!c || !d_Q || !d_L) return FSA_EINVAL;
     if ((const void*)d_Q == (const void*)d_L) return fail(c, FSA_EINVAL, "d_L aliases d_Q");
-    return enqueue_stage(c, d_Q, nullptr, d_L, 0, -1, -1, true, 0, 0.0, 1.0, 0.0, 1);
+    return enqueue_stage(c, d_Q, nullptr, d_L, 0, -1, true, 0, 0.0, 1.0, 0.0, 1);
 }
 
 int32_t fsa_rk3_steps(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps)
@@ -743,14 +748,13 @@ int32_t fsa_rk3_steps(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps)
     static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
     static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
     // the wave speeds of every stage input come from the kernel that wrote it, except for
-    // the first stage of the call, which reduces d_Q (slot 0) after clearing slots 0 and 1
-    hipLaunchKernelGGL(k_clear_slots, dim3(1), dim3(64), 0, c->stream, c->abits, 6);
+    // the first stage of the call, which reduces d_Q into slot 0
     for (int n = 0; n < nsteps; ++n) {
         for (int s = 0; s < 3; ++s) {
             const int g = 3 * n + s;
             const double* Qs = s == 0 ? d_Q : (s == 1 ? c->Qa : c->Qb);
             double* out = s == 0 ? c->Qa : (s == 1 ? c->Qb : d_Q);
-            if ((rc = enqueue_stage(c, Qs, d_Q, out, g % 3, (g + 1) % 3, (g + 2) % 3, g == 0, s + 1, CA[s], CB[s],
+            if ((rc = enqueue_stage(c, Qs, d_Q, out, g % 3, (g + 1) % 3, g == 0, s + 1, CA[s], CB[s],
                                     dt, 0)) != FSA_OK)
                 return rc;
         }
@@ -900,7 +904,7 @@ int32_t fsa_harvest(fsa_ctx* c, const double* d_Q, double keep_rate, uint64_t se
             return rc;
     }
     unsigned long long* bits = c->abits + 9;
-    int e = launch_alpha(c->G, c->P, d_Q, bits, c->stream);
+    int e = launch_alpha(c->G, c->P, d_Q, c->apart, bits, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "alpha launch");
     HarvestArgs H;
     std::memset(&H, 0, sizeof H);
@@ -930,7 +934,7 @@ int32_t fsa_face_flags(fsa_ctx* c, const double* d_Q, uint32_t* d_flags_x, uint3
     if (c->d.dim != 2) return fail(c, FSA_EUNSUPPORTED, "learned flags are built for 2D");
     if (!c->mlp_ready) return fail(c, FSA_ESTATE, "no network set");
     unsigned long long* bits = c->abits + 9;
-    int e = launch_alpha(c->G, c->P, d_Q, bits, c->stream);
+    int e = launch_alpha(c->G, c->P, d_Q, c->apart, bits, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "alpha launch");
     return enqueue_flags(c, d_Q, bits, d_flags_x, d_flags_y);
 }
@@ -984,10 +988,15 @@ int32_t fsa_stats_get(fsa_ctx* c, fsa_stats* out)
     out->window_cells = (int32_t)c->wcells;
     out->rows_per_wave = c->ty;
     if (c->counters) {
-        unsigned long long hc[2];
-        HIPCHK(c, hipMemcpy(hc, c->counters, sizeof hc, hipMemcpyDeviceToHost));
-        out->learned_sides = (int64_t)hc[0];
-        out->fallback_sides = (int64_t)hc[1];
+        const long long nb = flags2d_blocks(c->G);
+        std::vector<unsigned long long> hc((size_t)(3 * nb));
+        HIPCHK(c, hipMemcpy(hc.data(), c->counters, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        unsigned long long tot[3] = {0ull, 0ull, 0ull};
+        for (long long b = 0; b < nb; ++b)
+            for (int k = 0; k < 3; ++k) tot[k] += hc[(size_t)(3 * b + k)];
+        out->learned_sides = (int64_t)tot[0];
+        out->fallback_sides = (int64_t)tot[1];
+        out->significant_sides = (int64_t)tot[2];
     }
     return FSA_OK;
 }

@@ -274,6 +274,9 @@ struct KConst {
     Phys P;
     double inv12h;
     double Fx_inf[5], Fy_inf[5], Fz_inf[5];   // physical fluxes of the far-field state
+    double sig[3];      // 1e-8 times the natural scales of rho, velocity and p (rho_inf, c_inf,
+                        // rho_inf c_inf^2): significance threshold and feature floor of the
+                        // learned selector
 
     __device__ __forceinline__ double eta_dir(int d, int i) const
     {

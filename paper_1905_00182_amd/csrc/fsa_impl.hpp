@@ -17,8 +17,8 @@ struct StageArgs {
     double ca, cb, dt;
     int mode_rhs;
     int ty;                                // rows (2D) per wave segment
-    unsigned long long* alpha_out;         // if set: NaN-propagating max of |u_d| + c of the output
-    unsigned long long* alpha_zero;        // if set: slot cleared by the first lane of the grid
+    unsigned long long* alpha_part;        // if set: per wave, NaN-propagating max of |u_d| + c of
+                                           // the output, [wave][3] (reduced by launch_alpha_final)
     long long step;                        // step counter (inflow-noise counter)
     const unsigned* flags_x;               // learned form: keep patterns of the x faces
     const unsigned* flags_y;               // and of the y faces
@@ -49,8 +49,15 @@ struct IBArgs {
 };
 
 int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, hipStream_t s);
+long long stage2d_waves(const Grid& G, int ty);
 int stage2d_ncolx(int nx);
-int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* bits, hipStream_t s);
+// Wave speeds max over cells of |u_d| + c of Q into bits[3]: per-block partials in part
+// (ALPHA_MAX_BLOCKS x 3), then launch_alpha_final.  No same-address atomics.
+constexpr int ALPHA_MAX_BLOCKS = 2048;
+int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* part, unsigned long long* bits,
+                 hipStream_t s);
+// bits[d] = NaN-propagating max over n partials part[k * 3 + d] (d < 3).
+int launch_alpha_final(const unsigned long long* part, long long n, unsigned long long* bits, hipStream_t s);
 int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s);
 int launch_ib_weights(const Grid& G, const IBArgs& A, int* mj0, double* mw, double* cell_w, hipStream_t s);
 int launch_interp(const Grid& G, int npts, const double* X, const double* field, int ncomp, double* out,

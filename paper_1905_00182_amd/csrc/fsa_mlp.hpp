@@ -28,10 +28,12 @@ struct FlagArgs {
     long long step;
     const unsigned long long* alpha_bits;  // global LF speeds of Q
     MLPArgs M;
-    float conf_threshold;
+    float zthr;                            // confidence min_k |2 sigma(z_k) - 1| >= c  <=>
+                                           // min_k |z_k| >= ln((1 + c) / (1 - c))
     unsigned* flags_x;                     // [(nx+1) ny]: side 0 pattern | side 1 pattern << 16
     unsigned* flags_y;                     // [nx (ny+1)]
-    unsigned long long* counters;          // [0] face sides, [1] fallback sides (accumulated)
+    unsigned long long* counters;          // accumulated per block [flags2d_blocks][3]: face sides,
+                                           // fallback sides, significant sides
 };
 
 struct HarvestArgs {
@@ -48,6 +50,7 @@ struct HarvestArgs {
     long long* total;                      // selected sides (may exceed max_out)
 };
 
+long long flags2d_blocks(const Grid& G);
 int launch_flags2d(const KConst* K, const Grid& G, const FlagArgs& A, hipStream_t s);
 long long harvest2d_blocks(const Grid& G);
 int launch_harvest2d(const KConst* K, const Grid& G, const HarvestArgs& H, hipStream_t s);

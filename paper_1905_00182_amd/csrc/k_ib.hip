@@ -29,9 +29,10 @@ __device__ __forceinline__ unsigned long long wave_max_bits(unsigned long long v
 // alpha_d = max over cells of |u_d| + c, NaN-propagating (bits of non-negative doubles).
 template <int DIM>
 __global__ __launch_bounds__(RED_THREADS) void k_alpha(Grid G, Phys P, const double* __restrict__ Q,
-                                                       unsigned long long* __restrict__ bits)
+                                                       unsigned long long* __restrict__ part)
 {
-    __shared__ unsigned long long part[RED_THREADS / 64][DIM];
+    unsigned long long* __restrict__ out = part;
+    __shared__ unsigned long long wpart[RED_THREADS / 64][DIM];
     unsigned long long m[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) m[d] = 0ull;
@@ -56,19 +57,39 @@ __global__ __launch_bounds__(RED_THREADS) void k_alpha(Grid G, Phys P, const dou
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         const unsigned long long w = wave_max_bits(m[d]);
-        if (lane == 0) part[wid][d] = w;
+        if (lane == 0) wpart[wid][d] = w;
     }
     __syncthreads();
-    if (threadIdx.x < DIM) {
+    if (threadIdx.x < 3) {
         unsigned long long v = 0ull;
-        for (int w = 0; w < RED_THREADS / 64; ++w) v = max_bits(v, part[w][threadIdx.x]);
-        atomicMax(&bits[threadIdx.x], v);
+        if (threadIdx.x < DIM)
+            for (int w = 0; w < RED_THREADS / 64; ++w) v = max_bits(v, wpart[w][threadIdx.x]);
+        out[(long long)blockIdx.x * 3 + threadIdx.x] = v;
     }
 }
 
-__global__ void k_zero_bits(unsigned long long* bits, int n)
+// One block: bits[d] = max over the n partials (fixed order is irrelevant for a maximum).
+__global__ __launch_bounds__(256) void k_alpha_final(const unsigned long long* __restrict__ part, long long n,
+                                                     unsigned long long* __restrict__ bits)
 {
-    if (threadIdx.x < n) bits[threadIdx.x] = 0ull;
+    __shared__ unsigned long long red[4][3];
+    unsigned long long m[3] = {0ull, 0ull, 0ull};
+    for (long long k = threadIdx.x; k < n; k += blockDim.x) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) m[d] = max_bits(m[d], part[k * 3 + d]);
+    }
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const unsigned long long w = wave_max_bits(m[d]);
+        if (lane == 0) red[wid][d] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long v = 0ull;
+        for (int w = 0; w < 4; ++w) v = max_bits(v, red[w][threadIdx.x]);
+        bits[threadIdx.x] = v;
+    }
 }
 
 // Marker support: first cell and four weights per direction.
@@ -289,14 +310,20 @@ __global__ void k_probe_dp(Grid G, Phys P, int np, const double* __restrict__ Xp
 
 }  // namespace
 
-int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* bits, hipStream_t s)
+int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* part, unsigned long long* bits,
+                 hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_bits, dim3(1), dim3(64), 0, s, bits, 3);
     long long blocks = (G.ncell + RED_THREADS - 1) / RED_THREADS;
-    if (blocks > 2048) blocks = 2048;
+    if (blocks > ALPHA_MAX_BLOCKS) blocks = ALPHA_MAX_BLOCKS;
     if (blocks < 1) blocks = 1;
-    if (G.dim == 3) hipLaunchKernelGGL(k_alpha<3>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, bits);
-    else hipLaunchKernelGGL(k_alpha<2>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, bits);
+    if (G.dim == 3) hipLaunchKernelGGL(k_alpha<3>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, part);
+    else hipLaunchKernelGGL(k_alpha<2>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, part);
+    return launch_alpha_final(part, blocks, bits, s);
+}
+
+int launch_alpha_final(const unsigned long long* part, long long n, unsigned long long* bits, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_alpha_final, dim3(1), dim3(256), 0, s, part, n, bits);
     return (int)hipGetLastError();
 }
 

@@ -130,6 +130,7 @@ struct Column2D {
     T txx[5], txy[5], tyy[5], bx[5], by[5];
     T fy_prev[4], cy_queue[4];
     double qf[4];                   // prefetched state of the next front row
+    unsigned wy_pf, wx_pf;          // learned form: prefetched keep patterns of the next step
     double (*ring)[4][WAVE];        // LDS: the last five front rows of this wave, [slot][comp][lane]
     int lane;
 
@@ -163,6 +164,19 @@ struct Column2D {
         }
     }
 
+    // Learned form: keep patterns of the y face (R-3)+1/2 and the x face right of this lane
+    // in output row R-4, the faces step R reconstructs (rows clamped into range; the loads
+    // of steps that do not use them are harmless).
+    __device__ __forceinline__ void load_patterns(int R)
+    {
+        if constexpr (SCHEME == LEARNED) {
+            const int ny = K->G.n[1];
+            const int jy = min(max(R - 2, 0), ny), jx = min(max(R - 4, 0), ny - 1);
+            wy_pf = flags_y[(long long)jy * nx + xr];
+            wx_pf = flags_x[(long long)jx * (nx + 1) + min(max(i + 1, 0), nx)];
+        }
+    }
+
     template <int K5>
     __device__ __forceinline__ void step_row(int Rw)
     {
@@ -187,6 +201,8 @@ struct Column2D {
 #pragma unroll
         for (int c = 0; c < 4; ++c) ring[S0][c][lane] = q[c];
         load_row(Rw + 1, qf);
+        const unsigned word_y = wy_pf, word_x = wx_pf;
+        load_patterns(Rw + 1);
         const double inv_rho = rcp_nr(q[0]);
         const double u = q[1] * inv_rho, v = q[2] * inv_rho;
         const double p = gm1 * (q[3] - 0.5 * fma(q[1], u, q[2] * v));
@@ -207,8 +223,7 @@ struct Column2D {
         // ---- y face (Rw-3)+1/2: f+ rows Rw-5..Rw-1, f- rows Rw..Rw-4
         T cy_new[4] = {T(0), T(0), T(0), T(0)};
         if ((terms & T_CONVY) && Rw >= j0 + 2 && Rw <= j1 + 3) {
-            unsigned word = 0;
-            if constexpr (SCHEME == LEARNED) word = flags_y[(long long)(Rw - 2) * nx + xr];
+            const unsigned word = word_y;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int bp = (int)(word >> (3 * c)) & 7, bm = (int)(word >> (16 + 3 * c)) & 7;
@@ -256,8 +271,7 @@ struct Column2D {
             if (terms & T_CONVX) {
                 const double pr = gm1 * (qr[3] - 0.5 * fma(qr[1], ur, qr[2] * vr));
                 const double F[4] = {qr[1], fma(qr[1], ur, pr), qr[2] * ur, (qr[3] + pr) * ur};
-                unsigned word = 0;
-                if constexpr (SCHEME == LEARNED) word = flags_x[(long long)r * (nx + 1) + min(max(i + 1, 0), nx)];
+                const unsigned word = word_x;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     T fpx, fmx;
@@ -395,11 +409,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         C.uw[s] = C.vw[s] = T(0);
         C.txx[s] = C.txy[s] = C.tyy[s] = C.bx[s] = C.by[s] = T(0);
     }
-    C.want_alpha = A.alpha_out != nullptr;
+    C.want_alpha = A.alpha_part != nullptr;
     C.amax_x = C.amax_y = 0ull;
-    if (A.alpha_zero && blockIdx.x == 0 && blockIdx.y == 0 && lane < 3) A.alpha_zero[lane] = 0ull;
     const int Rend = C.j1 + HALO;
     C.load_row(C.j0 - HALO, C.qf);
+    C.wy_pf = C.wx_pf = 0u;
+    C.load_patterns(C.j0 - HALO);
     for (int Rw = C.j0 - HALO; Rw <= Rend; Rw += 5) {
         C.template step_row<0>(Rw);
         if (Rw + 1 > Rend) break;
@@ -418,9 +433,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             mx = max_bits(mx, __shfl_xor(mx, off, WAVE));
             my = max_bits(my, __shfl_xor(my, off, WAVE));
         }
-        if (lane == 0) {
-            atomicMax(&A.alpha_out[0], mx);
-            atomicMax(&A.alpha_out[1], my);
+        if (lane < 3) {
+            // one partial per wave (plain stores; launch_alpha_final reduces them)
+            const long long wv = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+            A.alpha_part[wv * 3 + lane] = lane == 0 ? mx : (lane == 1 ? my : 0ull);
         }
     }
 }
@@ -445,5 +461,10 @@ int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, co
 }
 
 int stage2d_ncolx(int nx) { return (nx + OUTW - 1) / OUTW; }
+
+long long stage2d_waves(const Grid& G, int ty)
+{
+    return (long long)((G.n[0] + OUTW - 1) / OUTW) * ((G.n[1] + ty - 1) / ty);
+}
 
 }  // namespace fsa

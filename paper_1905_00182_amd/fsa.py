@@ -66,6 +66,7 @@ class FsaStats(C.Structure):
         ("rows_per_wave", C.c_int32),
         ("learned_sides", C.c_int64),
         ("fallback_sides", C.c_int64),
+        ("significant_sides", C.c_int64),
     ]
 
 

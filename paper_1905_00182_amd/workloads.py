@@ -263,6 +263,14 @@ def config2(n=2048, h=1.0 / 16.0, sponge=10.0, steps=2000, nprobe=360, rprobe=50
 
 
 def config2_state(case):
+    """Initial condition of the rotating-cylinder case: the uniform far-field stream (the
+    seeded perturbation enters with the inflow)."""
+    return uniform_state(case)
+
+
+def config2_noisy_state(case):
+    """The rotating-cylinder case with the inflow perturbation already in every cell: a
+    stress input for parity tests (every face sees non-trivial TENO5 decisions)."""
     return free_stream_with_noise(case, case.inflow_amp, case.seed)
 
 

@@ -92,7 +92,7 @@ def _c2_small(n=200, nprobe=24):
 
 def test_rhs_config2_small_boundaries(torch_cuda):
     case = _c2_small()
-    Q0 = W.config2_state(case)
+    Q0 = W.config2_noisy_state(case)
     # a step so the rhs carries cut-off faces, plus the inflow noise and rotating markers
     Q0[0, 60:80, 90:120] *= 1.05
     _compare_rhs(torch_cuda, case, Q0)
@@ -181,7 +181,7 @@ def test_rk3_config1_full(torch_cuda):
 
 def test_rk3_config2_small(torch_cuda):
     case = _c2_small(n=256)
-    Q0 = W.config2_state(case)
+    Q0 = W.config2_noisy_state(case)
     s, o, Qg, Qo = _steps_both(torch_cuda, case, Q0, 20)
     _assert_q_close(Qg, Qo, Q0, case)
     np.testing.assert_allclose(s.marker_force(), o.marker_force(), rtol=1e-9, atol=1e-12)
@@ -198,7 +198,7 @@ def test_alpha_matches(torch_cuda):
 
 def test_deterministic_and_restartable(torch_cuda):
     case = _c2_small(n=128, nprobe=0)
-    Q0 = W.config2_state(case)
+    Q0 = W.config2_noisy_state(case)
     runs = []
     for _ in range(2):
         s = _solver(case)
@@ -228,7 +228,7 @@ def test_nonfinite_detected(torch_cuda):
 
     case = _c2_small(n=64, nprobe=0)
     s = _solver(case, nan_check=True)
-    Q = torch_cuda.from_numpy(W.config2_state(case)).cuda()
+    Q = torch_cuda.from_numpy(W.config2_noisy_state(case)).cuda()
     s.rk3_step(Q, case.dt)
     s.sync()
     Q[0, 10, 10] = float("nan")
@@ -253,7 +253,7 @@ def test_config2_full_size(torch_cuda, nsteps):
     """The 2048^2 TENO5 rotating-cylinder case at full size, in the launch configuration the
     benchmark times: a few RK3 steps against the oracle."""
     case = W.config2()
-    Q0 = W.config2_state(case)
+    Q0 = W.config2_noisy_state(case)
     s, o, Qg, Qo = _steps_both(torch_cuda, case, Q0, nsteps)
     _assert_q_close(Qg, Qo, Q0, case)
     # deviation from the initial state near the cylinder, where the IB acts
@@ -266,7 +266,7 @@ def test_segmentation_does_not_change_results(torch_cuda, monkeypatch):
     """The rows-per-wave segmentation is a launch parameter only: every face is computed
     from the same inputs whatever segment computes it, so results are bitwise equal."""
     case = _c2_small(n=150, nprobe=0)
-    Q0 = W.config2_state(case)
+    Q0 = W.config2_noisy_state(case)
     Q0[0, 40:70, 30:90] *= 1.03
     outs = []
     for ty in ("5", "13", "64", None):

@@ -43,7 +43,7 @@ def test_mixed32_rhs(torch_cuda, scheme):
     from paper_1905_00182_amd import fsa
 
     case = W.config2(n=200, h=1.0 / 16.0, sponge=2.0, nprobe=0).with_(scheme=scheme)
-    Q0 = W.config2_state(case)
+    Q0 = W.config2_noisy_state(case)
     Q0[0, 60:80, 90:120] *= 1.02
     _say("mixed32 rhs", scheme, case.n)
     s = fsa.Solver(case.with_(precision="mixed32"))
@@ -88,7 +88,8 @@ def test_mixed32_acoustic_error_config1(torch_cuda):
 
 
 def test_mixed32_acoustic_error_config2_small(torch_cuda):
-    case = W.config2(n=256, h=1.0 / 16.0, sponge=2.0, nprobe=48, rprobe=5.0)
-    ep, qrel, amp = _probe_run(torch_cuda, case, 40)
-    _say(f"C2 (256^2) mixed32, 40 steps: e_p = {ep:.3e} (probe |dp| up to {amp:.2e}), state rel L2 {qrel:.2e}")
+    # uniform start: the cylinder's start-up wave reaches the radius-3 probes after ~90 steps
+    case = W.config2(n=256, h=1.0 / 16.0, sponge=2.0, nprobe=48, rprobe=3.0)
+    ep, qrel, amp = _probe_run(torch_cuda, case, 150)
+    _say(f"C2 (256^2) mixed32, 150 steps: e_p = {ep:.3e} (probe |dp| up to {amp:.2e}), state rel L2 {qrel:.2e}")
     assert ep < 1e-2

@@ -82,20 +82,53 @@ def _row_case(n=24):
 def test_features_of_linear_and_constant_stencils(oracle_mod):
     case = _row_case()
     xs = W.centres(case)
+    h = case.h
     rho = 1.0 + 0.01 * xs[0]
     Q = W.conserved(case, rho, [0.1 + 0 * rho, 0 * rho], np.full(case.shape, 0.7))
     o = oracle_mod.Oracle(case)
+    # deviations 0.01 h (k - 2) over the largest one 0.02 h plus the floor 1e-8 rho_inf
+    r = 0.02 * h / (0.02 * h + 1e-8)
     f0 = o.face_features(Q, 0, (10, 5), 0)
-    np.testing.assert_allclose(f0[:5], [-1, -0.5, 0, 0.5, 1], atol=1e-12)
+    np.testing.assert_allclose(f0[:5], [-r, -r / 2, 0, r / 2, r], rtol=1e-9, atol=0)
+    assert 0.99998 < r < 0.99999
     np.testing.assert_allclose(f0[5:], 0.0, atol=0)          # u and p constant
     f1 = o.face_features(Q, 0, (10, 5), 1)                     # mirrored: cells 13..9
-    np.testing.assert_allclose(f1[:5], [1, 0.5, 0, -0.5, -1], atol=1e-12)
-    # normal velocity is negated on the mirrored side
+    np.testing.assert_allclose(f1[:5], [r, r / 2, 0, -r / 2, -r], rtol=1e-9, atol=0)
+    # normal velocity is negated on the mirrored side (c_inf = 1 here)
     Q2 = W.conserved(case, 1.0 + 0 * rho, [0.1 + 0.01 * xs[0], 0 * rho], np.full(case.shape, 0.7))
     g0 = o.face_features(Q2, 0, (10, 5), 0)
     g1 = o.face_features(Q2, 0, (10, 5), 1)
-    np.testing.assert_allclose(g0[5:10], [-1, -0.5, 0, 0.5, 1], atol=1e-12)
-    np.testing.assert_allclose(g1[5:10], [-1, -0.5, 0, 0.5, 1], atol=1e-12)
+    np.testing.assert_allclose(g0[5:10], [-r, -r / 2, 0, r / 2, r], rtol=1e-9)
+    np.testing.assert_allclose(g1[5:10], [-r, -r / 2, 0, r / 2, r], rtol=1e-9)
+
+
+def test_features_of_rounding_level_variation_vanish(oracle_mod):
+    # p varying by 1e-15 (rounding level): the floor 1e-8 rho c^2 = 1e-8 maps it to ~1e-7
+    case = _row_case()
+    xs = W.centres(case)
+    p = 0.7 + 1e-15 * np.sign(np.sin(7.0 * xs[0]))
+    Q = W.conserved(case, np.ones(case.shape), [0 * p + 0.1, 0 * p], p)
+    f = oracle_mod.Oracle(case).face_features(Q, 0, (10, 5), 0)
+    assert np.abs(f[10:]).max() < 1e-6
+
+
+def test_significance(oracle_mod):
+    case = _row_case()
+    xs = W.centres(case)
+    o = oracle_mod.Oracle(case)
+    const = W.uniform_state(case)
+    assert not o.face_significant(const, 0, (10, 5), 0)
+    for var, amp, want in (("rho", 0.9e-8, False), ("rho", 1.1e-8, True), ("v", 1.1e-8, True),
+                           ("v", 0.9e-8, False), ("p", 1.1e-8, True)):
+        # a jump of amp (natural scales are 1 here) between cells 11 and 12
+        jump = amp * (np.arange(case.n[0])[None, :] >= 12)
+        rho = 1.0 + (jump if var == "rho" else 0)
+        v = 0.0 + (jump if var == "v" else 0)
+        p = 1.0 / 1.4 + (jump if var == "p" else 0)
+        Q = W.conserved(case, rho * np.ones(case.shape), [0.0 * rho + 0.1, v * np.ones(case.shape)],
+                        p * np.ones(case.shape))
+        assert o.face_significant(Q, 0, (10, 5), 0) == want, (var, amp)
+        assert not o.face_significant(Q, 0, (6, 5), 0)          # cells 4..8: no jump
 
 
 def test_labels_smooth_and_step(oracle_mod):
