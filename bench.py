@@ -4,8 +4,15 @@ A step is one pass of the whole hot path: for each of the three stages, the glob
 Lax-Friedrichs wave-speed reduction, the penalty immersed-boundary step (interpolation,
 feedback force, spreading) and the fused stencil/update kernel (flux splitting, TENO5
 reconstruction in x and y, fourth-order viscous terms, IB and sponge sources, RK3 update).
-Inputs are synthetic (seeded free stream with the inflow perturbation) and resident in HBM
-before the timed region.
+Inputs are synthetic (the uniform Mach 0.2 stream; the seeded perturbation enters with the
+inflow) and resident in HBM before the timed region.
+
+Variants (unless --no-variants): the whole 2000-step run of the same case in FP64, in the
+FP32 precision form and in the FP32 + learned-selector form (network trained first, in
+process, by the library's own kernels from short FP64 runs of smaller cases), each timed
+over the run with the acoustic pressure sampled at the 360 probes every 10 steps; each
+variant's probe signal is compared with the FP64 run's (the FP64 path matches the CPU
+oracle to 1e-12).
 
 Prints one JSON line.  Metric: cell-stage updates per second (cells x 3 stages x steps /
 wall time).  roofline: the fused stage kernel, whose launches are bracketed by HIP events on
@@ -81,6 +88,87 @@ def cpu_baseline(case, steps):
     }
 
 
+def full_run(case, Q0, nsteps, every, net=None):
+    """nsteps SSP-RK3 steps from Q0 with the probe pressure sampled every `every` steps;
+    returns wall seconds, probe samples [nsteps / every][probes] and the final stats.  The
+    solver is warmed up (tuning launch, page-in) on a copy first and reset to step 0."""
+    import numpy as np
+    import torch
+
+    from paper_1905_00182_amd import fsa
+
+    s = fsa.Solver(case)
+    if net is not None:
+        s.mlp_set(net, 0.8)
+    Qw = Q0.clone()
+    s.rk3_steps(Qw, case.dt, 2)
+    s.sync()
+    s.set_state(np.zeros((case.dim, s.nm)), 0.0, 0)
+    stats0 = s.stats()
+    Q = Q0.clone()
+    nsamp = nsteps // every
+    dps = torch.empty((nsamp, s.np), dtype=torch.float64, device=Q.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(nsamp):
+        s.rk3_steps(Q, case.dt, every)
+        s.probe_dp(Q, out=dps[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = s.stats()
+    s.close()
+    sides = st.learned_sides - stats0.learned_sides
+    return wall, dps, {
+        "significant": (st.significant_sides - stats0.significant_sides) / sides if sides else None,
+        "fallback": (st.fallback_sides - stats0.fallback_sides) / sides if sides else None,
+    }
+
+
+def variants(case, Q0, nsteps, every=10):
+    import torch
+
+    from paper_1905_00182_amd import selector
+    from paper_1905_00182_amd import workloads as W
+
+    t0 = time.perf_counter()
+    F, L = selector.harvest(selector.training_cases())
+    net, losses = selector.train(F, L)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    res = {}
+    cs = case.ncell * 3 * nsteps
+    # probes: the configured radius-50 ring, and a radius-10 ring the start-up wave has
+    # crossed within the run (the same computation; only the sampled points differ)
+    near = case.with_(probes=W.ring_probes(case.probes.shape[1], 10.0))
+    runs = {}
+    for name, prec, n in (("fp64", "fp64", None), ("mixed32", "mixed32", None), ("learned32", "learned32", net)):
+        w, dp, fr = full_run(case.with_(precision=prec), Q0, nsteps, every, n)
+        _, dpn, _ = full_run(near.with_(precision=prec), Q0, nsteps, every, n)
+        runs[name] = (w, dp, dpn, fr)
+    w64, dp64, dpn64, _ = runs["fp64"]
+    res["fp64"] = {"value": round(cs / w64 / 1e6, 3), "ms_per_step": round(w64 / nsteps * 1e3, 4)}
+    for name in ("mixed32", "learned32"):
+        w, dp, dpn, fr = runs[name]
+        e = {
+            "value": round(cs / w / 1e6, 3),
+            "ms_per_step": round(w / nsteps * 1e3, 4),
+            "speedup_vs_fp64": round(w64 / w, 3),
+            "acoustic_err_r50": float(torch.linalg.norm(dp - dp64) / torch.linalg.norm(dp64)),
+            "acoustic_err_r10": float(torch.linalg.norm(dpn - dpn64) / torch.linalg.norm(dpn64)),
+        }
+        if name == "learned32":
+            e["significant_side_frac"] = round(fr["significant"], 4)
+            e["fallback_side_frac"] = round(fr["fallback"], 4)
+            e["training"] = {"harvested_sides": int(F.shape[0]), "adam_steps": 4000,
+                             "final_loss": round(losses[-1], 4), "seconds": round(t_train, 1)}
+        res[name] = e
+    res["run"] = {"steps": nsteps, "probes": int(dp64.shape[1]), "probe_every": every,
+                  "max_probe_dp_r50": float(dp64.abs().max()), "max_probe_dp_r10": float(dpn64.abs().max()),
+                  "note": "whole run from the uniform start, probe launches included in the timing (the r50 "
+                          "run's); errors are relative L2 over probes x samples against the FP64 run"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,7 +176,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="skip the FP32 precision-form run")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the full-run comparison of the FP64, FP32 and FP32+learned forms")
+    ap.add_argument("--variant-steps", type=int, default=None, help="steps of the full runs (default: the case's)")
     ap.add_argument("--scheme", default="teno5", choices=["teno5", "weno5js"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
@@ -181,25 +271,7 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_variants:
-        w32, k32, l32, Q32, _ = run(case.with_(precision="mixed32"))
-        v32 = cell_stages / w32 / 1e6
-        g = case.gamma
-        def pressure(Q):
-            return (g - 1.0) * (Q[3] - 0.5 * (Q[1] * Q[1] + Q[2] * Q[2]) / Q[0])
-        p64, p32 = pressure(Q64), pressure(Q32)
-        dp64 = p64 - case.prim_inf[4]
-        out["variants"] = {
-            "mixed32": {
-                "value": round(v32, 3),
-                "ms_per_step": round(w32 / args.steps * 1e3, 4),
-                "speedup_vs_fp64": round(v32 / value, 3),
-                "kernel_ms_per_launch": round(k32 / max(l32, 1), 4),
-                "pressure_dev_rel_l2_vs_fp64_run": float(torch.linalg.norm(p32 - p64) / torch.linalg.norm(dp64)),
-                "state_rel_l2_vs_fp64_run": float(torch.linalg.norm(Q32 - Q64) / torch.linalg.norm(Q64)),
-                "note": "FP32 reconstruction/viscous on far-field deviations, FP64 state; compared with the "
-                        "FP64 run of the same steps (the FP64 path matches the CPU oracle to 1e-12)",
-            }
-        }
+        out["variants"] = variants(case, Q0, args.variant_steps or case.steps)
     if not args.no_cpu and args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
     print(json.dumps(out), flush=True)

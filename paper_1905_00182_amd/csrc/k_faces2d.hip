@@ -307,6 +307,16 @@ constexpr int FT_X = 64, FT_Y = 16;                // faces per tile: 64 along x
 constexpr int LT_X = FT_X + 6, LT_Y = FT_Y + 6;    // cells of the tile with its halo
 constexpr unsigned FALLBACK = 0xFFFFu;             // pattern marker: evaluate plain TENO5
 
+// Order LDS traffic between the lanes of one wave: its LDS operations execute in program
+// order, so it suffices that neither the compiler nor the wave moves a later access above an
+// earlier one (the LDS arrays used this way are private to the wave).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // FP32 features of one side from the six cells' deviations v[0..5] (rho, un, p rows of w):
 // upwind order k -> cell SD == 0 ? k : 5 - k, normal velocity negated on side 1.
 template <int SD>
@@ -345,22 +355,36 @@ __global__ __launch_bounds__(256) void k_flags2d(const KConst* __restrict__ K, F
     const int x0 = blockIdx.x * FT_X, y0 = blockIdx.y * FT_Y;
     const long long ncell = K->G.ncell;
 
-    // ---- the tile's cells (halo 3) as FP32 deviations from the far field
-    for (int c = tid; c < LT_X * LT_Y; c += 256) {
+    // ---- the tile's cells (halo 3) as FP32 deviations from the far field: every interior
+    // load of the thread is issued before any is used (one memory latency, not seven)
+    constexpr int NT = LT_X * LT_Y, PER = (NT + 255) / 256;
+    double q[PER][4];
+    bool ghost[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int c = tid + 256 * t;
         const int ly = c / LT_X, lx = c - ly * LT_X;
         const int i = min(max(x0 - 3 + lx, -3), nx + 2), j = min(max(y0 - 3 + ly, -3), ny + 2);
-        double q[4];
-        if (i >= 0 && i < nx && j >= 0 && j < ny) {
+        ghost[t] = !(i >= 0 && i < nx && j >= 0 && j < ny);
+        if (c < NT && !ghost[t]) {
             const double* src = A.Q + (long long)j * nx + i;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) q[m] = src[m * ncell];
-        } else {
-            fetch_state<2>(A.Q, K->G, K->P, A.step, i, j, 0, q);
+            for (int m = 0; m < 4; ++m) q[t][m] = src[m * ncell];
         }
-        const double ir = rcp_nr(q[0]);
-        const double u = q[1] * ir, v = q[2] * ir;
-        const double p = K->P.gm1 * (q[3] - 0.5 * fma(q[1], u, q[2] * v));
-        sv[0][ly][lx] = (float)(q[0] - K->P.prim_inf[0]);
+    }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int c = tid + 256 * t;
+        if (c >= NT) continue;
+        const int ly = c / LT_X, lx = c - ly * LT_X;
+        if (ghost[t]) {
+            const int i = min(max(x0 - 3 + lx, -3), nx + 2), j = min(max(y0 - 3 + ly, -3), ny + 2);
+            fetch_state<2>(A.Q, K->G, K->P, A.step, i, j, 0, q[t]);
+        }
+        const double ir = rcp_nr(q[t][0]);
+        const double u = q[t][1] * ir, v = q[t][2] * ir;
+        const double p = K->P.gm1 * (q[t][3] - 0.5 * fma(q[t][1], u, q[t][2] * v));
+        sv[0][ly][lx] = (float)(q[t][0] - K->P.prim_inf[0]);
         sv[1][ly][lx] = (float)(u - K->P.prim_inf[1]);
         sv[2][ly][lx] = (float)(v - K->P.prim_inf[2]);
         sv[3][ly][lx] = (float)(p - K->P.prim_inf[4]);
@@ -462,7 +486,7 @@ __global__ __launch_bounds__(256) void k_flags2d(const KConst* __restrict__ K, F
             sfeat[w][2 * lane + 1][0] = make_int4(p1[0], p1[1], p1[2], p1[3]);
             sfeat[w][2 * lane + 1][1] = make_int4(p1[4], p1[5], p1[6], p1[7]);
         }
-        __syncthreads();
+        wave_sync();
         if (need) {
             // tile t holds samples 16t..16t+15 = both sides of lanes 8t..8t+7
             for (int t = 0; t < 8; ++t) {
@@ -494,7 +518,7 @@ __global__ __launch_bounds__(256) void k_flags2d(const KConst* __restrict__ K, F
                 }
             }
         }
-        __syncthreads();
+        wave_sync();
         if (!valid) continue;
         unsigned pat0 = 0x0FFFu, pat1 = 0x0FFFu;
         if (sg0) pat0 = spat[w][2 * lane];

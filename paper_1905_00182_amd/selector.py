@@ -1,0 +1,78 @@
+"""Training of the learned TENO5 sub-stencil selector on the GPU.
+
+Every arithmetic step runs in the library's kernels (harvest, BF16 MFMA forward/backward,
+Adam); this module only orders the calls: it runs short FP64 trajectories, harvests their
+significant face sides with their FP64 TENO5 labels, shuffles them and takes Adam steps on
+mini-batches.
+"""
+import numpy as np
+
+from . import fsa
+from . import workloads as W
+
+NPARAM = fsa.MLP_NPARAM
+_SHAPES = [(15, 32), (32,), (32, 32), (32,), (32, 3), (3,)]
+
+
+def init_params(seed):
+    """He initialisation (weights ~ N(0, 2 / fan_in), biases 0), flat FP32 [1667]."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shp in _SHAPES:
+        if len(shp) == 2:
+            parts.append(rng.normal(0.0, np.sqrt(2.0 / shp[0]), size=shp).reshape(-1))
+        else:
+            parts.append(np.zeros(shp))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def training_cases(n1=128, n2=256):
+    """The scattering case with TENO5 and a miniature of the rotating-cylinder case (same
+    cell size, uniform start), each with its initial state and sampling interval."""
+    c1 = W.config1(n=n1, scheme="teno5")
+    c2 = W.config2(n=n2, h=1.0 / 16.0, sponge=2.0, nprobe=48, rprobe=3.0)
+    return [(c1, W.config1_state(c1), 20), (c2, W.config2_state(c2), 50)]
+
+
+def harvest(cases, chunks=6, keep_rate=1.0, seed=100, cap=1 << 21):
+    """Significant face sides (features [n, 16] FP32, labels [n] uint8) from the states of FP64
+    runs of each case, sampled every `every` steps (chunks + 1 states per case)."""
+    import torch
+
+    F, L = [], []
+    for case, Q0, every in cases:
+        s = fsa.Solver(case.with_(precision="fp64"))
+        Q = torch.from_numpy(np.ascontiguousarray(Q0)).cuda()
+        for k in range(chunks + 1):
+            if k:
+                s.rk3_steps(Q, case.dt, every)
+            f, lab, _ = s.harvest(Q, keep_rate, seed + k, cap)
+            F.append(f.clone())
+            L.append(lab.clone())
+        s.sync()
+        s.close()
+    return torch.cat(F), torch.cat(L)
+
+
+def train(F, L, steps=4000, batch=4096, lr=3e-3, lr_final=1e-3, final_frac=0.25, seed=42, conf=0.8,
+          report_every=500):
+    """Adam on shuffled mini-batches; returns (parameters [1667] FP32, sampled losses)."""
+    import torch
+
+    tr = fsa.Solver(W.config2(n=64, h=1.0 / 16.0, sponge=1.0, nprobe=0).with_(precision="learned32"))
+    tr.mlp_set(init_params(seed), conf)
+    g = torch.Generator().manual_seed(seed)
+    perm = torch.randperm(F.shape[0], generator=g).to(F.device)
+    F, L = F[perm].contiguous(), L[perm].contiguous()
+    loss = torch.empty(1, dtype=torch.float32, device=F.device)
+    nb = max(F.shape[0] // batch, 1)
+    losses = []
+    for step in range(steps):
+        a = (step % nb) * batch
+        rate = lr if step < (1.0 - final_frac) * steps else lr_final
+        tr.mlp_train_step(F[a:a + batch], L[a:a + batch], rate, loss)
+        if step % report_every == 0 or step == steps - 1:
+            losses.append(float(loss.item()))
+    theta = tr.mlp_get()
+    tr.close()
+    return theta, losses
