@@ -68,11 +68,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_alpha(Grid G, Phys P, const dou
     }
 }
 
-// One block: bits[d] = max over the n partials (fixed order is irrelevant for a maximum).
-__global__ __launch_bounds__(256) void k_alpha_final(const unsigned long long* __restrict__ part, long long n,
-                                                     unsigned long long* __restrict__ bits)
+// One block of 1024 threads: bits[d] = max over the n partials (the order is irrelevant for a
+// maximum).  With ~4000 partials each thread issues its few loads at once.
+constexpr int FINAL_THREADS = 1024;
+__global__ __launch_bounds__(FINAL_THREADS) void k_alpha_final(const unsigned long long* __restrict__ part,
+                                                               long long n, unsigned long long* __restrict__ bits)
 {
-    __shared__ unsigned long long red[4][3];
+    __shared__ unsigned long long red[FINAL_THREADS / 64][3];
     unsigned long long m[3] = {0ull, 0ull, 0ull};
     for (long long k = threadIdx.x; k < n; k += blockDim.x) {
 #pragma unroll
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void k_alpha_final(const unsigned long long* _
     __syncthreads();
     if (threadIdx.x < 3) {
         unsigned long long v = 0ull;
-        for (int w = 0; w < 4; ++w) v = max_bits(v, red[w][threadIdx.x]);
+        for (int w = 0; w < FINAL_THREADS / 64; ++w) v = max_bits(v, red[w][threadIdx.x]);
         bits[threadIdx.x] = v;
     }
 }
@@ -323,7 +325,7 @@ int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long lo
 
 int launch_alpha_final(const unsigned long long* part, long long n, unsigned long long* bits, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_alpha_final, dim3(1), dim3(256), 0, s, part, n, bits);
+    hipLaunchKernelGGL(k_alpha_final, dim3(1), dim3(FINAL_THREADS), 0, s, part, n, bits);
     return (int)hipGetLastError();
 }
 

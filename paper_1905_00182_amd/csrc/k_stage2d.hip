@@ -127,10 +127,12 @@ struct Column2D {
     // register windows, slot = (row - first front row) mod 5
     T fp[5][4], fm[5][4];
     T uw[5], vw[5];                 // velocities (minus the far-field velocity in FP32)
-    T txx[5], txy[5], tyy[5], bx[5], by[5];
+    T txy[5], tyy[5];               // stresses used in y derivatives stay in registers
+    T (*vring)[3][WAVE];            // LDS: tau_xx, b_x, b_y of the last five stress rows, [slot][.][lane]
     T fy_prev[4], cy_queue[4];
     double qf[4];                   // prefetched state of the next front row
     unsigned wy_pf, wx_pf;          // learned form: prefetched keep patterns of the next step
+    double qn_pf[4];                // step-start state of the next output row (stages 2 and 3)
     double (*ring)[4][WAVE];        // LDS: the last five front rows of this wave, [slot][comp][lane]
     int lane;
 
@@ -177,6 +179,17 @@ struct Column2D {
         }
     }
 
+    // Step-start state Qn of output row r for this lane (issued one step before it is used,
+    // so the load latency hides behind a row of work).
+    __device__ __forceinline__ void load_qn(int r)
+    {
+        if (!mode_rhs && ca != 0.0 && out_lane && r >= j0 && r <= j1) {
+            const long long o = (long long)r * nx + i;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) qn_pf[c] = Qn[c * ncell + o];
+        }
+    }
+
     template <int K5>
     __device__ __forceinline__ void step_row(int Rw)
     {
@@ -203,6 +216,8 @@ struct Column2D {
         load_row(Rw + 1, qf);
         const unsigned word_y = wy_pf, word_x = wx_pf;
         load_patterns(Rw + 1);
+        const double qn[4] = {qn_pf[0], qn_pf[1], qn_pf[2], qn_pf[3]};
+        load_qn(Rw - 3);
         const double inv_rho = rcp_nr(q[0]);
         const double u = q[1] * inv_rho, v = q[2] * inv_rho;
         const double p = gm1 * (q[3] - 0.5 * fma(q[1], u, q[2] * v));
@@ -247,13 +262,13 @@ struct Column2D {
             const T sxx = mu * fma(T(-2.0 / 3.0), div, dudx + dudx);
             const T syy = mu * fma(T(-2.0 / 3.0), div, dvdy + dvdy);
             const T sxy = mu * (dudy + dvdx);
-            txx[S2] = sxx;
+            vring[S2][0][lane] = sxx;
             txy[S2] = sxy;
             tyy[S2] = syy;
             const T uf = F64 ? uc : uc + (T)K->P.prim_inf[1];
             const T vf = F64 ? vc : vc + (T)K->P.prim_inf[2];
-            bx[S2] = fma(uf, sxx, vf * sxy);
-            by[S2] = fma(uf, sxy, vf * syy);
+            vring[S2][1][lane] = fma(uf, sxx, vf * sxy);
+            vring[S2][2][lane] = fma(uf, sxy, vf * syy);
         }
 
         // ---- output row r = Rw-4
@@ -290,9 +305,12 @@ struct Column2D {
             }
             if (terms & T_VISC) {
                 // rows r-2..r+2 sit in slots S1, S0, S4, S3, S2
-                const T vx = d1_lanes(txx[S4], inv12h) + d1(txy[S1], txy[S0], txy[S3], txy[S2], inv12h);
+                // tau_xx, b_x of row r and b_y of rows r-2..r+2 from the wave's LDS ring (each
+                // lane reads back only what it wrote)
+                const T vx = d1_lanes(vring[S4][0][lane], inv12h) + d1(txy[S1], txy[S0], txy[S3], txy[S2], inv12h);
                 const T vy = d1_lanes(txy[S4], inv12h) + d1(tyy[S1], tyy[S0], tyy[S3], tyy[S2], inv12h);
-                const T ve = d1_lanes(bx[S4], inv12h) + d1(by[S1], by[S0], by[S3], by[S2], inv12h);
+                const T ve = d1_lanes(vring[S4][1][lane], inv12h) +
+                             d1(vring[S1][2][lane], vring[S0][2][lane], vring[S3][2][lane], vring[S2][2][lane], inv12h);
                 L[1] += (double)vx;
                 L[2] += (double)vy;
                 L[3] += (double)ve;
@@ -327,7 +345,7 @@ struct Column2D {
                         val[c] = l;
                     } else {
                         const double stage = fma(dt, l, qr[c]);
-                        val[c] = (ca == 0.0) ? stage : fma(ca, Qn[c * ncell + o], cb * stage);
+                        val[c] = (ca == 0.0) ? stage : fma(ca, qn[c], cb * stage);
                     }
                     out[c * ncell + o] = val[c];
                 }
@@ -385,8 +403,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.step = A.step;
 
     __shared__ double ring[5][4][WAVE];
+    __shared__ T vring[5][3][WAVE];
     const int lane = threadIdx.x;
     C.ring = ring;
+    C.vring = vring;
     C.lane = lane;
     const int nx = C.nx, ny = K->G.n[1];
     {
@@ -407,7 +427,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
         for (int c = 0; c < 4; ++c) C.fp[s][c] = C.fm[s][c] = T(0);
         C.uw[s] = C.vw[s] = T(0);
-        C.txx[s] = C.txy[s] = C.tyy[s] = C.bx[s] = C.by[s] = T(0);
+        C.txy[s] = C.tyy[s] = T(0);
     }
     C.want_alpha = A.alpha_part != nullptr;
     C.amax_x = C.amax_y = 0ull;
@@ -415,6 +435,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.load_row(C.j0 - HALO, C.qf);
     C.wy_pf = C.wx_pf = 0u;
     C.load_patterns(C.j0 - HALO);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) C.qn_pf[c] = 0.0;
     for (int Rw = C.j0 - HALO; Rw <= Rend; Rw += 5) {
         C.template step_row<0>(Rw);
         if (Rw + 1 > Rend) break;
