@@ -402,6 +402,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.terms = K->P.terms;
     C.step = A.step;
 
+    // XCD-aware placement: consecutive workgroups go round-robin to the 8 XCDs, each with its
+    // own L2, so the linear workgroup index is remapped to give every XCD one contiguous
+    // run of strips (row-major): neighbouring strips, which read each other's halo columns,
+    // then share an L2.  Any bijection is correct; this one only serves locality.
+    int bx, by;
+    {
+        const int nb = gridDim.x * gridDim.y, b = blockIdx.y * gridDim.x + blockIdx.x;
+        const int q = nb / 8, rm = nb % 8, xcd = b % 8, k = b / 8;
+        const int L = xcd < rm ? xcd * (q + 1) + k : rm * (q + 1) + (xcd - rm) * q + k;
+        bx = L % gridDim.x;
+        by = L / gridDim.x;
+    }
     __shared__ double ring[5][4][WAVE];
     __shared__ T vring[5][3][WAVE];
     const int lane = threadIdx.x;
@@ -410,7 +422,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.lane = lane;
     const int nx = C.nx, ny = K->G.n[1];
     {
-        const int i = blockIdx.x * OUTW - HALO + lane;
+        const int i = bx * OUTW - HALO + lane;
         C.i = min(max(i, -HALO), nx + HALO - 1);
         int inflow = 0, side = 0, depth = 0;
         C.xr = resolve_index(C.i, nx, K->G.bc[0][0], K->G.bc[0][1], 0, inflow, side, depth);
@@ -418,7 +430,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         C.out_lane = lane >= HALO && lane < WAVE - HALO && i < nx;
     }
     C.eta_x = C.out_lane ? K->eta_dir(0, C.i) : 0.0;
-    C.j0 = blockIdx.y * A.ty;
+    C.j0 = by * A.ty;
     C.j1 = min(C.j0 + A.ty, ny) - 1;
 #pragma unroll
     for (int c = 0; c < 4; ++c) C.fy_prev[c] = C.cy_queue[c] = T(0);
