@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfsa.so")
-SOURCES = ["fsa_api.hip", "k_stage2d.hip", "k_ib.hip", "k_mlp.hip", "k_faces2d.hip"]
+SOURCES = ["fsa_api.hip", "k_stage2d.hip", "k_stage3d.hip", "k_ib.hip", "k_mlp.hip", "k_faces2d.hip"]
 ARCH = os.environ.get("FSA_OFFLOAD_ARCH", "gfx950")
 
 

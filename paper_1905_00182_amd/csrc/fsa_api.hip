@@ -31,6 +31,7 @@ struct fsa_ctx {
     double* Qb = nullptr;
     unsigned long long* abits = nullptr; // alpha slots: [4][3]
     unsigned long long* apart = nullptr; // per-block / per-wave partial maxima [apart_n][3]
+    unsigned char* stress3d = nullptr;   // 3D: tau and b with two ghost layers, [9][ext cells] of T
     long long apart_n = 0;
     unsigned long long* h_abits = nullptr;  // pinned mirror of the last step's slots
     hipEvent_t ev_alpha = nullptr;
@@ -149,7 +150,7 @@ int validate(const fsa_desc* d, std::string& why)
         why = "bad precision";
         return FSA_EINVAL;
     }
-    if (d->dim == 3) { why = "3D path not built"; return FSA_EUNSUPPORTED; }
+    if (d->dim == 3 && d->precision == FSA_LEARNED32) { why = "the learned form is built for 2D"; return FSA_EUNSUPPORTED; }
     if (!(d->prim_inf[0] > 0.0) || !(d->prim_inf[4] > 0.0)) { why = "far field must have rho, p > 0"; return FSA_EINVAL; }
     return FSA_OK;
 }
@@ -354,6 +355,22 @@ bool ib_active(const fsa_ctx* c) { return (c->d.terms & FSA_TERM_IB) && c->nm > 
 // slot `in`, the penalty step, and the fused stencil/update kernel, which reads slot `in`,
 // writes the wave speeds of its output into slot `acc` (per-wave partials, then a one-block
 // reduction; slots of three doubles in abits; -1 = none).
+// Next pair of timing events of the context (created on first use).
+int timing_pair(fsa_ctx* c, hipEvent_t& t0, hipEvent_t& t1)
+{
+    if (c->tused + 2 > c->tev.size()) {
+        for (int k = 0; k < 2; ++k) {
+            hipEvent_t ev;
+            HIPCHK(c, hipEventCreate(&ev));
+            c->tev.push_back(ev);
+        }
+    }
+    t0 = c->tev[c->tused];
+    t1 = c->tev[c->tused + 1];
+    c->tused += 2;
+    return FSA_OK;
+}
+
 int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, int in, int acc, bool reduce,
                   int stage, double ca, double cb, double dt, int mode_rhs)
 {
@@ -397,6 +414,22 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     S.dt = dt;
     S.mode_rhs = mode_rhs;
     S.step = c->step;
+    if (c->G.dim == 3) {
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        if (c->timing) {
+            int rc = timing_pair(c, t0, t1);
+            if (rc != FSA_OK) return rc;
+            HIPCHK(c, hipEventRecord(t0, c->stream));
+        }
+        e = launch_stage3d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stress3d, c->stream);
+        if (e) return hipcheck(c, (hipError_t)e, "3D stage launch");
+        if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
+        if (acc >= 0) {
+            e = launch_alpha_final(c->apart, stage3d_blocks(c->G), c->abits + 3 * acc, c->stream);
+            if (e) return hipcheck(c, (hipError_t)e, "wave-speed reduction launch");
+        }
+        return FSA_OK;
+    }
     if (c->ty == 0) {
         int rc = tune_ty(c, S);
         if (rc != FSA_OK) return rc;
@@ -404,16 +437,8 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     S.ty = c->ty;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (c->timing) {
-        if (c->tused + 2 > c->tev.size()) {
-            for (int k = 0; k < 2; ++k) {
-                hipEvent_t ev;
-                HIPCHK(c, hipEventCreate(&ev));
-                c->tev.push_back(ev);
-            }
-        }
-        t0 = c->tev[c->tused];
-        t1 = c->tev[c->tused + 1];
-        c->tused += 2;
+        int rc = timing_pair(c, t0, t1);
+        if (rc != FSA_OK) return rc;
         HIPCHK(c, hipEventRecord(t0, c->stream));
     }
     e = launch_stage2d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stream);
@@ -571,10 +596,19 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
     if ((rc = dalloc(c, c->Qa, (size_t)c->nq * c->ncell)) != FSA_OK ||
         (rc = dalloc(c, c->Qb, (size_t)c->nq * c->ncell)) != FSA_OK ||
         (rc = dalloc(c, c->abits, 12)) != FSA_OK || (rc = dalloc(c, c->dK, 1)) != FSA_OK ||
-        (rc = dalloc(c, c->apart, 3 * (size_t)(c->apart_n = std::max<long long>(ALPHA_MAX_BLOCKS,
-                                                                                stage2d_waves(c->G, 4))))) != FSA_OK) {
+        (rc = dalloc(c, c->apart,
+                     3 * (size_t)(c->apart_n = std::max<long long>(
+                                      ALPHA_MAX_BLOCKS, c->G.dim == 3 ? stage3d_blocks(c->G) : stage2d_waves(c->G, 4))))) !=
+            FSA_OK) {
         fsa_destroy(c);
         return rc;
+    }
+    if (c->G.dim == 3) {
+        const size_t tsize = desc->precision == FSA_MIXED32 ? sizeof(float) : sizeof(double);
+        if ((rc = dalloc(c, c->stress3d, (size_t)stress3d_elems(c->G) * tsize)) != FSA_OK) {
+            fsa_destroy(c);
+            return rc;
+        }
     }
     {
         KConst hk;
@@ -623,6 +657,7 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->dK);
     dfree(c->abits);
     dfree(c->apart);
+    dfree(c->stress3d);
     dfree(c->X);
     dfree(c->dV);
     dfree(c->U);

@@ -1,0 +1,349 @@
+// 3D right-hand side / SSP-RK3 stage: two cell-centric passes for gfx950.
+//
+//  * k_stress3d: for every cell of the grid extended by two ghost layers, the velocity
+//    gradients by the fourth-order central difference (Sec. 2, Eqs. (5)-(6)), the Stokes
+//    stress tau and b = u . tau, stored as nine components [9][ext cells] (tau_xx, tau_yy,
+//    tau_zz, tau_xy, tau_xz, tau_yz, b_x, b_y, b_z).
+//  * k_stage3d: per interior cell, along each direction the seven cells i-3..i+3 give the
+//    split fluxes f+- = (F +- alpha Q)/2 of the five components, from which both faces
+//    i-1/2 and i+1/2 are reconstructed (so a face is computed by the two cells it bounds, by
+//    the same code on the same inputs: the flux difference still telescopes exactly); the
+//    viscous divergence comes from the stress buffer; then the penalty-IB source from the
+//    window array, the sponge, the RK3 combination, and one wave-speed partial per block.
+//
+// Threads of a block are 64 consecutive x cells by 4 rows, so every load along x is
+// coalesced; neighbours along y and z come through the caches.  Arithmetic type T as in 2D:
+// double (the method) or float (the precision form, on deviations from the far field).
+#include <type_traits>
+
+#include "fsa_impl.hpp"
+
+namespace fsa {
+
+namespace {
+
+constexpr int BX = 64, BY = 4;
+
+__device__ __forceinline__ long long lin3(const Grid& G, int i, int j, int k)
+{
+    return ((long long)k * G.n[1] + j) * G.n[0] + i;
+}
+
+// State of cell (i, j, k), ghosts resolved by the boundary conditions.
+__device__ __forceinline__ void cell_state(const KConst* K, const double* __restrict__ Q, long long step, int i, int j,
+                                           int k, double* q)
+{
+    const Grid& G = K->G;
+    if (i >= 0 && i < G.n[0] && j >= 0 && j < G.n[1] && k >= 0 && k < G.n[2]) {
+        const long long o = lin3(G, i, j, k);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) q[c] = Q[c * G.ncell + o];
+    } else {
+        fetch_state<3>(Q, G, K->P, step, i, j, k, q);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void offset(int& i, int& j, int& k, int s)
+{
+    if (D == 0) i += s;
+    else if (D == 1) j += s;
+    else k += s;
+}
+
+template <class T>
+__device__ __forceinline__ T d1(T gm2, T gm1, T gp1, T gp2, T inv12h)
+{
+    return (T(8) * (gp1 - gm1) - (gp2 - gm2)) * inv12h;
+}
+
+// ---------------------------------------------------------------------------------------
+// Stress pass
+// ---------------------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void velocity(const KConst* K, const double* Q, long long step, int i, int j, int k,
+                                         T* u)
+{
+    constexpr bool F64 = std::is_same<T, double>::value;
+    double q[5];
+    cell_state(K, Q, step, i, j, k, q);
+    const double ir = rcp_nr(q[0]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double v = q[1 + a] * ir;
+        u[a] = F64 ? (T)v : (T)(v - K->P.prim_inf[1 + a]);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(BX * BY) void k_stress3d(const KConst* __restrict__ K, const double* __restrict__ Q,
+                                                      long long step, T* __restrict__ S)
+{
+    constexpr bool F64 = std::is_same<T, double>::value;
+    const Grid& G = K->G;
+    const int ex = G.n[0] + 4, ey = G.n[1] + 4, ez = G.n[2] + 4;
+    const int xi = blockIdx.x * BX + (threadIdx.x & (BX - 1));
+    const int yi = blockIdx.y * BY + (threadIdx.x / BX);
+    const int zi = blockIdx.z;
+    if (xi >= ex || yi >= ey || zi >= ez) return;
+    const int i = xi - 2, j = yi - 2, k = zi - 2;
+    const T inv12h = (T)K->inv12h, mu = (T)K->P.mu;
+    T g[3][3];   // g[a][b] = d u_a / d x_b
+    T um[4][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int off[4] = {-2, -1, 1, 2};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            int ii = i, jj = j, kk = k;
+            if (b == 0) ii += off[m];
+            else if (b == 1) jj += off[m];
+            else kk += off[m];
+            velocity<T>(K, Q, step, ii, jj, kk, um[m]);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) g[a][b] = d1(um[0][a], um[1][a], um[2][a], um[3][a], inv12h);
+    }
+    T uc[3];
+    velocity<T>(K, Q, step, i, j, k, uc);
+    const T div = g[0][0] + g[1][1] + g[2][2];
+    const T sxx = mu * fma(T(-2.0 / 3.0), div, g[0][0] + g[0][0]);
+    const T syy = mu * fma(T(-2.0 / 3.0), div, g[1][1] + g[1][1]);
+    const T szz = mu * fma(T(-2.0 / 3.0), div, g[2][2] + g[2][2]);
+    const T sxy = mu * (g[0][1] + g[1][0]);
+    const T sxz = mu * (g[0][2] + g[2][0]);
+    const T syz = mu * (g[1][2] + g[2][1]);
+    T uf[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) uf[a] = F64 ? uc[a] : uc[a] + (T)K->P.prim_inf[1 + a];
+    const long long ne = (long long)ex * ey * ez;
+    const long long o = ((long long)zi * ey + yi) * ex + xi;
+    S[0 * ne + o] = sxx;
+    S[1 * ne + o] = syy;
+    S[2 * ne + o] = szz;
+    S[3 * ne + o] = sxy;
+    S[4 * ne + o] = sxz;
+    S[5 * ne + o] = syz;
+    S[6 * ne + o] = fma(uf[0], sxx, fma(uf[1], sxy, uf[2] * sxz));
+    S[7 * ne + o] = fma(uf[0], sxy, fma(uf[1], syy, uf[2] * syz));
+    S[8 * ne + o] = fma(uf[0], sxz, fma(uf[1], syz, uf[2] * szz));
+}
+
+// ---------------------------------------------------------------------------------------
+// Stage pass
+// ---------------------------------------------------------------------------------------
+template <int SCHEME>
+__device__ __forceinline__ double rec(double a, double b, double c, double d, double e, const Recon& R, const Recon32&)
+{
+    return recon5<SCHEME>(a, b, c, d, e, R);
+}
+template <int SCHEME>
+__device__ __forceinline__ float rec(float a, float b, float c, float d, float e, const Recon&, const Recon32& R)
+{
+    return recon5f<SCHEME>(a, b, c, d, e, R);
+}
+
+// -(F^_{i+1/2} - F^_{i-1/2}) / h along direction D, added to L.
+template <int SCHEME, class T, int D>
+__device__ __forceinline__ void convective(const KConst* K, const double* Q, long long step, int i, int j, int k,
+                                           double alpha, const Recon& R, const Recon32& R32, double* L)
+{
+    constexpr bool F64 = std::is_same<T, double>::value;
+    double q[7][5], ud[7], p[7];
+#pragma unroll
+    for (int s = 0; s < 7; ++s) {
+        int ii = i, jj = j, kk = k;
+        offset<D>(ii, jj, kk, s - 3);
+        cell_state(K, Q, step, ii, jj, kk, q[s]);
+        const double ir = rcp_nr(q[s][0]);
+        const double u = q[s][1] * ir, v = q[s][2] * ir, w = q[s][3] * ir;
+        p[s] = K->P.gm1 * (q[s][4] - 0.5 * fma(q[s][1], u, fma(q[s][2], v, q[s][3] * w)));
+        ud[s] = D == 0 ? u : (D == 1 ? v : w);
+    }
+    const double* Finf = D == 0 ? K->Fx_inf : (D == 1 ? K->Fy_inf : K->Fz_inf);
+    const T inv_h = (T)K->G.inv_h;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        T fp[7], fm[7];
+#pragma unroll
+        for (int s = 0; s < 7; ++s) {
+            double F;
+            if (c == 0) F = q[s][1 + D];
+            else if (c == 4) F = (q[s][4] + p[s]) * ud[s];
+            else if (c - 1 == D) F = fma(q[s][c], ud[s], p[s]);
+            else F = q[s][c] * ud[s];
+            if (F64) {
+                fp[s] = (T)(0.5 * fma(alpha, q[s][c], F));
+                fm[s] = (T)(0.5 * fma(-alpha, q[s][c], F));
+            } else {
+                const double dq = q[s][c] - K->P.q_inf[c], dF = F - Finf[c];
+                fp[s] = (T)(0.5 * fma(alpha, dq, dF));
+                fm[s] = (T)(0.5 * fma(-alpha, dq, dF));
+            }
+        }
+        // faces i-1/2 (cells 0..5) and i+1/2 (cells 1..6), each by the same expression
+        T fh[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+            fh[f] = rec<SCHEME>(fp[f], fp[f + 1], fp[f + 2], fp[f + 3], fp[f + 4], R, R32) +
+                    rec<SCHEME>(fm[f + 5], fm[f + 4], fm[f + 3], fm[f + 2], fm[f + 1], R, R32);
+        L[c] += (double)(-(fh[1] - fh[0]) * inv_h);
+    }
+}
+
+template <int SCHEME, class T>
+__global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ K, StageArgs A, const T* __restrict__ S)
+{
+    const Grid& G = K->G;
+    const int i = blockIdx.x * BX + (threadIdx.x & (BX - 1));
+    const int j = blockIdx.y * BY + (threadIdx.x / BX);
+    const int k = blockIdx.z;
+    const bool inside = i < G.n[0] && j < G.n[1];
+    const int terms = K->P.terms;
+    unsigned long long am[3] = {0ull, 0ull, 0ull};
+    if (inside) {
+        Recon R;
+        R.eps = SCHEME == WENO5JS ? K->P.weno_eps : K->P.teno_eps;
+        R.ct = K->P.teno_ct;
+        Recon32 R32;
+        R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;
+        R32.ct = (float)K->P.teno_ct;
+        double L[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (terms & T_CONVX)
+            convective<SCHEME, T, 0>(K, A.Qs, A.step, i, j, k, __longlong_as_double((long long)A.alpha_bits[0]), R,
+                                     R32, L);
+        if (terms & T_CONVY)
+            convective<SCHEME, T, 1>(K, A.Qs, A.step, i, j, k, __longlong_as_double((long long)A.alpha_bits[1]), R,
+                                     R32, L);
+        if (terms & T_CONVZ)
+            convective<SCHEME, T, 2>(K, A.Qs, A.step, i, j, k, __longlong_as_double((long long)A.alpha_bits[2]), R,
+                                     R32, L);
+        if (terms & T_VISC) {
+            // momentum a: sum_b D_b(tau_ab); energy: sum_b D_b(b_b)
+            const int ex = G.n[0] + 4, ey = G.n[1] + 4, ez = G.n[2] + 4;
+            const long long ne = (long long)ex * ey * ez;
+            const long long oc = ((long long)(k + 2) * ey + (j + 2)) * ex + (i + 2);
+            const long long st[3] = {1, ex, (long long)ex * ey};
+            const T inv12h = (T)K->inv12h;
+            // stress component index of tau_ab
+            constexpr int tidx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+            T acc[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int comp = a < 3 ? tidx[a][b] : 6 + b;
+                    const T* P = S + comp * ne + oc;
+                    acc[a] += d1(P[-2 * st[b]], P[-st[b]], P[st[b]], P[2 * st[b]], inv12h);
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) L[1 + a] += (double)acc[a];
+        }
+        const long long o = lin3(G, i, j, k);
+        double qc[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) qc[c] = A.Qs[c * G.ncell + o];
+        double src[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if ((terms & T_IB) && A.fwin) {
+            const int wi = i - A.wlo[0], wj = j - A.wlo[1], wk = k - A.wlo[2];
+            if (wi >= 0 && wi < A.wn[0] && wj >= 0 && wj < A.wn[1] && wk >= 0 && wk < A.wn[2]) {
+                const long long wc = ((long long)wk * A.wn[1] + wj) * A.wn[0] + wi;
+                const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
+                const double ir = rcp_nr(qc[0]);
+                double fu = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double f = A.fwin[a * wcells + wc];
+                    src[1 + a] = f;
+                    fu = fma(f, qc[1 + a] * ir, fu);
+                }
+                src[4] = fu;
+            }
+        }
+        if (terms & T_SPONGE) {
+            const double eta = fmax(K->eta_dir(0, i), fmax(K->eta_dir(1, j), K->eta_dir(2, k)));
+            if (eta > 0.0) {
+                const double sg = K->P.sigma * (eta * eta * eta);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) src[c] = fma(-sg, qc[c] - K->P.q_inf[c], src[c]);
+            }
+        }
+        double val[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const double l = L[c] + src[c];
+            if (A.mode_rhs) {
+                val[c] = l;
+            } else {
+                const double stage = fma(A.dt, l, qc[c]);
+                val[c] = (A.ca == 0.0) ? stage : fma(A.ca, A.Qn[c * G.ncell + o], A.cb * stage);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) A.out[c * G.ncell + o] = val[c];
+        if (A.alpha_part) {
+            const double ir = rcp_nr(val[0]);
+            const double u = val[1] * ir, v = val[2] * ir, w = val[3] * ir;
+            const double pn = K->P.gm1 * (val[4] - 0.5 * fma(val[1], u, fma(val[2], v, val[3] * w)));
+            const double cn = sqrt(K->P.gamma * pn * ir);
+            am[0] = (unsigned long long)__double_as_longlong(fabs(u) + cn);
+            am[1] = (unsigned long long)__double_as_longlong(fabs(v) + cn);
+            am[2] = (unsigned long long)__double_as_longlong(fabs(w) + cn);
+        }
+    }
+    if (A.alpha_part) {
+        // block maximum -> one partial per block (plain stores; reduced by launch_alpha_final)
+        __shared__ unsigned long long red[BX * BY / 64][3];
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            unsigned long long v = am[d];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v = max_bits(v, __shfl_xor(v, off, 64));
+            if (lane == 0) red[wid][d] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            unsigned long long v = 0ull;
+#pragma unroll
+            for (int w = 0; w < BX * BY / 64; ++w) v = max_bits(v, red[w][threadIdx.x]);
+            const long long b = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+            A.alpha_part[b * 3 + threadIdx.x] = v;
+        }
+    }
+}
+
+}  // namespace
+
+long long stress3d_elems(const Grid& G)
+{
+    return 9ll * (G.n[0] + 4) * (G.n[1] + 4) * (G.n[2] + 4);
+}
+
+long long stage3d_blocks(const Grid& G)
+{
+    return (long long)((G.n[0] + BX - 1) / BX) * ((G.n[1] + BY - 1) / BY) * G.n[2];
+}
+
+int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, void* stress,
+                   hipStream_t s)
+{
+    const dim3 block(BX * BY);
+    const dim3 gs((G.n[0] + 4 + BX - 1) / BX, (G.n[1] + 4 + BY - 1) / BY, G.n[2] + 4);
+    const dim3 gr((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
+    if (precision == 1) {
+        float* S = static_cast<float*>(stress);
+        hipLaunchKernelGGL(k_stress3d<float>, gs, block, 0, s, K, A.Qs, A.step, S);
+        if (scheme == TENO5) hipLaunchKernelGGL((k_stage3d<TENO5, float>), gr, block, 0, s, K, A, (const float*)S);
+        else hipLaunchKernelGGL((k_stage3d<WENO5JS, float>), gr, block, 0, s, K, A, (const float*)S);
+    } else {
+        double* S = static_cast<double*>(stress);
+        hipLaunchKernelGGL(k_stress3d<double>, gs, block, 0, s, K, A.Qs, A.step, S);
+        if (scheme == TENO5) hipLaunchKernelGGL((k_stage3d<TENO5, double>), gr, block, 0, s, K, A, (const double*)S);
+        else hipLaunchKernelGGL((k_stage3d<WENO5JS, double>), gr, block, 0, s, K, A, (const double*)S);
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace fsa

@@ -153,13 +153,18 @@ def natural_scale(case):
 def _assert_q_close(Qg, Qo, Q0, case, tol=1e-12):
     whole = np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo)
     _say(f"  whole state: rel L2 {whole:.3e}")
-    assert whole <= tol
     scale = natural_scale(case)
+    rels = []
     for c in range(Qo.shape[0]):
         ref = max(np.linalg.norm(Qo[c]), scale[c] * np.sqrt(Qo[c].size))
         rel = np.linalg.norm(Qg[c] - Qo[c]) / ref
+        d = np.abs(Qg[c] - Qo[c])
+        at = np.unravel_index(np.argmax(d), d.shape)
         dev = np.abs(Qo[c] - Q0[c]).max()
-        _say(f"  comp {c}: rel L2 {rel:.3e}; max|dQ| {np.abs(Qg[c] - Qo[c]).max():.3e} of change {dev:.3e}")
+        _say(f"  comp {c}: rel L2 {rel:.3e}; max|dQ| {d.max():.3e} at {tuple(int(x) for x in at)} of change {dev:.3e}")
+        rels.append(rel)
+    assert whole <= tol
+    for c, rel in enumerate(rels):
         assert rel <= tol, (c, rel)
 
 
