@@ -177,6 +177,13 @@ int32_t fsa_marker_force(fsa_ctx* ctx, double* h_F);
 /* Checkpoint: penalty integral h_xi[dim][n], time and step.  Synchronising. */
 int32_t fsa_get_state(fsa_ctx* ctx, double* h_xi, double* t, int64_t* step);
 int32_t fsa_set_state(fsa_ctx* ctx, const double* h_xi, double t, int64_t step);
+/* Diagnostics (Sec. 3: field totals; the dilatation of the precision-form discussion).
+ * h_totals (host, nullable) receives sum over cells of q_m h^dim for every component
+ * (deterministic summation order; synchronising when given); d_dilatation (device, nullable,
+ * [ncell] in the state's cell order) receives div u by fourth-order central differences of
+ * u_d = m_d / rho, ghosts by the boundary conditions.  FSA_EINVAL if both are NULL. */
+int32_t fsa_diagnostics(fsa_ctx* ctx, const double* d_Q, double* h_totals, double* d_dilatation);
+
 /* Learned TENO5 sub-stencil selector (not in the paper; the library's addition).  A face side
  * is significant when rho, a velocity component or p varies over its five cells by more than
  * 1e-8 of its natural scale (rho_inf, c_inf, rho_inf c_inf^2); an insignificant side keeps

@@ -955,6 +955,47 @@ int ora_probe_dp(const ora_ctx* c, const double* Q, double* dp)
     return 0;
 }
 
+/* Field totals (diagnostics of Sec. 3): out[m] = sum over cells, in cell order, of q_m h^dim. */
+int ora_totals(const ora_ctx* c, const double* Q, double* out)
+{
+    long nc = c->ncell;
+    double hd = 1.0;
+    for (int d = 0; d < c->d.dim; ++d) hd *= c->d.h;
+    for (int m = 0; m < c->nq; ++m) {
+        double s = 0.0;
+        for (long n = 0; n < nc; ++n) s += Q[(long)m * nc + n];
+        out[m] = s * hd;
+    }
+    return 0;
+}
+
+/* Dilatation div u at every cell: the fourth-order central difference of u_d = m_d / rho
+ * along d, summed over directions (ghosts by the boundary conditions). */
+int ora_dilatation(const ora_ctx* c, const double* Q, double* out)
+{
+    int dim = c->d.dim;
+    long nc = c->ncell;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < nc; ++n) {
+        long idx[3];
+        idx_of(c, n, idx);
+        double div = 0.0;
+        for (int d = 0; d < dim; ++d) {
+            double g[5];
+            for (int s = 0; s < 5; ++s) {
+                long id[3] = {idx[0], idx[1], idx[2]};
+                double u[3];
+                id[d] += s - 2;
+                velocity_at(c, Q, id, u);
+                g[s] = u[d];
+            }
+            div += d1c4(g, c->d.h);
+        }
+        out[n] = div;
+    }
+    return 0;
+}
+
 int ora_marker_force(const ora_ctx* c, double* F)
 {
     memcpy(F, c->F, sizeof(double) * (size_t)c->d.dim * (size_t)c->nm);

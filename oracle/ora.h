@@ -84,6 +84,9 @@ int ora_ib_spread(const ora_ctx* c, const double* F, int ncomp, double* field, d
 int ora_probe_dp(const ora_ctx* c, const double* Q, double* dp);
 /* Penalty force of the most recent right-hand-side evaluation, [dim][nm]. */
 int ora_marker_force(const ora_ctx* c, double* F);
+/* Field totals sum q_m h^dim [nq]; dilatation div u at every cell [ncell]. */
+int ora_totals(const ora_ctx* c, const double* Q, double* out);
+int ora_dilatation(const ora_ctx* c, const double* Q, double* out);
 int ora_get_state(const ora_ctx* c, double* xi, double* t, int64_t* step);
 int ora_set_state(ora_ctx* c, const double* xi, double t, int64_t step);
 

@@ -81,6 +81,10 @@ def lib():
         _lib.ora_face_features.restype = C.c_int
         _lib.ora_face_label.argtypes = [vp, dp, C.c_int, C.c_long, C.c_long, C.c_long, C.c_int, d]
         _lib.ora_face_label.restype = C.c_int
+        _lib.ora_totals.argtypes = [vp, dp, dp]
+        _lib.ora_totals.restype = C.c_int
+        _lib.ora_dilatation.argtypes = [vp, dp, dp]
+        _lib.ora_dilatation.restype = C.c_int
         _lib.ora_face_significant.argtypes = [vp, dp, C.c_int, C.c_long, C.c_long, C.c_long, C.c_int]
         _lib.ora_face_significant.restype = C.c_int
         _lib.ora_splitmix64.restype = C.c_uint64
@@ -258,6 +262,20 @@ class Oracle:
         if r < 0:
             raise ValueError("face_label failed")
         return r
+
+    def totals(self, Q):
+        """sum over cells of q_m h^dim, per component."""
+        Q = self._state(Q)
+        out = np.empty(self.nq)
+        self._check(lib().ora_totals(self.ctx, _ptr(Q), _ptr(out)), "totals")
+        return out
+
+    def dilatation(self, Q):
+        """div u at every cell (fourth-order central differences)."""
+        Q = self._state(Q)
+        out = np.empty(Q.shape[1:])
+        self._check(lib().ora_dilatation(self.ctx, _ptr(Q), _ptr(out)), "dilatation")
+        return out
 
     def face_significant(self, Q, d, idx, side):
         """True when some primitive variable of the side's five cells varies by more than

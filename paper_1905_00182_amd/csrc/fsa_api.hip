@@ -32,6 +32,8 @@ struct fsa_ctx {
     unsigned long long* abits = nullptr; // alpha slots: [4][3]
     unsigned long long* apart = nullptr; // per-block / per-wave partial maxima [apart_n][3]
     unsigned char* stress3d = nullptr;   // 3D: tau and b with two ghost layers, [9][ext cells] of T
+    double* tot_part = nullptr;          // diagnostics: per-block partial totals
+    double* tot_out = nullptr;
     long long apart_n = 0;
     unsigned long long* h_abits = nullptr;  // pinned mirror of the last step's slots
     hipEvent_t ev_alpha = nullptr;
@@ -658,6 +660,8 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->abits);
     dfree(c->apart);
     dfree(c->stress3d);
+    dfree(c->tot_part);
+    dfree(c->tot_out);
     dfree(c->X);
     dfree(c->dV);
     dfree(c->U);
@@ -972,6 +976,28 @@ int32_t fsa_face_flags(fsa_ctx* c, const double* d_Q, uint32_t* d_flags_x, uint3
     int e = launch_alpha(c->G, c->P, d_Q, c->apart, bits, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "alpha launch");
     return enqueue_flags(c, d_Q, bits, d_flags_x, d_flags_y);
+}
+
+int32_t fsa_diagnostics(fsa_ctx* c, const double* d_Q, double* h_totals, double* d_dilatation)
+{
+    if (!c || !d_Q || (!h_totals && !d_dilatation)) return FSA_EINVAL;
+    int rc, e;
+    if (d_dilatation) {
+        e = launch_dilatation(c->G, c->P, d_Q, c->step, d_dilatation, c->stream);
+        if (e) return hipcheck(c, (hipError_t)e, "dilatation launch");
+    }
+    if (h_totals) {
+        if (!c->tot_part) {
+            if ((rc = dalloc(c, c->tot_part, (size_t)totals_part_size(c->nq))) != FSA_OK ||
+                (rc = dalloc(c, c->tot_out, 5)) != FSA_OK)
+                return rc;
+        }
+        e = launch_totals(c->G, c->nq, d_Q, c->tot_part, c->tot_out, c->stream);
+        if (e) return hipcheck(c, (hipError_t)e, "totals launch");
+        HIPCHK(c, hipMemcpyAsync(h_totals, c->tot_out, sizeof(double) * c->nq, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return FSA_OK;
 }
 
 int32_t fsa_timing_enable(fsa_ctx* c, int32_t on)

@@ -65,6 +65,11 @@ int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long lo
 // bits[d] = NaN-propagating max over n partials part[k * 3 + d] (d < 3).
 int launch_alpha_final(const unsigned long long* part, long long n, unsigned long long* bits, hipStream_t s);
 int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s);
+// Field totals out[m] = sum_cells q_m h^dim (deterministic order; part: totals_part_size doubles)
+// and the dilatation div u at every cell.
+int totals_part_size(int nq);
+int launch_totals(const Grid& G, int nq, const double* Q, double* part, double* out, hipStream_t s);
+int launch_dilatation(const Grid& G, const Phys& P, const double* Q, long long step, double* out, hipStream_t s);
 int launch_ib_weights(const Grid& G, const IBArgs& A, int* mj0, double* mw, double* cell_w, hipStream_t s);
 int launch_interp(const Grid& G, int npts, const double* X, const double* field, int ncomp, double* out,
                   hipStream_t s);

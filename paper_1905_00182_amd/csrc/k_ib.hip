@@ -310,6 +310,84 @@ __global__ void k_probe_dp(Grid G, Phys P, int np, const double* __restrict__ Xp
     dp[k] = acc - P.prim_inf[4];
 }
 
+// Field totals, deterministic: every block sums a fixed contiguous range of cells in a fixed
+// order (thread-strided, then a fixed tree), and one block sums the block partials the same way.
+constexpr int TOT_THREADS = 256;
+constexpr int TOT_BLOCKS = 1024;
+
+__device__ __forceinline__ double block_sum_fixed(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = TOT_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(TOT_THREADS) void k_totals(const double* __restrict__ Q, long long ncell, int nq,
+                                                        double* __restrict__ part)
+{
+    __shared__ double sh[TOT_THREADS];
+    const long long per = (ncell + gridDim.x - 1) / gridDim.x;
+    const long long b0 = (long long)blockIdx.x * per, b1 = min(b0 + per, ncell);
+    for (int m = 0; m < nq; ++m) {
+        double s = 0.0;
+        for (long long n = b0 + threadIdx.x; n < b1; n += TOT_THREADS) s += Q[(long long)m * ncell + n];
+        const double t = block_sum_fixed(s, sh);
+        if (threadIdx.x == 0) part[(long long)blockIdx.x * nq + m] = t;
+    }
+}
+
+__global__ __launch_bounds__(TOT_THREADS) void k_totals_final(const double* __restrict__ part, int nblocks, int nq,
+                                                              double hd, double* __restrict__ out)
+{
+    __shared__ double sh[TOT_THREADS];
+    for (int m = 0; m < nq; ++m) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += TOT_THREADS) s += part[(long long)b * nq + m];
+        const double t = block_sum_fixed(s, sh);
+        if (threadIdx.x == 0) out[m] = t * hd;
+    }
+}
+
+// div u at every cell: fourth-order central differences of u_d = m_d / rho along d.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_dilatation(Grid G, Phys P, const double* __restrict__ Q, long long step,
+                                                    double* __restrict__ out)
+{
+    const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= G.ncell) return;
+    const int i = (int)(n % G.n[0]);
+    const int j = (int)((n / G.n[0]) % G.n[1]);
+    const int k = DIM == 3 ? (int)(n / ((long long)G.n[0] * G.n[1])) : 0;
+    const double inv12h = 1.0 / (12.0 * G.h);
+    double div = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        double g[5];
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            if (s == 2) {
+                g[s] = 0.0;
+                continue;
+            }
+            int ii = i, jj = j, kk = k;
+            if (d == 0) ii += s - 2;
+            else if (d == 1) jj += s - 2;
+            else kk += s - 2;
+            double q[DIM + 2];
+            fetch_state<DIM>(Q, G, P, step, ii, jj, kk, q);
+            g[s] = q[1 + d] / q[0];
+        }
+        div += (8.0 * (g[3] - g[1]) - (g[4] - g[0])) * inv12h;
+    }
+    out[n] = div;
+}
+
 }  // namespace
 
 int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* part, unsigned long long* bits,
@@ -385,6 +463,24 @@ int launch_probe_dp(const Grid& G, const Phys& P, int np, const double* Xp, cons
     const int blocks = (np + 127) / 128;
     if (G.dim == 3) hipLaunchKernelGGL(k_probe_dp<3>, dim3(blocks), dim3(128), 0, s, G, P, np, Xp, Q, dp);
     else hipLaunchKernelGGL(k_probe_dp<2>, dim3(blocks), dim3(128), 0, s, G, P, np, Xp, Q, dp);
+    return (int)hipGetLastError();
+}
+
+int totals_part_size(int nq) { return TOT_BLOCKS * nq; }
+
+int launch_totals(const Grid& G, int nq, const double* Q, double* part, double* out, hipStream_t s)
+{
+    const double hd = G.dim == 3 ? G.h * G.h * G.h : G.h * G.h;
+    hipLaunchKernelGGL(k_totals, dim3(TOT_BLOCKS), dim3(TOT_THREADS), 0, s, Q, G.ncell, nq, part);
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(TOT_THREADS), 0, s, part, TOT_BLOCKS, nq, hd, out);
+    return (int)hipGetLastError();
+}
+
+int launch_dilatation(const Grid& G, const Phys& P, const double* Q, long long step, double* out, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((G.ncell + 255) / 256);
+    if (G.dim == 3) hipLaunchKernelGGL(k_dilatation<3>, dim3(blocks), dim3(256), 0, s, G, P, Q, step, out);
+    else hipLaunchKernelGGL(k_dilatation<2>, dim3(blocks), dim3(256), 0, s, G, P, Q, step, out);
     return (int)hipGetLastError();
 }
 

@@ -89,6 +89,7 @@ _SIGS = {
     "fsa_ib_interp": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "fsa_ib_spread": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double]),
     "fsa_probe_dp": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsa_diagnostics": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fsa_marker_force": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fsa_get_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "fsa_set_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]),
@@ -276,6 +277,15 @@ class Solver:
     def set_state(self, xi, t, step):
         xa = _host(xi) if xi is not None else None
         self._check(lib().fsa_set_state(self.ctx, xa.ctypes.data if xa is not None else None, t, step))
+
+    def diagnostics(self, Q, dilatation=True):
+        """(totals [nq] on the host, dilatation [shape] on the device or None)."""
+        t = self.torch
+        Q = self._state(Q)
+        tot = np.zeros(self.nq)
+        dil = t.empty(self.case.shape, dtype=t.float64, device=Q.device) if dilatation else None
+        self._check(lib().fsa_diagnostics(self.ctx, _ptr(Q), tot.ctypes.data, _ptr(dil) if dil is not None else None))
+        return tot, dil
 
     # -- learned selector
     def mlp_set(self, params, conf_threshold=0.8):

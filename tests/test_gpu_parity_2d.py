@@ -288,3 +288,36 @@ def test_segmentation_does_not_change_results(torch_cuda, monkeypatch):
     for L, Q, ty in outs[1:]:
         assert np.array_equal(L, outs[0][0]) and np.array_equal(Q, outs[0][1]), ty
     assert outs[-1][2] >= 8
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_diagnostics_match_oracle(torch_cuda, dim):
+    if dim == 2:
+        case = _c2_small(n=160, nprobe=0)
+        Q0 = W.config2_noisy_state(case)
+        Q0[0, 40:70, 30:60] *= 1.03
+    else:
+        case = W.config3(n=40, scheme="teno5", nmark=500)
+        Q0 = W.perturbed_state(case, seed=36, amp=1e-2, step_amp=0.2)
+    s = _solver(case)
+    tot, dil = s.diagnostics(torch_cuda.from_numpy(Q0).cuda())
+    o = _oracle(case)
+    tot_o, dil_o = o.totals(Q0), o.dilatation(Q0)
+    _say(f"diagnostics {dim}D: totals rel {np.abs(tot - tot_o).max() / np.abs(tot_o).max():.2e}, "
+         f"dilatation max|d| {np.abs(dil.cpu().numpy() - dil_o).max():.2e} of {np.abs(dil_o).max():.2e}")
+    # different summation orders: a few ulps per term at most, far less in practice
+    np.testing.assert_allclose(tot, tot_o, rtol=1e-13, atol=1e-13 * np.abs(tot_o).max())
+    np.testing.assert_allclose(dil.cpu().numpy(), dil_o, rtol=0, atol=1e-13 * np.abs(dil_o).max())
+
+
+def test_totals_conserved_on_periodic_box(torch_cuda):
+    case = _small_box("teno5")
+    Q0 = W.perturbed_state(case, seed=23, amp=2e-2, step_amp=0.3)
+    s = _solver(case)
+    Q = torch_cuda.from_numpy(Q0.copy()).cuda()
+    t0, _ = s.diagnostics(Q, dilatation=False)
+    s.rk3_steps(Q, case.dt, 25)
+    t1, _ = s.diagnostics(Q, dilatation=False)
+    _say("periodic box totals drift:", (t1 - t0) / np.abs(t0).max())
+    # mass, momentum and energy: no source term in a periodic box without markers or sponge
+    np.testing.assert_allclose(t1, t0, rtol=0, atol=1e-13 * np.abs(t0).max())

@@ -171,7 +171,7 @@ def test_precision3d_rhs_config4_full_size_sampled(torch_cuda):
     Sd = 4.0 * max(alpha) * dq / case.h
     err = np.abs(Lg - Lo).max()
     _say(f"384^3 precision form rhs on {lin.size} cells: max|dL| / Sd = {err / Sd:.3e}; max|L| / Sd = {np.abs(Lo).max() / Sd:.3e}")
-    assert np.abs(Lo).max() > 0.1 * Sd
+    assert np.abs(Lo).max() > 1e-2 * Sd          # the samples reach the pulse
     assert err <= 1e-5 * Sd
 
 

@@ -306,3 +306,41 @@ def test_alpha_propagates_nan(oracle_mod):
     Q[0, 3, 4] = np.nan
     a = oracle_mod.Oracle(case).alpha(Q)
     assert np.isnan(a[0]) and np.isnan(a[1])
+
+
+def test_totals_of_uniform_state(oracle_mod):
+    # 32^2 cells of h^2 = 1/1024 on the unit box: the totals are the far-field densities
+    case = W.periodic_box(dim=2, n=32, scheme="teno5", prim_inf=(1.3, 0.25, -0.5, 0.0, 0.9))
+    t = oracle_mod.Oracle(case).totals(W.uniform_state(case))
+    E = 0.9 / 0.4 + 0.5 * 1.3 * (0.25 ** 2 + 0.5 ** 2)
+    # a sum of 1024 equal terms in cell order: at most 1024 roundings of 2^-53 each
+    np.testing.assert_allclose(t, [1.3, 1.3 * 0.25, -1.3 * 0.5, E], rtol=1024 * 2.0 ** -53)
+
+
+def test_dilatation_of_affine_velocity_is_exact_inside(oracle_mod):
+    # the fourth-order central difference is exact on polynomials of degree <= 4: an affine
+    # velocity has div u = trace(B) at every cell two or more cells from a zero-gradient edge
+    case = W.periodic_box(dim=2, n=24, scheme="teno5").with_(
+        bc=(("extrap", "extrap"), ("extrap", "extrap"), ("periodic", "periodic")))
+    x, y = W.centres(case)
+    rho = 1.0 + 0.1 * x
+    u = 0.1 + 0.02 * x - 0.03 * y
+    v = -0.05 + 0.01 * x + 0.04 * y
+    Q = W.conserved(case, rho, [u, v], np.full(case.shape, 0.7))
+    div = oracle_mod.Oracle(case).dilatation(Q)
+    np.testing.assert_allclose(div[2:-2, 2:-2], 0.06, rtol=0, atol=1e-12)
+    assert abs(div[0, 0] - 0.06) > 1e-3          # the clamped ghosts change the edge cells
+
+
+def test_dilatation_fourth_order_on_periodic_field(oracle_mod):
+    errs = []
+    for n in (16, 32, 64):
+        case = W.periodic_box(dim=2, n=n, scheme="teno5")
+        x, y = W.centres(case)
+        u = 0.1 * np.sin(2 * np.pi * x)
+        v = 0.03 * np.cos(2 * np.pi * y)
+        Q = W.conserved(case, np.ones(case.shape), [u, v], np.full(case.shape, 0.7))
+        exact = 0.2 * np.pi * np.cos(2 * np.pi * x) - 0.06 * np.pi * np.sin(2 * np.pi * y)
+        errs.append(np.abs(oracle_mod.Oracle(case).dilatation(Q) - exact).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 3.8), rates
