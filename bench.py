@@ -12,7 +12,7 @@ FP32 precision form and in the FP32 + learned-selector form (network trained fir
 process, by the library's own kernels from short FP64 runs of smaller cases), each timed
 over the run with the acoustic pressure sampled at the 360 probes every 10 steps; each
 variant's probe signal is compared with the FP64 run's (the FP64 path matches the CPU
-oracle to 1e-12).
+oracle to 1e-12).  The learned form is also run with the selector evaluated once per step.
 
 Prints one JSON line.  Metric: cell-stage updates per second (cells x 3 stages x steps /
 wall time).  roofline: the fused stage kernel, whose launches are bracketed by HIP events on
@@ -141,13 +141,15 @@ def variants(case, Q0, nsteps, every=10):
     # crossed within the run (the same computation; only the sampled points differ)
     near = case.with_(probes=W.ring_probes(case.probes.shape[1], 10.0))
     runs = {}
-    for name, prec, n in (("fp64", "fp64", None), ("mixed32", "mixed32", None), ("learned32", "learned32", net)):
-        w, dp, fr = full_run(case.with_(precision=prec), Q0, nsteps, every, n)
-        _, dpn, _ = full_run(near.with_(precision=prec), Q0, nsteps, every, n)
+    forms = (("fp64", "fp64", None, 1), ("mixed32", "mixed32", None, 1), ("learned32", "learned32", net, 1),
+             ("learned32_stride3", "learned32", net, 3))
+    for name, prec, n, stride in forms:
+        w, dp, fr = full_run(case.with_(precision=prec, extra={"selector_stride": stride}), Q0, nsteps, every, n)
+        _, dpn, _ = full_run(near.with_(precision=prec, extra={"selector_stride": stride}), Q0, nsteps, every, n)
         runs[name] = (w, dp, dpn, fr)
     w64, dp64, dpn64, _ = runs["fp64"]
     res["fp64"] = {"value": round(cs / w64 / 1e6, 3), "ms_per_step": round(w64 / nsteps * 1e3, 4)}
-    for name in ("mixed32", "learned32"):
+    for name in ("mixed32", "learned32", "learned32_stride3"):
         w, dp, dpn, fr = runs[name]
         e = {
             "value": round(cs / w / 1e6, 3),
@@ -156,17 +158,52 @@ def variants(case, Q0, nsteps, every=10):
             "acoustic_err_r50": float(torch.linalg.norm(dp - dp64) / torch.linalg.norm(dp64)),
             "acoustic_err_r10": float(torch.linalg.norm(dpn - dpn64) / torch.linalg.norm(dpn64)),
         }
-        if name == "learned32":
+        if name.startswith("learned32"):
             e["significant_side_frac"] = round(fr["significant"], 4)
             e["fallback_side_frac"] = round(fr["fallback"], 4)
-            e["training"] = {"harvested_sides": int(F.shape[0]), "adam_steps": 4000,
-                             "final_loss": round(losses[-1], 4), "seconds": round(t_train, 1)}
+            if name == "learned32":
+                e["training"] = {"harvested_sides": int(F.shape[0]), "adam_steps": 4000,
+                                 "final_loss": round(losses[-1], 4), "seconds": round(t_train, 1)}
+            else:
+                e["note"] = "keep patterns from each step's first stage, reused by its other two stages"
         res[name] = e
     res["run"] = {"steps": nsteps, "probes": int(dp64.shape[1]), "probe_every": every,
                   "max_probe_dp_r50": float(dp64.abs().max()), "max_probe_dp_r10": float(dpn64.abs().max()),
                   "note": "whole run from the uniform start, probe launches included in the timing (the r50 "
                           "run's); errors are relative L2 over probes x samples against the FP64 run"}
     return res
+
+
+def three_d(steps=3):
+    """Rates of the 3D path on the sphere cases (256^3 FP64 in both schemes, 384^3 precision
+    form): `steps` steps after one warm-up step, inputs resident on the device."""
+    import torch
+
+    from paper_1905_00182_amd import fsa
+    from paper_1905_00182_amd import workloads as W
+
+    out = {}
+    for name, case in (("c3_256_teno5_fp64", W.config3(n=256, scheme="teno5")),
+                       ("c3_256_weno5js_fp64", W.config3(n=256, scheme="weno5js")),
+                       ("c4_384_teno5_mixed32", W.config4(n=384))):
+        Q = torch.from_numpy(W.config3_state(case)).cuda()
+        s = fsa.Solver(case)
+        s.rk3_steps(Q, case.dt, 1)
+        s.timing(True)
+        s.timing_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.rk3_steps(Q, case.dt, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms, nl = s.timing_read()
+        s.close()
+        out[name] = {"value": round(case.ncell * 3 * steps / wall / 1e6, 1), "unit": "Mcell-stage/s",
+                     "ms_per_step": round(wall / steps * 1e3, 3),
+                     "stage_kernels_ms_per_stage": round(kms / max(nl, 1), 3)}
+        del Q
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -272,6 +309,7 @@ def main():
     }
     if not args.no_variants:
         out["variants"] = variants(case, Q0, args.variant_steps or case.steps)
+        out["variants"]["three_d"] = three_d()
     if not args.no_cpu and args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
     print(json.dumps(out), flush=True)

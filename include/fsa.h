@@ -91,7 +91,7 @@ typedef struct fsa_desc {
     double   gamma;               /* ratio of specific heats (ideal gas) */
     double   mu;                  /* dynamic viscosity, 1/Re folded in; 0 disables viscosity */
     int32_t  scheme;              /* FSA_WENO5JS or FSA_TENO5 */
-    int32_t  precision;           /* FSA_FP64 or FSA_MIXED32 */
+    int32_t  precision;           /* FSA_FP64, FSA_MIXED32 or FSA_LEARNED32 */
     int32_t  terms;               /* FSA_TERM_* mask */
     int32_t  nan_check;           /* 1: report non-finite wave speeds as FSA_ENONFINITE */
     double   weno_eps;            /* WENO5-JS epsilon (1e-6) */
@@ -104,6 +104,9 @@ typedef struct fsa_desc {
     double   sponge_sigma;        /* sigma_max */
     double   ib_alpha;            /* penalty constant on the integral term, Eq. (7) */
     double   ib_beta;             /* penalty constant on the proportional term, Eq. (7) */
+    int32_t  selector_stride;     /* learned form: 1 (or 0) = keep patterns from every stage's
+                                     state; 3 = from each step's first stage, reused by its
+                                     other two stages.  Other values: FSA_EINVAL */
 } fsa_desc;
 
 typedef struct fsa_ctx fsa_ctx;

@@ -153,6 +153,10 @@ int validate(const fsa_desc* d, std::string& why)
         return FSA_EINVAL;
     }
     if (d->dim == 3 && d->precision == FSA_LEARNED32) { why = "the learned form is built for 2D"; return FSA_EUNSUPPORTED; }
+    if (d->selector_stride != 0 && d->selector_stride != 1 && d->selector_stride != 3) {
+        why = "selector_stride must be 0, 1 or 3";
+        return FSA_EINVAL;
+    }
     if (!(d->prim_inf[0] > 0.0) || !(d->prim_inf[4] > 0.0)) { why = "far field must have rho, p > 0"; return FSA_EINVAL; }
     return FSA_OK;
 }
@@ -394,8 +398,12 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     }
     if (c->d.precision == FSA_LEARNED32) {
         if (!c->mlp_ready) return fail(c, FSA_ESTATE, "learned form without a network (fsa_mlp_set)");
-        int rc = enqueue_flags(c, Qs, bits, c->flags_x, c->flags_y);
-        if (rc != FSA_OK) return rc;
+        // stage 0 = a lone right-hand side; stages 2 and 3 reuse the first stage's patterns
+        // when the selector stride is 3
+        if (stage <= 1 || c->d.selector_stride != 3) {
+            int rc = enqueue_flags(c, Qs, bits, c->flags_x, c->flags_y);
+            if (rc != FSA_OK) return rc;
+        }
     }
     StageArgs S;
     std::memset(&S, 0, sizeof S);

@@ -51,6 +51,7 @@ class FsaDesc(C.Structure):
         ("sponge_sigma", C.c_double),
         ("ib_alpha", C.c_double),
         ("ib_beta", C.c_double),
+        ("selector_stride", C.c_int32),
     ]
 
 
@@ -139,6 +140,7 @@ def make_desc(case, nan_check=False) -> FsaDesc:
     d.precision = PRECISION[case.precision]
     d.terms = case.terms
     d.nan_check = 1 if nan_check else 0
+    d.selector_stride = int(case.extra.get("selector_stride", 1))
     d.weno_eps = case.weno_eps
     d.teno_ct = case.teno_ct
     d.teno_eps = case.teno_eps

@@ -277,7 +277,7 @@ def test_training_reduces_loss(trained):
     assert trained["conf"] > 0.6 and trained["accc"] > 0.95
 
 
-def _learned_vs_oracle(torch, case, Q0, theta, nsteps):
+def _learned_vs_oracle(torch, case, Q0, theta, nsteps, stride=1):
     from oracle.oracle import Oracle
 
     o = Oracle(case)
@@ -289,7 +289,7 @@ def _learned_vs_oracle(torch, case, Q0, theta, nsteps):
     dpo = np.array(dpo)
     res = {}
     for prec in ("mixed32", "learned32"):
-        sv = _solver(case.with_(precision=prec))
+        sv = _solver(case.with_(precision=prec, extra={"selector_stride": stride}))
         if prec == "learned32":
             sv.mlp_set(theta, 0.8)
         Q = torch.from_numpy(Q0.copy()).cuda()
@@ -302,19 +302,21 @@ def _learned_vs_oracle(torch, case, Q0, theta, nsteps):
         st = sv.stats()
         n = max(st.learned_sides, 1)
         res[prec] = (np.linalg.norm(dp - dpo) / np.linalg.norm(dpo), st.significant_sides / n, st.fallback_sides / n)
-    _say(f"{case.name} {case.n[:2]}, {nsteps} steps: e_p precision form {res['mixed32'][0]:.3e}, "
+    _say(f"{case.name} {case.n[:2]}, {nsteps} steps, selector stride {stride}: e_p precision form {res['mixed32'][0]:.3e}, "
          f"learned {res['learned32'][0]:.3e} (significant {res['learned32'][1]:.4f}, fallback "
          f"{res['learned32'][2]:.4f} of face sides); probe |dp| up to {np.abs(dpo).max():.2e}")
     return res
 
 
-def test_learned_acoustic_error_config1(torch_cuda, trained):
+@pytest.mark.parametrize("stride", [1, 3])
+def test_learned_acoustic_error_config1(torch_cuda, trained, stride):
     c = trained["c1"]
-    res = _learned_vs_oracle(torch_cuda, c, W.config1_state(c), trained["theta"], c.steps)
+    res = _learned_vs_oracle(torch_cuda, c, W.config1_state(c), trained["theta"], c.steps, stride)
     assert res["learned32"][0] < 1e-2
 
 
-def test_learned_acoustic_error_config2_small(torch_cuda, trained):
+@pytest.mark.parametrize("stride", [1, 3])
+def test_learned_acoustic_error_config2_small(torch_cuda, trained, stride):
     c = trained["c2"]
-    res = _learned_vs_oracle(torch_cuda, c, W.config2_state(c), trained["theta"], 150)
+    res = _learned_vs_oracle(torch_cuda, c, W.config2_state(c), trained["theta"], 150, stride)
     assert res["learned32"][0] < 1e-2
