@@ -32,6 +32,7 @@ struct fsa_ctx {
     unsigned long long* abits = nullptr; // alpha slots: [4][3]
     unsigned long long* apart = nullptr; // per-block / per-wave partial maxima [apart_n][3]
     unsigned char* stress3d = nullptr;   // 3D: tau and b with two ghost layers, [9][ext cells] of T
+    unsigned char* faces3d = nullptr;    // 3D: face fluxes of the three directions, [5][faces] of T
     double* tot_part = nullptr;          // diagnostics: per-block partial totals
     double* tot_out = nullptr;
     long long apart_n = 0;
@@ -431,7 +432,7 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
             if (rc != FSA_OK) return rc;
             HIPCHK(c, hipEventRecord(t0, c->stream));
         }
-        e = launch_stage3d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stress3d, c->stream);
+        e = launch_stage3d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stress3d, c->faces3d, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "3D stage launch");
         if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
         if (acc >= 0) {
@@ -615,7 +616,8 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
     }
     if (c->G.dim == 3) {
         const size_t tsize = desc->precision == FSA_MIXED32 ? sizeof(float) : sizeof(double);
-        if ((rc = dalloc(c, c->stress3d, (size_t)stress3d_elems(c->G) * tsize)) != FSA_OK) {
+        if ((rc = dalloc(c, c->stress3d, (size_t)stress3d_elems(c->G) * tsize)) != FSA_OK ||
+            (rc = dalloc(c, c->faces3d, (size_t)faces3d_elems(c->G) * tsize)) != FSA_OK) {
             fsa_destroy(c);
             return rc;
         }
@@ -668,6 +670,7 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->abits);
     dfree(c->apart);
     dfree(c->stress3d);
+    dfree(c->faces3d);
     dfree(c->tot_part);
     dfree(c->tot_out);
     dfree(c->X);

@@ -51,10 +51,12 @@ struct IBArgs {
 int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, hipStream_t s);
 long long stage2d_waves(const Grid& G, int ty);
 // 3D: stress pass into `stress` ([9][(nx+4)(ny+4)(nz+4)] of T = double, or float in the
-// precision form), then the stage pass; one wave-speed partial per block of the stage pass.
+// precision form), face-flux passes into `faces` (faces3d_elems of T), then the stage pass;
+// one wave-speed partial per block of the stage pass.
 int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, void* stress,
-                   hipStream_t s);
+                   void* faces, hipStream_t s);
 long long stress3d_elems(const Grid& G);
+long long faces3d_elems(const Grid& G);
 long long stage3d_blocks(const Grid& G);
 int stage2d_ncolx(int nx);
 // Wave speeds max over cells of |u_d| + c of Q into bits[3]: per-block partials in part

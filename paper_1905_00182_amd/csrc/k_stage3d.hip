@@ -4,12 +4,12 @@
 //    gradients by the fourth-order central difference (Sec. 2, Eqs. (5)-(6)), the Stokes
 //    stress tau and b = u . tau, stored as nine components [9][ext cells] (tau_xx, tau_yy,
 //    tau_zz, tau_xy, tau_xz, tau_yz, b_x, b_y, b_z).
-//  * k_stage3d: per interior cell, along each direction the seven cells i-3..i+3 give the
-//    split fluxes f+- = (F +- alpha Q)/2 of the five components, from which both faces
-//    i-1/2 and i+1/2 are reconstructed (so a face is computed by the two cells it bounds, by
-//    the same code on the same inputs: the flux difference still telescopes exactly); the
-//    viscous divergence comes from the stress buffer; then the penalty-IB source from the
-//    window array, the sponge, the RK3 combination, and one wave-speed partial per block.
+//  * k_faces3d<D>: one thread per face along direction D: the six cells i-2..i+3 give the
+//    split fluxes f+- = (F +- alpha Q)/2 of the five components and the face flux
+//    F^ = rec+(f+) + rec-(f-), stored per component [5][faces] (each face once).
+//  * k_stage3d: per interior cell, the flux differences of the three face buffers, the
+//    viscous divergence from the stress buffer, the penalty-IB source from the window
+//    array, the sponge, the RK3 combination, and one wave-speed partial per block.
 //
 // Threads of a block are 64 consecutive x cells by 4 rows, so every load along x is
 // coalesced; neighbours along y and z come through the caches.  Arithmetic type T as in 2D:
@@ -143,17 +143,53 @@ __device__ __forceinline__ float rec(float a, float b, float c, float d, float e
     return recon5f<SCHEME>(a, b, c, d, e, R);
 }
 
-// -(F^_{i+1/2} - F^_{i-1/2}) / h along direction D, added to L.
+// Face index of face f (between cells f-1 and f along D) of the line through (i, j, k):
+// x faces [nz][ny][nx+1], y faces [nz][ny+1][nx], z faces [nz+1][ny][nx].
+template <int D>
+__device__ __forceinline__ long long face_index(const Grid& G, int f, int i, int j, int k)
+{
+    if (D == 0) return ((long long)k * G.n[1] + j) * (G.n[0] + 1) + f;
+    if (D == 1) return ((long long)k * (G.n[1] + 1) + f) * G.n[0] + i;
+    return ((long long)f * G.n[1] + j) * G.n[0] + i;
+}
+
+template <int D>
+__host__ __device__ __forceinline__ long long faces_of(const Grid& G)
+{
+    return (long long)(G.n[0] + (D == 0)) * (G.n[1] + (D == 1)) * (G.n[2] + (D == 2));
+}
+
+// Face fluxes along D: threads cover the faces f = 0..n_D along D (x index for D = 0, y index
+// for D = 1, z index for D = 2) and the cells of the two other directions.
 template <int SCHEME, class T, int D>
-__device__ __forceinline__ void convective(const KConst* K, const double* Q, long long step, int i, int j, int k,
-                                           double alpha, const Recon& R, const Recon32& R32, double* L)
+__global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ K, const double* __restrict__ Q,
+                                                     long long step, const unsigned long long* __restrict__ abits,
+                                                     T* __restrict__ Fh)
 {
     constexpr bool F64 = std::is_same<T, double>::value;
-    double q[7][5], ud[7], p[7];
+    const Grid& G = K->G;
+    const int xi = blockIdx.x * BX + (threadIdx.x & (BX - 1));
+    const int yi = blockIdx.y * BY + (threadIdx.x / BX);
+    const int zi = blockIdx.z;
+    if (xi >= G.n[0] + (D == 0) || yi >= G.n[1] + (D == 1) || zi >= G.n[2] + (D == 2)) return;
+    // cell below the face along D, and the cell coordinates of the line
+    int i = xi, j = yi, k = zi;
+    if (D == 0) i -= 1;
+    else if (D == 1) j -= 1;
+    else k -= 1;
+    const int f = D == 0 ? xi : (D == 1 ? yi : zi);
+    const double alpha = __longlong_as_double((long long)abits[D]);
+    Recon R;
+    R.eps = SCHEME == WENO5JS ? K->P.weno_eps : K->P.teno_eps;
+    R.ct = K->P.teno_ct;
+    Recon32 R32;
+    R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;
+    R32.ct = (float)K->P.teno_ct;
+    double q[6][5], ud[6], p[6];
 #pragma unroll
-    for (int s = 0; s < 7; ++s) {
+    for (int s = 0; s < 6; ++s) {
         int ii = i, jj = j, kk = k;
-        offset<D>(ii, jj, kk, s - 3);
+        offset<D>(ii, jj, kk, s - 2);
         cell_state(K, Q, step, ii, jj, kk, q[s]);
         const double ir = rcp_nr(q[s][0]);
         const double u = q[s][1] * ir, v = q[s][2] * ir, w = q[s][3] * ir;
@@ -161,12 +197,13 @@ __device__ __forceinline__ void convective(const KConst* K, const double* Q, lon
         ud[s] = D == 0 ? u : (D == 1 ? v : w);
     }
     const double* Finf = D == 0 ? K->Fx_inf : (D == 1 ? K->Fy_inf : K->Fz_inf);
-    const T inv_h = (T)K->G.inv_h;
+    const long long nf = faces_of<D>(G);
+    const long long o = face_index<D>(G, f, D == 0 ? 0 : xi, D == 1 ? 0 : yi, D == 2 ? 0 : zi);
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        T fp[7], fm[7];
+        T fp[6], fm[6];
 #pragma unroll
-        for (int s = 0; s < 7; ++s) {
+        for (int s = 0; s < 6; ++s) {
             double F;
             if (c == 0) F = q[s][1 + D];
             else if (c == 4) F = (q[s][4] + p[s]) * ud[s];
@@ -181,18 +218,15 @@ __device__ __forceinline__ void convective(const KConst* K, const double* Q, lon
                 fm[s] = (T)(0.5 * fma(-alpha, dq, dF));
             }
         }
-        // faces i-1/2 (cells 0..5) and i+1/2 (cells 1..6), each by the same expression
-        T fh[2];
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-            fh[f] = rec<SCHEME>(fp[f], fp[f + 1], fp[f + 2], fp[f + 3], fp[f + 4], R, R32) +
-                    rec<SCHEME>(fm[f + 5], fm[f + 4], fm[f + 3], fm[f + 2], fm[f + 1], R, R32);
-        L[c] += (double)(-(fh[1] - fh[0]) * inv_h);
+        Fh[c * nf + o] = rec<SCHEME>(fp[0], fp[1], fp[2], fp[3], fp[4], R, R32) +
+                         rec<SCHEME>(fm[5], fm[4], fm[3], fm[2], fm[1], R, R32);
     }
 }
 
-template <int SCHEME, class T>
-__global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ K, StageArgs A, const T* __restrict__ S)
+template <class T>
+__global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ K, StageArgs A, const T* __restrict__ S,
+                                                     const T* __restrict__ Fx, const T* __restrict__ Fy,
+                                                     const T* __restrict__ Fz)
 {
     const Grid& G = K->G;
     const int i = blockIdx.x * BX + (threadIdx.x & (BX - 1));
@@ -202,22 +236,25 @@ __global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ 
     const int terms = K->P.terms;
     unsigned long long am[3] = {0ull, 0ull, 0ull};
     if (inside) {
-        Recon R;
-        R.eps = SCHEME == WENO5JS ? K->P.weno_eps : K->P.teno_eps;
-        R.ct = K->P.teno_ct;
-        Recon32 R32;
-        R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;
-        R32.ct = (float)K->P.teno_ct;
         double L[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        if (terms & T_CONVX)
-            convective<SCHEME, T, 0>(K, A.Qs, A.step, i, j, k, __longlong_as_double((long long)A.alpha_bits[0]), R,
-                                     R32, L);
-        if (terms & T_CONVY)
-            convective<SCHEME, T, 1>(K, A.Qs, A.step, i, j, k, __longlong_as_double((long long)A.alpha_bits[1]), R,
-                                     R32, L);
-        if (terms & T_CONVZ)
-            convective<SCHEME, T, 2>(K, A.Qs, A.step, i, j, k, __longlong_as_double((long long)A.alpha_bits[2]), R,
-                                     R32, L);
+        const T inv_h = (T)G.inv_h;
+        // -(F^_{i+1/2} - F^_{i-1/2}) / h per direction, each face read from its buffer
+        if (terms & T_CONVX) {
+            const long long nf = faces_of<0>(G), o = face_index<0>(G, i, 0, j, k);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) L[c] += (double)(-(Fx[c * nf + o + 1] - Fx[c * nf + o]) * inv_h);
+        }
+        if (terms & T_CONVY) {
+            const long long nf = faces_of<1>(G), o = face_index<1>(G, j, i, 0, k), st = G.n[0];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) L[c] += (double)(-(Fy[c * nf + o + st] - Fy[c * nf + o]) * inv_h);
+        }
+        if (terms & T_CONVZ) {
+            const long long nf = faces_of<2>(G), o = face_index<2>(G, k, i, j, 0);
+            const long long st = (long long)G.n[0] * G.n[1];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) L[c] += (double)(-(Fz[c * nf + o + st] - Fz[c * nf + o]) * inv_h);
+        }
         if (terms & T_VISC) {
             // momentum a: sum_b D_b(tau_ab); energy: sum_b D_b(b_b)
             const int ex = G.n[0] + 4, ey = G.n[1] + 4, ez = G.n[2] + 4;
@@ -326,22 +363,52 @@ long long stage3d_blocks(const Grid& G)
     return (long long)((G.n[0] + BX - 1) / BX) * ((G.n[1] + BY - 1) / BY) * G.n[2];
 }
 
+long long faces3d_elems(const Grid& G)
+{
+    return 5ll * (faces_of<0>(G) + faces_of<1>(G) + faces_of<2>(G));
+}
+
+template <int SCHEME, class T>
+static void launch_faces(const KConst* K, const Grid& G, const StageArgs& A, T* F, hipStream_t s)
+{
+    const dim3 block(BX * BY);
+    T* Fx = F;
+    T* Fy = Fx + 5 * faces_of<0>(G);
+    T* Fz = Fy + 5 * faces_of<1>(G);
+    hipLaunchKernelGGL((k_faces3d<SCHEME, T, 0>), dim3((G.n[0] + 1 + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]),
+                       block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx);
+    hipLaunchKernelGGL((k_faces3d<SCHEME, T, 1>), dim3((G.n[0] + BX - 1) / BX, (G.n[1] + 1 + BY - 1) / BY, G.n[2]),
+                       block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fy);
+    hipLaunchKernelGGL((k_faces3d<SCHEME, T, 2>), dim3((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2] + 1),
+                       block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fz);
+}
+
 int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, void* stress,
-                   hipStream_t s)
+                   void* faces, hipStream_t s)
 {
     const dim3 block(BX * BY);
     const dim3 gs((G.n[0] + 4 + BX - 1) / BX, (G.n[1] + 4 + BY - 1) / BY, G.n[2] + 4);
     const dim3 gr((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
     if (precision == 1) {
         float* S = static_cast<float*>(stress);
+        float* F = static_cast<float*>(faces);
         hipLaunchKernelGGL(k_stress3d<float>, gs, block, 0, s, K, A.Qs, A.step, S);
-        if (scheme == TENO5) hipLaunchKernelGGL((k_stage3d<TENO5, float>), gr, block, 0, s, K, A, (const float*)S);
-        else hipLaunchKernelGGL((k_stage3d<WENO5JS, float>), gr, block, 0, s, K, A, (const float*)S);
+        if (scheme == TENO5) launch_faces<TENO5, float>(K, G, A, F, s);
+        else launch_faces<WENO5JS, float>(K, G, A, F, s);
+        const float* Fx = F;
+        const float* Fy = Fx + 5 * faces_of<0>(G);
+        const float* Fz = Fy + 5 * faces_of<1>(G);
+        hipLaunchKernelGGL(k_stage3d<float>, gr, block, 0, s, K, A, (const float*)S, Fx, Fy, Fz);
     } else {
         double* S = static_cast<double*>(stress);
+        double* F = static_cast<double*>(faces);
         hipLaunchKernelGGL(k_stress3d<double>, gs, block, 0, s, K, A.Qs, A.step, S);
-        if (scheme == TENO5) hipLaunchKernelGGL((k_stage3d<TENO5, double>), gr, block, 0, s, K, A, (const double*)S);
-        else hipLaunchKernelGGL((k_stage3d<WENO5JS, double>), gr, block, 0, s, K, A, (const double*)S);
+        if (scheme == TENO5) launch_faces<TENO5, double>(K, G, A, F, s);
+        else launch_faces<WENO5JS, double>(K, G, A, F, s);
+        const double* Fx = F;
+        const double* Fy = Fx + 5 * faces_of<0>(G);
+        const double* Fz = Fy + 5 * faces_of<1>(G);
+        hipLaunchKernelGGL(k_stage3d<double>, gr, block, 0, s, K, A, (const double*)S, Fx, Fy, Fz);
     }
     return (int)hipGetLastError();
 }

@@ -1,0 +1,91 @@
+"""Error behaviour of the C ABI as declared in include/fsa.h: invalid descriptors, arguments and
+call orders return their status codes (raised by the binding as FsaError) and leave the
+context usable."""
+import numpy as np
+import pytest
+
+from paper_1905_00182_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fsa_mod():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_1905_00182_amd import fsa
+
+    return fsa
+
+
+def _box(dim=2, n=24, **kw):
+    c = W.periodic_box(dim=dim, n=n, scheme="teno5", mu=0.003)
+    return c.with_(**kw) if kw else c
+
+
+@pytest.mark.parametrize("change, code", [
+    ({"gamma": 1.0}, "EINVAL"),
+    ({"mu": -1.0}, "EINVAL"),
+    ({"bc": (("periodic", "extrap"), ("periodic", "periodic"), ("periodic", "periodic"))}, "EINVAL"),
+    ({"sponge_width": ((-1.0, 0.0), (0.0, 0.0), (0.0, 0.0))}, "EINVAL"),
+    ({"prim_inf": (0.0, 0.0, 0.0, 0.0, 1.0)}, "EINVAL"),
+    ({"extra": {"selector_stride": 2}}, "EINVAL"),
+])
+def test_invalid_descriptor(fsa_mod, change, code):
+    with pytest.raises(fsa_mod.FsaError) as e:
+        fsa_mod.Solver(_box(**change))
+    assert e.value.code == getattr(fsa_mod, code)
+
+
+def test_learned_form_in_3d_unsupported(fsa_mod):
+    with pytest.raises(fsa_mod.FsaError) as e:
+        fsa_mod.Solver(_box(dim=3, n=12, precision="learned32"))
+    assert e.value.code == fsa_mod.EUNSUPPORTED
+
+
+def test_argument_and_order_errors(fsa_mod):
+    import torch
+
+    case = _box()
+    s = fsa_mod.Solver(case)
+    Q = torch.from_numpy(W.perturbed_state(case, seed=1, amp=1e-2)).cuda()
+    lib = fsa_mod.lib()
+    p = fsa_mod._ptr(Q)
+    assert lib.fsa_rhs(s.ctx, p, p) == fsa_mod.EINVAL                    # output aliases input
+    assert lib.fsa_rk3_steps(s.ctx, p, 0.0, 1) == fsa_mod.EINVAL          # dt must be positive
+    assert lib.fsa_rk3_steps(s.ctx, p, case.dt, 0) == fsa_mod.EINVAL      # nsteps must be positive
+    assert lib.fsa_diagnostics(s.ctx, p, None, None) == fsa_mod.EINVAL    # nothing requested
+    assert lib.fsa_mlp_get(s.ctx, np.zeros(fsa_mod.MLP_NPARAM, np.float32).ctypes.data,
+                           fsa_mod.MLP_NPARAM) == fsa_mod.ESTATE          # no network yet
+    with pytest.raises(fsa_mod.FsaError) as e:
+        s.mlp_set(np.zeros(fsa_mod.MLP_NPARAM), conf_threshold=1.5)
+    assert e.value.code == fsa_mod.EINVAL
+    # the context still works after the rejected calls
+    L = s.rhs(Q)
+    s.sync()
+    assert torch.isfinite(L).all()
+
+
+def test_learned_form_needs_a_network(fsa_mod):
+    import torch
+
+    case = _box(precision="learned32")
+    s = fsa_mod.Solver(case)
+    Q = torch.from_numpy(W.uniform_state(case)).cuda()
+    with pytest.raises(fsa_mod.FsaError) as e:
+        s.rk3_step(Q, case.dt)
+    assert e.value.code == fsa_mod.ESTATE
+
+
+def test_harvest_in_3d_unsupported(fsa_mod):
+    import torch
+
+    case = _box(dim=3, n=12)
+    s = fsa_mod.Solver(case)
+    Q = torch.from_numpy(W.uniform_state(case)).cuda()
+    with pytest.raises(fsa_mod.FsaError) as e:
+        s.harvest(Q, 1.0, 1, 16)
+    assert e.value.code == fsa_mod.EUNSUPPORTED
