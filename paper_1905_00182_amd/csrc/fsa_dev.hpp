@@ -177,7 +177,28 @@ __device__ __forceinline__ double recon5(double a, double b, double c, double d,
 struct Recon32 {
     float eps;
     float ct;
+    const float4* wtab;   // TENO5 / learned: normalised weights of the 8 keep patterns (in LDS)
 };
+
+// Normalised linear weights d_k / (sum of the kept d_j), d = (0.1, 0.6, 0.3), of keep pattern
+// p (bit k = sub-stencil k kept), each rounded once to FP32; p = 0 does not occur and holds
+// the full set.  Lanes 0..7 of a block write the table; the block synchronises before use.
+__device__ __forceinline__ void init_keep_weights(float4* t, int tid)
+{
+    if (tid < 8) {
+        float4 w;
+        switch (tid) {
+        case 1: w = make_float4(1.0f, 0.0f, 0.0f, 0.0f); break;
+        case 2: w = make_float4(0.0f, 1.0f, 0.0f, 0.0f); break;
+        case 3: w = make_float4(1.0f / 7.0f, 6.0f / 7.0f, 0.0f, 0.0f); break;
+        case 4: w = make_float4(0.0f, 0.0f, 1.0f, 0.0f); break;
+        case 5: w = make_float4(0.25f, 0.0f, 0.75f, 0.0f); break;
+        case 6: w = make_float4(0.0f, 2.0f / 3.0f, 1.0f / 3.0f, 0.0f); break;
+        default: w = make_float4(0.1f, 0.6f, 0.3f, 0.0f); break;
+        }
+        t[tid] = w;
+    }
+}
 
 template <int SCHEME>
 __device__ __forceinline__ float recon5f(float a, float b, float c, float d, float e, const Recon32& R)
@@ -208,27 +229,22 @@ __device__ __forceinline__ float recon5f(float a, float b, float c, float d, flo
         const float c0 = x0 * x0 * x0, c1 = x1 * x1 * x1, c2 = x2 * x2 * x2;
         const float g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2;
         const float lim = R.ct * (g0 + g1 + g2);
-        const float d0 = g0 < lim ? 0.0f : 1.0f;
-        const float d1 = g1 < lim ? 0.0f : 6.0f;
-        const float d2 = g2 < lim ? 0.0f : 3.0f;
-        const float num = fmaf(d0, q0, fmaf(d1, q1, d2 * q2));
-        return num * __builtin_amdgcn_rcpf(d0 + d1 + d2);
+        const int keep = (g0 < lim ? 0 : 1) | (g1 < lim ? 0 : 2) | (g2 < lim ? 0 : 4);
+        const float4 w = R.wtab[keep];
+        return fmaf(w.x, q0, fmaf(w.y, q1, w.z * q2));
     }
 }
 
-// FP32 reconstruction with the sub-stencils given by keep bits (bit k = sub-stencil k): the
-// learned form.  The weighted sum is the same expression as recon5f's TENO5 branch, so all
-// bits set reproduces it exactly.
-__device__ __forceinline__ float recon5_bits(float a, float b, float c, float d, float e, int bits)
+// FP32 reconstruction with the sub-stencils given by keep bits (bit k = sub-stencil k, 1..7):
+// the learned form.  The weighted sum is the same expression as recon5f's TENO5 branch, so the
+// same bits give the same value.
+__device__ __forceinline__ float recon5_bits(float a, float b, float c, float d, float e, int bits, const float4* wtab)
 {
     const float q0 = fmaf(11.0f / 6.0f, c, fmaf(-7.0f / 6.0f, b, (1.0f / 3.0f) * a));
     const float q1 = fmaf(1.0f / 3.0f, d, fmaf(5.0f / 6.0f, c, (-1.0f / 6.0f) * b));
     const float q2 = fmaf(-1.0f / 6.0f, e, fmaf(5.0f / 6.0f, d, (1.0f / 3.0f) * c));
-    const float d0 = (bits & 1) ? 1.0f : 0.0f;
-    const float d1 = (bits & 2) ? 6.0f : 0.0f;
-    const float d2 = (bits & 4) ? 3.0f : 0.0f;
-    const float num = fmaf(d0, q0, fmaf(d1, q1, d2 * q2));
-    return num * __builtin_amdgcn_rcpf(d0 + d1 + d2);
+    const float4 w = wtab[bits];
+    return fmaf(w.x, q0, fmaf(w.y, q1, w.z * q2));
 }
 
 // ---------------------------------------------------------------------------------------

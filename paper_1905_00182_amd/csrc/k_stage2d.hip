@@ -90,12 +90,15 @@ __device__ __forceinline__ T recon_side(T a, T b, T c, T d, T e, const Recon& R,
     if constexpr (SCHEME == LEARNED) {
         (void)R;
         (void)R32;
-        return recon5_bits(a, b, c, d, e, bits);
+        return recon5_bits(a, b, c, d, e, bits, R32.wtab);
     } else {
         (void)bits;
         return recon<SCHEME>(a, b, c, d, e, R, R32);
     }
 }
+
+template <class T>
+constexpr bool F64v = std::is_same<T, double>::value;
 
 template <int SCHEME, class T>
 struct Column2D {
@@ -370,6 +373,11 @@ template <int SCHEME, class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_stage2d(
     const KConst* __restrict__ K, StageArgs A)
 {
+    __shared__ float4 wtab[8];
+    if (!F64v<T>) {
+        init_keep_weights(wtab, threadIdx.x);
+        __syncthreads();
+    }
     Column2D<SCHEME, T> C;
     C.K = K;
     C.Qs = A.Qs;
@@ -395,6 +403,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.R.ct = K->P.teno_ct;
     C.R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;   // FP32 TENO5 epsilon
     C.R32.ct = (float)K->P.teno_ct;
+    C.R32.wtab = wtab;
     C.ca = A.ca;
     C.cb = A.cb;
     C.dt = A.dt;
@@ -416,6 +425,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
     __shared__ double ring[5][4][WAVE];
     __shared__ T vring[5][3][WAVE];
+
     const int lane = threadIdx.x;
     C.ring = ring;
     C.vring = vring;

@@ -171,6 +171,11 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
     const int xi = blockIdx.x * BX + (threadIdx.x & (BX - 1));
     const int yi = blockIdx.y * BY + (threadIdx.x / BX);
     const int zi = blockIdx.z;
+    __shared__ float4 wtab[8];
+    if (!F64) {
+        init_keep_weights(wtab, threadIdx.x);
+        __syncthreads();
+    }
     if (xi >= G.n[0] + (D == 0) || yi >= G.n[1] + (D == 1) || zi >= G.n[2] + (D == 2)) return;
     // cell below the face along D, and the cell coordinates of the line
     int i = xi, j = yi, k = zi;
@@ -185,6 +190,7 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
     Recon32 R32;
     R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;
     R32.ct = (float)K->P.teno_ct;
+    R32.wtab = wtab;
     double q[6][5], ud[6], p[6];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
