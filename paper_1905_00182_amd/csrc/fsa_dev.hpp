@@ -127,18 +127,58 @@ __device__ __forceinline__ double rcp_nr(double x)
 // weighted WENO5-JS (alpha_k = d_k / (eps + beta_k)^2) or TENO5 (sharp cut-off of
 // gamma_k = (1 + tau5 / (beta_k + eps))^6 at C_T, kept stencils weighted by d_k).
 // Both are evaluated with reciprocals instead of divisions.
+//
+// TENO5's face value is a fixed linear form in (a..e) once the kept set is known: the
+// candidates' coefficients weighted by d_k / (sum of kept d_j).  The eight keep patterns'
+// forms are tabulated per block in LDS (row p, bit k = sub-stencil k kept; p = 0 does not
+// occur and holds the full set), so the face value is one row lookup and five fused
+// multiply-adds instead of three candidates, a weight sum and a reciprocal.
 // ---------------------------------------------------------------------------------------
+template <class T>
+using KeepRows = T[8][8];   // [pattern][coefficient of a..e, 3 unused]
+
+// Fill the table (lanes 0..7 of the block, one row each; the block synchronises before use).
+// Each coefficient is formed in FP64 and rounded once to T.
+template <class T>
+__device__ __forceinline__ void init_keep_rows(KeepRows<T>& t, int tid)
+{
+    if (tid < 8) {
+        const int p = tid == 0 ? 7 : tid;
+        constexpr double dk[3] = {0.1, 0.6, 0.3};
+        constexpr double cand[3][5] = {{1.0 / 3.0, -7.0 / 6.0, 11.0 / 6.0, 0.0, 0.0},
+                                       {0.0, -1.0 / 6.0, 5.0 / 6.0, 1.0 / 3.0, 0.0},
+                                       {0.0, 0.0, 1.0 / 3.0, 5.0 / 6.0, -1.0 / 6.0}};
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sum += ((p >> k) & 1) ? dk[k] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v += ((p >> k) & 1) ? dk[k] * cand[k][j] : 0.0;
+            t[tid][j] = (T)(v / sum);
+        }
+#pragma unroll
+        for (int j = 5; j < 8; ++j) t[tid][j] = T(0);
+    }
+}
+
+// Face value of keep pattern p from its table row.
+template <class T>
+__device__ __forceinline__ T keep_sum(const T* row, T a, T b, T c, T d, T e)
+{
+    return fma(row[4], e, fma(row[3], d, fma(row[2], c, fma(row[1], b, row[0] * a))));
+}
+
 struct Recon {
-    double eps;   // WENO epsilon or TENO epsilon
-    double ct;    // TENO cut-off
+    double eps;                  // WENO epsilon or TENO epsilon
+    double ct;                   // TENO cut-off
+    const double (*rows)[8];     // TENO5: keep-pattern table (LDS)
 };
 
 template <int SCHEME>
 __device__ __forceinline__ double recon5(double a, double b, double c, double d, double e, const Recon& R)
 {
-    const double q0 = fma(11.0 / 6.0, c, fma(-7.0 / 6.0, b, (1.0 / 3.0) * a));
-    const double q1 = fma(1.0 / 3.0, d, fma(5.0 / 6.0, c, (-1.0 / 6.0) * b));
-    const double q2 = fma(-1.0 / 6.0, e, fma(5.0 / 6.0, d, (1.0 / 3.0) * c));
     const double s0 = fma(-2.0, b, a) + c, t0 = fma(-4.0, b, a) + 3.0 * c;
     const double s1 = fma(-2.0, c, b) + d, t1 = b - d;
     const double s2 = fma(-2.0, d, c) + e, t2 = fma(-4.0, d, 3.0 * c) + e;
@@ -146,6 +186,9 @@ __device__ __forceinline__ double recon5(double a, double b, double c, double d,
     const double b1 = fma(13.0 / 12.0 * s1, s1, 0.25 * t1 * t1);
     const double b2 = fma(13.0 / 12.0 * s2, s2, 0.25 * t2 * t2);
     if (SCHEME == WENO5JS) {
+        const double q0 = fma(11.0 / 6.0, c, fma(-7.0 / 6.0, b, (1.0 / 3.0) * a));
+        const double q1 = fma(1.0 / 3.0, d, fma(5.0 / 6.0, c, (-1.0 / 6.0) * b));
+        const double q2 = fma(-1.0 / 6.0, e, fma(5.0 / 6.0, d, (1.0 / 3.0) * c));
         const double e0 = R.eps + b0, e1 = R.eps + b1, e2 = R.eps + b2;
         const double p0 = e0 * e0, p1 = e1 * e1, p2 = e2 * e2;
         // alpha_k proportional to d_k * prod_{j != k} (eps + beta_j)^2
@@ -162,11 +205,8 @@ __device__ __forceinline__ double recon5(double a, double b, double c, double d,
         const double c0 = x0 * x0 * x0, c1 = x1 * x1 * x1, c2 = x2 * x2 * x2;
         const double g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2;
         const double lim = R.ct * (g0 + g1 + g2);
-        const double d0 = g0 < lim ? 0.0 : 0.1;
-        const double d1 = g1 < lim ? 0.0 : 0.6;
-        const double d2 = g2 < lim ? 0.0 : 0.3;
-        const double num = fma(d0, q0, fma(d1, q1, d2 * q2));
-        return num * rcp_nr(d0 + d1 + d2);
+        const int keep = (g0 < lim ? 0 : 1) | (g1 < lim ? 0 : 2) | (g2 < lim ? 0 : 4);
+        return keep_sum(R.rows[keep], a, b, c, d, e);
     }
 }
 
@@ -177,35 +217,12 @@ __device__ __forceinline__ double recon5(double a, double b, double c, double d,
 struct Recon32 {
     float eps;
     float ct;
-    const float4* wtab;   // TENO5 / learned: normalised weights of the 8 keep patterns (in LDS)
+    const float (*rows)[8];   // TENO5 / learned: keep-pattern table (LDS)
 };
-
-// Normalised linear weights d_k / (sum of the kept d_j), d = (0.1, 0.6, 0.3), of keep pattern
-// p (bit k = sub-stencil k kept), each rounded once to FP32; p = 0 does not occur and holds
-// the full set.  Lanes 0..7 of a block write the table; the block synchronises before use.
-__device__ __forceinline__ void init_keep_weights(float4* t, int tid)
-{
-    if (tid < 8) {
-        float4 w;
-        switch (tid) {
-        case 1: w = make_float4(1.0f, 0.0f, 0.0f, 0.0f); break;
-        case 2: w = make_float4(0.0f, 1.0f, 0.0f, 0.0f); break;
-        case 3: w = make_float4(1.0f / 7.0f, 6.0f / 7.0f, 0.0f, 0.0f); break;
-        case 4: w = make_float4(0.0f, 0.0f, 1.0f, 0.0f); break;
-        case 5: w = make_float4(0.25f, 0.0f, 0.75f, 0.0f); break;
-        case 6: w = make_float4(0.0f, 2.0f / 3.0f, 1.0f / 3.0f, 0.0f); break;
-        default: w = make_float4(0.1f, 0.6f, 0.3f, 0.0f); break;
-        }
-        t[tid] = w;
-    }
-}
 
 template <int SCHEME>
 __device__ __forceinline__ float recon5f(float a, float b, float c, float d, float e, const Recon32& R)
 {
-    const float q0 = fmaf(11.0f / 6.0f, c, fmaf(-7.0f / 6.0f, b, (1.0f / 3.0f) * a));
-    const float q1 = fmaf(1.0f / 3.0f, d, fmaf(5.0f / 6.0f, c, (-1.0f / 6.0f) * b));
-    const float q2 = fmaf(-1.0f / 6.0f, e, fmaf(5.0f / 6.0f, d, (1.0f / 3.0f) * c));
     const float s0 = fmaf(-2.0f, b, a) + c, t0 = fmaf(-4.0f, b, a) + 3.0f * c;
     const float s1 = fmaf(-2.0f, c, b) + d, t1 = b - d;
     const float s2 = fmaf(-2.0f, d, c) + e, t2 = fmaf(-4.0f, d, 3.0f * c) + e;
@@ -213,6 +230,9 @@ __device__ __forceinline__ float recon5f(float a, float b, float c, float d, flo
     const float b1 = fmaf(13.0f / 12.0f * s1, s1, 0.25f * t1 * t1);
     const float b2 = fmaf(13.0f / 12.0f * s2, s2, 0.25f * t2 * t2);
     if (SCHEME == WENO5JS) {
+        const float q0 = fmaf(11.0f / 6.0f, c, fmaf(-7.0f / 6.0f, b, (1.0f / 3.0f) * a));
+        const float q1 = fmaf(1.0f / 3.0f, d, fmaf(5.0f / 6.0f, c, (-1.0f / 6.0f) * b));
+        const float q2 = fmaf(-1.0f / 6.0f, e, fmaf(5.0f / 6.0f, d, (1.0f / 3.0f) * c));
         const float e0 = R.eps + b0, e1 = R.eps + b1, e2 = R.eps + b2;
         const float w0 = 0.1f * __builtin_amdgcn_rcpf(e0 * e0);
         const float w1 = 0.6f * __builtin_amdgcn_rcpf(e1 * e1);
@@ -230,21 +250,17 @@ __device__ __forceinline__ float recon5f(float a, float b, float c, float d, flo
         const float g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2;
         const float lim = R.ct * (g0 + g1 + g2);
         const int keep = (g0 < lim ? 0 : 1) | (g1 < lim ? 0 : 2) | (g2 < lim ? 0 : 4);
-        const float4 w = R.wtab[keep];
-        return fmaf(w.x, q0, fmaf(w.y, q1, w.z * q2));
+        return keep_sum(R.rows[keep], a, b, c, d, e);
     }
 }
 
 // FP32 reconstruction with the sub-stencils given by keep bits (bit k = sub-stencil k, 1..7):
-// the learned form.  The weighted sum is the same expression as recon5f's TENO5 branch, so the
-// same bits give the same value.
-__device__ __forceinline__ float recon5_bits(float a, float b, float c, float d, float e, int bits, const float4* wtab)
+// the learned form.  The same table row as recon5f's TENO5 branch, so the same bits give the
+// same value.
+__device__ __forceinline__ float recon5_bits(float a, float b, float c, float d, float e, int bits,
+                                             const float (*rows)[8])
 {
-    const float q0 = fmaf(11.0f / 6.0f, c, fmaf(-7.0f / 6.0f, b, (1.0f / 3.0f) * a));
-    const float q1 = fmaf(1.0f / 3.0f, d, fmaf(5.0f / 6.0f, c, (-1.0f / 6.0f) * b));
-    const float q2 = fmaf(-1.0f / 6.0f, e, fmaf(5.0f / 6.0f, d, (1.0f / 3.0f) * c));
-    const float4 w = wtab[bits];
-    return fmaf(w.x, q0, fmaf(w.y, q1, w.z * q2));
+    return keep_sum(rows[bits], a, b, c, d, e);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -35,7 +35,8 @@ constexpr int WAVE = 64;
 constexpr int OUTW = WAVE - 2 * HALO;   // 56 output columns per wave
 
 // Lane shifts across the whole wave with DPP: wave_shr:1 gives lane i the value of lane i-1,
-// wave_shl:1 the value of lane i+1 (lanes without a source read 0; only halo lanes do).
+// wave_shl:1 the value of lane i+1 (bound_ctrl: lanes without a source read 0, so no old
+// value has to be set up first; only halo lanes read it).
 constexpr int DPP_WAVE_SHR1 = 0x138;
 constexpr int DPP_WAVE_SHL1 = 0x130;
 
@@ -43,14 +44,14 @@ template <int CTRL>
 __device__ __forceinline__ double dpp(double x)
 {
     const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 template <class T>
 __device__ __forceinline__ T lo1(T x) { return dpp<DPP_WAVE_SHR1>(x); }
@@ -90,7 +91,7 @@ __device__ __forceinline__ T recon_side(T a, T b, T c, T d, T e, const Recon& R,
     if constexpr (SCHEME == LEARNED) {
         (void)R;
         (void)R32;
-        return recon5_bits(a, b, c, d, e, bits, R32.wtab);
+        return recon5_bits(a, b, c, d, e, bits, R32.rows);
     } else {
         (void)bits;
         return recon<SCHEME>(a, b, c, d, e, R, R32);
@@ -373,9 +374,9 @@ template <int SCHEME, class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_stage2d(
     const KConst* __restrict__ K, StageArgs A)
 {
-    __shared__ float4 wtab[8];
-    if (!F64v<T>) {
-        init_keep_weights(wtab, threadIdx.x);
+    __shared__ __attribute__((aligned(16))) KeepRows<T> keep_rows;
+    if (SCHEME != WENO5JS) {
+        init_keep_rows<T>(keep_rows, threadIdx.x);
         __syncthreads();
     }
     Column2D<SCHEME, T> C;
@@ -403,7 +404,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.R.ct = K->P.teno_ct;
     C.R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;   // FP32 TENO5 epsilon
     C.R32.ct = (float)K->P.teno_ct;
-    C.R32.wtab = wtab;
+    if constexpr (F64v<T>) {
+        C.R.rows = keep_rows;
+        C.R32.rows = nullptr;
+    } else {
+        C.R.rows = nullptr;
+        C.R32.rows = keep_rows;
+    }
     C.ca = A.ca;
     C.cb = A.cb;
     C.dt = A.dt;

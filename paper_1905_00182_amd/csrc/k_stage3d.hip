@@ -171,9 +171,9 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
     const int xi = blockIdx.x * BX + (threadIdx.x & (BX - 1));
     const int yi = blockIdx.y * BY + (threadIdx.x / BX);
     const int zi = blockIdx.z;
-    __shared__ float4 wtab[8];
-    if (!F64) {
-        init_keep_weights(wtab, threadIdx.x);
+    __shared__ __attribute__((aligned(16))) KeepRows<T> keep_rows;
+    if (SCHEME != WENO5JS) {
+        init_keep_rows<T>(keep_rows, threadIdx.x);
         __syncthreads();
     }
     if (xi >= G.n[0] + (D == 0) || yi >= G.n[1] + (D == 1) || zi >= G.n[2] + (D == 2)) return;
@@ -190,7 +190,13 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
     Recon32 R32;
     R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;
     R32.ct = (float)K->P.teno_ct;
-    R32.wtab = wtab;
+    if constexpr (F64) {
+        R.rows = keep_rows;
+        R32.rows = nullptr;
+    } else {
+        R.rows = nullptr;
+        R32.rows = keep_rows;
+    }
     double q[6][5], ud[6], p[6];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
