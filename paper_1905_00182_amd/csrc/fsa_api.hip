@@ -197,7 +197,11 @@ void build_consts(fsa_ctx* c)
     P.inflow_amp = d.inflow_amp;
     P.seed = d.seed;
     for (int k = 0; k < 3; ++k)
-        for (int s = 0; s < 2; ++s) P.sw[k][s] = k < d.dim ? d.sponge_width[k][s] : 0.0;
+        for (int s = 0; s < 2; ++s) {
+            P.sw[k][s] = k < d.dim ? d.sponge_width[k][s] : 0.0;
+            P.inv_sw[k][s] = P.sw[k][s] > 0.0 ? 1.0 / P.sw[k][s] : 0.0;
+        }
+    P.e_inf = d.prim_inf[4] / P.gm1;
     P.sigma = d.sponge_sigma;
     P.weno_eps = d.weno_eps;
     P.teno_ct = d.teno_ct;

@@ -30,6 +30,8 @@ struct Phys {
     double inflow_amp;
     unsigned long long seed;
     double sw[3][2];          // sponge widths
+    double inv_sw[3][2];      // their reciprocals (0 where there is no sponge)
+    double e_inf;             // far-field internal energy per volume, p_inf / (gamma - 1)
     double sigma;             // sponge sigma_max
     double weno_eps, teno_ct, teno_eps;
     int terms;
@@ -88,7 +90,7 @@ __device__ __forceinline__ void inflow_state(const Phys& P, long long step, long
         q[1 + a] = rho * u;
         ke += u * u;
     }
-    q[DIM + 1] = P.prim_inf[4] / P.gm1 + 0.5 * rho * ke;
+    q[DIM + 1] = P.e_inf + 0.5 * rho * ke;
 }
 
 // State at a possibly out-of-range cell (i, j, k): boundary ghosts resolved x, then y, then z.
@@ -291,11 +293,12 @@ __device__ __forceinline__ void support4(double X, double lo, double h, int& j0,
 // Cubic sponge: depth ratio into the layers along one direction, clipped to [0, 1]; the
 // rate is sigma_max * (max over directions of the ratio)^3.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ double sponge_eta(double x, double lo, double hi, double wl, double wh)
+__device__ __forceinline__ double sponge_eta(double x, double lo, double hi, double wl, double wh, double iwl,
+                                            double iwh)
 {
     double eta = 0.0;
-    if (wl > 0.0 && x < lo + wl) eta = fmax(eta, (lo + wl - x) / wl);
-    if (wh > 0.0 && x > hi - wh) eta = fmax(eta, (x - (hi - wh)) / wh);
+    if (wl > 0.0 && x < lo + wl) eta = fmax(eta, (lo + wl - x) * iwl);
+    if (wh > 0.0 && x > hi - wh) eta = fmax(eta, (x - (hi - wh)) * iwh);
     return fmin(eta, 1.0);
 }
 
@@ -313,7 +316,8 @@ struct KConst {
     __device__ __forceinline__ double eta_dir(int d, int i) const
     {
         const double x = G.lo[d] + ((double)i + 0.5) * G.h;
-        return sponge_eta(x, G.lo[d], G.lo[d] + (double)G.n[d] * G.h, P.sw[d][0], P.sw[d][1]);
+        return sponge_eta(x, G.lo[d], G.lo[d] + (double)G.n[d] * G.h, P.sw[d][0], P.sw[d][1], P.inv_sw[d][0],
+                          P.inv_sw[d][1]);
     }
 };
 

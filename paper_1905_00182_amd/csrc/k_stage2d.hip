@@ -104,6 +104,9 @@ constexpr bool F64v = std::is_same<T, double>::value;
 template <int SCHEME, class T>
 struct Column2D {
     static constexpr bool F64 = std::is_same<T, double>::value;
+    // Rows of loads in flight ahead of their use: the FP32 forms have less arithmetic per row
+    // to cover memory latency with, and the registers for a second row.
+    static constexpr int PF = F64 ? 1 : 2;
     const KConst* __restrict__ K;   // grid and physics constants (device memory)
     const double* __restrict__ Qs;
     const double* Qn;               // may alias out (last stage writes in place)
@@ -112,7 +115,12 @@ struct Column2D {
     const unsigned* __restrict__ flags_x;
     const unsigned* __restrict__ flags_y;
     long long ncell;
-    int nx;
+    int nx, ny, bcy0, bcy1;
+    double sigma;                   // sponge sigma_max (0 when the sponge term is off)
+    // far-field constants used per row, read once at kernel start: a load from the constant
+    // block inside the march waits for every LDS access in flight (FP32 forms; the FP64
+    // kernel has no registers to spare and reads them where they are used)
+    double qinf[4], Fxinf[4], Fyinf[4], uinf, vinf, gamma;
     int wlo0, wlo1, wn0, wn1;
     double ax, ay, inv_h, gm1, ca, cb, dt;
     T inv_hT, inv12h, mu;
@@ -125,7 +133,9 @@ struct Column2D {
     bool x_inflow;                  // this lane is an inflow ghost column
     bool out_lane;
     bool want_alpha;
-    double eta_x;                   // sponge depth ratio of this lane's column
+    double sg_x;                    // sponge rate sigma * eta^3 of this lane's column
+    double sg_rows;                 // FP32 forms: sponge rate of row sg_base + lane
+    int sg_base;
     unsigned long long amax_x, amax_y;
     long long step;
     // register windows, slot = (row - first front row) mod 5
@@ -134,25 +144,26 @@ struct Column2D {
     T txy[5], tyy[5];               // stresses used in y derivatives stay in registers
     T (*vring)[3][WAVE];            // LDS: tau_xx, b_x, b_y of the last five stress rows, [slot][.][lane]
     T fy_prev[4], cy_queue[4];
-    double qf[4];                   // prefetched state of the next front row
-    unsigned wy_pf, wx_pf;          // learned form: prefetched keep patterns of the next step
-    double qn_pf[4];                // step-start state of the next output row (stages 2 and 3)
+    double qf[PF][4];               // prefetched state of the next PF front rows
+    unsigned wy_pf[PF], wx_pf[PF];  // learned form: prefetched keep patterns of the next PF steps
+    double qn_pf[PF][4];            // step-start state of the next PF output rows (stages 2 and 3)
+    double fw_pf[PF][2];            // penalty-IB force window values of the next PF output rows
+    bool ib_on;                     // the force window is present and overlaps this strip
     double (*ring)[4][WAVE];        // LDS: the last five front rows of this wave, [slot][comp][lane]
     int lane;
 
     // State of (this lane, row j): interior and periodic/zero-gradient ghosts are loads;
-    // inflow ghosts are built from the far field and the seeded perturbation.
+    // inflow ghosts are built from the far field and the seeded perturbation, replacing the
+    // (in-range, unused) load of their resolved cell.  Loading unconditionally leaves the
+    // previous contents of q dead, so no copies are made around a masked load.
     __device__ __forceinline__ void load_row(int j, double* q) const
     {
         int inflow = 0, side = 0, depth = 0;
-        const int jr = resolve_index(j, K->G.n[1], K->G.bc[1][0], K->G.bc[1][1], 1, inflow, side, depth);
-        if (!x_inflow && !inflow) {
-            const double* p = Qs + (long long)jr * nx + xr;
+        const int jr = resolve_index(j, ny, bcy0, bcy1, 1, inflow, side, depth);
+        const double* p = Qs + (long long)jr * nx + xr;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) q[c] = p[c * ncell];
-        } else {
-            fetch_state<2>(Qs, K->G, K->P, step, i, j, 0, q);
-        }
+        for (int c = 0; c < 4; ++c) q[c] = p[c * ncell];
+        if (x_inflow || inflow) fetch_state<2>(Qs, K->G, K->P, step, i, j, 0, q);
     }
 
     // Split fluxes f+- = (F +- alpha Q)/2 of component c of one direction, as stored in the
@@ -164,7 +175,7 @@ struct Column2D {
             fminus = (T)(0.5 * fma(-alpha, q, F));
             fplus = (T)(0.5 * fma(alpha, q, F));
         } else {
-            const double dq = q - K->P.q_inf[c], dF = F - Finf;
+            const double dq = q - qinf[c], dF = F - Finf;
             fminus = (T)(0.5 * fma(-alpha, dq, dF));
             fplus = (T)(0.5 * fma(alpha, dq, dF));
         }
@@ -173,24 +184,67 @@ struct Column2D {
     // Learned form: keep patterns of the y face (R-3)+1/2 and the x face right of this lane
     // in output row R-4, the faces step R reconstructs (rows clamped into range; the loads
     // of steps that do not use them are harmless).
-    __device__ __forceinline__ void load_patterns(int R)
+    __device__ __forceinline__ void load_patterns(int R, int slot)
     {
         if constexpr (SCHEME == LEARNED) {
-            const int ny = K->G.n[1];
             const int jy = min(max(R - 2, 0), ny), jx = min(max(R - 4, 0), ny - 1);
-            wy_pf = flags_y[(long long)jy * nx + xr];
-            wx_pf = flags_x[(long long)jx * (nx + 1) + min(max(i + 1, 0), nx)];
+            wy_pf[slot] = flags_y[(long long)jy * nx + xr];
+            wx_pf[slot] = flags_x[(long long)jx * (nx + 1) + min(max(i + 1, 0), nx)];
         }
     }
 
-    // Step-start state Qn of output row r for this lane (issued one step before it is used,
-    // so the load latency hides behind a row of work).
-    __device__ __forceinline__ void load_qn(int r)
+    // Step-start state Qn of output row r for this lane (issued PF steps before it is used,
+    // so the load latency hides behind rows of work).  Rows outside the segment and halo
+    // lanes load an in-range cell whose value is not used (a cache hit on a row the wave
+    // loads anyway), so the load needs no lane mask.
+    __device__ __forceinline__ void load_qn(int r, int slot)
     {
-        if (!mode_rhs && ca != 0.0 && out_lane && r >= j0 && r <= j1) {
-            const long long o = (long long)r * nx + i;
+        if (!mode_rhs && ca != 0.0) {
+            const long long o = (long long)min(max(r, j0), j1) * nx + xr;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) qn_pf[c] = Qn[c * ncell + o];
+            for (int c = 0; c < 4; ++c) qn_pf[slot][c] = Qn[c * ncell + o];
+        }
+    }
+
+    // Force-window values (f_x, f_y) of output row r at this lane's column, issued PF steps
+    // before use like the other loads (a load used at once would wait for every load in
+    // flight, the prefetches included).  Rows outside the window give zero; lanes outside it
+    // load an in-range cell and are masked where the values are used.
+    __device__ __forceinline__ void load_fwin(int r, int slot)
+    {
+        fw_pf[slot][0] = fw_pf[slot][1] = 0.0;
+        const int wj = r - wlo1;
+        if (ib_on && wj >= 0 && wj < wn1) {
+            const long long wc = (long long)wj * wn0 + min(max(i - wlo0, 0), wn0 - 1);
+            fw_pf[slot][0] = fwin[wc];
+            fw_pf[slot][1] = fwin[(long long)wn0 * wn1 + wc];
+        }
+    }
+
+    __device__ __forceinline__ double q_inf(int c) const { return F64 ? K->P.q_inf[c] : qinf[c]; }
+    __device__ __forceinline__ double gam() const { return F64 ? K->P.gamma : gamma; }
+
+    // Sponge rate sigma * eta^3 (zero when the sponge term is off).
+    __device__ __forceinline__ double sponge_rate(double eta) const { return sigma * (eta * eta * eta); }
+
+    // Sponge rate sigma * eta_y^3 of row r.  FP32 forms: each lane holds the rate of one of 64
+    // consecutive rows, refilled when r leaves them (r increases by one per call; called with
+    // all lanes active), and the row's value is a lane read instead of the profile arithmetic
+    // and its constant-block loads.
+    __device__ __forceinline__ double sponge_row(int r)
+    {
+        if constexpr (F64) {
+            return sponge_rate(K->eta_dir(1, r));
+        } else {
+            if (r - sg_base >= WAVE) {
+                sg_base = r;
+                sg_rows = sponge_rate(K->eta_dir(1, r + lane));
+            }
+            const int k = r - sg_base;
+            const long long b = __double_as_longlong(sg_rows);
+            const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+            const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+            return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
         }
     }
 
@@ -214,14 +268,28 @@ struct Column2D {
         }
 
         // ---- front row Rw (prefetched in the previous step): velocity and y-split fluxes
-        const double q[4] = {qf[0], qf[1], qf[2], qf[3]};
+        const double q[4] = {qf[0][0], qf[0][1], qf[0][2], qf[0][3]};
 #pragma unroll
         for (int c = 0; c < 4; ++c) ring[S0][c][lane] = q[c];
-        load_row(Rw + 1, qf);
-        const unsigned word_y = wy_pf, word_x = wx_pf;
-        load_patterns(Rw + 1);
-        const double qn[4] = {qn_pf[0], qn_pf[1], qn_pf[2], qn_pf[3]};
-        load_qn(Rw - 3);
+        const unsigned word_y = wy_pf[0], word_x = wx_pf[0];
+        const double qn[4] = {qn_pf[0][0], qn_pf[0][1], qn_pf[0][2], qn_pf[0][3]};
+        const double fw[2] = {fw_pf[0][0], fw_pf[0][1]};
+#pragma unroll
+        for (int s = 0; s + 1 < PF; ++s) {
+            wy_pf[s] = wy_pf[s + 1];
+            wx_pf[s] = wx_pf[s + 1];
+            fw_pf[s][0] = fw_pf[s + 1][0];
+            fw_pf[s][1] = fw_pf[s + 1][1];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                qf[s][c] = qf[s + 1][c];
+                qn_pf[s][c] = qn_pf[s + 1][c];
+            }
+        }
+        load_row(Rw + PF, qf[PF - 1]);
+        load_patterns(Rw + PF, PF - 1);
+        load_qn(Rw - 4 + PF, PF - 1);
+        load_fwin(Rw - 4 + PF, PF - 1);
         const double inv_rho = rcp_nr(q[0]);
         const double u = q[1] * inv_rho, v = q[2] * inv_rho;
         const double p = gm1 * (q[3] - 0.5 * fma(q[1], u, q[2] * v));
@@ -229,14 +297,14 @@ struct Column2D {
         {
             const double F[4] = {q[2], q[1] * v, fma(q[2], v, p), (q[3] + p) * v};
 #pragma unroll
-            for (int c = 0; c < 4; ++c) split(c, q[c], F[c], K->Fy_inf[c], ay, fpr[c], fm[S0][c]);
+            for (int c = 0; c < 4; ++c) split(c, q[c], F[c], Fyinf[c], ay, fpr[c], fm[S0][c]);
         }
         if (F64) {
             uw[S0] = (T)u;
             vw[S0] = (T)v;
         } else {
-            uw[S0] = (T)(u - K->P.prim_inf[1]);
-            vw[S0] = (T)(v - K->P.prim_inf[2]);
+            uw[S0] = (T)(u - uinf);
+            vw[S0] = (T)(v - vinf);
         }
 
         // ---- y face (Rw-3)+1/2: f+ rows Rw-5..Rw-1, f- rows Rw..Rw-4
@@ -269,14 +337,16 @@ struct Column2D {
             vring[S2][0][lane] = sxx;
             txy[S2] = sxy;
             tyy[S2] = syy;
-            const T uf = F64 ? uc : uc + (T)K->P.prim_inf[1];
-            const T vf = F64 ? vc : vc + (T)K->P.prim_inf[2];
+            const T uf = F64 ? uc : uc + (T)uinf;
+            const T vf = F64 ? vc : vc + (T)vinf;
             vring[S2][1][lane] = fma(uf, sxx, vf * sxy);
             vring[S2][2][lane] = fma(uf, sxy, vf * syy);
         }
 
         // ---- output row r = Rw-4
         if (do_out) {
+            // (a wave-uniform point: the FP32 forms' lane table is refilled by every lane)
+            const double sg_y = sponge_row(r);
             double ur, vr;
             if (F64) {
                 ur = (double)uw[S4];
@@ -294,7 +364,7 @@ struct Column2D {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     T fpx, fmx;
-                    split(c, qr[c], F[c], K->Fx_inf[c], ax, fpx, fmx);
+                    split(c, qr[c], F[c], Fxinf[c], ax, fpx, fmx);
                     const T pl1 = lo1(fpx), pu1 = up1(fpx);
                     const T ml1 = lo1(fmx), mu1 = up1(fmx), mu2 = up1(mu1);
                     const int bp = (int)(word >> (3 * c)) & 7, bm = (int)(word >> (16 + 3 * c)) & 7;
@@ -319,47 +389,42 @@ struct Column2D {
                 L[2] += (double)vy;
                 L[3] += (double)ve;
             }
-            if (out_lane) {
-                double s[4] = {0.0, 0.0, 0.0, 0.0};
-                if ((terms & T_IB) && fwin) {
-                    const int wi = i - wlo0, wj = r - wlo1;
-                    if (wi >= 0 && wi < wn0 && wj >= 0 && wj < wn1) {
-                        const long long wc = (long long)wj * wn0 + wi;
-                        const long long wcells = (long long)wn0 * wn1;
-                        const double f0 = fwin[wc], f1 = fwin[wcells + wc];
-                        s[1] = f0;
-                        s[2] = f1;
-                        s[3] = fma(f0, ur, f1 * vr);
-                    }
-                }
-                if (terms & T_SPONGE) {
-                    const double eta = fmax(eta_x, K->eta_dir(1, r));
-                    if (eta > 0.0) {
-                        const double sg = K->P.sigma * (eta * eta * eta);
+            // Sources, the stage combination and the wave speeds.  FP32 forms: formed on every
+            // lane (the halo lanes' values are discarded), so that only the stores and the
+            // wave-speed maximum depend on the lane and the tail of the row is one scheduling
+            // region.  FP64: on the output lanes only (its registers are all taken; the
+            // branch keeps the halo lanes' values from being live).  A zero force or sponge
+            // rate adds exact zeros.
+            if (!F64 || out_lane) {
+                const bool in_w = ib_on && (unsigned)(i - wlo0) < (unsigned)wn0;
+                const double f0 = in_w ? fw[0] : 0.0, f1 = in_w ? fw[1] : 0.0;
+                // sigma * max(eta_x, eta_y)^3 = max of the two rates (a monotone function of
+                // eta, rounded the same way for both; zero without a sponge)
+                const double sg = fmax(sg_x, sg_y);
+                double s[4] = {0.0, f0, f1, fma(f0, ur, f1 * vr)};
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) s[c] = fma(-sg, qr[c] - K->P.q_inf[c], s[c]);
-                    }
-                }
-                const long long o = (long long)r * nx + i;
+                for (int c = 0; c < 4; ++c) s[c] = fma(-sg, qr[c] - q_inf(c), s[c]);
                 double val[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const double l = L[c] + s[c];
-                    if (mode_rhs) {
-                        val[c] = l;
-                    } else {
-                        const double stage = fma(dt, l, qr[c]);
-                        val[c] = (ca == 0.0) ? stage : fma(ca, qn[c], cb * stage);
-                    }
-                    out[c * ncell + o] = val[c];
+                    const double stage = fma(dt, l, qr[c]);
+                    val[c] = mode_rhs ? l : ((ca == 0.0) ? stage : fma(ca, qn[c], cb * stage));
+                }
+                if (out_lane) {
+                    const long long o = (long long)r * nx + i;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) out[c * ncell + o] = val[c];
                 }
                 if (want_alpha) {
                     const double ir = rcp_nr(val[0]);
                     const double un = val[1] * ir, vn = val[2] * ir;
                     const double pn = gm1 * (val[3] - 0.5 * fma(val[1], un, val[2] * vn));
-                    const double cn = sqrt(K->P.gamma * pn * ir);
-                    amax_x = max_bits(amax_x, (unsigned long long)__double_as_longlong(fabs(un) + cn));
-                    amax_y = max_bits(amax_y, (unsigned long long)__double_as_longlong(fabs(vn) + cn));
+                    const double cn = sqrt(gam() * pn * ir);
+                    const unsigned long long sx = (unsigned long long)__double_as_longlong(fabs(un) + cn);
+                    const unsigned long long sy = (unsigned long long)__double_as_longlong(fabs(vn) + cn);
+                    amax_x = out_lane ? max_bits(amax_x, sx) : amax_x;
+                    amax_y = out_lane ? max_bits(amax_y, sy) : amax_y;
                 }
             }
         }
@@ -389,6 +454,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.flags_y = A.flags_y;
     C.ncell = K->G.ncell;
     C.nx = K->G.n[0];
+    C.ny = K->G.n[1];
+    C.bcy0 = K->G.bc[1][0];
+    C.bcy1 = K->G.bc[1][1];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        C.qinf[c] = K->P.q_inf[c];
+        C.Fxinf[c] = K->Fx_inf[c];
+        C.Fyinf[c] = K->Fy_inf[c];
+    }
+    C.uinf = K->P.prim_inf[1];
+    C.vinf = K->P.prim_inf[2];
+    C.gamma = K->P.gamma;
+    C.sigma = (K->P.terms & T_SPONGE) ? K->P.sigma : 0.0;
     C.wlo0 = A.wlo[0];
     C.wlo1 = A.wlo[1];
     C.wn0 = A.wn[0];
@@ -446,7 +524,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         C.x_inflow = inflow != 0;
         C.out_lane = lane >= HALO && lane < WAVE - HALO && i < nx;
     }
-    C.eta_x = C.out_lane ? K->eta_dir(0, C.i) : 0.0;
+    C.sg_x = C.out_lane ? C.sponge_rate(K->eta_dir(0, C.i)) : 0.0;
+    C.sg_rows = 0.0;
+    C.sg_base = -(1 << 30);   // the first sponge_row call fills the lane table
+    // the force window meets this strip's columns (a wave-uniform test)
+    C.ib_on = (C.terms & T_IB) && C.fwin && C.wn0 > 0 && C.wn1 > 0 && bx * OUTW - HALO + WAVE > C.wlo0 &&
+              bx * OUTW - HALO < C.wlo0 + C.wn0;
     C.j0 = by * A.ty;
     C.j1 = min(C.j0 + A.ty, ny) - 1;
 #pragma unroll
@@ -461,11 +544,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     C.want_alpha = A.alpha_part != nullptr;
     C.amax_x = C.amax_y = 0ull;
     const int Rend = C.j1 + HALO;
-    C.load_row(C.j0 - HALO, C.qf);
-    C.wy_pf = C.wx_pf = 0u;
-    C.load_patterns(C.j0 - HALO);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) C.qn_pf[c] = 0.0;
+    for (int s = 0; s < C.PF; ++s) {
+        C.load_row(C.j0 - HALO + s, C.qf[s]);
+        C.wy_pf[s] = C.wx_pf[s] = 0u;
+        C.load_patterns(C.j0 - HALO + s, s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) C.qn_pf[s][c] = 0.0;
+        C.load_qn(C.j0 - 2 * HALO + s, s);
+        C.load_fwin(C.j0 - 2 * HALO + s, s);
+    }
     for (int Rw = C.j0 - HALO; Rw <= Rend; Rw += 5) {
         C.template step_row<0>(Rw);
         if (Rw + 1 > Rend) break;
