@@ -1,7 +1,11 @@
 """Build the gfx950 solver library paper_1905_00182_amd/libfsa.so from csrc/ with hipcc.
 
-All device code is compiled with packed-FP32 instructions disabled (they are never emitted);
-the C ABI is declared in include/fsa.h at the repository root.
+All device code is compiled with packed-FP32 instructions disabled (they are never emitted)
+and with contraction of a multiply and an add into an FMA only within one source expression
+(-ffp-contract=on): the rounding of a formula is then fixed by its source text, so kernels
+that evaluate the same formula (the precision form's TENO5 and the learned form's fallback)
+agree bit for bit whatever the surrounding code.  The C ABI is declared in include/fsa.h at
+the repository root.
 """
 import os
 import subprocess
@@ -18,7 +22,7 @@ ARCH = os.environ.get("FSA_OFFLOAD_ARCH", "gfx950")
 def build(verbose: bool = False, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [
-        hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+        hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"), "-I", CSRC,
         "-o", LIB + ".tmp",

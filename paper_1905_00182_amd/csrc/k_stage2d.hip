@@ -101,6 +101,18 @@ __device__ __forceinline__ T recon_side(T a, T b, T c, T d, T e, const Recon& R,
 template <class T>
 constexpr bool F64v = std::is_same<T, double>::value;
 
+// Learned form: a face word (both sides) in which every component keeps every sub-stencil.
+constexpr unsigned ALL_KEPT2 = 0x0FFF0FFFu;
+
+// True when the learned form's face words of the whole wave keep everything: the faces then
+// take the all-kept table row at a compile-time index (no lookup waits on the word).
+template <int SCHEME>
+__device__ __forceinline__ bool wave_all_kept(unsigned word)
+{
+    if constexpr (SCHEME == LEARNED) return __ballot(word != ALL_KEPT2) == 0ull;
+    else return false;
+}
+
 template <int SCHEME, class T>
 struct Column2D {
     static constexpr bool F64 = std::is_same<T, double>::value;
@@ -310,16 +322,21 @@ struct Column2D {
         // ---- y face (Rw-3)+1/2: f+ rows Rw-5..Rw-1, f- rows Rw..Rw-4
         T cy_new[4] = {T(0), T(0), T(0), T(0)};
         if ((terms & T_CONVY) && Rw >= j0 + 2 && Rw <= j1 + 3) {
-            const unsigned word = word_y;
+            auto yface = [&](auto all_kept) {
+                const unsigned word = word_y;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int bp = (int)(word >> (3 * c)) & 7, bm = (int)(word >> (16 + 3 * c)) & 7;
-                const T fh =
-                    recon_side<SCHEME, T>(fp[S0][c], fp[S4][c], fp[S3][c], fp[S2][c], fp[S1][c], R, R32, bp) +
-                    recon_side<SCHEME, T>(fm[S0][c], fm[S1][c], fm[S2][c], fm[S3][c], fm[S4][c], R, R32, bm);
-                cy_new[c] = -(fh - fy_prev[c]) * inv_hT;
-                fy_prev[c] = fh;
-            }
+                for (int c = 0; c < 4; ++c) {
+                    const int bp = all_kept ? 7 : (int)(word >> (3 * c)) & 7;
+                    const int bm = all_kept ? 7 : (int)(word >> (16 + 3 * c)) & 7;
+                    const T fh =
+                        recon_side<SCHEME, T>(fp[S0][c], fp[S4][c], fp[S3][c], fp[S2][c], fp[S1][c], R, R32, bp) +
+                        recon_side<SCHEME, T>(fm[S0][c], fm[S1][c], fm[S2][c], fm[S3][c], fm[S4][c], R, R32, bm);
+                    cy_new[c] = -(fh - fy_prev[c]) * inv_hT;
+                    fy_prev[c] = fh;
+                }
+            };
+            if (wave_all_kept<SCHEME>(word_y)) yface(std::true_type{});
+            else yface(std::false_type{});
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) fp[S0][c] = fpr[c];
@@ -360,18 +377,23 @@ struct Column2D {
             if (terms & T_CONVX) {
                 const double pr = gm1 * (qr[3] - 0.5 * fma(qr[1], ur, qr[2] * vr));
                 const double F[4] = {qr[1], fma(qr[1], ur, pr), qr[2] * ur, (qr[3] + pr) * ur};
-                const unsigned word = word_x;
+                auto xface = [&](auto all_kept) {
+                    const unsigned word = word_x;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    T fpx, fmx;
-                    split(c, qr[c], F[c], Fxinf[c], ax, fpx, fmx);
-                    const T pl1 = lo1(fpx), pu1 = up1(fpx);
-                    const T ml1 = lo1(fmx), mu1 = up1(fmx), mu2 = up1(mu1);
-                    const int bp = (int)(word >> (3 * c)) & 7, bm = (int)(word >> (16 + 3 * c)) & 7;
-                    const T fh = recon_side<SCHEME, T>(lo1(pl1), pl1, fpx, pu1, up1(pu1), R, R32, bp) +
-                                 recon_side<SCHEME, T>(up1(mu2), mu2, mu1, fmx, ml1, R, R32, bm);
-                    L[c] = (double)(-(fh - lo1(fh)) * inv_hT);
-                }
+                    for (int c = 0; c < 4; ++c) {
+                        T fpx, fmx;
+                        split(c, qr[c], F[c], Fxinf[c], ax, fpx, fmx);
+                        const T pl1 = lo1(fpx), pu1 = up1(fpx);
+                        const T ml1 = lo1(fmx), mu1 = up1(fmx), mu2 = up1(mu1);
+                        const int bp = all_kept ? 7 : (int)(word >> (3 * c)) & 7;
+                        const int bm = all_kept ? 7 : (int)(word >> (16 + 3 * c)) & 7;
+                        const T fh = recon_side<SCHEME, T>(lo1(pl1), pl1, fpx, pu1, up1(pu1), R, R32, bp) +
+                                     recon_side<SCHEME, T>(up1(mu2), mu2, mu1, fmx, ml1, R, R32, bm);
+                        L[c] = (double)(-(fh - lo1(fh)) * inv_hT);
+                    }
+                };
+                if (wave_all_kept<SCHEME>(word_x)) xface(std::true_type{});
+                else xface(std::false_type{});
             }
             if (terms & T_CONVY) {
 #pragma unroll
