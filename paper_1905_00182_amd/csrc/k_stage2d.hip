@@ -84,17 +84,45 @@ __device__ __forceinline__ float recon(float a, float b, float c, float d, float
     return recon5f<SCHEME>(a, b, c, d, e, R);
 }
 
-// Face value of one side: the scheme's own weights, or the learned keep bits.
+// Face value of one side: the scheme's own weights, or (learned form) the keep-pattern row
+// given by its coefficients.
 template <int SCHEME, class T>
-__device__ __forceinline__ T recon_side(T a, T b, T c, T d, T e, const Recon& R, const Recon32& R32, int bits)
+__device__ __forceinline__ T recon_side(T a, T b, T c, T d, T e, const Recon& R, const Recon32& R32,
+                                        const float (&coef)[5])
 {
     if constexpr (SCHEME == LEARNED) {
         (void)R;
         (void)R32;
-        return recon5_bits(a, b, c, d, e, bits, R32.rows);
+        return keep_sum(coef, a, b, c, d, e);
     } else {
-        (void)bits;
+        (void)coef;
         return recon<SCHEME>(a, b, c, d, e, R, R32);
+    }
+}
+
+// Learned form: the keep-pattern rows of both sides of components C0, C0+1 of one face word,
+// all read before any is used so that the LDS reads overlap.
+template <int SCHEME, int C0>
+__device__ __forceinline__ void face_rows(unsigned word, bool all_kept, const float (*rows)[8], float (&cp)[4][5],
+                                          float (&cm)[4][5])
+{
+    if constexpr (SCHEME == LEARNED) {
+#pragma unroll
+        for (int c = C0; c < C0 + 2; ++c) {
+            const int bp = all_kept ? 7 : (int)(word >> (3 * c)) & 7;
+            const int bm = all_kept ? 7 : (int)(word >> (16 + 3 * c)) & 7;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                cp[c][j] = rows[bp][j];
+                cm[c][j] = rows[bm][j];
+            }
+        }
+    } else {
+        (void)word;
+        (void)all_kept;
+        (void)rows;
+        (void)cp;
+        (void)cm;
     }
 }
 
@@ -323,14 +351,14 @@ struct Column2D {
         T cy_new[4] = {T(0), T(0), T(0), T(0)};
         if ((terms & T_CONVY) && Rw >= j0 + 2 && Rw <= j1 + 3) {
             auto yface = [&](auto all_kept) {
-                const unsigned word = word_y;
+                float cp[4][5], cm[4][5];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const int bp = all_kept ? 7 : (int)(word >> (3 * c)) & 7;
-                    const int bm = all_kept ? 7 : (int)(word >> (16 + 3 * c)) & 7;
+                    if (c == 0) face_rows<SCHEME, 0>(word_y, all_kept, R32.rows, cp, cm);
+                    if (c == 2) face_rows<SCHEME, 2>(word_y, all_kept, R32.rows, cp, cm);
                     const T fh =
-                        recon_side<SCHEME, T>(fp[S0][c], fp[S4][c], fp[S3][c], fp[S2][c], fp[S1][c], R, R32, bp) +
-                        recon_side<SCHEME, T>(fm[S0][c], fm[S1][c], fm[S2][c], fm[S3][c], fm[S4][c], R, R32, bm);
+                        recon_side<SCHEME, T>(fp[S0][c], fp[S4][c], fp[S3][c], fp[S2][c], fp[S1][c], R, R32, cp[c]) +
+                        recon_side<SCHEME, T>(fm[S0][c], fm[S1][c], fm[S2][c], fm[S3][c], fm[S4][c], R, R32, cm[c]);
                     cy_new[c] = -(fh - fy_prev[c]) * inv_hT;
                     fy_prev[c] = fh;
                 }
@@ -378,17 +406,17 @@ struct Column2D {
                 const double pr = gm1 * (qr[3] - 0.5 * fma(qr[1], ur, qr[2] * vr));
                 const double F[4] = {qr[1], fma(qr[1], ur, pr), qr[2] * ur, (qr[3] + pr) * ur};
                 auto xface = [&](auto all_kept) {
-                    const unsigned word = word_x;
+                    float cp[4][5], cm[4][5];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
+                        if (c == 0) face_rows<SCHEME, 0>(word_x, all_kept, R32.rows, cp, cm);
+                        if (c == 2) face_rows<SCHEME, 2>(word_x, all_kept, R32.rows, cp, cm);
                         T fpx, fmx;
                         split(c, qr[c], F[c], Fxinf[c], ax, fpx, fmx);
                         const T pl1 = lo1(fpx), pu1 = up1(fpx);
                         const T ml1 = lo1(fmx), mu1 = up1(fmx), mu2 = up1(mu1);
-                        const int bp = all_kept ? 7 : (int)(word >> (3 * c)) & 7;
-                        const int bm = all_kept ? 7 : (int)(word >> (16 + 3 * c)) & 7;
-                        const T fh = recon_side<SCHEME, T>(lo1(pl1), pl1, fpx, pu1, up1(pu1), R, R32, bp) +
-                                     recon_side<SCHEME, T>(up1(mu2), mu2, mu1, fmx, ml1, R, R32, bm);
+                        const T fh = recon_side<SCHEME, T>(lo1(pl1), pl1, fpx, pu1, up1(pu1), R, R32, cp[c]) +
+                                     recon_side<SCHEME, T>(up1(mu2), mu2, mu1, fmx, ml1, R, R32, cm[c]);
                         L[c] = (double)(-(fh - lo1(fh)) * inv_hT);
                     }
                 };
