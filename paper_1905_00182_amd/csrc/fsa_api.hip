@@ -36,6 +36,8 @@ struct fsa_ctx {
     double* tot_part = nullptr;          // diagnostics: per-block partial totals
     double* tot_out = nullptr;
     long long apart_n = 0;
+    long long fin_n = 0;                 // deferred wave-speed reduction: partials in apart, and
+    unsigned long long* fin_bits = nullptr;  // the slot it writes (0: none pending)
     unsigned long long* h_abits = nullptr;  // pinned mirror of the last step's slots
     hipEvent_t ev_alpha = nullptr;
     bool alpha_pending = false;
@@ -382,12 +384,30 @@ int timing_pair(fsa_ctx* c, hipEvent_t& t0, hipEvent_t& t1)
     return FSA_OK;
 }
 
+// A stage's wave-speed partials are reduced into its output slot by the next launch that
+// can carry the reduction (the next stage's IB window launch), or on their own: before the
+// next stage's kernels when there is no IB step, and at the end of a call.
+void defer_alpha_final(fsa_ctx* c, long long n, int slot)
+{
+    c->fin_n = n;
+    c->fin_bits = c->abits + 3 * slot;
+}
+
+int flush_alpha_final(fsa_ctx* c)
+{
+    if (c->fin_n <= 0) return FSA_OK;
+    const int e = launch_alpha_final(c->apart, c->fin_n, c->fin_bits, c->stream);
+    c->fin_n = 0;
+    return e ? hipcheck(c, (hipError_t)e, "wave-speed reduction launch") : FSA_OK;
+}
+
 int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, int in, int acc, bool reduce,
                   int stage, double ca, double cb, double dt, int mode_rhs)
 {
     unsigned long long* bits = c->abits + 3 * in;
     int e;
     if (reduce) {
+        if ((e = flush_alpha_final(c)) != FSA_OK) return e;   // (apart is reused below)
         e = launch_alpha(c->G, c->P, Qs, c->apart, bits, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "alpha reduction launch");
     }
@@ -398,9 +418,15 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         A.ca = ca;
         A.cb = cb;
         A.dt = dt;
+        // the previous stage's wave-speed reduction rides on the window launch
+        A.alpha_part = c->fin_n > 0 ? c->apart : nullptr;
+        A.alpha_n = c->fin_n;
+        A.alpha_bits = c->fin_bits;
         e = launch_ib_stage(c->G, c->P, A, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "IB stage launch");
+        c->fin_n = 0;
     }
+    if ((e = flush_alpha_final(c)) != FSA_OK) return e;
     if (c->d.precision == FSA_LEARNED32) {
         if (!c->mlp_ready) return fail(c, FSA_ESTATE, "learned form without a network (fsa_mlp_set)");
         // stage 0 = a lone right-hand side; stages 2 and 3 reuse the first stage's patterns
@@ -439,10 +465,7 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         e = launch_stage3d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stress3d, c->faces3d, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "3D stage launch");
         if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
-        if (acc >= 0) {
-            e = launch_alpha_final(c->apart, stage3d_blocks(c->G), c->abits + 3 * acc, c->stream);
-            if (e) return hipcheck(c, (hipError_t)e, "wave-speed reduction launch");
-        }
+        if (acc >= 0) defer_alpha_final(c, stage3d_blocks(c->G), acc);
         return FSA_OK;
     }
     if (c->ty == 0) {
@@ -459,10 +482,7 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     e = launch_stage2d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch");
     if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
-    if (acc >= 0) {
-        e = launch_alpha_final(c->apart, stage2d_waves(c->G, S.ty), c->abits + 3 * acc, c->stream);
-        if (e) return hipcheck(c, (hipError_t)e, "wave-speed reduction launch");
-    }
+    if (acc >= 0) defer_alpha_final(c, stage2d_waves(c->G, S.ty), acc);
     return FSA_OK;
 }
 
@@ -815,6 +835,7 @@ int32_t fsa_rk3_steps(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps)
         c->t += dt;
         c->step += 1;
     }
+    if ((rc = flush_alpha_final(c)) != FSA_OK) return rc;
     c->last_slot = (3 * nsteps) % 3;
     if (c->d.nan_check) {
         HIPCHK(c, hipMemcpyAsync(c->h_abits, c->abits, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost,

@@ -46,6 +46,11 @@ struct IBArgs {
     const double* cell_w;  // per CSR entry: W(cell) dV_k / h^dim
     const int* mj0;        // per marker: first support cell per direction [nm][3]
     const double* mw;      // per marker: one-dimensional weights [nm][dim][4]
+    // optional: a wave-speed reduction (as launch_alpha_final) carried out by one extra
+    // block of the window launch; part == nullptr for none
+    const unsigned long long* alpha_part;
+    long long alpha_n;
+    unsigned long long* alpha_bits;
 };
 
 int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, hipStream_t s);

@@ -68,15 +68,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_alpha(Grid G, Phys P, const dou
     }
 }
 
-// One block of 1024 threads: bits[d] = max over the n partials (the order is irrelevant for a
+// One block of NT threads: bits[d] = max over the n partials (the order is irrelevant for a
 // maximum).  With ~4000 partials each thread issues its few loads at once.
-constexpr int FINAL_THREADS = 1024;
-__global__ __launch_bounds__(FINAL_THREADS) void k_alpha_final(const unsigned long long* __restrict__ part,
-                                                               long long n, unsigned long long* __restrict__ bits)
+template <int NT>
+__device__ __forceinline__ void alpha_final_block(const unsigned long long* __restrict__ part, long long n,
+                                                  unsigned long long* __restrict__ bits)
 {
-    __shared__ unsigned long long red[FINAL_THREADS / 64][3];
+    __shared__ unsigned long long red[NT / 64][3];
     unsigned long long m[3] = {0ull, 0ull, 0ull};
-    for (long long k = threadIdx.x; k < n; k += blockDim.x) {
+    for (long long k = threadIdx.x; k < n; k += NT) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) m[d] = max_bits(m[d], part[k * 3 + d]);
     }
@@ -89,9 +89,16 @@ __global__ __launch_bounds__(FINAL_THREADS) void k_alpha_final(const unsigned lo
     __syncthreads();
     if (threadIdx.x < 3) {
         unsigned long long v = 0ull;
-        for (int w = 0; w < FINAL_THREADS / 64; ++w) v = max_bits(v, red[w][threadIdx.x]);
+        for (int w = 0; w < NT / 64; ++w) v = max_bits(v, red[w][threadIdx.x]);
         bits[threadIdx.x] = v;
     }
+}
+
+constexpr int FINAL_THREADS = 1024;
+__global__ __launch_bounds__(FINAL_THREADS) void k_alpha_final(const unsigned long long* __restrict__ part,
+                                                               long long n, unsigned long long* __restrict__ bits)
+{
+    alpha_final_block<FINAL_THREADS>(part, n, bits);
 }
 
 // Marker support: first cell and four weights per direction.
@@ -206,10 +213,15 @@ __global__ __launch_bounds__(64) void k_ib_markers(Grid G, IBArgs A)
 
 // Spread force density on the window box: one wave per window cell; lane l sums the cell's
 // CSR entries l, l+64, ... in increasing marker index, then the wave adds the lane sums in a
-// fixed butterfly order, so the result is the same on every run.
+// fixed butterfly order, so the result is the same on every run.  With A.alpha_part set, the
+// last block instead reduces the wave-speed partials (one launch fewer per stage).
 template <int DIM>
 __global__ __launch_bounds__(256) void k_ib_window(IBArgs A)
 {
+    if (A.alpha_part && blockIdx.x == gridDim.x - 1) {
+        alpha_final_block<256>(A.alpha_part, A.alpha_n, A.alpha_bits);
+        return;
+    }
     const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
     const long long c = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
@@ -413,7 +425,7 @@ int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s
     if (A.nm <= 0) return 0;
     const unsigned mb = (unsigned)((A.nm + 63) / 64);
     const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
-    const unsigned wb = (unsigned)((wcells + 3) / 4);   // four waves (cells) per block
+    const unsigned wb = (unsigned)((wcells + 3) / 4) + (A.alpha_part ? 1u : 0u);   // four cells per block
     if (G.dim == 3) {
         hipLaunchKernelGGL(k_ib_markers<3>, dim3(mb), dim3(64), 0, s, G, A);
         hipLaunchKernelGGL(k_ib_window<3>, dim3(wb), dim3(256), 0, s, A);
