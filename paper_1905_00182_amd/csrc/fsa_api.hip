@@ -491,7 +491,25 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
 // fastest.
 int tune_ty(fsa_ctx* c, const StageArgs& S0)
 {
-    static const int cand[] = {8, 10, 12, 14, 16, 19, 22, 25, 28, 32, 37, 44, 52, 64};
+    // fixed candidates, plus for one to four rounds of waves the shortest segment whose wave
+    // count fits that many rounds of the device's wave slots (two waves per SIMD, four SIMDs
+    // per compute unit): the halo rows are paid once per segment, so the fewest segments that
+    // still fill the rounds are the natural candidates
+    std::vector<int> cand = {8, 10, 12, 14, 16, 19, 22, 25, 28, 32, 37, 44, 52, 64};
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+            const long long slots = 8ll * cus, strips = stage2d_ncolx(c->G.n[0]);
+            for (int rounds = 1; rounds <= 4; ++rounds) {
+                const long long segs = rounds * slots / strips;
+                if (segs < 1) continue;
+                const long long ty = (c->G.n[1] + segs - 1) / segs;
+                if (ty >= 4 && ty <= 4096 && std::find(cand.begin(), cand.end(), (int)ty) == cand.end())
+                    cand.push_back((int)ty);
+            }
+        }
+    }
     StageArgs S = S0;
     S.mode_rhs = 1;
     S.out = c->Qb;
@@ -500,10 +518,12 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    int best = 16;
-    float best_ms = 1e30f;
-    for (int rep = 0; rep < 2; ++rep)
-        for (int ty : cand) {
+    // each candidate's time is the least of three launches after a warm-up pass (single
+    // launches of ~0.3 ms vary by a few percent, as much as neighbouring candidates differ)
+    std::vector<float> tmin(cand.size(), 1e30f);
+    for (int rep = 0; rep < 4; ++rep)
+        for (size_t k = 0; k < cand.size(); ++k) {
+            const int ty = cand[k];
             if (ty > 2 * c->G.n[1] && ty != cand[0]) continue;
             S.ty = ty;
             HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -513,10 +533,14 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
             HIPCHK(c, hipEventSynchronize(e1));
             float ms = 0.0f;
             HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-            if (rep == 1 && ms < best_ms) {   // the first pass warms caches and clocks
-                best_ms = ms;
-                best = ty;
-            }
+            if (rep > 0) tmin[k] = std::min(tmin[k], ms);   // the first pass warms caches and clocks
+        }
+    int best = 16;
+    float best_ms = 1e30f;
+    for (size_t k = 0; k < cand.size(); ++k)
+        if (tmin[k] < best_ms) {
+            best_ms = tmin[k];
+            best = cand[k];
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
