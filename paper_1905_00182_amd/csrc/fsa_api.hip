@@ -76,6 +76,11 @@ struct fsa_ctx {
     unsigned* flags_x = nullptr;
     unsigned* flags_y = nullptr;
     unsigned long long* counters = nullptr;
+    float* qrange = nullptr;             // learned form: deviation ranges of the last stage output
+    const double* qrange_of = nullptr;   // the buffer they describe (null: none valid)
+    int qrange_ty = 0;                   // rows per segment they were taken with
+    bool quiet_tiles = true;             // flags passes may skip quiet tiles (FSA_NO_QUIET_TILES=1:
+                                         // never; tests compare the two)
     int* hv_count = nullptr;
     long long* hv_offset = nullptr;
     long long* hv_total = nullptr;
@@ -479,9 +484,13 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         if (rc != FSA_OK) return rc;
         HIPCHK(c, hipEventRecord(t0, c->stream));
     }
+    // learned form: the stage output's deviation ranges, for the next flags pass
+    S.qrange = (c->d.precision == FSA_LEARNED32 && acc >= 0) ? c->qrange : nullptr;
     e = launch_stage2d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch");
     if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
+    c->qrange_of = S.qrange ? out : nullptr;
+    c->qrange_ty = S.ty;
     if (acc >= 0) defer_alpha_final(c, stage2d_waves(c->G, S.ty), acc);
     return FSA_OK;
 }
@@ -566,7 +575,8 @@ int mlp_alloc(fsa_ctx* c)
         (rc = dalloc(c, c->mlp_m, MLP_NPARAM)) != FSA_OK || (rc = dalloc(c, c->mlp_v, MLP_NPARAM)) != FSA_OK ||
         (rc = dalloc(c, c->mlp_grad, MLP_NPARAM)) != FSA_OK ||
         (rc = dalloc(c, c->mlp_partial, (size_t)512 * MLP_NPARAM)) != FSA_OK ||
-        (rc = dalloc(c, c->mlp_loss_part, 512)) != FSA_OK || (rc = dalloc(c, c->counters, 3 * (size_t)flags2d_blocks(c->G))) != FSA_OK)
+        (rc = dalloc(c, c->mlp_loss_part, 512)) != FSA_OK || (rc = dalloc(c, c->counters, 3 * (size_t)flags2d_blocks(c->G))) != FSA_OK ||
+        (rc = dalloc(c, c->qrange, 8 * (size_t)stage2d_waves(c->G, 4))) != FSA_OK)
         return rc;
     HIPCHK(c, hipMemset(c->counters, 0, 3 * (size_t)flags2d_blocks(c->G) * sizeof(unsigned long long)));
     return FSA_OK;
@@ -586,6 +596,13 @@ int enqueue_flags(fsa_ctx* c, const double* Qs, const unsigned long long* bits, 
     F.flags_x = fx;
     F.flags_y = fy;
     F.counters = c->counters;
+    // tiles of a quiet region skip the state when Qs is the output of the last learned stage
+    if (c->quiet_tiles && c->qrange_of != nullptr && c->qrange_of == Qs && fx == c->flags_x) {
+        F.qrange = c->qrange;
+        F.qr_ty = c->qrange_ty;
+        F.qr_ncolx = stage2d_ncolx(c->G.n[0]);
+        F.qr_w = stage2d_strip_width();
+    }
     int e = launch_flags2d(c->dK, c->G, F, c->stream);
     return e ? hipcheck(c, (hipError_t)e, "flags launch") : FSA_OK;
 }
@@ -652,6 +669,7 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
     build_consts(c);
     c->ncell = c->G.ncell;
     c->ty = env_ty();
+    if (const char* e = std::getenv("FSA_NO_QUIET_TILES")) c->quiet_tiles = std::atoi(e) == 0;
     if ((rc = dalloc(c, c->Qa, (size_t)c->nq * c->ncell)) != FSA_OK ||
         (rc = dalloc(c, c->Qb, (size_t)c->nq * c->ncell)) != FSA_OK ||
         (rc = dalloc(c, c->abits, 12)) != FSA_OK || (rc = dalloc(c, c->dK, 1)) != FSA_OK ||
@@ -744,6 +762,7 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->flags_x);
     dfree(c->flags_y);
     dfree(c->counters);
+    dfree(c->qrange);
     dfree(c->hv_count);
     dfree(c->hv_offset);
     dfree(c->hv_total);
@@ -843,6 +862,7 @@ int32_t fsa_rk3_steps(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps)
     if (nsteps < 1) return fail(c, FSA_EINVAL, "nsteps must be positive");
     int rc = check_previous(c);
     if (rc != FSA_OK) return rc;
+    c->qrange_of = nullptr;   // d_Q may have changed since the last call
     static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
     static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
     // the wave speeds of every stage input come from the kernel that wrote it, except for

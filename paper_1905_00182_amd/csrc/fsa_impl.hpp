@@ -22,6 +22,9 @@ struct StageArgs {
     long long step;                        // step counter (inflow-noise counter)
     const unsigned* flags_x;               // learned form: keep patterns of the x faces
     const unsigned* flags_y;               // and of the y faces
+    float* qrange;                         // learned form, if set (with alpha_part): per strip and
+                                           // segment [segment][strip][8], the least and the largest
+                                           // FP32 deviation of rho, u, v, p of the cells written
 };
 
 // Arguments of the per-stage immersed-boundary kernel.
@@ -64,6 +67,7 @@ long long stress3d_elems(const Grid& G);
 long long faces3d_elems(const Grid& G);
 long long stage3d_blocks(const Grid& G);
 int stage2d_ncolx(int nx);
+int stage2d_strip_width();
 // Wave speeds max over cells of |u_d| + c of Q into bits[3]: per-block partials in part
 // (ALPHA_MAX_BLOCKS x 3), then launch_alpha_final.  No same-address atomics.
 constexpr int ALPHA_MAX_BLOCKS = 2048;

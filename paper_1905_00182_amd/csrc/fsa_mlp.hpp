@@ -34,6 +34,9 @@ struct FlagArgs {
     unsigned* flags_y;                     // [nx (ny+1)]
     unsigned long long* counters;          // accumulated per block [flags2d_blocks][3]: face sides,
                                            // fallback sides, significant sides
+    const float* qrange;                   // if set: deviation ranges of Q per stage-kernel strip and
+    int qr_ty, qr_ncolx, qr_w;             // segment (rows per segment, strips per row of segments,
+                                           // columns per strip)
 };
 
 struct HarvestArgs {

@@ -355,6 +355,77 @@ __global__ __launch_bounds__(256) void k_flags2d(const KConst* __restrict__ K, F
     const int x0 = blockIdx.x * FT_X, y0 = blockIdx.y * FT_Y;
     const long long ncell = K->G.ncell;
 
+    // ---- quiet tile: when every strip and segment of the stage kernel that wrote Q and that
+    // holds a cell of this tile (with its halo; ghosts only on zero-gradient sides, which copy
+    // such cells) spreads by no more than the thresholds, so does every stencil of the tile (a
+    // rounded max - min over a subset cannot exceed the rounded one over the union), and every
+    // side is insignificant: the words are written without loading the state.
+    if (A.qrange) {
+        __shared__ int quiet;
+        if (w == 0) {
+            const int xa = x0 - 3, xb = x0 + LT_X - 4, ya = y0 - 3, yb = y0 + LT_Y - 4;
+            bool ok = (xa >= 0 || K->G.bc[0][0] == BC_EXTRAP) && (xb < nx || K->G.bc[0][1] == BC_EXTRAP) &&
+                      (ya >= 0 || K->G.bc[1][0] == BC_EXTRAP) && (yb < ny || K->G.bc[1][1] == BC_EXTRAP);
+            const int sa = max(xa, 0) / A.qr_w, sb = min(xb, nx - 1) / A.qr_w;
+            const int ga = max(ya, 0) / A.qr_ty, gb = min(yb, ny - 1) / A.qr_ty;
+            const int ns = sb - sa + 1, nwav = ns * (gb - ga + 1);
+            ok = ok && nwav <= 64;
+            float mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY}, mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+            if (ok && lane < nwav) {
+                const int s = sa + lane % ns, gseg = ga + lane / ns;
+                const float* q = A.qrange + ((long long)gseg * A.qr_ncolx + s) * 8;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    mn[m] = q[2 * m];
+                    mx[m] = q[2 * m + 1];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    mn[m] = fminf(mn[m], __shfl_xor(mn[m], off, 64));
+                    mx[m] = fmaxf(mx[m], __shfl_xor(mx[m], off, 64));
+                }
+            const float th[4] = {(float)K->sig[0], (float)K->sig[1], (float)K->sig[1], (float)K->sig[2]};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) ok = ok && !(mx[m] - mn[m] > th[m]);
+            if (lane == 0) quiet = ok ? 1 : 0;
+        }
+        __syncthreads();
+        if (quiet) {
+            int n_sides = 0;
+            for (int pass = 0; pass < 8; ++pass) {
+                const int dir = pass >> 2, rs = 4 * w + (pass & 3);
+                if (dir == 0) {
+                    const int fi = x0 + lane - 1, fj = y0 + rs;
+                    if (fj < ny && fi + 1 <= nx) {
+                        A.flags_x[(long long)fj * (nx + 1) + (fi + 1)] = 0x0FFF0FFFu;
+                        n_sides += 2;
+                    }
+                } else {
+                    const int fi = x0 + lane, fj = y0 + rs - 1;
+                    if (fi < nx && fj + 1 <= ny) {
+                        A.flags_y[(long long)(fj + 1) * nx + fi] = 0x0FFF0FFFu;
+                        n_sides += 2;
+                    }
+                }
+            }
+            if (A.counters) {
+                __shared__ int qcnt[4];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) n_sides += __shfl_xor(n_sides, off, 64);
+                if (lane == 0) qcnt[w] = n_sides;
+                __syncthreads();
+                if (tid == 0) {
+                    const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+                    A.counters[blk * 3] += (unsigned long long)(qcnt[0] + qcnt[1] + qcnt[2] + qcnt[3]);
+                }
+            }
+            return;
+        }
+    }
+
     // ---- the tile's cells (halo 3) as FP32 deviations from the far field: every interior
     // load of the thread is issued before any is used (one memory latency, not seven)
     constexpr int NT = LT_X * LT_Y, PER = (NT + 255) / 256;

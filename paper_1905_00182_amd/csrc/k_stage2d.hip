@@ -173,6 +173,8 @@ struct Column2D {
     bool x_inflow;                  // this lane is an inflow ghost column
     bool out_lane;
     bool want_alpha;
+    float* qrange;                  // learned form: deviation ranges of the output (or null)
+    float (*rng)[WAVE];             // LDS [8][lane]: this lane's least / largest output deviations
     double sg_x;                    // sponge rate sigma * eta^3 of this lane's column
     double sg_rows;                 // FP32 forms: sponge rate of row sg_base + lane
     int sg_base;
@@ -475,6 +477,20 @@ struct Column2D {
                     const unsigned long long sy = (unsigned long long)__double_as_longlong(fabs(vn) + cn);
                     amax_x = out_lane ? max_bits(amax_x, sx) : amax_x;
                     amax_y = out_lane ? max_bits(amax_y, sy) : amax_y;
+                    if constexpr (SCHEME == LEARNED) {
+                        // the FP32 deviations the next flags pass forms from this output (same
+                        // expressions), for its test of tiles whose stencils are all
+                        // insignificant
+                        const float d[4] = {(float)(val[0] - K->P.prim_inf[0]), (float)(un - uinf),
+                                            (float)(vn - vinf), (float)(pn - K->P.prim_inf[4])};
+                        if (qrange && out_lane) {
+#pragma unroll
+                            for (int m = 0; m < 4; ++m) {
+                                rng[2 * m][lane] = fminf(rng[2 * m][lane], d[m]);
+                                rng[2 * m + 1][lane] = fmaxf(rng[2 * m + 1][lane], d[m]);
+                            }
+                        }
+                    }
                 }
             }
         }
@@ -592,6 +608,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         C.txy[s] = C.tyy[s] = T(0);
     }
     C.want_alpha = A.alpha_part != nullptr;
+    C.qrange = A.qrange;
+    __shared__ float rng[SCHEME == LEARNED ? 8 : 1][WAVE];   // (the other forms keep no ranges)
+    C.rng = rng;
+    if constexpr (SCHEME == LEARNED) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) rng[m][threadIdx.x] = (m & 1) ? -INFINITY : INFINITY;
+    }
     C.amax_x = C.amax_y = 0ull;
     const int Rend = C.j1 + HALO;
 #pragma unroll
@@ -627,6 +650,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
             const long long wv = (long long)blockIdx.y * gridDim.x + blockIdx.x;
             A.alpha_part[wv * 3 + lane] = lane == 0 ? mx : (lane == 1 ? my : 0ull);
         }
+        if constexpr (SCHEME == LEARNED) {
+            if (C.qrange) {
+                float r[8];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    float a = rng[2 * m][lane], b = rng[2 * m + 1][lane];
+#pragma unroll
+                    for (int off = 32; off > 0; off >>= 1) {
+                        a = fminf(a, __shfl_xor(a, off, WAVE));
+                        b = fmaxf(b, __shfl_xor(b, off, WAVE));
+                    }
+                    r[2 * m] = a;
+                    r[2 * m + 1] = b;
+                }
+                // indexed by the strip and segment this wave computed (not its launch slot)
+                float v = r[0];
+#pragma unroll
+                for (int k = 1; k < 8; ++k) v = lane == k ? r[k] : v;
+                if (lane < 8) C.qrange[((long long)by * gridDim.x + bx) * 8 + lane] = v;
+            }
+        }
     }
 }
 
@@ -650,6 +694,8 @@ int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, co
 }
 
 int stage2d_ncolx(int nx) { return (nx + OUTW - 1) / OUTW; }
+
+int stage2d_strip_width() { return OUTW; }
 
 long long stage2d_waves(const Grid& G, int ty)
 {

@@ -320,3 +320,32 @@ def test_learned_acoustic_error_config2_small(torch_cuda, trained, stride):
     c = trained["c2"]
     res = _learned_vs_oracle(torch_cuda, c, W.config2_state(c), trained["theta"], 150, stride)
     assert res["learned32"][0] < 1e-2
+
+
+@pytest.mark.parametrize("stride", [1, 3])
+def test_quiet_tiles_change_nothing(torch_cuda, trained, stride):
+    """The flags pass writes all-kept words for tiles whose covering stage-kernel strips spread
+    by no more than the significance thresholds, without loading the state; the run must be
+    bit for bit the one that evaluates every tile (FSA_NO_QUIET_TILES=1)."""
+    import os
+
+    c = trained["c2"].with_(precision="learned32", extra={"selector_stride": stride})
+    Q0 = torch_cuda.from_numpy(W.config2_state(c)).cuda()
+    out = []
+    for off in ("0", "1"):
+        os.environ["FSA_NO_QUIET_TILES"] = off
+        try:
+            s = _solver(c)
+        finally:
+            del os.environ["FSA_NO_QUIET_TILES"]
+        s.mlp_set(trained["theta"], 0.8)
+        Q = Q0.clone()
+        s.rk3_steps(Q, c.dt, 40)
+        s.rk3_steps(Q, c.dt, 20)
+        s.sync()
+        st = s.stats()
+        out.append((Q, st.significant_sides, st.fallback_sides, st.learned_sides))
+        s.close()
+    _say("quiet tiles, stride", stride, ": significant / fallback / sides", out[0][1:], "vs", out[1][1:])
+    assert out[0][1:] == out[1][1:]
+    assert torch_cuda.equal(out[0][0], out[1][0])
