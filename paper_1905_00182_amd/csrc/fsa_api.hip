@@ -423,13 +423,16 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         A.ca = ca;
         A.cb = cb;
         A.dt = dt;
-        // the previous stage's wave-speed reduction rides on the window launch
-        A.alpha_part = c->fin_n > 0 ? c->apart : nullptr;
-        A.alpha_n = c->fin_n;
+        // the previous stage's wave-speed reduction rides on the window launch when its
+        // partials are few (2D: one per wave); the 3D stage's many block partials keep the
+        // wider standalone reduction
+        const bool carry = c->fin_n > 0 && c->fin_n <= 16384;
+        A.alpha_part = carry ? c->apart : nullptr;
+        A.alpha_n = carry ? c->fin_n : 0;
         A.alpha_bits = c->fin_bits;
         e = launch_ib_stage(c->G, c->P, A, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "IB stage launch");
-        c->fin_n = 0;
+        if (carry) c->fin_n = 0;
     }
     if ((e = flush_alpha_final(c)) != FSA_OK) return e;
     if (c->d.precision == FSA_LEARNED32) {
