@@ -242,7 +242,7 @@ void far_field_fluxes(const fsa_ctx* c, KConst& k)
 // Rows per wave segment of the 2D stage kernel.  The best value depends on how the waves
 // fill the chip (occupancy, tail of the last wave round), which no simple model predicts, so
 // it is measured: on the first launch of a context every candidate is timed on the caller's
-// data in right-hand-side mode into a scratch buffer, and the fastest is kept.  The
+// data as an SSP-RK3 stage into a scratch buffer, and the fastest is kept.  The
 // segmentation changes no result: every face is computed from the same inputs whichever
 // segment computes it.  FSA_STAGE_TY fixes the value instead (tuning runs, tests).
 int env_ty()
@@ -522,11 +522,17 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
             }
         }
     }
+    // timed as an SSP-RK3 middle stage (step-start state read, combination, wave-speed
+    // partials), the work the height is chosen for; the output goes to a scratch buffer and
+    // the partials are overwritten by the real launch
     StageArgs S = S0;
-    S.mode_rhs = 1;
+    S.mode_rhs = 0;
+    S.Qn = S0.Qs;
+    S.ca = 0.75;
+    S.cb = 0.25;
     S.out = c->Qb;
-    S.Qn = nullptr;
-    S.alpha_part = nullptr;
+    S.alpha_part = c->apart;
+    S.qrange = nullptr;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));

@@ -160,7 +160,7 @@ struct Column2D {
     // far-field constants used per row, read once at kernel start: a load from the constant
     // block inside the march waits for every LDS access in flight (FP32 forms; the FP64
     // kernel has no registers to spare and reads them where they are used)
-    double qinf[4], Fxinf[4], Fyinf[4], uinf, vinf, gamma;
+    double qinf[4], Fxinf[4], Fyinf[4], rinf, uinf, vinf, pinf, gamma;
     int wlo0, wlo1, wn0, wn1;
     double ax, ay, inv_h, gm1, ca, cb, dt;
     T inv_hT, inv12h, mu;
@@ -481,8 +481,8 @@ struct Column2D {
                         // the FP32 deviations the next flags pass forms from this output (same
                         // expressions), for its test of tiles whose stencils are all
                         // insignificant
-                        const float d[4] = {(float)(val[0] - K->P.prim_inf[0]), (float)(un - uinf),
-                                            (float)(vn - vinf), (float)(pn - K->P.prim_inf[4])};
+                        const float d[4] = {(float)(val[0] - rinf), (float)(un - uinf), (float)(vn - vinf),
+                                            (float)(pn - pinf)};
                         if (qrange && out_lane) {
 #pragma unroll
                             for (int m = 0; m < 4; ++m) {
@@ -529,8 +529,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         C.Fxinf[c] = K->Fx_inf[c];
         C.Fyinf[c] = K->Fy_inf[c];
     }
+    C.rinf = K->P.prim_inf[0];
     C.uinf = K->P.prim_inf[1];
     C.vinf = K->P.prim_inf[2];
+    C.pinf = K->P.prim_inf[4];
     C.gamma = K->P.gamma;
     C.sigma = (K->P.terms & T_SPONGE) ? K->P.sigma : 0.0;
     C.wlo0 = A.wlo[0];
