@@ -536,8 +536,9 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    // each candidate's time is the least of three launches after a warm-up pass (single
-    // launches of ~0.3 ms vary by a few percent, as much as neighbouring candidates differ)
+    // each candidate's time is the least of three samples after a warm-up pass, a sample being
+    // three back-to-back launches (as the stages run; single launches of ~0.3 ms vary by a few
+    // percent, as much as neighbouring candidates differ)
     std::vector<float> tmin(cand.size(), 1e30f);
     for (int rep = 0; rep < 4; ++rep)
         for (size_t k = 0; k < cand.size(); ++k) {
@@ -545,8 +546,10 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
             if (ty > 2 * c->G.n[1] && ty != cand[0]) continue;
             S.ty = ty;
             HIPCHK(c, hipEventRecord(e0, c->stream));
-            int e = launch_stage2d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stream);
-            if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch (tuning)");
+            for (int l = 0; l < 3; ++l) {
+                int e = launch_stage2d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stream);
+                if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch (tuning)");
+            }
             HIPCHK(c, hipEventRecord(e1, c->stream));
             HIPCHK(c, hipEventSynchronize(e1));
             float ms = 0.0f;

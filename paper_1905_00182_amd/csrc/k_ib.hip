@@ -183,9 +183,9 @@ __global__ __launch_bounds__(64) void k_ib_markers(Grid G, IBArgs A)
                 if (DIM == 3) W = W * w[2][mz];
                 const long long lin =
                     ((long long)(DIM == 3 ? j0[2] + mz : 0) * G.n[1] + (j0[1] + my)) * G.n[0] + (j0[0] + mx);
-                const double rho = A.Qs[lin];
+                const double irho = rcp_nr(A.Qs[lin]);   // one refined reciprocal, not DIM divisions
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) uib[a] = fma(A.Qs[(1 + a) * nc + lin] / rho, W, uib[a]);
+                for (int a = 0; a < DIM; ++a) uib[a] = fma(A.Qs[(1 + a) * nc + lin] * irho, W, uib[a]);
             }
     double U[DIM];
     if (A.motion == 1) {

@@ -484,10 +484,13 @@ struct Column2D {
                         const float d[4] = {(float)(val[0] - rinf), (float)(un - uinf), (float)(vn - vinf),
                                             (float)(pn - pinf)};
                         if (qrange && out_lane) {
+                            // LDS min / max without a returned value: nothing waits on them
 #pragma unroll
                             for (int m = 0; m < 4; ++m) {
-                                rng[2 * m][lane] = fminf(rng[2 * m][lane], d[m]);
-                                rng[2 * m + 1][lane] = fmaxf(rng[2 * m + 1][lane], d[m]);
+                                __hip_atomic_fetch_min(&rng[2 * m][lane], d[m], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                                __hip_atomic_fetch_max(&rng[2 * m + 1][lane], d[m], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
                             }
                         }
                     }
