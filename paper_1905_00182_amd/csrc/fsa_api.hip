@@ -77,6 +77,8 @@ struct fsa_ctx {
     unsigned* flags_y = nullptr;
     unsigned long long* counters = nullptr;
     float* qrange = nullptr;             // learned form: deviation ranges of the last stage output
+    double* ghosts = nullptr;            // 2D with an inflow side: inflow ghost states of one step
+    long long ghosts_step = -1;          // the step they hold (-1: none)
     const double* qrange_of = nullptr;   // the buffer they describe (null: none valid)
     int qrange_ty = 0;                   // rows per segment they were taken with
     bool quiet_tiles = true;             // flags passes may skip quiet tiles (FSA_NO_QUIET_TILES=1:
@@ -447,7 +449,7 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     StageArgs S;
     std::memset(&S, 0, sizeof S);
     S.Qs = Qs;
-    S.Qn = Qn;
+    S.Qn = Qn ? Qn : Qs;   // (right-hand-side mode: read but not used)
     S.out = out;
     S.flags_x = c->flags_x;
     S.flags_y = c->flags_y;
@@ -476,6 +478,13 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         if (acc >= 0) defer_alpha_final(c, stage3d_blocks(c->G), acc);
         return FSA_OK;
     }
+    if (c->ghosts && c->ghosts_step != c->step) {
+        // inflow ghost states of this step, shared by its stages
+        e = launch_inflow_ghosts2d(c->dK, c->G, c->step, c->ghosts, c->stream);
+        if (e) return hipcheck(c, (hipError_t)e, "inflow ghost launch");
+        c->ghosts_step = c->step;
+    }
+    S.ghosts = c->ghosts;
     if (c->ty == 0) {
         int rc = tune_ty(c, S);
         if (rc != FSA_OK) return rc;
@@ -692,6 +701,11 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
         fsa_destroy(c);
         return rc;
     }
+    if (c->G.dim == 2 && has_inflow(c->G) &&
+        (rc = dalloc(c, c->ghosts, (size_t)inflow_ghosts2d_elems(c->G))) != FSA_OK) {
+        fsa_destroy(c);
+        return rc;
+    }
     if (c->G.dim == 3) {
         const size_t tsize = desc->precision == FSA_MIXED32 ? sizeof(float) : sizeof(double);
         if ((rc = dalloc(c, c->stress3d, (size_t)stress3d_elems(c->G) * tsize)) != FSA_OK ||
@@ -775,6 +789,7 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->flags_y);
     dfree(c->counters);
     dfree(c->qrange);
+    dfree(c->ghosts);
     dfree(c->hv_count);
     dfree(c->hv_offset);
     dfree(c->hv_total);

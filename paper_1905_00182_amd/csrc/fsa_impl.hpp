@@ -8,7 +8,8 @@ namespace fsa {
 // Arguments of the fused right-hand-side / stage kernels.
 struct StageArgs {
     const double* Qs;                      // state the right-hand side is evaluated on
-    const double* Qn;                      // step-start state (read only when ca != 0)
+    const double* Qn;                      // step-start state (used only when ca != 0; 2D: loaded
+                                           // in every stage, so never null there)
     double* out;                           // L (mode_rhs) or ca Qn + cb (Qs + dt L)
     const unsigned long long* alpha_bits;  // global LF speeds of Qs, as bit patterns [3]
     const double* fwin;                    // IB force density on the window box [dim][cells]
@@ -25,6 +26,8 @@ struct StageArgs {
     float* qrange;                         // learned form, if set (with alpha_part): per strip and
                                            // segment [segment][strip][8], the least and the largest
                                            // FP32 deviation of rho, u, v, p of the cells written
+    const double* ghosts;                  // 2D: inflow ghost states of this step (required when a
+                                           // side is an inflow; see launch_inflow_ghosts2d)
 };
 
 // Arguments of the per-stage immersed-boundary kernel.
@@ -57,6 +60,13 @@ struct IBArgs {
 };
 
 int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, hipStream_t s);
+// 2D inflow ghost states of step `step` (the far field with the seeded perturbation, the
+// values the boundary rule gives the four ghost layers of every inflow side) into g,
+// [component][side][depth - 1][position along the side] with the position stride
+// max(nx, ny); sides that are not inflows are left unwritten.
+long long inflow_ghosts2d_elems(const Grid& G);
+bool has_inflow(const Grid& G);
+int launch_inflow_ghosts2d(const KConst* K, const Grid& G, long long step, double* g, hipStream_t s);
 long long stage2d_waves(const Grid& G, int ty);
 // 3D: stress pass into `stress` ([9][(nx+4)(ny+4)(nz+4)] of T = double, or float in the
 // precision form), face-flux passes into `faces` (faces3d_elems of T), then the stage pass;

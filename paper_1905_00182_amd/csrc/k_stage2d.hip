@@ -22,6 +22,7 @@
 // fluxes minus those of the far-field state, formed in FP64 before rounding; the far-field
 // part cancels exactly in the flux difference, so FP32 only ever carries deviations.  The
 // state, the sources, the RK3 combination and the wave speeds stay FP64.
+#include <algorithm>
 #include <type_traits>
 
 #include "fsa_impl.hpp"
@@ -171,6 +172,11 @@ struct Column2D {
     int xr;                         // resolved x index of this lane
     int i;                          // x index of this lane (a ghost index in the halo)
     bool x_inflow;                  // this lane is an inflow ghost column
+    bool xg_wave;                   // some lane of this wave is (wave-uniform)
+    const double* ghosts;           // inflow ghost states of the step, [c][side][depth-1][along]
+    long long gcs;                  // their component stride
+    int gna;                        // their position stride
+    int gxo;                        // x inflow ghost lanes: offset of their side and depth
     bool out_lane;
     bool want_alpha;
     float* qrange;                  // learned form: deviation ranges of the output (or null)
@@ -194,18 +200,31 @@ struct Column2D {
     double (*ring)[4][WAVE];        // LDS: the last five front rows of this wave, [slot][comp][lane]
     int lane;
 
-    // State of (this lane, row j): interior and periodic/zero-gradient ghosts are loads;
-    // inflow ghosts are built from the far field and the seeded perturbation, replacing the
-    // (in-range, unused) load of their resolved cell.  Loading unconditionally leaves the
-    // previous contents of q dead, so no copies are made around a masked load.
+    // State of (this lane, row j): interior and periodic/zero-gradient ghosts are loads of
+    // their resolved cell; inflow ghosts (an x ghost lane's column, or a whole y ghost row)
+    // are loads from the step's ghost table.  Every lane's q is one load per component, so
+    // no write ever lands on a register a load in flight will fill (such a write would wait
+    // for all loads in flight, the prefetches included).  Waves without inflow ghosts take
+    // the plain path (a wave-uniform branch).
     __device__ __forceinline__ void load_row(int j, double* q) const
     {
         int inflow = 0, side = 0, depth = 0;
         const int jr = resolve_index(j, ny, bcy0, bcy1, 1, inflow, side, depth);
-        const double* p = Qs + (long long)jr * nx + xr;
+        if (xg_wave || inflow) {
+            // an x inflow side comes first, as in the boundary rule (x, then y)
+            const bool g = x_inflow || inflow;
+            const long long o = x_inflow ? (long long)gxo + jr
+                                         : (inflow ? (long long)(side * HALO + depth - 1) * gna + xr
+                                                   : (long long)jr * nx + xr);
+            const double* p = (g ? ghosts : Qs) + o;
+            const long long cs = g ? gcs : ncell;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) q[c] = p[c * ncell];
-        if (x_inflow || inflow) fetch_state<2>(Qs, K->G, K->P, step, i, j, 0, q);
+            for (int c = 0; c < 4; ++c) q[c] = p[c * cs];
+        } else {
+            const double* p = Qs + (long long)jr * nx + xr;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) q[c] = p[c * ncell];
+        }
     }
 
     // Split fluxes f+- = (F +- alpha Q)/2 of component c of one direction, as stored in the
@@ -238,14 +257,16 @@ struct Column2D {
     // Step-start state Qn of output row r for this lane (issued PF steps before it is used,
     // so the load latency hides behind rows of work).  Rows outside the segment and halo
     // lanes load an in-range cell whose value is not used (a cache hit on a row the wave
-    // loads anyway), so the load needs no lane mask.
+    // loads anyway), so the load needs no lane mask.  Issued in every stage, also where the
+    // combination does not read it (Qn is then the stage input): four loads that always
+    // follow the front-row load let the wait for that load, one step later, leave the
+    // younger loads and the stores in flight; with an issue that depended on the stage, the
+    // wait would have to assume none follow and drain everything.
     __device__ __forceinline__ void load_qn(int r, int slot)
     {
-        if (!mode_rhs && ca != 0.0) {
-            const long long o = (long long)min(max(r, j0), j1) * nx + xr;
+        const long long o = (long long)min(max(r, j0), j1) * nx + xr;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) qn_pf[slot][c] = Qn[c * ncell + o];
-        }
+        for (int c = 0; c < 4; ++c) qn_pf[slot][c] = Qn[c * ncell + o];
     }
 
     // Force-window values (f_x, f_y) of output row r at this lane's column, issued PF steps
@@ -593,6 +614,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         int inflow = 0, side = 0, depth = 0;
         C.xr = resolve_index(C.i, nx, K->G.bc[0][0], K->G.bc[0][1], 0, inflow, side, depth);
         C.x_inflow = inflow != 0;
+        C.ghosts = A.ghosts;
+        C.gna = max(nx, K->G.n[1]);
+        C.gcs = 4ll * HALO * C.gna;
+        C.gxo = C.x_inflow ? (side * HALO + depth - 1) * C.gna : 0;
+        C.xg_wave = __ballot(C.x_inflow) != 0ull;
         C.out_lane = lane >= HALO && lane < WAVE - HALO && i < nx;
     }
     C.sg_x = C.out_lane ? C.sponge_rate(K->eta_dir(0, C.i)) : 0.0;
@@ -625,6 +651,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
     for (int s = 0; s < C.PF; ++s) {
         C.load_row(C.j0 - HALO + s, C.qf[s]);
+        // the row's loads go out before the others, as in the march, so that the wait for
+        // them at the loop head can leave the younger loads in flight
+        __builtin_amdgcn_sched_barrier(0);
         C.wy_pf[s] = C.wx_pf[s] = 0u;
         C.load_patterns(C.j0 - HALO + s, s);
 #pragma unroll
@@ -679,10 +708,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
 }
 
+// Inflow ghost table of one step: thread (t, side * HALO + depth - 1) forms the state of
+// the ghost cell `depth` layers beyond side `side` (0: x-, 1: x+, 2: y-, 3: y+) at position t
+// along it, by the boundary rule used everywhere else (indices resolved x first, then y;
+// the far field with the seeded perturbation of the resolved cell), bit for bit.
+__global__ __launch_bounds__(256) void k_inflow_ghosts2d(const KConst* __restrict__ K, long long step,
+                                                         double* __restrict__ g)
+{
+    const Grid& G = K->G;
+    const int side = blockIdx.y / HALO, depth = blockIdx.y % HALO + 1, dir = side >> 1;
+    const int na = max(G.n[0], G.n[1]);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= G.n[dir ^ 1] || G.bc[dir][side & 1] != BC_INFLOW) return;
+    const int across = (side & 1) ? G.n[dir] - 1 + depth : -depth;
+    int inflow = 0, s = 0, d = 0;
+    const int ir = resolve_index(dir == 0 ? across : t, G.n[0], G.bc[0][0], G.bc[0][1], 0, inflow, s, d);
+    const int jr = resolve_index(dir == 0 ? t : across, G.n[1], G.bc[1][0], G.bc[1][1], 1, inflow, s, d);
+    double q[4];
+    inflow_state<2>(K->P, step, G.ncell, (long long)jr * G.n[0] + ir, s, d, q);
+    const long long o = (long long)(side * HALO + depth - 1) * na + t;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) g[c * 4ll * HALO * na + o] = q[c];
+}
+
 }  // namespace
 
 int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, hipStream_t s)
 {
+    if (has_inflow(G) && !A.ghosts) return (int)hipErrorInvalidValue;   // inflow sides need the ghost table
+    if (!A.Qn) return (int)hipErrorInvalidValue;                          // read in every stage
     const int ncolx = (G.n[0] + OUTW - 1) / OUTW;
     const int nseg = (G.n[1] + A.ty - 1) / A.ty;
     dim3 grid(ncolx, nseg), block(WAVE);
@@ -695,6 +749,23 @@ int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, co
         if (scheme == TENO5) hipLaunchKernelGGL((k_stage2d<TENO5, double>), grid, block, 0, s, K, A);
         else hipLaunchKernelGGL((k_stage2d<WENO5JS, double>), grid, block, 0, s, K, A);
     }
+    return (int)hipGetLastError();
+}
+
+bool has_inflow(const Grid& G)
+{
+    for (int d = 0; d < 2; ++d)
+        for (int e = 0; e < 2; ++e)
+            if (G.bc[d][e] == BC_INFLOW) return true;
+    return false;
+}
+
+long long inflow_ghosts2d_elems(const Grid& G) { return 4ll * 4 * HALO * std::max(G.n[0], G.n[1]); }
+
+int launch_inflow_ghosts2d(const KConst* K, const Grid& G, long long step, double* g, hipStream_t s)
+{
+    const int na = std::max(G.n[0], G.n[1]);
+    hipLaunchKernelGGL(k_inflow_ghosts2d, dim3((na + 255) / 256, 4 * HALO), dim3(256), 0, s, K, step, g);
     return (int)hipGetLastError();
 }
 
