@@ -525,6 +525,17 @@ struct Column2D {
     }
 };
 
+// Wave issue priority (0 lowest .. 3), set with the immediate the instruction takes.
+__device__ __forceinline__ void set_issue_priority(int p)
+{
+    switch (p) {
+    case 3: __builtin_amdgcn_s_setprio(3); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    default: __builtin_amdgcn_s_setprio(0); break;
+    }
+}
+
 template <int SCHEME, class T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_stage2d(
     const KConst* __restrict__ K, StageArgs A)
@@ -661,7 +672,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         C.load_qn(C.j0 - 2 * HALO + s, s);
         C.load_fwin(C.j0 - 2 * HALO + s, s);
     }
+    // Issue priority falls with progress (3 in the first quarter of the segment's rows, 0 in
+    // the last).  The two waves sharing a SIMD otherwise run oldest first: the older one
+    // finishes well ahead and the other then runs alone, with nothing to hide its latency
+    // behind; with the priority the wave that is behind is issued first, and the two stay
+    // within about a quarter of a segment of each other.
+    const int nrow = Rend - (C.j0 - HALO) + 1;
     for (int Rw = C.j0 - HALO; Rw <= Rend; Rw += 5) {
+        set_issue_priority(3 - (Rw - (C.j0 - HALO)) * 4 / nrow);
         C.template step_row<0>(Rw);
         if (Rw + 1 > Rend) break;
         C.template step_row<1>(Rw + 1);
