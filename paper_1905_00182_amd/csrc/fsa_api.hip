@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "fsa.h"
@@ -16,6 +17,9 @@
 #include "fsa_mlp.hpp"
 
 using namespace fsa;
+
+// steps of inflow ghost tables formed per launch
+constexpr int GHOST_STEPS = 16;
 
 struct fsa_ctx {
     fsa_desc d;
@@ -48,6 +52,8 @@ struct fsa_ctx {
     int motion = 0;
     double omega = 0.0;
     double *X = nullptr, *dV = nullptr, *U = nullptr, *xi = nullptr, *xi_n = nullptr, *F = nullptr;
+    double* xi2 = nullptr;               // the other penalty-integral buffer (one-launch IB stages
+                                         // write the update there; the two then swap)
     std::vector<double> hX;
     int wlo[3] = {0, 0, 0}, wn[3] = {0, 0, 0};
     long long wcells = 0;
@@ -77,8 +83,8 @@ struct fsa_ctx {
     unsigned* flags_y = nullptr;
     unsigned long long* counters = nullptr;
     float* qrange = nullptr;             // learned form: deviation ranges of the last stage output
-    double* ghosts = nullptr;            // 2D with an inflow side: inflow ghost states of one step
-    long long ghosts_step = -1;          // the step they hold (-1: none)
+    double* ghosts = nullptr;            // 2D with an inflow side: inflow ghost tables of
+    long long ghosts_step = -1;          // steps ghosts_step .. + GHOST_STEPS - 1 (-1: none)
     const double* qrange_of = nullptr;   // the buffer they describe (null: none valid)
     int qrange_ty = 0;                   // rows per segment they were taken with
     bool quiet_tiles = true;             // flags passes may skip quiet tiles (FSA_NO_QUIET_TILES=1:
@@ -352,6 +358,7 @@ IBArgs ib_args(const fsa_ctx* c)
     A.motion = c->motion;
     A.omega = c->omega;
     A.xi = c->xi;
+    A.xi_out = c->xi;
     A.xi_n = c->xi_n;
     A.F = c->F;
     A.alpha = c->d.ib_alpha;
@@ -432,8 +439,11 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         A.alpha_part = carry ? c->apart : nullptr;
         A.alpha_n = carry ? c->fin_n : 0;
         A.alpha_bits = c->fin_bits;
+        const bool swap_xi = stage > 0 && ib_stage_fused(c->G, c->nm);
+        if (swap_xi) A.xi_out = c->xi2;
         e = launch_ib_stage(c->G, c->P, A, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "IB stage launch");
+        if (swap_xi) std::swap(c->xi, c->xi2);   // (stream-ordered: later launches read the new one)
         if (carry) c->fin_n = 0;
     }
     if ((e = flush_alpha_final(c)) != FSA_OK) return e;
@@ -478,13 +488,14 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         if (acc >= 0) defer_alpha_final(c, stage3d_blocks(c->G), acc);
         return FSA_OK;
     }
-    if (c->ghosts && c->ghosts_step != c->step) {
-        // inflow ghost states of this step, shared by its stages
-        e = launch_inflow_ghosts2d(c->dK, c->G, c->step, c->ghosts, c->stream);
+    if (c->ghosts && (c->ghosts_step < 0 || c->step < c->ghosts_step || c->step >= c->ghosts_step + GHOST_STEPS)) {
+        // inflow ghost tables of this step and the next ones (stream-ordered: stages that
+        // read the previous tables were enqueued before)
+        e = launch_inflow_ghosts2d(c->dK, c->G, c->step, GHOST_STEPS, c->ghosts, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "inflow ghost launch");
         c->ghosts_step = c->step;
     }
-    S.ghosts = c->ghosts;
+    S.ghosts = c->ghosts ? c->ghosts + (c->step - c->ghosts_step) * inflow_ghosts2d_elems(c->G) : nullptr;
     if (c->ty == 0) {
         int rc = tune_ty(c, S);
         if (rc != FSA_OK) return rc;
@@ -702,7 +713,7 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
         return rc;
     }
     if (c->G.dim == 2 && has_inflow(c->G) &&
-        (rc = dalloc(c, c->ghosts, (size_t)inflow_ghosts2d_elems(c->G))) != FSA_OK) {
+        (rc = dalloc(c, c->ghosts, (size_t)GHOST_STEPS * inflow_ghosts2d_elems(c->G))) != FSA_OK) {
         fsa_destroy(c);
         return rc;
     }
@@ -769,6 +780,7 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->dV);
     dfree(c->U);
     dfree(c->xi);
+    dfree(c->xi2);
     dfree(c->xi_n);
     dfree(c->F);
     dfree(c->fwin);
@@ -817,10 +829,12 @@ int32_t fsa_set_markers(fsa_ctx* c, int32_t n, const double* X, const double* dV
     int rc;
     if ((rc = dalloc(c, c->X, ln)) != FSA_OK || (rc = dalloc(c, c->dV, (size_t)(n > 0 ? n : 1))) != FSA_OK ||
         (rc = dalloc(c, c->U, ln)) != FSA_OK || (rc = dalloc(c, c->xi, ln)) != FSA_OK ||
-        (rc = dalloc(c, c->xi_n, ln)) != FSA_OK || (rc = dalloc(c, c->F, ln)) != FSA_OK)
+        (rc = dalloc(c, c->xi2, ln)) != FSA_OK || (rc = dalloc(c, c->xi_n, ln)) != FSA_OK ||
+        (rc = dalloc(c, c->F, ln)) != FSA_OK)
         return rc;
     HIPCHK(c, hipMemset(c->U, 0, sizeof(double) * ln));
     HIPCHK(c, hipMemset(c->xi, 0, sizeof(double) * ln));
+    HIPCHK(c, hipMemset(c->xi2, 0, sizeof(double) * ln));
     HIPCHK(c, hipMemset(c->xi_n, 0, sizeof(double) * ln));
     HIPCHK(c, hipMemset(c->F, 0, sizeof(double) * ln));
     if (n > 0) {

@@ -26,7 +26,7 @@ struct StageArgs {
     float* qrange;                         // learned form, if set (with alpha_part): per strip and
                                            // segment [segment][strip][8], the least and the largest
                                            // FP32 deviation of rho, u, v, p of the cells written
-    const double* ghosts;                  // 2D: inflow ghost states of this step (required when a
+    const double* ghosts;                  // 2D: inflow ghost table of this step (required when a
                                            // side is an inflow; see launch_inflow_ghosts2d)
 };
 
@@ -39,7 +39,9 @@ struct IBArgs {
     const double* U;       // [dim][nm]
     int motion;            // 0 static, 1 rotating, 2 external
     double omega;
-    double* xi;            // penalty integral (stage value, updated in place)
+    double* xi;            // penalty integral (stage value)
+    double* xi_out;        // its update (== xi: in place; ib_stage_fused launches need another
+                           // buffer, which then holds the new value)
     double* xi_n;          // penalty integral at the step start
     double* F;             // penalty force [dim][nm]
     int stage;             // 0: right-hand side only; 1..3: SSP-RK3 stage
@@ -60,13 +62,14 @@ struct IBArgs {
 };
 
 int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, hipStream_t s);
-// 2D inflow ghost states of step `step` (the far field with the seeded perturbation, the
-// values the boundary rule gives the four ghost layers of every inflow side) into g,
+// 2D inflow ghost states of steps step0 .. step0 + nsteps - 1 (the far field with the
+// seeded perturbation, the values the boundary rule gives the four ghost layers of every
+// inflow side) into g, one table of inflow_ghosts2d_elems per step, each
 // [component][side][depth - 1][position along the side] with the position stride
 // max(nx, ny); sides that are not inflows are left unwritten.
 long long inflow_ghosts2d_elems(const Grid& G);
 bool has_inflow(const Grid& G);
-int launch_inflow_ghosts2d(const KConst* K, const Grid& G, long long step, double* g, hipStream_t s);
+int launch_inflow_ghosts2d(const KConst* K, const Grid& G, long long step0, int nsteps, double* g, hipStream_t s);
 long long stage2d_waves(const Grid& G, int ty);
 // 3D: stress pass into `stress` ([9][(nx+4)(ny+4)(nz+4)] of T = double, or float in the
 // precision form), face-flux passes into `faces` (faces3d_elems of T), then the stage pass;
@@ -86,6 +89,9 @@ int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long lo
 // bits[d] = NaN-propagating max over n partials part[k * 3 + d] (d < 3).
 int launch_alpha_final(const unsigned long long* part, long long n, unsigned long long* bits, hipStream_t s);
 int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s);
+// Whether launch_ib_stage takes the one-launch form (which writes the integral's update to a
+// buffer other than xi).
+bool ib_stage_fused(const Grid& G, int nm);
 // Field totals out[m] = sum_cells q_m h^dim (deterministic order; part: totals_part_size doubles)
 // and the dilatation div u at every cell.
 int totals_part_size(int nq);

@@ -154,13 +154,11 @@ __global__ void k_ib_weights(Grid G, IBArgs A, int* __restrict__ mj0, double* __
     }
 }
 
-// Penalty step per marker: U_ib = sum over the support of (m / rho) W, F_f = alpha xi +
-// beta (U_ib - U), and the stage's update of the penalty integral xi.
+// Penalty force of marker k: U_ib = sum over the support of (m / rho) W, d = U_ib - U and
+// F_f = alpha xi + beta d (xi the stage value).  Returns d in dv and F_f in Fk.
 template <int DIM>
-__global__ __launch_bounds__(64) void k_ib_markers(Grid G, IBArgs A)
+__device__ __forceinline__ void marker_force(const Grid& G, const IBArgs& A, int k, double* dv, double* Fk)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.nm) return;
     const long long nc = G.ncell;
     int j0[3];
     double w[3][4];
@@ -173,7 +171,8 @@ __global__ __launch_bounds__(64) void k_ib_markers(Grid G, IBArgs A)
     double uib[DIM];
 #pragma unroll
     for (int a = 0; a < DIM; ++a) uib[a] = 0.0;
-#pragma unroll
+    // (3D: one z layer of 16 cells at a time, so its loads fit the registers)
+#pragma nounroll
     for (int mz = 0; mz < (DIM == 3 ? 4 : 1); ++mz)
 #pragma unroll
         for (int my = 0; my < 4; ++my)
@@ -199,16 +198,38 @@ __global__ __launch_bounds__(64) void k_ib_markers(Grid G, IBArgs A)
     }
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
+        dv[a] = uib[a] - U[a];
+        Fk[a] = fma(A.alpha, A.xi[(long long)a * A.nm + k], A.beta * dv[a]);
+    }
+}
+
+// F_f of marker k, and the stage's update of its penalty integral into xi_out (stage 1 also
+// keeps the step-start value in xi_n).
+template <int DIM>
+__device__ __forceinline__ void marker_update(const IBArgs& A, int k, const double* dv, const double* Fk)
+{
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
         const long long o = (long long)a * A.nm + k;
-        const double d = uib[a] - U[a];
         const double xs = A.xi[o];
         double xn = xs;
         if (A.stage == 1) A.xi_n[o] = xs;
         else if (A.stage > 1) xn = A.xi_n[o];
-        A.F[o] = fma(A.alpha, xs, A.beta * d);
-        if (A.stage == 1) A.xi[o] = fma(A.dt, d, xn);
-        else if (A.stage > 1) A.xi[o] = fma(A.ca, xn, A.cb * fma(A.dt, d, xs));
+        A.F[o] = Fk[a];
+        if (A.stage == 1) A.xi_out[o] = fma(A.dt, dv[a], xn);
+        else if (A.stage > 1) A.xi_out[o] = fma(A.ca, xn, A.cb * fma(A.dt, dv[a], xs));
     }
+}
+
+// Penalty step per marker (xi_out may be xi: each thread reads its values before writing).
+template <int DIM>
+__global__ __launch_bounds__(64) void k_ib_markers(Grid G, IBArgs A)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.nm) return;
+    double dv[DIM], Fk[DIM];
+    marker_force<DIM>(G, A, k, dv, Fk);
+    marker_update<DIM>(A, k, dv, Fk);
 }
 
 // Spread force density on the window box: one wave per window cell; lane l sums the cell's
@@ -243,6 +264,43 @@ __global__ __launch_bounds__(256) void k_ib_window(IBArgs A)
     if (lane == 0) {
 #pragma unroll
         for (int a = 0; a < DIM; ++a) A.fwin[a * wcells + c] = f[a];
+    }
+}
+
+// Penalty step and spreading in one launch (2D, few markers): as k_ib_window, but each lane
+// forms the force of the marker of its CSR entry itself (marker_force, the operations of
+// k_ib_markers, so the same values) instead of reading it from a previous launch.  The entry
+// at the marker's first support cell also writes F and the integral's update, into
+// xi_out != xi (the marker's other entries read xi during the launch).
+__global__ __launch_bounds__(256) void k_ib_fused2d(Grid G, IBArgs A)
+{
+    if (A.alpha_part && blockIdx.x == gridDim.x - 1) {
+        alpha_final_block<256>(A.alpha_part, A.alpha_n, A.alpha_bits);
+        return;
+    }
+    const long long wcells = (long long)A.wn[0] * A.wn[1];
+    const long long c = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (c >= wcells) return;
+    const int ci = A.wlo[0] + (int)(c % A.wn[0]), cj = A.wlo[1] + (int)(c / A.wn[0]);
+    double f[2] = {0.0, 0.0};
+    const int e1 = A.cell_start[c + 1];
+    for (int e = A.cell_start[c] + lane; e < e1; e += 64) {
+        const int k = A.cell_marker[e];
+        const double we = A.cell_w[e];
+        double dv[2], Fk[2];
+        marker_force<2>(G, A, k, dv, Fk);
+        if (ci == A.mj0[k * 3] && cj == A.mj0[k * 3 + 1]) marker_update<2>(A, k, dv, Fk);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) f[a] = fma(-Fk[a], we, f[a]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) f[a] += __shfl_xor(f[a], off, 64);
+    if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) A.fwin[a * wcells + c] = f[a];
     }
 }
 
@@ -426,7 +484,10 @@ int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s
     const unsigned mb = (unsigned)((A.nm + 63) / 64);
     const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
     const unsigned wb = (unsigned)((wcells + 3) / 4) + (A.alpha_part ? 1u : 0u);   // four cells per block
-    if (G.dim == 3) {
+    if (ib_stage_fused(G, A.nm)) {
+        if (A.stage > 0 && A.xi_out == A.xi) return (int)hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_ib_fused2d, dim3(wb), dim3(256), 0, s, G, A);
+    } else if (G.dim == 3) {
         hipLaunchKernelGGL(k_ib_markers<3>, dim3(mb), dim3(64), 0, s, G, A);
         hipLaunchKernelGGL(k_ib_window<3>, dim3(wb), dim3(256), 0, s, A);
     } else {
@@ -435,6 +496,8 @@ int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s
     }
     return (int)hipGetLastError();
 }
+
+bool ib_stage_fused(const Grid& G, int nm) { return G.dim == 2 && nm <= 4096; }
 
 int launch_ib_weights(const Grid& G, const IBArgs& A, int* mj0, double* mw, double* cell_w, hipStream_t s)
 {

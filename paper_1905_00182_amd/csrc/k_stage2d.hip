@@ -726,11 +726,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
 }
 
-// Inflow ghost table of one step: thread (t, side * HALO + depth - 1) forms the state of
-// the ghost cell `depth` layers beyond side `side` (0: x-, 1: x+, 2: y-, 3: y+) at position t
+// Inflow ghost tables of steps step0 .. step0 + gridDim.z - 1 (one per z block index, each
+// inflow_ghosts2d_elems long): thread (t, side * HALO + depth - 1) forms the state of the
+// ghost cell `depth` layers beyond side `side` (0: x-, 1: x+, 2: y-, 3: y+) at position t
 // along it, by the boundary rule used everywhere else (indices resolved x first, then y;
 // the far field with the seeded perturbation of the resolved cell), bit for bit.
-__global__ __launch_bounds__(256) void k_inflow_ghosts2d(const KConst* __restrict__ K, long long step,
+__global__ __launch_bounds__(256) void k_inflow_ghosts2d(const KConst* __restrict__ K, long long step0,
                                                          double* __restrict__ g)
 {
     const Grid& G = K->G;
@@ -743,10 +744,11 @@ __global__ __launch_bounds__(256) void k_inflow_ghosts2d(const KConst* __restric
     const int ir = resolve_index(dir == 0 ? across : t, G.n[0], G.bc[0][0], G.bc[0][1], 0, inflow, s, d);
     const int jr = resolve_index(dir == 0 ? t : across, G.n[1], G.bc[1][0], G.bc[1][1], 1, inflow, s, d);
     double q[4];
-    inflow_state<2>(K->P, step, G.ncell, (long long)jr * G.n[0] + ir, s, d, q);
+    inflow_state<2>(K->P, step0 + blockIdx.z, G.ncell, (long long)jr * G.n[0] + ir, s, d, q);
+    double* gz = g + (long long)blockIdx.z * (16ll * HALO * na);
     const long long o = (long long)(side * HALO + depth - 1) * na + t;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) g[c * 4ll * HALO * na + o] = q[c];
+    for (int c = 0; c < 4; ++c) gz[c * 4ll * HALO * na + o] = q[c];
 }
 
 }  // namespace
@@ -780,10 +782,11 @@ bool has_inflow(const Grid& G)
 
 long long inflow_ghosts2d_elems(const Grid& G) { return 4ll * 4 * HALO * std::max(G.n[0], G.n[1]); }
 
-int launch_inflow_ghosts2d(const KConst* K, const Grid& G, long long step, double* g, hipStream_t s)
+int launch_inflow_ghosts2d(const KConst* K, const Grid& G, long long step0, int nsteps, double* g, hipStream_t s)
 {
     const int na = std::max(G.n[0], G.n[1]);
-    hipLaunchKernelGGL(k_inflow_ghosts2d, dim3((na + 255) / 256, 4 * HALO), dim3(256), 0, s, K, step, g);
+    if (nsteps < 1 || nsteps > 65535) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_inflow_ghosts2d, dim3((na + 255) / 256, 4 * HALO, nsteps), dim3(256), 0, s, K, step0, g);
     return (int)hipGetLastError();
 }
 
