@@ -182,7 +182,7 @@ struct Column2D {
     float* qrange;                  // learned form: deviation ranges of the output (or null)
     float (*rng)[WAVE];             // LDS [8][lane]: this lane's least / largest output deviations
     double sg_x;                    // sponge rate sigma * eta^3 of this lane's column
-    double sg_rows;                 // FP32 forms: sponge rate of row sg_base + lane
+    double sg_rows;                 // sponge rate of row sg_base + lane
     int sg_base;
     unsigned long long amax_x, amax_y;
     long long step;
@@ -285,30 +285,29 @@ struct Column2D {
     }
 
     __device__ __forceinline__ double q_inf(int c) const { return F64 ? K->P.q_inf[c] : qinf[c]; }
-    __device__ __forceinline__ double gam() const { return F64 ? K->P.gamma : gamma; }
+    // gamma (FP64: formed as (gamma - 1) + 1, which is exact, gamma - 1 being exact for
+    // gamma > 1: no scalar load inside the march)
+    __device__ __forceinline__ double gam() const { return F64 ? gm1 + 1.0 : gamma; }
 
     // Sponge rate sigma * eta^3 (zero when the sponge term is off).
     __device__ __forceinline__ double sponge_rate(double eta) const { return sigma * (eta * eta * eta); }
 
-    // Sponge rate sigma * eta_y^3 of row r.  FP32 forms: each lane holds the rate of one of 64
+    // Sponge rate sigma * eta_y^3 of row r.  Each lane holds the rate of one of 64
     // consecutive rows, refilled when r leaves them (r increases by one per call; called with
     // all lanes active), and the row's value is a lane read instead of the profile arithmetic
-    // and its constant-block loads.
+    // and its constant-block loads (scalar loads in the march wait for every LDS access in
+    // flight).
     __device__ __forceinline__ double sponge_row(int r)
     {
-        if constexpr (F64) {
-            return sponge_rate(K->eta_dir(1, r));
-        } else {
-            if (r - sg_base >= WAVE) {
-                sg_base = r;
-                sg_rows = sponge_rate(K->eta_dir(1, r + lane));
-            }
-            const int k = r - sg_base;
-            const long long b = __double_as_longlong(sg_rows);
-            const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
-            const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
-            return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+        if (r - sg_base >= WAVE) {
+            sg_base = r;
+            sg_rows = sponge_rate(K->eta_dir(1, r + lane));
         }
+        const int k = r - sg_base;
+        const long long b = __double_as_longlong(sg_rows);
+        const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+        return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
     }
 
     template <int K5>
@@ -413,7 +412,7 @@ struct Column2D {
 
         // ---- output row r = Rw-4
         if (do_out) {
-            // (a wave-uniform point: the FP32 forms' lane table is refilled by every lane)
+            // (a wave-uniform point: the lane table of sponge rates is refilled by every lane)
             const double sg_y = sponge_row(r);
             double ur, vr;
             if (F64) {
@@ -475,8 +474,12 @@ struct Column2D {
                 // eta, rounded the same way for both; zero without a sponge)
                 const double sg = fmax(sg_x, sg_y);
                 double s[4] = {0.0, f0, f1, fma(f0, ur, f1 * vr)};
+                // (FP64: only where the rate is not zero, where the term adds exact zeros, so
+                // that the far-field state is read from the constant block in sponge waves only)
+                if (!F64 || sg != 0.0) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) s[c] = fma(-sg, qr[c] - q_inf(c), s[c]);
+                    for (int c = 0; c < 4; ++c) s[c] = fma(-sg, qr[c] - q_inf(c), s[c]);
+                }
                 double val[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
