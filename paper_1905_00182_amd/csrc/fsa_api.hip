@@ -556,11 +556,11 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    // each candidate's time is the least of three samples after a warm-up pass, a sample being
+    // each candidate's time is the least of six samples after a warm-up pass, a sample being
     // three back-to-back launches (as the stages run; single launches of ~0.3 ms vary by a few
     // percent, as much as neighbouring candidates differ)
     std::vector<float> tmin(cand.size(), 1e30f);
-    for (int rep = 0; rep < 4; ++rep)
+    for (int rep = 0; rep < 7; ++rep)
         for (size_t k = 0; k < cand.size(); ++k) {
             const int ty = cand[k];
             if (ty > 2 * c->G.n[1] && ty != cand[0]) continue;
@@ -576,13 +576,14 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
             HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
             if (rep > 0) tmin[k] = std::min(tmin[k], ms);   // the first pass warms caches and clocks
         }
-    int best = 16;
+    // the tallest segments (fewest halo rows) among the candidates within 1% of the fastest:
+    // closer than that, the order of two candidates changes from run to run
     float best_ms = 1e30f;
+    for (size_t k = 0; k < cand.size(); ++k) best_ms = std::min(best_ms, tmin[k]);
+    int best = -1;
     for (size_t k = 0; k < cand.size(); ++k)
-        if (tmin[k] < best_ms) {
-            best_ms = tmin[k];
-            best = cand[k];
-        }
+        if (tmin[k] < 1e29f && tmin[k] <= 1.01f * best_ms && cand[k] > best) best = cand[k];
+    if (best < 0) best = 16;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->ty = best;
