@@ -675,14 +675,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         C.load_qn(C.j0 - 2 * HALO + s, s);
         C.load_fwin(C.j0 - 2 * HALO + s, s);
     }
-    // Issue priority falls with progress (3 in the first quarter of the segment's rows, 0 in
-    // the last).  The two waves sharing a SIMD otherwise run oldest first: the older one
-    // finishes well ahead and the other then runs alone, with nothing to hide its latency
-    // behind; with the priority the wave that is behind is issued first, and the two stay
-    // within about a quarter of a segment of each other.
+    // Issue priority falls with progress: 3 over the first 60% of the segment's rows, then 2,
+    // 1, and 0 over about the last 7%.  The two waves sharing a SIMD otherwise run oldest
+    // first: the older one finishes well ahead and the other then runs alone, with nothing to
+    // hide its latency behind.  When the leading wave's priority drops, the other is issued
+    // first until it drops too, so the pair is level again at each step; only within the last
+    // level does age decide, hence the short last interval.
     const int nrow = Rend - (C.j0 - HALO) + 1;
     for (int Rw = C.j0 - HALO; Rw <= Rend; Rw += 5) {
-        set_issue_priority(3 - (Rw - (C.j0 - HALO)) * 4 / nrow);
+        {
+            const int done100 = (Rw - (C.j0 - HALO)) * 100;
+            set_issue_priority(done100 < 60 * nrow ? 3 : done100 < 80 * nrow ? 2 : done100 < 93 * nrow ? 1 : 0);
+        }
         C.template step_row<0>(Rw);
         if (Rw + 1 > Rend) break;
         C.template step_row<1>(Rw + 1);
