@@ -98,6 +98,18 @@ def test_rhs_config2_small_boundaries(torch_cuda):
     _compare_rhs(torch_cuda, case, Q0)
 
 
+def test_inflow_every_side(torch_cuda):
+    """Inflow ghosts on all four sides, the corners included (x resolved first, then y), on a
+    non-square grid whose strips and segments end ragged: one right-hand side, then steps
+    across a refill of the kernels' per-step ghost tables, against the oracle."""
+    case = _c2_small(n=200, nprobe=0).with_(
+        n=(170, 130, 1), bc=(("inflow", "inflow"), ("inflow", "inflow"), ("periodic", "periodic")))
+    Q0 = W.config2_noisy_state(case)
+    _compare_rhs(torch_cuda, case, Q0)
+    s, o, Qg, Qo = _steps_both(torch_cuda, case, Q0, 20)
+    _assert_q_close(Qg, Qo, Q0, case)
+
+
 def test_free_stream_exactly_zero(torch_cuda):
     case = _c2_small(n=150, nprobe=0).with_(markers=None, inflow_amp=0.0)
     Q0 = W.uniform_state(case)
