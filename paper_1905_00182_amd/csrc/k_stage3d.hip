@@ -3,7 +3,8 @@
 //  * k_stress3d: for every cell of the grid extended by two ghost layers, the velocity
 //    gradients by the fourth-order central difference (Sec. 2, Eqs. (5)-(6)), the Stokes
 //    stress tau and b = u . tau, stored as nine components [9][ext cells] (tau_xx, tau_yy,
-//    tau_zz, tau_xy, tau_xz, tau_yz, b_x, b_y, b_z).
+//    tau_zz, tau_xy, tau_xz, tau_yz, b_x, b_y, b_z); a z march of 64 x 4 column tiles with
+//    the velocities of each plane formed once into LDS.
 //  * k_faces3d<D>: one thread per face along direction D: the six cells i-2..i+3 give the
 //    split fluxes f+- = (F +- alpha Q)/2 of the five components and the face flux
 //    F^ = rec+(f+) + rec-(f-), stored per component [5][faces] (each face once).
@@ -75,58 +76,83 @@ __device__ __forceinline__ void velocity(const KConst* K, const double* Q, long 
     }
 }
 
+// The stress pass marches a 64 x 4 column tile of the extended grid up z over a segment of
+// SZ planes: each step forms the velocities of one plane of the tile and its two-cell x and
+// y halo (every cell's velocity once, instead of once per neighbour that needs it) into a
+// four-plane LDS ring, keeps this thread's column of five planes in registers for the z
+// derivatives, and writes the stress of the plane two below.  One barrier per step: a slot
+// is rewritten two steps after its last read.
+constexpr int SZ = 32, TXS = BX + 4, TYS = BY + 4;
+
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_stress3d(const KConst* __restrict__ K, const double* __restrict__ Q,
                                                       long long step, T* __restrict__ S)
 {
     constexpr bool F64 = std::is_same<T, double>::value;
+    __shared__ T ring[4][3][TYS][TXS];
     const Grid& G = K->G;
     const int ex = G.n[0] + 4, ey = G.n[1] + 4, ez = G.n[2] + 4;
-    const int xi = blockIdx.x * BX + (threadIdx.x & (BX - 1));
-    const int yi = blockIdx.y * BY + (threadIdx.x / BX);
-    const int zi = blockIdx.z;
-    if (xi >= ex || yi >= ey || zi >= ez) return;
-    const int i = xi - 2, j = yi - 2, k = zi - 2;
+    const int tx = threadIdx.x & (BX - 1), ty = threadIdx.x / BX;
+    const int xi = blockIdx.x * BX + tx, yi = blockIdx.y * BY + ty;
+    const bool out = xi < ex && yi < ey;
+    const int za = blockIdx.z * SZ, zb = min(za + SZ, ez) - 1;   // extended output planes
+    const int ka = za - 2, kb = zb - 2;                           // their cell indices
     const T inv12h = (T)K->inv12h, mu = (T)K->P.mu;
-    T g[3][3];   // g[a][b] = d u_a / d x_b
-    T um[4][3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        const int off[4] = {-2, -1, 1, 2};
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            int ii = i, jj = j, kk = k;
-            if (b == 0) ii += off[m];
-            else if (b == 1) jj += off[m];
-            else kk += off[m];
-            velocity<T>(K, Q, step, ii, jj, kk, um[m]);
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) g[a][b] = d1(um[0][a], um[1][a], um[2][a], um[3][a], inv12h);
-    }
-    T uc[3];
-    velocity<T>(K, Q, step, i, j, k, uc);
-    const T div = g[0][0] + g[1][1] + g[2][2];
-    const T sxx = mu * fma(T(-2.0 / 3.0), div, g[0][0] + g[0][0]);
-    const T syy = mu * fma(T(-2.0 / 3.0), div, g[1][1] + g[1][1]);
-    const T szz = mu * fma(T(-2.0 / 3.0), div, g[2][2] + g[2][2]);
-    const T sxy = mu * (g[0][1] + g[1][0]);
-    const T sxz = mu * (g[0][2] + g[2][0]);
-    const T syz = mu * (g[1][2] + g[2][1]);
-    T uf[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) uf[a] = F64 ? uc[a] : uc[a] + (T)K->P.prim_inf[1 + a];
     const long long ne = (long long)ex * ey * ez;
-    const long long o = ((long long)zi * ey + yi) * ex + xi;
-    S[0 * ne + o] = sxx;
-    S[1 * ne + o] = syy;
-    S[2 * ne + o] = szz;
-    S[3 * ne + o] = sxy;
-    S[4 * ne + o] = sxz;
-    S[5 * ne + o] = syz;
-    S[6 * ne + o] = fma(uf[0], sxx, fma(uf[1], sxy, uf[2] * sxz));
-    S[7 * ne + o] = fma(uf[0], sxy, fma(uf[1], syy, uf[2] * syz));
-    S[8 * ne + o] = fma(uf[0], sxz, fma(uf[1], syz, uf[2] * szz));
+    T w[5][3];   // this column's velocities at planes k-2 .. k+2
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) w[m][a] = T(0);
+    for (int kf = ka - 2; kf <= kb + 2; ++kf) {
+        // front plane kf of the tile with its halo
+        T (*pl)[TYS][TXS] = ring[(kf + 8) & 3];
+        for (int c = threadIdx.x; c < TXS * TYS; c += BX * BY) {
+            const int ly = c / TXS, lx = c - ly * TXS;
+            T u[3];
+            velocity<T>(K, Q, step, blockIdx.x * BX + lx - 4, blockIdx.y * BY + ly - 4, kf, u);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) pl[a][ly][lx] = u[a];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) w[m][a] = w[m + 1][a];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) w[4][a] = pl[a][ty + 2][tx + 2];
+        const int k = kf - 2;
+        if (k < ka || !out) continue;
+        // plane k: x and y neighbours from its ring slot, z neighbours from the column
+        const T (*pk)[TYS][TXS] = ring[(k + 8) & 3];
+        T g[3][3];   // g[a][b] = d u_a / d x_b
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            g[a][0] = d1(pk[a][ty + 2][tx], pk[a][ty + 2][tx + 1], pk[a][ty + 2][tx + 3], pk[a][ty + 2][tx + 4], inv12h);
+            g[a][1] = d1(pk[a][ty][tx + 2], pk[a][ty + 1][tx + 2], pk[a][ty + 3][tx + 2], pk[a][ty + 4][tx + 2], inv12h);
+            g[a][2] = d1(w[0][a], w[1][a], w[3][a], w[4][a], inv12h);
+        }
+        const T div = g[0][0] + g[1][1] + g[2][2];
+        const T sxx = mu * fma(T(-2.0 / 3.0), div, g[0][0] + g[0][0]);
+        const T syy = mu * fma(T(-2.0 / 3.0), div, g[1][1] + g[1][1]);
+        const T szz = mu * fma(T(-2.0 / 3.0), div, g[2][2] + g[2][2]);
+        const T sxy = mu * (g[0][1] + g[1][0]);
+        const T sxz = mu * (g[0][2] + g[2][0]);
+        const T syz = mu * (g[1][2] + g[2][1]);
+        T uf[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) uf[a] = F64 ? w[2][a] : w[2][a] + (T)K->P.prim_inf[1 + a];
+        const long long o = ((long long)(k + 2) * ey + yi) * ex + xi;
+        S[0 * ne + o] = sxx;
+        S[1 * ne + o] = syy;
+        S[2 * ne + o] = szz;
+        S[3 * ne + o] = sxy;
+        S[4 * ne + o] = sxz;
+        S[5 * ne + o] = syz;
+        S[6 * ne + o] = fma(uf[0], sxx, fma(uf[1], sxy, uf[2] * sxz));
+        S[7 * ne + o] = fma(uf[0], sxy, fma(uf[1], syy, uf[2] * syz));
+        S[8 * ne + o] = fma(uf[0], sxz, fma(uf[1], syz, uf[2] * szz));
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -399,7 +425,7 @@ int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, co
                    void* faces, hipStream_t s)
 {
     const dim3 block(BX * BY);
-    const dim3 gs((G.n[0] + 4 + BX - 1) / BX, (G.n[1] + 4 + BY - 1) / BY, G.n[2] + 4);
+    const dim3 gs((G.n[0] + 4 + BX - 1) / BX, (G.n[1] + 4 + BY - 1) / BY, (G.n[2] + 4 + SZ - 1) / SZ);
     const dim3 gr((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
     if (precision == 1) {
         float* S = static_cast<float*>(stress);
