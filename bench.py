@@ -221,8 +221,8 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "decomposition is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver has no "
+              "multi-GPU domain decomposition.", file=sys.stderr)
         sys.exit(2)
 
     import torch
