@@ -507,8 +507,11 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         if (rc != FSA_OK) return rc;
         HIPCHK(c, hipEventRecord(t0, c->stream));
     }
-    // learned form: the stage output's deviation ranges, for the next flags pass
-    S.qrange = (c->d.precision == FSA_LEARNED32 && acc >= 0) ? c->qrange : nullptr;
+    // learned form: the stage output's deviation ranges, for the next flags pass (only from a
+    // stage whose output a flags pass reads: with the selector once per step, the last one)
+    S.qrange = (c->d.precision == FSA_LEARNED32 && acc >= 0 && (c->d.selector_stride != 3 || stage == 3))
+                   ? c->qrange
+                   : nullptr;
     e = launch_stage2d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "stage kernel launch");
     if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
