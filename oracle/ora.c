@@ -577,6 +577,20 @@ static void idx_of(const ora_ctx* c, long n, long* idx)
 
 /* Add the IB source S = [0, f, f . u] (f the spread force density, u the fluid velocity)
  * and the sponge -sigma (Q - Q_inf) at one cell. */
+/* Periodic Gaussian pressure source (Sec. 3, sphere scattering) at cell n and time t:
+ * A_p = -A exp(-B log(2) r^2) cos(omega t), r the distance from the source point. */
+static double pressure_source(const ora_ctx* c, long n, double t)
+{
+    long idx[3];
+    idx_of(c, n, idx);
+    double r2 = 0.0;
+    for (int a = 0; a < c->d.dim; ++a) {
+        double xa = c->d.lo[a] + ((double)idx[a] + 0.5) * c->d.h;
+        r2 += (xa - c->d.src_x[a]) * (xa - c->d.src_x[a]);
+    }
+    return -c->d.src_amp * exp(-c->d.src_b * log(2.0) * r2) * cos(c->d.src_omega * t);
+}
+
 static void sources_at(const ora_ctx* c, const double* Q, const double* fib, long n, double* out)
 {
     int dim = c->d.dim, nq = c->nq;
@@ -596,6 +610,7 @@ static void sources_at(const ora_ctx* c, const double* Q, const double* fib, lon
         double sg = sponge_sigma_at(c, idx);
         for (int m = 0; m < nq; ++m) out[m] += -sg * (Q[(long)m * nc + n] - c->q_inf[m]);
     }
+    if (c->d.src_amp != 0.0) out[dim + 1] += pressure_source(c, n, c->t) / (c->d.gamma - 1.0);
 }
 
 static int conv_on(const ora_ctx* c, int d) { return (c->d.terms >> d) & 1; }
@@ -754,6 +769,7 @@ int ora_rhs_cells(ora_ctx* c, const double* Q, int64_t nlist, const int64_t* cel
             double sg = sponge_sigma_at(c, idx);
             for (int m = 0; m < nq; ++m) s[m] += -sg * (Q[(long)m * nc + n] - c->q_inf[m]);
         }
+        if (c->d.src_amp != 0.0) s[dim + 1] += pressure_source(c, n, c->t) / (c->d.gamma - 1.0);
         for (int m = 0; m < nq; ++m) out[(long)m * nlist + l] = acc[m] + s[m];
     }
     free(fl);

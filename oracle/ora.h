@@ -54,6 +54,14 @@ typedef struct ora_desc {
     double   sponge_sigma;     /* sigma_max of the cubic sponge */
     double   ib_alpha;         /* penalty constant on the integral term */
     double   ib_beta;          /* penalty constant on the proportional term */
+    /* periodic Gaussian pressure source of the sphere-scattering case (Sec. 3):
+       A_p = -src_amp exp(-src_b log(2) |x - src_x|^2) cos(src_omega t), added to the energy
+       equation as A_p / (gamma - 1) (the pressure rate it makes at fixed rho and u);
+       src_amp = 0: none */
+    double   src_amp;
+    double   src_b;
+    double   src_omega;
+    double   src_x[3];
 } ora_desc;
 
 typedef struct ora_ctx ora_ctx;

@@ -39,6 +39,10 @@ class OraDesc(C.Structure):
         ("sponge_sigma", C.c_double),
         ("ib_alpha", C.c_double),
         ("ib_beta", C.c_double),
+        ("src_amp", C.c_double),
+        ("src_b", C.c_double),
+        ("src_omega", C.c_double),
+        ("src_x", C.c_double * 3),
     ]
 
 
@@ -146,6 +150,11 @@ def make_desc(case) -> OraDesc:
     d.sponge_sigma = case.sponge_sigma
     d.ib_alpha = case.ib_alpha
     d.ib_beta = case.ib_beta
+    d.src_amp = case.src_amp
+    d.src_b = case.src_b
+    d.src_omega = case.src_omega
+    for a in range(3):
+        d.src_x[a] = case.src_x[a]
     return d
 
 

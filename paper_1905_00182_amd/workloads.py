@@ -49,6 +49,12 @@ class Case:
     sponge_sigma: float = 0.0
     ib_alpha: float = 0.0
     ib_beta: float = 0.0
+    # periodic Gaussian pressure source (3D): A_p = -src_amp exp(-src_b log2 |x - src_x|^2)
+    # cos(src_omega t) into the energy equation as A_p / (gamma - 1); src_amp = 0: none
+    src_amp: float = 0.0
+    src_b: float = 16.0
+    src_omega: float = 2.0 * np.pi
+    src_x: tuple = (2.0, 0.0, 0.0)
     precision: str = "fp64"
     markers: Optional[dict] = None
     probes: Optional[np.ndarray] = None
@@ -289,6 +295,18 @@ def config3(n=256, scheme="teno5", steps=500, nmark=10000, L=12.0):
 
 def config3_state(case):
     return pulse_state(case, (2.0, 0.0, 0.0))
+
+
+def config3_source(n=256, scheme="teno5", steps=500, nmark=10000, L=12.0):
+    """The sphere case driven by the paper's periodic Gaussian pressure source instead of a
+    pulse (Sec. 3, scattering by a stationary sphere: A = 0.01, B = 16, omega = 2 pi, source at
+    x = 2, all in units of the sphere radius, the ambient density and sound speed).  With the
+    sphere of radius R = 0.5 here: B / R^2, omega / R and the source at (2R, 0, 0) in grid
+    units; the gas starts quiescent."""
+    R = 0.5
+    c = config3(n=n, scheme=scheme, steps=steps, nmark=nmark, L=L)
+    return c.with_(name="c3_sphere_periodic_source", src_amp=0.01, src_b=16.0 / R**2, src_omega=2.0 * np.pi / R,
+                   src_x=(2.0 * R, 0.0, 0.0))
 
 
 def config4(n=384, steps=500):
