@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define FSA_ABI_VERSION 1
+#define FSA_ABI_VERSION 2
 
 enum {
     FSA_OK = 0,
@@ -107,6 +107,15 @@ typedef struct fsa_desc {
     int32_t  selector_stride;     /* learned form: 1 (or 0) = keep patterns from every stage's
                                      state; 3 = from each step's first stage, reused by its
                                      other two stages.  Other values: FSA_EINVAL */
+    /* Periodic Gaussian pressure source of the sphere-scattering case (Sec. 3), 3D only:
+     * A_p = -src_amp exp(-src_b log(2) |x - src_x|^2) cos(src_omega t) at the cell centres,
+     * added to the energy equation as A_p / (gamma - 1) (the pressure rate it makes at fixed
+     * density and velocity), t the time of each SSP-RK3 stage (t, t + dt, t + dt/2).
+     * src_amp = 0: no source; nonzero in 2D: FSA_EUNSUPPORTED. */
+    double   src_amp;
+    double   src_b;
+    double   src_omega;
+    double   src_x[3];
 } fsa_desc;
 
 typedef struct fsa_ctx fsa_ctx;

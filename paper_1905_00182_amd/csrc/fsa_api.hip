@@ -174,6 +174,12 @@ int validate(const fsa_desc* d, std::string& why)
         return FSA_EINVAL;
     }
     if (!(d->prim_inf[0] > 0.0) || !(d->prim_inf[4] > 0.0)) { why = "far field must have rho, p > 0"; return FSA_EINVAL; }
+    if (!std::isfinite(d->src_amp) || !std::isfinite(d->src_b) || !std::isfinite(d->src_omega) ||
+        !std::isfinite(d->src_x[0]) || !std::isfinite(d->src_x[1]) || !std::isfinite(d->src_x[2])) {
+        why = "non-finite source parameters";
+        return FSA_EINVAL;
+    }
+    if (d->src_amp != 0.0 && d->dim != 3) { why = "the periodic pressure source is built for 3D"; return FSA_EUNSUPPORTED; }
     return FSA_OK;
 }
 
@@ -222,6 +228,10 @@ void build_consts(fsa_ctx* c)
     P.teno_ct = d.teno_ct;
     P.teno_eps = d.teno_eps;
     P.terms = d.terms;
+    P.src_amp = d.src_amp;
+    P.src_bl2 = d.src_b * std::log(2.0);
+    P.src_omega = d.src_omega;
+    for (int k = 0; k < 3; ++k) P.src_x[k] = d.src_x[k];
 }
 
 // Physical fluxes of the far-field state per direction (the precision form stores split
@@ -475,6 +485,8 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     S.dt = dt;
     S.mode_rhs = mode_rhs;
     S.step = c->step;
+    // stage times of SSP-RK3 (t, t + dt, t + dt/2; a lone right-hand side at t)
+    S.t = c->t + (stage == 2 ? dt : (stage == 3 ? 0.5 * dt : 0.0));
     if (c->G.dim == 3) {
         hipEvent_t t0 = nullptr, t1 = nullptr;
         if (c->timing) {

@@ -35,6 +35,9 @@ struct Phys {
     double sigma;             // sponge sigma_max
     double weno_eps, teno_ct, teno_eps;
     int terms;
+    // periodic Gaussian pressure source (3D): A_p = -src_amp exp(-src_bl2 |x - src_x|^2)
+    // cos(src_omega t), src_bl2 = B log 2; src_amp = 0: none
+    double src_amp, src_bl2, src_omega, src_x[3];
 };
 
 // ---------------------------------------------------------------------------------------

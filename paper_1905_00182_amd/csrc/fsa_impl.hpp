@@ -21,6 +21,7 @@ struct StageArgs {
     unsigned long long* alpha_part;        // if set: per wave, NaN-propagating max of |u_d| + c of
                                            // the output, [wave][3] (reduced by launch_alpha_final)
     long long step;                        // step counter (inflow-noise counter)
+    double t;                              // time of the stage (periodic pressure source)
     const unsigned* flags_x;               // learned form: keep patterns of the x faces
     const unsigned* flags_y;               // and of the y faces
     float* qrange;                         // learned form, if set (with alpha_part): per strip and

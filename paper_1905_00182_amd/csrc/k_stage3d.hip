@@ -344,6 +344,15 @@ __global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ 
                 for (int c = 0; c < 5; ++c) src[c] = fma(-sg, qc[c] - K->P.q_inf[c], src[c]);
             }
         }
+        if (K->P.src_amp != 0.0) {
+            // periodic Gaussian pressure source (Sec. 3), into the energy as A_p / (gamma - 1)
+            const double x = G.lo[0] + ((double)i + 0.5) * G.h, y = G.lo[1] + ((double)j + 0.5) * G.h,
+                         z = G.lo[2] + ((double)k + 0.5) * G.h;
+            const double dx = x - K->P.src_x[0], dy = y - K->P.src_x[1], dz = z - K->P.src_x[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double ap = -K->P.src_amp * exp(-K->P.src_bl2 * r2) * cos(K->P.src_omega * A.t);
+            src[4] += ap * K->P.inv_gm1;
+        }
         double val[5];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {

@@ -52,6 +52,10 @@ class FsaDesc(C.Structure):
         ("ib_alpha", C.c_double),
         ("ib_beta", C.c_double),
         ("selector_stride", C.c_int32),
+        ("src_amp", C.c_double),
+        ("src_b", C.c_double),
+        ("src_omega", C.c_double),
+        ("src_x", C.c_double * 3),
     ]
 
 
@@ -141,6 +145,11 @@ def make_desc(case, nan_check=False) -> FsaDesc:
     d.terms = case.terms
     d.nan_check = 1 if nan_check else 0
     d.selector_stride = int(case.extra.get("selector_stride", 1))
+    d.src_amp = case.src_amp
+    d.src_b = case.src_b
+    d.src_omega = case.src_omega
+    for k in range(3):
+        d.src_x[k] = case.src_x[k]
     d.weno_eps = case.weno_eps
     d.teno_ct = case.teno_ct
     d.teno_eps = case.teno_eps

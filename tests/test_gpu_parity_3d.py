@@ -90,6 +90,55 @@ def _steps3(torch, case, Q0, nsteps):
     return s, o, Qg, Qo
 
 
+def test_rhs3d_periodic_source(torch_cuda):
+    """The periodic Gaussian pressure source (Sec. 3) with every other term on, at a time that is
+    not a multiple of its period: one right-hand side against the oracle."""
+    case = _box3("teno5").with_(src_amp=0.01, src_b=16.0, src_omega=2.0 * np.pi, src_x=(0.41, 0.37, 0.33))
+    Q0 = W.perturbed_state(case, seed=31, amp=1e-2, step_amp=0.3)
+    t = 0.37
+    _say("rhs periodic source at t =", t)
+    s = _solver(case)
+    s.set_state(None, t, 0)
+    Lg = s.rhs(torch_cuda.from_numpy(Q0).cuda())
+    s.sync()
+    Lg = Lg.cpu().numpy()
+    o = _oracle(case)
+    o.set_state(None, t, 0)
+    Lo = o.rhs(Q0)
+    S = 2.0 * np.abs(Q0).max() * max(o.alpha(Q0)[:3]) / case.h
+    err = np.abs(Lg - Lo).max()
+    _say("  max |dL| / S =", err / S)
+    assert err <= 1e-13 * S
+    # the source is a visible part of the energy equation here
+    o0 = _oracle(case.with_(src_amp=0.0))
+    assert np.abs(Lo[4] - o0.rhs(Q0)[4]).max() > 1e-3 / (W.GAMMA - 1.0)
+
+
+def test_rk3_config3_source_miniature(torch_cuda):
+    """The sphere case driven by the periodic source from a quiescent start (the stage times
+    t, t + dt, t + dt/2 enter through the source), against the oracle: WENO5-JS over 30 steps
+    (about four periods of the source) to 1e-12; TENO5 over one step to 1e-12 (over many steps
+    its cut-off decides on the rounding noise of the quiescent far field, as on the pulse)."""
+    case = W.config3_source(n=48, scheme="weno5js", nmark=2000)
+    Q0 = W.uniform_state(case)
+    s, o, Qg, Qo = _steps3(torch_cuda, case, Q0, 30)
+    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
+    # without the source the quiescent state stays exactly as it is
+    assert np.abs(Qo[4] - Q0[4]).max() > 1e-7
+    np.testing.assert_allclose(s.marker_force(), o.marker_force(), rtol=1e-9, atol=1e-12)
+    case = case.with_(scheme="teno5")
+    s, o, Qg, Qo = _steps3(torch_cuda, case, Q0, 1)
+    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
+
+
+def test_source_rejected_in_2d(torch_cuda):
+    from paper_1905_00182_amd import fsa
+
+    case = W.periodic_box(dim=2, n=16).with_(src_amp=0.01)
+    with pytest.raises(fsa.FsaError):
+        fsa.Solver(case)
+
+
 def test_rk3_config3_miniature_weno(torch_cuda):
     case = W.config3(n=48, scheme="weno5js", nmark=2000)
     Q0 = W.config3_state(case)
