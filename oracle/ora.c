@@ -1067,6 +1067,17 @@ int ora_set_markers(ora_ctx* c, int n, const double* X, const double* dV, const 
     return 0;
 }
 
+int ora_set_marker_kinematics(ora_ctx* c, const double* X, const double* U)
+{
+    int dim = c->d.dim, n = c->nm;
+    if (n == 0 || c->motion != ORA_EXTERNAL || !X) return -1;
+    if (!supports_inside(c, n, X)) return -1;
+    memcpy(c->X, X, sizeof(double) * (size_t)dim * (size_t)n);
+    if (U) memcpy(c->U, U, sizeof(double) * (size_t)dim * (size_t)n);
+    else memset(c->U, 0, sizeof(double) * (size_t)dim * (size_t)n);
+    return 0;
+}
+
 int ora_set_probes(ora_ctx* c, int n, const double* Xp)
 {
     if (n < 0 || (n > 0 && !Xp)) return -1;

@@ -74,6 +74,9 @@ void     ora_destroy(ora_ctx* c);
  * Resets the penalty integral xi to zero. */
 int ora_set_markers(ora_ctx* c, int n, const double* X, const double* dV, const double* U,
                     int motion, double omega);
+/* EXTERNAL markers: new positions X and velocities U (NULL: zero) for the steps that follow;
+ * the penalty integral and the forces are kept (prescribed or structure-driven motion). */
+int ora_set_marker_kinematics(ora_ctx* c, const double* X, const double* U);
 int ora_set_probes(ora_ctx* c, int n, const double* Xp);
 
 /* Global Lax-Friedrichs speeds alpha[d] = max over cells of |u_d| + c. */

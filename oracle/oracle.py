@@ -64,6 +64,7 @@ def lib():
         _lib.ora_create.argtypes = [P(OraDesc)]
         _lib.ora_destroy.argtypes = [vp]
         _lib.ora_set_markers.argtypes = [vp, C.c_int, dp, dp, dp, C.c_int, d]
+        _lib.ora_set_marker_kinematics.argtypes = [vp, dp, dp]
         _lib.ora_set_probes.argtypes = [vp, C.c_int, dp]
         _lib.ora_alpha.argtypes = [vp, dp, dp]
         _lib.ora_rhs.argtypes = [vp, dp, dp]
@@ -196,6 +197,12 @@ class Oracle:
         self._check(lib().ora_set_markers(self.ctx, n, _ptr(X), _ptr(dV), Up, MOTION[motion], omega),
                     "set_markers")
         self.nm = n
+
+    def set_marker_kinematics(self, X, U=None):
+        X = _f64(X)
+        Ua = _f64(U) if U is not None else None
+        self._check(lib().ora_set_marker_kinematics(self.ctx, _ptr(X), _ptr(Ua) if Ua is not None else None),
+                    "set_marker_kinematics")
 
     def set_probes(self, Xp):
         Xp = _f64(Xp)

@@ -309,6 +309,50 @@ def config3_source(n=256, scheme="teno5", steps=500, nmark=10000, L=12.0):
                    src_x=(2.0 * R, 0.0, 0.0))
 
 
+def plate_kinematics(case, t):
+    """Marker positions X [2][n] and velocities U [2][n] of the rigid plate of `config5` at
+    time t (Sec. 4.1, the clamped leading edge's motion): X0(t) = (A0/2) cos(2 pi f t)
+    [cos beta, sin beta] added to the edge's rest point, pitch alpha(t) = (alpha_m/2)
+    sin(2 pi f t + phi) about the edge, nose up for alpha > 0, so that a marker at chord
+    position s sits at X0 + s (cos alpha, -sin alpha)."""
+    p = case.extra["plate"]
+    w = 2.0 * math.pi * p["f"]
+    s = p["s"]
+    b = p["beta"]
+    x0 = p["edge"][0] + 0.5 * p["A0"] * math.cos(w * t) * math.cos(b)
+    y0 = p["edge"][1] + 0.5 * p["A0"] * math.cos(w * t) * math.sin(b)
+    vx0 = -0.5 * p["A0"] * w * math.sin(w * t) * math.cos(b)
+    vy0 = -0.5 * p["A0"] * w * math.sin(w * t) * math.sin(b)
+    al = 0.5 * p["alpha_m"] * math.sin(w * t + p["phi"])
+    dal = 0.5 * p["alpha_m"] * w * math.cos(w * t + p["phi"])
+    X = np.stack([x0 + s * math.cos(al), y0 - s * math.sin(al)])
+    U = np.stack([vx0 - s * math.sin(al) * dal, vy0 - s * math.cos(al) * dal])
+    return X, U
+
+
+def config5(n=1024, L=16.0, nmark=256, steps=2000, scheme="teno5"):
+    """2D rigid flapping plate in a uniform stream (the prescribed-kinematics stand-in for the
+    flexible foil of Sec. 4.1): [-8,8]^2, U0 = 0.1, Re = 200 on the chord, plate of chord 1
+    with 256 markers clamped at its leading edge, heave amplitude A0/2 = 0.5 across the stream
+    (beta = 90 degrees), pitch amplitude alpha_m/2 = 30 degrees, reduced frequency
+    k = 2 pi f c / U0 = 0.8, phi = 0; inflow on x-, zero-gradient elsewhere, sponge 2 wide.
+    Markers move every step (`plate_kinematics`)."""
+    U0, chord = 0.1, 1.0
+    h = L / n
+    c = Case(name="c5_flapping_plate", dim=2, n=(n, n, 1), lo=(-L / 2, -L / 2, 0.0), h=h,
+             bc=(("inflow", "extrap"), ("extrap", "extrap"), ("periodic", "periodic")),
+             mu=U0 * chord / 200.0, scheme=scheme, prim_inf=(1.0, U0, 0.0, 0.0, 1.0 / GAMMA),
+             sponge_width=((2.0, 2.0), (2.0, 2.0), (0.0, 0.0)), sponge_sigma=20.0 / 2.0, steps=steps)
+    s = (np.arange(nmark) + 0.5) * chord / nmark
+    plate = {"s": s, "edge": (-0.5 * chord, 0.0), "A0": 1.0, "beta": 0.5 * math.pi,
+             "alpha_m": math.radians(60.0), "phi": 0.0, "f": 0.8 * U0 / (2.0 * math.pi * chord)}
+    c = c.with_(extra={"plate": plate})
+    X, _ = plate_kinematics(c, 0.0)
+    c = c.with_(markers={"X": X, "dV": np.full(nmark, chord / nmark), "U": plate_kinematics(c, 0.0)[1],
+                         "motion": "external", "omega": 0.0})
+    return _finish(c)
+
+
 def config4(n=384, steps=500):
     """Precision variant of the sphere case at 384^3 (FP32 faces, FP64 state)."""
     c = config3(n=n, scheme="teno5", steps=steps)
