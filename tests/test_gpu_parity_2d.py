@@ -110,6 +110,31 @@ def test_inflow_every_side(torch_cuda):
     _assert_q_close(Qg, Qo, Q0, case)
 
 
+@pytest.mark.parametrize("scheme,nsteps", [("weno5js", 20), ("teno5", 3)])
+def test_flapping_plate_moving_markers(torch_cuda, scheme, nsteps):
+    """The rigid flapping plate in a stream (prescribed heave and pitch of its clamped leading
+    edge): the markers move every step, positions and velocities set before each step on both
+    sides (the library rebuilds its spreading window), against the oracle with the marker
+    forces."""
+    case = W.config5(n=128, L=8.0, nmark=128, scheme=scheme)
+    Q0 = W.uniform_state(case)
+    _say("flapping plate", scheme, "x", nsteps)
+    s = _solver(case)
+    o = _oracle(case)
+    Qg = torch_cuda.from_numpy(Q0.copy()).cuda()
+    Qo = Q0.copy()
+    for n in range(nsteps):
+        X, U = W.plate_kinematics(case, n * case.dt)
+        s.set_marker_kinematics(X, U)
+        o.set_marker_kinematics(X, U)
+        s.rk3_step(Qg, case.dt)
+        o.rk3_step(Qo, case.dt)
+    s.sync()
+    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
+    np.testing.assert_allclose(s.marker_force(), o.marker_force(), rtol=1e-9, atol=1e-12)
+    assert np.abs(Qo[1:3] - Q0[1:3]).max() > 1e-4   # the plate has stirred the stream
+
+
 def test_free_stream_exactly_zero(torch_cuda):
     case = _c2_small(n=150, nprobe=0).with_(markers=None, inflow_amp=0.0)
     Q0 = W.uniform_state(case)
