@@ -63,6 +63,12 @@ struct fsa_ctx {
     double* cell_w = nullptr;            // per CSR entry spreading weight
     int* mj0 = nullptr;                  // per marker support origin
     double* mw = nullptr;                // per marker one-dimensional weights
+    long long cap_wcells = 0;            // window buffer capacities (kinematics updates only grow them)
+    long long cap_entries = 0;
+    char* h_stage = nullptr;             // pinned staging of kinematics updates
+    size_t stage_bytes = 0;
+    hipEvent_t ev_stage = nullptr;       // recorded after the last update's staging copies
+    bool stage_pending = false;
     // probes
     int np = 0;
     double* Xp = nullptr;
@@ -289,22 +295,14 @@ IBArgs ib_args(const fsa_ctx* c);
 int tune_ty(fsa_ctx* c, const StageArgs& S0);
 int enqueue_flags(fsa_ctx* c, const double* Qs, const unsigned long long* bits, unsigned* fx, unsigned* fy);
 
-// Window box over all marker supports and the CSR list window cell -> markers (in marker
-// order).  Index bookkeeping only; the weights are computed on the device.
-int build_window(fsa_ctx* c)
+// Window box over all marker supports (c->hX) and the CSR list window cell -> markers (in
+// marker order): index bookkeeping only, on the host.
+int window_lists(fsa_ctx* c, int* wlo, int* wn, std::vector<int>& count, std::vector<int>& marker)
 {
     const int dim = c->d.dim, n = c->nm;
-    dfree(c->fwin);
-    dfree(c->cell_start);
-    dfree(c->cell_marker);
-    dfree(c->cell_w);
-    dfree(c->mj0);
-    dfree(c->mw);
-    c->wcells = 0;
-    for (int k = 0; k < 3; ++k) { c->wlo[k] = 0; c->wn[k] = 1; }
-    if (n == 0) { c->wn[0] = c->wn[1] = c->wn[2] = 0; return FSA_OK; }
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     std::vector<int> j0((size_t)n * 3, 0);
+    for (int k = 0; k < 3; ++k) { wlo[k] = 0; wn[k] = 1; }
     for (int d = 0; d < dim; ++d) {
         lo[d] = 1 << 30;
         hi[d] = -(1 << 30);
@@ -315,19 +313,18 @@ int build_window(fsa_ctx* c)
             lo[d] = std::min(lo[d], j);
             hi[d] = std::max(hi[d], j + 3);
         }
-        c->wlo[d] = lo[d];
-        c->wn[d] = hi[d] - lo[d] + 1;
+        wlo[d] = lo[d];
+        wn[d] = hi[d] - lo[d] + 1;
     }
-    const long long wcells = (long long)c->wn[0] * c->wn[1] * c->wn[2];
+    const long long wcells = (long long)wn[0] * wn[1] * wn[2];
     if (wcells > (1ll << 26)) return fail(c, FSA_EINVAL, "marker supports span too large a box");
-    c->wcells = wcells;
-    std::vector<int> count((size_t)wcells + 1, 0);
+    count.assign((size_t)wcells + 1, 0);
     const int mz = dim == 3 ? 4 : 1;
     auto cell_of = [&](int k, int dx, int dy, int dz) {
-        const long long i = j0[(size_t)k * 3] + dx - c->wlo[0];
-        const long long j = j0[(size_t)k * 3 + 1] + dy - c->wlo[1];
-        const long long l = dim == 3 ? j0[(size_t)k * 3 + 2] + dz - c->wlo[2] : 0;
-        return (l * c->wn[1] + j) * c->wn[0] + i;
+        const long long i = j0[(size_t)k * 3] + dx - wlo[0];
+        const long long j = j0[(size_t)k * 3 + 1] + dy - wlo[1];
+        const long long l = dim == 3 ? j0[(size_t)k * 3 + 2] + dz - wlo[2] : 0;
+        return (l * wn[1] + j) * wn[0] + i;
     };
     for (int k = 0; k < n; ++k)
         for (int dz = 0; dz < mz; ++dz)
@@ -335,12 +332,36 @@ int build_window(fsa_ctx* c)
                 for (int dx = 0; dx < 4; ++dx) count[(size_t)cell_of(k, dx, dy, dz) + 1]++;
     for (long long w = 0; w < wcells; ++w) count[(size_t)w + 1] += count[(size_t)w];
     std::vector<int> fillp(count.begin(), count.end() - 1);
-    std::vector<int> marker((size_t)count[(size_t)wcells]);
+    marker.assign((size_t)count[(size_t)wcells], 0);
     for (int k = 0; k < n; ++k)
         for (int dz = 0; dz < mz; ++dz)
             for (int dy = 0; dy < 4; ++dy)
                 for (int dx = 0; dx < 4; ++dx) marker[(size_t)fillp[(size_t)cell_of(k, dx, dy, dz)]++] = k;
-    int rc;
+    return FSA_OK;
+}
+
+// First placement of the markers: the window's device lists (sized to fit) and their
+// weights, synchronously.
+int build_window(fsa_ctx* c)
+{
+    const int dim = c->d.dim, n = c->nm;
+    dfree(c->fwin);
+    dfree(c->cell_start);
+    dfree(c->cell_marker);
+    dfree(c->cell_w);
+    dfree(c->mj0);
+    dfree(c->mw);
+    c->wcells = 0;
+    c->cap_wcells = c->cap_entries = 0;
+    for (int k = 0; k < 3; ++k) { c->wlo[k] = 0; c->wn[k] = 1; }
+    if (n == 0) { c->wn[0] = c->wn[1] = c->wn[2] = 0; return FSA_OK; }
+    std::vector<int> count, marker;
+    int rc = window_lists(c, c->wlo, c->wn, count, marker);
+    if (rc != FSA_OK) return rc;
+    const long long wcells = (long long)c->wn[0] * c->wn[1] * c->wn[2];
+    c->wcells = wcells;
+    c->cap_wcells = wcells;
+    c->cap_entries = (long long)marker.size();
     if ((rc = dalloc(c, c->fwin, (size_t)dim * wcells)) != FSA_OK) return rc;
     if ((rc = dalloc(c, c->cell_start, (size_t)wcells + 1)) != FSA_OK) return rc;
     if ((rc = dalloc(c, c->cell_marker, marker.size())) != FSA_OK) return rc;
@@ -355,6 +376,67 @@ int build_window(fsa_ctx* c)
     if (e) return hipcheck(c, (hipError_t)e, "IB weight launch");
     HIPCHK(c, hipDeviceSynchronize());
     return FSA_OK;
+}
+
+// New positions and velocities of EXTERNAL markers (c->hX already holds X): the new window
+// lists, X and U go to the device by copies from pinned staging memory on the library's
+// stream, after the work already enqueued there, followed by the weights kernel; the host
+// waits only for the previous update's copies (before it reuses the staging memory) and, when
+// the window outgrows its buffers, for the stream (before they are replaced).
+int update_window_async(fsa_ctx* c, const double* X, const double* U)
+{
+    const int dim = c->d.dim, n = c->nm;
+    int wlo[3], wn[3];
+    std::vector<int> count, marker;
+    int rc = window_lists(c, wlo, wn, count, marker);
+    if (rc != FSA_OK) return rc;
+    const long long wcells = (long long)wn[0] * wn[1] * wn[2], nent = (long long)marker.size();
+    if (wcells > c->cap_wcells || nent > c->cap_entries) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const long long cw = std::max(wcells, c->cap_wcells) * 3 / 2, ce = std::max(nent, c->cap_entries) * 3 / 2;
+        if ((rc = dalloc(c, c->fwin, (size_t)dim * cw)) != FSA_OK) return rc;
+        if ((rc = dalloc(c, c->cell_start, (size_t)cw + 1)) != FSA_OK) return rc;
+        if ((rc = dalloc(c, c->cell_marker, (size_t)ce)) != FSA_OK) return rc;
+        if ((rc = dalloc(c, c->cell_w, (size_t)ce)) != FSA_OK) return rc;
+        c->cap_wcells = cw;
+        c->cap_entries = ce;
+    }
+    const size_t bx = sizeof(double) * (size_t)dim * n, bs = sizeof(int) * count.size(),
+                 bm = sizeof(int) * marker.size(), need = 2 * bx + bs + bm;
+    if (c->stage_pending) {
+        HIPCHK(c, hipEventSynchronize(c->ev_stage));
+        c->stage_pending = false;
+    }
+    if (need > c->stage_bytes) {
+        if (c->h_stage) (void)hipHostFree(c->h_stage);
+        c->h_stage = nullptr;
+        c->stage_bytes = 0;
+        if (hipHostMalloc((void**)&c->h_stage, need * 2, hipHostMallocDefault) != hipSuccess) {
+            c->h_stage = nullptr;
+            return fail(c, FSA_ENOMEM, "pinned staging allocation failed");
+        }
+        c->stage_bytes = need * 2;
+    }
+    char* h = c->h_stage;
+    std::memcpy(h, X, bx);
+    if (U) std::memcpy(h + bx, U, bx);
+    else std::memset(h + bx, 0, bx);
+    std::memcpy(h + 2 * bx, count.data(), bs);
+    std::memcpy(h + 2 * bx + bs, marker.data(), bm);
+    HIPCHK(c, hipMemcpyAsync(c->X, h, bx, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->U, h + bx, bx, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->cell_start, h + 2 * bx, bs, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->cell_marker, h + 2 * bx + bs, bm, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev_stage, c->stream));
+    c->stage_pending = true;
+    for (int k = 0; k < 3; ++k) {
+        c->wlo[k] = wlo[k];
+        c->wn[k] = wn[k];
+    }
+    c->wcells = wcells;
+    IBArgs A = ib_args(c);
+    int e = launch_ib_weights(c->G, A, c->mj0, c->mw, c->cell_w, c->stream);
+    return e ? hipcheck(c, (hipError_t)e, "IB weight launch") : FSA_OK;
 }
 
 IBArgs ib_args(const fsa_ctx* c)
@@ -766,7 +848,8 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
         }
     }
     if (hipHostMalloc((void**)&c->h_abits, 12 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_alpha, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_alpha, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming) != hipSuccess) {
         fsa_destroy(c);
         return FSA_ENOMEM;
     }
@@ -822,6 +905,8 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->hv_offset);
     dfree(c->hv_total);
     if (c->h_abits) (void)hipHostFree(c->h_abits);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
     for (hipEvent_t ev : c->tev) (void)hipEventDestroy(ev);
     if (c->ev_alpha) (void)hipEventDestroy(c->ev_alpha);
     delete c;
@@ -836,6 +921,7 @@ int32_t fsa_set_markers(fsa_ctx* c, int32_t n, const double* X, const double* dV
     if (motion < FSA_STATIC || motion > FSA_EXTERNAL) return fail(c, FSA_EINVAL, "bad motion");
     if (n > 0 && !support_inside(c, n, X)) return fail(c, FSA_EINVAL, "a marker support leaves the grid");
     HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+    c->stage_pending = false;   // (the stream is idle: earlier staging copies are done)
     const int dim = c->d.dim;
     c->nm = n;
     c->motion = motion;
@@ -867,13 +953,9 @@ int32_t fsa_set_marker_kinematics(fsa_ctx* c, const double* X, const double* U)
     if (c->nm == 0 || c->motion != FSA_EXTERNAL) return fail(c, FSA_ESTATE, "markers are not EXTERNAL");
     if (!X) return fail(c, FSA_EINVAL, "X is NULL");
     if (!support_inside(c, c->nm, X)) return fail(c, FSA_EINVAL, "a marker support leaves the grid");
-    HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
     const int dim = c->d.dim, n = c->nm;
     c->hX.assign(X, X + (size_t)dim * n);
-    HIPCHK(c, hipMemcpy(c->X, X, sizeof(double) * dim * n, hipMemcpyHostToDevice));
-    if (U) HIPCHK(c, hipMemcpy(c->U, U, sizeof(double) * dim * n, hipMemcpyHostToDevice));
-    else HIPCHK(c, hipMemset(c->U, 0, sizeof(double) * dim * n));
-    return build_window(c);
+    return update_window_async(c, X, U);   // (stream-ordered: the host does not wait for the device)
 }
 
 int32_t fsa_set_probes(fsa_ctx* c, int32_t n, const double* Xp)
