@@ -179,8 +179,9 @@ def flapping_plate(net, nsteps=2000, every=10):
     """Config 5's plate (rigid, with the paper's prescribed heave and pitch) at 1024^2 from the
     uniform stream: FP64 TENO5 against the learned form with the selector once per step.  The
     markers move every step (positions and velocities set before each step, one rk3_step call
-    per step, as a coupled structure solver would), Delta p on a radius-3 ring every `every`
-    steps; the learned form's error is the relative L2 over probes x samples against FP64."""
+    per step, each continuing the previous one's state, as a coupled structure solver would),
+    Delta p on a radius-3 ring every `every` steps; the learned form's error is the relative L2
+    over probes x samples against FP64."""
     import torch
 
     from paper_1905_00182_amd import fsa
@@ -203,7 +204,10 @@ def flapping_plate(net, nsteps=2000, every=10):
             for m in range(every):
                 X, U = W.plate_kinematics(c, (k * every + m) * c.dt)
                 s.set_marker_kinematics(X, U)
-                s.rk3_step(Q, c.dt)
+                if k == 0 and m == 0:
+                    s.rk3_step(Q, c.dt)
+                else:
+                    s.rk3_steps_resume(Q, c.dt)
             s.probe_dp(Q, out=dps[k])
         torch.cuda.synchronize()
         runs[name] = (time.perf_counter() - t0, dps)
@@ -219,8 +223,8 @@ def flapping_plate(net, nsteps=2000, every=10):
                                   "speedup_vs_fp64": round(w64 / wl, 3),
                                   "acoustic_err": float(torch.linalg.norm(dpl - dp64) / torch.linalg.norm(dp64))},
             "max_probe_dp": float(dp64.abs().max()),
-            "note": "markers moved before every step; each rk3_step call re-reduces the wave speeds "
-                    "of its input and evaluates its first flags pass without quiet tiles"}
+            "note": "markers moved before every step, one step call per step (continuing the "
+                    "previous call's state)"}
 
 
 def three_d(steps=3):

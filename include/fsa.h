@@ -155,7 +155,10 @@ int32_t fsa_destroy(fsa_ctx* ctx);
 int32_t fsa_set_markers(fsa_ctx* ctx, int32_t n, const double* X, const double* dV,
                         const double* U, int32_t motion, double omega);
 /* New positions and velocities for EXTERNAL markers (same count), e.g. from a structure
- * solver; keeps the penalty integral.  Synchronising. */
+ * solver; keeps the penalty integral.  Stream-ordered: the arrays are read before the call
+ * returns and take effect for work enqueued after it; the host waits at most for the
+ * previous update's host-to-device copy, and for the stream when the markers' window box
+ * outgrows its buffers. */
 int32_t fsa_set_marker_kinematics(fsa_ctx* ctx, const double* X, const double* U);
 /* Probe points Xp[dim][n] for fsa_probe_dp; supports must lie inside the grid. */
 int32_t fsa_set_probes(fsa_ctx* ctx, int32_t n, const double* Xp);
@@ -174,6 +177,16 @@ int32_t fsa_rk3_step(fsa_ctx* ctx, double* d_Q, double dt);
  * each stage input are taken from the kernel that wrote that state, so only the first stage
  * reduces d_Q on its own. */
 int32_t fsa_rk3_steps(fsa_ctx* ctx, double* d_Q, double dt, int32_t nsteps);
+/* fsa_rk3_steps continuing from the previous step call on this context: d_Q must be the
+ * buffer that call advanced, holding what it wrote (the caller has not changed it since).
+ * The first stage then takes the Lax-Friedrichs speeds of d_Q from the kernel that wrote it,
+ * and the learned form's first keep-pattern pass its quiet-tile ranges, instead of computing
+ * them afresh, so that k calls of one step each do what one call of k steps does (bit for
+ * bit).  For callers that change something else between steps (the markers' kinematics, the
+ * probes read-out).  FSA_ESTATE when the context holds no such state for d_Q: no step call
+ * yet, another buffer, or an fsa_rhs call since.  A change to d_Q in between is not seen and
+ * gives wrong results. */
+int32_t fsa_rk3_steps_resume(fsa_ctx* ctx, double* d_Q, double dt, int32_t nsteps);
 /* Interpolate ncomp fields d_field[ncomp][ncell] to the markers (Eq. (8)):
  * d_out[a][k] = sum over the support of field_a * prod lambda. */
 int32_t fsa_ib_interp(fsa_ctx* ctx, const double* d_field, int32_t ncomp, double* d_out);

@@ -47,6 +47,8 @@ struct fsa_ctx {
     bool alpha_pending = false;
     int nonfinite = 0;
     int last_slot = 0;                   // slot holding the wave speeds of the last state
+    const double* advanced = nullptr;    // the state the last step call left (slot 0 holds its
+                                         // wave speeds; null: none, or slot 0 reused since)
     // markers
     int nm = 0;
     int motion = 0;
@@ -65,10 +67,13 @@ struct fsa_ctx {
     double* mw = nullptr;                // per marker one-dimensional weights
     long long cap_wcells = 0;            // window buffer capacities (kinematics updates only grow them)
     long long cap_entries = 0;
-    char* h_stage = nullptr;             // pinned staging of kinematics updates
-    size_t stage_bytes = 0;
-    hipEvent_t ev_stage = nullptr;       // recorded after the last update's staging copies
-    bool stage_pending = false;
+    char* h_stage = nullptr;             // coherent pinned staging of marker placements, two
+    const char* h_stage_dev = nullptr;   // halves used in turn (and its device-side address)
+    char* d_stage = nullptr;             // its device twin (same size and layout)
+    size_t stage_bytes = 0;              // bytes per half
+    int stage_idx = 0;                   // the half the next placement fills
+    hipEvent_t ev_stage[2] = {nullptr, nullptr};  // recorded after the launch that read a half
+    bool stage_pending[2] = {false, false};
     // probes
     int np = 0;
     double* Xp = nullptr;
@@ -297,7 +302,8 @@ int enqueue_flags(fsa_ctx* c, const double* Qs, const unsigned long long* bits, 
 
 // Window box over all marker supports (c->hX) and the CSR list window cell -> markers (in
 // marker order): index bookkeeping only, on the host.
-int window_lists(fsa_ctx* c, int* wlo, int* wn, std::vector<int>& count, std::vector<int>& marker)
+int window_lists(fsa_ctx* c, int* wlo, int* wn, std::vector<int>& count, std::vector<int>& marker,
+                 std::vector<int>& ecell)
 {
     const int dim = c->d.dim, n = c->nm;
     int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -333,67 +339,40 @@ int window_lists(fsa_ctx* c, int* wlo, int* wn, std::vector<int>& count, std::ve
     for (long long w = 0; w < wcells; ++w) count[(size_t)w + 1] += count[(size_t)w];
     std::vector<int> fillp(count.begin(), count.end() - 1);
     marker.assign((size_t)count[(size_t)wcells], 0);
+    ecell.assign(marker.size(), 0);
     for (int k = 0; k < n; ++k)
         for (int dz = 0; dz < mz; ++dz)
             for (int dy = 0; dy < 4; ++dy)
-                for (int dx = 0; dx < 4; ++dx) marker[(size_t)fillp[(size_t)cell_of(k, dx, dy, dz)]++] = k;
+                for (int dx = 0; dx < 4; ++dx) {
+                    const long long w = cell_of(k, dx, dy, dz);
+                    const int e = fillp[(size_t)w]++;
+                    marker[(size_t)e] = k;
+                    ecell[(size_t)e] = (int)w;
+                }
     return FSA_OK;
 }
 
-// First placement of the markers: the window's device lists (sized to fit) and their
-// weights, synchronously.
-int build_window(fsa_ctx* c)
-{
-    const int dim = c->d.dim, n = c->nm;
-    dfree(c->fwin);
-    dfree(c->cell_start);
-    dfree(c->cell_marker);
-    dfree(c->cell_w);
-    dfree(c->mj0);
-    dfree(c->mw);
-    c->wcells = 0;
-    c->cap_wcells = c->cap_entries = 0;
-    for (int k = 0; k < 3; ++k) { c->wlo[k] = 0; c->wn[k] = 1; }
-    if (n == 0) { c->wn[0] = c->wn[1] = c->wn[2] = 0; return FSA_OK; }
-    std::vector<int> count, marker;
-    int rc = window_lists(c, c->wlo, c->wn, count, marker);
-    if (rc != FSA_OK) return rc;
-    const long long wcells = (long long)c->wn[0] * c->wn[1] * c->wn[2];
-    c->wcells = wcells;
-    c->cap_wcells = wcells;
-    c->cap_entries = (long long)marker.size();
-    if ((rc = dalloc(c, c->fwin, (size_t)dim * wcells)) != FSA_OK) return rc;
-    if ((rc = dalloc(c, c->cell_start, (size_t)wcells + 1)) != FSA_OK) return rc;
-    if ((rc = dalloc(c, c->cell_marker, marker.size())) != FSA_OK) return rc;
-    if ((rc = dalloc(c, c->cell_w, marker.size())) != FSA_OK) return rc;
-    if ((rc = dalloc(c, c->mj0, (size_t)n * 3)) != FSA_OK) return rc;
-    if ((rc = dalloc(c, c->mw, (size_t)n * dim * 4)) != FSA_OK) return rc;
-    HIPCHK(c, hipMemcpy(c->cell_start, count.data(), sizeof(int) * count.size(), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(c->cell_marker, marker.data(), sizeof(int) * marker.size(), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemset(c->fwin, 0, sizeof(double) * (size_t)dim * wcells));
-    IBArgs A = ib_args(c);
-    int e = launch_ib_weights(c->G, A, c->mj0, c->mw, c->cell_w, nullptr);
-    if (e) return hipcheck(c, (hipError_t)e, "IB weight launch");
-    HIPCHK(c, hipDeviceSynchronize());
-    return FSA_OK;
-}
-
-// New positions and velocities of EXTERNAL markers (c->hX already holds X): the new window
-// lists, X and U go to the device by copies from pinned staging memory on the library's
-// stream, after the work already enqueued there, followed by the weights kernel; the host
-// waits only for the previous update's copies (before it reuses the staging memory) and, when
-// the window outgrows its buffers, for the stream (before they are replaced).
+// Marker positions X (c->hX holds the same) and velocities U (null: zero): the window box
+// and its lists on the host, then one copy of a pinned staging block (X, U and the lists)
+// into its device twin and one launch that puts them in place and computes the weights, both
+// on the library's stream after the work already enqueued there.  The staging block has two
+// halves used in turn; the host waits only for the copy that read the half it is about to
+// fill (two placements back) and, when the window outgrows its buffers, for the stream
+// (before they are replaced).
 int update_window_async(fsa_ctx* c, const double* X, const double* U)
 {
     const int dim = c->d.dim, n = c->nm;
     int wlo[3], wn[3];
-    std::vector<int> count, marker;
-    int rc = window_lists(c, wlo, wn, count, marker);
+    std::vector<int> count, marker, ecell;
+    int rc = window_lists(c, wlo, wn, count, marker, ecell);
     if (rc != FSA_OK) return rc;
     const long long wcells = (long long)wn[0] * wn[1] * wn[2], nent = (long long)marker.size();
+    const size_t bx = sizeof(double) * (size_t)dim * n, bs = sizeof(int) * count.size(),
+                 bm = sizeof(int) * marker.size(), need = (2 * bx + bs + 2 * bm + 15) / 16 * 16;
+    const bool grow = wcells > c->cap_wcells || nent > c->cap_entries || need > c->stage_bytes;
+    if (grow) HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
     if (wcells > c->cap_wcells || nent > c->cap_entries) {
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        const long long cw = std::max(wcells, c->cap_wcells) * 3 / 2, ce = std::max(nent, c->cap_entries) * 3 / 2;
+        const long long cw = std::max(wcells, c->cap_wcells) * 3 / 2 + 1, ce = std::max(nent, c->cap_entries) * 3 / 2 + 1;
         if ((rc = dalloc(c, c->fwin, (size_t)dim * cw)) != FSA_OK) return rc;
         if ((rc = dalloc(c, c->cell_start, (size_t)cw + 1)) != FSA_OK) return rc;
         if ((rc = dalloc(c, c->cell_marker, (size_t)ce)) != FSA_OK) return rc;
@@ -401,42 +380,97 @@ int update_window_async(fsa_ctx* c, const double* X, const double* U)
         c->cap_wcells = cw;
         c->cap_entries = ce;
     }
-    const size_t bx = sizeof(double) * (size_t)dim * n, bs = sizeof(int) * count.size(),
-                 bm = sizeof(int) * marker.size(), need = 2 * bx + bs + bm;
-    if (c->stage_pending) {
-        HIPCHK(c, hipEventSynchronize(c->ev_stage));
-        c->stage_pending = false;
-    }
-    if (need > c->stage_bytes) {
+    if (need > c->stage_bytes) {   // (the stream is idle: see grow)
         if (c->h_stage) (void)hipHostFree(c->h_stage);
         c->h_stage = nullptr;
+        c->h_stage_dev = nullptr;
         c->stage_bytes = 0;
-        if (hipHostMalloc((void**)&c->h_stage, need * 2, hipHostMallocDefault) != hipSuccess) {
+        c->stage_pending[0] = c->stage_pending[1] = false;
+        void* hd = nullptr;
+        if (hipHostMalloc((void**)&c->h_stage, need * 4, hipHostMallocCoherent) != hipSuccess ||
+            hipHostGetDevicePointer(&hd, c->h_stage, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            if (c->h_stage) (void)hipHostFree(c->h_stage);
             c->h_stage = nullptr;
             return fail(c, FSA_ENOMEM, "pinned staging allocation failed");
         }
+        c->h_stage_dev = (const char*)hd;
+        if ((rc = dalloc(c, c->d_stage, need * 2)) != FSA_OK) return rc;
         c->stage_bytes = need * 2;
     }
-    char* h = c->h_stage;
+    // the half this placement fills: the launch that read it last time must have ended
+    const int half = c->stage_idx;
+    c->stage_idx ^= 1;
+    if (c->stage_pending[half]) {
+        HIPCHK(c, hipEventSynchronize(c->ev_stage[half]));
+        c->stage_pending[half] = false;
+    }
+    char* h = c->h_stage + half * c->stage_bytes;
     std::memcpy(h, X, bx);
     if (U) std::memcpy(h + bx, U, bx);
     else std::memset(h + bx, 0, bx);
     std::memcpy(h + 2 * bx, count.data(), bs);
     std::memcpy(h + 2 * bx + bs, marker.data(), bm);
-    HIPCHK(c, hipMemcpyAsync(c->X, h, bx, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->U, h + bx, bx, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->cell_start, h + 2 * bx, bs, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->cell_marker, h + 2 * bx + bs, bm, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipEventRecord(c->ev_stage, c->stream));
-    c->stage_pending = true;
+    std::memcpy(h + 2 * bx + bs + bm, ecell.data(), bm);
+    // (a copy kernel reading the coherent host block: a copy engine transfer would cost the
+    // stream more than ten microseconds of waiting per placement)
+    int e = launch_stage_in(c->h_stage_dev + half * c->stage_bytes, c->d_stage, (long long)(need / 16), c->stream);
+    if (e) return hipcheck(c, (hipError_t)e, "staging copy launch");
+    HIPCHK(c, hipEventRecord(c->ev_stage[half], c->stream));
+    c->stage_pending[half] = true;
     for (int k = 0; k < 3; ++k) {
         c->wlo[k] = wlo[k];
         c->wn[k] = wn[k];
     }
     c->wcells = wcells;
-    IBArgs A = ib_args(c);
-    int e = launch_ib_weights(c->G, A, c->mj0, c->mw, c->cell_w, c->stream);
-    return e ? hipcheck(c, (hipError_t)e, "IB weight launch") : FSA_OK;
+    WindowUpdate W;
+    const char* d = c->d_stage;
+    W.sX = (const double*)d;
+    W.sU = (const double*)(d + bx);
+    W.s_start = (const int*)(d + 2 * bx);
+    W.s_marker = (const int*)(d + 2 * bx + bs);
+    W.s_cell = (const int*)(d + 2 * bx + bs + bm);
+    W.nm = n;
+    W.wcells = wcells;
+    W.nent = nent;
+    for (int k = 0; k < 3; ++k) {
+        W.wlo[k] = wlo[k];
+        W.wn[k] = wn[k];
+    }
+    W.dV = c->dV;
+    W.X = c->X;
+    W.U = c->U;
+    W.cell_start = c->cell_start;
+    W.cell_marker = c->cell_marker;
+    W.mj0 = c->mj0;
+    W.mw = c->mw;
+    W.cell_w = c->cell_w;
+    e = launch_ib_window(c->G, W, c->stream);
+    return e ? hipcheck(c, (hipError_t)e, "IB window launch") : FSA_OK;
+}
+
+// First placement of the markers (c->hX, U; null U: zero), synchronously: the window buffers
+// are sized afresh.
+int build_window(fsa_ctx* c, const double* U)
+{
+    const int dim = c->d.dim, n = c->nm;
+    dfree(c->fwin);
+    dfree(c->cell_start);
+    dfree(c->cell_marker);
+    dfree(c->cell_w);
+    c->wcells = 0;
+    c->cap_wcells = c->cap_entries = 0;
+    for (int k = 0; k < 3; ++k) { c->wlo[k] = 0; c->wn[k] = 1; }
+    if (n == 0) { c->wn[0] = c->wn[1] = c->wn[2] = 0; return FSA_OK; }
+    int rc;
+    if ((rc = dalloc(c, c->mj0, (size_t)n * 3)) != FSA_OK) return rc;
+    if ((rc = dalloc(c, c->mw, (size_t)n * dim * 4)) != FSA_OK) return rc;
+    if ((rc = update_window_async(c, c->hX.data(), U)) != FSA_OK) return rc;
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemset(c->fwin, 0, sizeof(double) * (size_t)dim * c->cap_wcells));
+    HIPCHK(c, hipDeviceSynchronize());
+    c->stage_pending[0] = c->stage_pending[1] = false;
+    return FSA_OK;
 }
 
 IBArgs ib_args(const fsa_ctx* c)
@@ -849,7 +883,8 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
     }
     if (hipHostMalloc((void**)&c->h_abits, 12 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_alpha, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_stage, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_stage[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_stage[1], hipEventDisableTiming) != hipSuccess) {
         fsa_destroy(c);
         return FSA_ENOMEM;
     }
@@ -888,6 +923,7 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->cell_w);
     dfree(c->mj0);
     dfree(c->mw);
+    dfree(c->d_stage);
     dfree(c->Xp);
     dfree(c->mlp_master);
     dfree(c->mlp_wbf);
@@ -906,7 +942,8 @@ int32_t fsa_destroy(fsa_ctx* c)
     dfree(c->hv_total);
     if (c->h_abits) (void)hipHostFree(c->h_abits);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
-    if (c->ev_stage) (void)hipEventDestroy(c->ev_stage);
+    for (hipEvent_t ev : c->ev_stage)
+        if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : c->tev) (void)hipEventDestroy(ev);
     if (c->ev_alpha) (void)hipEventDestroy(c->ev_alpha);
     delete c;
@@ -921,7 +958,7 @@ int32_t fsa_set_markers(fsa_ctx* c, int32_t n, const double* X, const double* dV
     if (motion < FSA_STATIC || motion > FSA_EXTERNAL) return fail(c, FSA_EINVAL, "bad motion");
     if (n > 0 && !support_inside(c, n, X)) return fail(c, FSA_EINVAL, "a marker support leaves the grid");
     HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
-    c->stage_pending = false;   // (the stream is idle: earlier staging copies are done)
+    c->stage_pending[0] = c->stage_pending[1] = false;   // (the stream is idle: earlier staging copies are done)
     const int dim = c->d.dim;
     c->nm = n;
     c->motion = motion;
@@ -939,12 +976,8 @@ int32_t fsa_set_markers(fsa_ctx* c, int32_t n, const double* X, const double* dV
     HIPCHK(c, hipMemset(c->xi2, 0, sizeof(double) * ln));
     HIPCHK(c, hipMemset(c->xi_n, 0, sizeof(double) * ln));
     HIPCHK(c, hipMemset(c->F, 0, sizeof(double) * ln));
-    if (n > 0) {
-        HIPCHK(c, hipMemcpy(c->X, X, sizeof(double) * dim * n, hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(c->dV, dV, sizeof(double) * n, hipMemcpyHostToDevice));
-        if (U) HIPCHK(c, hipMemcpy(c->U, U, sizeof(double) * dim * n, hipMemcpyHostToDevice));
-    }
-    return build_window(c);
+    if (n > 0) HIPCHK(c, hipMemcpy(c->dV, dV, sizeof(double) * n, hipMemcpyHostToDevice));
+    return build_window(c, U);   // (X and U go to the device with the window lists)
 }
 
 int32_t fsa_set_marker_kinematics(fsa_ctx* c, const double* X, const double* U)
@@ -991,17 +1024,24 @@ int32_t fsa_rhs(fsa_ctx* c, const double* d_Q, double* d_L)
 {
     if (!c || !d_Q || !d_L) return FSA_EINVAL;
     if ((const void*)d_Q == (const void*)d_L) return fail(c, FSA_EINVAL, "d_L aliases d_Q");
+    c->advanced = nullptr;    // (the wave-speed reduction below reuses the step calls' slot 0)
+    c->qrange_of = nullptr;   // d_Q may have changed since the ranges were taken
     return enqueue_stage(c, d_Q, nullptr, d_L, 0, -1, true, 0, 0.0, 1.0, 0.0, 1);
 }
 
-int32_t fsa_rk3_steps(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps)
+namespace {
+
+int rk3_run(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps, bool resume)
 {
     if (!c || !d_Q) return FSA_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, FSA_EINVAL, "dt must be positive");
     if (nsteps < 1) return fail(c, FSA_EINVAL, "nsteps must be positive");
+    if (resume && c->advanced != d_Q)
+        return fail(c, FSA_ESTATE, "resume: d_Q is not the state the previous step call left");
     int rc = check_previous(c);
     if (rc != FSA_OK) return rc;
-    c->qrange_of = nullptr;   // d_Q may have changed since the last call
+    c->advanced = nullptr;
+    if (!resume) c->qrange_of = nullptr;   // d_Q may have changed since the last call
     static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
     static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
     // the wave speeds of every stage input come from the kernel that wrote it, except for
@@ -1011,8 +1051,8 @@ int32_t fsa_rk3_steps(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps)
             const int g = 3 * n + s;
             const double* Qs = s == 0 ? d_Q : (s == 1 ? c->Qa : c->Qb);
             double* out = s == 0 ? c->Qa : (s == 1 ? c->Qb : d_Q);
-            if ((rc = enqueue_stage(c, Qs, d_Q, out, g % 3, (g + 1) % 3, g == 0, s + 1, CA[s], CB[s],
-                                    dt, 0)) != FSA_OK)
+            if ((rc = enqueue_stage(c, Qs, d_Q, out, g % 3, (g + 1) % 3, g == 0 && !resume, s + 1, CA[s],
+                                    CB[s], dt, 0)) != FSA_OK)
                 return rc;
         }
         c->t += dt;
@@ -1026,9 +1066,17 @@ int32_t fsa_rk3_steps(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps)
         HIPCHK(c, hipEventRecord(c->ev_alpha, c->stream));
         c->alpha_pending = true;
     }
+    c->advanced = d_Q;   // (slot 0 holds its wave speeds)
     return FSA_OK;
 }
 
+}  // namespace
+
+int32_t fsa_rk3_steps(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps) { return rk3_run(c, d_Q, dt, nsteps, false); }
+int32_t fsa_rk3_steps_resume(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps)
+{
+    return rk3_run(c, d_Q, dt, nsteps, true);
+}
 int32_t fsa_rk3_step(fsa_ctx* c, double* d_Q, double dt) { return fsa_rk3_steps(c, d_Q, dt, 1); }
 
 int32_t fsa_ib_interp(fsa_ctx* c, const double* d_field, int32_t ncomp, double* d_out)

@@ -98,7 +98,29 @@ bool ib_stage_fused(const Grid& G, int nm);
 int totals_part_size(int nq);
 int launch_totals(const Grid& G, int nq, const double* Q, double* part, double* out, hipStream_t s);
 int launch_dilatation(const Grid& G, const Phys& P, const double* Q, long long step, double* out, hipStream_t s);
-int launch_ib_weights(const Grid& G, const IBArgs& A, int* mj0, double* mw, double* cell_w, hipStream_t s);
+// A marker placement: the staged arrays (device copies of one host block) are put in place
+// and the per-marker and per-entry weights computed from them.
+struct WindowUpdate {
+    const double* sX;         // staged positions [dim][nm]
+    const double* sU;         // staged velocities [dim][nm]
+    const int* s_start;       // staged CSR window cell -> markers: starts [wcells + 1]
+    const int* s_marker;      // markers per entry [nent] (increasing per cell)
+    const int* s_cell;        // window cell per entry [nent]
+    int nm;
+    long long wcells, nent;
+    int wlo[3], wn[3];
+    const double* dV;         // [nm]
+    double* X;                // out: positions, velocities, CSR lists
+    double* U;
+    int* cell_start;
+    int* cell_marker;
+    int* mj0;                 // out: per marker first support cell [nm][3]
+    double* mw;               // out: per marker one-dimensional weights [nm][dim][4]
+    double* cell_w;           // out: per entry W(cell) dV_k / h^dim
+};
+int launch_ib_window(const Grid& G, const WindowUpdate& W, hipStream_t s);
+// n16 16-byte words from src (host memory visible to the device, e.g. coherent pinned) to dst.
+int launch_stage_in(const void* src, void* dst, long long n16, hipStream_t s);
 int launch_interp(const Grid& G, int npts, const double* X, const double* field, int ncomp, double* out,
                   hipStream_t s);
 int launch_spread(const Grid& G, const IBArgs& A, const double* F, int ncomp, double* field, double scale,

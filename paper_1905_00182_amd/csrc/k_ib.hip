@@ -7,7 +7,8 @@
 // combination; then one thread per cell of the window box (the bounding box of all supports)
 // sums the spread force -F_k W_k dV_k / h^dim over that cell's markers in increasing marker
 // index (a deterministic gather).  The weights depend only on the marker positions and are
-// computed once per position update.
+// computed once per position update, by one launch that also puts the staged positions,
+// velocities and window lists in place.
 #include "fsa_impl.hpp"
 
 namespace fsa {
@@ -120,37 +121,49 @@ __device__ __forceinline__ double cell_weight(const Grid& G, const double* X, in
     return W;
 }
 
-// Set-up for static marker positions: per marker the first support cell and the
-// one-dimensional weights per direction; per CSR entry (window cell, marker) the spreading
-// weight W(cell) dV_k / h^dim.
+// 16-byte words from a host-visible block into device memory, each read once.
+__global__ __launch_bounds__(256) void k_stage_in(const uint4* __restrict__ src, uint4* __restrict__ dst, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// A marker placement from the staged lists (one contiguous host-to-device copy): per marker
+// X and U into place, the first support cell and the one-dimensional weights per direction;
+// the window's CSR lists into place; per CSR entry (window cell, marker) the spreading weight
+// W(cell) dV_k / h^dim.  One thread per item of the longest list, so every thread's loads are
+// at most two levels deep (entry -> marker position).
 template <int DIM>
-__global__ void k_ib_weights(Grid G, IBArgs A, int* __restrict__ mj0, double* __restrict__ mw,
-                             double* __restrict__ cell_w)
+__global__ void k_ib_window(Grid G, WindowUpdate W)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < A.nm) {
+    const int nm = W.nm;
+    if (t < (long long)DIM * nm) {
+        W.X[t] = W.sX[t];
+        W.U[t] = W.sU[t];
+    }
+    if (t < nm) {
         const int k = (int)t;
         int j0[3];
         double w[3][4];
-        marker_support<DIM>(G, A.X, A.nm, k, j0, w);
+        marker_support<DIM>(G, W.sX, nm, k, j0, w);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            mj0[k * 3 + d] = j0[d];
+            W.mj0[k * 3 + d] = j0[d];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) mw[(k * DIM + d) * 4 + m] = w[d][m];
+            for (int m = 0; m < 4; ++m) W.mw[(k * DIM + d) * 4 + m] = w[d][m];
         }
     }
-    const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
-    if (t < wcells) {
-        const long long c = t;
-        const int ci = A.wlo[0] + (int)(c % A.wn[0]);
-        const int cj = A.wlo[1] + (int)((c / A.wn[0]) % A.wn[1]);
-        const int ck = A.wlo[2] + (int)(c / ((long long)A.wn[0] * A.wn[1]));
+    if (t <= W.wcells) W.cell_start[t] = W.s_start[t];
+    if (t < W.nent) {
+        const int k = W.s_marker[t];
+        W.cell_marker[t] = k;
+        const long long c = W.s_cell[t];
+        const int ci = W.wlo[0] + (int)(c % W.wn[0]);
+        const int cj = W.wlo[1] + (int)((c / W.wn[0]) % W.wn[1]);
+        const int ck = W.wlo[2] + (int)(c / ((long long)W.wn[0] * W.wn[1]));
         const double hd = DIM == 3 ? G.h * G.h * G.h : G.h * G.h;
-        for (int e = A.cell_start[c]; e < A.cell_start[c + 1]; ++e) {
-            const int k = A.cell_marker[e];
-            cell_w[e] = (cell_weight<DIM>(G, A.X, A.nm, k, ci, cj, ck) * A.dV[k]) / hd;
-        }
+        W.cell_w[t] = (cell_weight<DIM>(G, W.sX, nm, k, ci, cj, ck) * W.dV[k]) / hd;
     }
 }
 
@@ -499,14 +512,24 @@ int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s
 
 bool ib_stage_fused(const Grid& G, int nm) { return G.dim == 2 && nm <= 4096; }
 
-int launch_ib_weights(const Grid& G, const IBArgs& A, int* mj0, double* mw, double* cell_w, hipStream_t s)
+int launch_stage_in(const void* src, void* dst, long long n16, hipStream_t s)
 {
-    const long long wcells = (long long)A.wn[0] * A.wn[1] * A.wn[2];
-    const long long n = wcells > A.nm ? wcells : A.nm;
-    if (n <= 0) return 0;
+    if (n16 <= 0) return 0;
+    long long b = (n16 + 255) / 256;
+    if (b > 256) b = 256;
+    hipLaunchKernelGGL(k_stage_in, dim3((unsigned)b), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
+    return (int)hipGetLastError();
+}
+
+int launch_ib_window(const Grid& G, const WindowUpdate& W, hipStream_t s)
+{
+    long long n = (long long)G.dim * W.nm;
+    n = n > W.wcells + 1 ? n : W.wcells + 1;
+    n = n > W.nent ? n : W.nent;
+    if (W.nm <= 0) return 0;
     const unsigned b = (unsigned)((n + 127) / 128);
-    if (G.dim == 3) hipLaunchKernelGGL(k_ib_weights<3>, dim3(b), dim3(128), 0, s, G, A, mj0, mw, cell_w);
-    else hipLaunchKernelGGL(k_ib_weights<2>, dim3(b), dim3(128), 0, s, G, A, mj0, mw, cell_w);
+    if (G.dim == 3) hipLaunchKernelGGL(k_ib_window<3>, dim3(b), dim3(128), 0, s, G, W);
+    else hipLaunchKernelGGL(k_ib_window<2>, dim3(b), dim3(128), 0, s, G, W);
     return (int)hipGetLastError();
 }
 

@@ -91,6 +91,7 @@ _SIGS = {
     "fsa_rhs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fsa_rk3_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double]),
     "fsa_rk3_steps": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32]),
+    "fsa_rk3_steps_resume": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32]),
     "fsa_ib_interp": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "fsa_ib_spread": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double]),
     "fsa_probe_dp": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -254,6 +255,11 @@ class Solver:
 
     def rk3_steps(self, Q, dt, nsteps):
         self._check(lib().fsa_rk3_steps(self.ctx, _ptr(self._state(Q)), dt, nsteps))
+        return Q
+
+    def rk3_steps_resume(self, Q, dt, nsteps=1):
+        """Continue from the previous step call on this Q (unchanged since): see fsa.h."""
+        self._check(lib().fsa_rk3_steps_resume(self.ctx, _ptr(self._state(Q)), dt, nsteps))
         return Q
 
     def ib_interp(self, field):

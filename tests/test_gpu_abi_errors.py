@@ -69,6 +69,29 @@ def test_argument_and_order_errors(fsa_mod):
     assert torch.isfinite(L).all()
 
 
+def test_resume_needs_the_state_of_the_last_step_call(fsa_mod):
+    import torch
+
+    case = _box()
+    s = fsa_mod.Solver(case)
+    Q = torch.from_numpy(W.perturbed_state(case, seed=2, amp=1e-2)).cuda()
+    Q2 = Q.clone()
+    lib = fsa_mod.lib()
+    p, p2 = fsa_mod._ptr(Q), fsa_mod._ptr(Q2)
+    assert lib.fsa_rk3_steps_resume(s.ctx, p, case.dt, 1) == fsa_mod.ESTATE    # no step call yet
+    s.rk3_step(Q, case.dt)
+    assert lib.fsa_rk3_steps_resume(s.ctx, p2, case.dt, 1) == fsa_mod.ESTATE   # another buffer
+    assert lib.fsa_rk3_steps_resume(s.ctx, p, 0.0, 1) == fsa_mod.EINVAL        # dt must be positive
+    s.rk3_steps_resume(Q, case.dt)                                               # the state it left
+    s.rk3_steps_resume(Q, case.dt, 2)
+    s.rhs(Q2)
+    assert lib.fsa_rk3_steps_resume(s.ctx, p, case.dt, 1) == fsa_mod.ESTATE    # slot reused since
+    s.rk3_step(Q, case.dt)
+    s.rk3_steps_resume(Q, case.dt)
+    s.sync()
+    assert torch.isfinite(Q).all()
+
+
 def test_learned_form_needs_a_network(fsa_mod):
     import torch
 

@@ -349,3 +349,32 @@ def test_quiet_tiles_change_nothing(torch_cuda, trained, stride):
     _say("quiet tiles, stride", stride, ": significant / fallback / sides", out[0][1:], "vs", out[1][1:])
     assert out[0][1:] == out[1][1:]
     assert torch_cuda.equal(out[0][0], out[1][0])
+
+
+@pytest.mark.parametrize("precision,stride", [("fp64", 1), ("learned32", 1), ("learned32", 3)])
+def test_resume_equals_one_call(torch_cuda, trained, precision, stride):
+    """Steps continued one call at a time (fsa_rk3_steps_resume: the wave speeds and quiet-tile
+    ranges of the state taken from the kernels that wrote it) are bit for bit the steps of one
+    call, on the rotating-cylinder miniature (markers, sponge, learned selector)."""
+    c = trained["c2"].with_(precision=precision, extra={"selector_stride": stride})
+    Q0 = torch_cuda.from_numpy(W.config2_state(c)).cuda()
+    out = []
+    for resume in (False, True):
+        s = _solver(c)
+        if precision == "learned32":
+            s.mlp_set(trained["theta"], 0.8)
+        Q = Q0.clone()
+        if resume:
+            s.rk3_step(Q, c.dt)
+            for _ in range(29):
+                s.rk3_steps_resume(Q, c.dt)
+        else:
+            s.rk3_steps(Q, c.dt, 30)
+        s.sync()
+        st = s.stats()
+        out.append((Q, st.significant_sides, st.fallback_sides, st.learned_sides))
+        s.close()
+    _say(precision, "stride", stride, ": resumed one step at a time vs one call of 30 steps;",
+         "significant / fallback / sides", out[1][1:], "vs", out[0][1:])
+    assert out[0][1:] == out[1][1:]
+    assert torch_cuda.equal(out[0][0], out[1][0])

@@ -110,12 +110,13 @@ def test_inflow_every_side(torch_cuda):
     _assert_q_close(Qg, Qo, Q0, case)
 
 
-@pytest.mark.parametrize("scheme,nsteps", [("weno5js", 20), ("teno5", 3)])
-def test_flapping_plate_moving_markers(torch_cuda, scheme, nsteps):
+@pytest.mark.parametrize("scheme,nsteps,resume", [("weno5js", 20, True), ("teno5", 3, False)])
+def test_flapping_plate_moving_markers(torch_cuda, scheme, nsteps, resume):
     """The rigid flapping plate in a stream (prescribed heave and pitch of its clamped leading
     edge): the markers move every step, positions and velocities set before each step on both
     sides (the library rebuilds its spreading window), against the oracle with the marker
-    forces."""
+    forces; the library's steps after the first either continue the previous call's state
+    (resume) or start afresh."""
     case = W.config5(n=128, L=8.0, nmark=128, scheme=scheme)
     Q0 = W.uniform_state(case)
     _say("flapping plate", scheme, "x", nsteps)
@@ -127,7 +128,10 @@ def test_flapping_plate_moving_markers(torch_cuda, scheme, nsteps):
         X, U = W.plate_kinematics(case, n * case.dt)
         s.set_marker_kinematics(X, U)
         o.set_marker_kinematics(X, U)
-        s.rk3_step(Qg, case.dt)
+        if resume and n > 0:
+            s.rk3_steps_resume(Qg, case.dt)
+        else:
+            s.rk3_step(Qg, case.dt)
         o.rk3_step(Qo, case.dt)
     s.sync()
     _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
