@@ -445,8 +445,8 @@ int update_window_async(fsa_ctx* c, const double* X, const double* U)
     W.mj0 = c->mj0;
     W.mw = c->mw;
     W.cell_w = c->cell_w;
-    e = launch_ib_window(c->G, W, c->stream);
-    return e ? hipcheck(c, (hipError_t)e, "IB window launch") : FSA_OK;
+    e = launch_ib_place(c->G, W, c->stream);
+    return e ? hipcheck(c, (hipError_t)e, "IB placement launch") : FSA_OK;
 }
 
 // First placement of the markers (c->hX, U; null U: zero), synchronously: the window buffers

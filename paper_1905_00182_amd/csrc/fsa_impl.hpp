@@ -118,7 +118,7 @@ struct WindowUpdate {
     double* mw;               // out: per marker one-dimensional weights [nm][dim][4]
     double* cell_w;           // out: per entry W(cell) dV_k / h^dim
 };
-int launch_ib_window(const Grid& G, const WindowUpdate& W, hipStream_t s);
+int launch_ib_place(const Grid& G, const WindowUpdate& W, hipStream_t s);
 // n16 16-byte words from src (host memory visible to the device, e.g. coherent pinned) to dst.
 int launch_stage_in(const void* src, void* dst, long long n16, hipStream_t s);
 int launch_interp(const Grid& G, int npts, const double* X, const double* field, int ncomp, double* out,

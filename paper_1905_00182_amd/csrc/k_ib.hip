@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_stage_in(const uint4* __restrict__ src,
 // W(cell) dV_k / h^dim.  One thread per item of the longest list, so every thread's loads are
 // at most two levels deep (entry -> marker position).
 template <int DIM>
-__global__ void k_ib_window(Grid G, WindowUpdate W)
+__global__ void k_ib_place(Grid G, WindowUpdate W)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int nm = W.nm;
@@ -521,15 +521,15 @@ int launch_stage_in(const void* src, void* dst, long long n16, hipStream_t s)
     return (int)hipGetLastError();
 }
 
-int launch_ib_window(const Grid& G, const WindowUpdate& W, hipStream_t s)
+int launch_ib_place(const Grid& G, const WindowUpdate& W, hipStream_t s)
 {
     long long n = (long long)G.dim * W.nm;
     n = n > W.wcells + 1 ? n : W.wcells + 1;
     n = n > W.nent ? n : W.nent;
     if (W.nm <= 0) return 0;
     const unsigned b = (unsigned)((n + 127) / 128);
-    if (G.dim == 3) hipLaunchKernelGGL(k_ib_window<3>, dim3(b), dim3(128), 0, s, G, W);
-    else hipLaunchKernelGGL(k_ib_window<2>, dim3(b), dim3(128), 0, s, G, W);
+    if (G.dim == 3) hipLaunchKernelGGL(k_ib_place<3>, dim3(b), dim3(128), 0, s, G, W);
+    else hipLaunchKernelGGL(k_ib_place<2>, dim3(b), dim3(128), 0, s, G, W);
     return (int)hipGetLastError();
 }
 
