@@ -111,10 +111,13 @@ class Plate:
         self.a[4:] = np.linalg.solve(self.M[4:, 4:], rhs)
         self._dt = None
 
-    def set_state(self, e, v, t):
+    def set_state(self, e, v, t, a=None):
         """Checkpoint restore: coordinates, their velocities and the time; the accelerations
-        follow from the equation without load."""
+        as given, else from the equation without load."""
         self.e, self.v, self.t = np.array(e, dtype=np.float64), np.array(v, dtype=np.float64), float(t)
+        if a is not None:
+            self.a = np.array(a, dtype=np.float64)
+            return self
         r, d, rt, dt_, rtt, dtt = self.clamp(self.t)
         ap = np.concatenate([rtt, dtt])
         self.a = np.zeros(self.ndof)

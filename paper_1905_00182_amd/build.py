@@ -4,8 +4,8 @@ All device code is compiled with packed-FP32 instructions disabled (they are nev
 and with contraction of a multiply and an add into an FMA only within one source expression
 (-ffp-contract=on): the rounding of a formula is then fixed by its source text, so kernels
 that evaluate the same formula (the precision form's TENO5 and the learned form's fallback)
-agree bit for bit whatever the surrounding code.  The C ABI is declared in include/fsa.h at
-the repository root.
+agree bit for bit whatever the surrounding code.  The C ABI is declared in include/fsa.h
+(the solver) and include/fsa_plate.h (the flexible plate, host code) at the repository root.
 """
 import os
 import subprocess
@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfsa.so")
-SOURCES = ["fsa_api.hip", "k_stage2d.hip", "k_stage3d.hip", "k_ib.hip", "k_mlp.hip", "k_faces2d.hip"]
+SOURCES = ["fsa_api.hip", "k_stage2d.hip", "k_stage3d.hip", "k_ib.hip", "k_mlp.hip", "k_faces2d.hip", "plate.cpp"]
 ARCH = os.environ.get("FSA_OFFLOAD_ARCH", "gfx950")
 
 

@@ -77,6 +77,26 @@ class FsaStats(C.Structure):
 
 _lib = None
 
+class FsaPlateDesc(C.Structure):
+    _fields_ = [
+        ("length", C.c_double),
+        ("n_elements", C.c_int32),
+        ("rho_s", C.c_double),
+        ("k_s", C.c_double),
+        ("k_b", C.c_double),
+        ("n_markers", C.c_int32),
+        ("s_mark", C.c_void_p),
+        ("dv_mark", C.c_void_p),
+        ("edge", C.c_double * 2),
+        ("a0", C.c_double),
+        ("beta", C.c_double),
+        ("alpha_m", C.c_double),
+        ("freq", C.c_double),
+        ("phi", C.c_double),
+        ("t0", C.c_double),
+    ]
+
+
 _SIGS = {
     "fsa_abi_version": (C.c_int32, []),
     "fsa_status_str": (C.c_char_p, [C.c_int32]),
@@ -111,7 +131,73 @@ _SIGS = {
     "fsa_timing_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "fsa_sync": (C.c_int32, [C.c_void_p]),
     "fsa_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(FsaStats)]),
+    # include/fsa_plate.h
+    "fsa_plate_create": (C.c_int32, [C.POINTER(FsaPlateDesc), C.POINTER(C.c_void_p)]),
+    "fsa_plate_destroy": (C.c_int32, [C.c_void_p]),
+    "fsa_plate_markers": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsa_plate_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double]),
+    "fsa_plate_get_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "fsa_plate_set_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
+    "fsa_plate_last_error": (C.c_char_p, [C.c_void_p]),
 }
+
+
+class Plate:
+    """The flexible plate of include/fsa_plate.h (host code) for a case whose extra holds the
+    clamp kinematics ("plate") and the structure ("flex"); the markers are the case's."""
+
+    def __init__(self, case, t0=0.0):
+        p, fl = case.extra["plate"], case.extra["flex"]
+        self._s = np.ascontiguousarray(p["s"], dtype=np.float64)
+        self._dv = np.ascontiguousarray(case.markers["dV"], dtype=np.float64)
+        self.nm, self.ndof = len(self._s), 4 * (int(fl["nel"]) + 1)
+        d = FsaPlateDesc()
+        d.length, d.n_elements, d.rho_s, d.k_s, d.k_b = fl["length"], fl["nel"], fl["rho_s"], fl["k_s"], fl["k_b"]
+        d.n_markers, d.s_mark, d.dv_mark = self.nm, self._s.ctypes.data, self._dv.ctypes.data
+        d.edge[0], d.edge[1] = p["edge"]
+        d.a0, d.beta, d.alpha_m, d.freq, d.phi, d.t0 = p["A0"], p["beta"], p["alpha_m"], p["f"], p["phi"], t0
+        h = C.c_void_p()
+        rc = lib().fsa_plate_create(C.byref(d), C.byref(h))
+        if rc != OK:
+            raise FsaError(rc, "fsa_plate_create")
+        self.h = h
+
+    def _check(self, rc):
+        if rc != OK:
+            raise FsaError(rc, lib().fsa_plate_last_error(self.h).decode())
+
+    def markers(self):
+        X = np.empty((2, self.nm))
+        U = np.empty((2, self.nm))
+        self._check(lib().fsa_plate_markers(self.h, X.ctypes.data, U.ctypes.data))
+        return X, U
+
+    def step(self, F, dt):
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        assert F.shape == (2, self.nm)
+        self._check(lib().fsa_plate_step(self.h, F.ctypes.data, dt))
+
+    def get_state(self):
+        e, v, a, t = np.empty(self.ndof), np.empty(self.ndof), np.empty(self.ndof), C.c_double()
+        self._check(lib().fsa_plate_get_state(self.h, e.ctypes.data, v.ctypes.data, a.ctypes.data, C.byref(t)))
+        return e, v, a, t.value
+
+    def set_state(self, e, v, a, t):
+        e, v = np.ascontiguousarray(e, dtype=np.float64), np.ascontiguousarray(v, dtype=np.float64)
+        a = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        self._check(lib().fsa_plate_set_state(self.h, e.ctypes.data, v.ctypes.data,
+                                              None if a is None else a.ctypes.data, t))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fsa_plate_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def lib():

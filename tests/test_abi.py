@@ -1,5 +1,5 @@
 """The C-ABI library loads on a machine without a GPU and exports every function that
-include/fsa.h declares (no compute calls are made here)."""
+include/*.h declares (no GPU calls are made here)."""
 import ctypes
 import os
 import re
@@ -11,7 +11,8 @@ HEADER = os.path.join(ROOT, "include", "fsa.h")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**(fsa_[a-z_0-9]+)\s*\(", text, flags=re.M)))
 
@@ -53,3 +54,12 @@ def test_descriptor_layouts_match_the_header():
     body = re.search(r"typedef struct fsa_stats \{(.*?)\} fsa_stats;", text, flags=re.S).group(1)
     fields = re.findall(r"^\s*[a-z_0-9]+\s+([a-z_0-9]+)(?:\[|;)", body, flags=re.M)
     assert fields == [f[0] for f in fsa.FsaStats._fields_]
+
+
+def test_plate_descriptor_layout_matches_the_header():
+    from paper_1905_00182_amd import fsa
+
+    text = open(os.path.join(ROOT, "include", "fsa_plate.h")).read()
+    body = re.search(r"typedef struct fsa_plate_desc \{(.*?)\} fsa_plate_desc;", text, flags=re.S).group(1)
+    fields = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**([a-z_0-9]+)(?:\[|;)", body, flags=re.M)
+    assert fields == [f[0] for f in fsa.FsaPlateDesc._fields_]

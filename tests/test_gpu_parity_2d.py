@@ -139,6 +139,49 @@ def test_flapping_plate_moving_markers(torch_cuda, scheme, nsteps, resume):
     assert np.abs(Qo[1:3] - Q0[1:3]).max() > 1e-4   # the plate has stirred the stream
 
 
+def test_flexible_plate_coupled(torch_cuda):
+    """The flexible flapping plate: fluid and structure coupled explicitly every step (the
+    markers follow the plate; the plate is loaded by the step's marker forces), the library's
+    HIP fluid and host plate against the oracle's fluid and plate."""
+    from oracle.ancf import Plate, flapping_clamp
+    from paper_1905_00182_amd import fsa
+
+    # (10 elements: the miniature's fluid step, 0.015, is above a 40-element plate's explicit
+    # stretching limit, 0.0043, which scales with the element length)
+    case = W.config5_flexible(n=128, L=8.0, nmark=128, scheme="weno5js", nel=10)
+    p, fl = case.extra["plate"], case.extra["flex"]
+    Q0 = W.uniform_state(case)
+    _say("flexible plate coupled x 20")
+    s = _solver(case)
+    o = _oracle(case)
+    lp = fsa.Plate(case)
+    op = Plate(fl["length"], fl["nel"], fl["rho_s"], fl["k_s"], fl["k_b"], p["s"], case.markers["dV"],
+               flapping_clamp(p))
+    Qg = torch_cuda.from_numpy(Q0.copy()).cuda()
+    Qo = Q0.copy()
+    for n in range(20):
+        X, U = lp.markers()
+        s.set_marker_kinematics(X, U)
+        if n > 0:
+            s.rk3_steps_resume(Qg, case.dt)
+        else:
+            s.rk3_step(Qg, case.dt)
+        lp.step(s.marker_force(), case.dt)
+        Xo, Uo = op.markers()
+        o.set_marker_kinematics(Xo, Uo)
+        o.rk3_step(Qo, case.dt)
+        op.step(o.marker_force(), case.dt)
+    s.sync()
+    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
+    e, v, a, t = lp.get_state()
+    # (the plate's own rounding bound over 20 steps is ~1e-12; the forces agree to ~1e-9)
+    np.testing.assert_allclose(e, op.e, atol=1e-11, rtol=0)
+    np.testing.assert_allclose(v, op.v, atol=1e-9, rtol=0)
+    rigid = Plate(fl["length"], fl["nel"], fl["rho_s"], fl["k_s"], fl["k_b"], p["s"], case.markers["dV"],
+                  flapping_clamp(p), t0=op.t)
+    assert np.abs(op.e - rigid.e).max() > 1e-7      # the fluid has bent the plate
+
+
 def test_free_stream_exactly_zero(torch_cuda):
     case = _c2_small(n=150, nprobe=0).with_(markers=None, inflow_amp=0.0)
     Q0 = W.uniform_state(case)

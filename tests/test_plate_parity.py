@@ -1,0 +1,98 @@
+"""The library's flexible plate (include/fsa_plate.h, host code) against the oracle's, on the
+CPU: the same coordinates, velocities and markers to rounding after hundreds of steps of the
+flapping-plate kinematics under seeded marker loads, exact checkpoint restarts, and the
+rejections its header states."""
+import numpy as np
+import pytest
+
+from paper_1905_00182_amd import workloads as W
+
+
+def _oracle_plate(case, t0=0.0):
+    from oracle.ancf import Plate, flapping_clamp
+
+    p, fl = case.extra["plate"], case.extra["flex"]
+    return Plate(fl["length"], fl["nel"], fl["rho_s"], fl["k_s"], fl["k_b"], p["s"], case.markers["dV"],
+                 flapping_clamp(p), t0=t0)
+
+
+def _loads(nm, n, seed):
+    # smooth along the plate, varying in time: a few modes of amplitude ~1e-2 (the size of
+    # the flapping plate's pressure loads at U0 = 0.1)
+    r = np.random.default_rng(seed)
+    s = (np.arange(nm) + 0.5) / nm
+    a = r.normal(size=(n, 2, 4)) * 1e-2
+    return [np.stack([sum(a[k, c, m] * np.cos(np.pi * m * s) for m in range(4)) for c in range(2)]) for k in range(n)]
+
+
+@pytest.fixture(scope="module")
+def case():
+    return W.config5_flexible(n=128, L=8.0, nmark=64)
+
+
+def test_library_plate_matches_the_oracle(case):
+    from paper_1905_00182_amd import fsa
+
+    lp, op = fsa.Plate(case, t0=0.3), _oracle_plate(case, t0=0.3)
+    X0, U0 = lp.markers()
+    Xo, Uo = op.markers()
+    np.testing.assert_allclose(X0, Xo, atol=1e-15)
+    np.testing.assert_allclose(U0, Uo, atol=1e-15)
+    dt = W.config5_flexible(n=1024).dt        # the bench's fluid step
+    # Tolerances: the bending force K e of a nearly straight plate cancels entries of size
+    # 12 K_B / l^3 ~ 8e3 to ~1e-12, which M^-1 (through the slope coordinates) amplifies to
+    # ~1e-7 in the accelerations; each step carries dt^2/4 of that into the coordinates,
+    # ~6e-14 per step.  One step: 1e-13; 400 steps: 2e-10 (chord units).  Velocities take
+    # dt/2 of the acceleration difference (~4e-10), which does not accumulate: 1e-9.
+    for k, F in enumerate(_loads(case.markers["X"].shape[1], 400, seed=7)):
+        lp.step(F, dt)
+        op.step(F, dt)
+        if k == 0:
+            np.testing.assert_allclose(lp.get_state()[0], op.e, atol=1e-13, rtol=0)
+    e, v, a, t = lp.get_state()
+    assert t == pytest.approx(op.t, rel=1e-15)
+    defl = np.abs(op.e - _oracle_plate(case, t0=op.t).e).max()     # distance from the rigid plate
+    assert defl > 1e-3
+    np.testing.assert_allclose(e, op.e, atol=2e-10, rtol=0)
+    np.testing.assert_allclose(v, op.v, atol=1e-9, rtol=0)
+    X, U = lp.markers()
+    Xo, Uo = op.markers()
+    np.testing.assert_allclose(X, Xo, atol=2e-10, rtol=0)
+    np.testing.assert_allclose(U, Uo, atol=1e-9, rtol=0)
+
+
+def test_checkpoint_restart_is_exact(case):
+    from paper_1905_00182_amd import fsa
+
+    dt = W.config5_flexible(n=1024).dt
+    loads = _loads(case.markers["X"].shape[1], 40, seed=3)
+    run = fsa.Plate(case)
+    for F in loads[:20]:
+        run.step(F, dt)
+    state = run.get_state()
+    for F in loads[20:]:
+        run.step(F, dt)
+    again = fsa.Plate(case)
+    again.set_state(*state)
+    for F in loads[20:]:
+        again.step(F, dt)
+    for x, y in zip(run.get_state(), again.get_state()):
+        assert np.array_equal(x, y)
+
+
+def test_rejections(case):
+    from paper_1905_00182_amd import fsa
+
+    p = fsa.Plate(case)
+    F = np.zeros((2, p.nm))
+    for dt in (0.0, -1.0, 1.0):      # 1.0: far above the stretching limit
+        with pytest.raises(fsa.FsaError) as e:
+            p.step(F, dt)
+        assert e.value.code == fsa.EINVAL
+    with pytest.raises(fsa.FsaError) as e:
+        p.step(F, 1.0)
+    assert "stretching limit" in str(e.value)
+    p.step(F, 1e-3)                  # still usable
+    bad = case.with_(extra={**case.extra, "flex": {**case.extra["flex"], "rho_s": 0.0}})
+    with pytest.raises(fsa.FsaError):
+        fsa.Plate(bad)
