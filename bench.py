@@ -124,7 +124,7 @@ def full_run(case, Q0, nsteps, every, net=None):
     }
 
 
-def variants(case, Q0, nsteps, every=10):
+def variants(case, Q0, nsteps, every=10, plate_steps=None):
     import torch
 
     from paper_1905_00182_amd import selector
@@ -167,8 +167,8 @@ def variants(case, Q0, nsteps, every=10):
             else:
                 e["note"] = "keep patterns from each step's first stage, reused by its other two stages"
         res[name] = e
-    res["c5_flapping_plate"] = flapping_plate(net)
-    res["c5_flexible_plate"] = flapping_plate(net, flexible=True)
+    res["c5_flapping_plate"] = flapping_plate(net, nsteps=plate_steps)
+    res["c5_flexible_plate"] = flapping_plate(net, nsteps=plate_steps, flexible=True)
     res["run"] = {"steps": nsteps, "probes": int(dp64.shape[1]), "probe_every": every,
                   "max_probe_dp_r50": float(dp64.abs().max()), "max_probe_dp_r10": float(dpn64.abs().max()),
                   "note": "whole run from the uniform start, probe launches included in the timing (the r50 "
@@ -294,6 +294,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the full-run comparison of the FP64, FP32 and FP32+learned forms")
     ap.add_argument("--variant-steps", type=int, default=None, help="steps of the full runs (default: the case's)")
+    ap.add_argument("--plate-steps", type=int, default=None,
+                    help="steps of the flapping-plate runs (default: one flapping period)")
     ap.add_argument("--scheme", default="teno5", choices=["teno5", "weno5js"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
@@ -386,7 +388,7 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_variants:
-        out["variants"] = variants(case, Q0, args.variant_steps or case.steps)
+        out["variants"] = variants(case, Q0, args.variant_steps or case.steps, plate_steps=args.plate_steps)
         out["variants"]["three_d"] = three_d()
     if not args.no_cpu and args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
