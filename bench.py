@@ -169,6 +169,7 @@ def variants(case, Q0, nsteps, every=10, plate_steps=None):
         res[name] = e
     res["c5_flapping_plate"] = flapping_plate(net, nsteps=plate_steps)
     res["c5_flexible_plate"] = flapping_plate(net, nsteps=plate_steps, flexible=True)
+    res["hovering_insect"] = hovering_insect(net, nsteps=plate_steps)
     res["run"] = {"steps": nsteps, "probes": int(dp64.shape[1]), "probe_every": every,
                   "max_probe_dp_r50": float(dp64.abs().max()), "max_probe_dp_r10": float(dpn64.abs().max()),
                   "note": "whole run from the uniform start, probe launches included in the timing (the r50 "
@@ -178,22 +179,41 @@ def variants(case, Q0, nsteps, every=10, plate_steps=None):
 
 def flapping_plate(net, nsteps=None, every=10, flexible=False):
     """Config 5's plate at 1024^2 from the uniform stream over one flapping period
-    (nsteps=None; 21,110 steps at CFL 0.5): FP64 TENO5 against the learned form with the
-    selector once per step.  The markers move every step (positions and velocities set before
-    each step, one step call per step continuing the previous one's state): rigid, with the
-    paper's prescribed heave and pitch, or (flexible=True) following the flexible plate, which
-    each step's marker forces load (explicit coupling: the force read-out synchronises every
-    step).  Delta p on a radius-3 ring every `every` steps; the learned form's error is the
-    relative L2 over probes x samples against FP64."""
+    (nsteps=None; 21,110 steps at CFL 0.5), rigid with the paper's prescribed heave and pitch
+    or (flexible=True) following the flexible plate, which each step's marker forces load
+    (explicit coupling: the force read-out synchronises every step); probes on a radius-3
+    ring.  See moving_body_forms."""
+    from paper_1905_00182_amd import workloads as W
+
+    case = (W.config5_flexible(n=1024) if flexible else W.config5(n=1024)).with_(probes=W.ring_probes(64, 3.0))
+    if nsteps is None:
+        nsteps = int(round(1.0 / case.extra["plate"]["f"] / case.dt))
+    return moving_body_forms(case, W.plate_kinematics, net, nsteps, every, flexible)
+
+
+def hovering_insect(net, nsteps=None, every=10):
+    """The hovering insect at 800^2 (50 cells per wing length) from rest over one flapping
+    period (nsteps=None; 8000 steps); probes on a radius-5 ring.  See moving_body_forms."""
+    from paper_1905_00182_amd import workloads as W
+
+    case = W.insect()
+    if nsteps is None:
+        nsteps = int(round(1.0 / case.extra["insect"]["f"] / case.dt))
+    return moving_body_forms(case, W.insect_kinematics, net, nsteps, every, False)
+
+
+def moving_body_forms(case, kinematics, net, nsteps, every=10, flexible=False):
+    """FP64 TENO5 against the FP32 precision form and the learned form with the selector once
+    per step on a case whose markers move every step (positions and velocities set before
+    each step by kinematics(case, t), or by the flexible plate; one step call per step
+    continuing the previous one's state).  Delta p on the case's probes every `every` steps;
+    errors are relative L2 over probes x samples against FP64."""
     import numpy as np
     import torch
 
     from paper_1905_00182_amd import fsa
     from paper_1905_00182_amd import workloads as W
 
-    case = (W.config5_flexible(n=1024) if flexible else W.config5(n=1024)).with_(probes=W.ring_probes(64, 3.0))
-    if nsteps is None:
-        nsteps = int(round(1.0 / case.extra["plate"]["f"] / case.dt))
     nsteps -= nsteps % every
     Q0 = torch.from_numpy(W.uniform_state(case)).cuda()
     runs = {}
@@ -210,7 +230,7 @@ def flapping_plate(net, nsteps=None, every=10, flexible=False):
         t0 = time.perf_counter()
         for k in range(nsamp):
             for m in range(every):
-                X, U = plate.markers() if flexible else W.plate_kinematics(c, (k * every + m) * c.dt)
+                X, U = plate.markers() if flexible else kinematics(c, (k * every + m) * c.dt)
                 s.set_marker_kinematics(X, U)
                 if k == 0 and m == 0:
                     s.rk3_step(Q, c.dt)
@@ -222,9 +242,8 @@ def flapping_plate(net, nsteps=None, every=10, flexible=False):
         torch.cuda.synchronize()
         runs[name] = (time.perf_counter() - t0, dps)
         if flexible:
-            e, _, _, _ = plate.get_state()
             X, _ = plate.markers()
-            Xr, _ = W.plate_kinematics(c, nsteps * c.dt)
+            Xr, _ = kinematics(c, nsteps * c.dt)
             runs[name] += (float(np.abs(X - Xr).max()),)
             plate.close()
         s.close()
@@ -232,7 +251,8 @@ def flapping_plate(net, nsteps=None, every=10, flexible=False):
     wm, dpm = runs["mixed32"][:2]
     wl, dpl = runs["learned32_stride3"][:2]
     cs = case.ncell * 3 * nsteps
-    return {"grid": list(case.n[:2]), "steps": nsteps, "probes": 64, "probe_every": every,
+    return {"grid": list(case.n[:2]), "steps": nsteps, "markers": int(case.markers["X"].shape[1]),
+            "probes": int(dp64.shape[1]), "probe_every": every,
             "fp64": {"value": round(cs / w64 / 1e6, 1), "unit": "Mcell-stage/s",
                      "ms_per_step": round(w64 / nsteps * 1e3, 4)},
             "mixed32": {"value": round(cs / wm / 1e6, 1), "unit": "Mcell-stage/s",
@@ -295,7 +315,7 @@ def main():
                     help="skip the full-run comparison of the FP64, FP32 and FP32+learned forms")
     ap.add_argument("--variant-steps", type=int, default=None, help="steps of the full runs (default: the case's)")
     ap.add_argument("--plate-steps", type=int, default=None,
-                    help="steps of the flapping-plate runs (default: one flapping period)")
+                    help="steps of the flapping-plate and hovering-insect runs (default: one flapping period)")
     ap.add_argument("--scheme", default="teno5", choices=["teno5", "weno5js"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")

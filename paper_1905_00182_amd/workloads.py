@@ -368,6 +368,66 @@ def config5_flexible(n=1024, L=16.0, nmark=256, steps=2000, scheme="teno5", nel=
     return c.with_(name="c5_flexible_plate", extra={**c.extra, "flex": flex})
 
 
+def insect_kinematics(case, t):
+    """Markers of the hovering insect at time t (Sec. 3, insect in hovering flight): the body
+    (static) and the two wings, rigid ellipses hinged at the body's sides and flapping
+    symmetrically by alpha(t) = alpha0 [1 + sin(2 pi f t)] (upward from the horizontal).
+    Returns X[2][n], U[2][n] in the order body, right wing, left wing (the left wing is the
+    mirror image of the right one in x = 0)."""
+    p = case.extra["insect"]
+    w = 2.0 * math.pi * p["f"]
+    al = p["alpha0"] * (1.0 + math.sin(w * t))
+    alt = p["alpha0"] * w * math.cos(w * t)
+    th = p["theta"]
+    ca, sa = math.cos(al), math.sin(al)
+    hx = p["hinge"]
+    # right wing: centre at the hinge plus a along the wing's axis (cos al, sin al)
+    cx, cy = hx + p["a"] * ca, p["a"] * sa
+    ex, ey = p["a"] * np.cos(th), p["b"] * np.sin(th)
+    xr = cx + ca * ex - sa * ey
+    yr = cy + sa * ex + ca * ey
+    ur = -alt * yr                        # rotation about the hinge (hx, 0) at rate alt
+    vr = alt * (xr - hx)
+    nb = len(p["body_x"])
+    X = np.concatenate([np.stack([p["body_x"], p["body_y"]]), np.stack([xr, yr]), np.stack([-xr, yr])], axis=1)
+    U = np.concatenate([np.zeros((2, nb)), np.stack([ur, vr]), np.stack([-ur, vr])], axis=1)
+    return X, U
+
+
+def insect(n=800, L=16.0, sponge=2.0, steps=2000, scheme="teno5", nprobe=64, rprobe=5.0):
+    """2D hovering insect (Sec. 3): a circular body of diameter 0.5 and two elliptic wings of
+    length 1 and width 0.4 (the wing length is the unit), hinged at the body's sides, in a
+    quiescent fluid; Re = rho U_max / mu = 200 and M = U_max / c = 0.1 with U_max the
+    reference velocity, the flapping frequency from St = f / U_max = 0.25 (the paper's wing-tip
+    reading of U_max does not fit its alpha0 and St together; U_max is taken as the reference
+    speed and f from St), alpha0 = 25.3 degrees; 50 cells per wing length on [-L/2, L/2]^2,
+    zero-gradient sides, sponge `sponge` wide; markers about one cell apart, the wings'
+    at equal parameter steps with their arc-length weights.  The markers move every step
+    (`insect_kinematics`)."""
+    umax = 0.1
+    h = L / n
+    c = Case(name="insect_hovering", dim=2, n=(n, n, 1), lo=(-L / 2, -L / 2, 0.0), h=h,
+             bc=(("extrap", "extrap"), ("extrap", "extrap"), ("periodic", "periodic")),
+             mu=umax / 200.0, scheme=scheme, prim_inf=(1.0, 0.0, 0.0, 0.0, 1.0 / GAMMA),
+             sponge_width=((sponge, sponge), (sponge, sponge), (0.0, 0.0)), sponge_sigma=20.0 / max(sponge, 1e-9),
+             steps=steps)
+    rb, a, b = 0.25, 0.5, 0.2
+    nb = max(8, int(round(2 * math.pi * rb / h)))
+    tb = 2 * math.pi * (np.arange(nb) + 0.5) / nb
+    perim = math.pi * (3 * (a + b) - math.sqrt((3 * a + b) * (a + 3 * b)))
+    nw = max(8, int(round(perim / h)))
+    th = 2 * math.pi * (np.arange(nw) + 0.5) / nw
+    dvw = np.hypot(a * np.sin(th), b * np.cos(th)) * (2 * math.pi / nw)   # |dX/dtheta| dtheta
+    ins = {"hinge": rb, "a": a, "b": b, "theta": th, "alpha0": math.radians(25.3), "f": 0.25 * umax,
+           "body_x": rb * np.cos(tb), "body_y": rb * np.sin(tb)}
+    c = c.with_(extra={"insect": ins})
+    X, U = insect_kinematics(c, 0.0)
+    dV = np.concatenate([np.full(nb, 2 * math.pi * rb / nb), dvw, dvw])
+    c = c.with_(markers={"X": X, "dV": dV, "U": U, "motion": "external", "omega": 0.0},
+                probes=ring_probes(nprobe, rprobe) if nprobe else None)
+    return _finish(c)
+
+
 def config4(n=384, steps=500):
     """Precision variant of the sphere case at 384^3 (FP32 faces, FP64 state)."""
     c = config3(n=n, scheme="teno5", steps=steps)

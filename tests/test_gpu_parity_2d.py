@@ -139,6 +139,31 @@ def test_flapping_plate_moving_markers(torch_cuda, scheme, nsteps, resume):
     assert np.abs(Qo[1:3] - Q0[1:3]).max() > 1e-4   # the plate has stirred the stream
 
 
+def test_hovering_insect_moving_markers(torch_cuda):
+    """The hovering insect: body and two flapping wings (309 markers, the wings' moved every
+    step on both sides) in a quiescent gas, against the oracle with the marker forces."""
+    case = W.insect(n=192, L=3.84, sponge=0.5, nprobe=0, scheme="weno5js")
+    Q0 = W.uniform_state(case)
+    _say("hovering insect x 15")
+    s = _solver(case)
+    o = _oracle(case)
+    Qg = torch_cuda.from_numpy(Q0.copy()).cuda()
+    Qo = Q0.copy()
+    for n in range(15):
+        X, U = W.insect_kinematics(case, n * case.dt)
+        s.set_marker_kinematics(X, U)
+        o.set_marker_kinematics(X, U)
+        if n > 0:
+            s.rk3_steps_resume(Qg, case.dt)
+        else:
+            s.rk3_step(Qg, case.dt)
+        o.rk3_step(Qo, case.dt)
+    s.sync()
+    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
+    np.testing.assert_allclose(s.marker_force(), o.marker_force(), rtol=1e-9, atol=1e-12)
+    assert np.abs(Qo[1:3]).max() > 1e-5     # the wings have set the gas moving
+
+
 def test_flexible_plate_coupled(torch_cuda):
     """The flexible flapping plate: fluid and structure coupled explicitly every step (the
     markers follow the plate; the plate is loaded by the step's marker forces), the library's
