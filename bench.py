@@ -229,15 +229,15 @@ def moving_body_forms(case, kinematics, net, nsteps, every=10, flexible=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(nsamp):
-            for m in range(every):
-                X, U = plate.markers() if flexible else kinematics(c, (k * every + m) * c.dt)
-                s.set_marker_kinematics(X, U)
-                if k == 0 and m == 0:
-                    s.rk3_step(Q, c.dt)
-                else:
-                    s.rk3_steps_resume(Q, c.dt)
-                if flexible:
-                    plate.step(s.marker_force(), c.dt)
+            if flexible:     # the coupling loop inside the library
+                plate.coupled_steps(s, Q, c.dt, every, resume=k > 0)
+            else:
+                for m in range(every):
+                    s.set_marker_kinematics(*kinematics(c, (k * every + m) * c.dt))
+                    if k == 0 and m == 0:
+                        s.rk3_step(Q, c.dt)
+                    else:
+                        s.rk3_steps_resume(Q, c.dt)
             s.probe_dp(Q, out=dps[k])
         torch.cuda.synchronize()
         runs[name] = (time.perf_counter() - t0, dps)

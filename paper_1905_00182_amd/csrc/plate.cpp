@@ -458,6 +458,27 @@ int32_t fsa_plate_set_state(fsa_plate* p, const double* e, const double* v, cons
     return FSA_OK;
 }
 
+int32_t fsa_plate_coupled_steps(fsa_ctx* ctx, fsa_plate* p, double* d_Q, double dt, int32_t nsteps,
+                                int32_t resume)
+{
+    if (!ctx || !p || !d_Q || nsteps < 0) return FSA_EINVAL;
+    try {
+        std::vector<double> X(2 * (size_t)p->nm), U(2 * (size_t)p->nm), F(2 * (size_t)p->nm);
+        for (int n = 0; n < nsteps; ++n) {
+            int rc = fsa_plate_markers(p, X.data(), U.data());
+            if (rc == FSA_OK) rc = fsa_set_marker_kinematics(ctx, X.data(), U.data());
+            if (rc == FSA_OK)
+                rc = (resume || n > 0) ? fsa_rk3_steps_resume(ctx, d_Q, dt, 1) : fsa_rk3_steps(ctx, d_Q, dt, 1);
+            if (rc == FSA_OK) rc = fsa_marker_force(ctx, F.data());
+            if (rc != FSA_OK) return rc;
+            if ((rc = fsa_plate_step(p, F.data(), dt)) != FSA_OK) return rc;
+        }
+    } catch (...) {
+        return FSA_ENOMEM;
+    }
+    return FSA_OK;
+}
+
 const char* fsa_plate_last_error(const fsa_plate* p) { return p ? p->err.c_str() : "null plate"; }
 
 }  // extern "C"

@@ -139,6 +139,7 @@ _SIGS = {
     "fsa_plate_get_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "fsa_plate_set_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
     "fsa_plate_last_error": (C.c_char_p, [C.c_void_p]),
+    "fsa_plate_coupled_steps": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32]),
 }
 
 
@@ -176,6 +177,14 @@ class Plate:
         F = np.ascontiguousarray(F, dtype=np.float64)
         assert F.shape == (2, self.nm)
         self._check(lib().fsa_plate_step(self.h, F.ctypes.data, dt))
+
+    def coupled_steps(self, solver, Q, dt, nsteps, resume=True):
+        """nsteps coupled fluid-plate steps in the library (fsa_plate_coupled_steps)."""
+        rc = lib().fsa_plate_coupled_steps(solver.ctx, self.h, _ptr(solver._state(Q)), dt, nsteps, 1 if resume else 0)
+        if rc != OK:
+            raise FsaError(rc, f"coupled steps: plate: {lib().fsa_plate_last_error(self.h).decode()}; "
+                               f"solver: {lib().fsa_last_error(solver.ctx).decode()}")
+        return Q
 
     def get_state(self):
         e, v, a, t = np.empty(self.ndof), np.empty(self.ndof), np.empty(self.ndof), C.c_double()

@@ -207,6 +207,35 @@ def test_flexible_plate_coupled(torch_cuda):
     assert np.abs(op.e - rigid.e).max() > 1e-7      # the fluid has bent the plate
 
 
+def test_coupled_steps_equal_the_callers_loop(torch_cuda):
+    """fsa_plate_coupled_steps (the coupling loop inside the library) is bit for bit the same
+    calls made one by one from the caller."""
+    from paper_1905_00182_amd import fsa
+
+    case = W.config5_flexible(n=128, L=8.0, nmark=128, scheme="teno5", nel=10)
+    Q0 = torch_cuda.from_numpy(W.uniform_state(case)).cuda()
+    out = []
+    for inside in (False, True):
+        s = _solver(case)
+        pl = fsa.Plate(case)
+        Q = Q0.clone()
+        if inside:
+            pl.coupled_steps(s, Q, case.dt, 4, resume=False)
+            pl.coupled_steps(s, Q, case.dt, 6)
+        else:
+            for n in range(10):
+                s.set_marker_kinematics(*pl.markers())
+                (s.rk3_steps_resume if n else s.rk3_step)(Q, case.dt)
+                pl.step(s.marker_force(), case.dt)
+        s.sync()
+        out.append((Q, pl.get_state()))
+        s.close()
+        pl.close()
+    assert torch_cuda.equal(out[0][0], out[1][0])
+    for x, y in zip(out[0][1], out[1][1]):
+        assert np.array_equal(x, y)
+
+
 def test_free_stream_exactly_zero(torch_cuda):
     case = _c2_small(n=150, nprobe=0).with_(markers=None, inflow_amp=0.0)
     Q0 = W.uniform_state(case)
