@@ -625,6 +625,7 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     }
     S.ghosts = c->ghosts ? c->ghosts + (c->step - c->ghosts_step) * inflow_ghosts2d_elems(c->G) : nullptr;
     if (c->ty == 0) {
+        if (int rf = flush_alpha_final(c)) return rf;   // (the timing launches write the partials)
         int rc = tune_ty(c, S);
         if (rc != FSA_OK) return rc;
     }
@@ -1007,6 +1008,7 @@ int32_t fsa_set_probes(fsa_ctx* c, int32_t n, const double* Xp)
 int32_t fsa_alpha(fsa_ctx* c, const double* d_Q, double* alpha)
 {
     if (!c || !d_Q || !alpha) return FSA_EINVAL;
+    if (int rf = flush_alpha_final(c)) return rf;
     unsigned long long* bits = c->abits + 9;
     int e = launch_alpha(c->G, c->P, d_Q, c->apart, bits, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "alpha launch");
@@ -1058,15 +1060,18 @@ int rk3_run(fsa_ctx* c, double* d_Q, double dt, int32_t nsteps, bool resume)
         c->t += dt;
         c->step += 1;
     }
-    if ((rc = flush_alpha_final(c)) != FSA_OK) return rc;
+    // the last stage's reduction stays pending: the next step call's first IB launch carries
+    // it (as between the steps of one call), and every other reader of the partials or the
+    // slots flushes it first
     c->last_slot = (3 * nsteps) % 3;
     if (c->d.nan_check) {
+        if ((rc = flush_alpha_final(c)) != FSA_OK) return rc;
         HIPCHK(c, hipMemcpyAsync(c->h_abits, c->abits, 9 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                  c->stream));
         HIPCHK(c, hipEventRecord(c->ev_alpha, c->stream));
         c->alpha_pending = true;
     }
-    c->advanced = d_Q;   // (slot 0 holds its wave speeds)
+    c->advanced = d_Q;   // (slot 0 holds, or the pending reduction writes, its wave speeds)
     return FSA_OK;
 }
 
@@ -1209,6 +1214,7 @@ int32_t fsa_harvest(fsa_ctx* c, const double* d_Q, double keep_rate, uint64_t se
             (rc = dalloc(c, c->hv_total, 1)) != FSA_OK)
             return rc;
     }
+    if (int rf = flush_alpha_final(c)) return rf;
     unsigned long long* bits = c->abits + 9;
     int e = launch_alpha(c->G, c->P, d_Q, c->apart, bits, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "alpha launch");
@@ -1239,6 +1245,7 @@ int32_t fsa_face_flags(fsa_ctx* c, const double* d_Q, uint32_t* d_flags_x, uint3
     if (!c || !d_Q || !d_flags_x || !d_flags_y) return FSA_EINVAL;
     if (c->d.dim != 2) return fail(c, FSA_EUNSUPPORTED, "learned flags are built for 2D");
     if (!c->mlp_ready) return fail(c, FSA_ESTATE, "no network set");
+    if (int rf = flush_alpha_final(c)) return rf;
     unsigned long long* bits = c->abits + 9;
     int e = launch_alpha(c->G, c->P, d_Q, c->apart, bits, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "alpha launch");
@@ -1301,6 +1308,7 @@ int32_t fsa_stats_get(fsa_ctx* c, fsa_stats* out)
 {
     if (!c || !out) return FSA_EINVAL;
     unsigned long long hb[3];
+    if (int rf = flush_alpha_final(c)) return rf;
     HIPCHK(c, hipMemcpyAsync(hb, c->abits + 3 * c->last_slot, sizeof hb, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     std::memset(out, 0, sizeof *out);
