@@ -199,6 +199,10 @@ int32_t fsa_probe_dp(fsa_ctx* ctx, const double* d_Q, double* d_dp);
 /* Penalty force on the structure from the most recent right-hand side, host h_F[dim][n]
  * (the force on the fluid is its negative, Sec. 2).  Synchronising. */
 int32_t fsa_marker_force(fsa_ctx* ctx, double* h_F);
+/* The markers' count and motion (FSA_STATIC, FSA_ROTATING, FSA_EXTERNAL), e.g. for a structure
+ * solver to check that its arrays fit before it exchanges X, U and F (host; either output may
+ * be NULL). */
+int32_t fsa_marker_info(const fsa_ctx* ctx, int32_t* n, int32_t* motion);
 /* Checkpoint: penalty integral h_xi[dim][n], time and step.  Synchronising. */
 int32_t fsa_get_state(fsa_ctx* ctx, double* h_xi, double* t, int64_t* step);
 int32_t fsa_set_state(fsa_ctx* ctx, const double* h_xi, double t, int64_t step);

@@ -72,8 +72,9 @@ int32_t fsa_plate_set_state(fsa_plate* plate, const double* e, const double* v, 
  * solver (fsa_set_marker_kinematics), one SSP-RK3 step of d_Q (fsa_rk3_steps_resume when
  * resume is nonzero or after the first step, else fsa_rk3_steps), the step's marker forces
  * (fsa_marker_force, synchronising) and the plate's step under them (fsa_plate_step): what a
- * caller would do per step, without the round trips through the caller.  Returns the first
- * failing call's status (its message in fsa_last_error or fsa_plate_last_error). */
+ * caller would do per step, without the round trips through the caller.  FSA_ESTATE (before
+ * any step) unless the solver's markers are EXTERNAL and as many as the plate's.  Returns the
+ * first failing call's status (its message in fsa_last_error or fsa_plate_last_error). */
 int32_t fsa_plate_coupled_steps(fsa_ctx* ctx, fsa_plate* plate, double* d_Q, double dt,
                                 int32_t nsteps, int32_t resume);
 /* Message of the last failed call on the plate (plate-owned). */

@@ -1107,6 +1107,14 @@ int32_t fsa_probe_dp(fsa_ctx* c, const double* d_Q, double* d_dp)
     return e ? hipcheck(c, (hipError_t)e, "probe launch") : FSA_OK;
 }
 
+int32_t fsa_marker_info(const fsa_ctx* c, int32_t* n, int32_t* motion)
+{
+    if (!c) return FSA_EINVAL;
+    if (n) *n = c->nm;
+    if (motion) *motion = c->motion;
+    return FSA_OK;
+}
+
 int32_t fsa_marker_force(fsa_ctx* c, double* h_F)
 {
     if (!c || !h_F) return FSA_EINVAL;

@@ -462,6 +462,9 @@ int32_t fsa_plate_coupled_steps(fsa_ctx* ctx, fsa_plate* p, double* d_Q, double 
                                 int32_t resume)
 {
     if (!ctx || !p || !d_Q || nsteps < 0) return FSA_EINVAL;
+    int32_t nm = 0, motion = -1;
+    if (fsa_marker_info(ctx, &nm, &motion) != FSA_OK || nm != p->nm || motion != FSA_EXTERNAL)
+        return fail(p, FSA_ESTATE, "the solver's markers are not the plate's (count or EXTERNAL motion)");
     try {
         std::vector<double> X(2 * (size_t)p->nm), U(2 * (size_t)p->nm), F(2 * (size_t)p->nm);
         for (int n = 0; n < nsteps; ++n) {

@@ -132,6 +132,7 @@ _SIGS = {
     "fsa_sync": (C.c_int32, [C.c_void_p]),
     "fsa_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(FsaStats)]),
     # include/fsa_plate.h
+    "fsa_marker_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "fsa_plate_create": (C.c_int32, [C.POINTER(FsaPlateDesc), C.POINTER(C.c_void_p)]),
     "fsa_plate_destroy": (C.c_int32, [C.c_void_p]),
     "fsa_plate_markers": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -112,3 +112,25 @@ def test_harvest_in_3d_unsupported(fsa_mod):
     with pytest.raises(fsa_mod.FsaError) as e:
         s.harvest(Q, 1.0, 1, 16)
     assert e.value.code == fsa_mod.EUNSUPPORTED
+
+
+def test_coupled_steps_need_the_plates_markers(fsa_mod):
+    import torch
+
+    case = W.config5_flexible(n=128, L=8.0, nmark=128, nel=10)
+    plate = fsa_mod.Plate(case)
+    Q = torch.from_numpy(W.uniform_state(case)).cuda()
+    n, motion = fsa_mod.C.c_int32(), fsa_mod.C.c_int32()
+    s = fsa_mod.Solver(case)
+    assert fsa_mod.lib().fsa_marker_info(s.ctx, fsa_mod.C.byref(n), fsa_mod.C.byref(motion)) == fsa_mod.OK
+    assert (n.value, motion.value) == (128, fsa_mod.MOTION["external"])
+    for other in (W.config5_flexible(n=128, L=8.0, nmark=96, nel=10),          # fewer markers
+                  case.with_(markers={**case.markers, "motion": "static"})):  # not EXTERNAL
+        so = fsa_mod.Solver(other)
+        with pytest.raises(fsa_mod.FsaError) as e:
+            plate.coupled_steps(so, Q, case.dt, 1, resume=False)
+        assert e.value.code == fsa_mod.ESTATE
+        so.close()
+    plate.coupled_steps(s, Q, case.dt, 2, resume=False)      # the matching pair still works
+    s.sync()
+    assert torch.isfinite(Q).all()
