@@ -176,7 +176,8 @@ class Plate:
 
     def step(self, F, dt):
         F = np.ascontiguousarray(F, dtype=np.float64)
-        assert F.shape == (2, self.nm)
+        if F.shape != (2, self.nm):
+            raise ValueError(f"F must have shape (2, {self.nm}), not {F.shape}")
         self._check(lib().fsa_plate_step(self.h, F.ctypes.data, dt))
 
     def coupled_steps(self, solver, Q, dt, nsteps, resume=True):
@@ -195,6 +196,9 @@ class Plate:
     def set_state(self, e, v, a, t):
         e, v = np.ascontiguousarray(e, dtype=np.float64), np.ascontiguousarray(v, dtype=np.float64)
         a = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        for x in (e, v) + (() if a is None else (a,)):
+            if x.shape != (self.ndof,):
+                raise ValueError(f"plate state arrays must have {self.ndof} entries, not {x.shape}")
         self._check(lib().fsa_plate_set_state(self.h, e.ctypes.data, v.ctypes.data,
                                               None if a is None else a.ctypes.data, t))
 
@@ -313,23 +317,32 @@ class Solver:
         return Q
 
     # -- set-up
+    def _host_shape(self, A, shape, what):
+        A = _host(A)
+        if tuple(A.shape) != tuple(shape):
+            raise ValueError(f"{what} must have shape {tuple(shape)}, not {tuple(A.shape)}")
+        return A
+
     def set_markers(self, X, dV, U=None, motion="static", omega=0.0):
-        X, dV = _host(X), _host(dV)
-        Ua = _host(U) if U is not None else None
+        dV = _host(dV)
         n = dV.shape[0]
+        X = self._host_shape(X, (self.nq - 2, n), "X")
+        Ua = self._host_shape(U, (self.nq - 2, n), "U") if U is not None else None
         self._check(lib().fsa_set_markers(self.ctx, n, X.ctypes.data, dV.ctypes.data,
                                           Ua.ctypes.data if Ua is not None else None, MOTION[motion], omega))
         self.nm = n
 
     def set_marker_kinematics(self, X, U=None):
-        X = _host(X)
-        Ua = _host(U) if U is not None else None
+        X = self._host_shape(X, (self.nq - 2, self.nm), "X")
+        Ua = self._host_shape(U, (self.nq - 2, self.nm), "U") if U is not None else None
         self._check(lib().fsa_set_marker_kinematics(self.ctx, X.ctypes.data,
                                                     Ua.ctypes.data if Ua is not None else None))
 
     def set_probes(self, Xp):
         Xp = _host(Xp)
         n = Xp.shape[1] if Xp.ndim == 2 else 0
+        if n and Xp.shape[0] != self.nq - 2:
+            raise ValueError(f"probe points must have shape ({self.nq - 2}, n), not {tuple(Xp.shape)}")
         self._check(lib().fsa_set_probes(self.ctx, n, Xp.ctypes.data))
         self.np = n
 
@@ -388,7 +401,7 @@ class Solver:
         return xi[:, : self.nm], t.value, step.value
 
     def set_state(self, xi, t, step):
-        xa = _host(xi) if xi is not None else None
+        xa = self._host_shape(xi, (self.nq - 2, self.nm), "xi") if xi is not None else None
         self._check(lib().fsa_set_state(self.ctx, xa.ctypes.data if xa is not None else None, t, step))
 
     def diagnostics(self, Q, dilatation=True):

@@ -134,3 +134,18 @@ def test_coupled_steps_need_the_plates_markers(fsa_mod):
     plate.coupled_steps(s, Q, case.dt, 2, resume=False)      # the matching pair still works
     s.sync()
     assert torch.isfinite(Q).all()
+
+
+def test_binding_rejects_wrong_shapes(fsa_mod):
+    case = W.config5(n=128, L=8.0, nmark=64)
+    s = fsa_mod.Solver(case)
+    X, U = W.plate_kinematics(case, 0.0)
+    for bad in (X[:, :-1], X.T, X[:1]):
+        with pytest.raises(ValueError):
+            s.set_marker_kinematics(bad, U)
+    with pytest.raises(ValueError):
+        s.set_probes(np.zeros((3, 4)))
+    with pytest.raises(ValueError):
+        s.set_state(np.zeros((2, 63)), 0.0, 0)
+    s.set_marker_kinematics(X, U)    # the right shapes still work
+    s.sync()

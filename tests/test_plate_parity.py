@@ -96,3 +96,15 @@ def test_rejections(case):
     bad = case.with_(extra={**case.extra, "flex": {**case.extra["flex"], "rho_s": 0.0}})
     with pytest.raises(fsa.FsaError):
         fsa.Plate(bad)
+
+
+def test_binding_rejects_wrong_shapes(case):
+    from paper_1905_00182_amd import fsa
+
+    p = fsa.Plate(case)
+    with pytest.raises(ValueError):
+        p.step(np.zeros((2, p.nm - 1)), 1e-3)
+    e, v, a, t = p.get_state()
+    with pytest.raises(ValueError):
+        p.set_state(e[:-4], v, a, t)
+    p.set_state(e, v, None, t)       # accelerations from the unloaded equation
