@@ -24,8 +24,15 @@
  *     returns without waiting; the buffers must stay alive until the stream has passed the
  *     call.  Calls documented as synchronising wait for the stream.
  *   - A context belongs to one host thread at a time.
- *   - Ownership: the library allocates and frees its own internal device memory (stage
- *     buffers, marker and window arrays); it never frees a caller's buffer.
+ *   - Ownership: the caller owns all device memory.  fsa_workspace_bytes states how much one
+ *     context needs for its descriptor (RK stage buffers, reduction partials, marker, window
+ *     and probe arrays up to the descriptor's capacities, 3D stress and face buffers, the
+ *     selector network); the caller allocates it (e.g. a torch tensor) and hands it to
+ *     fsa_init, and keeps it alive, unused by anything else, until fsa_destroy returns.  The
+ *     library never allocates, frees or resizes device memory.  It allocates only small pinned
+ *     host buffers (the wave-speed read-back and the double-buffered marker placement
+ *     staging, 2 x the placement size at the marker capacity) and HIP events, all freed by
+ *     fsa_destroy.
  *
  * Errors: every function returns FSA_OK (0) or a negative status.  Argument and shape errors
  * are reported synchronously as FSA_EINVAL with a message from fsa_last_error.  Device
@@ -43,7 +50,7 @@
 extern "C" {
 #endif
 
-#define FSA_ABI_VERSION 2
+#define FSA_ABI_VERSION 3
 
 enum {
     FSA_OK = 0,
@@ -116,6 +123,13 @@ typedef struct fsa_desc {
     double   src_b;
     double   src_omega;
     double   src_x[3];
+    /* Capacities of the workspace (fsa_workspace_bytes): markers and probes the context can
+     * hold (fsa_set_markers / fsa_set_probes with more: FSA_EINVAL), and cells of the box that
+     * holds every marker's four-point support (0: the whole grid, always enough; a placement
+     * whose box is larger: FSA_EINVAL). */
+    int32_t  max_markers;
+    int32_t  max_probes;
+    int64_t  max_window_cells;
 } fsa_desc;
 
 typedef struct fsa_ctx fsa_ctx;
@@ -140,10 +154,16 @@ const char* fsa_status_str(int32_t status);
 /* Message of the last error on ctx (owned by ctx, valid until the next call on ctx). */
 const char* fsa_last_error(const fsa_ctx* ctx);
 
+/* Device bytes a context for desc needs (*bytes; 0 on error).  Validates desc (FSA_EINVAL).
+ * Depends on the descriptor only: the grid, dimension, precision, boundary kinds and the
+ * three capacities. */
+int32_t fsa_workspace_bytes(const fsa_desc* desc, size_t* bytes);
 /* Create a context on the current HIP device, enqueuing on hip_stream (a hipStream_t; NULL
- * is the null stream).  Validates desc (FSA_EINVAL) and allocates the two RK stage buffers
- * and the reduction slots (FSA_ENOMEM). */
-int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out);
+ * is the null stream), its device buffers carved from the caller's d_workspace (a device
+ * pointer to at least fsa_workspace_bytes(desc) bytes, any alignment; its contents need not
+ * be initialised).  FSA_EINVAL: invalid desc, NULL or too small a workspace.  Synchronising
+ * (the constants are copied in). */
+int32_t fsa_init(const fsa_desc* desc, void* d_workspace, size_t ws_bytes, void* hip_stream, fsa_ctx** out);
 /* Free everything the context owns.  Synchronising.  NULL is accepted. */
 int32_t fsa_destroy(fsa_ctx* ctx);
 
@@ -199,10 +219,10 @@ int32_t fsa_probe_dp(fsa_ctx* ctx, const double* d_Q, double* d_dp);
 /* Penalty force on the structure from the most recent right-hand side, host h_F[dim][n]
  * (the force on the fluid is its negative, Sec. 2).  Synchronising. */
 int32_t fsa_marker_force(fsa_ctx* ctx, double* h_F);
-/* The markers' count and motion (FSA_STATIC, FSA_ROTATING, FSA_EXTERNAL), e.g. for a structure
- * solver to check that its arrays fit before it exchanges X, U and F (host; either output may
- * be NULL). */
-int32_t fsa_marker_info(const fsa_ctx* ctx, int32_t* n, int32_t* motion);
+/* The markers' count, motion (FSA_STATIC, FSA_ROTATING, FSA_EXTERNAL) and the solver's
+ * dimension, e.g. for a structure solver to check that its arrays fit before it exchanges X,
+ * U and F ([dim][n] each; host; any output may be NULL). */
+int32_t fsa_marker_info(const fsa_ctx* ctx, int32_t* n, int32_t* motion, int32_t* dim);
 /* Checkpoint: penalty integral h_xi[dim][n], time and step.  Synchronising. */
 int32_t fsa_get_state(fsa_ctx* ctx, double* h_xi, double* t, int64_t* step);
 int32_t fsa_set_state(fsa_ctx* ctx, const double* h_xi, double t, int64_t step);

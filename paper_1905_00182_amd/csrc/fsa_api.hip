@@ -65,12 +65,14 @@ struct fsa_ctx {
     double* cell_w = nullptr;            // per CSR entry spreading weight
     int* mj0 = nullptr;                  // per marker support origin
     double* mw = nullptr;                // per marker one-dimensional weights
-    long long cap_wcells = 0;            // window buffer capacities (kinematics updates only grow them)
-    long long cap_entries = 0;
+    long long cap_wcells = 0;            // window capacities in the workspace (desc.max_window_cells,
+    long long cap_entries = 0;           // 4^dim entries per marker)
+    int cap_markers = 0;                 // desc.max_markers, desc.max_probes
+    int cap_probes = 0;
     char* h_stage = nullptr;             // coherent pinned staging of marker placements, two
     const char* h_stage_dev = nullptr;   // halves used in turn (and its device-side address)
     char* d_stage = nullptr;             // its device twin (same size and layout)
-    size_t stage_bytes = 0;              // bytes per half
+    size_t stage_bytes = 0;              // bytes per half (the device twin holds one)
     int stage_idx = 0;                   // the half the next placement fills
     hipEvent_t ev_stage[2] = {nullptr, nullptr};  // recorded after the launch that read a half
     bool stage_pending[2] = {false, false};
@@ -132,24 +134,92 @@ int hipcheck(fsa_ctx* c, hipError_t e, const char* what)
         if (rc_ != FSA_OK) return rc_;                             \
     } while (0)
 
-template <class T>
-void dfree(T*& p)
+// Bump allocation of the context's device buffers from the caller's workspace, 256-byte
+// aligned (base null: only the byte count).
+struct Carve {
+    char* base;
+    size_t off;
+    template <class T>
+    T* take(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return p;
+    }
+};
+
+// Bytes of one marker placement staged for the device: X and U, the CSR starts and, per
+// entry, its marker and window cell.
+size_t stage_need(int dim, long long nm, long long wcells, long long nent)
 {
-    if (p) (void)hipFree(p);
-    p = nullptr;
+    const size_t bx = sizeof(double) * (size_t)dim * (size_t)nm, bs = sizeof(int) * (size_t)(wcells + 1),
+                 bm = sizeof(int) * (size_t)nent;
+    return (2 * bx + bs + 2 * bm + 15) / 16 * 16;
 }
 
-template <class T>
-int dalloc(fsa_ctx* c, T*& p, size_t count)
+// Every device buffer of context c (its desc, grid and capacities set) in the workspace at
+// base; returns the bytes used.  The layout depends on the descriptor only.
+size_t carve(fsa_ctx* c, char* base)
 {
-    dfree(p);
-    if (count == 0) count = 1;
-    if (hipMalloc((void**)&p, count * sizeof(T)) != hipSuccess) {
-        p = nullptr;
-        (void)hipGetLastError();
-        return fail(c, FSA_ENOMEM, "device allocation failed");
+    Carve W{base, 0};
+    const fsa_desc& d = c->d;
+    const int dim = d.dim;
+    const Grid& G = c->G;
+    const size_t nq = (size_t)(dim + 2), nc = (size_t)G.ncell;
+    c->dK = W.take<KConst>(1);
+    c->Qa = W.take<double>(nq * nc);
+    c->Qb = W.take<double>(nq * nc);
+    c->abits = W.take<unsigned long long>(12);
+    c->apart_n = std::max<long long>(ALPHA_MAX_BLOCKS, dim == 3 ? stage3d_blocks(G) : stage2d_waves(G, 4));
+    c->apart = W.take<unsigned long long>(3 * (size_t)c->apart_n);
+    c->ghosts = (dim == 2 && has_inflow(G)) ? W.take<double>((size_t)GHOST_STEPS * inflow_ghosts2d_elems(G)) : nullptr;
+    if (dim == 3) {
+        const size_t tsize = d.precision == FSA_MIXED32 ? sizeof(float) : sizeof(double);
+        c->stress3d = W.take<unsigned char>((size_t)stress3d_elems(G) * tsize);
+        c->faces3d = W.take<unsigned char>((size_t)faces3d_elems(G) * tsize);
     }
-    return FSA_OK;
+    c->tot_part = W.take<double>((size_t)totals_part_size((int)nq));
+    c->tot_out = W.take<double>(5);
+    // the selector network (any context may run or train it)
+    c->mlp_master = W.take<float>(MLP_NPARAM);
+    c->mlp_wbf = W.take<unsigned short>(MLP_NPARAM);
+    c->mlp_m = W.take<float>(MLP_NPARAM);
+    c->mlp_v = W.take<float>(MLP_NPARAM);
+    c->mlp_grad = W.take<float>(MLP_NPARAM);
+    c->mlp_partial = W.take<float>((size_t)512 * MLP_NPARAM);
+    c->mlp_loss_part = W.take<float>(512);
+    if (dim == 2) {
+        c->counters = W.take<unsigned long long>(3 * (size_t)flags2d_blocks(G));
+        c->qrange = W.take<float>(8 * (size_t)stage2d_waves(G, 4));
+        const size_t nb = (size_t)harvest2d_blocks(G);
+        c->hv_count = W.take<int>(nb);
+        c->hv_offset = W.take<long long>(nb);
+        c->hv_total = W.take<long long>(1);
+    }
+    if (d.precision == FSA_LEARNED32) {
+        c->flags_x = W.take<unsigned>((size_t)(G.n[0] + 1) * G.n[1]);
+        c->flags_y = W.take<unsigned>((size_t)G.n[0] * (G.n[1] + 1));
+    }
+    // markers, their window and the device twin of the placement staging
+    const size_t cm = (size_t)c->cap_markers, ln = (size_t)dim * cm;
+    c->X = W.take<double>(ln);
+    c->U = W.take<double>(ln);
+    c->xi = W.take<double>(ln);
+    c->xi2 = W.take<double>(ln);
+    c->xi_n = W.take<double>(ln);
+    c->F = W.take<double>(ln);
+    c->dV = W.take<double>(cm);
+    c->mj0 = W.take<int>(3 * cm);
+    c->mw = W.take<double>(ln * 4);
+    c->fwin = W.take<double>((size_t)dim * (size_t)c->cap_wcells);
+    c->cell_start = W.take<int>((size_t)c->cap_wcells + 1);
+    c->cell_marker = W.take<int>((size_t)c->cap_entries);
+    c->cell_w = W.take<double>((size_t)c->cap_entries);
+    c->stage_bytes = cm ? stage_need(dim, (long long)cm, c->cap_wcells, c->cap_entries) : 0;
+    c->d_stage = W.take<char>(c->stage_bytes);
+    c->Xp = W.take<double>((size_t)dim * (size_t)c->cap_probes);
+    return W.off + 256;   // (room to align the base up)
 }
 
 int validate(const fsa_desc* d, std::string& why)
@@ -357,8 +427,7 @@ int window_lists(fsa_ctx* c, int* wlo, int* wn, std::vector<int>& count, std::ve
 // into its device twin and one launch that puts them in place and computes the weights, both
 // on the library's stream after the work already enqueued there.  The staging block has two
 // halves used in turn; the host waits only for the copy that read the half it is about to
-// fill (two placements back) and, when the window outgrows its buffers, for the stream
-// (before they are replaced).
+// fill (two placements back).  The window must fit the workspace's capacities.
 int update_window_async(fsa_ctx* c, const double* X, const double* U)
 {
     const int dim = c->d.dim, n = c->nm;
@@ -367,37 +436,13 @@ int update_window_async(fsa_ctx* c, const double* X, const double* U)
     int rc = window_lists(c, wlo, wn, count, marker, ecell);
     if (rc != FSA_OK) return rc;
     const long long wcells = (long long)wn[0] * wn[1] * wn[2], nent = (long long)marker.size();
+    if (wcells > c->cap_wcells)
+        return fail(c, FSA_EINVAL, "the markers' supports span " + std::to_string(wcells) +
+                                       " cells, more than desc.max_window_cells (" + std::to_string(c->cap_wcells) + ")");
+    if (nent > c->cap_entries) return fail(c, FSA_EINVAL, "more support entries than the workspace holds");
     const size_t bx = sizeof(double) * (size_t)dim * n, bs = sizeof(int) * count.size(),
-                 bm = sizeof(int) * marker.size(), need = (2 * bx + bs + 2 * bm + 15) / 16 * 16;
-    const bool grow = wcells > c->cap_wcells || nent > c->cap_entries || need > c->stage_bytes;
-    if (grow) HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
-    if (wcells > c->cap_wcells || nent > c->cap_entries) {
-        const long long cw = std::max(wcells, c->cap_wcells) * 3 / 2 + 1, ce = std::max(nent, c->cap_entries) * 3 / 2 + 1;
-        if ((rc = dalloc(c, c->fwin, (size_t)dim * cw)) != FSA_OK) return rc;
-        if ((rc = dalloc(c, c->cell_start, (size_t)cw + 1)) != FSA_OK) return rc;
-        if ((rc = dalloc(c, c->cell_marker, (size_t)ce)) != FSA_OK) return rc;
-        if ((rc = dalloc(c, c->cell_w, (size_t)ce)) != FSA_OK) return rc;
-        c->cap_wcells = cw;
-        c->cap_entries = ce;
-    }
-    if (need > c->stage_bytes) {   // (the stream is idle: see grow)
-        if (c->h_stage) (void)hipHostFree(c->h_stage);
-        c->h_stage = nullptr;
-        c->h_stage_dev = nullptr;
-        c->stage_bytes = 0;
-        c->stage_pending[0] = c->stage_pending[1] = false;
-        void* hd = nullptr;
-        if (hipHostMalloc((void**)&c->h_stage, need * 4, hipHostMallocCoherent) != hipSuccess ||
-            hipHostGetDevicePointer(&hd, c->h_stage, 0) != hipSuccess) {
-            (void)hipGetLastError();
-            if (c->h_stage) (void)hipHostFree(c->h_stage);
-            c->h_stage = nullptr;
-            return fail(c, FSA_ENOMEM, "pinned staging allocation failed");
-        }
-        c->h_stage_dev = (const char*)hd;
-        if ((rc = dalloc(c, c->d_stage, need * 2)) != FSA_OK) return rc;
-        c->stage_bytes = need * 2;
-    }
+                 bm = sizeof(int) * marker.size(), need = stage_need(dim, n, wcells, nent);
+    if (need > c->stage_bytes || !c->h_stage) return fail(c, FSA_EINVAL, "marker staging exceeds its capacity");
     // the half this placement fills: the launch that read it last time must have ended
     const int half = c->stage_idx;
     c->stage_idx ^= 1;
@@ -449,26 +494,18 @@ int update_window_async(fsa_ctx* c, const double* X, const double* U)
     return e ? hipcheck(c, (hipError_t)e, "IB placement launch") : FSA_OK;
 }
 
-// First placement of the markers (c->hX, U; null U: zero), synchronously: the window buffers
-// are sized afresh.
+// First placement of the markers (c->hX, U; null U: zero), synchronously, with the window's
+// force buffer cleared.
 int build_window(fsa_ctx* c, const double* U)
 {
     const int dim = c->d.dim, n = c->nm;
-    dfree(c->fwin);
-    dfree(c->cell_start);
-    dfree(c->cell_marker);
-    dfree(c->cell_w);
     c->wcells = 0;
-    c->cap_wcells = c->cap_entries = 0;
     for (int k = 0; k < 3; ++k) { c->wlo[k] = 0; c->wn[k] = 1; }
     if (n == 0) { c->wn[0] = c->wn[1] = c->wn[2] = 0; return FSA_OK; }
     int rc;
-    if ((rc = dalloc(c, c->mj0, (size_t)n * 3)) != FSA_OK) return rc;
-    if ((rc = dalloc(c, c->mw, (size_t)n * dim * 4)) != FSA_OK) return rc;
     if ((rc = update_window_async(c, c->hX.data(), U)) != FSA_OK) return rc;
-    HIPCHK(c, hipDeviceSynchronize());
-    HIPCHK(c, hipMemset(c->fwin, 0, sizeof(double) * (size_t)dim * c->cap_wcells));
-    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemsetAsync(c->fwin, 0, sizeof(double) * (size_t)dim * c->cap_wcells, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     c->stage_pending[0] = c->stage_pending[1] = false;
     return FSA_OK;
 }
@@ -732,21 +769,6 @@ MLPArgs mlp_args(const fsa_ctx* c)
     return M;
 }
 
-int mlp_alloc(fsa_ctx* c)
-{
-    if (c->mlp_master) return FSA_OK;
-    int rc;
-    if ((rc = dalloc(c, c->mlp_master, MLP_NPARAM)) != FSA_OK || (rc = dalloc(c, c->mlp_wbf, MLP_NPARAM)) != FSA_OK ||
-        (rc = dalloc(c, c->mlp_m, MLP_NPARAM)) != FSA_OK || (rc = dalloc(c, c->mlp_v, MLP_NPARAM)) != FSA_OK ||
-        (rc = dalloc(c, c->mlp_grad, MLP_NPARAM)) != FSA_OK ||
-        (rc = dalloc(c, c->mlp_partial, (size_t)512 * MLP_NPARAM)) != FSA_OK ||
-        (rc = dalloc(c, c->mlp_loss_part, 512)) != FSA_OK || (rc = dalloc(c, c->counters, 3 * (size_t)flags2d_blocks(c->G))) != FSA_OK ||
-        (rc = dalloc(c, c->qrange, 8 * (size_t)stage2d_waves(c->G, 4))) != FSA_OK)
-        return rc;
-    HIPCHK(c, hipMemset(c->counters, 0, 3 * (size_t)flags2d_blocks(c->G) * sizeof(unsigned long long)));
-    return FSA_OK;
-}
-
 // Learned keep patterns of the faces of Qs (the learned form's per-stage pass).
 int enqueue_flags(fsa_ctx* c, const double* Qs, const unsigned long long* bits, unsigned* fx, unsigned* fy)
 {
@@ -815,49 +837,84 @@ const char* fsa_status_str(int32_t s)
 
 const char* fsa_last_error(const fsa_ctx* c) { return c ? c->err.c_str() : "no context"; }
 
-int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
+}  // extern "C"
+
+namespace {
+
+// Context fields that follow from the descriptor alone (grid, constants, capacities).
+void plan(fsa_ctx* c, const fsa_desc* desc)
+{
+    c->d = *desc;
+    c->nq = desc->dim + 2;
+    build_consts(c);
+    c->ncell = c->G.ncell;
+    const int dim = desc->dim;
+    c->cap_markers = desc->max_markers;
+    c->cap_probes = desc->max_probes;
+    c->cap_entries = (long long)desc->max_markers * (dim == 3 ? 64 : 16);
+    c->cap_wcells = desc->max_markers == 0 ? 0
+                    : (desc->max_window_cells > 0 ? std::min<long long>(desc->max_window_cells, c->ncell) : c->ncell);
+}
+
+int validate_caps(const fsa_desc* d, std::string& why)
+{
+    if (d->max_markers < 0 || d->max_probes < 0 || d->max_window_cells < 0) {
+        why = "negative capacity";
+        return FSA_EINVAL;
+    }
+    return FSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fsa_workspace_bytes(const fsa_desc* desc, size_t* bytes)
+{
+    if (!bytes) return FSA_EINVAL;
+    *bytes = 0;
+    std::string why;
+    int rc = validate(desc, why);
+    if (rc == FSA_OK) rc = validate_caps(desc, why);
+    if (rc != FSA_OK) {
+        std::fprintf(stderr, "fsa_workspace_bytes: %s\n", why.c_str());
+        return rc;
+    }
+    fsa_ctx* c = new (std::nothrow) fsa_ctx();
+    if (!c) return FSA_ENOMEM;
+    plan(c, desc);
+    *bytes = carve(c, nullptr);
+    delete c;
+    return FSA_OK;
+}
+
+int32_t fsa_init(const fsa_desc* desc, void* d_workspace, size_t ws_bytes, void* hip_stream, fsa_ctx** out)
 {
     if (!out) return FSA_EINVAL;
     *out = nullptr;
     std::string why;
     int rc = validate(desc, why);
+    if (rc == FSA_OK) rc = validate_caps(desc, why);
     if (rc != FSA_OK) {
         std::fprintf(stderr, "fsa_init: %s\n", why.c_str());
         return rc;
     }
     fsa_ctx* c = new (std::nothrow) fsa_ctx();
     if (!c) return FSA_ENOMEM;
-    c->d = *desc;
+    plan(c, desc);
+    const size_t need = carve(c, nullptr);
+    if (!d_workspace || ws_bytes < need) {
+        std::fprintf(stderr, "fsa_init: the workspace needs %zu bytes (fsa_workspace_bytes), got %zu\n", need,
+                     d_workspace ? ws_bytes : (size_t)0);
+        delete c;
+        return FSA_EINVAL;
+    }
     c->stream = (hipStream_t)hip_stream;
     (void)hipGetDevice(&c->device);
-    c->nq = desc->dim + 2;
-    build_consts(c);
-    c->ncell = c->G.ncell;
     c->ty = env_ty();
     if (const char* e = std::getenv("FSA_NO_QUIET_TILES")) c->quiet_tiles = std::atoi(e) == 0;
-    if ((rc = dalloc(c, c->Qa, (size_t)c->nq * c->ncell)) != FSA_OK ||
-        (rc = dalloc(c, c->Qb, (size_t)c->nq * c->ncell)) != FSA_OK ||
-        (rc = dalloc(c, c->abits, 12)) != FSA_OK || (rc = dalloc(c, c->dK, 1)) != FSA_OK ||
-        (rc = dalloc(c, c->apart,
-                     3 * (size_t)(c->apart_n = std::max<long long>(
-                                      ALPHA_MAX_BLOCKS, c->G.dim == 3 ? stage3d_blocks(c->G) : stage2d_waves(c->G, 4))))) !=
-            FSA_OK) {
-        fsa_destroy(c);
-        return rc;
-    }
-    if (c->G.dim == 2 && has_inflow(c->G) &&
-        (rc = dalloc(c, c->ghosts, (size_t)GHOST_STEPS * inflow_ghosts2d_elems(c->G))) != FSA_OK) {
-        fsa_destroy(c);
-        return rc;
-    }
-    if (c->G.dim == 3) {
-        const size_t tsize = desc->precision == FSA_MIXED32 ? sizeof(float) : sizeof(double);
-        if ((rc = dalloc(c, c->stress3d, (size_t)stress3d_elems(c->G) * tsize)) != FSA_OK ||
-            (rc = dalloc(c, c->faces3d, (size_t)faces3d_elems(c->G) * tsize)) != FSA_OK) {
-            fsa_destroy(c);
-            return rc;
-        }
-    }
+    char* base = (char*)(((uintptr_t)d_workspace + 255) & ~(uintptr_t)255);
+    carve(c, base);
     {
         KConst hk;
         std::memset(&hk, 0, sizeof hk);
@@ -865,33 +922,34 @@ int32_t fsa_init(const fsa_desc* desc, void* hip_stream, fsa_ctx** out)
         hk.P = c->P;
         hk.inv12h = 1.0 / (12.0 * c->G.h);
         far_field_fluxes(c, hk);
-        if (hipMemcpy(c->dK, &hk, sizeof hk, hipMemcpyHostToDevice) != hipSuccess) {
+        if (hipMemcpyAsync(c->dK, &hk, sizeof hk, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemsetAsync(c->abits, 0, 12 * sizeof(unsigned long long), c->stream) != hipSuccess ||
+            (c->counters && hipMemsetAsync(c->counters, 0, 3 * (size_t)flags2d_blocks(c->G) * sizeof(unsigned long long),
+                                           c->stream) != hipSuccess) ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            (void)hipGetLastError();
             fsa_destroy(c);
             return FSA_EDEVICE;
         }
     }
-    if (desc->precision == FSA_LEARNED32) {
-        if (desc->dim != 2) {
-            fsa_destroy(c);
-            return FSA_EUNSUPPORTED;
-        }
-        const size_t nfx = (size_t)(c->G.n[0] + 1) * c->G.n[1], nfy = (size_t)c->G.n[0] * (c->G.n[1] + 1);
-        if ((rc = dalloc(c, c->flags_x, nfx)) != FSA_OK || (rc = dalloc(c, c->flags_y, nfy)) != FSA_OK ||
-            (rc = mlp_alloc(c)) != FSA_OK) {
-            fsa_destroy(c);
-            return rc;
-        }
-    }
+    // pinned host memory: wave-speed read-back and the two halves of the marker staging
     if (hipHostMalloc((void**)&c->h_abits, 12 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_alpha, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_stage[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_stage[1], hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
         fsa_destroy(c);
         return FSA_ENOMEM;
     }
-    if (hipMemset(c->abits, 0, 12 * sizeof(unsigned long long)) != hipSuccess) {
-        fsa_destroy(c);
-        return FSA_EDEVICE;
+    if (c->stage_bytes) {
+        void* hd = nullptr;
+        if (hipHostMalloc((void**)&c->h_stage, 2 * c->stage_bytes, hipHostMallocCoherent) != hipSuccess ||
+            hipHostGetDevicePointer(&hd, c->h_stage, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            fsa_destroy(c);
+            return FSA_ENOMEM;
+        }
+        c->h_stage_dev = (const char*)hd;
     }
     *out = c;
     return FSA_OK;
@@ -902,45 +960,6 @@ int32_t fsa_destroy(fsa_ctx* c)
     if (!c) return FSA_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    dfree(c->Qa);
-    dfree(c->Qb);
-    dfree(c->dK);
-    dfree(c->abits);
-    dfree(c->apart);
-    dfree(c->stress3d);
-    dfree(c->faces3d);
-    dfree(c->tot_part);
-    dfree(c->tot_out);
-    dfree(c->X);
-    dfree(c->dV);
-    dfree(c->U);
-    dfree(c->xi);
-    dfree(c->xi2);
-    dfree(c->xi_n);
-    dfree(c->F);
-    dfree(c->fwin);
-    dfree(c->cell_start);
-    dfree(c->cell_marker);
-    dfree(c->cell_w);
-    dfree(c->mj0);
-    dfree(c->mw);
-    dfree(c->d_stage);
-    dfree(c->Xp);
-    dfree(c->mlp_master);
-    dfree(c->mlp_wbf);
-    dfree(c->mlp_m);
-    dfree(c->mlp_v);
-    dfree(c->mlp_grad);
-    dfree(c->mlp_partial);
-    dfree(c->mlp_loss_part);
-    dfree(c->flags_x);
-    dfree(c->flags_y);
-    dfree(c->counters);
-    dfree(c->qrange);
-    dfree(c->ghosts);
-    dfree(c->hv_count);
-    dfree(c->hv_offset);
-    dfree(c->hv_total);
     if (c->h_abits) (void)hipHostFree(c->h_abits);
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     for (hipEvent_t ev : c->ev_stage)
@@ -957,6 +976,9 @@ int32_t fsa_set_markers(fsa_ctx* c, int32_t n, const double* X, const double* dV
     if (!c) return FSA_EINVAL;
     if (n < 0 || (n > 0 && (!X || !dV))) return fail(c, FSA_EINVAL, "bad marker arrays");
     if (motion < FSA_STATIC || motion > FSA_EXTERNAL) return fail(c, FSA_EINVAL, "bad motion");
+    if (n > c->cap_markers)
+        return fail(c, FSA_EINVAL, "more markers (" + std::to_string(n) + ") than desc.max_markers (" +
+                                       std::to_string(c->cap_markers) + ")");
     if (n > 0 && !support_inside(c, n, X)) return fail(c, FSA_EINVAL, "a marker support leaves the grid");
     HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
     c->stage_pending[0] = c->stage_pending[1] = false;   // (the stream is idle: earlier staging copies are done)
@@ -965,19 +987,16 @@ int32_t fsa_set_markers(fsa_ctx* c, int32_t n, const double* X, const double* dV
     c->motion = motion;
     c->omega = omega;
     c->hX.assign(X ? X : nullptr, X ? X + (size_t)dim * n : nullptr);
-    const size_t ln = (size_t)dim * (n > 0 ? n : 1);
-    int rc;
-    if ((rc = dalloc(c, c->X, ln)) != FSA_OK || (rc = dalloc(c, c->dV, (size_t)(n > 0 ? n : 1))) != FSA_OK ||
-        (rc = dalloc(c, c->U, ln)) != FSA_OK || (rc = dalloc(c, c->xi, ln)) != FSA_OK ||
-        (rc = dalloc(c, c->xi2, ln)) != FSA_OK || (rc = dalloc(c, c->xi_n, ln)) != FSA_OK ||
-        (rc = dalloc(c, c->F, ln)) != FSA_OK)
-        return rc;
-    HIPCHK(c, hipMemset(c->U, 0, sizeof(double) * ln));
-    HIPCHK(c, hipMemset(c->xi, 0, sizeof(double) * ln));
-    HIPCHK(c, hipMemset(c->xi2, 0, sizeof(double) * ln));
-    HIPCHK(c, hipMemset(c->xi_n, 0, sizeof(double) * ln));
-    HIPCHK(c, hipMemset(c->F, 0, sizeof(double) * ln));
-    if (n > 0) HIPCHK(c, hipMemcpy(c->dV, dV, sizeof(double) * n, hipMemcpyHostToDevice));
+    const size_t ln = (size_t)dim * n;
+    if (ln) {
+        HIPCHK(c, hipMemsetAsync(c->U, 0, sizeof(double) * ln, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->xi, 0, sizeof(double) * ln, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->xi2, 0, sizeof(double) * ln, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->xi_n, 0, sizeof(double) * ln, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->F, 0, sizeof(double) * ln, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->dV, dV, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     return build_window(c, U);   // (X and U go to the device with the window lists)
 }
 
@@ -997,11 +1016,15 @@ int32_t fsa_set_probes(fsa_ctx* c, int32_t n, const double* Xp)
     if (!c) return FSA_EINVAL;
     if (n < 0 || (n > 0 && !Xp)) return fail(c, FSA_EINVAL, "bad probe array");
     if (n > 0 && !support_inside(c, n, Xp)) return fail(c, FSA_EINVAL, "a probe support leaves the grid");
+    if (n > c->cap_probes)
+        return fail(c, FSA_EINVAL, "more probes (" + std::to_string(n) + ") than desc.max_probes (" +
+                                       std::to_string(c->cap_probes) + ")");
     HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
     c->np = n;
-    int rc = dalloc(c, c->Xp, (size_t)c->d.dim * (n > 0 ? n : 1));
-    if (rc != FSA_OK) return rc;
-    if (n > 0) HIPCHK(c, hipMemcpy(c->Xp, Xp, sizeof(double) * c->d.dim * n, hipMemcpyHostToDevice));
+    if (n > 0) {
+        HIPCHK(c, hipMemcpyAsync(c->Xp, Xp, sizeof(double) * c->d.dim * n, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     return FSA_OK;
 }
 
@@ -1107,11 +1130,12 @@ int32_t fsa_probe_dp(fsa_ctx* c, const double* d_Q, double* d_dp)
     return e ? hipcheck(c, (hipError_t)e, "probe launch") : FSA_OK;
 }
 
-int32_t fsa_marker_info(const fsa_ctx* c, int32_t* n, int32_t* motion)
+int32_t fsa_marker_info(const fsa_ctx* c, int32_t* n, int32_t* motion, int32_t* dim)
 {
     if (!c) return FSA_EINVAL;
     if (n) *n = c->nm;
     if (motion) *motion = c->motion;
+    if (dim) *dim = c->d.dim;
     return FSA_OK;
 }
 
@@ -1154,12 +1178,9 @@ int32_t fsa_mlp_set(fsa_ctx* c, const float* h_params, int32_t nparams, double c
     if (!c || !h_params) return FSA_EINVAL;
     if (nparams != MLP_NPARAM) return fail(c, FSA_EINVAL, "the network has 1667 parameters");
     if (!(conf_threshold >= 0.0 && conf_threshold <= 1.0)) return fail(c, FSA_EINVAL, "threshold outside [0, 1]");
-    int rc = mlp_alloc(c);
-    if (rc != FSA_OK) return rc;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(c->mlp_master, h_params, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemset(c->mlp_m, 0, sizeof(float) * MLP_NPARAM));
-    HIPCHK(c, hipMemset(c->mlp_v, 0, sizeof(float) * MLP_NPARAM));
+    HIPCHK(c, hipMemcpyAsync(c->mlp_master, h_params, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->mlp_m, 0, sizeof(float) * MLP_NPARAM, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->mlp_v, 0, sizeof(float) * MLP_NPARAM, c->stream));
     int e = launch_mlp_round(mlp_args(c), c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "mlp round launch");
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1216,12 +1237,7 @@ int32_t fsa_harvest(fsa_ctx* c, const double* d_Q, double keep_rate, uint64_t se
     if (c->d.dim != 2) return fail(c, FSA_EUNSUPPORTED, "harvest is built for 2D");
     if (!(keep_rate >= 0.0 && keep_rate <= 1.0)) return fail(c, FSA_EINVAL, "keep_rate outside [0, 1]");
     const long long nb = harvest2d_blocks(c->G);
-    int rc;
-    if (!c->hv_count) {
-        if ((rc = dalloc(c, c->hv_count, (size_t)nb)) != FSA_OK || (rc = dalloc(c, c->hv_offset, (size_t)nb)) != FSA_OK ||
-            (rc = dalloc(c, c->hv_total, 1)) != FSA_OK)
-            return rc;
-    }
+    (void)nb;
     if (int rf = flush_alpha_final(c)) return rf;
     unsigned long long* bits = c->abits + 9;
     int e = launch_alpha(c->G, c->P, d_Q, c->apart, bits, c->stream);
@@ -1263,17 +1279,12 @@ int32_t fsa_face_flags(fsa_ctx* c, const double* d_Q, uint32_t* d_flags_x, uint3
 int32_t fsa_diagnostics(fsa_ctx* c, const double* d_Q, double* h_totals, double* d_dilatation)
 {
     if (!c || !d_Q || (!h_totals && !d_dilatation)) return FSA_EINVAL;
-    int rc, e;
+    int e;
     if (d_dilatation) {
         e = launch_dilatation(c->G, c->P, d_Q, c->step, d_dilatation, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "dilatation launch");
     }
     if (h_totals) {
-        if (!c->tot_part) {
-            if ((rc = dalloc(c, c->tot_part, (size_t)totals_part_size(c->nq))) != FSA_OK ||
-                (rc = dalloc(c, c->tot_out, 5)) != FSA_OK)
-                return rc;
-        }
         e = launch_totals(c->G, c->nq, d_Q, c->tot_part, c->tot_out, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "totals launch");
         HIPCHK(c, hipMemcpyAsync(h_totals, c->tot_out, sizeof(double) * c->nq, hipMemcpyDeviceToHost, c->stream));
@@ -1331,7 +1342,7 @@ int32_t fsa_stats_get(fsa_ctx* c, fsa_stats* out)
     out->n_probes = c->np;
     out->window_cells = (int32_t)c->wcells;
     out->rows_per_wave = c->ty;
-    if (c->counters) {
+    if (c->counters && c->mlp_ready) {
         const long long nb = flags2d_blocks(c->G);
         std::vector<unsigned long long> hc((size_t)(3 * nb));
         HIPCHK(c, hipMemcpy(hc.data(), c->counters, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));

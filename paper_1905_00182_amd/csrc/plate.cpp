@@ -462,8 +462,10 @@ int32_t fsa_plate_coupled_steps(fsa_ctx* ctx, fsa_plate* p, double* d_Q, double 
                                 int32_t resume)
 {
     if (!ctx || !p || !d_Q || nsteps < 0) return FSA_EINVAL;
-    int32_t nm = 0, motion = -1;
-    if (fsa_marker_info(ctx, &nm, &motion) != FSA_OK || nm != p->nm || motion != FSA_EXTERNAL)
+    int32_t nm = 0, motion = -1, dim = 0;
+    if (fsa_marker_info(ctx, &nm, &motion, &dim) != FSA_OK) return fail(p, FSA_EINVAL, "bad solver context");
+    if (dim != 2) return fail(p, FSA_EUNSUPPORTED, "the plate is planar: the solver must be 2D");
+    if (nm != p->nm || motion != FSA_EXTERNAL)
         return fail(p, FSA_ESTATE, "the solver's markers are not the plate's (count or EXTERNAL motion)");
     try {
         std::vector<double> X(2 * (size_t)p->nm), U(2 * (size_t)p->nm), F(2 * (size_t)p->nm);

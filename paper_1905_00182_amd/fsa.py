@@ -56,6 +56,9 @@ class FsaDesc(C.Structure):
         ("src_b", C.c_double),
         ("src_omega", C.c_double),
         ("src_x", C.c_double * 3),
+        ("max_markers", C.c_int32),
+        ("max_probes", C.c_int32),
+        ("max_window_cells", C.c_int64),
     ]
 
 
@@ -101,7 +104,8 @@ _SIGS = {
     "fsa_abi_version": (C.c_int32, []),
     "fsa_status_str": (C.c_char_p, [C.c_int32]),
     "fsa_last_error": (C.c_char_p, [C.c_void_p]),
-    "fsa_init": (C.c_int32, [C.POINTER(FsaDesc), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "fsa_workspace_bytes": (C.c_int32, [C.POINTER(FsaDesc), C.POINTER(C.c_size_t)]),
+    "fsa_init": (C.c_int32, [C.POINTER(FsaDesc), C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
     "fsa_destroy": (C.c_int32, [C.c_void_p]),
     "fsa_set_markers": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                     C.c_double]),
@@ -132,7 +136,7 @@ _SIGS = {
     "fsa_sync": (C.c_int32, [C.c_void_p]),
     "fsa_stats_get": (C.c_int32, [C.c_void_p, C.POINTER(FsaStats)]),
     # include/fsa_plate.h
-    "fsa_marker_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "fsa_marker_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "fsa_plate_create": (C.c_int32, [C.POINTER(FsaPlateDesc), C.POINTER(C.c_void_p)]),
     "fsa_plate_destroy": (C.c_int32, [C.c_void_p]),
     "fsa_plate_markers": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -261,7 +265,30 @@ def make_desc(case, nan_check=False) -> FsaDesc:
     d.sponge_sigma = case.sponge_sigma
     d.ib_alpha = case.ib_alpha
     d.ib_beta = case.ib_beta
+    d.max_markers, d.max_probes, d.max_window_cells = capacities(case)
     return d
+
+
+def capacities(case):
+    """Workspace capacities (markers, probes, window cells) for a case: case.extra's
+    max_markers / max_probes / max_window_cells when given, else the case's own markers and
+    probes (at least 64 each) and, for markers that do not move, the box of their supports
+    with a margin (moving markers: 0, the whole grid)."""
+    ex = case.extra
+    m = case.markers
+    nm = int(np.asarray(m["dV"]).shape[0]) if m is not None else 0
+    npr = int(np.asarray(case.probes).shape[1]) if case.probes is not None else 0
+    mm = int(ex.get("max_markers", max(nm, 64)))
+    mp = int(ex.get("max_probes", max(npr, 64)))
+    if "max_window_cells" in ex:
+        mw = int(ex["max_window_cells"])
+    elif nm and m.get("motion", "static") != "external":
+        X = np.asarray(m["X"], dtype=np.float64).reshape(case.dim, nm)
+        ext = X.max(axis=1) - X.min(axis=1)
+        mw = int(np.prod(np.floor(ext / case.h) + 8))     # a support reaches 2 cells either side
+    else:
+        mw = 0
+    return mm, mp, mw
 
 
 def _host(a):
@@ -286,8 +313,13 @@ class Solver:
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.desc = make_desc(case, nan_check)
+        nbytes = C.c_size_t()
+        self._check(lib().fsa_workspace_bytes(C.byref(self.desc), C.byref(nbytes)), None)
+        # the context's device memory: a torch allocation the library carves up
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
         ctx = C.c_void_p()
-        self._check(lib().fsa_init(C.byref(self.desc), C.c_void_p(self.stream.cuda_stream), C.byref(ctx)), None)
+        self._check(lib().fsa_init(C.byref(self.desc), C.c_void_p(self.workspace.data_ptr()), nbytes.value,
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(ctx)), None)
         self.ctx = ctx
         self.nm = 0
         self.np = 0
@@ -299,8 +331,9 @@ class Solver:
 
     def close(self):
         if getattr(self, "ctx", None):
-            lib().fsa_destroy(self.ctx)
+            lib().fsa_destroy(self.ctx)     # (waits for the stream: the workspace is then free)
             self.ctx = None
+        self.workspace = None
 
     __del__ = close
 
@@ -310,11 +343,24 @@ class Solver:
             msg = lib().fsa_last_error(c).decode() if c else lib().fsa_status_str(rc).decode()
             raise FsaError(rc, msg)
 
-    def _state(self, Q):
+    def _dev(self, x, shape, dtype, what):
+        """A device argument: a contiguous tensor of this dtype and shape on the context's
+        device (anything else would let a kernel read or write outside it)."""
         t = self.torch
-        assert Q.dtype == t.float64 and Q.is_cuda and Q.is_contiguous(), "Q must be contiguous float64 on the GPU"
-        assert tuple(Q.shape) == self.shape, (tuple(Q.shape), self.shape)
-        return Q
+        if not isinstance(x, t.Tensor):
+            raise ValueError(f"{what} must be a torch tensor")
+        if x.dtype != dtype:
+            raise ValueError(f"{what} must be {dtype}, not {x.dtype}")
+        if x.device != self.device:
+            raise ValueError(f"{what} must be on {self.device}, not {x.device}")
+        if not x.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        if tuple(x.shape) != tuple(shape):
+            raise ValueError(f"{what} must have shape {tuple(shape)}, not {tuple(x.shape)}")
+        return x
+
+    def _state(self, Q, what="Q"):
+        return self._dev(Q, self.shape, self.torch.float64, what)
 
     # -- set-up
     def _host_shape(self, A, shape, what):
@@ -354,7 +400,7 @@ class Solver:
 
     def rhs(self, Q, out=None):
         Q = self._state(Q)
-        L = out if out is not None else self.torch.empty_like(Q)
+        L = self._state(out, "out") if out is not None else self.torch.empty_like(Q)
         self._check(lib().fsa_rhs(self.ctx, _ptr(Q), _ptr(L)))
         return L
 
@@ -372,19 +418,31 @@ class Solver:
         return Q
 
     def ib_interp(self, field):
-        ncomp = field.shape[0]
-        out = self.torch.empty((ncomp, self.nm), dtype=self.torch.float64, device=field.device)
-        self._check(lib().fsa_ib_interp(self.ctx, _ptr(field.contiguous()), ncomp, _ptr(out)))
+        t = self.torch
+        ncomp = field.shape[0] if isinstance(field, t.Tensor) and field.dim() > 0 else 0
+        if ncomp < 1:
+            raise ValueError("field must be [ncomp] + grid shape with ncomp >= 1")
+        field = self._dev(field, (ncomp,) + self.case.shape, t.float64, "field")
+        out = t.empty((ncomp, self.nm), dtype=t.float64, device=self.device)
+        self._check(lib().fsa_ib_interp(self.ctx, _ptr(field), ncomp, _ptr(out)))
         return out
 
     def ib_spread(self, F, field, scale=1.0):
-        assert field.is_contiguous()
-        self._check(lib().fsa_ib_spread(self.ctx, _ptr(F.contiguous()), F.shape[0], _ptr(field), scale))
+        t = self.torch
+        ncomp = F.shape[0] if isinstance(F, t.Tensor) and F.dim() > 0 else 0
+        if ncomp < 1:
+            raise ValueError("F must be [ncomp][markers] with ncomp >= 1")
+        F = self._dev(F, (ncomp, self.nm), t.float64, "F")
+        field = self._dev(field, (ncomp,) + self.case.shape, t.float64, "field")
+        self._check(lib().fsa_ib_spread(self.ctx, _ptr(F), ncomp, _ptr(field), scale))
         return field
 
     def probe_dp(self, Q, out=None):
-        dp = out if out is not None else self.torch.empty(self.np, dtype=self.torch.float64, device=Q.device)
-        self._check(lib().fsa_probe_dp(self.ctx, _ptr(self._state(Q)), _ptr(dp)))
+        t = self.torch
+        Q = self._state(Q)
+        dp = self._dev(out, (self.np,), t.float64, "out") if out is not None else \
+            t.empty(self.np, dtype=t.float64, device=self.device)
+        self._check(lib().fsa_probe_dp(self.ctx, _ptr(Q), _ptr(dp)))
         return dp
 
     # -- synchronising calls
@@ -424,21 +482,33 @@ class Solver:
         self._check(lib().fsa_mlp_get(self.ctx, p.ctypes.data, MLP_NPARAM))
         return p
 
+    def _feats(self, feats, labels=None):
+        t = self.torch
+        n = feats.shape[0] if isinstance(feats, t.Tensor) and feats.dim() == 2 else -1
+        feats = self._dev(feats, (n, 16), t.float32, "feats")
+        if labels is not None:
+            labels = self._dev(labels, (n,), t.uint8, "labels")
+        return feats, labels, n
+
     def mlp_forward(self, feats):
         t = self.torch
-        assert feats.dtype == t.float32 and feats.is_contiguous() and feats.shape[1] == 16
-        z = t.empty((feats.shape[0], 3), dtype=t.float32, device=feats.device)
+        feats, _, n = self._feats(feats)
+        z = t.empty((n, 3), dtype=t.float32, device=self.device)
         self._check(lib().fsa_mlp_forward(self.ctx, _ptr(feats), feats.shape[0], _ptr(z)))
         return z
 
     def mlp_grad(self, feats, labels):
         t = self.torch
-        g = t.empty(MLP_NPARAM, dtype=t.float32, device=feats.device)
-        loss = t.empty(1, dtype=t.float32, device=feats.device)
+        feats, labels, _ = self._feats(feats, labels)
+        g = t.empty(MLP_NPARAM, dtype=t.float32, device=self.device)
+        loss = t.empty(1, dtype=t.float32, device=self.device)
         self._check(lib().fsa_mlp_grad(self.ctx, _ptr(feats), _ptr(labels), feats.shape[0], _ptr(g), _ptr(loss)))
         return g, loss
 
     def mlp_train_step(self, feats, labels, lr, loss=None):
+        feats, labels, _ = self._feats(feats, labels)
+        if loss is not None:
+            loss = self._dev(loss, (1,), self.torch.float32, "loss")
         self._check(lib().fsa_mlp_train_step(self.ctx, _ptr(feats), _ptr(labels), feats.shape[0], lr,
                                              _ptr(loss) if loss is not None else None))
 

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(fsa.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert fsa.lib().fsa_abi_version() == 2
+    assert fsa.lib().fsa_abi_version() == 3
     assert fsa.lib().fsa_status_str(-4) == b"non-finite state"
 
 
@@ -63,3 +63,48 @@ def test_plate_descriptor_layout_matches_the_header():
     body = re.search(r"typedef struct fsa_plate_desc \{(.*?)\} fsa_plate_desc;", text, flags=re.S).group(1)
     fields = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**([a-z_0-9]+)(?:\[|;)", body, flags=re.M)
     assert fields == [f[0] for f in fsa.FsaPlateDesc._fields_]
+
+
+def test_workspace_bytes_follow_the_descriptor():
+    # fsa_workspace_bytes is host arithmetic on the descriptor: no GPU call
+    from paper_1905_00182_amd import fsa, workloads as W
+
+    def nbytes(case):
+        n = ctypes.c_size_t(7)
+        rc = fsa.lib().fsa_workspace_bytes(ctypes.byref(fsa.make_desc(case)), ctypes.byref(n))
+        return rc, n.value
+
+    c1 = W.config1()
+    rc, b1 = nbytes(c1)
+    assert rc == fsa.OK
+    assert b1 >= 2 * c1.nq * c1.ncell * 8            # the two RK stage buffers at least
+    rc, b_more = nbytes(c1.with_(extra={"max_markers": 5000}))
+    assert rc == fsa.OK and b_more > b1              # markers and their support entries
+    rc, b_probe = nbytes(c1.with_(extra={"max_probes": 100000}))
+    assert rc == fsa.OK and b_probe >= b1 + (100000 - 64) * 2 * 8
+    rc, b_big = nbytes(W.config1(n=256))
+    assert rc == fsa.OK and b_big - b1 >= 2 * c1.nq * (256 * 256 - 128 * 128) * 8
+    c3 = W.config3(n=32, nmark=100)
+    rc, b3 = nbytes(c3)
+    assert rc == fsa.OK and b3 >= 2 * c3.nq * c3.ncell * 8
+    bad = fsa.make_desc(c1)
+    bad.dim = 4
+    n = ctypes.c_size_t(7)
+    assert fsa.lib().fsa_workspace_bytes(ctypes.byref(bad), ctypes.byref(n)) == fsa.EINVAL and n.value == 0
+    bad = fsa.make_desc(c1)
+    bad.max_markers = -1
+    assert fsa.lib().fsa_workspace_bytes(ctypes.byref(bad), ctypes.byref(n)) == fsa.EINVAL
+
+
+def test_init_rejects_a_missing_or_small_workspace():
+    # rejected before any device work
+    from paper_1905_00182_amd import fsa, workloads as W
+
+    d = fsa.make_desc(W.config1())
+    need = ctypes.c_size_t()
+    assert fsa.lib().fsa_workspace_bytes(ctypes.byref(d), ctypes.byref(need)) == fsa.OK
+    ctx = ctypes.c_void_p()
+    assert fsa.lib().fsa_init(ctypes.byref(d), None, need.value, None, ctypes.byref(ctx)) == fsa.EINVAL
+    assert fsa.lib().fsa_init(ctypes.byref(d), ctypes.c_void_p(4096), need.value - 1, None,
+                              ctypes.byref(ctx)) == fsa.EINVAL
+    assert not ctx.value

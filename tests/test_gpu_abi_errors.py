@@ -120,10 +120,11 @@ def test_coupled_steps_need_the_plates_markers(fsa_mod):
     case = W.config5_flexible(n=128, L=8.0, nmark=128, nel=10)
     plate = fsa_mod.Plate(case)
     Q = torch.from_numpy(W.uniform_state(case)).cuda()
-    n, motion = fsa_mod.C.c_int32(), fsa_mod.C.c_int32()
+    n, motion, dim = fsa_mod.C.c_int32(), fsa_mod.C.c_int32(), fsa_mod.C.c_int32()
     s = fsa_mod.Solver(case)
-    assert fsa_mod.lib().fsa_marker_info(s.ctx, fsa_mod.C.byref(n), fsa_mod.C.byref(motion)) == fsa_mod.OK
-    assert (n.value, motion.value) == (128, fsa_mod.MOTION["external"])
+    assert fsa_mod.lib().fsa_marker_info(s.ctx, fsa_mod.C.byref(n), fsa_mod.C.byref(motion),
+                                         fsa_mod.C.byref(dim)) == fsa_mod.OK
+    assert (n.value, motion.value, dim.value) == (128, fsa_mod.MOTION["external"], 2)
     for other in (W.config5_flexible(n=128, L=8.0, nmark=96, nel=10),          # fewer markers
                   case.with_(markers={**case.markers, "motion": "static"})):  # not EXTERNAL
         so = fsa_mod.Solver(other)
@@ -131,6 +132,16 @@ def test_coupled_steps_need_the_plates_markers(fsa_mod):
             plate.coupled_steps(so, Q, case.dt, 1, resume=False)
         assert e.value.code == fsa_mod.ESTATE
         so.close()
+    # a 3D solver with as many EXTERNAL markers: its [3][n] arrays are not the plate's [2][n]
+    c3 = W.config3(n=16, nmark=128, L=4.0)
+    X3 = np.stack([np.linspace(-0.5, 0.5, 128), np.zeros(128), np.zeros(128)])
+    c3 = c3.with_(markers={"X": X3, "dV": np.full(128, 1.0 / 128), "U": None, "motion": "external", "omega": 0.0})
+    s3 = fsa_mod.Solver(c3)
+    Q3 = torch.from_numpy(W.uniform_state(c3)).cuda()
+    with pytest.raises(fsa_mod.FsaError) as e:
+        plate.coupled_steps(s3, Q3, c3.dt, 1, resume=False)
+    assert e.value.code == fsa_mod.EUNSUPPORTED
+    s3.close()
     plate.coupled_steps(s, Q, case.dt, 2, resume=False)      # the matching pair still works
     s.sync()
     assert torch.isfinite(Q).all()
@@ -149,3 +160,34 @@ def test_binding_rejects_wrong_shapes(fsa_mod):
         s.set_state(np.zeros((2, 63)), 0.0, 0)
     s.set_marker_kinematics(X, U)    # the right shapes still work
     s.sync()
+
+
+def test_workspace_capacities_are_enforced(fsa_mod):
+    import torch
+
+    case = W.config1(n=64)
+    s = fsa_mod.Solver(case.with_(extra={"max_markers": 64, "max_probes": 32}))
+    need = fsa_mod.C.c_size_t()
+    assert fsa_mod.lib().fsa_workspace_bytes(fsa_mod.C.byref(s.desc), fsa_mod.C.byref(need)) == fsa_mod.OK
+    assert s.workspace.numel() == need.value and s.workspace.is_cuda
+    X, dV = W.circle_markers(65, 0.5)
+    with pytest.raises(fsa_mod.FsaError) as e:
+        s.set_markers(X, dV)                                     # one more than the capacity
+    assert e.value.code == fsa_mod.EINVAL and "max_markers" in str(e.value)
+    with pytest.raises(fsa_mod.FsaError) as e:
+        s.set_probes(W.ring_probes(33, 2.0))
+    assert e.value.code == fsa_mod.EINVAL
+    # a window capacity that the markers' supports outgrow
+    sw = fsa_mod.Solver(case.with_(extra={"max_markers": 64, "max_window_cells": 100}))
+    X, dV = W.circle_markers(64, 0.5)
+    with pytest.raises(fsa_mod.FsaError) as e:
+        sw.set_markers(X, dV)
+    assert e.value.code == fsa_mod.EINVAL and "max_window_cells" in str(e.value)
+    # within the capacities the context still steps
+    s.set_markers(*W.circle_markers(64, 0.5))
+    Q = torch.from_numpy(W.config1_state(case)).cuda()
+    s.rk3_step(Q, case.dt)
+    s.sync()
+    assert torch.isfinite(Q).all()
+    s.close()
+    sw.close()
