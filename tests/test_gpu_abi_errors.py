@@ -178,7 +178,7 @@ def test_workspace_capacities_are_enforced(fsa_mod):
         s.set_probes(W.ring_probes(33, 2.0))
     assert e.value.code == fsa_mod.EINVAL
     # a window capacity that the markers' supports outgrow
-    sw = fsa_mod.Solver(case.with_(extra={"max_markers": 64, "max_window_cells": 100}))
+    sw = fsa_mod.Solver(case.with_(markers=None, extra={"max_markers": 64, "max_window_cells": 40}))
     X, dV = W.circle_markers(64, 0.5)
     with pytest.raises(fsa_mod.FsaError) as e:
         sw.set_markers(X, dV)
