@@ -186,6 +186,18 @@ int32_t fsa_set_probes(fsa_ctx* ctx, int32_t n, const double* Xp);
 /* Global Lax-Friedrichs speeds alpha[d] = max over cells of |u_d| + c of d_Q, written to the
  * host array alpha[3] (NaN-propagating).  Synchronising. */
 int32_t fsa_alpha(fsa_ctx* ctx, const double* d_Q, double* alpha);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc), and need no context: the global Lax-Friedrichs
+ * speeds of fsa_alpha, max over the cells of d_Q (the grid and gas of desc, FP64 state as
+ * above) of |u_d| + c, NaN-propagating, written to the DEVICE array d_alpha[3] (directions
+ * beyond dim: 0) on hip_stream, without synchronising.  Allocates nothing: its per-block
+ * partial maxima (at most 2048 blocks x 3) live in a static device array of the library, one
+ * per GPU (48 KB, held until the process ends), which every call on that GPU shares and which
+ * keeps the last call's partials; calls that overlap on one GPU (on different streams, or
+ * from different threads without ordering) race and give wrong results.  Any grid desc
+ * accepts fits (larger grids fold into the same number of partials); FSA_EINVAL for an invalid
+ * desc or NULL pointers, FSA_EDEVICE if the launch fails. */
+int32_t fsa_alpha_noalloc(const fsa_desc* desc, const double* d_Q, double* d_alpha, void* hip_stream);
 /* d_L = L(d_Q) at the context's time, step and penalty integral (Sec. 2, Eq. (2) with the
  * IB source of Eqs. (7)-(9)).  d_L must not alias d_Q.  Also records the penalty force. */
 int32_t fsa_rhs(fsa_ctx* ctx, const double* d_Q, double* d_L);

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -815,6 +816,35 @@ int check_previous(fsa_ctx* c)
     return FSA_OK;
 }
 
+// Scratch of fsa_alpha_noalloc: the per-block partial maxima of the wave-speed reduction
+// (three per block, at most ALPHA_MAX_BLOCKS blocks), in a static device array instead of a
+// context's workspace.  Each GPU holds its own copy at its own address, taken once per device
+// with hipGetSymbolAddress; host code passes that address, never the array's name.
+constexpr long long NOALLOC_PARTIALS = 3ll * ALPHA_MAX_BLOCKS;
+static __device__ __align__(256) unsigned long long scratch[NOALLOC_PARTIALS];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device (taken on the first call there).
+hipError_t scratch_address(unsigned long long** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (unsigned long long*)g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1043,6 +1073,32 @@ int32_t fsa_alpha(fsa_ctx* c, const double* d_Q, double* alpha)
         else alpha[d] = 0.0;
     }
     return FSA_OK;
+}
+
+int32_t fsa_alpha_noalloc(const fsa_desc* desc, const double* d_Q, double* d_alpha, void* hip_stream)
+{
+    std::string why;
+    if (!d_Q || !d_alpha) return FSA_EINVAL;
+    if (validate(desc, why) != FSA_OK) {
+        std::fprintf(stderr, "fsa_alpha_noalloc: %s\n", why.c_str());
+        return FSA_EINVAL;
+    }
+    fsa_ctx tmp;                       // (grid and gas constants only: no buffers)
+    tmp.d = *desc;
+    build_consts(&tmp);
+    long long blocks = alpha_blocks(tmp.G);
+    if (3 * blocks > NOALLOC_PARTIALS) {
+        std::fprintf(stderr, "fsa_alpha_noalloc: %lld partials exceed the static scratch of %lld\n", 3 * blocks,
+                     NOALLOC_PARTIALS);
+        return FSA_EINVAL;
+    }
+    unsigned long long* part = nullptr;
+    if (scratch_address(&part) != hipSuccess) {
+        (void)hipGetLastError();
+        return FSA_EDEVICE;
+    }
+    int e = launch_alpha(tmp.G, tmp.P, d_Q, part, (unsigned long long*)d_alpha, (hipStream_t)hip_stream);
+    return e ? FSA_EDEVICE : FSA_OK;
 }
 
 int32_t fsa_rhs(fsa_ctx* c, const double* d_Q, double* d_L)

@@ -85,6 +85,8 @@ int stage2d_strip_width();
 // Wave speeds max over cells of |u_d| + c of Q into bits[3]: per-block partials in part
 // (ALPHA_MAX_BLOCKS x 3), then launch_alpha_final.  No same-address atomics.
 constexpr int ALPHA_MAX_BLOCKS = 2048;
+// Blocks (partials) launch_alpha uses for grid G: one per 256 cells, at most ALPHA_MAX_BLOCKS.
+long long alpha_blocks(const Grid& G);
 int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* part, unsigned long long* bits,
                  hipStream_t s);
 // bits[d] = NaN-propagating max over n partials part[k * 3 + d] (d < 3).

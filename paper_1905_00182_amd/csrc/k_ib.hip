@@ -473,12 +473,17 @@ __global__ __launch_bounds__(256) void k_dilatation(Grid G, Phys P, const double
 
 }  // namespace
 
-int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* part, unsigned long long* bits,
-                 hipStream_t s)
+long long alpha_blocks(const Grid& G)
 {
     long long blocks = (G.ncell + RED_THREADS - 1) / RED_THREADS;
     if (blocks > ALPHA_MAX_BLOCKS) blocks = ALPHA_MAX_BLOCKS;
-    if (blocks < 1) blocks = 1;
+    return blocks < 1 ? 1 : blocks;
+}
+
+int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* part, unsigned long long* bits,
+                 hipStream_t s)
+{
+    const long long blocks = alpha_blocks(G);
     if (G.dim == 3) hipLaunchKernelGGL(k_alpha<3>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, part);
     else hipLaunchKernelGGL(k_alpha<2>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, part);
     return launch_alpha_final(part, blocks, bits, s);

@@ -112,6 +112,7 @@ _SIGS = {
     "fsa_set_marker_kinematics": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fsa_set_probes": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "fsa_alpha": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsa_alpha_noalloc": (C.c_int32, [C.POINTER(FsaDesc), C.c_void_p, C.c_void_p, C.c_void_p]),
     "fsa_rhs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fsa_rk3_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double]),
     "fsa_rk3_steps": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32]),
@@ -297,6 +298,26 @@ def _host(a):
 
 def _ptr(t):
     return C.c_void_p(t.data_ptr())
+
+
+def alpha_noalloc(case, Q, out, stream=None):
+    """fsa_alpha_noalloc: the wave speeds of Q (case's grid and gas) into the device tensor
+    out[3], on torch's current stream (or `stream`), with no context and no allocation."""
+    import torch
+
+    nq = case.dim + 2
+    for x, shape, what in ((Q, (nq,) + case.shape, "Q"), (out, (3,), "out")):
+        if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.is_cuda and x.is_contiguous()
+                and tuple(x.shape) == shape):
+            raise ValueError(f"{what} must be a contiguous float64 CUDA tensor of shape {shape}")
+    if Q.device != out.device:
+        raise ValueError("Q and out must be on one device")
+    st = stream if stream is not None else torch.cuda.current_stream(Q.device)
+    d = make_desc(case)
+    rc = lib().fsa_alpha_noalloc(C.byref(d), _ptr(Q), _ptr(out), C.c_void_p(st.cuda_stream))
+    if rc != OK:
+        raise FsaError(rc, "fsa_alpha_noalloc: " + lib().fsa_status_str(rc).decode())
+    return out
 
 
 class Solver:
