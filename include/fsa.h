@@ -280,6 +280,18 @@ int32_t fsa_harvest(fsa_ctx* ctx, const double* d_Q, double keep_rate, uint64_t 
  * bits 3c..3c+2 (side "+") and 16+3c.. (side "-") for component c. */
 int32_t fsa_face_flags(fsa_ctx* ctx, const double* d_Q, uint32_t* d_flags_x, uint32_t* d_flags_y);
 
+/* Test read-out of the TENO5 sub-stencil decisions (FP64 TENO5 only; FSA_EUNSUPPORTED
+ * otherwise): while d_bits (DEVICE, uint32) is set, every right-hand side and SSP-RK3 stage
+ * enqueued on ctx also writes the keep pattern its reconstruction chose at every face, for
+ * the state that stage evaluates, into d_bits[stage][faces] (a lone fsa_rhs: stage 0; RK3
+ * stages 0, 1, 2; a multi-step call leaves its last step's): x faces [nz][ny][nx+1], then y
+ * faces [nz][ny+1][nx], then (3D) z faces [nz+1][ny][nx], one word per face with bits 3c+k
+ * (side "+", component c, sub-stencil k kept) and 16+3c+k (side "-") -- the layout of
+ * fsa_face_flags.  The kernels then run an instantiation that adds these stores to the same
+ * arithmetic.  NULL turns the read-out off.  Used by tests to check that where the library
+ * and an independent implementation decide differently, the decision is a tie. */
+int32_t fsa_debug_teno_bits(fsa_ctx* ctx, uint32_t* d_bits);
+
 /* Measurement: with timing on, a pair of HIP events on the context's stream brackets every
  * launch of the fused stencil/update kernel.  fsa_timing_read (synchronising) returns the
  * summed kernel milliseconds and the number of launches since the previous read. */

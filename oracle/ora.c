@@ -50,6 +50,7 @@ struct ora_ctx {
     double* Xp;
     double t;
     int64_t step;
+    double* record;    /* if set: ora_rk3_step copies each stage's input state here (test hook) */
 };
 
 /* ------------------------------------------------------------------------------------ */
@@ -230,6 +231,16 @@ int ora_teno_flags(double a, double b, double cc, double d, double e, double ten
     double q[3], beta[3];
     candidates(a, b, cc, d, e, q, beta);
     return teno_keep(beta, teno_ct, teno_eps);
+}
+
+/* ora_teno_flags of n stencils v[n][5] into out[n] (a convenience for tests). */
+int ora_teno_flags_n(const double* v, long n, double teno_ct, double teno_eps, int* out)
+{
+    for (long i = 0; i < n; ++i) {
+        const double* w = v + 5 * i;
+        out[i] = ora_teno_flags(w[0], w[1], w[2], w[3], w[4], teno_ct, teno_eps);
+    }
+    return 0;
 }
 
 double ora_recon5(double a, double b, double cc, double d, double e, int scheme,
@@ -915,6 +926,7 @@ int ora_rk3_step(ora_ctx* c, double* Q, double dt)
 
     /* stage 1 at time t */
     c->t = t0;
+    if (c->record) memcpy(c->record, Qn, sizeof(double) * (size_t)len);
     ora_rhs(c, Qn, L);
     #pragma omp parallel for
     for (long i = 0; i < len; ++i) Qs[i] = Qn[i] + dt * L[i];
@@ -923,6 +935,7 @@ int ora_rk3_step(ora_ctx* c, double* Q, double dt)
 
     /* stage 2 at time t + dt */
     c->t = t0 + dt;
+    if (c->record) memcpy(c->record + len, Qs, sizeof(double) * (size_t)len);
     ora_rhs(c, Qs, L);
     #pragma omp parallel for
     for (long i = 0; i < len; ++i) Qs[i] = 0.75 * Qn[i] + 0.25 * (Qs[i] + dt * L[i]);
@@ -931,6 +944,7 @@ int ora_rk3_step(ora_ctx* c, double* Q, double dt)
 
     /* stage 3 at time t + dt/2 */
     c->t = t0 + 0.5 * dt;
+    if (c->record) memcpy(c->record + 2 * len, Qs, sizeof(double) * (size_t)len);
     ora_rhs(c, Qs, L);
     #pragma omp parallel for
     for (long i = 0; i < len; ++i) Q[i] = (1.0 / 3.0) * Qn[i] + (2.0 / 3.0) * (Qs[i] + dt * L[i]);
@@ -944,6 +958,120 @@ int ora_rk3_step(ora_ctx* c, double* Q, double dt)
     free(Qs);
     free(L);
     free(xin);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Test hooks on the TENO5 decisions (they compute nothing the solver uses)               */
+/* ------------------------------------------------------------------------------------ */
+
+int ora_record_stages(ora_ctx* c, double* buf)
+{
+    c->record = buf;
+    return 0;
+}
+
+/* Split fluxes of the six cells around face `f` (between cells f-1 and f along dir) of the
+ * line through (i, j, k): fp[s][m], fm[s][m] for cells f-3+s, s = 0..5. */
+static void face_splits(const ora_ctx* c, const double* Q, int dir, long f, long i, long j, long k, double alpha,
+                        double fp[6][5], double fm[6][5])
+{
+    long idx[3] = {i, j, k};
+    idx[dir] = f - 3;
+    for (int s = 0; s < 6; ++s) {
+        long id[3] = {idx[0], idx[1], idx[2]};
+        id[dir] += s;
+        double q[5], fl[5];
+        fetch(c, Q, id[0], id[1], id[2], q);
+        phys_flux(c, q, dir, fl);
+        for (int m = 0; m < c->nq; ++m) {
+            fp[s][m] = 0.5 * (fl[m] + alpha * q[m]);
+            fm[s][m] = 0.5 * (fl[m] - alpha * q[m]);
+        }
+    }
+}
+
+/* Number of faces along dir: x faces [nz][ny][nx+1], y faces [nz][ny+1][nx], z faces
+ * [nz+1][ny][nx]. */
+static long faces_along(const ora_ctx* c, int dir)
+{
+    return (c->nx + (dir == 0)) * (c->ny + (dir == 1)) * (c->nz + (dir == 2));
+}
+
+static void face_coords(const ora_ctx* c, int dir, long lin, long* f, long* i, long* j, long* k)
+{
+    long mx = c->nx + (dir == 0), my = c->ny + (dir == 1);
+    long a = lin % mx, b = (lin / mx) % my, d = lin / (mx * my);
+    *i = a;
+    *j = b;
+    *k = d;
+    *f = dir == 0 ? a : (dir == 1 ? b : d);
+}
+
+/* The TENO5 keep patterns the oracle's reconstruction takes at every face of Q (its own wave
+ * speeds), in the face layout above, directions one after the other: bits 3m+k for side "+"
+ * (values f+_{f-3..f+1}), 16+3m+k for side "-" (f-_{f+2..f-2}), component m, sub-stencil k. */
+int ora_teno_bits(const ora_ctx* c, const double* Q, uint32_t* out)
+{
+    double alpha[3];
+    ora_alpha(c, Q, alpha);
+    long off = 0;
+    for (int dir = 0; dir < c->d.dim; ++dir) {
+        long nf = faces_along(c, dir);
+        #pragma omp parallel for
+        for (long lin = 0; lin < nf; ++lin) {
+            long f, i, j, k;
+            double fp[6][5], fm[6][5];
+            face_coords(c, dir, lin, &f, &i, &j, &k);
+            face_splits(c, Q, dir, f, i, j, k, alpha[dir], fp, fm);
+            uint32_t w = 0;
+            for (int m = 0; m < c->nq; ++m) {
+                int kp = ora_teno_flags(fp[0][m], fp[1][m], fp[2][m], fp[3][m], fp[4][m], c->d.teno_ct, c->d.teno_eps);
+                int km = ora_teno_flags(fm[5][m], fm[4][m], fm[3][m], fm[2][m], fm[1][m], c->d.teno_ct, c->d.teno_eps);
+                w |= (uint32_t)kp << (3 * m);
+                w |= (uint32_t)km << (16 + 3 * m);
+            }
+            out[off + lin] = w;
+        }
+        off += nf;
+    }
+    return 0;
+}
+
+/* For n entries (face g[i] in the layout of ora_teno_bits, component m[i], side sd[i]: 0 "+",
+ * 1 "-") of Q at the wave speeds alpha[3]: the five upwind-ordered split-flux values
+ * v[i][5] and chi_k = gamma_k / sum gamma of TENO5 on them, chi[i][3]. */
+int ora_teno_values_n(const ora_ctx* c, const double* Q, const double* alpha, long n, const long* g, const int* m,
+                      const int* sd, double* v, double* chi)
+{
+    for (long e = 0; e < n; ++e) {
+        long lin = g[e];
+        int dir = 0;
+        while (dir < c->d.dim && lin >= faces_along(c, dir)) lin -= faces_along(c, dir++);
+        if (dir >= c->d.dim || m[e] < 0 || m[e] >= c->nq) return -1;
+    }
+    #pragma omp parallel for
+    for (long e = 0; e < n; ++e) {
+        long lin = g[e];
+        int dir = 0;
+        while (lin >= faces_along(c, dir)) lin -= faces_along(c, dir++);
+        long f, i, j, k;
+        double fp[6][5], fm[6][5];
+        face_coords(c, dir, lin, &f, &i, &j, &k);
+        face_splits(c, Q, dir, f, i, j, k, alpha[dir], fp, fm);
+        double* w = v + 5 * e;
+        for (int s = 0; s < 5; ++s) w[s] = sd[e] == 0 ? fp[s][m[e]] : fm[5 - s][m[e]];
+        double q[3], beta[3];
+        candidates(w[0], w[1], w[2], w[3], w[4], q, beta);
+        double tau = fabs(beta[0] - beta[2]), gk[3], sum = 0.0;
+        for (int kk = 0; kk < 3; ++kk) {
+            double x = 1.0 + tau / (beta[kk] + c->d.teno_eps);
+            double x3 = x * x * x;
+            gk[kk] = x3 * x3;
+            sum += gk[kk];
+        }
+        for (int kk = 0; kk < 3; ++kk) chi[3 * e + kk] = gk[kk] / sum;
+    }
     return 0;
 }
 

@@ -107,6 +107,20 @@ int ora_face_features(const ora_ctx* c, const double* Q, int dir, long i, long j
 int ora_face_label(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side, double alpha);
 int ora_face_significant(const ora_ctx* c, const double* Q, int dir, long i, long j, long k, int side);
 
+/* Test hooks on the TENO5 decisions (nothing the solver uses):
+ * ora_record_stages: while buf is set, ora_rk3_step copies the input state of each of its
+ *   three stages into buf[stage][nq][ncell] (NULL stops);
+ * ora_teno_bits: the keep patterns of every face of Q at Q's own wave speeds, x faces
+ *   [nz][ny][nx+1], y faces [nz][ny+1][nx], (z faces [nz+1][ny][nx]) one after the other,
+ *   bits 3m+k (side "+") and 16+3m+k (side "-") for component m and sub-stencil k;
+ * ora_teno_values_n: for n (face in that layout, component, side 0 "+" / 1 "-") entries at
+ *   the wave speeds alpha[3], the five upwind-ordered split-flux values v[n][5] and
+ *   chi_k[n][3]. */
+int ora_record_stages(ora_ctx* c, double* buf);
+int ora_teno_bits(const ora_ctx* c, const double* Q, uint32_t* out);
+int ora_teno_values_n(const ora_ctx* c, const double* Q, const double* alpha, long n, const long* g, const int* m,
+                      const int* sd, double* v, double* chi);
+
 /* Scalar building blocks exposed for the pins. */
 double ora_delta4(double r);
 /* Reconstruction at a face from five upwind-ordered values. */
@@ -115,6 +129,8 @@ double ora_recon5(double a, double b, double cc, double d, double e, int scheme,
 /* TENO5 keep flags of one stencil (bit k set = sub-stencil k kept). */
 int ora_teno_flags(double a, double b, double cc, double d, double e,
                    double teno_ct, double teno_eps);
+/* The same for n stencils v[n][5] into out[n]. */
+int ora_teno_flags_n(const double* v, long n, double teno_ct, double teno_eps, int* out);
 /* Counter-based SplitMix64: output number ctr of the generator seeded with seed. */
 uint64_t ora_splitmix64(uint64_t seed, uint64_t ctr);
 

@@ -76,6 +76,10 @@ def lib():
         _lib.ora_marker_force.argtypes = [vp, dp]
         _lib.ora_get_state.argtypes = [vp, dp, dp, P(C.c_int64)]
         _lib.ora_set_state.argtypes = [vp, dp, d, i64]
+        _lib.ora_teno_flags_n.argtypes = [dp, C.c_long, d, d, vp]
+        _lib.ora_record_stages.argtypes = [vp, vp]
+        _lib.ora_teno_bits.argtypes = [vp, dp, vp]
+        _lib.ora_teno_values_n.argtypes = [vp, dp, dp, C.c_long, vp, vp, vp, dp, dp]
         _lib.ora_delta4.restype = d
         _lib.ora_delta4.argtypes = [d]
         _lib.ora_recon5.restype = d
@@ -121,6 +125,14 @@ def recon5(v, scheme="weno5js", weno_eps=1e-6, teno_ct=1e-6, teno_eps=1e-40):
 def teno_flags(v, teno_ct=1e-6, teno_eps=1e-40):
     a, b, c, d, e = (float(x) for x in v)
     return lib().ora_teno_flags(a, b, c, d, e, teno_ct, teno_eps)
+
+
+def teno_flags_n(V, teno_ct=1e-6, teno_eps=1e-40):
+    """teno_flags of every row of V [n][5]."""
+    V = np.ascontiguousarray(V, dtype=np.float64).reshape(-1, 5)
+    out = np.zeros(V.shape[0], dtype=np.int32)
+    lib().ora_teno_flags_n(_ptr(V), V.shape[0], teno_ct, teno_eps, out.ctypes.data)
+    return out
 
 
 def splitmix64(seed, ctr):
@@ -308,6 +320,40 @@ class Oracle:
         out = np.empty((self.dim, self.nm))
         self._check(lib().ora_marker_force(self.ctx, _ptr(out)), "marker_force")
         return out
+
+    # -- test hooks on the TENO5 decisions
+    def record_stages(self, on=True):
+        """While on, rk3_step copies each stage's input state into self.stage_states
+        [3][nq][...] (a fresh array per call of this method)."""
+        if on:
+            self.stage_states = np.zeros((3, self.nq) + self.shape)
+            lib().ora_record_stages(self.ctx, self.stage_states.ctypes.data)
+        else:
+            lib().ora_record_stages(self.ctx, None)
+
+    def face_counts(self):
+        n = list(self.case.n[: self.dim]) + [1] * (3 - self.dim)
+        return [int(np.prod([n[a] + (a == d) for a in range(3)])) for d in range(self.dim)]
+
+    def teno_bits(self, Q):
+        """Keep patterns of every face of Q (uint32, directions concatenated)."""
+        Q = self._state(Q)
+        out = np.zeros(sum(self.face_counts()), dtype=np.uint32)
+        self._check(lib().ora_teno_bits(self.ctx, _ptr(Q), out.ctypes.data), "teno_bits")
+        return out
+
+    def teno_values(self, Q, faces, comps, sides, alpha=None):
+        """For entries (face index in teno_bits' layout, component, side): the five split-flux
+        values [n][5] and chi [n][3], at Q's wave speeds (or the given alpha[3])."""
+        Q = self._state(Q)
+        a = _f64(self.alpha(Q) if alpha is None else alpha)
+        g = np.ascontiguousarray(faces, dtype=np.int64)
+        m = np.ascontiguousarray(comps, dtype=np.int32)
+        sd = np.ascontiguousarray(sides, dtype=np.int32)
+        v, chi = np.zeros((g.size, 5)), np.zeros((g.size, 3))
+        self._check(lib().ora_teno_values_n(self.ctx, _ptr(Q), _ptr(a), g.size, g.ctypes.data, m.ctypes.data,
+                                            sd.ctypes.data, _ptr(v), _ptr(chi)), "teno_values")
+        return v, chi
 
     def get_state(self):
         xi = np.empty((self.dim, max(self.nm, 1)))

@@ -106,6 +106,7 @@ struct fsa_ctx {
     int* hv_count = nullptr;
     long long* hv_offset = nullptr;
     long long* hv_total = nullptr;
+    unsigned* dbg_bits = nullptr;        // test read-out of the TENO5 keep patterns (or null)
     // kernel timing
     bool timing = false;
     std::vector<hipEvent_t> tev;   // pairs (start, stop) per timed launch
@@ -639,6 +640,14 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     S.dt = dt;
     S.mode_rhs = mode_rhs;
     S.step = c->step;
+    if (c->dbg_bits) {
+        const long long nx = c->G.n[0], ny = c->G.n[1], nz = c->G.n[2];
+        const long long fx = (nx + 1) * ny * nz, fy = nx * (ny + 1) * nz, fz = c->G.dim == 3 ? nx * ny * (nz + 1) : 0;
+        unsigned* b = c->dbg_bits + (stage > 0 ? stage - 1 : 0) * (fx + fy + fz);
+        S.dbg_x = b;
+        S.dbg_y = b + fx;
+        S.dbg_z = c->G.dim == 3 ? b + fx + fy : nullptr;
+    }
     // stage times of SSP-RK3 (t, t + dt, t + dt/2; a lone right-hand side at t)
     S.t = c->t + (stage == 2 ? dt : (stage == 3 ? 0.5 * dt : 0.0));
     if (c->G.dim == 3) {
@@ -716,6 +725,7 @@ int tune_ty(fsa_ctx* c, const StageArgs& S0)
     // partials), the work the height is chosen for; the output goes to a scratch buffer and
     // the partials are overwritten by the real launch
     StageArgs S = S0;
+    S.dbg_x = S.dbg_y = S.dbg_z = nullptr;
     S.mode_rhs = 0;
     S.Qn = S0.Qs;
     S.ca = 0.75;
@@ -1346,6 +1356,15 @@ int32_t fsa_diagnostics(fsa_ctx* c, const double* d_Q, double* h_totals, double*
         HIPCHK(c, hipMemcpyAsync(h_totals, c->tot_out, sizeof(double) * c->nq, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    return FSA_OK;
+}
+
+int32_t fsa_debug_teno_bits(fsa_ctx* c, uint32_t* d_bits)
+{
+    if (!c) return FSA_EINVAL;
+    if (d_bits && (c->d.scheme != FSA_TENO5 || c->d.precision != FSA_FP64))
+        return fail(c, FSA_EUNSUPPORTED, "the keep-pattern read-out is built for FP64 TENO5");
+    c->dbg_bits = d_bits;
     return FSA_OK;
 }
 

@@ -181,15 +181,47 @@ struct Recon {
     const double (*rows)[8];     // TENO5: keep-pattern table (LDS)
 };
 
-template <int SCHEME>
-__device__ __forceinline__ double recon5(double a, double b, double c, double d, double e, const Recon& R)
+// Jiang-Shu smoothness indicators of the three sub-stencils (FP64).
+__device__ __forceinline__ void js_beta(double a, double b, double c, double d, double e, double& b0, double& b1,
+                                        double& b2)
 {
     const double s0 = fma(-2.0, b, a) + c, t0 = fma(-4.0, b, a) + 3.0 * c;
     const double s1 = fma(-2.0, c, b) + d, t1 = b - d;
     const double s2 = fma(-2.0, d, c) + e, t2 = fma(-4.0, d, 3.0 * c) + e;
-    const double b0 = fma(13.0 / 12.0 * s0, s0, 0.25 * t0 * t0);
-    const double b1 = fma(13.0 / 12.0 * s1, s1, 0.25 * t1 * t1);
-    const double b2 = fma(13.0 / 12.0 * s2, s2, 0.25 * t2 * t2);
+    b0 = fma(13.0 / 12.0 * s0, s0, 0.25 * t0 * t0);
+    b1 = fma(13.0 / 12.0 * s1, s1, 0.25 * t1 * t1);
+    b2 = fma(13.0 / 12.0 * s2, s2, 0.25 * t2 * t2);
+}
+
+// TENO5 keep pattern (bit k = sub-stencil k kept) from the indicators: chi_k < C_T cuts,
+// tested as gamma_k < C_T sum gamma.
+__device__ __forceinline__ int teno_keep_beta(double b0, double b1, double b2, const Recon& R)
+{
+    const double tau = fabs(b0 - b2);
+    const double e0 = b0 + R.eps, e1 = b1 + R.eps, e2 = b2 + R.eps;
+    const double e01 = e0 * e1;
+    const double inv = rcp_nr(e01 * e2);
+    const double r0 = (e1 * e2) * inv, r1 = (e0 * e2) * inv, r2 = e01 * inv;  // 1 / e_k
+    const double x0 = fma(tau, r0, 1.0), x1 = fma(tau, r1, 1.0), x2 = fma(tau, r2, 1.0);
+    const double c0 = x0 * x0 * x0, c1 = x1 * x1 * x1, c2 = x2 * x2 * x2;
+    const double g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2;
+    const double lim = R.ct * (g0 + g1 + g2);
+    return (g0 < lim ? 0 : 1) | (g1 < lim ? 0 : 2) | (g2 < lim ? 0 : 4);
+}
+
+// TENO5 keep pattern of the five upwind-ordered values (what recon5<TENO5> decides).
+__device__ __forceinline__ int teno_keep5(double a, double b, double c, double d, double e, const Recon& R)
+{
+    double b0, b1, b2;
+    js_beta(a, b, c, d, e, b0, b1, b2);
+    return teno_keep_beta(b0, b1, b2, R);
+}
+
+template <int SCHEME>
+__device__ __forceinline__ double recon5(double a, double b, double c, double d, double e, const Recon& R)
+{
+    double b0, b1, b2;
+    js_beta(a, b, c, d, e, b0, b1, b2);
     if (SCHEME == WENO5JS) {
         const double q0 = fma(11.0 / 6.0, c, fma(-7.0 / 6.0, b, (1.0 / 3.0) * a));
         const double q1 = fma(1.0 / 3.0, d, fma(5.0 / 6.0, c, (-1.0 / 6.0) * b));
@@ -201,17 +233,7 @@ __device__ __forceinline__ double recon5(double a, double b, double c, double d,
         const double num = fma(w0, q0, fma(w1, q1, w2 * q2));
         return num * rcp_nr(w0 + w1 + w2);
     } else {
-        const double tau = fabs(b0 - b2);
-        const double e0 = b0 + R.eps, e1 = b1 + R.eps, e2 = b2 + R.eps;
-        const double e01 = e0 * e1;
-        const double inv = rcp_nr(e01 * e2);
-        const double r0 = (e1 * e2) * inv, r1 = (e0 * e2) * inv, r2 = e01 * inv;  // 1 / e_k
-        const double x0 = fma(tau, r0, 1.0), x1 = fma(tau, r1, 1.0), x2 = fma(tau, r2, 1.0);
-        const double c0 = x0 * x0 * x0, c1 = x1 * x1 * x1, c2 = x2 * x2 * x2;
-        const double g0 = c0 * c0, g1 = c1 * c1, g2 = c2 * c2;
-        const double lim = R.ct * (g0 + g1 + g2);
-        const int keep = (g0 < lim ? 0 : 1) | (g1 < lim ? 0 : 2) | (g2 < lim ? 0 : 4);
-        return keep_sum(R.rows[keep], a, b, c, d, e);
+        return keep_sum(R.rows[teno_keep_beta(b0, b1, b2, R)], a, b, c, d, e);
     }
 }
 

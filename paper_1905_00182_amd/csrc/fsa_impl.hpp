@@ -29,6 +29,10 @@ struct StageArgs {
                                            // FP32 deviation of rho, u, v, p of the cells written
     const double* ghosts;                  // 2D: inflow ghost table of this step (required when a
                                            // side is an inflow; see launch_inflow_ghosts2d)
+    unsigned* dbg_x;                       // if set (FP64 TENO5 only): the keep pattern of every
+    unsigned* dbg_y;                       // x, y (and z) face this launch reconstructs, bits
+    unsigned* dbg_z;                       // 3c+k (side +) and 16+3c+k (side -), face layout of
+                                           // launch_stage2d / launch_stage3d
 };
 
 // Arguments of the per-stage immersed-boundary kernel.

@@ -142,7 +142,7 @@ __device__ __forceinline__ bool wave_all_kept(unsigned word)
     else return false;
 }
 
-template <int SCHEME, class T>
+template <int SCHEME, class T, bool DBG = false>
 struct Column2D {
     static constexpr bool F64 = std::is_same<T, double>::value;
     // Rows of loads in flight ahead of their use: the FP32 forms have less arithmetic per row
@@ -199,6 +199,8 @@ struct Column2D {
     bool ib_on;                     // the force window is present and overlaps this strip
     double (*ring)[4][WAVE];        // LDS: the last five front rows of this wave, [slot][comp][lane]
     int lane;
+    unsigned* dbg_x;                // DBG (FP64 TENO5 only): the keep patterns of every x face
+    unsigned* dbg_y;                // [ny][nx+1] and y face [ny+1][nx] this stage decides
 
     // State of (this lane, row j): interior and periodic/zero-gradient ghosts are loads of
     // their resolved cell; inflow ghosts (an x ghost lane's column, or a whole y ghost row)
@@ -384,6 +386,18 @@ struct Column2D {
                     cy_new[c] = -(fh - fy_prev[c]) * inv_hT;
                     fy_prev[c] = fh;
                 }
+                if constexpr (DBG) {
+                    // the decisions recon5 took above, on the same values: face (Rw-3)+1/2 is
+                    // y face Rw-2
+                    unsigned word = 0u;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        word |= (unsigned)teno_keep5(fp[S0][c], fp[S4][c], fp[S3][c], fp[S2][c], fp[S1][c], R) << (3 * c);
+                        word |= (unsigned)teno_keep5(fm[S0][c], fm[S1][c], fm[S2][c], fm[S3][c], fm[S4][c], R)
+                                << (16 + 3 * c);
+                    }
+                    if (out_lane) dbg_y[(long long)(Rw - 2) * nx + i] = word;
+                }
             };
             if (wave_all_kept<SCHEME>(word_y)) yface(std::true_type{});
             else yface(std::false_type{});
@@ -429,6 +443,8 @@ struct Column2D {
                 const double F[4] = {qr[1], fma(qr[1], ur, pr), qr[2] * ur, (qr[3] + pr) * ur};
                 auto xface = [&](auto all_kept) {
                     float cp[4][5], cm[4][5];
+                    unsigned dword = 0u;
+                    (void)dword;
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         if (c == 0) face_rows<SCHEME, 0>(word_x, all_kept, R32.rows, cp, cm);
@@ -440,6 +456,16 @@ struct Column2D {
                         const T fh = recon_side<SCHEME, T>(lo1(pl1), pl1, fpx, pu1, up1(pu1), R, R32, cp[c]) +
                                      recon_side<SCHEME, T>(up1(mu2), mu2, mu1, fmx, ml1, R, R32, cm[c]);
                         L[c] = (double)(-(fh - lo1(fh)) * inv_hT);
+                        if constexpr (DBG) {
+                            // x face i+1 (right of this lane) of row r, decided above on the same
+                            // values
+                            dword |= (unsigned)teno_keep5(lo1(pl1), pl1, fpx, pu1, up1(pu1), R) << (3 * c);
+                            dword |= (unsigned)teno_keep5(up1(mu2), mu2, mu1, fmx, ml1, R) << (16 + 3 * c);
+                        }
+                    }
+                    if constexpr (DBG) {
+                        if ((out_lane || lane == HALO - 1) && i >= -1 && i + 1 <= nx)
+                            dbg_x[(long long)r * (nx + 1) + i + 1] = dword;
                     }
                 };
                 if (wave_all_kept<SCHEME>(word_x)) xface(std::true_type{});
@@ -539,7 +565,7 @@ __device__ __forceinline__ void set_issue_priority(int p)
     }
 }
 
-template <int SCHEME, class T>
+template <int SCHEME, class T, bool DBG = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_stage2d(
     const KConst* __restrict__ K, StageArgs A)
 {
@@ -548,8 +574,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         init_keep_rows<T>(keep_rows, threadIdx.x);
         __syncthreads();
     }
-    Column2D<SCHEME, T> C;
+    Column2D<SCHEME, T, DBG> C;
     C.K = K;
+    C.dbg_x = A.dbg_x;
+    C.dbg_y = A.dbg_y;
     C.Qs = A.Qs;
     C.Qn = A.Qn;
     C.out = A.out;
@@ -772,6 +800,10 @@ int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, co
     } else if (precision == 1) {
         if (scheme == TENO5) hipLaunchKernelGGL((k_stage2d<TENO5, float>), grid, block, 0, s, K, A);
         else hipLaunchKernelGGL((k_stage2d<WENO5JS, float>), grid, block, 0, s, K, A);
+    } else if (A.dbg_x) {
+        // the FP64 TENO5 kernel that also writes its keep patterns (test read-out)
+        if (scheme != TENO5 || !A.dbg_y) return (int)hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_stage2d<TENO5, double, true>), grid, block, 0, s, K, A);
     } else {
         if (scheme == TENO5) hipLaunchKernelGGL((k_stage2d<TENO5, double>), grid, block, 0, s, K, A);
         else hipLaunchKernelGGL((k_stage2d<WENO5JS, double>), grid, block, 0, s, K, A);

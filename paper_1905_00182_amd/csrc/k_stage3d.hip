@@ -187,10 +187,11 @@ __host__ __device__ __forceinline__ long long faces_of(const Grid& G)
 
 // Face fluxes along D: threads cover the faces f = 0..n_D along D (x index for D = 0, y index
 // for D = 1, z index for D = 2) and the cells of the two other directions.
-template <int SCHEME, class T, int D>
+// DBG (FP64 TENO5 only) also writes each face's keep patterns to dbg, in the face layout.
+template <int SCHEME, class T, int D, bool DBG = false>
 __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ K, const double* __restrict__ Q,
                                                      long long step, const unsigned long long* __restrict__ abits,
-                                                     T* __restrict__ Fh)
+                                                     T* __restrict__ Fh, unsigned* __restrict__ dbg)
 {
     constexpr bool F64 = std::is_same<T, double>::value;
     const Grid& G = K->G;
@@ -237,6 +238,9 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
     const double* Finf = D == 0 ? K->Fx_inf : (D == 1 ? K->Fy_inf : K->Fz_inf);
     const long long nf = faces_of<D>(G);
     const long long o = face_index<D>(G, f, D == 0 ? 0 : xi, D == 1 ? 0 : yi, D == 2 ? 0 : zi);
+    unsigned word = 0u;
+    (void)word;
+    (void)dbg;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         T fp[6], fm[6];
@@ -258,7 +262,12 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
         }
         Fh[c * nf + o] = rec<SCHEME>(fp[0], fp[1], fp[2], fp[3], fp[4], R, R32) +
                          rec<SCHEME>(fm[5], fm[4], fm[3], fm[2], fm[1], R, R32);
+        if constexpr (DBG) {
+            word |= (unsigned)teno_keep5(fp[0], fp[1], fp[2], fp[3], fp[4], R) << (3 * c);
+            word |= (unsigned)teno_keep5(fm[5], fm[4], fm[3], fm[2], fm[1], R) << (16 + 3 * c);
+        }
     }
+    if constexpr (DBG) dbg[o] = word;
 }
 
 template <class T>
@@ -422,17 +431,26 @@ static void launch_faces(const KConst* K, const Grid& G, const StageArgs& A, T* 
     T* Fx = F;
     T* Fy = Fx + 5 * faces_of<0>(G);
     T* Fz = Fy + 5 * faces_of<1>(G);
-    hipLaunchKernelGGL((k_faces3d<SCHEME, T, 0>), dim3((G.n[0] + 1 + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]),
-                       block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx);
-    hipLaunchKernelGGL((k_faces3d<SCHEME, T, 1>), dim3((G.n[0] + BX - 1) / BX, (G.n[1] + 1 + BY - 1) / BY, G.n[2]),
-                       block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fy);
-    hipLaunchKernelGGL((k_faces3d<SCHEME, T, 2>), dim3((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2] + 1),
-                       block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fz);
+    const dim3 gx((G.n[0] + 1 + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
+    const dim3 gy((G.n[0] + BX - 1) / BX, (G.n[1] + 1 + BY - 1) / BY, G.n[2]);
+    const dim3 gz((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2] + 1);
+    if constexpr (SCHEME == TENO5 && std::is_same<T, double>::value) {
+        if (A.dbg_x) {
+            hipLaunchKernelGGL((k_faces3d<SCHEME, T, 0, true>), gx, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, A.dbg_x);
+            hipLaunchKernelGGL((k_faces3d<SCHEME, T, 1, true>), gy, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fy, A.dbg_y);
+            hipLaunchKernelGGL((k_faces3d<SCHEME, T, 2, true>), gz, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fz, A.dbg_z);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_faces3d<SCHEME, T, 0>), gx, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, nullptr);
+    hipLaunchKernelGGL((k_faces3d<SCHEME, T, 1>), gy, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fy, nullptr);
+    hipLaunchKernelGGL((k_faces3d<SCHEME, T, 2>), gz, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fz, nullptr);
 }
 
 int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, void* stress,
                    void* faces, hipStream_t s)
 {
+    if (A.dbg_x && (scheme != TENO5 || precision != 0 || !A.dbg_y || !A.dbg_z)) return (int)hipErrorInvalidValue;
     const dim3 block(BX * BY);
     const dim3 gs((G.n[0] + 4 + BX - 1) / BX, (G.n[1] + 4 + BY - 1) / BY, (G.n[2] + 4 + SZ - 1) / SZ);
     const dim3 gr((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);

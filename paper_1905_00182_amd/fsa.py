@@ -132,6 +132,7 @@ _SIGS = {
     "fsa_harvest": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_uint64, C.c_int64, C.c_void_p, C.c_void_p,
                                 C.POINTER(C.c_int64)]),
     "fsa_face_flags": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fsa_debug_teno_bits": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fsa_timing_enable": (C.c_int32, [C.c_void_p, C.c_int32]),
     "fsa_timing_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "fsa_sync": (C.c_int32, [C.c_void_p]),
@@ -550,6 +551,24 @@ class Solver:
         fy = t.empty((ny + 1, nx), dtype=t.int32, device=Q.device)
         self._check(lib().fsa_face_flags(self.ctx, _ptr(self._state(Q)), _ptr(fx), _ptr(fy)))
         return fx, fy
+
+    def face_counts(self):
+        """Faces per direction: x, y (and z)."""
+        nx, ny, nz = self.case.n[0], self.case.n[1], self.case.n[2] if self.dim == 3 else 1
+        fc = [(nx + 1) * ny * nz, nx * (ny + 1) * nz]
+        return fc + ([nx * ny * (nz + 1)] if self.dim == 3 else [])
+
+    def debug_teno_bits(self, on=True):
+        """Turn the TENO5 keep-pattern read-out on (returns its device buffer [3][faces],
+        int32 words) or off (fsa_debug_teno_bits)."""
+        t = self.torch
+        if not on:
+            self._check(lib().fsa_debug_teno_bits(self.ctx, None))
+            self._dbg = None
+            return None
+        self._dbg = t.zeros((3, sum(self.face_counts())), dtype=t.int32, device=self.device)
+        self._check(lib().fsa_debug_teno_bits(self.ctx, _ptr(self._dbg)))
+        return self._dbg
 
     def timing(self, on=True):
         self._check(lib().fsa_timing_enable(self.ctx, 1 if on else 0))

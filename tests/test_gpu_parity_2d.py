@@ -110,7 +110,7 @@ def test_inflow_every_side(torch_cuda):
     _assert_q_close(Qg, Qo, Q0, case)
 
 
-@pytest.mark.parametrize("scheme,nsteps,resume", [("weno5js", 20, True), ("teno5", 3, False)])
+@pytest.mark.parametrize("scheme,nsteps,resume", [("weno5js", 20, True), ("teno5", 3, False), ("teno5", 20, True)])
 def test_flapping_plate_moving_markers(torch_cuda, scheme, nsteps, resume):
     """The rigid flapping plate in a stream (prescribed heave and pitch of its clamped leading
     edge): the markers move every step, positions and velocities set before each step on both
@@ -139,12 +139,13 @@ def test_flapping_plate_moving_markers(torch_cuda, scheme, nsteps, resume):
     assert np.abs(Qo[1:3] - Q0[1:3]).max() > 1e-4   # the plate has stirred the stream
 
 
-def test_hovering_insect_moving_markers(torch_cuda):
+@pytest.mark.parametrize("scheme", ["weno5js", "teno5"])
+def test_hovering_insect_moving_markers(torch_cuda, scheme):
     """The hovering insect: body and two flapping wings (309 markers, the wings' moved every
     step on both sides) in a quiescent gas, against the oracle with the marker forces."""
-    case = W.insect(n=192, L=3.84, sponge=0.5, nprobe=0, scheme="weno5js")
+    case = W.insect(n=192, L=3.84, sponge=0.5, nprobe=0, scheme=scheme)
     Q0 = W.uniform_state(case)
-    _say("hovering insect x 15")
+    _say("hovering insect x 15", scheme)
     s = _solver(case)
     o = _oracle(case)
     Qg = torch_cuda.from_numpy(Q0.copy()).cuda()
@@ -159,8 +160,12 @@ def test_hovering_insect_moving_markers(torch_cuda):
             s.rk3_step(Qg, case.dt)
         o.rk3_step(Qo, case.dt)
     s.sync()
-    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
-    np.testing.assert_allclose(s.marker_force(), o.marker_force(), rtol=1e-9, atol=1e-12)
+    if scheme == "teno5":
+        _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case, tol=TENO_TIE_TOL, tol_elem=TENO_TIE_ELEM)
+        np.testing.assert_allclose(s.marker_force(), o.marker_force(), rtol=1e-6, atol=1e-9)
+    else:
+        _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
+        np.testing.assert_allclose(s.marker_force(), o.marker_force(), rtol=1e-9, atol=1e-12)
     assert np.abs(Qo[1:3]).max() > 1e-5     # the wings have set the gas moving
 
 
@@ -288,22 +293,48 @@ def natural_scale(case):
     return [rho] + [rho * (c + abs(x)) for x in u] + [E]
 
 
-def _assert_q_close(Qg, Qo, Q0, case, tol=1e-12):
+# Element-wise bound: max |Q_gpu - Q_ora| per component within TOL_ELEM of that component's
+# largest change over the run, max |Q_ora - Q0|, plus ELEM_ULPS ulps of its natural size
+# (differences below the state's own last bits are the rounding of representing it).
+TOL_ELEM = 1e-10
+ELEM_ULPS = 32
+
+# Bounds of TENO5 runs in which tie decisions matter.  test_gpu_teno_ties.py shows, on every
+# stage input of such runs, that the library's sub-stencil choices differ from the oracle's
+# only at ties: stencils flat to rounding, or choices the oracle itself makes within a few
+# ulps of the same values.  Where a tie sits on a signal above rounding (the tails of a pulse,
+# the wake of flapping wings), the two sides then follow different, equally correct,
+# choices there, and the local difference is a fraction of that signal: observed up to
+# 7.5e-7 of a run's largest change (hovering insect, 15 steps) and 6.7e-10 in relative L2.
+TENO_TIE_TOL = 1e-9       # whole state and per component, relative L2
+TENO_TIE_ELEM = 1e-5      # element-wise, of the component's largest change over the run
+
+
+def _assert_q_close(Qg, Qo, Q0, case, tol=1e-12, tol_elem=TOL_ELEM):
+    """Whole-state and per-component relative L2 <= tol (per component against its natural
+    size where the component is itself a small fluctuation), and element-wise against the
+    change from the initial state (TOL_ELEM above)."""
     whole = np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo)
     _say(f"  whole state: rel L2 {whole:.3e}")
     scale = natural_scale(case)
-    rels = []
+    rels, elems = [], []
+    eps = np.finfo(np.float64).eps
     for c in range(Qo.shape[0]):
         ref = max(np.linalg.norm(Qo[c]), scale[c] * np.sqrt(Qo[c].size))
         rel = np.linalg.norm(Qg[c] - Qo[c]) / ref
         d = np.abs(Qg[c] - Qo[c])
         at = np.unravel_index(np.argmax(d), d.shape)
         dev = np.abs(Qo[c] - Q0[c]).max()
-        _say(f"  comp {c}: rel L2 {rel:.3e}; max|dQ| {d.max():.3e} at {tuple(int(x) for x in at)} of change {dev:.3e}")
+        bound = tol_elem * dev + ELEM_ULPS * eps * scale[c]
+        _say(f"  comp {c}: rel L2 {rel:.3e}; max|dQ| {d.max():.3e} at {tuple(int(x) for x in at)} of change "
+             f"{dev:.3e} (ratio {d.max() / max(dev, 1e-300):.2e}; element bound {bound:.2e})")
         rels.append(rel)
+        elems.append((d.max(), bound))
     assert whole <= tol
     for c, rel in enumerate(rels):
         assert rel <= tol, (c, rel)
+    for c, (dm, bound) in enumerate(elems):
+        assert dm <= bound, (c, dm, bound)
 
 
 def test_rk3_config1_full(torch_cuda):

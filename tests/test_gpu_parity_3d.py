@@ -10,7 +10,7 @@ import pytest
 
 from paper_1905_00182_amd import workloads as W
 
-from test_gpu_parity_2d import _assert_q_close, _compare_rhs, _oracle, _say, _solver
+from test_gpu_parity_2d import TENO_TIE_ELEM, TENO_TIE_TOL, _assert_q_close, _compare_rhs, _oracle, _say, _solver
 
 pytestmark = pytest.mark.gpu
 
@@ -159,24 +159,15 @@ def test_rk3_config3_miniature_teno_smooth_state(torch_cuda):
 
 
 def test_rk3_config3_miniature_teno_pulse(torch_cuda):
-    """TENO5 on the pulse state.  One step meets 1e-12.  Over 30 steps the two sides part by
-    more: the Gaussian's tails reach the ambient state's last bits, where the five values of a
-    stencil differ by a few ulps, and TENO5's cut-off (epsilon 1e-40, scale invariant) then
-    decides on rounding noise -- noise that the two sides produce differently (operation order,
-    contraction, reciprocals).  The WENO5-JS run of the same case, which has no discrete
-    decision, matches to 1e-15 over the same 30 steps.  Bound for these decisions on noise:
-    whole-state relative L2 <= 1e-10 and the probe pressure to 1e-6 of its amplitude."""
+    """TENO5 on the pulse state: one step to 1e-12 in relative L2; 30 steps to the tie bounds
+    (TENO_TIE_*: the decisions are checked on the same run's stage inputs in
+    test_gpu_teno_ties.py), with the probe pressure to 1e-6 of its amplitude."""
     case = W.config3(n=48, scheme="teno5", nmark=2000)
     Q0 = W.config3_state(case)
     s, o, Qg, Qo = _steps3(torch_cuda, case, Q0, 1)
-    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
+    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case, tol_elem=TENO_TIE_ELEM)
     s, o, Qg, Qo = _steps3(torch_cuda, case, Q0, 30)
-    try:
-        _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
-    except AssertionError:
-        pass
-    whole = np.linalg.norm(Qg.cpu().numpy() - Qo) / np.linalg.norm(Qo)
-    assert whole <= 1e-10
+    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case, tol=TENO_TIE_TOL, tol_elem=TENO_TIE_ELEM)
     dpg = s.probe_dp(Qg).cpu().numpy()
     dpo = o.probe_dp(Qo)
     _say(f"  probes: max |dp_gpu - dp_ora| = {np.abs(dpg - dpo).max():.3e} of amplitude {np.abs(dpo).max():.3e}")
@@ -185,11 +176,16 @@ def test_rk3_config3_miniature_teno_pulse(torch_cuda):
 
 @pytest.mark.parametrize("scheme", ["teno5", "weno5js"])
 def test_config3_full_size(torch_cuda, scheme):
-    """The 256^3 sphere case with 10^4 markers, one step, whole state against the oracle."""
+    """The 256^3 sphere case with 10^4 markers, one step, whole state against the oracle
+    (relative L2 1e-12; TENO5 element-wise to the tie bound: a tie in the pulse's far tail,
+    where the signal is 1e-11 of the state, already decides differently in one step)."""
     case = W.config3(n=256, scheme=scheme)
     Q0 = W.config3_state(case)
     s, o, Qg, Qo = _steps3(torch_cuda, case, Q0, 1)
-    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
+    if scheme == "teno5":
+        _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case, tol_elem=TENO_TIE_ELEM)
+    else:
+        _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
 
 
 def test_precision3d_rhs_config4_full_size_sampled(torch_cuda):
