@@ -66,25 +66,50 @@ def traffic_from_profile(launch_cells):
         return None
 
 
-def cpu_baseline(case, steps):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(case, steps, steps_1t=1):
+    """The FP64 CPU oracle on this host: `steps` SSP-RK3 steps of the case with every core's
+    OpenMP thread, then `steps_1t` with one thread (each after a warm-up step)."""
     from oracle import oracle as ora
     from paper_1905_00182_amd import workloads as W
 
     Q = W.config2_state(case)
     o = ora.Oracle(case)
+    threads = ora.threads()
     o.rk3_step(Q, case.dt)            # warm-up step (page-in, thread start)
     t0 = time.perf_counter()
     for _ in range(steps):
         o.rk3_step(Q, case.dt)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    one = None
+    if steps_1t > 0:
+        ora.threads(1)
+        o.rk3_step(Q, case.dt)
+        t1 = time.perf_counter()
+        for _ in range(steps_1t):
+            o.rk3_step(Q, case.dt)
+        dt1 = time.perf_counter() - t1
+        ora.threads(threads)
+        one = {"value": round(case.ncell * 3 * steps_1t / dt1 / 1e6, 3), "cores": 1,
+               "sample": f"{steps_1t} step(s) after one warm-up step ({dt1:.1f} s)"}
     return {
         "value": case.ncell * 3 * steps / dt / 1e6,
         "unit": "Mcell-stage/s",
         "cores": threads,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
         "sample": f"{steps} SSP-RK3 steps of the same {case.n[0]}x{case.n[1]} case after one warm-up step "
                   f"({dt:.1f} s, FP64 C oracle, OpenMP)",
+        "one_thread": one,
     }
 
 

@@ -26,6 +26,7 @@
 #include "ora.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -624,6 +625,78 @@ static void sources_at(const ora_ctx* c, const double* Q, const double* fib, lon
     if (c->d.src_amp != 0.0) out[dim + 1] += pressure_source(c, n, c->t) / (c->d.gamma - 1.0);
 }
 
+/* Non-reflecting boundary of Thompson (1987, 1990), the far-field treatment Sec. 2 applies:
+ * at the boundary cell of a NONREFLECT side, the convective term along the boundary normal d
+ * is replaced by its characteristic (locally one-dimensional) form, with the amplitudes of
+ * the waves that enter the domain set to zero.  With primitives (rho, u_a, p), u_n = u_d,
+ * c = sqrt(gamma p / rho) and one-sided second-order derivatives along d (the boundary cell
+ * and the next two inward),
+ *   L1 = (u_n - c)(p' - rho c u_n'),   L2 = u_n (c^2 rho' - p'),   L_a = u_n u_a' (a != d),
+ *   L5 = (u_n + c)(p' + rho c u_n');
+ * a wave whose speed points into the domain (negative at the high side, positive at the low
+ * side) has its L set to zero.  Then
+ *   d1 = (L2 + (L5 + L1)/2) / c^2,  d2 = (L5 + L1)/2,  dn = (L5 - L1)/(2 rho c),  d_a = L_a,
+ * and the normal flux derivative dF/dx_d of the conserved variables is
+ *   [d1,  u_d d1 + rho dn,  u_a d1 + rho d_a,  |u|^2/2 d1 + d2/(gamma-1) + rho u_d dn + sum_a rho u_a d_a];
+ * out receives its negative (the convective term). */
+static void nrbc_conv(const ora_ctx* c, const double* Q, int d, int side, const long* idx, double* out)
+{
+    int dim = c->d.dim;
+    double rho[3], u[3][3], p[3];
+    for (int s = 0; s < 3; ++s) {
+        long id[3] = {idx[0], idx[1], idx[2]};
+        id[d] += side == 0 ? s : -s;
+        double q[5];
+        for (int m = 0; m < c->nq; ++m) q[m] = Q[(long)m * c->ncell + cell_index(c, id[0], id[1], id[2])];
+        rho[s] = q[0];
+        primitives(c, q, u[s], &p[s]);
+    }
+    /* one-sided derivative along +x_d: (-3 f0 + 4 f1 - f2) / 2h at the low side, where f1, f2
+     * lie inward (+x_d); at the high side they lie toward -x_d, which flips the sign.  Written
+     * as (4 (f1 - f0) - (f2 - f0)) / 2h so that constant data give exactly zero. */
+    double sg = side == 0 ? 1.0 : -1.0;
+    double h2 = 2.0 * c->d.h;
+#define ONE_SIDED(f0, f1, f2) (sg * (4.0 * ((f1) - (f0)) - ((f2) - (f0))) / h2)
+    double drho = ONE_SIDED(rho[0], rho[1], rho[2]);
+    double dp = ONE_SIDED(p[0], p[1], p[2]);
+    double du[3];
+    for (int a = 0; a < dim; ++a) du[a] = ONE_SIDED(u[0][a], u[1][a], u[2][a]);
+#undef ONE_SIDED
+    double r = rho[0], un = u[0][d];
+    double cs = sqrt(c->d.gamma * p[0] / r);
+    double lam1 = un - cs, lam2 = un, lam5 = un + cs;
+    double L1 = lam1 * (dp - r * cs * du[d]);
+    double L2 = lam2 * (cs * cs * drho - dp);
+    double L5 = lam5 * (dp + r * cs * du[d]);
+    double La[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < dim; ++a)
+        if (a != d) La[a] = lam2 * du[a];
+    /* incoming waves carry nothing in */
+    int in_high = side == 1;
+    if (in_high ? lam1 < 0.0 : lam1 > 0.0) L1 = 0.0;
+    if (in_high ? lam2 < 0.0 : lam2 > 0.0) {
+        L2 = 0.0;
+        for (int a = 0; a < 3; ++a) La[a] = 0.0;
+    }
+    if (in_high ? lam5 < 0.0 : lam5 > 0.0) L5 = 0.0;
+    double d1 = (L2 + 0.5 * (L5 + L1)) / (cs * cs);
+    double d2 = 0.5 * (L5 + L1);
+    double dn = (L5 - L1) / (2.0 * r * cs);
+    double ke = 0.0;
+    for (int a = 0; a < dim; ++a) ke += u[0][a] * u[0][a];
+    out[0] = -d1;
+    double e = 0.5 * ke * d1 + d2 / (c->d.gamma - 1.0) + r * un * dn;
+    for (int a = 0; a < dim; ++a) {
+        if (a == d) {
+            out[1 + a] = -(un * d1 + r * dn);
+        } else {
+            out[1 + a] = -(u[0][a] * d1 + r * La[a]);
+            e += r * u[0][a] * La[a];
+        }
+    }
+    out[dim + 1] = -e;
+}
+
 static int conv_on(const ora_ctx* c, int d) { return (c->d.terms >> d) & 1; }
 static int visc_on(const ora_ctx* c) { return (c->d.terms & ORA_VISC) && c->d.mu != 0.0; }
 
@@ -661,6 +734,14 @@ int ora_rhs(ora_ctx* c, const double* Q, double* L)
                 long idx[3] = {base[0], base[1], base[2]};
                 idx[d] = i;
                 long n = cell_index(c, idx[0], idx[1], idx[2]);
+                int side = (i == 0 && c->d.bc[d][0] == ORA_BC_NONREFLECT) ? 0
+                           : ((i == nd - 1 && c->d.bc[d][1] == ORA_BC_NONREFLECT) ? 1 : -1);
+                if (side >= 0 && nd >= 3) {
+                    double cv[5];
+                    nrbc_conv(c, Q, d, side, idx, cv);
+                    for (int m = 0; m < nq; ++m) L[(long)m * nc + n] += cv[m];
+                    continue;
+                }
                 for (int m = 0; m < nq; ++m)
                     L[(long)m * nc + n] += -(Fh[(i + 1) * nq + m] - Fh[i * nq + m]) / c->d.h;
             }
@@ -745,6 +826,15 @@ int ora_rhs_cells(ora_ctx* c, const double* Q, int64_t nlist, const int64_t* cel
         double acc[5] = {0, 0, 0, 0, 0};
         for (int d = 0; d < dim; ++d) {
             if (!conv_on(c, d)) continue;
+            long nd = n_of(c, d);
+            int side = (idx[d] == 0 && c->d.bc[d][0] == ORA_BC_NONREFLECT) ? 0
+                       : ((idx[d] == nd - 1 && c->d.bc[d][1] == ORA_BC_NONREFLECT) ? 1 : -1);
+            if (side >= 0 && nd >= 3) {
+                double cv[5];
+                nrbc_conv(c, Q, d, side, idx, cv);
+                for (int m = 0; m < nq; ++m) acc[m] += cv[m];
+                continue;
+            }
             double Fr[5], Fl[5];
             long id[3] = {idx[0], idx[1], idx[2]};
             face_flux(c, Q, d, id, alpha[d], Fr);
@@ -964,6 +1054,13 @@ int ora_rk3_step(ora_ctx* c, double* Q, double dt)
 /* ------------------------------------------------------------------------------------ */
 /* Test hooks on the TENO5 decisions (they compute nothing the solver uses)               */
 /* ------------------------------------------------------------------------------------ */
+
+/* Threads of the OpenMP loops (n < 1: leave as is); returns the count in effect. */
+int ora_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
 
 int ora_record_stages(ora_ctx* c, double* buf)
 {

@@ -25,7 +25,7 @@
 extern "C" {
 #endif
 
-enum { ORA_BC_PERIODIC = 0, ORA_BC_EXTRAP = 1, ORA_BC_INFLOW = 2 };
+enum { ORA_BC_PERIODIC = 0, ORA_BC_EXTRAP = 1, ORA_BC_INFLOW = 2, ORA_BC_NONREFLECT = 3 };
 enum { ORA_WENO5JS = 0, ORA_TENO5 = 1 };
 enum { ORA_STATIC = 0, ORA_ROTATING = 1, ORA_EXTERNAL = 2 };
 /* Terms of the right-hand side that are evaluated (bit mask). */
@@ -117,6 +117,8 @@ int ora_face_significant(const ora_ctx* c, const double* Q, int dir, long i, lon
  *   the wave speeds alpha[3], the five upwind-ordered split-flux values v[n][5] and
  *   chi_k[n][3]. */
 int ora_record_stages(ora_ctx* c, double* buf);
+/* Threads of the oracle's OpenMP loops (n < 1: unchanged); returns the count in effect. */
+int ora_threads(int n);
 int ora_teno_bits(const ora_ctx* c, const double* Q, uint32_t* out);
 int ora_teno_values_n(const ora_ctx* c, const double* Q, const double* alpha, long n, const long* g, const int* m,
                       const int* sd, double* v, double* chi);

@@ -12,7 +12,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libora.so")
 
-BC = {"periodic": 0, "extrap": 1, "inflow": 2}
+BC = {"periodic": 0, "extrap": 1, "inflow": 2, "nonreflect": 3}
 SCHEME = {"weno5js": 0, "teno5": 1}
 MOTION = {"static": 0, "rotating": 1, "external": 2}
 TERMS = {"conv_x": 1, "conv_y": 2, "conv_z": 4, "visc": 8, "ib": 16, "sponge": 32, "all": 63}
@@ -77,6 +77,7 @@ def lib():
         _lib.ora_get_state.argtypes = [vp, dp, dp, P(C.c_int64)]
         _lib.ora_set_state.argtypes = [vp, dp, d, i64]
         _lib.ora_teno_flags_n.argtypes = [dp, C.c_long, d, d, vp]
+        _lib.ora_threads.argtypes = [C.c_int]
         _lib.ora_record_stages.argtypes = [vp, vp]
         _lib.ora_teno_bits.argtypes = [vp, dp, vp]
         _lib.ora_teno_values_n.argtypes = [vp, dp, dp, C.c_long, vp, vp, vp, dp, dp]
@@ -125,6 +126,11 @@ def recon5(v, scheme="weno5js", weno_eps=1e-6, teno_ct=1e-6, teno_eps=1e-40):
 def teno_flags(v, teno_ct=1e-6, teno_eps=1e-40):
     a, b, c, d, e = (float(x) for x in v)
     return lib().ora_teno_flags(a, b, c, d, e, teno_ct, teno_eps)
+
+
+def threads(n=0):
+    """Set the oracle's OpenMP thread count (n >= 1) and return the count in effect."""
+    return lib().ora_threads(int(n))
 
 
 def teno_flags_n(V, teno_ct=1e-6, teno_eps=1e-40):
