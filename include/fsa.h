@@ -62,8 +62,11 @@ enum {
     FSA_EUNSUPPORTED = -6
 };
 
-/* Boundary conditions per direction and side. */
-enum { FSA_BC_PERIODIC = 0, FSA_BC_EXTRAP = 1, FSA_BC_INFLOW = 2 };
+/* Boundary conditions per direction and side.  NONREFLECT is the non-reflecting boundary of
+ * Thompson (1987, 1990) that Sec. 2 applies on the outer boundaries: ghosts as EXTRAP for the
+ * stencils, and at the boundary cell the convective term along the boundary normal in its
+ * characteristic form with the amplitudes of incoming waves set to zero (see fsa_desc). */
+enum { FSA_BC_PERIODIC = 0, FSA_BC_EXTRAP = 1, FSA_BC_INFLOW = 2, FSA_BC_NONREFLECT = 3 };
 /* Convective reconstruction. */
 enum { FSA_WENO5JS = 0, FSA_TENO5 = 1 };
 /* Arithmetic of the face reconstruction and viscous fluxes (the state is always FP64):
@@ -88,7 +91,17 @@ enum {
  * of the nearest interior cell.  Directions are resolved in the order x, y, z.
  *
  * Sponge: S = -sigma(x) (Q - Q_inf), sigma = sponge_sigma * eta^3, eta = max over
- * directions of (depth into the layer) / (layer width), clipped to 1. */
+ * directions of (depth into the layer) / (layer width), clipped to 1.
+ *
+ * Non-reflecting side (FSA_BC_NONREFLECT, a direction with at least 3 cells): at its boundary
+ * cell, with primitives rho, u, p, c = sqrt(gamma p / rho), u_n the normal velocity and
+ * one-sided derivatives along the normal from the boundary cell and the next two inward,
+ * (4 (f1 - f0) - (f2 - f0)) / 2h pointing outward-in, the wave amplitudes
+ * L1 = (u_n - c)(p' - rho c u_n'), L2 = u_n (c^2 rho' - p'), L_t = u_n u_t' (tangential),
+ * L5 = (u_n + c)(p' + rho c u_n') are zeroed where their speed points into the domain, and
+ * the normal flux derivative is [d1, u d1 + rho (dn e_n + d_t e_t), |u|^2/2 d1 + d2/(gamma-1)
+ * + rho (u_n dn + u_t d_t)] with d1 = (L2 + (L5+L1)/2)/c^2, d2 = (L5+L1)/2,
+ * dn = (L5-L1)/(2 rho c), d_t = L_t.  Computed in FP64 in every form. */
 typedef struct fsa_desc {
     int32_t  dim;                 /* 2 or 3 */
     int32_t  n[3];                /* cells per direction; n[2] = 1 in 2D */

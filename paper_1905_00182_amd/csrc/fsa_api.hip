@@ -237,7 +237,11 @@ int validate(const fsa_desc* d, std::string& why)
     for (int k = 0; k < 3; ++k)
         for (int s = 0; s < 2; ++s) {
             if (k >= d->dim) continue;
-            if (d->bc[k][s] < FSA_BC_PERIODIC || d->bc[k][s] > FSA_BC_INFLOW) { why = "bad bc"; return FSA_EINVAL; }
+            if (d->bc[k][s] < FSA_BC_PERIODIC || d->bc[k][s] > FSA_BC_NONREFLECT) { why = "bad bc"; return FSA_EINVAL; }
+            if (d->bc[k][s] == FSA_BC_NONREFLECT && d->n[k] < 3) {
+                why = "a non-reflecting side needs at least 3 cells along its normal";
+                return FSA_EINVAL;
+            }
             if ((d->bc[k][0] == FSA_BC_PERIODIC) != (d->bc[k][1] == FSA_BC_PERIODIC)) {
                 why = "periodic must be set on both sides";
                 return FSA_EINVAL;
@@ -543,6 +547,33 @@ IBArgs ib_args(const fsa_ctx* c)
 
 bool ib_active(const fsa_ctx* c) { return (c->d.terms & FSA_TERM_IB) && c->nm > 0; }
 
+// Non-reflecting sides as a bit mask (bit 2d+s), 0 for none.
+int nrbc_mask(const fsa_ctx* c)
+{
+    int m = 0;
+    for (int d = 0; d < c->d.dim; ++d)
+        for (int s = 0; s < 2; ++s)
+            if (c->d.bc[d][s] == FSA_BC_NONREFLECT) m |= 1 << (2 * d + s);
+    return m;
+}
+
+// After a stage kernel with non-reflecting sides: their characteristic terms, then the
+// wave speeds of the corrected output into slot acc (the stage kernel took none).
+int finish_nrbc(fsa_ctx* c, const StageArgs& S, int acc)
+{
+    for (int d = 0; d < c->d.dim; ++d)
+        for (int side = 0; side < 2; ++side)
+            if ((S.nrbc >> (2 * d + side)) & 1 && (c->d.terms & (FSA_TERM_CONV_X << d))) {
+                int e = launch_nrbc(c->dK, c->G, d, side, S, c->stream);
+                if (e) return hipcheck(c, (hipError_t)e, "non-reflecting boundary launch");
+            }
+    if (acc >= 0) {
+        int e = launch_alpha(c->G, c->P, S.out, c->apart, c->abits + 3 * acc, c->stream);
+        if (e) return hipcheck(c, (hipError_t)e, "alpha reduction launch");
+    }
+    return FSA_OK;
+}
+
 // One right-hand-side evaluation on Qs: (optionally) the wave-speed reduction of Qs into
 // slot `in`, the penalty step, and the fused stencil/update kernel, which reads slot `in`,
 // writes the wave speeds of its output into slot `acc` (per-wave partials, then a one-block
@@ -629,7 +660,9 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     S.flags_x = c->flags_x;
     S.flags_y = c->flags_y;
     S.alpha_bits = bits;
-    S.alpha_part = acc >= 0 ? c->apart : nullptr;
+    S.nrbc = nrbc_mask(c);
+    // (non-reflecting sides: the wave speeds come from the corrected output, finish_nrbc)
+    S.alpha_part = (acc >= 0 && !S.nrbc) ? c->apart : nullptr;
     S.fwin = ib_active(c) ? c->fwin : nullptr;
     for (int k = 0; k < 3; ++k) {
         S.wlo[k] = c->wlo[k];
@@ -660,6 +693,7 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
         e = launch_stage3d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stress3d, c->faces3d, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "3D stage launch");
         if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
+        if (S.nrbc) return finish_nrbc(c, S, acc);
         if (acc >= 0) defer_alpha_final(c, stage3d_blocks(c->G), acc);
         return FSA_OK;
     }
@@ -685,7 +719,7 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     }
     // learned form: the stage output's deviation ranges, for the next flags pass (only from a
     // stage whose output a flags pass reads: with the selector once per step, the last one)
-    S.qrange = (c->d.precision == FSA_LEARNED32 && acc >= 0 && (c->d.selector_stride != 3 || stage == 3))
+    S.qrange = (c->d.precision == FSA_LEARNED32 && acc >= 0 && !S.nrbc && (c->d.selector_stride != 3 || stage == 3))
                    ? c->qrange
                    : nullptr;
     e = launch_stage2d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stream);
@@ -693,6 +727,7 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
     c->qrange_of = S.qrange ? out : nullptr;
     c->qrange_ty = S.ty;
+    if (S.nrbc) return finish_nrbc(c, S, acc);
     if (acc >= 0) defer_alpha_final(c, stage2d_waves(c->G, S.ty), acc);
     return FSA_OK;
 }

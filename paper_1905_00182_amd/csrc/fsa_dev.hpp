@@ -8,7 +8,7 @@
 
 namespace fsa {
 
-enum : int { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_INFLOW = 2 };
+enum : int { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_INFLOW = 2, BC_NONREFLECT = 3 };
 enum : int { WENO5JS = 0, TENO5 = 1, LEARNED = 2 };
 enum : int { T_CONVX = 1, T_CONVY = 2, T_CONVZ = 4, T_VISC = 8, T_IB = 16, T_SPONGE = 32 };
 

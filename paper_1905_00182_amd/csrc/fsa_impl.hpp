@@ -29,6 +29,10 @@ struct StageArgs {
                                            // FP32 deviation of rho, u, v, p of the cells written
     const double* ghosts;                  // 2D: inflow ghost table of this step (required when a
                                            // side is an inflow; see launch_inflow_ghosts2d)
+    int nrbc;                              // bit 2d+s: side s of direction d is non-reflecting; the
+                                           // stage kernels leave out the convective term along d
+                                           // at its boundary cells (launch_nrbc adds its
+                                           // characteristic form)
     unsigned* dbg_x;                       // if set (FP64 TENO5 only): the keep pattern of every
     unsigned* dbg_y;                       // x, y (and z) face this launch reconstructs, bits
     unsigned* dbg_z;                       // 3c+k (side +) and 16+3c+k (side -), face layout of
@@ -67,6 +71,10 @@ struct IBArgs {
 };
 
 int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, hipStream_t s);
+// Non-reflecting side `side` (0 low, 1 high) of direction d: at its boundary cells, out +=
+// cb dt C (mode_rhs: out += C), C the characteristic form of the convective term along d of
+// A.Qs (see fsa.h).  One launch per side; sides sharing a corner cell run one after another.
+int launch_nrbc(const KConst* K, const Grid& G, int d, int side, const StageArgs& A, hipStream_t s);
 // 2D inflow ghost states of steps step0 .. step0 + nsteps - 1 (the far field with the
 // seeded perturbation, the values the boundary rule gives the four ghost layers of every
 // inflow side) into g, one table of inflow_ghosts2d_elems per step, each

@@ -142,7 +142,7 @@ __device__ __forceinline__ bool wave_all_kept(unsigned word)
     else return false;
 }
 
-template <int SCHEME, class T, bool DBG = false>
+template <int SCHEME, class T, bool DBG = false, bool NR = false>
 struct Column2D {
     static constexpr bool F64 = std::is_same<T, double>::value;
     // Rows of loads in flight ahead of their use: the FP32 forms have less arithmetic per row
@@ -199,6 +199,9 @@ struct Column2D {
     bool ib_on;                     // the force window is present and overlaps this strip
     double (*ring)[4][WAVE];        // LDS: the last five front rows of this wave, [slot][comp][lane]
     int lane;
+    bool nrbc_x;                    // this lane's cell is the boundary cell of a non-reflecting
+                                    // x side (its x convective term is left to launch_nrbc)
+    int nrbc;                       // the non-reflecting sides (StageArgs::nrbc)
     unsigned* dbg_x;                // DBG (FP64 TENO5 only): the keep patterns of every x face
     unsigned* dbg_y;                // [ny][nx+1] and y face [ny+1][nx] this stage decides
 
@@ -470,8 +473,14 @@ struct Column2D {
                 };
                 if (wave_all_kept<SCHEME>(word_x)) xface(std::true_type{});
                 else xface(std::false_type{});
+                if constexpr (NR) {
+                    if (nrbc_x) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) L[c] = 0.0;
+                    }
+                }
             }
-            if (terms & T_CONVY) {
+            if ((terms & T_CONVY) && !(NR && (((nrbc & 4) && r == 0) || ((nrbc & 8) && r == ny - 1)))) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) L[c] += (double)cy_queue[c];
             }
@@ -565,7 +574,8 @@ __device__ __forceinline__ void set_issue_priority(int p)
     }
 }
 
-template <int SCHEME, class T, bool DBG = false>
+// NR: the instantiation for contexts with non-reflecting sides (StageArgs::nrbc).
+template <int SCHEME, class T, bool DBG = false, bool NR = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_stage2d(
     const KConst* __restrict__ K, StageArgs A)
 {
@@ -574,7 +584,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         init_keep_rows<T>(keep_rows, threadIdx.x);
         __syncthreads();
     }
-    Column2D<SCHEME, T, DBG> C;
+    Column2D<SCHEME, T, DBG, NR> C;
     C.K = K;
     C.dbg_x = A.dbg_x;
     C.dbg_y = A.dbg_y;
@@ -662,6 +672,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         C.gxo = C.x_inflow ? (side * HALO + depth - 1) * C.gna : 0;
         C.xg_wave = __ballot(C.x_inflow) != 0ull;
         C.out_lane = lane >= HALO && lane < WAVE - HALO && i < nx;
+        C.nrbc = A.nrbc;
+        C.nrbc_x = ((A.nrbc & 1) && C.i == 0) || ((A.nrbc & 2) && C.i == nx - 1);
     }
     C.sg_x = C.out_lane ? C.sponge_rate(K->eta_dir(0, C.i)) : 0.0;
     C.sg_rows = 0.0;
@@ -795,7 +807,15 @@ int launch_stage2d(const KConst* K, const Grid& G, int scheme, int precision, co
     const int ncolx = (G.n[0] + OUTW - 1) / OUTW;
     const int nseg = (G.n[1] + A.ty - 1) / A.ty;
     dim3 grid(ncolx, nseg), block(WAVE);
-    if (precision == 2) {
+    if (A.nrbc) {
+        if (A.dbg_x) return (int)hipErrorInvalidValue;
+        if (precision == 2) hipLaunchKernelGGL((k_stage2d<LEARNED, float, false, true>), grid, block, 0, s, K, A);
+        else if (precision == 1 && scheme == TENO5)
+            hipLaunchKernelGGL((k_stage2d<TENO5, float, false, true>), grid, block, 0, s, K, A);
+        else if (precision == 1) hipLaunchKernelGGL((k_stage2d<WENO5JS, float, false, true>), grid, block, 0, s, K, A);
+        else if (scheme == TENO5) hipLaunchKernelGGL((k_stage2d<TENO5, double, false, true>), grid, block, 0, s, K, A);
+        else hipLaunchKernelGGL((k_stage2d<WENO5JS, double, false, true>), grid, block, 0, s, K, A);
+    } else if (precision == 2) {
         hipLaunchKernelGGL((k_stage2d<LEARNED, float>), grid, block, 0, s, K, A);
     } else if (precision == 1) {
         if (scheme == TENO5) hipLaunchKernelGGL((k_stage2d<TENO5, float>), grid, block, 0, s, K, A);

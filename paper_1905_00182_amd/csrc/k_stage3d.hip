@@ -286,17 +286,22 @@ __global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ 
         double L[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         const T inv_h = (T)G.inv_h;
         // -(F^_{i+1/2} - F^_{i-1/2}) / h per direction, each face read from its buffer
-        if (terms & T_CONVX) {
+        // (a non-reflecting side's boundary cells leave the normal term to launch_nrbc)
+        const int nr = A.nrbc;
+        const bool skx = ((nr & 1) && i == 0) || ((nr & 2) && i == G.n[0] - 1);
+        const bool sky = ((nr & 4) && j == 0) || ((nr & 8) && j == G.n[1] - 1);
+        const bool skz = ((nr & 16) && k == 0) || ((nr & 32) && k == G.n[2] - 1);
+        if ((terms & T_CONVX) && !skx) {
             const long long nf = faces_of<0>(G), o = face_index<0>(G, i, 0, j, k);
 #pragma unroll
             for (int c = 0; c < 5; ++c) L[c] += (double)(-(Fx[c * nf + o + 1] - Fx[c * nf + o]) * inv_h);
         }
-        if (terms & T_CONVY) {
+        if ((terms & T_CONVY) && !sky) {
             const long long nf = faces_of<1>(G), o = face_index<1>(G, j, i, 0, k), st = G.n[0];
 #pragma unroll
             for (int c = 0; c < 5; ++c) L[c] += (double)(-(Fy[c * nf + o + st] - Fy[c * nf + o]) * inv_h);
         }
-        if (terms & T_CONVZ) {
+        if ((terms & T_CONVZ) && !skz) {
             const long long nf = faces_of<2>(G), o = face_index<2>(G, k, i, j, 0);
             const long long st = (long long)G.n[0] * G.n[1];
 #pragma unroll

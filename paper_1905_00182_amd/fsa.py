@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfsa.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-BC = {"periodic": 0, "extrap": 1, "inflow": 2}
+BC = {"periodic": 0, "extrap": 1, "inflow": 2, "nonreflect": 3}
 SCHEME = {"weno5js": 0, "teno5": 1}
 PRECISION = {"fp64": 0, "mixed32": 1, "learned32": 2}
 MLP_NPARAM = 1667
