@@ -281,12 +281,15 @@ int32_t fsa_mlp_grad(fsa_ctx* ctx, const float* d_feats, const uint8_t* d_labels
 /* One Adam step (beta 0.9/0.999, eps 1e-8) on the gradient of this batch; d_loss may be NULL. */
 int32_t fsa_mlp_train_step(fsa_ctx* ctx, const float* d_feats, const uint8_t* d_labels, int64_t n, float lr,
                            float* d_loss);
-/* Harvest training samples from a 2D state at its own wave speeds: every significant face
- * side with a TENO5 cut-off and a seeded fraction keep_rate of the significant all-kept ones
- * (side s of face f is kept when the SplitMix64 number 2 f' + s of seed, as a uniform in
- * [0, 1), is below keep_rate; f' counts x faces first, then y faces), written in face order
- * (x faces, then y faces) as d_feats[max_out][16], d_labels[max_out].  *h_count receives the
- * number selected (only the first max_out are written).  Synchronising. */
+/* Harvest training samples from a 2D or 3D state at its own wave speeds: every significant
+ * face side with a TENO5 cut-off and a seeded fraction keep_rate of the significant all-kept
+ * ones (side s of face f is kept when the SplitMix64 number 2 f' + s of seed, as a uniform in
+ * [0, 1), is below keep_rate; f' counts x faces first, then y faces, then z faces), written
+ * in face order (x faces [nz][ny][nx+1], y faces [nz][ny+1][nx], z faces [nz+1][ny][nx]) as
+ * d_feats[max_out][16], d_labels[max_out].  In 3D the features are those of 2D (rho, the
+ * normal velocity and p of the five cells) and the label ANDs the five components.
+ * *h_count receives the number selected (only the first max_out are written).
+ * Synchronising. */
 int32_t fsa_harvest(fsa_ctx* ctx, const double* d_Q, double keep_rate, uint64_t seed, int64_t max_out,
                     float* d_feats, uint8_t* d_labels, int64_t* h_count);
 /* Keep patterns the learned form uses for d_Q: x faces [(nx+1) ny], y faces [nx (ny+1)];

@@ -194,7 +194,9 @@ size_t carve(fsa_ctx* c, char* base)
     if (dim == 2) {
         c->counters = W.take<unsigned long long>(3 * (size_t)flags2d_blocks(G));
         c->qrange = W.take<float>(8 * (size_t)stage2d_waves(G, 4));
-        const size_t nb = (size_t)harvest2d_blocks(G);
+    }
+    {
+        const size_t nb = (size_t)(dim == 2 ? harvest2d_blocks(G) : harvest3d_blocks(G));
         c->hv_count = W.take<int>(nb);
         c->hv_offset = W.take<long long>(nb);
         c->hv_total = W.take<long long>(1);
@@ -1335,10 +1337,7 @@ int32_t fsa_harvest(fsa_ctx* c, const double* d_Q, double keep_rate, uint64_t se
                     uint8_t* d_labels, int64_t* h_count)
 {
     if (!c || !d_Q || !h_count || max_out < 0 || (max_out > 0 && (!d_feats || !d_labels))) return FSA_EINVAL;
-    if (c->d.dim != 2) return fail(c, FSA_EUNSUPPORTED, "harvest is built for 2D");
     if (!(keep_rate >= 0.0 && keep_rate <= 1.0)) return fail(c, FSA_EINVAL, "keep_rate outside [0, 1]");
-    const long long nb = harvest2d_blocks(c->G);
-    (void)nb;
     if (int rf = flush_alpha_final(c)) return rf;
     unsigned long long* bits = c->abits + 9;
     int e = launch_alpha(c->G, c->P, d_Q, c->apart, bits, c->stream);
@@ -1356,7 +1355,7 @@ int32_t fsa_harvest(fsa_ctx* c, const double* d_Q, double keep_rate, uint64_t se
     H.block_count = c->hv_count;
     H.block_offset = c->hv_offset;
     H.total = c->hv_total;
-    e = launch_harvest2d(c->dK, c->G, H, c->stream);
+    e = c->G.dim == 3 ? launch_harvest3d(c->dK, c->G, H, c->stream) : launch_harvest2d(c->dK, c->G, H, c->stream);
     if (e) return hipcheck(c, (hipError_t)e, "harvest launch");
     long long tot = 0;
     HIPCHK(c, hipMemcpyAsync(&tot, c->hv_total, sizeof tot, hipMemcpyDeviceToHost, c->stream));

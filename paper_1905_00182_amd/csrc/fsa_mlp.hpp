@@ -56,6 +56,9 @@ struct HarvestArgs {
 long long flags2d_blocks(const Grid& G);
 int launch_flags2d(const KConst* K, const Grid& G, const FlagArgs& A, hipStream_t s);
 long long harvest2d_blocks(const Grid& G);
+// 3D: the faces of the three directions; blocks of both passes (3 x faces / 256).
+long long harvest3d_blocks(const Grid& G);
+int launch_harvest3d(const KConst* K, const Grid& G, const HarvestArgs& H, hipStream_t s);
 int launch_harvest2d(const KConst* K, const Grid& G, const HarvestArgs& H, hipStream_t s);
 
 int launch_mlp_forward(const MLPArgs& M, const float* feats, long long n, float* logits, hipStream_t s);

@@ -23,6 +23,8 @@
 //    numerically constant component keeps everything) of every significant side; all sides
 //    with a cut-off and a seeded fraction of the all-kept ones are written, in face order, by
 //    a two-pass compaction (deterministic).
+#include <algorithm>
+
 #include "fsa_mlp.hpp"
 
 namespace fsa {
@@ -736,6 +738,195 @@ __global__ void k_scan_counts(const int* __restrict__ count, long long n, long l
     *total = s;
 }
 
+// ---------------------------------------------------------------------------------------
+// Harvest in 3D: the same features, significance gate and labels as in 2D, for the faces of
+// all three directions (x faces [nz][ny][nx+1], then y faces [nz][ny+1][nx], then z faces
+// [nz+1][ny][nx]); side s of face f' (counted over the directions in that order) is drawn
+// with SplitMix64 number 2 f' + s.
+// ---------------------------------------------------------------------------------------
+struct FaceCells3 {
+    double q[6][5];
+    double rho[6], u[6][3], p[6];
+};
+
+__device__ __forceinline__ long long faces3_of(const Grid& G, int dir)
+{
+    return (long long)(G.n[0] + (dir == 0)) * (G.n[1] + (dir == 1)) * (G.n[2] + (dir == 2));
+}
+
+// Cell (i, j, k) below face f along dir.
+__device__ __forceinline__ bool face_origin3(const Grid& G, int dir, long long f, int& i, int& j, int& k)
+{
+    const long long mx = G.n[0] + (dir == 0), my = G.n[1] + (dir == 1);
+    if (f >= faces3_of(G, dir)) return false;
+    i = (int)(f % mx) - (dir == 0);
+    j = (int)((f / mx) % my) - (dir == 1);
+    k = (int)(f / (mx * my)) - (dir == 2);
+    return true;
+}
+
+__device__ __forceinline__ void load_face3(const KConst* K, const double* Q, long long step, int dir, int i, int j,
+                                           int k, FaceCells3& C)
+{
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const int ii = i + (dir == 0 ? s - 2 : 0), jj = j + (dir == 1 ? s - 2 : 0), kk = k + (dir == 2 ? s - 2 : 0);
+        fetch_state<3>(Q, K->G, K->P, step, ii, jj, kk, C.q[s]);
+        const double ir = 1.0 / C.q[s][0];
+        double ke = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            C.u[s][a] = C.q[s][1 + a] * ir;
+            ke += C.q[s][1 + a] * C.u[s][a];
+        }
+        C.rho[s] = C.q[s][0];
+        C.p[s] = K->P.gm1 * (C.q[s][4] - 0.5 * ke);
+    }
+}
+
+template <int SD>
+__device__ __forceinline__ void side_features3(const KConst* K, const FaceCells3& C, int dir, float* f)
+{
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const double sgn = (m == 1 && SD == 1) ? -1.0 : 1.0;
+        double v[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int s = cell_of<SD>(k);
+            v[k] = sgn * (m == 0 ? C.rho[s] : (m == 1 ? C.u[s][dir] : C.p[s]));
+        }
+        double mx = 0.0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) mx = fmax(mx, fabs(v[k] - v[2]));
+#pragma unroll
+        for (int k = 0; k < 5; ++k) f[m * 5 + k] = (float)((v[k] - v[2]) / (mx + K->sig[m]));
+    }
+}
+
+template <int SD>
+__device__ __forceinline__ bool side_significant3(const KConst* K, const FaceCells3& C)
+{
+    bool sig = false;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+        double lo = 0.0, hi = 0.0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int s = cell_of<SD>(k);
+            const double v = m == 0 ? C.rho[s] : (m == 4 ? C.p[s] : C.u[s][m - 1]);
+            lo = k ? fmin(lo, v) : v;
+            hi = k ? fmax(hi, v) : v;
+        }
+        sig = sig || (hi - lo > K->sig[m == 0 ? 0 : (m == 4 ? 2 : 1)]);
+    }
+    return sig;
+}
+
+// Split flux (F + a q)/2 of component c of one 3D state along dir for the labels, no
+// contraction (as label_split_flux).
+__device__ __forceinline__ double label_split_flux3(const KConst* K, const double* q, int dir, int c, double a)
+{
+#pragma clang fp contract(off)
+    const double u = q[1] / q[0], v = q[2] / q[0], w = q[3] / q[0];
+    double ke = 0.0;
+    ke += q[1] * u;
+    ke += q[2] * v;
+    ke += q[3] * w;
+    const double p = K->P.gm1 * (q[4] - 0.5 * ke);
+    const double ud = dir == 0 ? u : (dir == 1 ? v : w);
+    double F;
+    if (c == 0) F = q[1 + dir];
+    else if (c == 4) F = (q[4] + p) * ud;
+    else F = q[c] * ud + (c - 1 == dir ? p : 0.0);
+    return 0.5 * (F + a * q[c]);
+}
+
+template <int SD>
+__device__ __forceinline__ int side_label3(const KConst* K, const FaceCells3& C, int dir, double alpha)
+{
+    const double a = SD == 0 ? alpha : -alpha;
+    int all = 7;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double v[5], lo = 0, hi = 0, mag = 0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            v[k] = label_split_flux3(K, C.q[cell_of<SD>(k)], dir, c, a);
+            lo = k ? fmin(lo, v[k]) : v[k];
+            hi = k ? fmax(hi, v[k]) : v[k];
+            mag = fmax(mag, fabs(v[k]));
+        }
+        if (hi - lo <= 1e-12 * mag) continue;
+        all &= teno_flags64(v[0], v[1], v[2], v[3], v[4], K->P.teno_eps, K->P.teno_ct);
+    }
+    return all;
+}
+
+__global__ __launch_bounds__(256) void k_harvest3d(const KConst* __restrict__ K, HarvestArgs H, int pass)
+{
+    const int dir = blockIdx.y;
+    const Grid& G = K->G;
+    const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int i = 0, j = 0, k = 0;
+    const bool valid = face_origin3(G, dir, f, i, j, k);
+    FaceCells3 C;
+    int lab0 = 7, lab1 = 7;
+    bool sel0 = false, sel1 = false;
+    const double alpha = __longlong_as_double((long long)H.alpha_bits[dir]);
+    if (valid) {
+        load_face3(K, H.Q, H.step, dir, i, j, k, C);
+        long long off = 0;
+        for (int d = 0; d < dir; ++d) off += faces3_of(G, d);
+        const long long gid = 2 * (off + f);
+        if (side_significant3<0>(K, C)) {
+            lab0 = side_label3<0>(K, C, dir, alpha);
+            sel0 = select_side(H, gid, lab0);
+        }
+        if (side_significant3<1>(K, C)) {
+            lab1 = side_label3<1>(K, C, dir, alpha);
+            sel1 = select_side(H, gid + 1, lab1);
+        }
+    }
+    const int mine = (int)sel0 + (int)sel1;
+    __shared__ int wsum[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int q = 0; q < wid; ++q) before += wsum[q];
+    const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    if (pass == 0) {
+        if (threadIdx.x == blockDim.x - 1) H.block_count[blk] = before + incl;
+        return;
+    }
+    long long pos = H.block_offset[blk] + before + incl - mine;
+    float ft[15];
+    if (sel0) {
+        if (pos < H.max_out) {
+            side_features3<0>(K, C, dir, ft);
+#pragma unroll
+            for (int m = 0; m < 15; ++m) H.feats[pos * 16 + m] = ft[m];
+            H.feats[pos * 16 + 15] = 0.f;
+            H.labels[pos] = (unsigned char)lab0;
+        }
+        ++pos;
+    }
+    if (sel1 && pos < H.max_out) {
+        side_features3<1>(K, C, dir, ft);
+#pragma unroll
+        for (int m = 0; m < 15; ++m) H.feats[pos * 16 + m] = ft[m];
+        H.feats[pos * 16 + 15] = 0.f;
+        H.labels[pos] = (unsigned char)lab1;
+    }
+}
+
 }  // namespace
 
 long long flags2d_blocks(const Grid& G)
@@ -755,6 +946,23 @@ long long harvest2d_blocks(const Grid& G)
     const long long nfx = (long long)(G.n[0] + 1) * G.n[1], nfy = (long long)G.n[0] * (G.n[1] + 1);
     const long long nf = nfx > nfy ? nfx : nfy;
     return 2 * ((nf + 255) / 256);
+}
+
+long long harvest3d_blocks(const Grid& G)
+{
+    long long nf = 0;
+    for (int d = 0; d < 3; ++d)
+        nf = std::max(nf, (long long)(G.n[0] + (d == 0)) * (G.n[1] + (d == 1)) * (G.n[2] + (d == 2)));
+    return 3 * ((nf + 255) / 256);
+}
+
+int launch_harvest3d(const KConst* K, const Grid& G, const HarvestArgs& H, hipStream_t s)
+{
+    const unsigned bx = (unsigned)(harvest3d_blocks(G) / 3);
+    hipLaunchKernelGGL(k_harvest3d, dim3(bx, 3), dim3(256), 0, s, K, H, 0);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(64), 0, s, H.block_count, 3ll * bx, H.block_offset, H.total);
+    hipLaunchKernelGGL(k_harvest3d, dim3(bx, 3), dim3(256), 0, s, K, H, 1);
+    return (int)hipGetLastError();
 }
 
 int launch_harvest2d(const KConst* K, const Grid& G, const HarvestArgs& H, hipStream_t s)

@@ -26,18 +26,24 @@ def init_params(seed):
     return np.concatenate(parts).astype(np.float32)
 
 
-def training_cases(n1=128, n2=256, n5=512):
-    """The scattering case with TENO5, a miniature of the rotating-cylinder case (same cell
-    size, uniform start) and one of the flapping plate (rigid, same cell size, the wake inside
-    [-2, 2]^2, a tenth of its sides without a cut-off kept, so that its mostly smooth wake does
-    not crowd out the other cases), each with its initial state and sampling interval."""
+def training_cases(n1=128, n2=2048, n3=128, n5=512, every2=200):
+    """FP64 runs whose face sides train the selector (about 1e7 sides): the cylinder
+    scattering case with TENO5 (config 1), the rotating-cylinder case at its full size from
+    its uniform start (config 2, a state every `every2` steps: the start-up wave, wake and
+    inflow noise), the sphere-scattering case in 3D (config 3's set-up at n3^3, its sides in
+    all three directions) and the rigid flapping plate (config 5's cell size, the wake inside
+    [-2, 2]^2, a tenth of its sides without a cut-off kept so that its mostly smooth wake does
+    not crowd out the rest), each with its initial state, sampling interval and the keep rate
+    of its all-kept sides (every side with a cut-off is kept)."""
     c1 = W.config1(n=n1, scheme="teno5")
-    c2 = W.config2(n=n2, h=1.0 / 16.0, sponge=2.0, nprobe=48, rprobe=3.0)
+    c2 = W.config2(n=n2, nprobe=8, rprobe=3.0)
+    c3 = W.config3(n=n3, scheme="teno5", nmark=2000)
     c5 = W.config5(n=n5, L=n5 / 64.0)
-    return [(c1, W.config1_state(c1), 20), (c2, W.config2_state(c2), 50), (c5, W.uniform_state(c5), 300, 0.1)]
+    return [(c1, W.config1_state(c1), 20), (c2, W.config2_state(c2), every2), (c3, W.config3_state(c3), 40),
+            (c5, W.uniform_state(c5), 300, 0.1)]
 
 
-def harvest(cases, chunks=6, keep_rate=1.0, seed=100, cap=1 << 21):
+def harvest(cases, chunks=6, keep_rate=1.0, seed=100, cap=1 << 22):
     """Significant face sides (features [n, 16] FP32, labels [n] uint8) from the states of FP64
     runs of each case, sampled every `every` steps (chunks + 1 states per case); a case with
     plate kinematics has its markers moved before every step.  A case may carry its own keep

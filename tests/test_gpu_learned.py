@@ -9,6 +9,8 @@
 * a network trained on the GPU from harvested faces: loss falls, and the FP32+learned run
   matches the FP64 oracle's acoustic pressure within 1%.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -157,6 +159,39 @@ def test_harvest_matches_oracle(torch_cuda):
                 _say(f"  label mismatch at dir {d} cell ({i},{j}) side {sd}: gpu {L[k]} oracle {lo}")
     _say("harvest: label mismatches", bad, "of", len(picks), "; sides with a cut-off", len(cut))
     assert bad == 0
+
+
+def test_harvest3d_matches_oracle(torch_cuda):
+    """3D harvest (the sphere case's pulse at 32^3): the significant sides of all three
+    directions in face order, their features and labels against the oracle's."""
+    from oracle.oracle import Oracle
+
+    case = W.config3(n=32, scheme="teno5", nmark=400)
+    Q0 = W.config3_state(case)
+    s = _solver(case)
+    nx, ny, nz = case.n
+    faces = [(0, i, j, k) for k in range(nz) for j in range(ny) for i in range(-1, nx)]
+    faces += [(1, i, j, k) for k in range(nz) for j in range(-1, ny) for i in range(nx)]
+    faces += [(2, i, j, k) for k in range(-1, nz) for j in range(ny) for i in range(nx)]
+    total = 2 * len(faces)
+    feats, labels, n = s.harvest(torch_cuda.from_numpy(Q0).cuda(), 1.0, 1, total)
+    F, L = feats.cpu().numpy(), labels.cpu().numpy()
+    o = Oracle(case)
+    alpha = o.alpha(Q0)
+    sides = [(d, i, j, k, sd) for (d, i, j, k) in faces for sd in (0, 1)
+             if o.face_significant(Q0, d, (i, j, k), sd)]
+    _say("3D harvest: significant sides", len(sides), "of", total, "; GPU wrote", n)
+    assert 0 < len(sides) < total // 2
+    assert n == len(sides)
+    rng = np.random.default_rng(10)
+    cut = np.flatnonzero(L != 7)
+    picks = np.concatenate([rng.choice(n, 300, replace=False), rng.choice(cut, min(200, len(cut)), replace=False)])
+    for kk in picks:
+        d, i, j, k, sd = sides[int(kk)]
+        np.testing.assert_allclose(F[kk, :15], o.face_features(Q0, d, (i, j, k), sd), rtol=0, atol=1e-6)
+        assert L[kk] == o.face_label(Q0, d, (i, j, k), sd, alpha[d]), (d, i, j, k, sd)
+    _say("3D harvest: sides with a cut-off", len(cut))
+    assert len(cut) > 20
 
 
 def test_harvest_selection_is_deterministic(torch_cuda):
@@ -309,17 +344,65 @@ def _learned_vs_oracle(torch, case, Q0, theta, nsteps, stride=1):
 
 
 @pytest.mark.parametrize("stride", [1, 3])
-def test_learned_acoustic_error_config1(torch_cuda, trained, stride):
+def test_learned_acoustic_error_config1_held_out(torch_cuda, trained, stride):
+    """Config 1 with the pulse moved to (-1.5, 1.0): a run the selector was not trained on."""
     c = trained["c1"]
-    res = _learned_vs_oracle(torch_cuda, c, W.config1_state(c), trained["theta"], c.steps, stride)
+    res = _learned_vs_oracle(torch_cuda, c, W.pulse_state(c, (-1.5, 1.0)), trained["theta"], c.steps, stride)
     assert res["learned32"][0] < 1e-2
+    assert res["mixed32"][0] < 1e-5
 
 
 @pytest.mark.parametrize("stride", [1, 3])
 def test_learned_acoustic_error_config2_small(torch_cuda, trained, stride):
-    c = trained["c2"]
+    """A 256^2 miniature of the rotating-cylinder case (the selector was trained on the full
+    case), 150 steps from the uniform start."""
+    c = W.config2(n=256, h=1.0 / 16.0, sponge=2.0, nprobe=48, rprobe=3.0)
     res = _learned_vs_oracle(torch_cuda, c, W.config2_state(c), trained["theta"], 150, stride)
     assert res["learned32"][0] < 1e-2
+
+
+def test_network_gain_over_plain_teno(torch_cuda, trained):
+    """What the trained network gains over the method without it, on the 2048^2 rotating
+    cylinder (800 steps from the uniform start): with the selector once per step, plain TENO5
+    is evaluated on under a tenth of the face sides (the fallback ones) instead of all, and
+    the step takes at most 0.85 of the precision form's (plain FP32 TENO5) time, with the
+    far-field probe pressure (a ring of radius 10, which the start-up wave crosses) within 1%
+    of the FP64 run's (itself the oracle's: the parity tests)."""
+    torch = torch_cuda
+    c = W.config2(nprobe=64, rprobe=10.0)
+    Q0 = torch.from_numpy(W.config2_state(c)).cuda()
+    out = {}
+    for name, prec, stride in (("fp64", "fp64", 1), ("mixed32", "mixed32", 1), ("learned32", "learned32", 3)):
+        sv = _solver(c.with_(precision=prec, extra={"selector_stride": stride}))
+        if prec == "learned32":
+            sv.mlp_set(trained["theta"], 0.8)
+        Q = Q0.clone()
+        sv.rk3_steps(Q, c.dt, 3)                  # warm-up (segment tuning)
+        Q = Q0.clone()
+        sv.set_state(None, 0.0, 0)
+        st0 = sv.stats()
+        dps = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(80):
+            sv.rk3_steps(Q, c.dt, 10)
+            dps.append(sv.probe_dp(Q))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = sv.stats()
+        n = max(st.learned_sides - st0.learned_sides, 1)
+        out[name] = (wall, torch.stack(dps), (st.fallback_sides - st0.fallback_sides) / n)
+        sv.close()
+    e_p = float(torch.linalg.norm(out["learned32"][1] - out["fp64"][1]) / torch.linalg.norm(out["fp64"][1]))
+    ratio = out["learned32"][0] / out["mixed32"][0]
+    _say(f"network gain: learned (stride 3) {out['learned32'][0] * 1e3 / 800:.3f} ms/step vs plain FP32 TENO5 "
+         f"{out['mixed32'][0] * 1e3 / 800:.3f} (ratio {ratio:.3f}), FP64 {out['fp64'][0] * 1e3 / 800:.3f}; fallback "
+         f"{out['learned32'][2]:.4f} of sides; e_p vs FP64 {e_p:.3e} (|dp| up to "
+         f"{float(out['fp64'][1].abs().max()):.2e})")
+    assert float(out["fp64"][1].abs().max()) > 1e-5
+    assert out["learned32"][2] < 0.1
+    assert ratio < 0.85
+    assert e_p < 1e-2
 
 
 @pytest.mark.parametrize("stride", [1, 3])
