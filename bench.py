@@ -7,12 +7,15 @@ reconstruction in x and y, fourth-order viscous terms, IB and sponge sources, RK
 Inputs are synthetic (the uniform Mach 0.2 stream; the seeded perturbation enters with the
 inflow) and resident in HBM before the timed region.
 
-Variants (unless --no-variants): the whole 2000-step run of the same case in FP64, in the
-FP32 precision form and in the FP32 + learned-selector form (network trained first, in
-process, by the library's own kernels from short FP64 runs of smaller cases), each timed
-over the run with the acoustic pressure sampled at the 360 probes every 10 steps; each
-variant's probe signal is compared with the FP64 run's (the FP64 path matches the CPU
-oracle to 1e-12).  The learned form is also run with the selector evaluated once per step.
+Variants (unless --no-variants): the whole run of the same case (the configured 2000 steps
+and their continuation to 4000, by which the cylinder's start-up wave crosses the radius-50
+ring) in FP64, in the FP32 precision form and in the FP32 + learned-selector form (network
+trained first, in process, by the library's own kernels from FP64 runs of configs 1-3 and the
+plate), each timed over the run with the acoustic pressure sampled every 10 steps on the 360
+probes of the radius-50 ring and on a radius-10 ring; each form's probe signal is compared
+with the CPU oracle's record of the same run (tests/golden/c2_oracle_run.npz, when present)
+and with the FP64 GPU run.  The learned form is also run with the selector evaluated once
+per step.
 
 Prints one JSON line.  Metric: cell-stage updates per second (cells x 3 stages x steps /
 wall time).  roofline: the fused stage kernel, whose launches are bracketed by HIP events on
@@ -136,7 +139,7 @@ def full_run(case, Q0, nsteps, every, net=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(nsamp):
-        s.rk3_steps(Q, case.dt, every)
+        s.rk3_steps(Q, case.dt, every) if k == 0 else s.rk3_steps_resume(Q, case.dt, every)
         s.probe_dp(Q, out=dps[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -149,7 +152,15 @@ def full_run(case, Q0, nsteps, every, net=None):
     }
 
 
+ORACLE_RECORD = os.path.join(ROOT, "tests", "golden", "c2_oracle_run.npz")
+
+
 def variants(case, Q0, nsteps, every=10, plate_steps=None):
+    """The FP64, precision and learned forms over the whole run (probes on the configured
+    radius-50 ring and a radius-10 ring, sampled every `every` steps), each form's acoustic
+    error against the CPU oracle's record of the same run (tests/golden/c2_oracle_run.npz,
+    written by the oracle alone) and against the FP64 GPU run."""
+    import numpy as np
     import torch
 
     from paper_1905_00182_amd import selector
@@ -160,29 +171,35 @@ def variants(case, Q0, nsteps, every=10, plate_steps=None):
     net, losses = selector.train(F, L)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    nprobe = case.probes.shape[1]
+    rings = case.with_(probes=np.concatenate([case.probes, W.ring_probes(nprobe, 10.0)], axis=1))
+    rec = None
+    if os.path.exists(ORACLE_RECORD):
+        z = np.load(ORACLE_RECORD)
+        if int(z["every"]) == every and abs(float(z["dt"]) - case.dt) == 0.0:
+            rec = {"r50": torch.from_numpy(z["dp_r50"]).cuda(), "r10": torch.from_numpy(z["dp_r10"]).cuda()}
     res = {}
     cs = case.ncell * 3 * nsteps
-    # probes: the configured radius-50 ring, and a radius-10 ring the start-up wave has
-    # crossed within the run (the same computation; only the sampled points differ)
-    near = case.with_(probes=W.ring_probes(case.probes.shape[1], 10.0))
     runs = {}
     forms = (("fp64", "fp64", None, 1), ("mixed32", "mixed32", None, 1), ("learned32", "learned32", net, 1),
              ("learned32_stride3", "learned32", net, 3))
     for name, prec, n, stride in forms:
-        w, dp, fr = full_run(case.with_(precision=prec, extra={"selector_stride": stride}), Q0, nsteps, every, n)
-        _, dpn, _ = full_run(near.with_(precision=prec, extra={"selector_stride": stride}), Q0, nsteps, every, n)
-        runs[name] = (w, dp, dpn, fr)
-    w64, dp64, dpn64, _ = runs["fp64"]
-    res["fp64"] = {"value": round(cs / w64 / 1e6, 3), "ms_per_step": round(w64 / nsteps * 1e3, 4)}
-    for name in ("mixed32", "learned32", "learned32_stride3"):
-        w, dp, dpn, fr = runs[name]
-        e = {
-            "value": round(cs / w / 1e6, 3),
-            "ms_per_step": round(w / nsteps * 1e3, 4),
-            "speedup_vs_fp64": round(w64 / w, 3),
-            "acoustic_err_r50": float(torch.linalg.norm(dp - dp64) / torch.linalg.norm(dp64)),
-            "acoustic_err_r10": float(torch.linalg.norm(dpn - dpn64) / torch.linalg.norm(dpn64)),
-        }
+        runs[name] = full_run(rings.with_(precision=prec, extra={"selector_stride": stride}), Q0, nsteps, every, n)
+
+    def err(a, b):
+        return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+    w64, dp64, _ = runs["fp64"]
+    for name, (w, dp, fr) in runs.items():
+        e = {"value": round(cs / w / 1e6, 3), "ms_per_step": round(w / nsteps * 1e3, 4)}
+        if name != "fp64":
+            e["speedup_vs_fp64"] = round(w64 / w, 3)
+            e["acoustic_err_r50_vs_fp64"] = err(dp[:, :nprobe], dp64[:, :nprobe])
+            e["acoustic_err_r10_vs_fp64"] = err(dp[:, nprobe:], dp64[:, nprobe:])
+        if rec is not None:
+            k50, k10 = min(rec["r50"].shape[0], dp.shape[0]), min(rec["r10"].shape[0], dp.shape[0])
+            e["acoustic_err_r50_vs_oracle"] = err(dp[:k50, :nprobe], rec["r50"][:k50])
+            e["acoustic_err_r10_vs_oracle"] = err(dp[:k10, nprobe:], rec["r10"][:k10])
         if name.startswith("learned32"):
             e["significant_side_frac"] = round(fr["significant"], 4)
             e["fallback_side_frac"] = round(fr["fallback"], 4)
@@ -195,10 +212,14 @@ def variants(case, Q0, nsteps, every=10, plate_steps=None):
     res["c5_flapping_plate"] = flapping_plate(net, nsteps=plate_steps)
     res["c5_flexible_plate"] = flapping_plate(net, nsteps=plate_steps, flexible=True)
     res["hovering_insect"] = hovering_insect(net, nsteps=plate_steps)
-    res["run"] = {"steps": nsteps, "probes": int(dp64.shape[1]), "probe_every": every,
-                  "max_probe_dp_r50": float(dp64.abs().max()), "max_probe_dp_r10": float(dpn64.abs().max()),
-                  "note": "whole run from the uniform start, probe launches included in the timing (the r50 "
-                          "run's); errors are relative L2 over probes x samples against the FP64 run"}
+    res["run"] = {"steps": nsteps, "probes_per_ring": nprobe, "probe_every": every,
+                  "max_probe_dp_r50": float(dp64[:, :nprobe].abs().max()),
+                  "max_probe_dp_r10": float(dp64[:, nprobe:].abs().max()),
+                  "oracle_record": rec is not None,
+                  "note": "whole run from the uniform start (the configured 2000 steps and their continuation "
+                          "until the start-up wave crosses the radius-50 ring), probe launches included in the "
+                          "timing; errors are relative L2 over probes x samples, against the oracle's record "
+                          "(radius 10: its first 2000 steps) and against the FP64 GPU run"}
     return res
 
 
@@ -338,7 +359,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the full-run comparison of the FP64, FP32 and FP32+learned forms")
-    ap.add_argument("--variant-steps", type=int, default=None, help="steps of the full runs (default: the case's)")
+    ap.add_argument("--variant-steps", type=int, default=4000,
+                    help="steps of the full runs (default 4000: the configured 2000 and their continuation until "
+                         "the start-up wave crosses the radius-50 ring)")
     ap.add_argument("--plate-steps", type=int, default=None,
                     help="steps of the flapping-plate and hovering-insect runs (default: one flapping period)")
     ap.add_argument("--scheme", default="teno5", choices=["teno5", "weno5js"])
@@ -433,7 +456,7 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_variants:
-        out["variants"] = variants(case, Q0, args.variant_steps or case.steps, plate_steps=args.plate_steps)
+        out["variants"] = variants(case, Q0, args.variant_steps, plate_steps=args.plate_steps)
         out["variants"]["three_d"] = three_d()
     if not args.no_cpu and args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
