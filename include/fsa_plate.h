@@ -16,8 +16,9 @@
  *
  * Step.  Newmark's average-acceleration rule (beta = 1/4, gamma = 1/2) for the free
  * coordinates with M and K implicit and the stretching force explicit at the Newmark
- * predictor; stable while dt omega_s < 2, omega_s the largest stretching frequency (the call
- * rejects larger steps).  The load is the fluid force of the step just taken.
+ * predictor, stable while the step times omega_s (the largest stretching frequency) is below 2:
+ * a call of size dt takes n = ceil(dt omega_s / 1.9) equal sub-steps under the same load (at
+ * most 16; larger steps are rejected).  The load is the fluid force of the step just taken.
  *
  * Status codes are those of fsa.h.  Not thread-safe per plate. */
 #ifndef FSA_PLATE_H
@@ -57,8 +58,9 @@ int32_t fsa_plate_destroy(fsa_plate* plate);
 /* Marker positions X[2][n] and velocities U[2][n] (host arrays): S(s_k) e and S(s_k) e_t. */
 int32_t fsa_plate_markers(const fsa_plate* plate, double* X, double* U);
 /* One step of size dt under the marker forces F[2][n] (host; the force on the plate per unit
- * length, as fsa_marker_force returns it).  FSA_EINVAL when dt <= 0 or dt omega_s >= 2 (the
- * explicit stretching limit; the message names 2 / omega_s). */
+ * length, as fsa_marker_force returns it), in ceil(dt omega_s / 1.9) equal sub-steps.
+ * FSA_EINVAL when dt <= 0 or dt needs more than 16 sub-steps (the message names the explicit
+ * stretching limit 1.9 / omega_s). */
 int32_t fsa_plate_step(fsa_plate* plate, const double* F, double dt);
 /* Checkpoint: coordinates e[4(n_elements + 1)] (node j: x, y, x_s, y_s), their velocities and
  * accelerations (the Newmark state) and the time; outputs may be NULL.  set_state with a NULL

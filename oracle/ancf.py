@@ -102,6 +102,15 @@ class Plate:
             self.e[4 * i + 2:4 * i + 4] = d
             self.v[4 * i:4 * i + 2] = rt + s * dt_
             self.v[4 * i + 2:4 * i + 4] = dt_
+        # largest stretching frequency of the unstretched plate, bounded by an element's:
+        # K_S int dN dN^T ds against the element mass, per coordinate
+        ke = np.zeros((4, 4))
+        me = np.zeros((4, 4))
+        for xi, wq in zip(self.gx, self.gw):
+            N, dN, _ = hermite(xi, self.l)
+            ke += self.k_s * self.l * wq * np.outer(dN, dN)
+            me += self.rho_s * self.l * wq * np.outer(N, N)
+        self.omega_s = math.sqrt(max(np.linalg.eigvals(np.linalg.solve(me, ke)).real)) if self.k_s > 0 else 0.0
         # initial acceleration of the free coordinates: no load
         f = self.stretch_force(self.e)
         ap = np.concatenate([rtt, dtt])
@@ -163,9 +172,19 @@ class Plate:
             U[:, k] = S @ self.v[4 * j:4 * j + 8]
         return X, U
 
+    SUBSTEP_LIMIT = 1.9
+
     def step(self, F, dt):
-        """Advance by dt under the marker forces F[2][n] (force per unit length on the plate)."""
-        dt = float(dt)
+        """Advance by dt under the marker forces F[2][n] (force per unit length on the plate):
+        n equal sub-steps under the same forces, n the least with (dt / n) omega_s < 1.9, so
+        that each keeps the explicit stretching force within its stability limit 2."""
+        n = max(1, math.ceil(float(dt) * self.omega_s / self.SUBSTEP_LIMIT))
+        for _ in range(n):
+            self._newmark(F, float(dt) / n)
+        return self
+
+    def _newmark(self, F, dt):
+        """One Newmark step of size dt (average acceleration, stretching force explicit)."""
         beta, gamma = 0.25, 0.5
         et = self.e + dt * self.v + dt * dt * (0.5 - beta) * self.a     # predictors
         vt = self.v + dt * (1.0 - gamma) * self.a

@@ -16,6 +16,11 @@
 
 #include "fsa_plate.h"
 
+// Sub-steps of a plate step: dt_sub omega_s < SUBSTEP_LIMIT (the explicit stretching force
+// is stable below 2), at most MAX_SUBSTEPS of them.
+constexpr double SUBSTEP_LIMIT = 1.9;
+constexpr int MAX_SUBSTEPS = 16;
+
 namespace {
 
 constexpr int BW = 7;
@@ -372,15 +377,11 @@ int32_t fsa_plate_markers(const fsa_plate* p, double* X, double* U)
     return FSA_OK;
 }
 
-int32_t fsa_plate_step(fsa_plate* p, const double* F, double dt)
+namespace {
+
+// One Newmark step of size dt (within the explicit stretching limit).
+int32_t plate_substep(fsa_plate* p, const double* F, double dt)
 {
-    if (!p) return FSA_EINVAL;
-    if (!F) return fail(p, FSA_EINVAL, "F is NULL");
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, FSA_EINVAL, "dt must be positive");
-    if (dt * p->omega_s >= 2.0) {
-        p->err = "dt above the explicit stretching limit 2 / omega_s = " + std::to_string(2.0 / p->omega_s);
-        return FSA_EINVAL;
-    }
     const int nd = p->ndof, nf = nd - 4;
     if (dt != p->A_dt) {
         p->A.init(nf);
@@ -434,6 +435,30 @@ int32_t fsa_plate_step(fsa_plate* p, const double* F, double dt)
     }
     p->t = t1;
     return finite ? FSA_OK : fail(p, FSA_ENONFINITE, "non-finite plate state");
+}
+
+}  // namespace
+
+int32_t fsa_plate_step(fsa_plate* p, const double* F, double dt)
+{
+    if (!p) return FSA_EINVAL;
+    if (!F) return fail(p, FSA_EINVAL, "F is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(p, FSA_EINVAL, "dt must be positive");
+    // equal sub-steps under the same forces, each within the explicit stretching limit
+    // (dt_sub omega_s < 1.9 < 2)
+    const double ratio = dt * p->omega_s / SUBSTEP_LIMIT;
+    if (!(ratio <= MAX_SUBSTEPS)) {
+        p->err = "dt needs more than " + std::to_string(MAX_SUBSTEPS) +
+                 " sub-steps of the explicit stretching limit 1.9 / omega_s = " + std::to_string(SUBSTEP_LIMIT / p->omega_s);
+        return FSA_EINVAL;
+    }
+    const int nsub = std::max(1, (int)std::ceil(ratio));
+    const double h = dt / nsub;
+    for (int k = 0; k < nsub; ++k) {
+        const int32_t rc = plate_substep(p, F, h);
+        if (rc != FSA_OK) return rc;
+    }
+    return FSA_OK;
 }
 
 int32_t fsa_plate_get_state(const fsa_plate* p, double* e, double* v, double* a, double* t)

@@ -357,7 +357,11 @@ class Solver:
             self.ctx = None
         self.workspace = None
 
-    __del__ = close
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:      # interpreter shutdown: the module's globals may be gone
+            pass
 
     def _check(self, rc, ctx="self"):
         if rc != OK:

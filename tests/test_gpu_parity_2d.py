@@ -169,16 +169,17 @@ def test_hovering_insect_moving_markers(torch_cuda, scheme):
     assert np.abs(Qo[1:3]).max() > 1e-5     # the wings have set the gas moving
 
 
-def test_flexible_plate_coupled(torch_cuda):
+@pytest.mark.parametrize("nel,mass_ratio", [(10, 5.0), (40, 1.0)])
+def test_flexible_plate_coupled(torch_cuda, nel, mass_ratio):
     """The flexible flapping plate: fluid and structure coupled explicitly every step (the
     markers follow the plate; the plate is loaded by the step's marker forces), the library's
-    HIP fluid and host plate against the oracle's fluid and plate."""
+    HIP fluid and host plate against the oracle's fluid and plate: with 10 elements at the
+    paper's mass ratio 5 (one plate step per fluid step), and with 40 elements at the
+    configuration's mass ratio 1 (the miniature's fluid step takes 9 plate sub-steps)."""
     from oracle.ancf import Plate, flapping_clamp
     from paper_1905_00182_amd import fsa
 
-    # (10 elements: the miniature's fluid step, 0.015, is above a 40-element plate's explicit
-    # stretching limit, 0.0043, which scales with the element length)
-    case = W.config5_flexible(n=128, L=8.0, nmark=128, scheme="weno5js", nel=10)
+    case = W.config5_flexible(n=128, L=8.0, nmark=128, scheme="weno5js", nel=nel, mass_ratio=mass_ratio)
     p, fl = case.extra["plate"], case.extra["flex"]
     Q0 = W.uniform_state(case)
     _say("flexible plate coupled x 20")
@@ -202,7 +203,10 @@ def test_flexible_plate_coupled(torch_cuda):
         o.rk3_step(Qo, case.dt)
         op.step(o.marker_force(), case.dt)
     s.sync()
-    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case)
+    # (element-wise for the 40-element plate: its bending matrix's conditioning lets the two
+    # plates' coordinates part at ~1e-12 of the chord within 20 steps, which the markers carry
+    # into the fluid next to the plate: ~2e-10 of the change there)
+    _assert_q_close(Qg.cpu().numpy(), Qo, Q0, case, tol_elem=TOL_ELEM if nel == 10 else 1e-9)
     e, v, a, t = lp.get_state()
     # (the plate's own rounding bound over 20 steps is ~1e-12; the forces agree to ~1e-9)
     np.testing.assert_allclose(e, op.e, atol=1e-11, rtol=0)

@@ -80,12 +80,31 @@ def test_checkpoint_restart_is_exact(case):
         assert np.array_equal(x, y)
 
 
+def test_light_plate_substeps_match_the_oracle():
+    """Mass ratio 1 (the configuration's statement): at the bench's fluid step the plate's
+    stretching frequency needs three sub-steps per step on both sides."""
+    from paper_1905_00182_amd import fsa
+
+    case = W.config5_flexible(n=128, L=8.0, nmark=64, mass_ratio=1.0)
+    lp, op = fsa.Plate(case), _oracle_plate(case)
+    dt = W.config5_flexible(n=1024).dt
+    assert 2 * 1.9 < dt * op.omega_s < 3 * 1.9      # three sub-steps; one step would be unstable
+    for F in _loads(case.markers["X"].shape[1], 200, seed=8):
+        lp.step(F, dt)
+        op.step(F, dt)
+    e, v, a, t = lp.get_state()
+    assert t == pytest.approx(op.t, rel=1e-14)
+    assert np.abs(op.e - _oracle_plate(case, t0=op.t).e).max() > 1e-3
+    np.testing.assert_allclose(e, op.e, atol=2e-10, rtol=0)
+    np.testing.assert_allclose(v, op.v, atol=1e-9, rtol=0)
+
+
 def test_rejections(case):
     from paper_1905_00182_amd import fsa
 
     p = fsa.Plate(case)
     F = np.zeros((2, p.nm))
-    for dt in (0.0, -1.0, 1.0):      # 1.0: far above the stretching limit
+    for dt in (0.0, -1.0, 1.0):      # 1.0: more than 16 sub-steps of the stretching limit
         with pytest.raises(fsa.FsaError) as e:
             p.step(F, dt)
         assert e.value.code == fsa.EINVAL
