@@ -103,15 +103,19 @@ def test_learned_form_needs_a_network(fsa_mod):
     assert e.value.code == fsa_mod.ESTATE
 
 
-def test_harvest_in_3d_unsupported(fsa_mod):
+def test_harvest_rejections_and_a_uniform_3d_state(fsa_mod):
+    """A keep rate outside [0, 1] is refused; a uniform 3D state has no significant side."""
     import torch
 
     case = _box(dim=3, n=12)
     s = fsa_mod.Solver(case)
     Q = torch.from_numpy(W.uniform_state(case)).cuda()
-    with pytest.raises(fsa_mod.FsaError) as e:
-        s.harvest(Q, 1.0, 1, 16)
-    assert e.value.code == fsa_mod.EUNSUPPORTED
+    for rate in (-0.5, 1.5, float("nan")):
+        with pytest.raises(fsa_mod.FsaError) as e:
+            s.harvest(Q, rate, 1, 16)
+        assert e.value.code == fsa_mod.EINVAL
+    feats, labels, n = s.harvest(Q, 1.0, 1, 16)
+    assert n == 0 and feats.shape[0] == 0
 
 
 def test_coupled_steps_need_the_plates_markers(fsa_mod):
