@@ -43,6 +43,14 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_stage2d_teno5_2048_pmc.txt")
 KERNEL_SOURCES = ["paper_1905_00182_amd/csrc/k_stage2d.hip", "paper_1905_00182_amd/csrc/fsa_dev.hpp"]
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """A progress line on stderr (the JSON result is the one line on stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_hash():
     h = hashlib.sha256()
     for s in KERNEL_SOURCES:
@@ -171,6 +179,7 @@ def variants(case, Q0, nsteps, every=10, plate_steps=None):
     net, losses = selector.train(F, L)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    progress(f"selector trained on {F.shape[0]} sides in {t_train:.1f} s")
     nprobe = case.probes.shape[1]
     rings = case.with_(probes=np.concatenate([case.probes, W.ring_probes(nprobe, 10.0)], axis=1))
     rec = None
@@ -185,6 +194,7 @@ def variants(case, Q0, nsteps, every=10, plate_steps=None):
              ("learned32_stride3", "learned32", net, 3))
     for name, prec, n, stride in forms:
         runs[name] = full_run(rings.with_(precision=prec, extra={"selector_stride": stride}), Q0, nsteps, every, n)
+        progress(f"C2 {name}: {nsteps} steps in {runs[name][0]:.2f} s")
 
     def err(a, b):
         return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
@@ -210,9 +220,13 @@ def variants(case, Q0, nsteps, every=10, plate_steps=None):
                 e["note"] = "keep patterns from each step's first stage, reused by its other two stages"
         res[name] = e
     res["c5_flapping_plate"] = flapping_plate(net, nsteps=plate_steps)
+    progress("C5 rigid plate done")
     res["c5_flexible_plate_m1"] = flapping_plate(net, nsteps=plate_steps, flexible=True, mass_ratio=1.0)
+    progress("C5 flexible plate, mass ratio 1, done")
     res["c5_flexible_plate"] = flapping_plate(net, nsteps=plate_steps, flexible=True)
+    progress("C5 flexible plate, mass ratio 5, done")
     res["hovering_insect"] = hovering_insect(net, nsteps=plate_steps)
+    progress("hovering insect done")
     res["run"] = {"steps": nsteps, "probes_per_ring": nprobe, "probe_every": every,
                   "max_probe_dp_r50": float(dp64[:, :nprobe].abs().max()),
                   "max_probe_dp_r10": float(dp64[:, nprobe:].abs().max()),
@@ -356,6 +370,7 @@ def three_d(steps=3):
                      "stage_kernels_ms_per_stage": round(kms / max(nl, 1), 3)}
         del Q
         torch.cuda.empty_cache()
+        progress(f"3D {name}: {out[name]['value']} Mcell-stage/s")
     return out
 
 
@@ -376,6 +391,8 @@ def main():
     ap.add_argument("--scheme", default="teno5", choices=["teno5", "weno5js"])
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
+    ap.add_argument("--only-3d", action="store_true",
+                    help="only the 3D sphere-case rates, --steps steps each (for profiling the 3D kernels)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver has no "
@@ -395,6 +412,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": b.numel() * 8,
                           "launches": 3}), flush=True)
+        return
+    if args.only_3d:
+        print(json.dumps({"three_d": three_d(args.steps)}), flush=True)
         return
     case = W.config2()
     if args.scheme != case.scheme:
@@ -420,6 +440,7 @@ def main():
         return wall, kms, launches, Q, s
 
     wall, kms, launches, Q64, s = run(case)
+    progress(f"headline: {args.steps} steps in {wall:.3f} s")
     cell_stages = case.ncell * 3 * args.steps
     value = cell_stages / wall / 1e6
     per_launch_ms = kms / max(launches, 1)
@@ -468,6 +489,7 @@ def main():
         out["variants"] = variants(case, Q0, args.variant_steps, plate_steps=args.plate_steps)
         out["variants"]["three_d"] = three_d()
     if not args.no_cpu and args.cpu_steps > 0:
+        progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
