@@ -285,8 +285,97 @@ static void phys_flux(const ora_ctx* c, const double* q, int dir, double* f)
     f[dim + 1] = (q[dim + 1] + p) * u[dir];
 }
 
+/* Eigenvectors of the flux Jacobian dF_dir/dQ at the Roe average of the conserved states qa
+ * and qb (Roe 1981): with r = sqrt(rho), the velocity and the total enthalpy H = (E + p)/rho
+ * averaged with weights r_a, r_b, |u|^2 = sum u_a^2 and c^2 = (gamma - 1)(H - |u|^2/2).  Along
+ * the unit normal n = e_dir, u_n = u_dir, the right eigenvectors (columns, conserved
+ * components rho, m_1..m_dim, E) are
+ *   u_n - c:  [1, u - c n, H - u_n c]
+ *   entropy:  [1, u, |u|^2/2]
+ *   shear t:  [0, e_t, u_t]          for each tangential direction t != dir
+ *   u_n + c:  [1, u + c n, H + u_n c]
+ * and, with b1 = (gamma - 1)/c^2 and b2 = b1 |u|^2/2, the left ones (rows, R's inverse)
+ *   u_n - c:  [(b2 + u_n/c)/2, -(b1 u + n/c)/2, b1/2]
+ *   entropy:  [1 - b2, b1 u, -b1]
+ *   shear t:  [-u_t, e_t, 0]
+ *   u_n + c:  [(b2 - u_n/c)/2, -(b1 u - n/c)/2, b1/2]. */
+static void roe_vectors(const ora_ctx* c, const double* qa, const double* qb, int dir, double L[5][5], double R[5][5])
+{
+    int dim = c->d.dim, nq = c->nq;
+    double gm = c->d.gamma;
+    double ua[3], ub[3], pa, pb;
+    primitives(c, qa, ua, &pa);
+    primitives(c, qb, ub, &pb);
+    double ra = sqrt(qa[0]), rb = sqrt(qb[0]);
+    double Ha = (qa[dim + 1] + pa) / qa[0], Hb = (qb[dim + 1] + pb) / qb[0];
+    double u[3] = {0.0, 0.0, 0.0};
+    double q2 = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        u[a] = (ra * ua[a] + rb * ub[a]) / (ra + rb);
+        q2 += u[a] * u[a];
+    }
+    double H = (ra * Ha + rb * Hb) / (ra + rb);
+    double cs = sqrt((gm - 1.0) * (H - 0.5 * q2));
+    double un = u[dir];
+    double b1 = (gm - 1.0) / (cs * cs), b2 = 0.5 * b1 * q2;
+    for (int m = 0; m < nq; ++m)
+        for (int k = 0; k < nq; ++k) L[k][m] = R[m][k] = 0.0;
+    /* field 0: u_n - c; field 1: entropy; fields 2..dim: shear; field dim + 1: u_n + c */
+    R[0][0] = 1.0;
+    R[0][1] = 1.0;
+    R[0][nq - 1] = 1.0;
+    for (int a = 0; a < dim; ++a) {
+        double na = a == dir ? 1.0 : 0.0;
+        R[1 + a][0] = u[a] - cs * na;
+        R[1 + a][1] = u[a];
+        R[1 + a][nq - 1] = u[a] + cs * na;
+    }
+    R[nq - 1][0] = H - un * cs;
+    R[nq - 1][1] = 0.5 * q2;
+    R[nq - 1][nq - 1] = H + un * cs;
+    L[0][0] = 0.5 * (b2 + un / cs);
+    L[1][0] = 1.0 - b2;
+    L[nq - 1][0] = 0.5 * (b2 - un / cs);
+    for (int a = 0; a < dim; ++a) {
+        double na = a == dir ? 1.0 : 0.0;
+        L[0][1 + a] = -0.5 * (b1 * u[a] + na / cs);
+        L[1][1 + a] = b1 * u[a];
+        L[nq - 1][1 + a] = -0.5 * (b1 * u[a] - na / cs);
+    }
+    L[0][nq - 1] = 0.5 * b1;
+    L[1][nq - 1] = -b1;
+    L[nq - 1][nq - 1] = 0.5 * b1;
+    int k = 2;
+    for (int t = 0; t < dim; ++t) {
+        if (t == dir) continue;
+        R[1 + t][k] = 1.0;
+        R[nq - 1][k] = u[t];
+        L[k][0] = -u[t];
+        L[k][1 + t] = 1.0;
+        ++k;
+    }
+}
+
+int ora_char_vectors(const ora_ctx* c, const double* qa, const double* qb, int dir, double* L, double* R)
+{
+    if (!c || !qa || !qb || !L || !R || dir < 0 || dir >= c->d.dim) return -1;
+    double Lm[5][5], Rm[5][5];
+    roe_vectors(c, qa, qb, dir, Lm, Rm);
+    for (int a = 0; a < c->nq; ++a)
+        for (int b = 0; b < c->nq; ++b) {
+            L[a * c->nq + b] = Lm[a][b];
+            R[a * c->nq + b] = Rm[a][b];
+        }
+    return 0;
+}
+
 /* Numerical flux at the face between cell idx and idx + e_dir:
- * F_hat = rec+(f+_{i-2..i+2}) + rec-(f-_{i+3..i-1}), f+- = (F +- alpha Q)/2. */
+ * F_hat = rec+(f+_{i-2..i+2}) + rec-(f-_{i+3..i-1}), f+- = (F +- alpha Q)/2, component by
+ * component; or, characteristic-wise (charwise = 1; the variables the schemes act on are a
+ * reading, Jiang & Shu 1996 reconstruct characteristic fields), with L and R the eigenvectors
+ * at the Roe average of cells i and i + 1: g+-_s = L f+-_s for the six cells, each field
+ * reconstructed, F_hat = R (rec+(g+) + rec-(g-)).  A global Lax-Friedrichs splitting is
+ * linear in Q and F, so projecting the split fluxes splits the projected ones alike. */
 static void face_flux(const ora_ctx* c, const double* Q, int dir, const long* idx, double alpha, double* Fh)
 {
     int nq = c->nq;
@@ -303,6 +392,40 @@ static void face_flux(const ora_ctx* c, const double* Q, int dir, const long* id
         }
     }
     const ora_desc* dd = &c->d;
+    if (dd->charwise) {
+        double qa[5], qb[5];
+        fetch(c, Q, idx[0], idx[1], idx[2], qa);
+        long ib[3] = {idx[0], idx[1], idx[2]};
+        ib[dir] += 1;
+        fetch(c, Q, ib[0], ib[1], ib[2], qb);
+        double L[5][5], R[5][5];
+        roe_vectors(c, qa, qb, dir, L, R);
+        double gp[6][5], gm[6][5];
+        for (int s = 0; s < 6; ++s)
+            for (int k = 0; k < nq; ++k) {
+                double a = 0.0, b = 0.0;
+                for (int m = 0; m < nq; ++m) {
+                    a += L[k][m] * fp[s][m];
+                    b += L[k][m] * fm[s][m];
+                }
+                gp[s][k] = a;
+                gm[s][k] = b;
+            }
+        double gh[5];
+        for (int k = 0; k < nq; ++k) {
+            double plus = ora_recon5(gp[0][k], gp[1][k], gp[2][k], gp[3][k], gp[4][k], dd->scheme,
+                                     dd->weno_eps, dd->teno_ct, dd->teno_eps);
+            double minus = ora_recon5(gm[5][k], gm[4][k], gm[3][k], gm[2][k], gm[1][k], dd->scheme,
+                                      dd->weno_eps, dd->teno_ct, dd->teno_eps);
+            gh[k] = plus + minus;
+        }
+        for (int m = 0; m < nq; ++m) {
+            double a = 0.0;
+            for (int k = 0; k < nq; ++k) a += R[m][k] * gh[k];
+            Fh[m] = a;
+        }
+        return;
+    }
     for (int m = 0; m < nq; ++m) {
         double plus = ora_recon5(fp[0][m], fp[1][m], fp[2][m], fp[3][m], fp[4][m], dd->scheme,
                                  dd->weno_eps, dd->teno_ct, dd->teno_eps);
@@ -1321,6 +1444,7 @@ ora_ctx* ora_create(const ora_desc* desc)
         if (desc->n[d] < 1) return NULL;
     if (desc->dim == 2 && desc->n[2] != 1) return NULL;
     if (!(desc->h > 0.0)) return NULL;
+    if (desc->charwise != 0 && desc->charwise != 1) return NULL;
     ora_ctx* c = (ora_ctx*)calloc(1, sizeof(ora_ctx));
     c->d = *desc;
     c->nq = desc->dim + 2;

@@ -62,6 +62,10 @@ typedef struct ora_desc {
     double   src_b;
     double   src_omega;
     double   src_x[3];
+    /* variables the reconstruction acts on: 0 = the conserved components, one by one;
+       1 = the characteristic fields of the flux Jacobian along the face normal at the Roe
+       average of the two cells beside the face (see ora.c) */
+    int32_t  charwise;
 } ora_desc;
 
 typedef struct ora_ctx ora_ctx;
@@ -117,6 +121,12 @@ int ora_face_significant(const ora_ctx* c, const double* Q, int dir, long i, lon
  *   the wave speeds alpha[3], the five upwind-ordered split-flux values v[n][5] and
  *   chi_k[n][3]. */
 int ora_record_stages(ora_ctx* c, double* buf);
+/* The characteristic-wise reconstruction's eigenvectors (a test hook): left rows L[nq][nq]
+ * and right columns R[nq][nq] (row-major, R[m * nq + k] = component m of field k) of the flux
+ * Jacobian along dir at the Roe average of the conserved states qa and qb; fields in the
+ * order u_n - c, entropy, the shear waves of the tangential directions in increasing order,
+ * u_n + c. */
+int ora_char_vectors(const ora_ctx* c, const double* qa, const double* qb, int dir, double* L, double* R);
 /* Threads of the oracle's OpenMP loops (n < 1: unchanged); returns the count in effect. */
 int ora_threads(int n);
 int ora_teno_bits(const ora_ctx* c, const double* Q, uint32_t* out);

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libora.so")
 
 BC = {"periodic": 0, "extrap": 1, "inflow": 2, "nonreflect": 3}
 SCHEME = {"weno5js": 0, "teno5": 1}
+VARIABLES = {"component": 0, "characteristic": 1}
 MOTION = {"static": 0, "rotating": 1, "external": 2}
 TERMS = {"conv_x": 1, "conv_y": 2, "conv_z": 4, "visc": 8, "ib": 16, "sponge": 32, "all": 63}
 
@@ -43,6 +44,7 @@ class OraDesc(C.Structure):
         ("src_b", C.c_double),
         ("src_omega", C.c_double),
         ("src_x", C.c_double * 3),
+        ("charwise", C.c_int32),
     ]
 
 
@@ -79,6 +81,7 @@ def lib():
         _lib.ora_teno_flags_n.argtypes = [dp, C.c_long, d, d, vp]
         _lib.ora_threads.argtypes = [C.c_int]
         _lib.ora_record_stages.argtypes = [vp, vp]
+        _lib.ora_char_vectors.argtypes = [vp, dp, dp, C.c_int, dp, dp]
         _lib.ora_teno_bits.argtypes = [vp, dp, vp]
         _lib.ora_teno_values_n.argtypes = [vp, dp, dp, C.c_long, vp, vp, vp, dp, dp]
         _lib.ora_delta4.restype = d
@@ -174,6 +177,7 @@ def make_desc(case) -> OraDesc:
     d.src_omega = case.src_omega
     for a in range(3):
         d.src_x[a] = case.src_x[a]
+    d.charwise = VARIABLES[case.variables]
     return d
 
 
@@ -326,6 +330,18 @@ class Oracle:
         out = np.empty((self.dim, self.nm))
         self._check(lib().ora_marker_force(self.ctx, _ptr(out)), "marker_force")
         return out
+
+    def char_vectors(self, qa, qb, direction):
+        """Left rows L[nq][nq] and right columns R[nq][nq] of the characteristic-wise
+        reconstruction at the Roe average of the conserved states qa, qb along `direction`."""
+        qa = np.ascontiguousarray(qa, dtype=np.float64)
+        qb = np.ascontiguousarray(qb, dtype=np.float64)
+        L = np.zeros((self.nq, self.nq))
+        R = np.zeros((self.nq, self.nq))
+        rc = lib().ora_char_vectors(self.ctx, _ptr(qa), _ptr(qb), direction, _ptr(L), _ptr(R))
+        if rc != 0:
+            raise ValueError("ora_char_vectors failed")
+        return L, R
 
     # -- test hooks on the TENO5 decisions
     def record_stages(self, on=True):

@@ -56,6 +56,9 @@ class Case:
     src_omega: float = 2.0 * np.pi
     src_x: tuple = (2.0, 0.0, 0.0)
     precision: str = "fp64"
+    # the variables the reconstruction acts on: "component" (the conserved components one by
+    # one) or "characteristic" (the flux Jacobian's characteristic fields at each face)
+    variables: str = "component"
     markers: Optional[dict] = None
     probes: Optional[np.ndarray] = None
     dt: float = 0.0
