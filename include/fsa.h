@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define FSA_ABI_VERSION 3
+#define FSA_ABI_VERSION 4
 
 enum {
     FSA_OK = 0,
@@ -73,6 +73,17 @@ enum { FSA_WENO5JS = 0, FSA_TENO5 = 1 };
  * FP64; FP32 on deviations from the far field (precision form); FP32 with the sub-stencils
  * chosen by the learned selector (fsa_mlp_set), plain TENO5 on low-confidence faces. */
 enum { FSA_FP64 = 0, FSA_MIXED32 = 1, FSA_LEARNED32 = 2 };
+/* Variables the reconstruction acts on.  COMPONENT: the conserved components, one by one
+ * (global Lax-Friedrichs splitting, component-wise).  CHARACTERISTIC (FP64 only; other
+ * precisions: FSA_EUNSUPPORTED): at each face the split fluxes of the six cells are projected
+ * on the left eigenvectors of the flux Jacobian along the face normal at the Roe average of
+ * the face's two cells, each characteristic field is reconstructed by the scheme, and the
+ * face flux is recombined with the right eigenvectors (Jiang & Shu 1996); the paper does not
+ * state which variables its schemes act on.  Fields are ordered u_n - c, entropy, shear
+ * (tangential directions in increasing order), u_n + c; with r = sqrt(rho) weights the Roe
+ * average takes u and H = (E + p)/rho, c^2 = (gamma - 1)(H - |u|^2/2).  In 2D this form runs
+ * as separate stress, face and stage passes. */
+enum { FSA_COMPONENT = 0, FSA_CHARACTERISTIC = 1 };
 /* Marker motion. */
 enum { FSA_STATIC = 0, FSA_ROTATING = 1, FSA_EXTERNAL = 2 };
 /* Right-hand-side terms (bit mask). */
@@ -143,6 +154,7 @@ typedef struct fsa_desc {
     int32_t  max_markers;
     int32_t  max_probes;
     int64_t  max_window_cells;
+    int32_t  variables;           /* FSA_COMPONENT or FSA_CHARACTERISTIC */
 } fsa_desc;
 
 typedef struct fsa_ctx fsa_ctx;
@@ -296,8 +308,8 @@ int32_t fsa_harvest(fsa_ctx* ctx, const double* d_Q, double keep_rate, uint64_t 
  * bits 3c..3c+2 (side "+") and 16+3c.. (side "-") for component c. */
 int32_t fsa_face_flags(fsa_ctx* ctx, const double* d_Q, uint32_t* d_flags_x, uint32_t* d_flags_y);
 
-/* Test read-out of the TENO5 sub-stencil decisions (FP64 TENO5 only; FSA_EUNSUPPORTED
- * otherwise): while d_bits (DEVICE, uint32) is set, every right-hand side and SSP-RK3 stage
+/* Test read-out of the TENO5 sub-stencil decisions (component-wise FP64 TENO5 only;
+ * FSA_EUNSUPPORTED otherwise): while d_bits (DEVICE, uint32) is set, every right-hand side and SSP-RK3 stage
  * enqueued on ctx also writes the keep pattern its reconstruction chose at every face, for
  * the state that stage evaluates, into d_bits[stage][faces] (a lone fsa_rhs: stage 0; RK3
  * stages 0, 1, 2; a multi-step call leaves its last step's): x faces [nz][ny][nx+1], then y

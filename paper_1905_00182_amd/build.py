@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfsa.so")
-SOURCES = ["fsa_api.hip", "k_stage2d.hip", "k_stage3d.hip", "k_ib.hip", "k_mlp.hip", "k_faces2d.hip", "k_nrbc.hip",
-           "plate.cpp"]
+SOURCES = ["fsa_api.hip", "k_stage2d.hip", "k_stage3d.hip", "k_pass2d.hip", "k_ib.hip", "k_mlp.hip", "k_faces2d.hip",
+           "k_nrbc.hip", "plate.cpp"]
 ARCH = os.environ.get("FSA_OFFLOAD_ARCH", "gfx950")
 
 

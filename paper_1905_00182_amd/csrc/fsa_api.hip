@@ -36,7 +36,8 @@ struct fsa_ctx {
     double* Qb = nullptr;
     unsigned long long* abits = nullptr; // alpha slots: [4][3]
     unsigned long long* apart = nullptr; // per-block / per-wave partial maxima [apart_n][3]
-    unsigned char* stress3d = nullptr;   // 3D: tau and b with two ghost layers, [9][ext cells] of T
+    unsigned char* stress3d = nullptr;   // 3D: tau and b with two ghost layers, [9][ext cells] of T;
+                                         // 2D characteristic-wise: [5][ext cells] of double
     unsigned char* faces3d = nullptr;    // 3D: face fluxes of the three directions, [5][faces] of T
     double* tot_part = nullptr;          // diagnostics: per-block partial totals
     double* tot_out = nullptr;
@@ -173,13 +174,18 @@ size_t carve(fsa_ctx* c, char* base)
     c->Qa = W.take<double>(nq * nc);
     c->Qb = W.take<double>(nq * nc);
     c->abits = W.take<unsigned long long>(12);
+    const bool pass2d = dim == 2 && d.variables == FSA_CHARACTERISTIC;
     c->apart_n = std::max<long long>(ALPHA_MAX_BLOCKS, dim == 3 ? stage3d_blocks(G) : stage2d_waves(G, 4));
+    if (pass2d) c->apart_n = std::max(c->apart_n, pass2d_blocks(G));
     c->apart = W.take<unsigned long long>(3 * (size_t)c->apart_n);
     c->ghosts = (dim == 2 && has_inflow(G)) ? W.take<double>((size_t)GHOST_STEPS * inflow_ghosts2d_elems(G)) : nullptr;
     if (dim == 3) {
         const size_t tsize = d.precision == FSA_MIXED32 ? sizeof(float) : sizeof(double);
         c->stress3d = W.take<unsigned char>((size_t)stress3d_elems(G) * tsize);
         c->faces3d = W.take<unsigned char>((size_t)faces3d_elems(G) * tsize);
+    } else if (pass2d) {
+        c->stress3d = W.take<unsigned char>((size_t)pass2d_stress_elems(G) * sizeof(double));
+        c->faces3d = W.take<unsigned char>((size_t)pass2d_face_elems(G) * sizeof(double));
     }
     c->tot_part = W.take<double>((size_t)totals_part_size((int)nq));
     c->tot_out = W.take<double>(5);
@@ -258,6 +264,11 @@ int validate(const fsa_desc* d, std::string& why)
         return FSA_EINVAL;
     }
     if (d->dim == 3 && d->precision == FSA_LEARNED32) { why = "the learned form is built for 2D"; return FSA_EUNSUPPORTED; }
+    if (d->variables != FSA_COMPONENT && d->variables != FSA_CHARACTERISTIC) { why = "bad variables"; return FSA_EINVAL; }
+    if (d->variables == FSA_CHARACTERISTIC && d->precision != FSA_FP64) {
+        why = "the characteristic-wise reconstruction is built in FP64";
+        return FSA_EUNSUPPORTED;
+    }
     if (d->selector_stride != 0 && d->selector_stride != 1 && d->selector_stride != 3) {
         why = "selector_stride must be 0, 1 or 3";
         return FSA_EINVAL;
@@ -692,11 +703,28 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
             if (rc != FSA_OK) return rc;
             HIPCHK(c, hipEventRecord(t0, c->stream));
         }
-        e = launch_stage3d(c->dK, c->G, c->d.scheme, c->d.precision, S, c->stress3d, c->faces3d, c->stream);
+        e = launch_stage3d(c->dK, c->G, c->d.scheme, c->d.precision, c->d.variables, S, c->stress3d, c->faces3d,
+                           c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "3D stage launch");
         if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
         if (S.nrbc) return finish_nrbc(c, S, acc);
         if (acc >= 0) defer_alpha_final(c, stage3d_blocks(c->G), acc);
+        return FSA_OK;
+    }
+    if (c->d.variables == FSA_CHARACTERISTIC) {
+        // 2D characteristic-wise: stress, face and stage passes (ghosts resolved where read)
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        if (c->timing) {
+            int rc = timing_pair(c, t0, t1);
+            if (rc != FSA_OK) return rc;
+            HIPCHK(c, hipEventRecord(t0, c->stream));
+        }
+        e = launch_pass2d(c->dK, c->G, c->d.scheme, c->d.terms, c->d.mu, S, static_cast<double*>((void*)c->stress3d),
+                          static_cast<double*>((void*)c->faces3d), c->stream);
+        if (e) return hipcheck(c, (hipError_t)e, "2D pass launch");
+        if (t1) HIPCHK(c, hipEventRecord(t1, c->stream));
+        if (S.nrbc) return finish_nrbc(c, S, acc);
+        if (acc >= 0) defer_alpha_final(c, pass2d_blocks(c->G), acc);
         return FSA_OK;
     }
     if (c->ghosts && (c->ghosts_step < 0 || c->step < c->ghosts_step || c->step >= c->ghosts_step + GHOST_STEPS)) {
@@ -1396,8 +1424,8 @@ int32_t fsa_diagnostics(fsa_ctx* c, const double* d_Q, double* h_totals, double*
 int32_t fsa_debug_teno_bits(fsa_ctx* c, uint32_t* d_bits)
 {
     if (!c) return FSA_EINVAL;
-    if (d_bits && (c->d.scheme != FSA_TENO5 || c->d.precision != FSA_FP64))
-        return fail(c, FSA_EUNSUPPORTED, "the keep-pattern read-out is built for FP64 TENO5");
+    if (d_bits && (c->d.scheme != FSA_TENO5 || c->d.precision != FSA_FP64 || c->d.variables != FSA_COMPONENT))
+        return fail(c, FSA_EUNSUPPORTED, "the keep-pattern read-out is built for component-wise FP64 TENO5");
     c->dbg_bits = d_bits;
     return FSA_OK;
 }

@@ -346,6 +346,130 @@ struct KConst {
     }
 };
 
+// ---------------------------------------------------------------------------------------
+// Characteristic-wise reconstruction: the eigenvectors of the flux Jacobian along D at the
+// Roe average of a face's two cells (Roe 1981).  With r = sqrt(rho) weights, the velocity u
+// and the total enthalpy H = (E + p)/rho are averaged, c^2 = (gamma - 1)(H - |u|^2/2),
+// b1 = (gamma - 1)/c^2, b2 = b1 |u|^2/2.  Fields k = 0: u_n - c, 1: entropy, 2..DIM: shear
+// along the tangential directions in increasing order, DIM + 1: u_n + c.  Left rows
+//   u_n -+ c: [(b2 +- u_n/c)/2, -(b1 u +- e_n/c)/2, b1/2]
+//   entropy:  [1 - b2, b1 u, -b1]        shear t: [-u_t, e_t, 0]
+// and right columns
+//   u_n -+ c: [1, u -+ c e_n, H -+ u_n c]
+//   entropy:  [1, u, |u|^2/2]            shear t: [0, e_t, u_t].
+// ---------------------------------------------------------------------------------------
+template <int DIM, int D>
+struct RoeVec {
+    static constexpr int NQ = DIM + 2;
+    double u[DIM];
+    double H, c, ic, b1, b2, q2h;
+
+    // tangential direction of shear field k (2 <= k <= DIM)
+    static constexpr int tang(int k) { return (k - 2) < D ? k - 2 : k - 1; }
+
+    // qa, qb conserved states [NQ], pa, pb their pressures
+    __device__ __forceinline__ RoeVec(const double* qa, double pa, const double* qb, double pb, double gm1)
+    {
+        const double ra = sqrt(qa[0]), rb = sqrt(qb[0]);
+        const double iw = 1.0 / (ra + rb);
+        const double ira = 1.0 / ra, irb = 1.0 / rb;     // r / rho = 1 / r
+        double q2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            u[a] = (qa[1 + a] * ira + qb[1 + a] * irb) * iw;
+            q2 = fma(u[a], u[a], q2);
+        }
+        H = ((qa[NQ - 1] + pa) * ira + (qb[NQ - 1] + pb) * irb) * iw;
+        q2h = 0.5 * q2;
+        c = sqrt(gm1 * (H - q2h));
+        ic = 1.0 / c;
+        b1 = gm1 * ic * ic;
+        b2 = b1 * q2h;
+    }
+
+    // g_k = l_k . f
+    template <int K>
+    __device__ __forceinline__ double left(const double* f) const
+    {
+        if constexpr (K == 0 || K == NQ - 1) {
+            constexpr double sg = K == 0 ? 1.0 : -1.0;
+            double g = 0.5 * fma(sg * u[D], ic, b2) * f[0];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const double la = a == D ? fma(b1, u[a], sg * ic) : b1 * u[a];
+                g = fma(-0.5 * la, f[1 + a], g);
+            }
+            return fma(0.5 * b1, f[NQ - 1], g);
+        } else if constexpr (K == 1) {
+            double g = (1.0 - b2) * f[0];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) g = fma(b1 * u[a], f[1 + a], g);
+            return fma(-b1, f[NQ - 1], g);
+        } else {
+            constexpr int t = tang(K);
+            return fma(-u[t], f[0], f[1 + t]);
+        }
+    }
+
+    // F += r_k g
+    template <int K>
+    __device__ __forceinline__ void right_add(double g, double* F) const
+    {
+        if constexpr (K == 0 || K == NQ - 1) {
+            constexpr double sg = K == 0 ? -1.0 : 1.0;
+            F[0] += g;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) F[1 + a] = fma(a == D ? fma(sg, c, u[a]) : u[a], g, F[1 + a]);
+            F[NQ - 1] = fma(fma(sg * u[D], c, H), g, F[NQ - 1]);
+        } else if constexpr (K == 1) {
+            F[0] += g;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) F[1 + a] = fma(u[a], g, F[1 + a]);
+            F[NQ - 1] = fma(q2h, g, F[NQ - 1]);
+        } else {
+            constexpr int t = tang(K);
+            F[1 + t] += g;
+            F[NQ - 1] = fma(u[t], g, F[NQ - 1]);
+        }
+    }
+};
+
+// One characteristic field KF of a face: the split fluxes of the six cells i-2..i+3,
+// g+- = l_KF . (F +- alpha q)/2 = (l.F +- alpha l.q)/2, reconstructed (g+ from i-2..i+2,
+// g- from i+3..i-1) and added to the face flux Fo along r_KF.
+template <int SCHEME, int DIM, int D, int KF>
+__device__ __forceinline__ void char_field(const RoeVec<DIM, D>& V, const double (&q)[6][DIM + 2],
+                                           const double (&F)[6][DIM + 2], double alpha, const Recon& R, double* Fo)
+{
+    double gp[6], gm[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const double lq = V.template left<KF>(q[s]), lF = V.template left<KF>(F[s]);
+        gp[s] = 0.5 * fma(alpha, lq, lF);
+        gm[s] = 0.5 * fma(-alpha, lq, lF);
+    }
+    const double g = recon5<SCHEME>(gp[0], gp[1], gp[2], gp[3], gp[4], R) +
+                     recon5<SCHEME>(gm[5], gm[4], gm[3], gm[2], gm[1], R);
+    V.template right_add<KF>(g, Fo);
+}
+
+// Characteristic-wise face flux Fo[DIM + 2] from the six cells' conserved states q, their
+// physical fluxes F along D and pressures p (the Roe average of cells 2 and 3, the two
+// beside the face).
+template <int SCHEME, int DIM, int D>
+__device__ __forceinline__ void char_face(const double (&q)[6][DIM + 2], const double (&F)[6][DIM + 2],
+                                          const double* p, double gm1, double alpha, const Recon& R, double* Fo)
+{
+    const RoeVec<DIM, D> V(q[2], p[2], q[3], p[3], gm1);
+#pragma unroll
+    for (int m = 0; m < DIM + 2; ++m) Fo[m] = 0.0;
+    char_field<SCHEME, DIM, D, 0>(V, q, F, alpha, R, Fo);
+    char_field<SCHEME, DIM, D, 1>(V, q, F, alpha, R, Fo);
+    char_field<SCHEME, DIM, D, 2>(V, q, F, alpha, R, Fo);
+    char_field<SCHEME, DIM, D, 3>(V, q, F, alpha, R, Fo);
+    if constexpr (DIM == 3) char_field<SCHEME, DIM, D, 4>(V, q, F, alpha, R, Fo);
+}
+
 // NaN-propagating maximum of non-negative doubles through their bit patterns: for x >= 0
 // the unsigned order of the bits is the numeric order, and every NaN pattern sorts above
 // +Inf.

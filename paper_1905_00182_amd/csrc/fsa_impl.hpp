@@ -85,10 +85,20 @@ bool has_inflow(const Grid& G);
 int launch_inflow_ghosts2d(const KConst* K, const Grid& G, long long step0, int nsteps, double* g, hipStream_t s);
 long long stage2d_waves(const Grid& G, int ty);
 // 3D: stress pass into `stress` ([9][(nx+4)(ny+4)(nz+4)] of T = double, or float in the
-// precision form), face-flux passes into `faces` (faces3d_elems of T), then the stage pass;
-// one wave-speed partial per block of the stage pass.
-int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, void* stress,
-                   void* faces, hipStream_t s);
+// precision form), face-flux passes into `faces` (faces3d_elems of T; variables = 1:
+// characteristic-wise, FP64 only), then the stage pass; one wave-speed partial per block of
+// the stage pass.
+int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, int variables, const StageArgs& A,
+                   void* stress, void* faces, hipStream_t s);
+// 2D in three passes (the characteristic-wise reconstruction, FP64): stress pass into
+// `stress` (pass2d_stress_elems doubles; skipped without viscosity), characteristic-wise
+// face-flux passes into `faces` (pass2d_face_elems doubles), then the stage pass; one
+// wave-speed partial per block of the stage pass (pass2d_blocks).
+int launch_pass2d(const KConst* K, const Grid& G, int scheme, int terms, double mu, const StageArgs& A,
+                  double* stress, double* faces, hipStream_t s);
+long long pass2d_stress_elems(const Grid& G);
+long long pass2d_face_elems(const Grid& G);
+long long pass2d_blocks(const Grid& G);
 long long stress3d_elems(const Grid& G);
 long long faces3d_elems(const Grid& G);
 long long stage3d_blocks(const Grid& G);

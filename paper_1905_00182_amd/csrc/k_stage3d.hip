@@ -7,7 +7,10 @@
 //    the velocities of each plane formed once into LDS.
 //  * k_faces3d<D>: one thread per face along direction D: the six cells i-2..i+3 give the
 //    split fluxes f+- = (F +- alpha Q)/2 of the five components and the face flux
-//    F^ = rec+(f+) + rec-(f-), stored per component [5][faces] (each face once).
+//    F^ = rec+(f+) + rec-(f-), stored per component [5][faces] (each face once); in the
+//    characteristic-wise instantiation (FP64) the split fluxes are projected on the
+//    eigenvectors at the Roe average of the face's two cells, reconstructed field by field
+//    and recombined (char_face).
 //  * k_stage3d: per interior cell, the flux differences of the three face buffers, the
 //    viscous divergence from the stress buffer, the penalty-IB source from the window
 //    array, the sponge, the RK3 combination, and one wave-speed partial per block.
@@ -188,7 +191,8 @@ __host__ __device__ __forceinline__ long long faces_of(const Grid& G)
 // Face fluxes along D: threads cover the faces f = 0..n_D along D (x index for D = 0, y index
 // for D = 1, z index for D = 2) and the cells of the two other directions.
 // DBG (FP64 TENO5 only) also writes each face's keep patterns to dbg, in the face layout.
-template <int SCHEME, class T, int D, bool DBG = false>
+// CH (FP64 only): characteristic-wise reconstruction.
+template <int SCHEME, class T, int D, bool DBG = false, bool CH = false>
 __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ K, const double* __restrict__ Q,
                                                      long long step, const unsigned long long* __restrict__ abits,
                                                      T* __restrict__ Fh, unsigned* __restrict__ dbg)
@@ -238,6 +242,22 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
     const double* Finf = D == 0 ? K->Fx_inf : (D == 1 ? K->Fy_inf : K->Fz_inf);
     const long long nf = faces_of<D>(G);
     const long long o = face_index<D>(G, f, D == 0 ? 0 : xi, D == 1 ? 0 : yi, D == 2 ? 0 : zi);
+    if constexpr (CH) {
+        static_assert(F64 && !DBG, "characteristic-wise faces are FP64");
+        double Fs[6][5];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            Fs[s][0] = q[s][1 + D];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) Fs[s][1 + a] = a == D ? fma(q[s][1 + a], ud[s], p[s]) : q[s][1 + a] * ud[s];
+            Fs[s][4] = (q[s][4] + p[s]) * ud[s];
+        }
+        double Fo[5];
+        char_face<SCHEME, 3, D>(q, Fs, p, K->P.gm1, alpha, R, Fo);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) Fh[c * nf + o] = Fo[c];
+        return;
+    }
     unsigned word = 0u;
     (void)word;
     (void)dbg;
@@ -430,7 +450,7 @@ long long faces3d_elems(const Grid& G)
 }
 
 template <int SCHEME, class T>
-static void launch_faces(const KConst* K, const Grid& G, const StageArgs& A, T* F, hipStream_t s)
+static void launch_faces(const KConst* K, const Grid& G, const StageArgs& A, T* F, bool ch, hipStream_t s)
 {
     const dim3 block(BX * BY);
     T* Fx = F;
@@ -439,6 +459,14 @@ static void launch_faces(const KConst* K, const Grid& G, const StageArgs& A, T* 
     const dim3 gx((G.n[0] + 1 + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
     const dim3 gy((G.n[0] + BX - 1) / BX, (G.n[1] + 1 + BY - 1) / BY, G.n[2]);
     const dim3 gz((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2] + 1);
+    if constexpr (std::is_same<T, double>::value) {
+        if (ch) {
+            hipLaunchKernelGGL((k_faces3d<SCHEME, T, 0, false, true>), gx, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, nullptr);
+            hipLaunchKernelGGL((k_faces3d<SCHEME, T, 1, false, true>), gy, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fy, nullptr);
+            hipLaunchKernelGGL((k_faces3d<SCHEME, T, 2, false, true>), gz, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fz, nullptr);
+            return;
+        }
+    }
     if constexpr (SCHEME == TENO5 && std::is_same<T, double>::value) {
         if (A.dbg_x) {
             hipLaunchKernelGGL((k_faces3d<SCHEME, T, 0, true>), gx, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, A.dbg_x);
@@ -452,10 +480,13 @@ static void launch_faces(const KConst* K, const Grid& G, const StageArgs& A, T* 
     hipLaunchKernelGGL((k_faces3d<SCHEME, T, 2>), gz, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fz, nullptr);
 }
 
-int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, const StageArgs& A, void* stress,
-                   void* faces, hipStream_t s)
+int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, int variables, const StageArgs& A,
+                   void* stress, void* faces, hipStream_t s)
 {
-    if (A.dbg_x && (scheme != TENO5 || precision != 0 || !A.dbg_y || !A.dbg_z)) return (int)hipErrorInvalidValue;
+    if (A.dbg_x && (scheme != TENO5 || precision != 0 || variables != 0 || !A.dbg_y || !A.dbg_z))
+        return (int)hipErrorInvalidValue;
+    if (variables != 0 && precision != 0) return (int)hipErrorInvalidValue;
+    const bool ch = variables != 0;
     const dim3 block(BX * BY);
     const dim3 gs((G.n[0] + 4 + BX - 1) / BX, (G.n[1] + 4 + BY - 1) / BY, (G.n[2] + 4 + SZ - 1) / SZ);
     const dim3 gr((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
@@ -463,8 +494,8 @@ int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, co
         float* S = static_cast<float*>(stress);
         float* F = static_cast<float*>(faces);
         hipLaunchKernelGGL(k_stress3d<float>, gs, block, 0, s, K, A.Qs, A.step, S);
-        if (scheme == TENO5) launch_faces<TENO5, float>(K, G, A, F, s);
-        else launch_faces<WENO5JS, float>(K, G, A, F, s);
+        if (scheme == TENO5) launch_faces<TENO5, float>(K, G, A, F, false, s);
+        else launch_faces<WENO5JS, float>(K, G, A, F, false, s);
         const float* Fx = F;
         const float* Fy = Fx + 5 * faces_of<0>(G);
         const float* Fz = Fy + 5 * faces_of<1>(G);
@@ -473,8 +504,8 @@ int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, co
         double* S = static_cast<double*>(stress);
         double* F = static_cast<double*>(faces);
         hipLaunchKernelGGL(k_stress3d<double>, gs, block, 0, s, K, A.Qs, A.step, S);
-        if (scheme == TENO5) launch_faces<TENO5, double>(K, G, A, F, s);
-        else launch_faces<WENO5JS, double>(K, G, A, F, s);
+        if (scheme == TENO5) launch_faces<TENO5, double>(K, G, A, F, ch, s);
+        else launch_faces<WENO5JS, double>(K, G, A, F, ch, s);
         const double* Fx = F;
         const double* Fy = Fx + 5 * faces_of<0>(G);
         const double* Fz = Fy + 5 * faces_of<1>(G);

@@ -17,6 +17,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -
 BC = {"periodic": 0, "extrap": 1, "inflow": 2, "nonreflect": 3}
 SCHEME = {"weno5js": 0, "teno5": 1}
 PRECISION = {"fp64": 0, "mixed32": 1, "learned32": 2}
+VARIABLES = {"component": 0, "characteristic": 1}
+ABI_VERSION = 4          # the fsa_desc / fsa_stats layout mirrored below (include/fsa.h)
 MLP_NPARAM = 1667
 MOTION = {"static": 0, "rotating": 1, "external": 2}
 TERM = {"conv_x": 1, "conv_y": 2, "conv_z": 4, "visc": 8, "ib": 16, "sponge": 32, "all": 63}
@@ -59,6 +61,7 @@ class FsaDesc(C.Structure):
         ("max_markers", C.c_int32),
         ("max_probes", C.c_int32),
         ("max_window_cells", C.c_int64),
+        ("variables", C.c_int32),
     ]
 
 
@@ -231,6 +234,9 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        if L.fsa_abi_version() != ABI_VERSION:
+            raise RuntimeError(f"{LIB_PATH} has ABI version {L.fsa_abi_version()}, the binding mirrors "
+                               f"{ABI_VERSION}: rebuild it with __graft_entry__.build()")
         _lib = L
     return _lib
 
@@ -268,6 +274,7 @@ def make_desc(case, nan_check=False) -> FsaDesc:
     d.ib_alpha = case.ib_alpha
     d.ib_beta = case.ib_beta
     d.max_markers, d.max_probes, d.max_window_cells = capacities(case)
+    d.variables = VARIABLES[case.variables]
     return d
 
 

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(fsa.LIB_PATH)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
-    assert fsa.lib().fsa_abi_version() == 3
+    assert fsa.lib().fsa_abi_version() == 4
     assert fsa.lib().fsa_status_str(-4) == b"non-finite state"
 
 
