@@ -30,6 +30,11 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Grids smaller than this run their loops on one thread: there a thread team's start-up and
+ * barriers cost more than the loop (the results are the same either way: every loop has
+ * disjoint writes and a fixed order per element). */
+#define ORA_PAR_MIN_CELLS 16384
+
 struct ora_ctx {
     ora_desc d;
     int nq;            /* dim + 2 conserved components */
@@ -652,7 +657,7 @@ static double* ib_force(ora_ctx* c, const double* Q, double t)
     int dim = c->d.dim;
     long nc = c->ncell;
     double* vel = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)nc);
-    #pragma omp parallel for
+    #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS)
     for (long n = 0; n < nc; ++n)
         for (int a = 0; a < dim; ++a) vel[(long)a * nc + n] = Q[(long)(1 + a) * nc + n] / Q[n];
     for (int k = 0; k < c->nm; ++k) {
@@ -836,7 +841,7 @@ int ora_rhs(ora_ctx* c, const double* Q, double* L)
         if (!conv_on(c, d)) continue;
         long nd = n_of(c, d);
         long nlines = nc / nd;
-        #pragma omp parallel for schedule(dynamic, 16)
+        #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS) schedule(dynamic, 16)
         for (long ln = 0; ln < nlines; ++ln) {
             long base[3];
             /* enumerate lines: the index along d is 0, the others run over the grid */
@@ -880,7 +885,7 @@ int ora_rhs(ora_ctx* c, const double* Q, double* L)
         double* tau = (double*)malloc(sizeof(double) * (size_t)ne * (size_t)ntau);
         double* bw = (double*)malloc(sizeof(double) * (size_t)ne * (size_t)nbw);
         long zoff = dim == 3 ? 2 : 0;
-        #pragma omp parallel for schedule(dynamic, 64)
+        #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS) schedule(dynamic, 64)
         for (long e = 0; e < ne; ++e) {
             long idx[3] = {e % ex - 2, (e / ex) % ey - 2, e / (ex * ey) - zoff};
             double t3[3][3] = {{0}}, b3[3] = {0};
@@ -890,7 +895,7 @@ int ora_rhs(ora_ctx* c, const double* Q, double* L)
                 bw[e * nbw + a] = b3[a];
             }
         }
-        #pragma omp parallel for schedule(dynamic, 64)
+        #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS) schedule(dynamic, 64)
         for (long n = 0; n < nc; ++n) {
             long idx[3];
             idx_of(c, n, idx);
@@ -915,7 +920,7 @@ int ora_rhs(ora_ctx* c, const double* Q, double* L)
     /* immersed-boundary source and sponge */
     double* fib = NULL;
     if ((c->d.terms & ORA_IB) && c->nm > 0) fib = ib_force(c, Q, c->t);
-    #pragma omp parallel for
+    #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS)
     for (long n = 0; n < nc; ++n) {
         double s[5] = {0, 0, 0, 0, 0};
         sources_at(c, Q, fib, n, s);
@@ -941,7 +946,7 @@ int ora_rhs_cells(ora_ctx* c, const double* Q, int64_t nlist, const int64_t* cel
             for (int a = 0; a < dim; ++a) fl[(long)a * nlist + l] = f[(long)a * nc + cells[l]];
         free(f);
     }
-    #pragma omp parallel for schedule(dynamic, 4)
+    #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS) schedule(dynamic, 4)
     for (int64_t l = 0; l < nlist; ++l) {
         long n = cells[l];
         long idx[3];
@@ -1141,7 +1146,7 @@ int ora_rk3_step(ora_ctx* c, double* Q, double dt)
     c->t = t0;
     if (c->record) memcpy(c->record, Qn, sizeof(double) * (size_t)len);
     ora_rhs(c, Qn, L);
-    #pragma omp parallel for
+    #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS)
     for (long i = 0; i < len; ++i) Qs[i] = Qn[i] + dt * L[i];
     if (ib)
         for (long i = 0; i < lm; ++i) c->xi[i] = xin[i] + dt * c->dxi[i];
@@ -1150,7 +1155,7 @@ int ora_rk3_step(ora_ctx* c, double* Q, double dt)
     c->t = t0 + dt;
     if (c->record) memcpy(c->record + len, Qs, sizeof(double) * (size_t)len);
     ora_rhs(c, Qs, L);
-    #pragma omp parallel for
+    #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS)
     for (long i = 0; i < len; ++i) Qs[i] = 0.75 * Qn[i] + 0.25 * (Qs[i] + dt * L[i]);
     if (ib)
         for (long i = 0; i < lm; ++i) c->xi[i] = 0.75 * xin[i] + 0.25 * (c->xi[i] + dt * c->dxi[i]);
@@ -1159,7 +1164,7 @@ int ora_rk3_step(ora_ctx* c, double* Q, double dt)
     c->t = t0 + 0.5 * dt;
     if (c->record) memcpy(c->record + 2 * len, Qs, sizeof(double) * (size_t)len);
     ora_rhs(c, Qs, L);
-    #pragma omp parallel for
+    #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS)
     for (long i = 0; i < len; ++i) Q[i] = (1.0 / 3.0) * Qn[i] + (2.0 / 3.0) * (Qs[i] + dt * L[i]);
     if (ib)
         for (long i = 0; i < lm; ++i)
@@ -1238,7 +1243,7 @@ int ora_teno_bits(const ora_ctx* c, const double* Q, uint32_t* out)
     long off = 0;
     for (int dir = 0; dir < c->d.dim; ++dir) {
         long nf = faces_along(c, dir);
-        #pragma omp parallel for
+        #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS)
         for (long lin = 0; lin < nf; ++lin) {
             long f, i, j, k;
             double fp[6][5], fm[6][5];
@@ -1270,7 +1275,7 @@ int ora_teno_values_n(const ora_ctx* c, const double* Q, const double* alpha, lo
         while (dir < c->d.dim && lin >= faces_along(c, dir)) lin -= faces_along(c, dir++);
         if (dir >= c->d.dim || m[e] < 0 || m[e] >= c->nq) return -1;
     }
-    #pragma omp parallel for
+    #pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS)
     for (long e = 0; e < n; ++e) {
         long lin = g[e];
         int dir = 0;
@@ -1339,7 +1344,7 @@ int ora_dilatation(const ora_ctx* c, const double* Q, double* out)
 {
     int dim = c->d.dim;
     long nc = c->ncell;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for if (c->ncell >= ORA_PAR_MIN_CELLS) schedule(static)
     for (long n = 0; n < nc; ++n) {
         long idx[3];
         idx_of(c, n, idx);
