@@ -84,6 +84,9 @@ enum { FSA_FP64 = 0, FSA_MIXED32 = 1, FSA_LEARNED32 = 2 };
  * average takes u and H = (E + p)/rho, c^2 = (gamma - 1)(H - |u|^2/2).  In 2D this form runs
  * as separate stress, face and stage passes. */
 enum { FSA_COMPONENT = 0, FSA_CHARACTERISTIC = 1 };
+/* Cell layers a stage's output at one cell depends on along each direction (the viscous
+ * terms: two for the stress, two for its divergence), the halo depth of a block. */
+enum { FSA_HALO = 4 };
 /* Marker motion. */
 enum { FSA_STATIC = 0, FSA_ROTATING = 1, FSA_EXTERNAL = 2 };
 /* Right-hand-side terms (bit mask). */
@@ -155,6 +158,14 @@ typedef struct fsa_desc {
     int32_t  max_probes;
     int64_t  max_window_cells;
     int32_t  variables;           /* FSA_COMPONENT or FSA_CHARACTERISTIC */
+    /* Placement in a larger grid (a block of a decomposed domain; global_n[d] = 0: none):
+     * local cell i along d is global cell i + origin[d] of a grid of global_n[d] cells whose
+     * lower corner is lo.  Cell positions (sponge, markers, probes, source) and the inflow
+     * noise counters are then those of the global grid, so a block computes its cells as the
+     * whole grid would.  origin may reach FSA_HALO cells below 0 and the block as far beyond
+     * global_n (halo layers wrapped across a periodic direction); otherwise FSA_EINVAL. */
+    int32_t  origin[3];
+    int32_t  global_n[3];
 } fsa_desc;
 
 typedef struct fsa_ctx fsa_ctx;
@@ -328,6 +339,55 @@ int32_t fsa_timing_read(fsa_ctx* ctx, double* ms, int64_t* launches);
 /* Wait for the stream; returns FSA_ENONFINITE if nan_check saw a NaN/Inf. */
 int32_t fsa_sync(fsa_ctx* ctx);
 int32_t fsa_stats_get(fsa_ctx* ctx, fsa_stats* out);
+
+/* ---------------------------------------------------------------------------------------
+ * Several blocks of one domain on one GPU: the one-GPU stand-in for the domain decomposition
+ * across processes that the paper's solver runs with MPI (Sec. 2).
+ *
+ * The domain desc describes is cut into nblocks slabs along its last direction (y in 2D, z
+ * in 3D), the first (n % nblocks) of them one cell layer thicker.  Each block is a context
+ * over its own layers plus FSA_HALO layers of each neighbouring block (across the domain's
+ * ends too when that direction is periodic), placed in the global grid with origin /
+ * global_n; the block's own boundary rule at a halo side is EXTRAP and only ever shapes the
+ * halo layers' output.  Every SSP-RK3 stage is enqueued on all blocks, then explicit device
+ * copies refresh each block's halo layers from its neighbours' stage output, and the global
+ * Lax-Friedrichs speeds of that output are the maximum over the blocks' own (the all-reduce
+ * of a multi-process run).  Each block holds the markers whose supports reach its own
+ * layers, in their global order.  The result equals one context's over the whole domain bit
+ * for bit.  Markers must be STATIC or ROTATING (positions fixed), probes and diagnostics are
+ * taken on the gathered state.  Every call is stream-ordered on hip_stream unless it says
+ * synchronising.
+ *
+ * Device memory: one workspace of fsa_mb_workspace_bytes (the blocks' contexts and states
+ * and the copy tables) owned by the caller; the library allocates host memory only.
+ * --------------------------------------------------------------------------------------- */
+typedef struct fsa_mb fsa_mb;
+/* Workspace bytes for desc in nblocks blocks.  FSA_EINVAL: invalid desc (its origin and
+ * global_n must be zero), nblocks < 1, or a block thinner than FSA_HALO layers. */
+int32_t fsa_mb_workspace_bytes(const fsa_desc* desc, int32_t nblocks, size_t* bytes);
+int32_t fsa_mb_init(const fsa_desc* desc, int32_t nblocks, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                    fsa_mb** out);
+int32_t fsa_mb_destroy(fsa_mb* mb);
+const char* fsa_mb_last_error(const fsa_mb* mb);
+/* Block b's first global layer, layer count, and halo layers below and above. */
+int32_t fsa_mb_block_info(const fsa_mb* mb, int32_t b, int32_t* first, int32_t* count, int32_t* halo_lo,
+                          int32_t* halo_hi);
+/* Markers of the whole domain (HOST arrays as fsa_set_markers; motion STATIC or ROTATING,
+ * else FSA_EUNSUPPORTED), shared out to the blocks whose layers their supports reach;
+ * resets the penalty integral.  Synchronising. */
+int32_t fsa_mb_set_markers(fsa_mb* mb, int32_t n, const double* X, const double* dV, const double* U,
+                           int32_t motion, double omega);
+/* The whole domain's state (DEVICE, [nq][cells] as fsa_rk3_step) into the blocks, halo
+ * layers included; resets time and step to zero. */
+int32_t fsa_mb_scatter(fsa_mb* mb, const double* d_Q);
+/* The blocks' own layers into the whole domain's state d_Q (DEVICE). */
+int32_t fsa_mb_gather(const fsa_mb* mb, double* d_Q);
+/* nsteps SSP-RK3 steps of size dt on the blocks, halo copies and the wave-speed maximum
+ * after every stage. */
+int32_t fsa_mb_rk3_steps(fsa_mb* mb, double dt, int32_t nsteps);
+/* Penalty force of the last stage per marker, h_F[dim][n] (HOST), each marker from a block
+ * holding it.  Synchronising. */
+int32_t fsa_mb_marker_force(fsa_mb* mb, double* h_F);
 
 #ifdef __cplusplus
 }

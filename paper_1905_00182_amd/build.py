@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfsa.so")
 SOURCES = ["fsa_api.hip", "k_stage2d.hip", "k_stage3d.hip", "k_pass2d.hip", "k_ib.hip", "k_mlp.hip", "k_faces2d.hip",
-           "k_nrbc.hip", "plate.cpp"]
+           "k_nrbc.hip", "k_halo.hip", "plate.cpp"]
 ARCH = os.environ.get("FSA_OFFLOAD_ARCH", "gfx950")
 
 

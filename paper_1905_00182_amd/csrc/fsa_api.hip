@@ -265,6 +265,16 @@ int validate(const fsa_desc* d, std::string& why)
     }
     if (d->dim == 3 && d->precision == FSA_LEARNED32) { why = "the learned form is built for 2D"; return FSA_EUNSUPPORTED; }
     if (d->variables != FSA_COMPONENT && d->variables != FSA_CHARACTERISTIC) { why = "bad variables"; return FSA_EINVAL; }
+    for (int k = 0; k < d->dim; ++k) {
+        if (d->global_n[k] == 0) {
+            if (d->origin[k] != 0) { why = "origin without global_n"; return FSA_EINVAL; }
+            continue;
+        }
+        if (d->global_n[k] < 1 || d->origin[k] < -FSA_HALO || d->origin[k] + d->n[k] > d->global_n[k] + FSA_HALO) {
+            why = "the block must lie within global_n (up to FSA_HALO cells beyond, for a wrapped halo)";
+            return FSA_EINVAL;
+        }
+    }
     if (d->variables == FSA_CHARACTERISTIC && d->precision != FSA_FP64) {
         why = "the characteristic-wise reconstruction is built in FP64";
         return FSA_EUNSUPPORTED;
@@ -296,6 +306,12 @@ void build_consts(fsa_ctx* c)
         G.bc[k][1] = d.bc[k][1];
     }
     G.ncell = (long long)G.n[0] * G.n[1] * G.n[2];
+    for (int k = 0; k < 3; ++k) {
+        const bool placed = k < d.dim && d.global_n[k] > 0;
+        G.org[k] = placed ? d.origin[k] : 0;
+        G.gn[k] = placed ? d.global_n[k] : G.n[k];
+    }
+    G.gncell = (long long)G.gn[0] * G.gn[1] * G.gn[2];
     G.h = d.h;
     G.inv_h = 1.0 / d.h;
     Phys& P = c->P;
@@ -379,7 +395,7 @@ bool support_inside(const fsa_ctx* c, int n, const double* X)
             const double x = X[(size_t)d * n + k];
             if (!std::isfinite(x)) return false;
             const double r0 = (x - c->d.lo[d]) / c->d.h - 0.5;
-            const double j0 = std::floor(r0) - 1.0;
+            const double j0 = std::floor(r0) - 1.0 - (double)c->G.org[d];   // (local cell index)
             if (j0 < 0.0 || j0 + 3.0 > (double)(c->G.n[d] - 1)) return false;
         }
     return true;
@@ -403,7 +419,7 @@ int window_lists(fsa_ctx* c, int* wlo, int* wn, std::vector<int>& count, std::ve
         hi[d] = -(1 << 30);
         for (int k = 0; k < n; ++k) {
             const double r0 = (c->hX[(size_t)d * n + k] - c->d.lo[d]) / c->d.h - 0.5;
-            const int j = (int)std::floor(r0) - 1;
+            const int j = (int)std::floor(r0) - 1 - c->G.org[d];   // (local cell index)
             j0[(size_t)k * 3 + d] = j;
             lo[d] = std::min(lo[d], j);
             hi[d] = std::max(hi[d], j + 3);
@@ -1489,6 +1505,393 @@ int32_t fsa_stats_get(fsa_ctx* c, fsa_stats* out)
         out->learned_sides = (int64_t)tot[0];
         out->fallback_sides = (int64_t)tot[1];
         out->significant_sides = (int64_t)tot[2];
+    }
+    return FSA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Several blocks of one domain on one GPU (fsa_mb_*, see fsa.h): slabs along the last
+// direction, each an ordinary context over its layers plus FSA_HALO halo layers per
+// neighbour, stepped stage by stage with explicit halo copies and the cross-block maximum of
+// the wave speeds after every stage.
+// ---------------------------------------------------------------------------------------
+struct fsa_mb {
+    fsa_desc whole;
+    int nb = 0, dir = 0, nq = 0;
+    long long plane = 0;                     // cells of one layer across the slab direction
+    bool periodic = false;
+    hipStream_t stream = nullptr;
+    std::vector<fsa_ctx*> blk;
+    std::vector<int> first, count, hlo, hhi;
+    std::vector<fsa_desc> bdesc;
+    std::vector<size_t> ws_off, q_off;       // workspace offsets of each block's context and state
+    size_t copy_off = 0, slot_off = 0, total = 0;
+    std::vector<double*> Q;                  // each block's state (own layers and halos)
+    CopyEntry* d_copy[3] = {nullptr, nullptr, nullptr};   // halo copies of stage outputs Qa, Qb, Q
+    int ncopy = 0;
+    long long copy_max = 0;
+    unsigned long long** d_slot_in = nullptr;   // per block: slot 1, its own maximum
+    unsigned long long** d_slot_out = nullptr;  // per block: slot 0, the global maximum
+    std::vector<std::vector<int>> marker_of;    // per block: global indices of its markers
+    std::vector<int> owner, owner_idx;          // per marker: a block holding it, its index there
+    int nm = 0;
+    std::string err;
+};
+
+namespace {
+
+int mb_fail(fsa_mb* m, int code, const std::string& msg)
+{
+    m->err = msg;
+    return code;
+}
+
+// The blocks of desc in nb slabs and their descriptors and workspace layout (device
+// pointers are not touched).
+int mb_plan(fsa_mb* m, const fsa_desc* desc, int nb, std::string& why)
+{
+    int rc = validate(desc, why);
+    if (rc == FSA_OK) rc = validate_caps(desc, why);
+    if (rc != FSA_OK) return rc;
+    for (int k = 0; k < 3; ++k)
+        if (desc->origin[k] != 0 || desc->global_n[k] != 0) {
+            why = "the whole domain's origin and global_n must be zero";
+            return FSA_EINVAL;
+        }
+    if (nb < 1) { why = "nblocks must be positive"; return FSA_EINVAL; }
+    m->whole = *desc;
+    m->nb = nb;
+    m->dir = desc->dim - 1;
+    m->nq = desc->dim + 2;
+    m->periodic = desc->bc[m->dir][0] == FSA_BC_PERIODIC;
+    m->plane = desc->dim == 3 ? (long long)desc->n[0] * desc->n[1] : (long long)desc->n[0];
+    const int N = desc->n[m->dir];
+    m->first.assign(nb, 0);
+    m->count.assign(nb, 0);
+    m->hlo.assign(nb, 0);
+    m->hhi.assign(nb, 0);
+    m->bdesc.assign(nb, *desc);
+    m->ws_off.assign(nb, 0);
+    m->q_off.assign(nb, 0);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        const size_t at = off;
+        off += std::max<size_t>(bytes, 1);
+        return at;
+    };
+    int at = 0;
+    for (int b = 0; b < nb; ++b) {
+        m->first[b] = at;
+        m->count[b] = N / nb + (b < N % nb ? 1 : 0);
+        at += m->count[b];
+        m->hlo[b] = (b > 0 || m->periodic) ? FSA_HALO : 0;
+        m->hhi[b] = (b < nb - 1 || m->periodic) ? FSA_HALO : 0;
+        if ((m->hlo[b] || m->hhi[b]) && m->count[b] < FSA_HALO) {
+            why = "a block is thinner than FSA_HALO layers";
+            return FSA_EINVAL;
+        }
+        fsa_desc& d = m->bdesc[b];
+        d.n[m->dir] = m->hlo[b] + m->count[b] + m->hhi[b];
+        for (int k = 0; k < desc->dim; ++k) d.global_n[k] = desc->n[k];
+        d.origin[m->dir] = m->first[b] - m->hlo[b];
+        if (m->hlo[b]) d.bc[m->dir][0] = FSA_BC_EXTRAP;
+        if (m->hhi[b]) d.bc[m->dir][1] = FSA_BC_EXTRAP;
+        size_t wb = 0;
+        if ((rc = fsa_workspace_bytes(&d, &wb)) != FSA_OK) {
+            why = "a block's descriptor is invalid";
+            return rc;
+        }
+        m->ws_off[b] = take(wb);
+        long long cells = m->plane * d.n[m->dir];
+        m->q_off[b] = take(sizeof(double) * (size_t)m->nq * (size_t)cells);
+    }
+    const int nif = m->periodic ? nb : nb - 1;   // interfaces
+    m->ncopy = 2 * m->nq * nif;
+    m->copy_max = FSA_HALO * m->plane;
+    m->copy_off = take(3 * sizeof(CopyEntry) * (size_t)std::max(m->ncopy, 1));
+    m->slot_off = take(2 * sizeof(unsigned long long*) * (size_t)nb);
+    m->total = off + 256;   // (room to align the base up)
+    return FSA_OK;
+}
+
+// Copy list refreshing every halo from the neighbours' own layers, for stage buffers bufs[b].
+std::vector<CopyEntry> mb_copies(const fsa_mb* m, const std::vector<double*>& bufs)
+{
+    std::vector<CopyEntry> e;
+    const int H = FSA_HALO;
+    const long long P = m->plane;
+    auto cells = [&](int b) { return P * (long long)(m->hlo[b] + m->count[b] + m->hhi[b]); };
+    for (int b = 0; b < m->nb; ++b) {
+        const int up = b + 1 < m->nb ? b + 1 : (m->periodic ? 0 : -1);
+        if (up < 0) continue;
+        for (int c = 0; c < m->nq; ++c) {
+            // b's upper halo <- up's first own layers; up's lower halo <- b's last own layers
+            e.push_back({bufs[up] + c * cells(up) + (long long)m->hlo[up] * P,
+                         bufs[b] + c * cells(b) + (long long)(m->hlo[b] + m->count[b]) * P, H * P});
+            e.push_back({bufs[b] + c * cells(b) + (long long)(m->hlo[b] + m->count[b] - H) * P,
+                         bufs[up] + c * cells(up), H * P});
+        }
+    }
+    return e;
+}
+
+// Wave speeds of every block's bufs[b] (exact in all its layers: own ones and refreshed
+// halos), their maximum into every block's slot 0.
+int mb_alpha(fsa_mb* m, const std::vector<const double*>& bufs)
+{
+    for (int b = 0; b < m->nb; ++b) {
+        fsa_ctx* c = m->blk[b];
+        if (int rf = flush_alpha_final(c)) return rf;
+        const int e = launch_alpha(c->G, c->P, bufs[b], c->apart, c->abits + 3, m->stream);
+        if (e) return mb_fail(m, FSA_EDEVICE, "wave-speed launch failed");
+    }
+    if (launch_amax_blocks(m->d_slot_in, m->d_slot_out, m->nb, m->stream))
+        return mb_fail(m, FSA_EDEVICE, "cross-block maximum launch failed");
+    return FSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fsa_mb_workspace_bytes(const fsa_desc* desc, int32_t nblocks, size_t* bytes)
+{
+    if (!bytes) return FSA_EINVAL;
+    *bytes = 0;
+    fsa_mb m;
+    std::string why;
+    const int rc = mb_plan(&m, desc, nblocks, why);
+    if (rc != FSA_OK) {
+        std::fprintf(stderr, "fsa_mb_workspace_bytes: %s\n", why.c_str());
+        return rc;
+    }
+    *bytes = m.total;
+    return FSA_OK;
+}
+
+int32_t fsa_mb_init(const fsa_desc* desc, int32_t nblocks, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                    fsa_mb** out)
+{
+    if (!out) return FSA_EINVAL;
+    *out = nullptr;
+    fsa_mb* m = new (std::nothrow) fsa_mb();
+    if (!m) return FSA_ENOMEM;
+    std::string why;
+    int rc = mb_plan(m, desc, nblocks, why);
+    if (rc == FSA_OK && (!d_workspace || ws_bytes < m->total)) {
+        why = "the workspace is smaller than fsa_mb_workspace_bytes";
+        rc = FSA_EINVAL;
+    }
+    if (rc != FSA_OK) {
+        std::fprintf(stderr, "fsa_mb_init: %s\n", why.c_str());
+        delete m;
+        return rc;
+    }
+    m->stream = (hipStream_t)hip_stream;
+    char* base = (char*)(((uintptr_t)d_workspace + 255) & ~(uintptr_t)255);
+    m->blk.assign(m->nb, nullptr);
+    m->Q.assign(m->nb, nullptr);
+    for (int b = 0; b < m->nb; ++b) {
+        size_t wb = 0;
+        fsa_workspace_bytes(&m->bdesc[b], &wb);
+        if ((rc = fsa_init(&m->bdesc[b], base + m->ws_off[b], wb, hip_stream, &m->blk[b])) != FSA_OK) {
+            fsa_mb_destroy(m);
+            return rc;
+        }
+        m->Q[b] = reinterpret_cast<double*>(base + m->q_off[b]);
+    }
+    // halo copy tables of the three stage outputs and the slot pointer lists
+    for (int s = 0; s < 3; ++s) {
+        std::vector<double*> bufs(m->nb);
+        for (int b = 0; b < m->nb; ++b) bufs[b] = s == 0 ? m->blk[b]->Qa : (s == 1 ? m->blk[b]->Qb : m->Q[b]);
+        const std::vector<CopyEntry> e = mb_copies(m, bufs);
+        m->d_copy[s] = reinterpret_cast<CopyEntry*>(base + m->copy_off) + (size_t)s * std::max(m->ncopy, 1);
+        if (!e.empty() && hipMemcpy(m->d_copy[s], e.data(), sizeof(CopyEntry) * e.size(), hipMemcpyHostToDevice) !=
+                              hipSuccess) {
+            fsa_mb_destroy(m);
+            return FSA_EDEVICE;
+        }
+    }
+    std::vector<unsigned long long*> slots(2 * (size_t)m->nb);
+    for (int b = 0; b < m->nb; ++b) {
+        slots[b] = m->blk[b]->abits + 3;
+        slots[(size_t)m->nb + b] = m->blk[b]->abits;
+    }
+    m->d_slot_in = reinterpret_cast<unsigned long long**>(base + m->slot_off);
+    m->d_slot_out = m->d_slot_in + m->nb;
+    if (hipMemcpy(m->d_slot_in, slots.data(), sizeof(unsigned long long*) * slots.size(), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+        fsa_mb_destroy(m);
+        return FSA_EDEVICE;
+    }
+    m->marker_of.assign(m->nb, {});
+    *out = m;
+    return FSA_OK;
+}
+
+int32_t fsa_mb_destroy(fsa_mb* m)
+{
+    if (!m) return FSA_OK;
+    for (fsa_ctx* c : m->blk) fsa_destroy(c);
+    delete m;
+    return FSA_OK;
+}
+
+const char* fsa_mb_last_error(const fsa_mb* m) { return m ? m->err.c_str() : "null block set"; }
+
+int32_t fsa_mb_block_info(const fsa_mb* m, int32_t b, int32_t* first, int32_t* count, int32_t* halo_lo,
+                          int32_t* halo_hi)
+{
+    if (!m || b < 0 || b >= m->nb) return FSA_EINVAL;
+    if (first) *first = m->first[b];
+    if (count) *count = m->count[b];
+    if (halo_lo) *halo_lo = m->hlo[b];
+    if (halo_hi) *halo_hi = m->hhi[b];
+    return FSA_OK;
+}
+
+int32_t fsa_mb_set_markers(fsa_mb* m, int32_t n, const double* X, const double* dV, const double* U, int32_t motion,
+                           double omega)
+{
+    if (!m || n < 0 || (n > 0 && (!X || !dV))) return FSA_EINVAL;
+    if (motion != FSA_STATIC && motion != FSA_ROTATING)
+        return mb_fail(m, FSA_EUNSUPPORTED, "blocks hold STATIC or ROTATING markers only");
+    const fsa_desc& w = m->whole;
+    const int dim = w.dim;
+    std::vector<int> j0(n);
+    for (int k = 0; k < n; ++k)
+        for (int d = 0; d < dim; ++d) {
+            const double x = X[(size_t)d * n + k];
+            if (!std::isfinite(x)) return mb_fail(m, FSA_EINVAL, "non-finite marker position");
+            const double j = std::floor((x - w.lo[d]) / w.h - 0.5) - 1.0;
+            if (j < 0.0 || j + 3.0 > (double)(w.n[d] - 1)) return mb_fail(m, FSA_EINVAL, "a marker support leaves the grid");
+            if (d == m->dir) j0[k] = (int)j;
+        }
+    m->nm = n;
+    m->owner.assign(n, -1);
+    m->owner_idx.assign(n, -1);
+    for (int b = 0; b < m->nb; ++b) {
+        std::vector<int>& mine = m->marker_of[b];
+        mine.clear();
+        const int lo = m->first[b], hi = m->first[b] + m->count[b] - 1;
+        for (int k = 0; k < n; ++k)
+            if (j0[k] + 3 >= lo && j0[k] <= hi) {
+                if (m->owner[k] < 0) {
+                    m->owner[k] = b;
+                    m->owner_idx[k] = (int)mine.size();
+                }
+                mine.push_back(k);
+            }
+        const int nbk = (int)mine.size();
+        std::vector<double> Xb((size_t)dim * nbk), Ub((size_t)dim * nbk, 0.0), dVb(nbk);
+        for (int i = 0; i < nbk; ++i) {
+            const int k = mine[i];
+            dVb[i] = dV[k];
+            for (int d = 0; d < dim; ++d) {
+                Xb[(size_t)d * nbk + i] = X[(size_t)d * n + k];
+                if (U) Ub[(size_t)d * nbk + i] = U[(size_t)d * n + k];
+            }
+        }
+        const int rc = fsa_set_markers(m->blk[b], nbk, Xb.data(), dVb.data(), U ? Ub.data() : nullptr, motion, omega);
+        if (rc != FSA_OK) return mb_fail(m, rc, std::string("block marker set: ") + fsa_last_error(m->blk[b]));
+    }
+    return FSA_OK;
+}
+
+int32_t fsa_mb_scatter(fsa_mb* m, const double* d_Q)
+{
+    if (!m || !d_Q) return FSA_EINVAL;
+    const int N = m->whole.n[m->dir];
+    const long long P = m->plane, whole_cells = P * N;
+    for (int b = 0; b < m->nb; ++b) {
+        const int nl = m->hlo[b] + m->count[b] + m->hhi[b];
+        const long long bcells = P * nl;
+        // runs of local layers whose global layers are consecutive (halos may wrap)
+        int L = 0;
+        while (L < nl) {
+            const int g0 = ((m->first[b] - m->hlo[b] + L) % N + N) % N;
+            const int len = std::min(nl - L, N - g0);
+            for (int c = 0; c < m->nq; ++c)
+                if (hipMemcpyAsync(m->Q[b] + c * bcells + (long long)L * P, d_Q + c * whole_cells + (long long)g0 * P,
+                                   sizeof(double) * (size_t)(len * P), hipMemcpyDeviceToDevice, m->stream) != hipSuccess)
+                    return mb_fail(m, FSA_EDEVICE, "scatter copy failed");
+            L += len;
+        }
+        m->blk[b]->t = 0.0;
+        m->blk[b]->step = 0;
+    }
+    return FSA_OK;
+}
+
+int32_t fsa_mb_gather(const fsa_mb* m, double* d_Q)
+{
+    if (!m || !d_Q) return FSA_EINVAL;
+    const long long P = m->plane, whole_cells = P * m->whole.n[m->dir];
+    for (int b = 0; b < m->nb; ++b) {
+        const long long bcells = P * (m->hlo[b] + m->count[b] + m->hhi[b]);
+        for (int c = 0; c < m->nq; ++c)
+            if (hipMemcpyAsync(d_Q + c * whole_cells + (long long)m->first[b] * P,
+                               m->Q[b] + c * bcells + (long long)m->hlo[b] * P, sizeof(double) * (size_t)(m->count[b] * P),
+                               hipMemcpyDeviceToDevice, m->stream) != hipSuccess)
+                return FSA_EDEVICE;
+    }
+    return FSA_OK;
+}
+
+int32_t fsa_mb_rk3_steps(fsa_mb* m, double dt, int32_t nsteps)
+{
+    if (!m) return FSA_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return mb_fail(m, FSA_EINVAL, "dt must be positive");
+    if (nsteps < 1) return mb_fail(m, FSA_EINVAL, "nsteps must be positive");
+    static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
+    static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
+    std::vector<const double*> bufs(m->nb);
+    for (int b = 0; b < m->nb; ++b) {
+        m->blk[b]->advanced = nullptr;
+        bufs[b] = m->Q[b];
+    }
+    int rc = mb_alpha(m, bufs);   // the states' wave speeds (their halos are exact)
+    if (rc != FSA_OK) return rc;
+    for (int n = 0; n < nsteps; ++n) {
+        for (int s = 0; s < 3; ++s) {
+            for (int b = 0; b < m->nb; ++b) {
+                fsa_ctx* c = m->blk[b];
+                const double* Qs = s == 0 ? m->Q[b] : (s == 1 ? c->Qa : c->Qb);
+                double* out = s == 0 ? c->Qa : (s == 1 ? c->Qb : m->Q[b]);
+                if ((rc = enqueue_stage(c, Qs, m->Q[b], out, 0, -1, false, s + 1, CA[s], CB[s], dt, 0)) != FSA_OK)
+                    return mb_fail(m, rc, std::string("block stage: ") + fsa_last_error(c));
+                bufs[b] = out;
+            }
+            if (launch_copy_list(m->d_copy[s], m->ncopy, m->copy_max, m->stream))
+                return mb_fail(m, FSA_EDEVICE, "halo copy launch failed");
+            if ((rc = mb_alpha(m, bufs)) != FSA_OK) return rc;
+        }
+        for (fsa_ctx* c : m->blk) {
+            c->t += dt;
+            c->step += 1;
+        }
+    }
+    return FSA_OK;
+}
+
+int32_t fsa_mb_marker_force(fsa_mb* m, double* h_F)
+{
+    if (!m || !h_F) return FSA_EINVAL;
+    const int dim = m->whole.dim;
+    for (int b = 0; b < m->nb; ++b) {
+        const int nbk = (int)m->marker_of[b].size();
+        if (nbk == 0) continue;
+        std::vector<double> F((size_t)dim * nbk);
+        const int rc = fsa_marker_force(m->blk[b], F.data());
+        if (rc != FSA_OK) return mb_fail(m, rc, "block marker force");
+        for (int i = 0; i < nbk; ++i) {
+            const int k = m->marker_of[b][i];
+            if (m->owner[k] != b) continue;
+            for (int d = 0; d < dim; ++d) h_F[(size_t)d * m->nm + k] = F[(size_t)d * nbk + i];
+        }
     }
     return FSA_OK;
 }

@@ -20,6 +20,18 @@ struct Grid {
     double lo[3];
     double h, inv_h;
     int bc[3][2];
+    // placement in a larger grid (a block of a decomposed domain): local cell i is global cell
+    // i + org of a grid of gn cells (gncell in all); lo is the global grid's corner.  Cell
+    // positions, the sponge and the inflow-noise counters are those of the global grid.
+    int org[3];
+    int gn[3];
+    long long gncell;
+
+    // global linear index of local cell (i, j, k)
+    __host__ __device__ __forceinline__ long long glin(int i, int j, int k) const
+    {
+        return ((long long)(k + org[2]) * gn[1] + (j + org[1])) * gn[0] + (i + org[0]);
+    }
 };
 
 struct Phys {
@@ -112,7 +124,7 @@ __device__ __forceinline__ void fetch_state(const double* __restrict__ Q, const 
         for (int c = 0; c < DIM + 2; ++c) q[c] = Q[c * G.ncell + lin];
         return;
     }
-    inflow_state<DIM>(P, step, G.ncell, lin, side, depth, q);
+    inflow_state<DIM>(P, step, G.gncell, G.glin(i, j, k), side, depth, q);
 }
 
 // Reciprocal from the hardware estimate refined by two Newton steps (within an ulp or two of
@@ -340,8 +352,8 @@ struct KConst {
 
     __device__ __forceinline__ double eta_dir(int d, int i) const
     {
-        const double x = G.lo[d] + ((double)i + 0.5) * G.h;
-        return sponge_eta(x, G.lo[d], G.lo[d] + (double)G.n[d] * G.h, P.sw[d][0], P.sw[d][1], P.inv_sw[d][0],
+        const double x = G.lo[d] + ((double)(i + G.org[d]) + 0.5) * G.h;
+        return sponge_eta(x, G.lo[d], G.lo[d] + (double)G.gn[d] * G.h, P.sw[d][0], P.sw[d][1], P.inv_sw[d][0],
                           P.inv_sw[d][1]);
     }
 };

@@ -97,6 +97,16 @@ int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, in
 int launch_pass2d(const KConst* K, const Grid& G, int scheme, int terms, double mu, const StageArgs& A,
                   double* stress, double* faces, hipStream_t s);
 long long pass2d_stress_elems(const Grid& G);
+// Blocks of one domain on one GPU: a list of contiguous double runs copied in one launch
+// (entries in device memory, max_count the longest run), and the NaN-propagating maximum of
+// nb wave-speed slots written into nb others.
+struct CopyEntry {
+    const double* src;
+    double* dst;
+    long long count;
+};
+int launch_copy_list(const CopyEntry* d_list, int n, long long max_count, hipStream_t s);
+int launch_amax_blocks(unsigned long long* const* d_in, unsigned long long* const* d_out, int nb, hipStream_t s);
 long long pass2d_face_elems(const Grid& G);
 long long pass2d_blocks(const Grid& G);
 long long stress3d_elems(const Grid& G);

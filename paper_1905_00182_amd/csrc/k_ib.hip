@@ -40,14 +40,17 @@ __global__ __launch_bounds__(RED_THREADS) void k_alpha(Grid G, Phys P, const dou
     const long long nc = G.ncell;
     for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < nc;
          n += (long long)gridDim.x * blockDim.x) {
-        const double rho = Q[n];
-        const double inv = 1.0 / rho;
-        double u[DIM], ke = 0.0;
+        // the stage kernels' expressions for the wave speeds of their output, operation for
+        // operation, so that a stage input's speeds do not depend on which kernel took them
+        const double inv = rcp_nr(Q[n]);
+        double u[DIM], mom[DIM];
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            u[d] = Q[(1 + d) * nc + n] * inv;
-            ke = fma(Q[(1 + d) * nc + n], u[d], ke);
+            mom[d] = Q[(1 + d) * nc + n];
+            u[d] = mom[d] * inv;
         }
+        const double ke = DIM == 3 ? fma(mom[0], u[0], fma(mom[1], u[1], mom[DIM - 1] * u[DIM - 1]))
+                                   : fma(mom[0], u[0], mom[DIM - 1] * u[DIM - 1]);
         const double p = P.gm1 * (Q[(DIM + 1) * nc + n] - 0.5 * ke);
         const double c = sqrt(P.gamma * p * inv);
 #pragma unroll
@@ -108,16 +111,19 @@ __device__ __forceinline__ void marker_support(const Grid& G, const double* X, i
                                                double (*w)[4])
 {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) support4(X[(long long)d * n + k], G.lo[d], G.h, j0[d], w[d]);
+    for (int d = 0; d < DIM; ++d) {
+        support4(X[(long long)d * n + k], G.lo[d], G.h, j0[d], w[d]);   // (global cell index)
+        j0[d] -= G.org[d];
+    }
 }
 
 // Tensor-product weight of cell (ci, cj, ck) for point k.
 template <int DIM>
 __device__ __forceinline__ double cell_weight(const Grid& G, const double* X, int n, int k, int ci, int cj, int ck)
 {
-    double W = delta4(cell_coord(X[k], G.lo[0], G.h) - (double)ci) *
-               delta4(cell_coord(X[(long long)n + k], G.lo[1], G.h) - (double)cj);
-    if (DIM == 3) W = W * delta4(cell_coord(X[2ll * n + k], G.lo[2], G.h) - (double)ck);
+    double W = delta4(cell_coord(X[k], G.lo[0], G.h) - (double)(ci + G.org[0])) *
+               delta4(cell_coord(X[(long long)n + k], G.lo[1], G.h) - (double)(cj + G.org[1]));
+    if (DIM == 3) W = W * delta4(cell_coord(X[2ll * n + k], G.lo[2], G.h) - (double)(ck + G.org[2]));
     return W;
 }
 

@@ -791,7 +791,7 @@ __global__ __launch_bounds__(256) void k_inflow_ghosts2d(const KConst* __restric
     const int ir = resolve_index(dir == 0 ? across : t, G.n[0], G.bc[0][0], G.bc[0][1], 0, inflow, s, d);
     const int jr = resolve_index(dir == 0 ? t : across, G.n[1], G.bc[1][0], G.bc[1][1], 1, inflow, s, d);
     double q[4];
-    inflow_state<2>(K->P, step0 + blockIdx.z, G.ncell, (long long)jr * G.n[0] + ir, s, d, q);
+    inflow_state<2>(K->P, step0 + blockIdx.z, G.gncell, G.glin(ir, jr, 0), s, d, q);
     double* gz = g + (long long)blockIdx.z * (16ll * HALO * na);
     const long long o = (long long)(side * HALO + depth - 1) * na + t;
 #pragma unroll

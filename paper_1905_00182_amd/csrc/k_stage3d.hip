@@ -380,8 +380,9 @@ __global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ 
         }
         if (K->P.src_amp != 0.0) {
             // periodic Gaussian pressure source (Sec. 3), into the energy as A_p / (gamma - 1)
-            const double x = G.lo[0] + ((double)i + 0.5) * G.h, y = G.lo[1] + ((double)j + 0.5) * G.h,
-                         z = G.lo[2] + ((double)k + 0.5) * G.h;
+            const double x = G.lo[0] + ((double)(i + G.org[0]) + 0.5) * G.h,
+                         y = G.lo[1] + ((double)(j + G.org[1]) + 0.5) * G.h,
+                         z = G.lo[2] + ((double)(k + G.org[2]) + 0.5) * G.h;
             const double dx = x - K->P.src_x[0], dy = y - K->P.src_x[1], dz = z - K->P.src_x[2];
             const double r2 = dx * dx + dy * dy + dz * dz;
             const double ap = -K->P.src_amp * exp(-K->P.src_bl2 * r2) * cos(K->P.src_omega * A.t);

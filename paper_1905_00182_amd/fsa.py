@@ -62,6 +62,8 @@ class FsaDesc(C.Structure):
         ("max_probes", C.c_int32),
         ("max_window_cells", C.c_int64),
         ("variables", C.c_int32),
+        ("origin", C.c_int32 * 3),
+        ("global_n", C.c_int32 * 3),
     ]
 
 
@@ -150,6 +152,20 @@ _SIGS = {
     "fsa_plate_set_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double]),
     "fsa_plate_last_error": (C.c_char_p, [C.c_void_p]),
     "fsa_plate_coupled_steps": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_int32]),
+    # several blocks of one domain on one GPU
+    "fsa_mb_workspace_bytes": (C.c_int32, [C.POINTER(FsaDesc), C.c_int32, C.POINTER(C.c_size_t)]),
+    "fsa_mb_init": (C.c_int32, [C.POINTER(FsaDesc), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                                C.POINTER(C.c_void_p)]),
+    "fsa_mb_destroy": (C.c_int32, [C.c_void_p]),
+    "fsa_mb_last_error": (C.c_char_p, [C.c_void_p]),
+    "fsa_mb_block_info": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "fsa_mb_set_markers": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                       C.c_double]),
+    "fsa_mb_scatter": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fsa_mb_gather": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "fsa_mb_rk3_steps": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32]),
+    "fsa_mb_marker_force": (C.c_int32, [C.c_void_p, C.c_void_p]),
 }
 
 
@@ -276,6 +292,96 @@ def make_desc(case, nan_check=False) -> FsaDesc:
     d.max_markers, d.max_probes, d.max_window_cells = capacities(case)
     d.variables = VARIABLES[case.variables]
     return d
+
+
+class MultiBlock:
+    """One domain cut into `nblocks` slabs along its last direction on the current HIP device
+    and torch's current stream (include/fsa.h, fsa_mb_*): each block an ordinary context over
+    its layers and FSA_HALO halo layers, halo copies and the cross-block wave-speed maximum
+    after every stage; the whole state goes in with scatter and comes out with gather."""
+
+    def __init__(self, case, nblocks, stream=None):
+        import torch
+
+        self.torch = torch
+        self.case = case
+        self.nq = case.dim + 2
+        self.shape = (self.nq,) + case.shape
+        self.nblocks = nblocks
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.desc = make_desc(case)
+        nbytes = C.c_size_t()
+        self._check(lib().fsa_mb_workspace_bytes(C.byref(self.desc), nblocks, C.byref(nbytes)), None)
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        mb = C.c_void_p()
+        self._check(lib().fsa_mb_init(C.byref(self.desc), nblocks, C.c_void_p(self.workspace.data_ptr()),
+                                      nbytes.value, C.c_void_p(self.stream.cuda_stream), C.byref(mb)), None)
+        self.mb = mb
+        self.nm = 0
+        if case.markers is not None:
+            m = case.markers
+            self.set_markers(m["X"], m["dV"], m.get("U"), m.get("motion", "static"), m.get("omega", 0.0))
+
+    def close(self):
+        if getattr(self, "mb", None):
+            lib().fsa_mb_destroy(self.mb)
+            self.mb = None
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:      # interpreter shutdown: the module's globals may be gone
+            pass
+
+    def _check(self, rc, mb="self"):
+        if rc != OK:
+            m = self.mb if mb == "self" else None
+            msg = lib().fsa_mb_last_error(m).decode() if m else lib().fsa_status_str(rc).decode()
+            raise FsaError(rc, msg)
+
+    def _state(self, Q):
+        t = self.torch
+        if not isinstance(Q, t.Tensor) or Q.dtype != t.float64 or Q.device != self.device or not Q.is_contiguous() \
+                or tuple(Q.shape) != tuple(self.shape):
+            raise ValueError(f"Q must be a contiguous float64 tensor of shape {self.shape} on {self.device}")
+        return Q
+
+    def block_info(self, b):
+        v = [C.c_int32() for _ in range(4)]
+        self._check(lib().fsa_mb_block_info(self.mb, b, *[C.byref(x) for x in v]))
+        return tuple(x.value for x in v)       # first layer, layers, halo below, halo above
+
+    def set_markers(self, X, dV, U=None, motion="static", omega=0.0):
+        dV = _host(dV)
+        n = dV.shape[0]
+        X = _host(X)
+        if X.shape != (self.nq - 2, n):
+            raise ValueError(f"X must have shape {(self.nq - 2, n)}, not {X.shape}")
+        Ua = _host(U) if U is not None else None
+        if Ua is not None and Ua.shape != X.shape:
+            raise ValueError(f"U must have shape {X.shape}, not {Ua.shape}")
+        self._check(lib().fsa_mb_set_markers(self.mb, n, X.ctypes.data, dV.ctypes.data,
+                                             Ua.ctypes.data if Ua is not None else None, MOTION[motion], omega))
+        self.nm = n
+
+    def scatter(self, Q):
+        self._check(lib().fsa_mb_scatter(self.mb, _ptr(self._state(Q))))
+
+    def gather(self, Q=None):
+        Q = self.torch.empty(self.shape, dtype=self.torch.float64, device=self.device) if Q is None else self._state(Q)
+        self._check(lib().fsa_mb_gather(self.mb, _ptr(Q)))
+        return Q
+
+    def rk3_steps(self, dt, nsteps):
+        self._check(lib().fsa_mb_rk3_steps(self.mb, dt, nsteps))
+
+    def marker_force(self):
+        F = np.zeros((self.nq - 2, self.nm))
+        if self.nm:
+            self._check(lib().fsa_mb_marker_force(self.mb, F.ctypes.data))
+        return F
 
 
 def capacities(case):
