@@ -352,6 +352,45 @@ def moving_body_forms(case, kinematics, net, nsteps, every=10, flexible=False):
                     "previous call's state)"}
 
 
+def blocks(case, Q0, nsteps=200, nblocks=4):
+    """The benchmark case in `nblocks` slabs on one GPU (fsa_mb_*, bit for bit the single
+    context's result) against one context: ms per step of each, and whether the states
+    agree bitwise after the run."""
+    import torch
+
+    from paper_1905_00182_amd import fsa
+
+    import numpy as np
+
+    s = fsa.Solver(case)
+    Q = Q0.clone()
+    s.rk3_steps(Q, case.dt, 2)
+    s.set_state(np.zeros((case.dim, s.nm)), 0.0, 0)     # (as the blocks' scatter: a fresh start)
+    Q = Q0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.rk3_steps(Q, case.dt, nsteps)
+    torch.cuda.synchronize()
+    w1 = time.perf_counter() - t0
+    s.close()
+    m = fsa.MultiBlock(case, nblocks)
+    m.scatter(Q0)
+    m.rk3_steps(case.dt, 2)
+    m.scatter(Q0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.rk3_steps(case.dt, nsteps)
+    torch.cuda.synchronize()
+    wb = time.perf_counter() - t0
+    same = bool(torch.equal(m.gather(), Q))
+    m.close()
+    return {"blocks": nblocks, "steps": nsteps, "ms_per_step_single": round(w1 / nsteps * 1e3, 4),
+            "ms_per_step_blocks": round(wb / nsteps * 1e3, 4), "overhead": round(wb / w1 - 1.0, 4),
+            "bitwise_equal": same,
+            "note": "slabs along y, each with 4 halo rows per neighbour recomputed, halo copies and the "
+                    "cross-block wave-speed maximum after every stage"}
+
+
 def three_d(steps=3):
     """Rates of the 3D path on the sphere cases (256^3 FP64 in both schemes, 384^3 precision
     form): `steps` steps after one warm-up step, inputs resident on the device."""
@@ -501,6 +540,8 @@ def main():
     if not args.no_variants:
         out["variants"] = variants(case, Q0, args.variant_steps, plate_steps=args.plate_steps)
         out["variants"]["three_d"] = three_d()
+        out["variants"]["c2_blocks"] = blocks(case, Q0)
+        progress("blocks done")
     if not args.no_cpu and args.cpu_steps > 0:
         progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

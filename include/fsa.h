@@ -356,7 +356,9 @@ int32_t fsa_stats_get(fsa_ctx* ctx, fsa_stats* out);
  * layers, in their global order.  The result equals one context's over the whole domain bit
  * for bit.  Markers must be STATIC or ROTATING (positions fixed), probes and diagnostics are
  * taken on the gathered state.  Every call is stream-ordered on hip_stream unless it says
- * synchronising.
+ * synchronising: the blocks' stages run side by side on streams of their own (created with
+ * the default priority), which wait for hip_stream before each stage and which hip_stream
+ * waits for after it.
  *
  * Device memory: one workspace of fsa_mb_workspace_bytes (the blocks' contexts and states
  * and the copy tables) owned by the caller; the library allocates host memory only.
@@ -378,7 +380,7 @@ int32_t fsa_mb_block_info(const fsa_mb* mb, int32_t b, int32_t* first, int32_t* 
 int32_t fsa_mb_set_markers(fsa_mb* mb, int32_t n, const double* X, const double* dV, const double* U,
                            int32_t motion, double omega);
 /* The whole domain's state (DEVICE, [nq][cells] as fsa_rk3_step) into the blocks, halo
- * layers included; resets time and step to zero. */
+ * layers included; a fresh start: time, step and the penalty integral zero. */
 int32_t fsa_mb_scatter(fsa_mb* mb, const double* d_Q);
 /* The blocks' own layers into the whole domain's state d_Q (DEVICE). */
 int32_t fsa_mb_gather(const fsa_mb* mb, double* d_Q);

@@ -102,6 +102,8 @@ struct fsa_ctx {
     long long ghosts_step = -1;          // steps ghosts_step .. + GHOST_STEPS - 1 (-1: none)
     const double* qrange_of = nullptr;   // the buffer they describe (null: none valid)
     int qrange_ty = 0;                   // rows per segment they were taken with
+    int arow0 = 0, arow1 = 0;            // layers along the last direction whose cells enter the
+                                         // wave speeds (all of them; a block: its own layers)
     bool quiet_tiles = true;             // flags passes may skip quiet tiles (FSA_NO_QUIET_TILES=1:
                                          // never; tests compare the two)
     int* hv_count = nullptr;
@@ -597,7 +599,7 @@ int finish_nrbc(fsa_ctx* c, const StageArgs& S, int acc)
                 if (e) return hipcheck(c, (hipError_t)e, "non-reflecting boundary launch");
             }
     if (acc >= 0) {
-        int e = launch_alpha(c->G, c->P, S.out, c->apart, c->abits + 3 * acc, c->stream);
+        int e = launch_alpha_rows(c->G, c->P, S.out, S.arow0, S.arow1, c->apart, c->abits + 3 * acc, c->stream);
         if (e) return hipcheck(c, (hipError_t)e, "alpha reduction launch");
     }
     return FSA_OK;
@@ -702,6 +704,8 @@ int enqueue_stage(fsa_ctx* c, const double* Qs, const double* Qn, double* out, i
     S.dt = dt;
     S.mode_rhs = mode_rhs;
     S.step = c->step;
+    S.arow0 = c->arow0;
+    S.arow1 = c->arow1;
     if (c->dbg_bits) {
         const long long nx = c->G.n[0], ny = c->G.n[1], nz = c->G.n[2];
         const long long fx = (nx + 1) * ny * nz, fy = nx * (ny + 1) * nz, fz = c->G.dim == 3 ? nx * ny * (nz + 1) : 0;
@@ -1036,6 +1040,8 @@ int32_t fsa_init(const fsa_desc* desc, void* d_workspace, size_t ws_bytes, void*
     if (const char* e = std::getenv("FSA_NO_QUIET_TILES")) c->quiet_tiles = std::atoi(e) == 0;
     char* base = (char*)(((uintptr_t)d_workspace + 255) & ~(uintptr_t)255);
     carve(c, base);
+    c->arow0 = 0;
+    c->arow1 = c->G.n[c->G.dim - 1];
     {
         KConst hk;
         std::memset(&hk, 0, sizeof hk);
@@ -1522,7 +1528,10 @@ struct fsa_mb {
     int nb = 0, dir = 0, nq = 0;
     long long plane = 0;                     // cells of one layer across the slab direction
     bool periodic = false;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;            // the caller's: copies, wave speeds, joins
+    std::vector<hipStream_t> bstream;        // one per block (default priority): the blocks'
+    std::vector<hipEvent_t> bev;             // stages run side by side, joined by events
+    hipEvent_t ev_main = nullptr;
     std::vector<fsa_ctx*> blk;
     std::vector<int> first, count, hlo, hhi;
     std::vector<fsa_desc> bdesc;
@@ -1638,14 +1647,13 @@ std::vector<CopyEntry> mb_copies(const fsa_mb* m, const std::vector<double*>& bu
     return e;
 }
 
-// Wave speeds of every block's bufs[b] (exact in all its layers: own ones and refreshed
-// halos), their maximum into every block's slot 0.
+// Wave speeds of the own layers of every block's bufs[b], their maximum into every block's
+// slot 0 (the start of a step call; between stages the stage kernels' partials serve).
 int mb_alpha(fsa_mb* m, const std::vector<const double*>& bufs)
 {
     for (int b = 0; b < m->nb; ++b) {
         fsa_ctx* c = m->blk[b];
-        if (int rf = flush_alpha_final(c)) return rf;
-        const int e = launch_alpha(c->G, c->P, bufs[b], c->apart, c->abits + 3, m->stream);
+        const int e = launch_alpha_rows(c->G, c->P, bufs[b], c->arow0, c->arow1, c->apart, c->abits + 3, m->stream);
         if (e) return mb_fail(m, FSA_EDEVICE, "wave-speed launch failed");
     }
     if (launch_amax_blocks(m->d_slot_in, m->d_slot_out, m->nb, m->stream))
@@ -1694,14 +1702,33 @@ int32_t fsa_mb_init(const fsa_desc* desc, int32_t nblocks, void* d_workspace, si
     char* base = (char*)(((uintptr_t)d_workspace + 255) & ~(uintptr_t)255);
     m->blk.assign(m->nb, nullptr);
     m->Q.assign(m->nb, nullptr);
+    m->bstream.assign(m->nb, nullptr);
+    m->bev.assign(m->nb, nullptr);
+    if (hipEventCreateWithFlags(&m->ev_main, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        fsa_mb_destroy(m);
+        return FSA_ENOMEM;
+    }
     for (int b = 0; b < m->nb; ++b) {
+        if (hipStreamCreateWithFlags(&m->bstream[b], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&m->bev[b], hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            fsa_mb_destroy(m);
+            return FSA_ENOMEM;
+        }
         size_t wb = 0;
         fsa_workspace_bytes(&m->bdesc[b], &wb);
-        if ((rc = fsa_init(&m->bdesc[b], base + m->ws_off[b], wb, hip_stream, &m->blk[b])) != FSA_OK) {
+        if ((rc = fsa_init(&m->bdesc[b], base + m->ws_off[b], wb, m->bstream[b], &m->blk[b])) != FSA_OK) {
             fsa_mb_destroy(m);
             return rc;
         }
         m->Q[b] = reinterpret_cast<double*>(base + m->q_off[b]);
+        // wave speeds from the block's own layers only; no quiet-tile skipping in the learned
+        // form (the stage kernel's deviation ranges would include the halo layers' output
+        // before the copies refresh them)
+        m->blk[b]->arow0 = m->hlo[b];
+        m->blk[b]->arow1 = m->hlo[b] + m->count[b];
+        m->blk[b]->quiet_tiles = false;
     }
     // halo copy tables of the three stage outputs and the slot pointer lists
     for (int s = 0; s < 3; ++s) {
@@ -1735,7 +1762,13 @@ int32_t fsa_mb_init(const fsa_desc* desc, int32_t nblocks, void* d_workspace, si
 int32_t fsa_mb_destroy(fsa_mb* m)
 {
     if (!m) return FSA_OK;
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
     for (fsa_ctx* c : m->blk) fsa_destroy(c);
+    for (hipStream_t st : m->bstream)
+        if (st) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : m->bev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (m->ev_main) (void)hipEventDestroy(m->ev_main);
     delete m;
     return FSA_OK;
 }
@@ -1820,8 +1853,16 @@ int32_t fsa_mb_scatter(fsa_mb* m, const double* d_Q)
                     return mb_fail(m, FSA_EDEVICE, "scatter copy failed");
             L += len;
         }
-        m->blk[b]->t = 0.0;
-        m->blk[b]->step = 0;
+        // a fresh start: time, step and penalty integral zero
+        fsa_ctx* c = m->blk[b];
+        if (c->nm > 0) {
+            std::vector<double> zero((size_t)c->d.dim * c->nm, 0.0);
+            const int rc = fsa_set_state(c, zero.data(), 0.0, 0);
+            if (rc != FSA_OK) return mb_fail(m, rc, std::string("block state: ") + fsa_last_error(c));
+        } else {
+            c->t = 0.0;
+            c->step = 0;
+        }
     }
     return FSA_OK;
 }
@@ -1853,21 +1894,32 @@ int32_t fsa_mb_rk3_steps(fsa_mb* m, double dt, int32_t nsteps)
         m->blk[b]->advanced = nullptr;
         bufs[b] = m->Q[b];
     }
-    int rc = mb_alpha(m, bufs);   // the states' wave speeds (their halos are exact)
+    int rc = mb_alpha(m, bufs);   // the states' wave speeds
     if (rc != FSA_OK) return rc;
     for (int n = 0; n < nsteps; ++n) {
         for (int s = 0; s < 3; ++s) {
+            // the blocks' stages side by side on their streams, after the caller's stream
+            // (copies, wave speeds), which then waits for all of them
+            if (hipEventRecord(m->ev_main, m->stream) != hipSuccess) return mb_fail(m, FSA_EDEVICE, "event record");
             for (int b = 0; b < m->nb; ++b) {
                 fsa_ctx* c = m->blk[b];
+                if (hipStreamWaitEvent(m->bstream[b], m->ev_main, 0) != hipSuccess)
+                    return mb_fail(m, FSA_EDEVICE, "stream wait");
                 const double* Qs = s == 0 ? m->Q[b] : (s == 1 ? c->Qa : c->Qb);
                 double* out = s == 0 ? c->Qa : (s == 1 ? c->Qb : m->Q[b]);
-                if ((rc = enqueue_stage(c, Qs, m->Q[b], out, 0, -1, false, s + 1, CA[s], CB[s], dt, 0)) != FSA_OK)
+                // the stage kernel's wave-speed partials of the block's own layers, reduced into
+                // its slot 1 on its stream
+                if ((rc = enqueue_stage(c, Qs, m->Q[b], out, 0, 1, false, s + 1, CA[s], CB[s], dt, 0)) != FSA_OK ||
+                    (rc = flush_alpha_final(c)) != FSA_OK)
                     return mb_fail(m, rc, std::string("block stage: ") + fsa_last_error(c));
                 bufs[b] = out;
+                if (hipEventRecord(m->bev[b], m->bstream[b]) != hipSuccess ||
+                    hipStreamWaitEvent(m->stream, m->bev[b], 0) != hipSuccess)
+                    return mb_fail(m, FSA_EDEVICE, "stream join");
             }
-            if (launch_copy_list(m->d_copy[s], m->ncopy, m->copy_max, m->stream))
-                return mb_fail(m, FSA_EDEVICE, "halo copy launch failed");
-            if ((rc = mb_alpha(m, bufs)) != FSA_OK) return rc;
+            if (launch_copy_list(m->d_copy[s], m->ncopy, m->copy_max, m->stream) ||
+                launch_amax_blocks(m->d_slot_in, m->d_slot_out, m->nb, m->stream))
+                return mb_fail(m, FSA_EDEVICE, "halo copy or cross-block maximum launch failed");
         }
         for (fsa_ctx* c : m->blk) {
             c->t += dt;

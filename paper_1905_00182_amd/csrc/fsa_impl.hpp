@@ -37,6 +37,8 @@ struct StageArgs {
     unsigned* dbg_y;                       // x, y (and z) face this launch reconstructs, bits
     unsigned* dbg_z;                       // 3c+k (side +) and 16+3c+k (side -), face layout of
                                            // launch_stage2d / launch_stage3d
+    int arow0, arow1;                      // layers along the last direction (y in 2D, z in 3D)
+                                           // whose cells enter the wave-speed partials
 };
 
 // Arguments of the per-stage immersed-boundary kernel.
@@ -121,6 +123,9 @@ constexpr int ALPHA_MAX_BLOCKS = 2048;
 long long alpha_blocks(const Grid& G);
 int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* part, unsigned long long* bits,
                  hipStream_t s);
+// The same over the layers row0 .. row1 - 1 along the last direction only.
+int launch_alpha_rows(const Grid& G, const Phys& P, const double* Q, int row0, int row1, unsigned long long* part,
+                      unsigned long long* bits, hipStream_t s);
 // bits[d] = NaN-propagating max over n partials part[k * 3 + d] (d < 3).
 int launch_alpha_final(const unsigned long long* part, long long n, unsigned long long* bits, hipStream_t s);
 int launch_ib_stage(const Grid& G, const Phys& P, const IBArgs& A, hipStream_t s);

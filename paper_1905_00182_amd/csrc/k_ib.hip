@@ -30,7 +30,8 @@ __device__ __forceinline__ unsigned long long wave_max_bits(unsigned long long v
 // alpha_d = max over cells of |u_d| + c, NaN-propagating (bits of non-negative doubles).
 template <int DIM>
 __global__ __launch_bounds__(RED_THREADS) void k_alpha(Grid G, Phys P, const double* __restrict__ Q,
-                                                       unsigned long long* __restrict__ part)
+                                                       unsigned long long* __restrict__ part, long long c0,
+                                                       long long c1)
 {
     unsigned long long* __restrict__ out = part;
     __shared__ unsigned long long wpart[RED_THREADS / 64][DIM];
@@ -38,7 +39,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_alpha(Grid G, Phys P, const dou
 #pragma unroll
     for (int d = 0; d < DIM; ++d) m[d] = 0ull;
     const long long nc = G.ncell;
-    for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < nc;
+    for (long long n = c0 + (long long)blockIdx.x * blockDim.x + threadIdx.x; n < c1;
          n += (long long)gridDim.x * blockDim.x) {
         // the stage kernels' expressions for the wave speeds of their output, operation for
         // operation, so that a stage input's speeds do not depend on which kernel took them
@@ -489,9 +490,19 @@ long long alpha_blocks(const Grid& G)
 int launch_alpha(const Grid& G, const Phys& P, const double* Q, unsigned long long* part, unsigned long long* bits,
                  hipStream_t s)
 {
+    return launch_alpha_rows(G, P, Q, 0, G.n[G.dim - 1], part, bits, s);
+}
+
+int launch_alpha_rows(const Grid& G, const Phys& P, const double* Q, int row0, int row1, unsigned long long* part,
+                      unsigned long long* bits, hipStream_t s)
+{
     const long long blocks = alpha_blocks(G);
-    if (G.dim == 3) hipLaunchKernelGGL(k_alpha<3>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, part);
-    else hipLaunchKernelGGL(k_alpha<2>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, part);
+    const long long plane = G.dim == 3 ? (long long)G.n[0] * G.n[1] : (long long)G.n[0];
+    const long long c0 = plane * row0, c1 = plane * row1;
+    if (G.dim == 3)
+        hipLaunchKernelGGL(k_alpha<3>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, part, c0, c1);
+    else
+        hipLaunchKernelGGL(k_alpha<2>, dim3((unsigned)blocks), dim3(RED_THREADS), 0, s, G, P, Q, part, c0, c1);
     return launch_alpha_final(part, blocks, bits, s);
 }
 

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(BX * BY) void k_pstage2d(const KConst* __restrict__
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) A.out[c * G.ncell + o] = val[c];
-        if (A.alpha_part) {
+        if (A.alpha_part && j >= A.arow0 && j < A.arow1) {
             const double ir = rcp_nr(val[0]);
             const double u = val[1] * ir, v = val[2] * ir;
             const double pn = K->P.gm1 * (val[3] - 0.5 * fma(val[1], u, val[2] * v));

@@ -185,6 +185,7 @@ struct Column2D {
     double sg_rows;                 // sponge rate of row sg_base + lane
     int sg_base;
     unsigned long long amax_x, amax_y;
+    int ar0, ar1;                   // rows whose cells enter the wave-speed maximum
     long long step;
     // register windows, slot = (row - first front row) mod 5
     T fp[5][4], fm[5][4];
@@ -534,8 +535,9 @@ struct Column2D {
                     const double cn = sqrt(gam() * pn * ir);
                     const unsigned long long sx = (unsigned long long)__double_as_longlong(fabs(un) + cn);
                     const unsigned long long sy = (unsigned long long)__double_as_longlong(fabs(vn) + cn);
-                    amax_x = out_lane ? max_bits(amax_x, sx) : amax_x;
-                    amax_y = out_lane ? max_bits(amax_y, sy) : amax_y;
+                    const bool ain = out_lane && r >= ar0 && r < ar1;
+                    amax_x = ain ? max_bits(amax_x, sx) : amax_x;
+                    amax_y = ain ? max_bits(amax_y, sy) : amax_y;
                     if constexpr (SCHEME == LEARNED) {
                         // the FP32 deviations the next flags pass forms from this output (same
                         // expressions), for its test of tiles whose stencils are all
@@ -701,6 +703,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         for (int m = 0; m < 8; ++m) rng[m][threadIdx.x] = (m & 1) ? -INFINITY : INFINITY;
     }
     C.amax_x = C.amax_y = 0ull;
+    C.ar0 = A.arow0;
+    C.ar1 = A.arow1;
     const int Rend = C.j1 + HALO;
 #pragma unroll
     for (int s = 0; s < C.PF; ++s) {

@@ -401,7 +401,7 @@ __global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ 
         }
 #pragma unroll
         for (int c = 0; c < 5; ++c) A.out[c * G.ncell + o] = val[c];
-        if (A.alpha_part) {
+        if (A.alpha_part && k >= A.arow0 && k < A.arow1) {
             const double ir = rcp_nr(val[0]);
             const double u = val[1] * ir, v = val[2] * ir, w = val[3] * ir;
             const double pn = K->P.gm1 * (val[4] - 0.5 * fma(val[1], u, fma(val[2], v, val[3] * w)));
