@@ -16,7 +16,10 @@ wave reaches the radius-50 probe ring).  It records:
 
 Only oracle/ computes; paper_1905_00182_amd.workloads builds the case and its initial state.
 One run takes a few hours on 8 host cores; `--checkpoint DIR` saves the state every 500
-steps there and resumes from the latest one.
+steps there and resumes from the latest one.  `--scheme weno5js --steps 200 --out
+tests/golden/c2_oracle_run_weno5js_200.npz` writes the companion record of the same set-up in
+WENO5-JS, whose continuous weights make the run determined to rounding (a snapshot is also
+taken after the last step).
 """
 import argparse
 import os
@@ -59,9 +62,12 @@ def main():
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--checkpoint", default=None)
     ap.add_argument("--out", default=OUT)
+    ap.add_argument("--scheme", default="teno5", choices=["teno5", "weno5js"])
     args = ap.parse_args()
 
     case = W.config2()
+    if args.scheme != case.scheme:
+        case = case.with_(scheme=args.scheme)
     nprobe = case.probes.shape[1]
     rings = np.concatenate([case.probes, W.ring_probes(nprobe, 10.0)], axis=1)
     o = Oracle(case.with_(probes=rings))
@@ -76,7 +82,7 @@ def main():
     force = np.zeros((nrec, 2))
     norms = np.zeros((args.steps // NORM_EVERY, case.nq))
     dnorms = np.zeros_like(norms)
-    snaps_at = [s for s in SNAP_STEPS if s <= args.steps]
+    snaps_at = sorted(set([s for s in SNAP_STEPS if s <= args.steps] + [args.steps]))
     snaps = np.zeros((len(snaps_at), case.nq, cells.size))
 
     start = 0
@@ -128,7 +134,7 @@ def main():
         args.out, steps=np.int64(args.steps), every=np.int64(EVERY), norm_every=np.int64(NORM_EVERY),
         dt=np.float64(case.dt), seed=np.int64(case.seed), dp_r50=dp_r50, dp_r10=dp_r10, force=force,
         norms=norms, dnorms=dnorms, cells=cells, snap_steps=np.array(snaps_at, dtype=np.int64), snaps=snaps,
-        note=np.array("CPU oracle, FP64; see c2_oracle_run.py"))
+        scheme=np.array(args.scheme), note=np.array("CPU oracle, FP64; see c2_oracle_run.py"))
     print(f"wrote {args.out} after {time.time() - t0:.0f} s", flush=True)
 
 

@@ -159,3 +159,59 @@ def test_sampled_state(runs):
             _check(rows, f"step {n} component {c} (change up to {np.abs(o[c] - Q0s[c]).max():.2e})",
                    _rel(g[c] - Q0s[c], o[c] - Q0s[c]), _rel(g[c] - Q0s[c], z[c] - Q0s[c]), SNAP_PHYS)
     _assert_rows(rows)
+
+
+RECORD_WENO = os.path.join(os.path.dirname(__file__), "golden", "c2_oracle_run_weno5js_200.npz")
+
+
+def test_weno5js_companion_run_to_rounding():
+    """The same 2048^2 set-up in WENO5-JS, whose continuous weights leave the run determined to
+    rounding: 200 steps from the uniform start against the oracle's record of them
+    (c2_oracle_run_weno5js_200.npz), held to the parity tests' bounds -- R20's 1e-12 (relative
+    L2 per component, scaled by its natural size) and the element-wise bound on the sampled
+    state after the last step, the probe pressure to 1e-12 of p_inf, force and norms to 1e-10
+    relative."""
+    import torch
+
+    from test_gpu_parity_2d import ELEM_ULPS, TOL_ELEM, natural_scale
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(RECORD_WENO):
+        pytest.skip("the WENO5-JS record has not been written (tests/golden/c2_oracle_run.py --scheme weno5js)")
+    rec = np.load(RECORD_WENO)
+    assert str(rec["scheme"]) == "weno5js"
+    steps, every, norm_every = int(rec["steps"]), int(rec["every"]), int(rec["norm_every"])
+    case = W.config2().with_(scheme="weno5js")
+    assert abs(float(rec["dt"]) - case.dt) == 0.0
+    nprobe = case.probes.shape[1]
+    s = _solver(case.with_(probes=np.concatenate([case.probes, W.ring_probes(nprobe, 10.0)], axis=1)))
+    Q0 = W.config2_state(case)
+    Q = torch.from_numpy(Q0.copy()).cuda()
+    dp, force, norms = [], [], []
+    for k in range(steps // every):
+        s.rk3_steps(Q, case.dt, every) if k == 0 else s.rk3_steps_resume(Q, case.dt, every)
+        dp.append(s.probe_dp(Q).cpu().numpy())
+        force.append((s.marker_force() * case.markers["dV"]).sum(axis=1))
+        if ((k + 1) * every) % norm_every == 0:
+            norms.append([float(torch.linalg.norm(Q[c])) for c in range(case.nq)])
+    s.sync()
+    dp, force = np.array(dp), np.array(force)
+    p_inf = case.prim_inf[4]
+    d50 = np.abs(dp[:, :nprobe] - rec["dp_r50"]).max()
+    d10 = np.abs(dp[:, nprobe:] - rec["dp_r10"][: dp.shape[0]]).max()
+    _say(f"  WENO5-JS {steps} steps: probes max|d dp| r=50 {d50:.2e}, r=10 {d10:.2e} of p_inf {p_inf:.3f}; "
+         f"force rel {_rel(force, rec['force']):.2e}; norms rel {_rel(np.array(norms), rec['norms']):.2e}")
+    assert d50 <= 1e-12 * p_inf and d10 <= 1e-12 * p_inf
+    assert _rel(force, rec["force"]) <= 1e-10
+    assert _rel(np.array(norms), rec["norms"]) <= 1e-12
+    g = Q.reshape(case.nq, -1)[:, torch.from_numpy(rec["cells"]).cuda()].cpu().numpy()
+    o = rec["snaps"][-1]
+    Q0s = Q0.reshape(case.nq, -1)[:, rec["cells"]]
+    scale = natural_scale(case)
+    for c in range(case.nq):
+        rel = np.linalg.norm(g[c] - o[c]) / max(np.linalg.norm(o[c]), scale[c] * np.sqrt(o[c].size))
+        d, dev = np.abs(g[c] - o[c]).max(), np.abs(o[c] - Q0s[c]).max()
+        _say(f"  step {steps} component {c}: rel L2 {rel:.3e}, max|dQ| {d:.3e} of change {dev:.3e}")
+        assert rel <= 1e-12
+        assert d <= TOL_ELEM * dev + ELEM_ULPS * np.finfo(float).eps * scale[c], (c, d, dev)
