@@ -47,14 +47,6 @@ __device__ __forceinline__ void cell_state(const KConst* K, const double* __rest
     }
 }
 
-template <int D>
-__device__ __forceinline__ void offset(int& i, int& j, int& k, int s)
-{
-    if (D == 0) i += s;
-    else if (D == 1) j += s;
-    else k += s;
-}
-
 template <class T>
 __device__ __forceinline__ T d1(T gm2, T gm1, T gp1, T gp2, T inv12h)
 {
@@ -188,6 +180,17 @@ __host__ __device__ __forceinline__ long long faces_of(const Grid& G)
     return (long long)(G.n[0] + (D == 0)) * (G.n[1] + (D == 1)) * (G.n[2] + (D == 2));
 }
 
+// A block's faces along D: 64 along x by 4 along a second axis (y for D = 0 and 1, z for
+// D = 2, the block then taking one y row); the cells those faces read form a tile of
+// TX x TA cells (3 more on either side along D), staged in LDS with their pressure and normal
+// velocity, so that each cell is loaded and its primitives formed once per block instead of
+// once per face that reads it (six), in the same expressions.
+template <int D>
+struct FaceTile {
+    static constexpr int TX = BX + (D == 0 ? 6 : 0);   // cells along x
+    static constexpr int TA = D == 0 ? BY : BY + 6;    // cells along the second axis
+};
+
 // Face fluxes along D: threads cover the faces f = 0..n_D along D (x index for D = 0, y index
 // for D = 1, z index for D = 2) and the cells of the two other directions.
 // DBG (FP64 TENO5 only) also writes each face's keep patterns to dbg, in the face layout.
@@ -198,21 +201,33 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
                                                      T* __restrict__ Fh, unsigned* __restrict__ dbg)
 {
     constexpr bool F64 = std::is_same<T, double>::value;
+    constexpr int TX = FaceTile<D>::TX, TA = FaceTile<D>::TA;
     const Grid& G = K->G;
-    const int xi = blockIdx.x * BX + (threadIdx.x & (BX - 1));
-    const int yi = blockIdx.y * BY + (threadIdx.x / BX);
-    const int zi = blockIdx.z;
+    __shared__ double tq[5][TA][TX];
+    __shared__ double tp[TA][TX], tu[TA][TX];
     __shared__ __attribute__((aligned(16))) KeepRows<T> keep_rows;
-    if (SCHEME != WENO5JS) {
-        init_keep_rows<T>(keep_rows, threadIdx.x);
-        __syncthreads();
+    if (SCHEME != WENO5JS) init_keep_rows<T>(keep_rows, threadIdx.x);
+    const int x0 = blockIdx.x * BX - (D == 0 ? 3 : 0);
+    for (int c = threadIdx.x; c < TA * TX; c += BX * BY) {
+        const int ca = c / TX, cx = c - ca * TX;
+        const int ci = x0 + cx;
+        const int cj = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * BY + ca - (D == 1 ? 3 : 0);
+        const int ck = D == 2 ? (int)blockIdx.z * BY + ca - 3 : (int)blockIdx.z;
+        double qc[5];
+        cell_state(K, Q, step, ci, cj, ck, qc);   // (ghosts resolved by the boundary rules)
+        const double ir = rcp_nr(qc[0]);
+        const double u = qc[1] * ir, v = qc[2] * ir, w = qc[3] * ir;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) tq[m][ca][cx] = qc[m];
+        tp[ca][cx] = K->P.gm1 * (qc[4] - 0.5 * fma(qc[1], u, fma(qc[2], v, qc[3] * w)));
+        tu[ca][cx] = D == 0 ? u : (D == 1 ? v : w);
     }
+    __syncthreads();
+    const int fx = threadIdx.x & (BX - 1), fa = threadIdx.x / BX;
+    const int xi = blockIdx.x * BX + fx;
+    const int yi = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * BY + fa;
+    const int zi = D == 2 ? (int)blockIdx.z * BY + fa : (int)blockIdx.z;
     if (xi >= G.n[0] + (D == 0) || yi >= G.n[1] + (D == 1) || zi >= G.n[2] + (D == 2)) return;
-    // cell below the face along D, and the cell coordinates of the line
-    int i = xi, j = yi, k = zi;
-    if (D == 0) i -= 1;
-    else if (D == 1) j -= 1;
-    else k -= 1;
     const int f = D == 0 ? xi : (D == 1 ? yi : zi);
     const double alpha = __longlong_as_double((long long)abits[D]);
     Recon R;
@@ -228,16 +243,15 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
         R.rows = nullptr;
         R32.rows = keep_rows;
     }
+    // the six cells i-2..i+3 of the face (i below it along D) from the tile
     double q[6][5], ud[6], p[6];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
-        int ii = i, jj = j, kk = k;
-        offset<D>(ii, jj, kk, s - 2);
-        cell_state(K, Q, step, ii, jj, kk, q[s]);
-        const double ir = rcp_nr(q[s][0]);
-        const double u = q[s][1] * ir, v = q[s][2] * ir, w = q[s][3] * ir;
-        p[s] = K->P.gm1 * (q[s][4] - 0.5 * fma(q[s][1], u, fma(q[s][2], v, q[s][3] * w)));
-        ud[s] = D == 0 ? u : (D == 1 ? v : w);
+        const int cx = D == 0 ? fx + s : fx, ca = D == 0 ? fa : fa + s;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) q[s][m] = tq[m][ca][cx];
+        p[s] = tp[ca][cx];
+        ud[s] = tu[ca][cx];
     }
     const double* Finf = D == 0 ? K->Fx_inf : (D == 1 ? K->Fy_inf : K->Fz_inf);
     const long long nf = faces_of<D>(G);
@@ -459,7 +473,7 @@ static void launch_faces(const KConst* K, const Grid& G, const StageArgs& A, T* 
     T* Fz = Fy + 5 * faces_of<1>(G);
     const dim3 gx((G.n[0] + 1 + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
     const dim3 gy((G.n[0] + BX - 1) / BX, (G.n[1] + 1 + BY - 1) / BY, G.n[2]);
-    const dim3 gz((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2] + 1);
+    const dim3 gz((G.n[0] + BX - 1) / BX, G.n[1], (G.n[2] + 1 + BY - 1) / BY);   // (x by z faces)
     if constexpr (std::is_same<T, double>::value) {
         if (ch) {
             hipLaunchKernelGGL((k_faces3d<SCHEME, T, 0, false, true>), gx, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, nullptr);
