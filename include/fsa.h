@@ -353,9 +353,9 @@ int32_t fsa_stats_get(fsa_ctx* ctx, fsa_stats* out);
  * copies refresh each block's halo layers from its neighbours' stage output, and the global
  * Lax-Friedrichs speeds of that output are the maximum over the blocks' own (the all-reduce
  * of a multi-process run).  Each block holds the markers whose supports reach its own
- * layers, in their global order.  The result equals one context's over the whole domain bit
- * for bit.  Markers must be STATIC or ROTATING (positions fixed), probes and diagnostics are
- * taken on the gathered state.  Every call is stream-ordered on hip_stream unless it says
+ * layers, in their global order (re-dealt when EXTERNAL markers move, their penalty integrals
+ * going with them).  The result equals one context's over the whole domain bit for bit.
+ * Probes and diagnostics are taken on the gathered state.  Every call is stream-ordered on hip_stream unless it says
  * synchronising: the blocks' stages run side by side on streams of their own (created with
  * the default priority), which wait for hip_stream before each stage and which hip_stream
  * waits for after it.
@@ -374,11 +374,16 @@ const char* fsa_mb_last_error(const fsa_mb* mb);
 /* Block b's first global layer, layer count, and halo layers below and above. */
 int32_t fsa_mb_block_info(const fsa_mb* mb, int32_t b, int32_t* first, int32_t* count, int32_t* halo_lo,
                           int32_t* halo_hi);
-/* Markers of the whole domain (HOST arrays as fsa_set_markers; motion STATIC or ROTATING,
- * else FSA_EUNSUPPORTED), shared out to the blocks whose layers their supports reach;
- * resets the penalty integral.  Synchronising. */
+/* Markers of the whole domain (HOST arrays as fsa_set_markers), shared out to the blocks
+ * whose layers their supports reach; resets the penalty integral.  Synchronising. */
 int32_t fsa_mb_set_markers(fsa_mb* mb, int32_t n, const double* X, const double* dV, const double* U,
                            int32_t motion, double omega);
+/* EXTERNAL markers: new positions X and velocities U (HOST [dim][n], U NULL: zero) for the
+ * steps that follow, as fsa_set_marker_kinematics.  A block whose markers stay the same takes
+ * the kinematics; one whose set changes is given its new markers with their penalty integrals
+ * (read back from the blocks that held them: synchronising then).  FSA_ESTATE: the markers
+ * are not EXTERNAL. */
+int32_t fsa_mb_set_marker_kinematics(fsa_mb* mb, const double* X, const double* U);
 /* The whole domain's state (DEVICE, [nq][cells] as fsa_rk3_step) into the blocks, halo
  * layers included; a fresh start: time, step and the penalty integral zero. */
 int32_t fsa_mb_scatter(fsa_mb* mb, const double* d_Q);

@@ -1546,6 +1546,9 @@ struct fsa_mb {
     std::vector<std::vector<int>> marker_of;    // per block: global indices of its markers
     std::vector<int> owner, owner_idx;          // per marker: a block holding it, its index there
     int nm = 0;
+    int motion = FSA_STATIC;
+    double omega = 0.0;
+    std::vector<double> dV;                     // every marker's quadrature weight
     std::string err;
 };
 
@@ -1786,51 +1789,124 @@ int32_t fsa_mb_block_info(const fsa_mb* m, int32_t b, int32_t* first, int32_t* c
     return FSA_OK;
 }
 
-int32_t fsa_mb_set_markers(fsa_mb* m, int32_t n, const double* X, const double* dV, const double* U, int32_t motion,
-                           double omega)
+// The blocks whose own layers the support of each marker reaches, in the markers' global
+// order (validating that every support lies inside the whole grid).
+int mb_partition(fsa_mb* m, int n, const double* X, std::vector<std::vector<int>>& lists)
 {
-    if (!m || n < 0 || (n > 0 && (!X || !dV))) return FSA_EINVAL;
-    if (motion != FSA_STATIC && motion != FSA_ROTATING)
-        return mb_fail(m, FSA_EUNSUPPORTED, "blocks hold STATIC or ROTATING markers only");
     const fsa_desc& w = m->whole;
-    const int dim = w.dim;
     std::vector<int> j0(n);
     for (int k = 0; k < n; ++k)
-        for (int d = 0; d < dim; ++d) {
+        for (int d = 0; d < w.dim; ++d) {
             const double x = X[(size_t)d * n + k];
             if (!std::isfinite(x)) return mb_fail(m, FSA_EINVAL, "non-finite marker position");
             const double j = std::floor((x - w.lo[d]) / w.h - 0.5) - 1.0;
             if (j < 0.0 || j + 3.0 > (double)(w.n[d] - 1)) return mb_fail(m, FSA_EINVAL, "a marker support leaves the grid");
             if (d == m->dir) j0[k] = (int)j;
         }
-    m->nm = n;
-    m->owner.assign(n, -1);
-    m->owner_idx.assign(n, -1);
+    lists.assign(m->nb, {});
     for (int b = 0; b < m->nb; ++b) {
-        std::vector<int>& mine = m->marker_of[b];
-        mine.clear();
         const int lo = m->first[b], hi = m->first[b] + m->count[b] - 1;
         for (int k = 0; k < n; ++k)
-            if (j0[k] + 3 >= lo && j0[k] <= hi) {
-                if (m->owner[k] < 0) {
-                    m->owner[k] = b;
-                    m->owner_idx[k] = (int)mine.size();
-                }
-                mine.push_back(k);
-            }
-        const int nbk = (int)mine.size();
-        std::vector<double> Xb((size_t)dim * nbk), Ub((size_t)dim * nbk, 0.0), dVb(nbk);
-        for (int i = 0; i < nbk; ++i) {
-            const int k = mine[i];
-            dVb[i] = dV[k];
-            for (int d = 0; d < dim; ++d) {
-                Xb[(size_t)d * nbk + i] = X[(size_t)d * n + k];
-                if (U) Ub[(size_t)d * nbk + i] = U[(size_t)d * n + k];
+            if (j0[k] + 3 >= lo && j0[k] <= hi) lists[b].push_back(k);
+    }
+    return FSA_OK;
+}
+
+// Block b's slice of the markers' host arrays ([dim][n]) for its list.
+void mb_slice(const fsa_mb* m, const std::vector<int>& list, int n, const double* A, std::vector<double>& out)
+{
+    const int dim = m->whole.dim, nbk = (int)list.size();
+    out.assign((size_t)dim * nbk, 0.0);
+    if (!A) return;
+    for (int i = 0; i < nbk; ++i)
+        for (int d = 0; d < dim; ++d) out[(size_t)d * nbk + i] = A[(size_t)d * n + list[i]];
+}
+
+void mb_owners(fsa_mb* m)
+{
+    m->owner.assign(m->nm, -1);
+    m->owner_idx.assign(m->nm, -1);
+    for (int b = 0; b < m->nb; ++b)
+        for (int i = 0; i < (int)m->marker_of[b].size(); ++i) {
+            const int k = m->marker_of[b][i];
+            if (m->owner[k] < 0) {
+                m->owner[k] = b;
+                m->owner_idx[k] = i;
             }
         }
+}
+
+int32_t fsa_mb_set_markers(fsa_mb* m, int32_t n, const double* X, const double* dV, const double* U, int32_t motion,
+                           double omega)
+{
+    if (!m || n < 0 || (n > 0 && (!X || !dV))) return FSA_EINVAL;
+    if (motion < FSA_STATIC || motion > FSA_EXTERNAL) return mb_fail(m, FSA_EINVAL, "bad motion");
+    std::vector<std::vector<int>> lists;
+    if (int rc = mb_partition(m, n, X, lists)) return rc;
+    m->nm = n;
+    m->motion = motion;
+    m->omega = omega;
+    m->dV.assign(dV ? dV : nullptr, dV ? dV + n : nullptr);
+    for (int b = 0; b < m->nb; ++b) {
+        m->marker_of[b] = lists[b];
+        const int nbk = (int)lists[b].size();
+        std::vector<double> Xb, Ub, dVb(nbk);
+        mb_slice(m, lists[b], n, X, Xb);
+        mb_slice(m, lists[b], n, U, Ub);
+        for (int i = 0; i < nbk; ++i) dVb[i] = dV[lists[b][i]];
         const int rc = fsa_set_markers(m->blk[b], nbk, Xb.data(), dVb.data(), U ? Ub.data() : nullptr, motion, omega);
         if (rc != FSA_OK) return mb_fail(m, rc, std::string("block marker set: ") + fsa_last_error(m->blk[b]));
     }
+    mb_owners(m);
+    return FSA_OK;
+}
+
+int32_t fsa_mb_set_marker_kinematics(fsa_mb* m, const double* X, const double* U)
+{
+    if (!m || !X) return FSA_EINVAL;
+    if (m->nm == 0 || m->motion != FSA_EXTERNAL) return mb_fail(m, FSA_ESTATE, "markers are not EXTERNAL");
+    const int n = m->nm, dim = m->whole.dim;
+    std::vector<std::vector<int>> lists;
+    if (int rc = mb_partition(m, n, X, lists)) return rc;
+    bool moved = false;
+    for (int b = 0; b < m->nb; ++b) moved = moved || lists[b] != m->marker_of[b];
+    // the penalty integral of every marker, from a block holding it, when a marker's supports
+    // reach another set of blocks now (every holder keeps the same values)
+    std::vector<double> xi;
+    if (moved) {
+        xi.assign((size_t)dim * n, 0.0);
+        for (int b = 0; b < m->nb; ++b) {
+            const std::vector<int>& old = m->marker_of[b];
+            if (old.empty()) continue;
+            std::vector<double> xb((size_t)dim * old.size());
+            if (int rc = fsa_get_state(m->blk[b], xb.data(), nullptr, nullptr)) return mb_fail(m, rc, "block state");
+            for (int i = 0; i < (int)old.size(); ++i)
+                for (int d = 0; d < dim; ++d) xi[(size_t)d * n + old[i]] = xb[(size_t)d * old.size() + i];
+        }
+    }
+    for (int b = 0; b < m->nb; ++b) {
+        std::vector<double> Xb, Ub;
+        mb_slice(m, lists[b], n, X, Xb);
+        mb_slice(m, lists[b], n, U, Ub);
+        int rc = FSA_OK;
+        if (lists[b] == m->marker_of[b]) {
+            if (!lists[b].empty()) rc = fsa_set_marker_kinematics(m->blk[b], Xb.data(), U ? Ub.data() : nullptr);
+        } else {
+            const int nbk = (int)lists[b].size();
+            std::vector<double> dVb(nbk), xb;
+            for (int i = 0; i < nbk; ++i) dVb[i] = m->dV[lists[b][i]];
+            mb_slice(m, lists[b], n, xi.data(), xb);
+            double t = 0.0;
+            int64_t step = 0;
+            rc = fsa_get_state(m->blk[b], nullptr, &t, &step);
+            if (rc == FSA_OK)
+                rc = fsa_set_markers(m->blk[b], nbk, Xb.data(), dVb.data(), U ? Ub.data() : nullptr, FSA_EXTERNAL, 0.0);
+            if (rc == FSA_OK) rc = fsa_set_state(m->blk[b], nbk ? xb.data() : nullptr, t, step);
+            m->marker_of[b] = lists[b];
+        }
+        if (rc != FSA_OK) return mb_fail(m, rc, std::string("block kinematics: ") + fsa_last_error(m->blk[b]));
+    }
+    mb_owners(m);
     return FSA_OK;
 }
 

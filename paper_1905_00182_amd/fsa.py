@@ -162,6 +162,7 @@ _SIGS = {
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "fsa_mb_set_markers": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                        C.c_double]),
+    "fsa_mb_set_marker_kinematics": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fsa_mb_scatter": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fsa_mb_gather": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "fsa_mb_rk3_steps": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32]),
@@ -365,6 +366,16 @@ class MultiBlock:
         self._check(lib().fsa_mb_set_markers(self.mb, n, X.ctypes.data, dV.ctypes.data,
                                              Ua.ctypes.data if Ua is not None else None, MOTION[motion], omega))
         self.nm = n
+
+    def set_marker_kinematics(self, X, U=None):
+        X = _host(X)
+        if X.shape != (self.nq - 2, self.nm):
+            raise ValueError(f"X must have shape {(self.nq - 2, self.nm)}, not {X.shape}")
+        Ua = _host(U) if U is not None else None
+        if Ua is not None and Ua.shape != X.shape:
+            raise ValueError(f"U must have shape {X.shape}, not {Ua.shape}")
+        self._check(lib().fsa_mb_set_marker_kinematics(self.mb, X.ctypes.data,
+                                                       Ua.ctypes.data if Ua is not None else None))
 
     def scatter(self, Q):
         self._check(lib().fsa_mb_scatter(self.mb, _ptr(self._state(Q))))

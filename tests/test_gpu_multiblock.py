@@ -5,8 +5,8 @@ the one-GPU stand-in for the paper's domain decomposition across processes (Sec.
 
 The blocks' result must equal one context's over the whole domain bit for bit. The cases
 are the rotating-cylinder set-up with inflow noise, sponge and markers (2D, blocks along y),
-a periodic box whose halos wrap around (2D), and the sphere with its markers (3D, blocks
-along z), with uneven block sizes.
+a periodic box whose halos wrap around (2D), the sphere with its markers (3D, blocks along
+z), with uneven block sizes, and markers that move from block to block.
 """
 import numpy as np
 import pytest
@@ -81,6 +81,60 @@ def test_periodic_box_wrapped_halos(torch_cuda):
     _assert_bitwise(Qs, Qm, Q0)
 
 
+def _blocks_reached(X, case, info):
+    """For each marker, the set of blocks whose own layers its 4-point support reaches."""
+    d = case.dim - 1
+    j0 = np.floor((X[d] - case.lo[d]) / case.h - 0.5).astype(int) - 1
+    return [frozenset(b for b, (first, count, _, _) in enumerate(info) if j + 3 >= first and j <= first + count - 1)
+            for j in j0]
+
+
+@pytest.mark.parametrize("what", ["plate", "insect"])
+def test_moving_markers_cross_blocks(torch_cuda, what):
+    """EXTERNAL markers moved every step on both sides: the rigid flapping plate (its motion
+    played 40 times faster, so that it heaves through the block boundary at y = 0 in 60 steps)
+    in 4 blocks (24 steps re-deal markers) and the hovering insect's wings in 5 uneven blocks
+    (3 steps). The markers whose supports
+    come to reach another set of blocks are dealt out again with their penalty integrals; the
+    state and marker forces must stay equal to one context's bit for bit."""
+    from paper_1905_00182_amd import fsa
+
+    torch = torch_cuda
+    if what == "plate":
+        case, nb, nsteps, least = W.config5(n=128, L=8.0, nmark=128), 4, 60, 10
+        kin = lambda n: (W.plate_kinematics(case, 40.0 * n * case.dt)[0],
+                         W.plate_kinematics(case, 40.0 * n * case.dt)[1])
+    else:
+        case, nb, nsteps, least = W.insect(n=192, L=3.84, sponge=0.5, nprobe=0), 5, 40, 2
+        kin = lambda n: W.insect_kinematics(case, n * case.dt)
+    Q0 = W.uniform_state(case)
+    s = _solver(case)
+    m = fsa.MultiBlock(case, nb)
+    info = [m.block_info(b) for b in range(nb)]
+    Qs = torch.from_numpy(Q0.copy()).cuda()
+    m.scatter(torch.from_numpy(Q0.copy()).cuda())
+    deals, redealt = [], 0
+    for n in range(nsteps):
+        X, U = kin(n)
+        deal = _blocks_reached(X, case, info)
+        redealt += int(bool(deals) and deal != deals[-1])
+        deals.append(deal)
+        s.set_marker_kinematics(X, U)
+        m.set_marker_kinematics(X, U)
+        s.rk3_step(Qs, case.dt) if n == 0 else s.rk3_steps_resume(Qs, case.dt)
+        m.rk3_steps(case.dt, 1)
+    Qm = m.gather()
+    torch.cuda.synchronize()
+    crossing = sum(len(d) > 1 for d in deals[-1])
+    _say(f"{what} in {nb} blocks: {redealt} of {nsteps - 1} steps dealt markers out again; "
+         f"{crossing} markers reach two blocks at the end")
+    assert redealt >= least
+    Qs, Qm = Qs.cpu().numpy(), Qm.cpu().numpy()
+    _assert_bitwise(Qs, Qm, Q0)
+    assert np.isfinite(Qs).all()
+    assert np.array_equal(s.marker_force(), m.marker_force())
+
+
 def test_precision_form_and_characteristic_variant(torch_cuda):
     base = W.config2(n=200, h=1.0 / 16.0, sponge=2.0, nprobe=8, rprobe=2.0).with_(n=(160, 150, 1))
     Q0 = W.config2_noisy_state(base)
@@ -104,11 +158,15 @@ def test_block_set_rejections(torch_cuda):
     with pytest.raises(fsa.FsaError) as e:
         fsa.MultiBlock(case, 17)                 # 64 layers in 17 blocks: thinner than the halo
     assert e.value.code == fsa.EINVAL
-    m = fsa.MultiBlock(case.with_(markers=None), 2)
+    m = fsa.MultiBlock(case, 2)                  # the rotating cylinder's markers
     X = case.markers["X"]
     with pytest.raises(fsa.FsaError) as e:
-        m.set_markers(X, case.markers["dV"], None, "external", 0.0)
-    assert e.value.code == fsa.EUNSUPPORTED
+        m.set_marker_kinematics(X)               # the markers are not EXTERNAL
+    assert e.value.code == fsa.ESTATE
+    m.set_markers(X, case.markers["dV"], None, "external", 0.0)
+    with pytest.raises(fsa.FsaError) as e:
+        m.set_marker_kinematics(X + 10.0)        # supports outside the grid
+    assert e.value.code == fsa.EINVAL
     with pytest.raises(fsa.FsaError) as e:
         m.set_markers(X + 10.0, case.markers["dV"])  # supports outside the grid
     assert e.value.code == fsa.EINVAL
