@@ -72,19 +72,24 @@ __device__ __forceinline__ void velocity(const KConst* K, const double* Q, long 
 }
 
 // The stress pass marches a 64 x 4 column tile of the extended grid up z over a segment of
-// SZ planes: each step forms the velocities of one plane of the tile and its two-cell x and
-// y halo (every cell's velocity once, instead of once per neighbour that needs it) into a
-// four-plane LDS ring, keeps this thread's column of five planes in registers for the z
-// derivatives, and writes the stress of the plane two below.  One barrier per step: a slot
-// is rewritten two steps after its last read.
+// SZ planes.  Each step stages the velocities of one front plane of the tile and its two-cell
+// x and y halo (every cell's velocity once, instead of once per neighbour that needs it) in
+// LDS, takes this thread's x and y derivatives of that plane there at once and keeps them,
+// with its column's velocities of five planes for the z derivatives, in registers until the
+// plane two above arrives; it then writes the stress of the plane two below.  The state of
+// the next front plane is loaded before the current plane's arithmetic, so the loads are in
+// flight while it runs.  Two LDS slots and one barrier per step: a slot is rewritten one step
+// after its last read, and every thread has passed that step's barrier by then.
 constexpr int SZ = 32, TXS = BX + 4, TYS = BY + 4;
+constexpr int SCELLS = TXS * TYS;                        // staged cells per plane
+constexpr int SPER = (SCELLS + BX * BY - 1) / (BX * BY);  // per thread
 
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_stress3d(const KConst* __restrict__ K, const double* __restrict__ Q,
                                                       long long step, T* __restrict__ S)
 {
     constexpr bool F64 = std::is_same<T, double>::value;
-    __shared__ T ring[4][3][TYS][TXS];
+    __shared__ T ring[2][3][TYS][TXS];
     const Grid& G = K->G;
     const int ex = G.n[0] + 4, ey = G.n[1] + 4, ez = G.n[2] + 4;
     const int tx = threadIdx.x & (BX - 1), ty = threadIdx.x / BX;
@@ -94,37 +99,90 @@ __global__ __launch_bounds__(BX * BY) void k_stress3d(const KConst* __restrict__
     const int ka = za - 2, kb = zb - 2;                           // their cell indices
     const T inv12h = (T)K->inv12h, mu = (T)K->P.mu;
     const long long ne = (long long)ex * ey * ez;
-    T w[5][3];   // this column's velocities at planes k-2 .. k+2
+    // this thread's staged cells (cell c = threadIdx.x + m * 256 of the tile with its halo)
+    // and their state for the next front plane (interior cells; ghosts are resolved when used)
+    int ci[SPER], cj[SPER];
+    bool cin[SPER];
+    double pq[SPER][5];
+#pragma unroll
+    for (int m = 0; m < SPER; ++m) {
+        const int c = threadIdx.x + m * BX * BY;
+        const int ly = c / TXS, lx = c - ly * TXS;
+        ci[m] = blockIdx.x * BX + lx - 4;
+        cj[m] = blockIdx.y * BY + ly - 4;
+        cin[m] = c < SCELLS && ci[m] >= 0 && ci[m] < G.n[0] && cj[m] >= 0 && cj[m] < G.n[1];
+    }
+    auto prefetch = [&](int kf) {
+        const bool kin = kf >= 0 && kf < G.n[2];
+#pragma unroll
+        for (int m = 0; m < SPER; ++m) {
+            if (cin[m] && kin) {
+                const long long o = lin3(G, ci[m], cj[m], kf);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) pq[m][c] = Q[c * G.ncell + o];
+            }
+        }
+    };
+    T w[5][3];    // this column's velocities at planes k-2 .. k+2
+    T gd[3][6];   // its x and y derivatives d u_a / d x, d u_a / d y at planes k .. k+2
 #pragma unroll
     for (int m = 0; m < 5; ++m)
 #pragma unroll
         for (int a = 0; a < 3; ++a) w[m][a] = T(0);
-    for (int kf = ka - 2; kf <= kb + 2; ++kf) {
-        // front plane kf of the tile with its halo
-        T (*pl)[TYS][TXS] = ring[(kf + 8) & 3];
-        for (int c = threadIdx.x; c < TXS * TYS; c += BX * BY) {
-            const int ly = c / TXS, lx = c - ly * TXS;
-            T u[3];
-            velocity<T>(K, Q, step, blockIdx.x * BX + lx - 4, blockIdx.y * BY + ly - 4, kf, u);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) pl[a][ly][lx] = u[a];
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) gd[m][a] = T(0);
+    prefetch(ka - 2);
+    for (int kf = ka - 2; kf <= kb + 2; ++kf) {
+        // front plane kf of the tile with its halo, from the state loaded one step ago
+        T (*pl)[TYS][TXS] = ring[kf & 1];
+        const bool kin = kf >= 0 && kf < G.n[2];
+#pragma unroll
+        for (int m = 0; m < SPER; ++m) {
+            const int c = threadIdx.x + m * BX * BY;
+            if (c < SCELLS) {
+                double q[5];
+                if (cin[m] && kin) {
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) q[a] = pq[m][a];
+                } else {
+                    fetch_state<3>(Q, G, K->P, step, ci[m], cj[m], kf, q);
+                }
+                const double ir = rcp_nr(q[0]);
+                const int ly = c / TXS, lx = c - ly * TXS;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double v = q[1 + a] * ir;
+                    pl[a][ly][lx] = F64 ? (T)v : (T)(v - K->P.prim_inf[1 + a]);
+                }
+            }
         }
+        if (kf < kb + 2) prefetch(kf + 1);
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int a = 0; a < 3; ++a) w[m][a] = w[m + 1][a];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) w[4][a] = pl[a][ty + 2][tx + 2];
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int a = 0; a < 6; ++a) gd[m][a] = gd[m + 1][a];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            w[4][a] = pl[a][ty + 2][tx + 2];
+            gd[2][2 * a] = d1(pl[a][ty + 2][tx], pl[a][ty + 2][tx + 1], pl[a][ty + 2][tx + 3], pl[a][ty + 2][tx + 4], inv12h);
+            gd[2][2 * a + 1] =
+                d1(pl[a][ty][tx + 2], pl[a][ty + 1][tx + 2], pl[a][ty + 3][tx + 2], pl[a][ty + 4][tx + 2], inv12h);
+        }
         const int k = kf - 2;
         if (k < ka || !out) continue;
-        // plane k: x and y neighbours from its ring slot, z neighbours from the column
-        const T (*pk)[TYS][TXS] = ring[(k + 8) & 3];
+        // plane k: x and y derivatives taken when it was staged, z derivatives from the column
         T g[3][3];   // g[a][b] = d u_a / d x_b
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            g[a][0] = d1(pk[a][ty + 2][tx], pk[a][ty + 2][tx + 1], pk[a][ty + 2][tx + 3], pk[a][ty + 2][tx + 4], inv12h);
-            g[a][1] = d1(pk[a][ty][tx + 2], pk[a][ty + 1][tx + 2], pk[a][ty + 3][tx + 2], pk[a][ty + 4][tx + 2], inv12h);
+            g[a][0] = gd[0][2 * a];
+            g[a][1] = gd[0][2 * a + 1];
             g[a][2] = d1(w[0][a], w[1][a], w[3][a], w[4][a], inv12h);
         }
         const T div = g[0][0] + g[1][1] + g[2][2];
