@@ -249,44 +249,25 @@ struct FaceTile {
     static constexpr int TA = D == 0 ? BY : BY + 6;    // cells along the second axis
 };
 
-// Face fluxes along D: threads cover the faces f = 0..n_D along D (x index for D = 0, y index
-// for D = 1, z index for D = 2) and the cells of the two other directions.
-// DBG (FP64 TENO5 only) also writes each face's keep patterns to dbg, in the face layout.
-// CH (FP64 only): characteristic-wise reconstruction.
-template <int SCHEME, class T, int D, bool DBG = false, bool CH = false>
-__global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ K, const double* __restrict__ Q,
-                                                     long long step, const unsigned long long* __restrict__ abits,
-                                                     T* __restrict__ Fh, unsigned* __restrict__ dbg)
+// Pressure and velocity along D of a staged cell, in the expressions every face pass uses.
+template <int D>
+__device__ __forceinline__ void cell_prims(const KConst* K, const double* qc, double& p, double& ud)
+{
+    const double ir = rcp_nr(qc[0]);
+    const double u = qc[1] * ir, v = qc[2] * ir, w = qc[3] * ir;
+    p = K->P.gm1 * (qc[4] - 0.5 * fma(qc[1], u, fma(qc[2], v, qc[3] * w)));
+    ud = D == 0 ? u : (D == 1 ? v : w);
+}
+
+// Face flux of one face along D from its six cells i-2..i+3 (i below it along D): state q,
+// pressure p and velocity ud; written per component to Fh[c * nf + o].  DBG (FP64 TENO5
+// only) also writes the face's keep patterns to dbg[o]; CH (FP64 only): characteristic-wise.
+template <int SCHEME, class T, int D, bool DBG, bool CH>
+__device__ __forceinline__ void face_emit(const KConst* K, const unsigned long long* abits, const KeepRows<T>& keep_rows,
+                                          const double (&q)[6][5], const double (&p)[6], const double (&ud)[6],
+                                          T* __restrict__ Fh, unsigned* __restrict__ dbg, long long nf, long long o)
 {
     constexpr bool F64 = std::is_same<T, double>::value;
-    constexpr int TX = FaceTile<D>::TX, TA = FaceTile<D>::TA;
-    const Grid& G = K->G;
-    __shared__ double tq[5][TA][TX];
-    __shared__ double tp[TA][TX], tu[TA][TX];
-    __shared__ __attribute__((aligned(16))) KeepRows<T> keep_rows;
-    if (SCHEME != WENO5JS) init_keep_rows<T>(keep_rows, threadIdx.x);
-    const int x0 = blockIdx.x * BX - (D == 0 ? 3 : 0);
-    for (int c = threadIdx.x; c < TA * TX; c += BX * BY) {
-        const int ca = c / TX, cx = c - ca * TX;
-        const int ci = x0 + cx;
-        const int cj = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * BY + ca - (D == 1 ? 3 : 0);
-        const int ck = D == 2 ? (int)blockIdx.z * BY + ca - 3 : (int)blockIdx.z;
-        double qc[5];
-        cell_state(K, Q, step, ci, cj, ck, qc);   // (ghosts resolved by the boundary rules)
-        const double ir = rcp_nr(qc[0]);
-        const double u = qc[1] * ir, v = qc[2] * ir, w = qc[3] * ir;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) tq[m][ca][cx] = qc[m];
-        tp[ca][cx] = K->P.gm1 * (qc[4] - 0.5 * fma(qc[1], u, fma(qc[2], v, qc[3] * w)));
-        tu[ca][cx] = D == 0 ? u : (D == 1 ? v : w);
-    }
-    __syncthreads();
-    const int fx = threadIdx.x & (BX - 1), fa = threadIdx.x / BX;
-    const int xi = blockIdx.x * BX + fx;
-    const int yi = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * BY + fa;
-    const int zi = D == 2 ? (int)blockIdx.z * BY + fa : (int)blockIdx.z;
-    if (xi >= G.n[0] + (D == 0) || yi >= G.n[1] + (D == 1) || zi >= G.n[2] + (D == 2)) return;
-    const int f = D == 0 ? xi : (D == 1 ? yi : zi);
     const double alpha = __longlong_as_double((long long)abits[D]);
     Recon R;
     R.eps = SCHEME == WENO5JS ? K->P.weno_eps : K->P.teno_eps;
@@ -301,19 +282,7 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
         R.rows = nullptr;
         R32.rows = keep_rows;
     }
-    // the six cells i-2..i+3 of the face (i below it along D) from the tile
-    double q[6][5], ud[6], p[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        const int cx = D == 0 ? fx + s : fx, ca = D == 0 ? fa : fa + s;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) q[s][m] = tq[m][ca][cx];
-        p[s] = tp[ca][cx];
-        ud[s] = tu[ca][cx];
-    }
     const double* Finf = D == 0 ? K->Fx_inf : (D == 1 ? K->Fy_inf : K->Fz_inf);
-    const long long nf = faces_of<D>(G);
-    const long long o = face_index<D>(G, f, D == 0 ? 0 : xi, D == 1 ? 0 : yi, D == 2 ? 0 : zi);
     if constexpr (CH) {
         static_assert(F64 && !DBG, "characteristic-wise faces are FP64");
         double Fs[6][5];
@@ -360,6 +329,81 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
         }
     }
     if constexpr (DBG) dbg[o] = word;
+}
+
+// Face fluxes along D: threads cover the faces f = 0..n_D along D (x index for D = 0, y index
+// for D = 1, z index for D = 2) and the cells of the two other directions; along x only the
+// faces below 64 * ceil(n_x / 64), the last face of a grid whose n_x is a multiple of 64
+// being left to k_xedge3d (a block column for one face would idle 63 of its 64 lanes).
+// DBG (FP64 TENO5 only) also writes each face's keep patterns to dbg, in the face layout.
+// CH (FP64 only): characteristic-wise reconstruction.
+template <int SCHEME, class T, int D, bool DBG = false, bool CH = false>
+__global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ K, const double* __restrict__ Q,
+                                                     long long step, const unsigned long long* __restrict__ abits,
+                                                     T* __restrict__ Fh, unsigned* __restrict__ dbg)
+{
+    constexpr int TX = FaceTile<D>::TX, TA = FaceTile<D>::TA;
+    const Grid& G = K->G;
+    __shared__ double tq[5][TA][TX];
+    __shared__ double tp[TA][TX], tu[TA][TX];
+    __shared__ __attribute__((aligned(16))) KeepRows<T> keep_rows;
+    if (SCHEME != WENO5JS) init_keep_rows<T>(keep_rows, threadIdx.x);
+    const int x0 = blockIdx.x * BX - (D == 0 ? 3 : 0);
+    for (int c = threadIdx.x; c < TA * TX; c += BX * BY) {
+        const int ca = c / TX, cx = c - ca * TX;
+        const int ci = x0 + cx;
+        const int cj = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * BY + ca - (D == 1 ? 3 : 0);
+        const int ck = D == 2 ? (int)blockIdx.z * BY + ca - 3 : (int)blockIdx.z;
+        double qc[5];
+        cell_state(K, Q, step, ci, cj, ck, qc);   // (ghosts resolved by the boundary rules)
+#pragma unroll
+        for (int m = 0; m < 5; ++m) tq[m][ca][cx] = qc[m];
+        cell_prims<D>(K, qc, tp[ca][cx], tu[ca][cx]);
+    }
+    __syncthreads();
+    const int fx = threadIdx.x & (BX - 1), fa = threadIdx.x / BX;
+    const int xi = blockIdx.x * BX + fx;
+    const int yi = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * BY + fa;
+    const int zi = D == 2 ? (int)blockIdx.z * BY + fa : (int)blockIdx.z;
+    if (xi >= G.n[0] + (D == 0) || yi >= G.n[1] + (D == 1) || zi >= G.n[2] + (D == 2)) return;
+    const int f = D == 0 ? xi : (D == 1 ? yi : zi);
+    // the six cells i-2..i+3 of the face (i below it along D) from the tile
+    double q[6][5], ud[6], p[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const int cx = D == 0 ? fx + s : fx, ca = D == 0 ? fa : fa + s;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) q[s][m] = tq[m][ca][cx];
+        p[s] = tp[ca][cx];
+        ud[s] = tu[ca][cx];
+    }
+    const long long o = face_index<D>(G, f, D == 0 ? 0 : xi, D == 1 ? 0 : yi, D == 2 ? 0 : zi);
+    face_emit<SCHEME, T, D, DBG, CH>(K, abits, keep_rows, q, p, ud, Fh, dbg, faces_of<D>(G), o);
+}
+
+// The x faces f = n_x of a grid whose n_x is a multiple of 64: one thread per (j, k), its six
+// cells n_x-3 .. n_x+2 loaded directly (the last three are ghosts), the same primitives and
+// face arithmetic as k_faces3d.
+template <int SCHEME, class T, bool DBG = false, bool CH = false>
+__global__ __launch_bounds__(BX * BY) void k_xedge3d(const KConst* __restrict__ K, const double* __restrict__ Q,
+                                                     long long step, const unsigned long long* __restrict__ abits,
+                                                     T* __restrict__ Fh, unsigned* __restrict__ dbg)
+{
+    const Grid& G = K->G;
+    __shared__ __attribute__((aligned(16))) KeepRows<T> keep_rows;
+    if (SCHEME != WENO5JS) init_keep_rows<T>(keep_rows, threadIdx.x);
+    __syncthreads();
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)G.n[1] * G.n[2]) return;
+    const int j = (int)(t % G.n[1]), k = (int)(t / G.n[1]);
+    const int f = G.n[0];
+    double q[6][5], ud[6], p[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        cell_state(K, Q, step, f - 3 + s, j, k, q[s]);
+        cell_prims<0>(K, q[s], p[s], ud[s]);
+    }
+    face_emit<SCHEME, T, 0, DBG, CH>(K, abits, keep_rows, q, p, ud, Fh, dbg, faces_of<0>(G), face_index<0>(G, f, 0, j, k));
 }
 
 template <class T>
@@ -529,12 +573,17 @@ static void launch_faces(const KConst* K, const Grid& G, const StageArgs& A, T* 
     T* Fx = F;
     T* Fy = Fx + 5 * faces_of<0>(G);
     T* Fz = Fy + 5 * faces_of<1>(G);
-    const dim3 gx((G.n[0] + 1 + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
+    const dim3 gx((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
     const dim3 gy((G.n[0] + BX - 1) / BX, (G.n[1] + 1 + BY - 1) / BY, G.n[2]);
     const dim3 gz((G.n[0] + BX - 1) / BX, G.n[1], (G.n[2] + 1 + BY - 1) / BY);   // (x by z faces)
+    // the x faces f = n_x when the x blocks end there
+    const bool xedge = G.n[0] % BX == 0;
+    const dim3 ge((unsigned)(((long long)G.n[1] * G.n[2] + BX * BY - 1) / (BX * BY)));
     if constexpr (std::is_same<T, double>::value) {
         if (ch) {
             hipLaunchKernelGGL((k_faces3d<SCHEME, T, 0, false, true>), gx, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, nullptr);
+            if (xedge)
+                hipLaunchKernelGGL((k_xedge3d<SCHEME, T, false, true>), ge, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, nullptr);
             hipLaunchKernelGGL((k_faces3d<SCHEME, T, 1, false, true>), gy, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fy, nullptr);
             hipLaunchKernelGGL((k_faces3d<SCHEME, T, 2, false, true>), gz, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fz, nullptr);
             return;
@@ -543,12 +592,15 @@ static void launch_faces(const KConst* K, const Grid& G, const StageArgs& A, T* 
     if constexpr (SCHEME == TENO5 && std::is_same<T, double>::value) {
         if (A.dbg_x) {
             hipLaunchKernelGGL((k_faces3d<SCHEME, T, 0, true>), gx, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, A.dbg_x);
+            if (xedge)
+                hipLaunchKernelGGL((k_xedge3d<SCHEME, T, true>), ge, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, A.dbg_x);
             hipLaunchKernelGGL((k_faces3d<SCHEME, T, 1, true>), gy, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fy, A.dbg_y);
             hipLaunchKernelGGL((k_faces3d<SCHEME, T, 2, true>), gz, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fz, A.dbg_z);
             return;
         }
     }
     hipLaunchKernelGGL((k_faces3d<SCHEME, T, 0>), gx, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, nullptr);
+    if (xedge) hipLaunchKernelGGL((k_xedge3d<SCHEME, T>), ge, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fx, nullptr);
     hipLaunchKernelGGL((k_faces3d<SCHEME, T, 1>), gy, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fy, nullptr);
     hipLaunchKernelGGL((k_faces3d<SCHEME, T, 2>), gz, block, 0, s, K, A.Qs, A.step, A.alpha_bits, Fz, nullptr);
 }
