@@ -47,6 +47,20 @@ def test_rhs3d_single_terms(torch_cuda, term):
     _compare_rhs(torch_cuda, case, Q0)
 
 
+@pytest.mark.parametrize("xhi", ["periodic", "extrap", "inflow", "nonreflect"])
+def test_rhs3d_last_x_face_column(torch_cuda, xhi):
+    """A grid whose n_x is a multiple of 64 takes its last x face column (x = n_x) from a
+    kernel of its own: the right-hand side against the oracle with each boundary kind on the
+    x+ side behind that column (component-wise TENO5, and characteristic-wise WENO5-JS)."""
+    case = _box3("teno5", n=(64, 10, 8))
+    lo = "periodic" if xhi == "periodic" else "extrap"
+    case = case.with_(bc=((lo, xhi), ("periodic", "periodic"), ("periodic", "periodic")),
+                      prim_inf=(1.0, 0.2, -0.1, 0.05, 1.0 / 1.4), inflow_amp=2e-5)
+    Q0 = W.perturbed_state(case, seed=35, amp=2e-2, step_amp=0.3)
+    _compare_rhs(torch_cuda, case, Q0)
+    _compare_rhs(torch_cuda, case.with_(scheme="weno5js", variables="characteristic"), Q0)
+
+
 def test_rhs3d_inflow_and_markers(torch_cuda):
     # inflow with the seeded perturbation on x-, zero-gradient elsewhere, sponge, a sphere
     case = W.config3(n=32, scheme="teno5", nmark=600, L=4.0).with_(

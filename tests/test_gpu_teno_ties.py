@@ -141,7 +141,7 @@ def check_decisions(torch, oracle_mod, case, Q0, nsteps, kinematics=None):
 def test_readout_instantiation_is_the_production_arithmetic(torch_cuda):
     torch = torch_cuda
     for case, Q0 in ((W.config2(n=160, nprobe=8, rprobe=3.0, sponge=1.0), None),
-                     (W.config3(n=40, scheme="teno5", nmark=1000), None)):
+                     (W.config3(n=64, scheme="teno5", nmark=1000), None)):   # (n_x = 64: the last x face column too)
         Q0 = W.config2_noisy_state(case) if case.dim == 2 else W.config3_state(case)
         out = []
         for dbg in (False, True):
