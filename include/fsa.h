@@ -295,6 +295,9 @@ int32_t fsa_diagnostics(fsa_ctx* ctx, const double* d_Q, double* h_totals, doubl
  * keeps sub-stencil k for every component (a component whose five values agree to 1e-12
  * counts as keeping all). */
 int32_t fsa_mlp_set(fsa_ctx* ctx, const float* h_params, int32_t nparams, double conf_threshold);
+/* As fsa_mlp_set from BF16 parameters (HOST uint16 bit patterns, the same flat layout): each is
+ * widened exactly to the FP32 master copy, so inference uses these BF16 values unchanged. */
+int32_t fsa_set_mlp(fsa_ctx* ctx, const uint16_t* h_bf16_params, int32_t nparams, double conf_threshold);
 int32_t fsa_mlp_get(fsa_ctx* ctx, float* h_params, int32_t nparams);            /* synchronising */
 /* Logits d_logits[n][3] of features d_feats[n][16] (column 15 ignored). */
 int32_t fsa_mlp_forward(fsa_ctx* ctx, const float* d_feats, int64_t n, float* d_logits);

@@ -1343,6 +1343,20 @@ int32_t fsa_mlp_set(fsa_ctx* c, const float* h_params, int32_t nparams, double c
     return FSA_OK;
 }
 
+int32_t fsa_set_mlp(fsa_ctx* c, const uint16_t* h_bf16_params, int32_t nparams, double conf_threshold)
+{
+    if (!c || !h_bf16_params) return FSA_EINVAL;
+    if (nparams != MLP_NPARAM) return fail(c, FSA_EINVAL, "the network has 1667 parameters");
+    // BF16 -> FP32 is exact (the BF16 bits are the FP32 value's upper half), and rounding
+    // that FP32 value back to BF16 returns it unchanged
+    std::vector<float> f(MLP_NPARAM);
+    for (int k = 0; k < MLP_NPARAM; ++k) {
+        const uint32_t bits = (uint32_t)h_bf16_params[k] << 16;
+        std::memcpy(&f[k], &bits, sizeof(float));
+    }
+    return fsa_mlp_set(c, f.data(), nparams, conf_threshold);
+}
+
 int32_t fsa_mlp_get(fsa_ctx* c, float* h_params, int32_t nparams)
 {
     if (!c || !h_params || nparams != MLP_NPARAM) return FSA_EINVAL;

@@ -130,6 +130,7 @@ _SIGS = {
     "fsa_get_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "fsa_set_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]),
     "fsa_mlp_set": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double]),
+    "fsa_set_mlp": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double]),
     "fsa_mlp_get": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32]),
     "fsa_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "fsa_mlp_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
@@ -626,6 +627,18 @@ class Solver:
         p = np.ascontiguousarray(params, dtype=np.float32)
         assert p.shape == (MLP_NPARAM,)
         self._check(lib().fsa_mlp_set(self.ctx, p.ctypes.data, MLP_NPARAM, conf_threshold))
+
+    def set_mlp_bf16(self, params, conf_threshold=0.8):
+        """Parameters as BF16: a torch.bfloat16 tensor or their uint16 bit patterns."""
+        t = self.torch
+        if isinstance(params, t.Tensor):
+            if params.dtype != t.bfloat16:
+                raise ValueError("a tensor of BF16 parameters must have dtype torch.bfloat16")
+            params = params.detach().cpu().contiguous().view(t.int16).numpy().view(np.uint16)
+        p = np.ascontiguousarray(params, dtype=np.uint16)
+        if p.shape != (MLP_NPARAM,):
+            raise ValueError(f"the network has {MLP_NPARAM} parameters, not {p.shape}")
+        self._check(lib().fsa_set_mlp(self.ctx, p.ctypes.data, MLP_NPARAM, conf_threshold))
 
     def mlp_get(self):
         p = np.zeros(MLP_NPARAM, dtype=np.float32)

@@ -73,6 +73,26 @@ def test_mlp_forward_matches_oracle(torch_cuda, mlp):
     assert np.abs(zg - zo).max() < 1e-2 * np.abs(zo).max()
 
 
+def test_bf16_parameters_set_exactly(torch_cuda, mlp):
+    """fsa_set_mlp takes BF16 parameters: the FP32 master copy it keeps is their exact
+    widening, and the logits equal those of fsa_mlp_set given that FP32 copy, bit for bit."""
+    torch = torch_cuda
+    theta = torch.from_numpy(_rand_theta(mlp, 3).astype(np.float32)).to(torch.bfloat16)
+    wide = theta.to(torch.float32).numpy()
+    X = torch.from_numpy(_rand_feats(500, 4)).cuda()
+    a, b = _solver(_small()), _solver(_small())
+    a.set_mlp_bf16(theta)
+    b.mlp_set(wide)
+    assert np.array_equal(a.mlp_get(), wide)
+    za, zb = a.mlp_forward(X).cpu().numpy(), b.mlp_forward(X).cpu().numpy()
+    assert np.array_equal(za, zb) and np.abs(za).max() > 0
+    bits = theta.view(torch.int16).numpy().view(np.uint16)
+    a.set_mlp_bf16(bits)                        # the same parameters as uint16 bit patterns
+    assert np.array_equal(a.mlp_get(), wide)
+    with pytest.raises(ValueError):
+        a.set_mlp_bf16(bits[:-1])
+
+
 def test_mlp_gradient_matches_oracle(torch_cuda, mlp):
     s = _solver(_small())
     theta = _rand_theta(mlp, 3)
