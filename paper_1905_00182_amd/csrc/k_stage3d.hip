@@ -238,15 +238,17 @@ __host__ __device__ __forceinline__ long long faces_of(const Grid& G)
     return (long long)(G.n[0] + (D == 0)) * (G.n[1] + (D == 1)) * (G.n[2] + (D == 2));
 }
 
-// A block's faces along D: 64 along x by 4 along a second axis (y for D = 0 and 1, z for
-// D = 2, the block then taking one y row); the cells those faces read form a tile of
-// TX x TA cells (3 more on either side along D), staged in LDS with their pressure and normal
-// velocity, so that each cell is loaded and its primitives formed once per block instead of
-// once per face that reads it (six), in the same expressions.
+// A block's 256 faces along D: FX along x by FA along a second axis (y for D = 0 and 1, z for
+// D = 2, the block then taking one y row) -- 64 x 4 for x faces, 32 x 8 for y and z faces,
+// whose tiles then stage 1.75 cells per face instead of 2.5; the cells those faces read form a
+// tile of TX x TA cells (3 more on either side along D), staged in LDS once per block instead
+// of once per face that reads them (six), in the same expressions.
 template <int D>
 struct FaceTile {
-    static constexpr int TX = BX + (D == 0 ? 6 : 0);   // cells along x
-    static constexpr int TA = D == 0 ? BY : BY + 6;    // cells along the second axis
+    static constexpr int FX = D == 0 ? BX : 32;        // faces along x
+    static constexpr int FA = BX * BY / FX;            // faces along the second axis
+    static constexpr int TX = FX + (D == 0 ? 6 : 0);   // cells along x
+    static constexpr int TA = D == 0 ? FA : FA + 6;    // cells along the second axis
 };
 
 // Pressure and velocity along D of a staged cell, in the expressions every face pass uses.
@@ -259,131 +261,180 @@ __device__ __forceinline__ void cell_prims(const KConst* K, const double* qc, do
     ud = D == 0 ? u : (D == 1 ? v : w);
 }
 
-// Face flux of one face along D from its six cells i-2..i+3 (i below it along D): state q,
-// pressure p and velocity ud; written per component to Fh[c * nf + o].  DBG (FP64 TENO5
-// only) also writes the face's keep patterns to dbg[o]; CH (FP64 only): characteristic-wise.
-template <int SCHEME, class T, int D, bool DBG, bool CH>
-__device__ __forceinline__ void face_emit(const KConst* K, const unsigned long long* abits, const KeepRows<T>& keep_rows,
-                                          const double (&q)[6][5], const double (&p)[6], const double (&ud)[6],
-                                          T* __restrict__ Fh, unsigned* __restrict__ dbg, long long nf, long long o)
+// Split fluxes f+- = (F +- alpha Q) / 2 along D of one cell, each rounded once to T (FP64: of
+// the state; the precision form: of its deviation from the far field, formed in FP64).
+template <class T, int D>
+__device__ __forceinline__ void cell_split(const KConst* K, const double* q, double p, double ud, double alpha, T* fp,
+                                           T* fm)
 {
     constexpr bool F64 = std::is_same<T, double>::value;
-    const double alpha = __longlong_as_double((long long)abits[D]);
-    Recon R;
+    const double* Finf = D == 0 ? K->Fx_inf : (D == 1 ? K->Fy_inf : K->Fz_inf);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double F;
+        if (c == 0) F = q[1 + D];
+        else if (c == 4) F = (q[4] + p) * ud;
+        else if (c - 1 == D) F = fma(q[c], ud, p);
+        else F = q[c] * ud;
+        if (F64) {
+            fp[c] = (T)(0.5 * fma(alpha, q[c], F));
+            fm[c] = (T)(0.5 * fma(-alpha, q[c], F));
+        } else {
+            const double dq = q[c] - K->P.q_inf[c], dF = F - Finf[c];
+            fp[c] = (T)(0.5 * fma(alpha, dq, dF));
+            fm[c] = (T)(0.5 * fma(-alpha, dq, dF));
+        }
+    }
+}
+
+template <int SCHEME, class T>
+__device__ __forceinline__ void recon_setup(const KConst* K, const KeepRows<T>& keep_rows, Recon& R, Recon32& R32)
+{
     R.eps = SCHEME == WENO5JS ? K->P.weno_eps : K->P.teno_eps;
     R.ct = K->P.teno_ct;
-    Recon32 R32;
     R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;
     R32.ct = (float)K->P.teno_ct;
-    if constexpr (F64) {
+    if constexpr (std::is_same<T, double>::value) {
         R.rows = keep_rows;
         R32.rows = nullptr;
     } else {
         R.rows = nullptr;
         R32.rows = keep_rows;
     }
-    const double* Finf = D == 0 ? K->Fx_inf : (D == 1 ? K->Fy_inf : K->Fz_inf);
-    if constexpr (CH) {
-        static_assert(F64 && !DBG, "characteristic-wise faces are FP64");
-        double Fs[6][5];
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            Fs[s][0] = q[s][1 + D];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) Fs[s][1 + a] = a == D ? fma(q[s][1 + a], ud[s], p[s]) : q[s][1 + a] * ud[s];
-            Fs[s][4] = (q[s][4] + p[s]) * ud[s];
-        }
-        double Fo[5];
-        char_face<SCHEME, 3, D>(q, Fs, p, K->P.gm1, alpha, R, Fo);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) Fh[c * nf + o] = Fo[c];
-        return;
+}
+
+// Face flux of component c from the split fluxes of the face's six cells i-2..i+3 (i below it
+// along D): F^ = rec+(f+ of i-2..i+2) + rec-(f- of i+3..i-1); with DBG (FP64 TENO5) also the
+// keep patterns of both sides into *word.
+template <int SCHEME, class T, bool DBG>
+__device__ __forceinline__ T face_comp(const T (&fp)[6], const T (&fm)[6], const Recon& R, const Recon32& R32, int c,
+                                       unsigned* word)
+{
+    if constexpr (DBG) {
+        *word |= (unsigned)teno_keep5(fp[0], fp[1], fp[2], fp[3], fp[4], R) << (3 * c);
+        *word |= (unsigned)teno_keep5(fm[5], fm[4], fm[3], fm[2], fm[1], R) << (16 + 3 * c);
+    } else {
+        (void)c;
+        (void)word;
     }
-    unsigned word = 0u;
-    (void)word;
-    (void)dbg;
+    return rec<SCHEME>(fp[0], fp[1], fp[2], fp[3], fp[4], R, R32) + rec<SCHEME>(fm[5], fm[4], fm[3], fm[2], fm[1], R, R32);
+}
+
+// Characteristic-wise face flux (FP64) from the face's six cells: state q, pressure p and
+// velocity ud; written per component to Fh[c * nf + o].
+template <int SCHEME, int D>
+__device__ __forceinline__ void char_face_emit(const KConst* K, double alpha, const Recon& R, const double (&q)[6][5],
+                                               const double (&p)[6], const double (&ud)[6], double* __restrict__ Fh,
+                                               long long nf, long long o)
+{
+    double Fs[6][5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        T fp[6], fm[6];
+    for (int s = 0; s < 6; ++s) {
+        Fs[s][0] = q[s][1 + D];
 #pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            double F;
-            if (c == 0) F = q[s][1 + D];
-            else if (c == 4) F = (q[s][4] + p[s]) * ud[s];
-            else if (c - 1 == D) F = fma(q[s][c], ud[s], p[s]);
-            else F = q[s][c] * ud[s];
-            if (F64) {
-                fp[s] = (T)(0.5 * fma(alpha, q[s][c], F));
-                fm[s] = (T)(0.5 * fma(-alpha, q[s][c], F));
-            } else {
-                const double dq = q[s][c] - K->P.q_inf[c], dF = F - Finf[c];
-                fp[s] = (T)(0.5 * fma(alpha, dq, dF));
-                fm[s] = (T)(0.5 * fma(-alpha, dq, dF));
-            }
-        }
-        Fh[c * nf + o] = rec<SCHEME>(fp[0], fp[1], fp[2], fp[3], fp[4], R, R32) +
-                         rec<SCHEME>(fm[5], fm[4], fm[3], fm[2], fm[1], R, R32);
-        if constexpr (DBG) {
-            word |= (unsigned)teno_keep5(fp[0], fp[1], fp[2], fp[3], fp[4], R) << (3 * c);
-            word |= (unsigned)teno_keep5(fm[5], fm[4], fm[3], fm[2], fm[1], R) << (16 + 3 * c);
-        }
+        for (int a = 0; a < 3; ++a) Fs[s][1 + a] = a == D ? fma(q[s][1 + a], ud[s], p[s]) : q[s][1 + a] * ud[s];
+        Fs[s][4] = (q[s][4] + p[s]) * ud[s];
     }
-    if constexpr (DBG) dbg[o] = word;
+    double Fo[5];
+    char_face<SCHEME, 3, D>(q, Fs, p, K->P.gm1, alpha, R, Fo);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Fh[c * nf + o] = Fo[c];
 }
 
 // Face fluxes along D: threads cover the faces f = 0..n_D along D (x index for D = 0, y index
 // for D = 1, z index for D = 2) and the cells of the two other directions; along x only the
 // faces below 64 * ceil(n_x / 64), the last face of a grid whose n_x is a multiple of 64
 // being left to k_xedge3d (a block column for one face would idle 63 of its 64 lanes).
-// DBG (FP64 TENO5 only) also writes each face's keep patterns to dbg, in the face layout.
-// CH (FP64 only): characteristic-wise reconstruction.
+// Component-wise, each staged cell's split fluxes along D are formed once into LDS (instead
+// of once per face that reads them, six); characteristic-wise its state, pressure and
+// velocity are staged.  DBG (FP64 TENO5 only) also writes each face's keep patterns to dbg,
+// in the face layout.  CH (FP64 only): characteristic-wise reconstruction.
 template <int SCHEME, class T, int D, bool DBG = false, bool CH = false>
 __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ K, const double* __restrict__ Q,
                                                      long long step, const unsigned long long* __restrict__ abits,
                                                      T* __restrict__ Fh, unsigned* __restrict__ dbg)
 {
-    constexpr int TX = FaceTile<D>::TX, TA = FaceTile<D>::TA;
+    constexpr int TX = FaceTile<D>::TX, TA = FaceTile<D>::TA, FX = FaceTile<D>::FX, FA = FaceTile<D>::FA;
     const Grid& G = K->G;
-    __shared__ double tq[5][TA][TX];
-    __shared__ double tp[TA][TX], tu[TA][TX];
     __shared__ __attribute__((aligned(16))) KeepRows<T> keep_rows;
     if (SCHEME != WENO5JS) init_keep_rows<T>(keep_rows, threadIdx.x);
-    const int x0 = blockIdx.x * BX - (D == 0 ? 3 : 0);
-    for (int c = threadIdx.x; c < TA * TX; c += BX * BY) {
-        const int ca = c / TX, cx = c - ca * TX;
-        const int ci = x0 + cx;
-        const int cj = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * BY + ca - (D == 1 ? 3 : 0);
-        const int ck = D == 2 ? (int)blockIdx.z * BY + ca - 3 : (int)blockIdx.z;
-        double qc[5];
-        cell_state(K, Q, step, ci, cj, ck, qc);   // (ghosts resolved by the boundary rules)
-#pragma unroll
-        for (int m = 0; m < 5; ++m) tq[m][ca][cx] = qc[m];
-        cell_prims<D>(K, qc, tp[ca][cx], tu[ca][cx]);
-    }
-    __syncthreads();
-    const int fx = threadIdx.x & (BX - 1), fa = threadIdx.x / BX;
-    const int xi = blockIdx.x * BX + fx;
-    const int yi = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * BY + fa;
-    const int zi = D == 2 ? (int)blockIdx.z * BY + fa : (int)blockIdx.z;
-    if (xi >= G.n[0] + (D == 0) || yi >= G.n[1] + (D == 1) || zi >= G.n[2] + (D == 2)) return;
+    const double alpha = __longlong_as_double((long long)abits[D]);
+    const int x0 = blockIdx.x * FX - (D == 0 ? 3 : 0);
+    const int fx = threadIdx.x % FX, fa = threadIdx.x / FX;
+    const int xi = blockIdx.x * FX + fx;
+    const int yi = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * FA + fa;
+    const int zi = D == 2 ? (int)blockIdx.z * FA + fa : (int)blockIdx.z;
+    const bool face_in = xi < G.n[0] + (D == 0) && yi < G.n[1] + (D == 1) && zi < G.n[2] + (D == 2);
     const int f = D == 0 ? xi : (D == 1 ? yi : zi);
-    // the six cells i-2..i+3 of the face (i below it along D) from the tile
-    double q[6][5], ud[6], p[6];
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        const int cx = D == 0 ? fx + s : fx, ca = D == 0 ? fa : fa + s;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) q[s][m] = tq[m][ca][cx];
-        p[s] = tp[ca][cx];
-        ud[s] = tu[ca][cx];
-    }
+    const long long nf = faces_of<D>(G);
     const long long o = face_index<D>(G, f, D == 0 ? 0 : xi, D == 1 ? 0 : yi, D == 2 ? 0 : zi);
-    face_emit<SCHEME, T, D, DBG, CH>(K, abits, keep_rows, q, p, ud, Fh, dbg, faces_of<D>(G), o);
+    Recon R;
+    Recon32 R32;
+    recon_setup<SCHEME, T>(K, keep_rows, R, R32);
+    if constexpr (CH) {
+        static_assert(std::is_same<T, double>::value && !DBG, "characteristic-wise faces are FP64");
+        __shared__ double tq[5][TA][TX];
+        __shared__ double tp[TA][TX], tu[TA][TX];
+        for (int c = threadIdx.x; c < TA * TX; c += BX * BY) {
+            const int ca = c / TX, cx = c - ca * TX;
+            const int cj = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * FA + ca - (D == 1 ? 3 : 0);
+            const int ck = D == 2 ? (int)blockIdx.z * FA + ca - 3 : (int)blockIdx.z;
+            double qc[5];
+            cell_state(K, Q, step, x0 + cx, cj, ck, qc);   // (ghosts resolved by the boundary rules)
+#pragma unroll
+            for (int m = 0; m < 5; ++m) tq[m][ca][cx] = qc[m];
+            cell_prims<D>(K, qc, tp[ca][cx], tu[ca][cx]);
+        }
+        __syncthreads();
+        if (!face_in) return;
+        double q[6][5], ud[6], p[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            const int cx = D == 0 ? fx + s : fx, ca = D == 0 ? fa : fa + s;
+#pragma unroll
+            for (int m = 0; m < 5; ++m) q[s][m] = tq[m][ca][cx];
+            p[s] = tp[ca][cx];
+            ud[s] = tu[ca][cx];
+        }
+        char_face_emit<SCHEME, D>(K, alpha, R, q, p, ud, Fh, nf, o);
+    } else {
+        __shared__ T sp[5][TA][TX], sm[5][TA][TX];
+        for (int c = threadIdx.x; c < TA * TX; c += BX * BY) {
+            const int ca = c / TX, cx = c - ca * TX;
+            const int cj = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * FA + ca - (D == 1 ? 3 : 0);
+            const int ck = D == 2 ? (int)blockIdx.z * FA + ca - 3 : (int)blockIdx.z;
+            double qc[5], p, ud;
+            T fpc[5], fmc[5];
+            cell_state(K, Q, step, x0 + cx, cj, ck, qc);   // (ghosts resolved by the boundary rules)
+            cell_prims<D>(K, qc, p, ud);
+            cell_split<T, D>(K, qc, p, ud, alpha, fpc, fmc);
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                sp[m][ca][cx] = fpc[m];
+                sm[m][ca][cx] = fmc[m];
+            }
+        }
+        __syncthreads();
+        if (!face_in) return;
+        unsigned word = 0u;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            T fp[6], fm[6];
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const int cx = D == 0 ? fx + s : fx, ca = D == 0 ? fa : fa + s;
+                fp[s] = sp[c][ca][cx];
+                fm[s] = sm[c][ca][cx];
+            }
+            Fh[c * nf + o] = face_comp<SCHEME, T, DBG>(fp, fm, R, R32, c, &word);
+        }
+        if constexpr (DBG) dbg[o] = word;
+    }
 }
 
 // The x faces f = n_x of a grid whose n_x is a multiple of 64: one thread per (j, k), its six
-// cells n_x-3 .. n_x+2 loaded directly (the last three are ghosts), the same primitives and
-// face arithmetic as k_faces3d.
+// cells n_x-3 .. n_x+2 loaded directly (the last three are ghosts), the same primitives,
+// split fluxes and face arithmetic as k_faces3d.
 template <int SCHEME, class T, bool DBG = false, bool CH = false>
 __global__ __launch_bounds__(BX * BY) void k_xedge3d(const KConst* __restrict__ K, const double* __restrict__ Q,
                                                      long long step, const unsigned long long* __restrict__ abits,
@@ -397,13 +448,37 @@ __global__ __launch_bounds__(BX * BY) void k_xedge3d(const KConst* __restrict__ 
     if (t >= (long long)G.n[1] * G.n[2]) return;
     const int j = (int)(t % G.n[1]), k = (int)(t / G.n[1]);
     const int f = G.n[0];
+    const double alpha = __longlong_as_double((long long)abits[0]);
+    const long long nf = faces_of<0>(G), o = face_index<0>(G, f, 0, j, k);
+    Recon R;
+    Recon32 R32;
+    recon_setup<SCHEME, T>(K, keep_rows, R, R32);
     double q[6][5], ud[6], p[6];
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
         cell_state(K, Q, step, f - 3 + s, j, k, q[s]);
         cell_prims<0>(K, q[s], p[s], ud[s]);
     }
-    face_emit<SCHEME, T, 0, DBG, CH>(K, abits, keep_rows, q, p, ud, Fh, dbg, faces_of<0>(G), face_index<0>(G, f, 0, j, k));
+    if constexpr (CH) {
+        static_assert(std::is_same<T, double>::value && !DBG, "characteristic-wise faces are FP64");
+        char_face_emit<SCHEME, 0>(K, alpha, R, q, p, ud, Fh, nf, o);
+    } else {
+        T sp[6][5], sm[6][5];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) cell_split<T, 0>(K, q[s], p[s], ud[s], alpha, sp[s], sm[s]);
+        unsigned word = 0u;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            T fp[6], fm[6];
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                fp[s] = sp[s][c];
+                fm[s] = sm[s][c];
+            }
+            Fh[c * nf + o] = face_comp<SCHEME, T, DBG>(fp, fm, R, R32, c, &word);
+        }
+        if constexpr (DBG) dbg[o] = word;
+    }
 }
 
 template <class T>
@@ -574,8 +649,9 @@ static void launch_faces(const KConst* K, const Grid& G, const StageArgs& A, T* 
     T* Fy = Fx + 5 * faces_of<0>(G);
     T* Fz = Fy + 5 * faces_of<1>(G);
     const dim3 gx((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
-    const dim3 gy((G.n[0] + BX - 1) / BX, (G.n[1] + 1 + BY - 1) / BY, G.n[2]);
-    const dim3 gz((G.n[0] + BX - 1) / BX, G.n[1], (G.n[2] + 1 + BY - 1) / BY);   // (x by z faces)
+    constexpr int FXa = FaceTile<1>::FX, FAa = FaceTile<1>::FA;   // (the same for z faces)
+    const dim3 gy((G.n[0] + FXa - 1) / FXa, (G.n[1] + 1 + FAa - 1) / FAa, G.n[2]);
+    const dim3 gz((G.n[0] + FXa - 1) / FXa, G.n[1], (G.n[2] + 1 + FAa - 1) / FAa);   // (x by z faces)
     // the x faces f = n_x when the x blocks end there
     const bool xedge = G.n[0] % BX == 0;
     const dim3 ge((unsigned)(((long long)G.n[1] * G.n[2] + BX * BY - 1) / (BX * BY)));
