@@ -391,6 +391,12 @@ def blocks(case, Q0, nsteps=200, nblocks=4):
                     "cross-block wave-speed maximum after every stage"}
 
 
+# Algorithmic work and traffic of one 3D cell-stage (the 2D count carried to three directions
+# and five components: 30 reconstructions, nine velocity derivatives, six stress components).
+ALGO_FLOPS_3D = {"teno5": 2938, "weno5js": 2398}
+ALGO_BYTES_3D = 106.7
+
+
 def three_d(steps=3):
     """Rates of the 3D path on the sphere cases (256^3 FP64 in both schemes, 384^3 precision
     form): `steps` steps after one warm-up step, inputs resident on the device."""
@@ -417,9 +423,20 @@ def three_d(steps=3):
         wall = time.perf_counter() - t0
         kms, nl = s.timing_read()
         s.close()
+        stage_ms = kms / max(nl, 1)
         out[name] = {"value": round(case.ncell * 3 * steps / wall / 1e6, 1), "unit": "Mcell-stage/s",
                      "ms_per_step": round(wall / steps * 1e3, 3),
-                     "stage_kernels_ms_per_stage": round(kms / max(nl, 1), 3)}
+                     "stage_kernels_ms_per_stage": round(stage_ms, 3)}
+        if case.variables == "component" and stage_ms > 0:
+            # the whole 3D stage (stress, face and stage passes) against the FP64 (C3) or FP32
+            # (C4, its reconstruction's type) vector peak, at the method's algorithmic work
+            flops = ALGO_FLOPS_3D[case.scheme]
+            achieved = flops * case.ncell / (stage_ms * 1e-3) / 1e12
+            peak = 78.6 if case.precision == "fp64" else 157.3
+            out[name]["roofline"] = {
+                "bound": "alu", "kernels": "the stage's passes", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "algo_flops_per_cell_stage": flops,
+                "hbm_frac_algorithmic": round(ALGO_BYTES_3D * case.ncell / (stage_ms * 1e-3) / 8e12, 4)}
         del Q
         torch.cuda.empty_cache()
         progress(f"3D {name}: {out[name]['value']} Mcell-stage/s")
