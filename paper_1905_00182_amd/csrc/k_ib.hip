@@ -9,6 +9,8 @@
 // index (a deterministic gather).  The weights depend only on the marker positions and are
 // computed once per position update, by one launch that also puts the staged positions,
 // velocities and window lists in place.
+#include <algorithm>
+
 #include "fsa_impl.hpp"
 
 namespace fsa {
@@ -104,6 +106,40 @@ __global__ __launch_bounds__(FINAL_THREADS) void k_alpha_final(const unsigned lo
                                                                long long n, unsigned long long* __restrict__ bits)
 {
     alpha_final_block<FINAL_THREADS>(part, n, bits);
+}
+
+// Many partials (a 3D stage leaves one per block): blocks reduce contiguous chunks and merge
+// their maxima into the slot with an atomic maximum on the bit patterns (non-negative
+// doubles order as their bits; the slot is cleared by k_bits_clear first).
+__global__ __launch_bounds__(64) void k_bits_clear(unsigned long long* __restrict__ bits)
+{
+    if (threadIdx.x < 3) bits[threadIdx.x] = 0ull;
+}
+
+constexpr int CHUNK_THREADS = 256;
+__global__ __launch_bounds__(CHUNK_THREADS) void k_alpha_chunks(const unsigned long long* __restrict__ part,
+                                                                long long n, long long chunk,
+                                                                unsigned long long* __restrict__ bits)
+{
+    const long long a = (long long)blockIdx.x * chunk, b = min(n, a + chunk);
+    __shared__ unsigned long long red[CHUNK_THREADS / 64][3];
+    unsigned long long m[3] = {0ull, 0ull, 0ull};
+    for (long long k = a + threadIdx.x; k < b; k += CHUNK_THREADS) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) m[d] = max_bits(m[d], part[k * 3 + d]);
+    }
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const unsigned long long w = wave_max_bits(m[d]);
+        if (lane == 0) red[wid][d] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long v = 0ull;
+        for (int w = 0; w < CHUNK_THREADS / 64; ++w) v = max_bits(v, red[w][threadIdx.x]);
+        atomicMax(&bits[threadIdx.x], v);
+    }
 }
 
 // Marker support: first cell and four weights per direction.
@@ -508,7 +544,14 @@ int launch_alpha_rows(const Grid& G, const Phys& P, const double* Q, int row0, i
 
 int launch_alpha_final(const unsigned long long* part, long long n, unsigned long long* bits, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_alpha_final, dim3(1), dim3(FINAL_THREADS), 0, s, part, n, bits);
+    if (n <= 16384) {
+        hipLaunchKernelGGL(k_alpha_final, dim3(1), dim3(FINAL_THREADS), 0, s, part, n, bits);
+    } else {
+        // ~2048 partials per block (one CU alone reads them at a fraction of the chip's rate)
+        const long long nb = std::min<long long>(1024, (n + 2047) / 2048), chunk = (n + nb - 1) / nb;
+        hipLaunchKernelGGL(k_bits_clear, dim3(1), dim3(64), 0, s, bits);
+        hipLaunchKernelGGL(k_alpha_chunks, dim3((unsigned)nb), dim3(CHUNK_THREADS), 0, s, part, n, chunk, bits);
+    }
     return (int)hipGetLastError();
 }
 
