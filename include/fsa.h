@@ -385,7 +385,8 @@ int32_t fsa_mb_set_markers(fsa_mb* mb, int32_t n, const double* X, const double*
  * steps that follow, as fsa_set_marker_kinematics.  A block whose markers stay the same takes
  * the kinematics; one whose set changes is given its new markers with their penalty integrals
  * (read back from the blocks that held them: synchronising then).  FSA_ESTATE: the markers
- * are not EXTERNAL. */
+ * are not EXTERNAL; FSA_EINVAL: a support leaves the grid (nothing changed).  After another
+ * error the blocks' markers are undefined until fsa_mb_set_markers. */
 int32_t fsa_mb_set_marker_kinematics(fsa_mb* mb, const double* X, const double* U);
 /* The whole domain's state (DEVICE, [nq][cells] as fsa_rk3_step) into the blocks, halo
  * layers included; a fresh start: time, step and the penalty integral zero. */
