@@ -443,6 +443,69 @@ def three_d(steps=3):
     return out
 
 
+C3_RECORDS = {sch: os.path.join(ROOT, "tests", "golden", f"c3_oracle_run_{sch}.npz") for sch in ("teno5", "weno5js")}
+
+
+def sphere_acoustics(nsteps=None):
+    """The sphere cases' acoustic pressure at full size, at the 64 probes on the radius-4 sphere
+    every 5 steps over the configured 500 steps: C4 (384^3) in the precision form against the
+    same run in FP64, and C3 (256^3, TENO5 and WENO5-JS) in both forms against the CPU
+    oracle's records of those runs (tests/golden/c3_oracle_run_<scheme>.npz, when present)."""
+    import numpy as np
+    import torch
+
+    from paper_1905_00182_amd import fsa
+    from paper_1905_00182_amd import workloads as W
+
+    def run(case, steps):
+        s = fsa.Solver(case)
+        Q = torch.from_numpy(W.config3_state(case)).cuda()
+        dp = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps // 5):
+            s.rk3_steps(Q, case.dt, 5) if k == 0 else s.rk3_steps_resume(Q, case.dt, 5)
+            dp.append(s.probe_dp(Q))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s.close()
+        del Q
+        torch.cuda.empty_cache()
+        return torch.stack(dp).cpu().numpy(), wall
+
+    def err(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    out = {}
+    c4 = W.config4(n=384)
+    steps = nsteps or c4.steps
+    dp64, w64 = run(c4.with_(precision="fp64"), steps)
+    dp32, w32 = run(c4, steps)
+    out["c4_384"] = {"steps": steps, "probes": int(dp64.shape[1]), "probe_every": 5,
+                     "max_probe_dp_rel_p_inf": float(np.abs(dp64).max() / c4.prim_inf[4]),
+                     "fp64_ms_per_step": round(w64 / steps * 1e3, 3),
+                     "mixed32_ms_per_step": round(w32 / steps * 1e3, 3),
+                     "acoustic_err_mixed32_vs_fp64": err(dp32, dp64)}
+    progress(f"C4 384^3 acoustics: precision form vs FP64 {out['c4_384']['acoustic_err_mixed32_vs_fp64']:.2e}")
+    for sch, path in C3_RECORDS.items():
+        if not os.path.exists(path):
+            continue
+        rec = np.load(path)
+        c3 = W.config3(n=256, scheme=sch)
+        k = min(int(rec["steps"]), nsteps or c3.steps) // int(rec["every"])
+        d64, _ = run(c3, k * 5)
+        d32, _ = run(c3.with_(precision="mixed32"), k * 5)
+        o = rec["dp"][:k]
+        out[f"c3_256_{sch}"] = {"steps": k * 5, "max_probe_dp_rel_p_inf": float(np.abs(o).max() / c3.prim_inf[4]),
+                                "acoustic_err_fp64_vs_oracle": err(d64, o),
+                                "acoustic_err_mixed32_vs_oracle": err(d32, o),
+                                "acoustic_err_mixed32_vs_fp64": err(d32, d64)}
+        progress(f"C3 256^3 {sch} acoustics vs the oracle's record: FP64 "
+                 f"{out[f'c3_256_{sch}']['acoustic_err_fp64_vs_oracle']:.2e}, precision form "
+                 f"{out[f'c3_256_{sch}']['acoustic_err_mixed32_vs_oracle']:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -462,6 +525,9 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy three times (counter calibration)")
     ap.add_argument("--only-3d", action="store_true",
                     help="only the 3D sphere-case rates, --steps steps each (for profiling the 3D kernels)")
+    ap.add_argument("--only-sphere-acoustics", action="store_true",
+                    help="only the sphere cases' full-size acoustic errors (C4 precision form vs FP64, C3 vs the "
+                         "oracle's records)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the solver has no "
@@ -484,6 +550,9 @@ def main():
         return
     if args.only_3d:
         print(json.dumps({"three_d": three_d(args.steps)}), flush=True)
+        return
+    if args.only_sphere_acoustics:
+        print(json.dumps({"sphere_acoustics": sphere_acoustics()}), flush=True)
         return
     case = W.config2()
     if args.scheme != case.scheme:
@@ -557,6 +626,7 @@ def main():
     if not args.no_variants:
         out["variants"] = variants(case, Q0, args.variant_steps, plate_steps=args.plate_steps)
         out["variants"]["three_d"] = three_d()
+        out["variants"]["sphere_acoustics"] = sphere_acoustics()
         out["variants"]["c2_blocks"] = blocks(case, Q0)
         progress("blocks done")
     if not args.no_cpu and args.cpu_steps > 0:
