@@ -5,8 +5,10 @@ by c3_oracle_run.py with the oracle alone): the configured 500 SSP-RK3 steps fro
 WENO5-JS (c3_oracle_run_weno5js.npz): continuous weights leave the run determined to
 rounding, so it is held to the parity tests' bounds -- R20's 1e-12 (relative L2 per
 component, scaled by its natural size) and the element-wise bound on 8192 sampled cells after
-steps 100, 250 and 500; the probe pressure to 1e-12 of p_inf; the force and the norms of
-Q - Q0 to 1e-10 relative.
+steps 100, 250 and 500; the probe pressure to 1e-12 of p_inf; the total force on the sphere
+to 1e-12 of its natural size, p_inf times the sphere's cross-section (the net force here is a
+small residual of the markers' forces, which follow the 1e-6 acoustic velocity, so rounding
+of the O(1) state moves it by ~1e-10 of itself); the norms of Q - Q0 to 1e-10 relative.
 
 TENO5 (c3_oracle_run_teno5.npz): the sharp cut-off makes the run indeterminate beyond
 rounding where chi_k meets C_T within rounding (the same reading as the 2048^2 record's), so
@@ -70,7 +72,9 @@ def test_sphere_full_size_run_to_rounding():
          f"{_rel(force, rec['force']):.2e}; |Q - Q0| norms rel {_rel(np.array(dnorms), rec['dnorms']):.2e}")
     assert np.abs(rec["dp"]).max() > 1e-6 * p_inf          # the pulse has reached the probes
     assert d <= 1e-12 * p_inf
-    assert _rel(force, rec["force"]) <= 1e-10
+    f_nat = p_inf * np.pi * 0.5**2          # p_inf on the cross-section of the sphere (R = 0.5)
+    _say(f"  force: max|dF| {np.abs(force - rec['force']).max():.2e} of natural size {f_nat:.2e}")
+    assert np.abs(force - rec["force"]).max() <= 1e-12 * f_nat
     assert _rel(np.array(dnorms), rec["dnorms"]) <= 1e-10
     assert _rel(np.array(norms), rec["norms"]) <= 1e-12
     Q0s = Q0.reshape(case.nq, -1)[:, rec["cells"]]
