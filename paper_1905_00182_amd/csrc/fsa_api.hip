@@ -1048,6 +1048,7 @@ int32_t fsa_init(const fsa_desc* desc, void* d_workspace, size_t ws_bytes, void*
         hk.G = c->G;
         hk.P = c->P;
         hk.inv12h = 1.0 / (12.0 * c->G.h);
+        hk.teno_tall = teno_all_kept_bound(c->P.teno_ct);
         far_field_fluxes(c, hk);
         if (hipMemcpyAsync(c->dK, &hk, sizeof hk, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
             hipMemsetAsync(c->abits, 0, 12 * sizeof(unsigned long long), c->stream) != hipSuccess ||

@@ -191,7 +191,19 @@ struct Recon {
     double eps;                  // WENO epsilon or TENO epsilon
     double ct;                   // TENO cut-off
     const double (*rows)[8];     // TENO5: keep-pattern table (LDS)
+    double tall;                 // TENO5 all-kept certificate bound (recon5w only)
 };
+
+// TENO5 keeps every sub-stencil whenever tau5 <= T (beta_min + eps) with
+// T = (3 C_T)^(-1/6) (1 - 1e-2) - 1: then each x_k = 1 + tau5 / (beta_k + eps) lies in
+// [1, 1 + T], so gamma_k = x_k^6 >= 1 while C_T (gamma_0 + gamma_1 + gamma_2) <= 3 C_T (1 + T)^6
+// < 0.95, below every gamma_k; the 1% margin covers the rounding of both evaluations many
+// times over.  (The FP32 form's normalised test, x_k = (1 + a_k) / (1 + a_max) >= 1 / (1 + T),
+// is certified by the same bound.)  Negative for C_T >= 1/3: the certificate never holds.
+__host__ __device__ inline double teno_all_kept_bound(double ct)
+{
+    return ct > 0.0 ? pow(3.0 * ct, -1.0 / 6.0) * (1.0 - 1e-2) - 1.0 : -1.0;
+}
 
 // Jiang-Shu smoothness indicators of the three sub-stencils (FP64).
 __device__ __forceinline__ void js_beta(double a, double b, double c, double d, double e, double& b0, double& b1,
@@ -230,6 +242,28 @@ __device__ __forceinline__ int teno_keep5(double a, double b, double c, double d
 }
 
 template <int SCHEME>
+__device__ __forceinline__ double recon5(double a, double b, double c, double d, double e, const Recon& R);
+
+// recon5 with a wave-wide shortcut for TENO5: when every active lane of the wave holds the
+// all-kept certificate (teno_all_kept_bound), the face value takes the all-kept row of the
+// table without the weights -- the decision the full test takes for these values, so the same
+// value bit for bit.  Call with the whole wave converged at the call (a wave-uniform branch).
+template <int SCHEME>
+__device__ __forceinline__ double recon5w(double a, double b, double c, double d, double e, const Recon& R)
+{
+    if constexpr (SCHEME == TENO5) {
+        double b0, b1, b2;
+        js_beta(a, b, c, d, e, b0, b1, b2);
+        const double bmin = fmin(b0, fmin(b1, b2));
+        const bool cert = fabs(b0 - b2) <= R.tall * (bmin + R.eps);
+        if (__ballot(!cert) == 0ull) return keep_sum(R.rows[7], a, b, c, d, e);
+        return keep_sum(R.rows[teno_keep_beta(b0, b1, b2, R)], a, b, c, d, e);
+    } else {
+        return recon5<SCHEME>(a, b, c, d, e, R);
+    }
+}
+
+template <int SCHEME>
 __device__ __forceinline__ double recon5(double a, double b, double c, double d, double e, const Recon& R)
 {
     double b0, b1, b2;
@@ -257,6 +291,7 @@ struct Recon32 {
     float eps;
     float ct;
     const float (*rows)[8];   // TENO5 / learned: keep-pattern table (LDS)
+    float tall;               // TENO5 all-kept certificate bound (recon5fw only)
 };
 
 template <int SCHEME>
@@ -291,6 +326,23 @@ __device__ __forceinline__ float recon5f(float a, float b, float c, float d, flo
         const int keep = (g0 < lim ? 0 : 1) | (g1 < lim ? 0 : 2) | (g2 < lim ? 0 : 4);
         return keep_sum(R.rows[keep], a, b, c, d, e);
     }
+}
+
+// recon5f with the wave-wide all-kept shortcut of recon5w (TENO5).
+template <int SCHEME>
+__device__ __forceinline__ float recon5fw(float a, float b, float c, float d, float e, const Recon32& R)
+{
+    if constexpr (SCHEME == TENO5) {
+        const float s0 = fmaf(-2.0f, b, a) + c, t0 = fmaf(-4.0f, b, a) + 3.0f * c;
+        const float s1 = fmaf(-2.0f, c, b) + d, t1 = b - d;
+        const float s2 = fmaf(-2.0f, d, c) + e, t2 = fmaf(-4.0f, d, 3.0f * c) + e;
+        const float b0 = fmaf(13.0f / 12.0f * s0, s0, 0.25f * t0 * t0);
+        const float b1 = fmaf(13.0f / 12.0f * s1, s1, 0.25f * t1 * t1);
+        const float b2 = fmaf(13.0f / 12.0f * s2, s2, 0.25f * t2 * t2);
+        const bool cert = fabsf(b0 - b2) <= R.tall * (fminf(b0, fminf(b1, b2)) + R.eps);
+        if (__ballot(!cert) == 0ull) return keep_sum(R.rows[7], a, b, c, d, e);
+    }
+    return recon5f<SCHEME>(a, b, c, d, e, R);
 }
 
 // FP32 reconstruction with the sub-stencils given by keep bits (bit k = sub-stencil k, 1..7):
@@ -349,6 +401,7 @@ struct KConst {
     double sig[3];      // 1e-8 times the natural scales of rho, velocity and p (rho_inf, c_inf,
                         // rho_inf c_inf^2): significance threshold and feature floor of the
                         // learned selector
+    double teno_tall;   // TENO5 all-kept certificate bound (teno_all_kept_bound)
 
     __device__ __forceinline__ double eta_dir(int d, int i) const
     {

@@ -211,15 +211,16 @@ __global__ __launch_bounds__(BX * BY) void k_stress3d(const KConst* __restrict__
 // ---------------------------------------------------------------------------------------
 // Stage pass
 // ---------------------------------------------------------------------------------------
+// (the wave-wide all-kept shortcut: callers are converged waves)
 template <int SCHEME>
 __device__ __forceinline__ double rec(double a, double b, double c, double d, double e, const Recon& R, const Recon32&)
 {
-    return recon5<SCHEME>(a, b, c, d, e, R);
+    return recon5w<SCHEME>(a, b, c, d, e, R);
 }
 template <int SCHEME>
 __device__ __forceinline__ float rec(float a, float b, float c, float d, float e, const Recon&, const Recon32& R)
 {
-    return recon5f<SCHEME>(a, b, c, d, e, R);
+    return recon5fw<SCHEME>(a, b, c, d, e, R);
 }
 
 // Face index of face f (between cells f-1 and f along D) of the line through (i, j, k):
@@ -292,8 +293,10 @@ __device__ __forceinline__ void recon_setup(const KConst* K, const KeepRows<T>& 
 {
     R.eps = SCHEME == WENO5JS ? K->P.weno_eps : K->P.teno_eps;
     R.ct = K->P.teno_ct;
+    R.tall = K->teno_tall;
     R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;
     R32.ct = (float)K->P.teno_ct;
+    R32.tall = (float)K->teno_tall;
     if constexpr (std::is_same<T, double>::value) {
         R.rows = keep_rows;
         R32.rows = nullptr;
