@@ -191,7 +191,6 @@ struct Recon {
     double eps;                  // WENO epsilon or TENO epsilon
     double ct;                   // TENO cut-off
     const double (*rows)[8];     // TENO5: keep-pattern table (LDS)
-    double tall;                 // TENO5 all-kept certificate bound (recon5w only)
 };
 
 // TENO5 keeps every sub-stencil whenever tau5 <= T (beta_min + eps) with
@@ -245,17 +244,18 @@ template <int SCHEME>
 __device__ __forceinline__ double recon5(double a, double b, double c, double d, double e, const Recon& R);
 
 // recon5 with a wave-wide shortcut for TENO5: when every active lane of the wave holds the
-// all-kept certificate (teno_all_kept_bound), the face value takes the all-kept row of the
+// all-kept certificate (teno_all_kept_bound(C_T) = tall), the face value takes the all-kept row of the
 // table without the weights -- the decision the full test takes for these values, so the same
 // value bit for bit.  Call with the whole wave converged at the call (a wave-uniform branch).
 template <int SCHEME>
-__device__ __forceinline__ double recon5w(double a, double b, double c, double d, double e, const Recon& R)
+__device__ __forceinline__ double recon5w(double a, double b, double c, double d, double e, const Recon& R,
+                                          double tall)
 {
     if constexpr (SCHEME == TENO5) {
         double b0, b1, b2;
         js_beta(a, b, c, d, e, b0, b1, b2);
         const double bmin = fmin(b0, fmin(b1, b2));
-        const bool cert = fabs(b0 - b2) <= R.tall * (bmin + R.eps);
+        const bool cert = fabs(b0 - b2) <= tall * (bmin + R.eps);
         if (__ballot(!cert) == 0ull) return keep_sum(R.rows[7], a, b, c, d, e);
         return keep_sum(R.rows[teno_keep_beta(b0, b1, b2, R)], a, b, c, d, e);
     } else {
@@ -291,7 +291,6 @@ struct Recon32 {
     float eps;
     float ct;
     const float (*rows)[8];   // TENO5 / learned: keep-pattern table (LDS)
-    float tall;               // TENO5 all-kept certificate bound (recon5fw only)
 };
 
 template <int SCHEME>
@@ -330,7 +329,7 @@ __device__ __forceinline__ float recon5f(float a, float b, float c, float d, flo
 
 // recon5f with the wave-wide all-kept shortcut of recon5w (TENO5).
 template <int SCHEME>
-__device__ __forceinline__ float recon5fw(float a, float b, float c, float d, float e, const Recon32& R)
+__device__ __forceinline__ float recon5fw(float a, float b, float c, float d, float e, const Recon32& R, float tall)
 {
     if constexpr (SCHEME == TENO5) {
         const float s0 = fmaf(-2.0f, b, a) + c, t0 = fmaf(-4.0f, b, a) + 3.0f * c;
@@ -339,7 +338,7 @@ __device__ __forceinline__ float recon5fw(float a, float b, float c, float d, fl
         const float b0 = fmaf(13.0f / 12.0f * s0, s0, 0.25f * t0 * t0);
         const float b1 = fmaf(13.0f / 12.0f * s1, s1, 0.25f * t1 * t1);
         const float b2 = fmaf(13.0f / 12.0f * s2, s2, 0.25f * t2 * t2);
-        const bool cert = fabsf(b0 - b2) <= R.tall * (fminf(b0, fminf(b1, b2)) + R.eps);
+        const bool cert = fabsf(b0 - b2) <= tall * (fminf(b0, fminf(b1, b2)) + R.eps);
         if (__ballot(!cert) == 0ull) return keep_sum(R.rows[7], a, b, c, d, e);
     }
     return recon5f<SCHEME>(a, b, c, d, e, R);

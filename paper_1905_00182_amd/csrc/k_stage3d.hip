@@ -213,14 +213,16 @@ __global__ __launch_bounds__(BX * BY) void k_stress3d(const KConst* __restrict__
 // ---------------------------------------------------------------------------------------
 // (the wave-wide all-kept shortcut: callers are converged waves)
 template <int SCHEME>
-__device__ __forceinline__ double rec(double a, double b, double c, double d, double e, const Recon& R, const Recon32&)
+__device__ __forceinline__ double rec(double a, double b, double c, double d, double e, const Recon& R, const Recon32&,
+                                      double tall)
 {
-    return recon5w<SCHEME>(a, b, c, d, e, R);
+    return recon5w<SCHEME>(a, b, c, d, e, R, tall);
 }
 template <int SCHEME>
-__device__ __forceinline__ float rec(float a, float b, float c, float d, float e, const Recon&, const Recon32& R)
+__device__ __forceinline__ float rec(float a, float b, float c, float d, float e, const Recon&, const Recon32& R,
+                                     double tall)
 {
-    return recon5fw<SCHEME>(a, b, c, d, e, R);
+    return recon5fw<SCHEME>(a, b, c, d, e, R, (float)tall);
 }
 
 // Face index of face f (between cells f-1 and f along D) of the line through (i, j, k):
@@ -293,10 +295,8 @@ __device__ __forceinline__ void recon_setup(const KConst* K, const KeepRows<T>& 
 {
     R.eps = SCHEME == WENO5JS ? K->P.weno_eps : K->P.teno_eps;
     R.ct = K->P.teno_ct;
-    R.tall = K->teno_tall;
     R32.eps = SCHEME == WENO5JS ? (float)K->P.weno_eps : 1e-30f;
     R32.ct = (float)K->P.teno_ct;
-    R32.tall = (float)K->teno_tall;
     if constexpr (std::is_same<T, double>::value) {
         R.rows = keep_rows;
         R32.rows = nullptr;
@@ -310,8 +310,8 @@ __device__ __forceinline__ void recon_setup(const KConst* K, const KeepRows<T>& 
 // along D): F^ = rec+(f+ of i-2..i+2) + rec-(f- of i+3..i-1); with DBG (FP64 TENO5) also the
 // keep patterns of both sides into *word.
 template <int SCHEME, class T, bool DBG>
-__device__ __forceinline__ T face_comp(const T (&fp)[6], const T (&fm)[6], const Recon& R, const Recon32& R32, int c,
-                                       unsigned* word)
+__device__ __forceinline__ T face_comp(const T (&fp)[6], const T (&fm)[6], const Recon& R, const Recon32& R32,
+                                       double tall, int c, unsigned* word)
 {
     if constexpr (DBG) {
         *word |= (unsigned)teno_keep5(fp[0], fp[1], fp[2], fp[3], fp[4], R) << (3 * c);
@@ -320,7 +320,8 @@ __device__ __forceinline__ T face_comp(const T (&fp)[6], const T (&fm)[6], const
         (void)c;
         (void)word;
     }
-    return rec<SCHEME>(fp[0], fp[1], fp[2], fp[3], fp[4], R, R32) + rec<SCHEME>(fm[5], fm[4], fm[3], fm[2], fm[1], R, R32);
+    return rec<SCHEME>(fp[0], fp[1], fp[2], fp[3], fp[4], R, R32, tall) +
+           rec<SCHEME>(fm[5], fm[4], fm[3], fm[2], fm[1], R, R32, tall);
 }
 
 // Characteristic-wise face flux (FP64) from the face's six cells: state q, pressure p and
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
                 fp[s] = sp[c][ca][cx];
                 fm[s] = sm[c][ca][cx];
             }
-            Fh[c * nf + o] = face_comp<SCHEME, T, DBG>(fp, fm, R, R32, c, &word);
+            Fh[c * nf + o] = face_comp<SCHEME, T, DBG>(fp, fm, R, R32, K->teno_tall, c, &word);
         }
         if constexpr (DBG) dbg[o] = word;
     }
@@ -478,7 +479,7 @@ __global__ __launch_bounds__(BX * BY) void k_xedge3d(const KConst* __restrict__ 
                 fp[s] = sp[s][c];
                 fm[s] = sm[s][c];
             }
-            Fh[c * nf + o] = face_comp<SCHEME, T, DBG>(fp, fm, R, R32, c, &word);
+            Fh[c * nf + o] = face_comp<SCHEME, T, DBG>(fp, fm, R, R32, K->teno_tall, c, &word);
         }
         if constexpr (DBG) dbg[o] = word;
     }
