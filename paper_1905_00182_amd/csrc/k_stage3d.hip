@@ -1,4 +1,4 @@
-// 3D right-hand side / SSP-RK3 stage: two cell-centric passes for gfx950.
+// 3D right-hand side / SSP-RK3 stage for gfx950: stress, face and stage passes.
 //
 //  * k_stress3d: for every cell of the grid extended by two ghost layers, the velocity
 //    gradients by the fourth-order central difference (Sec. 2, Eqs. (5)-(6)), the Stokes
@@ -6,17 +6,19 @@
 //    tau_zz, tau_xy, tau_xz, tau_yz, b_x, b_y, b_z); a z march of 64 x 4 column tiles with
 //    the velocities of each plane formed once into LDS.
 //  * k_faces3d<D>: one thread per face along direction D: the six cells i-2..i+3 give the
-//    split fluxes f+- = (F +- alpha Q)/2 of the five components and the face flux
-//    F^ = rec+(f+) + rec-(f-), stored per component [5][faces] (each face once); in the
-//    characteristic-wise instantiation (FP64) the split fluxes are projected on the
+//    split fluxes f+- = (F +- alpha Q)/2 of the five components (each block's cells' splits
+//    formed once into LDS) and the face flux F^ = rec+(f+) + rec-(f-), stored per component
+//    [5][faces] (each face once), with TENO5's wave-wide all-kept certificate (recon5w); in
+//    the characteristic-wise instantiation (FP64) the split fluxes are projected on the
 //    eigenvectors at the Roe average of the face's two cells, reconstructed field by field
-//    and recombined (char_face).
+//    and recombined (char_face).  k_xedge3d takes the x faces at x = n_x when n_x is a
+//    multiple of 64.
 //  * k_stage3d: per interior cell, the flux differences of the three face buffers, the
 //    viscous divergence from the stress buffer, the penalty-IB source from the window
 //    array, the sponge, the RK3 combination, and one wave-speed partial per block.
 //
-// Threads of a block are 64 consecutive x cells by 4 rows, so every load along x is
-// coalesced; neighbours along y and z come through the caches.  Arithmetic type T as in 2D:
+// Threads of a block are 64 (32 for y and z faces) consecutive x cells by 4 (8) rows, so
+// every load along x is coalesced; neighbours along y and z come through the caches.  Arithmetic type T as in 2D:
 // double (the method) or float (the precision form, on deviations from the far field).
 #include <type_traits>
 
