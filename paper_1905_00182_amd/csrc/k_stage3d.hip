@@ -365,10 +365,19 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
     __shared__ __attribute__((aligned(16))) KeepRows<T> keep_rows;
     if (SCHEME != WENO5JS) init_keep_rows<T>(keep_rows, threadIdx.x);
     const double alpha = __longlong_as_double((long long)abits[D]);
-    const int x0 = blockIdx.x * FX - (D == 0 ? 3 : 0);
+    // x faces: XCD bands as in the stage pass (within a plane, XCD x takes the tile rows of
+    // band x), so the rows of neighbouring tiles are read by one XCD close together
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (D == 0 && gridDim.y % 8 == 0) {
+        const int r = blockIdx.y * gridDim.x + blockIdx.x;
+        const int xcd = r % 8, slot = r / 8;
+        bx = slot % gridDim.x;
+        by = xcd * (gridDim.y / 8) + slot / gridDim.x;
+    }
+    const int x0 = bx * FX - (D == 0 ? 3 : 0);
     const int fx = threadIdx.x % FX, fa = threadIdx.x / FX;
-    const int xi = blockIdx.x * FX + fx;
-    const int yi = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * FA + fa;
+    const int xi = bx * FX + fx;
+    const int yi = D == 2 ? by : by * FA + fa;
     const int zi = D == 2 ? (int)blockIdx.z * FA + fa : (int)blockIdx.z;
     const bool face_in = xi < G.n[0] + (D == 0) && yi < G.n[1] + (D == 1) && zi < G.n[2] + (D == 2);
     const int f = D == 0 ? xi : (D == 1 ? yi : zi);
@@ -383,7 +392,7 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
         __shared__ double tp[TA][TX], tu[TA][TX];
         for (int c = threadIdx.x; c < TA * TX; c += BX * BY) {
             const int ca = c / TX, cx = c - ca * TX;
-            const int cj = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * FA + ca - (D == 1 ? 3 : 0);
+            const int cj = D == 2 ? by : by * FA + ca - (D == 1 ? 3 : 0);
             const int ck = D == 2 ? (int)blockIdx.z * FA + ca - 3 : (int)blockIdx.z;
             double qc[5];
             cell_state(K, Q, step, x0 + cx, cj, ck, qc);   // (ghosts resolved by the boundary rules)
@@ -407,7 +416,7 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
         __shared__ T sp[5][TA][TX], sm[5][TA][TX];
         for (int c = threadIdx.x; c < TA * TX; c += BX * BY) {
             const int ca = c / TX, cx = c - ca * TX;
-            const int cj = D == 2 ? (int)blockIdx.y : (int)blockIdx.y * FA + ca - (D == 1 ? 3 : 0);
+            const int cj = D == 2 ? by : by * FA + ca - (D == 1 ? 3 : 0);
             const int ck = D == 2 ? (int)blockIdx.z * FA + ca - 3 : (int)blockIdx.z;
             double qc[5], p, ud;
             T fpc[5], fmc[5];
@@ -493,8 +502,20 @@ __global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ 
                                                      const T* __restrict__ Fz)
 {
     const Grid& G = K->G;
-    const int i = blockIdx.x * BX + (threadIdx.x & (BX - 1));
-    const int j = blockIdx.y * BY + (threadIdx.x / BX);
+    // XCD bands: workgroups go round-robin to the 8 XCDs; within a plane, XCD x takes the
+    // tile rows of band x (an eighth of the plane's rows, every x tile), so that the rows a
+    // tile reads above and below it, and the planes above and below, are read by the same
+    // XCD within a short time (its L2 holds a band over five planes).  Any bijection of the
+    // blocks is correct; this one only serves locality.
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (gridDim.y % 8 == 0) {
+        const int r = blockIdx.y * gridDim.x + blockIdx.x;   // (blockIdx.z is the plane)
+        const int xcd = r % 8, slot = r / 8, bw = gridDim.y / 8;
+        bx = slot % gridDim.x;
+        by = xcd * bw + slot / gridDim.x;
+    }
+    const int i = bx * BX + (threadIdx.x & (BX - 1));
+    const int j = by * BY + (threadIdx.x / BX);
     const int k = blockIdx.z;
     const bool inside = i < G.n[0] && j < G.n[1];
     const int terms = K->P.terms;
