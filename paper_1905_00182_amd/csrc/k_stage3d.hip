@@ -35,6 +35,15 @@ __device__ __forceinline__ long long lin3(const Grid& G, int i, int j, int k)
     return ((long long)k * G.n[1] + j) * G.n[0] + i;
 }
 
+// Store into a buffer the next pass reads: FP64 values with a nontemporal store (the
+// buffers far exceed the caches; measured faster for FP64, slower for the FP32 form).
+template <class T>
+__device__ __forceinline__ void store_buffer(T v, T* p)
+{
+    if constexpr (std::is_same<T, double>::value) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // State of cell (i, j, k), ghosts resolved by the boundary conditions.
 __device__ __forceinline__ void cell_state(const KConst* K, const double* __restrict__ Q, long long step, int i, int j,
                                            int k, double* q)
@@ -198,15 +207,15 @@ __global__ __launch_bounds__(BX * BY) void k_stress3d(const KConst* __restrict__
 #pragma unroll
         for (int a = 0; a < 3; ++a) uf[a] = F64 ? w[2][a] : w[2][a] + (T)K->P.prim_inf[1 + a];
         const long long o = ((long long)(k + 2) * ey + yi) * ex + xi;
-        S[0 * ne + o] = sxx;
-        S[1 * ne + o] = syy;
-        S[2 * ne + o] = szz;
-        S[3 * ne + o] = sxy;
-        S[4 * ne + o] = sxz;
-        S[5 * ne + o] = syz;
-        S[6 * ne + o] = fma(uf[0], sxx, fma(uf[1], sxy, uf[2] * sxz));
-        S[7 * ne + o] = fma(uf[0], sxy, fma(uf[1], syy, uf[2] * syz));
-        S[8 * ne + o] = fma(uf[0], sxz, fma(uf[1], syz, uf[2] * szz));
+        store_buffer(sxx, &S[0 * ne + o]);
+        store_buffer(syy, &S[1 * ne + o]);
+        store_buffer(szz, &S[2 * ne + o]);
+        store_buffer(sxy, &S[3 * ne + o]);
+        store_buffer(sxz, &S[4 * ne + o]);
+        store_buffer(syz, &S[5 * ne + o]);
+        store_buffer(fma(uf[0], sxx, fma(uf[1], sxy, uf[2] * sxz)), &S[6 * ne + o]);
+        store_buffer(fma(uf[0], sxy, fma(uf[1], syy, uf[2] * syz)), &S[7 * ne + o]);
+        store_buffer(fma(uf[0], sxz, fma(uf[1], syz, uf[2] * szz)), &S[8 * ne + o]);
     }
 }
 
@@ -344,7 +353,7 @@ __device__ __forceinline__ void char_face_emit(const KConst* K, double alpha, co
     double Fo[5];
     char_face<SCHEME, 3, D>(q, Fs, p, K->P.gm1, alpha, R, Fo);
 #pragma unroll
-    for (int c = 0; c < 5; ++c) Fh[c * nf + o] = Fo[c];
+    for (int c = 0; c < 5; ++c) store_buffer(Fo[c], &Fh[c * nf + o]);
 }
 
 // Face fluxes along D: threads cover the faces f = 0..n_D along D (x index for D = 0, y index
@@ -441,7 +450,7 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
                 fp[s] = sp[c][ca][cx];
                 fm[s] = sm[c][ca][cx];
             }
-            Fh[c * nf + o] = face_comp<SCHEME, T, DBG>(fp, fm, R, R32, K->teno_tall, c, &word);
+            store_buffer(face_comp<SCHEME, T, DBG>(fp, fm, R, R32, K->teno_tall, c, &word), &Fh[c * nf + o]);
         }
         if constexpr (DBG) dbg[o] = word;
     }
@@ -490,7 +499,7 @@ __global__ __launch_bounds__(BX * BY) void k_xedge3d(const KConst* __restrict__ 
                 fp[s] = sp[s][c];
                 fm[s] = sm[s][c];
             }
-            Fh[c * nf + o] = face_comp<SCHEME, T, DBG>(fp, fm, R, R32, K->teno_tall, c, &word);
+            store_buffer(face_comp<SCHEME, T, DBG>(fp, fm, R, R32, K->teno_tall, c, &word), &Fh[c * nf + o]);
         }
         if constexpr (DBG) dbg[o] = word;
     }
@@ -618,7 +627,11 @@ __global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ 
             }
         }
 #pragma unroll
-        for (int c = 0; c < 5; ++c) A.out[c * G.ncell + o] = val[c];
+        for (int c = 0; c < 5; ++c) {
+            // (the FP64 method's output streams past the caches like its buffers)
+            if constexpr (std::is_same<T, double>::value) __builtin_nontemporal_store(val[c], &A.out[c * G.ncell + o]);
+            else A.out[c * G.ncell + o] = val[c];
+        }
         if (A.alpha_part && k >= A.arow0 && k < A.arow1) {
             const double ir = rcp_nr(val[0]);
             const double u = val[1] * ir, v = val[2] * ir, w = val[3] * ir;
