@@ -579,7 +579,7 @@ __global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ 
         const long long o = lin3(G, i, j, k);
         double qc[5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) qc[c] = A.Qs[c * G.ncell + o];
+        for (int c = 0; c < 5; ++c) qc[c] = __builtin_nontemporal_load(&A.Qs[c * G.ncell + o]);
         double src[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
         if ((terms & T_IB) && A.fwin) {
             const int wi = i - A.wlo[0], wj = j - A.wlo[1], wk = k - A.wlo[2];
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ 
                 val[c] = l;
             } else {
                 const double stage = fma(A.dt, l, qc[c]);
-                val[c] = (A.ca == 0.0) ? stage : fma(A.ca, A.Qn[c * G.ncell + o], A.cb * stage);
+                val[c] = (A.ca == 0.0) ? stage : fma(A.ca, __builtin_nontemporal_load(&A.Qn[c * G.ncell + o]), A.cb * stage);
             }
         }
 #pragma unroll
