@@ -91,9 +91,18 @@ __device__ __forceinline__ void velocity(const KConst* K, const double* Q, long 
 // the next front plane is loaded before the current plane's arithmetic, so the loads are in
 // flight while it runs.  Two LDS slots and one barrier per step: a slot is rewritten one step
 // after its last read, and every thread has passed that step's barrier by then.
+// The grid is one-dimensional, stress_tiles() blocks per z segment (its tiles rounded up to a
+// multiple of 8), and within a segment XCD x takes the x-th eighth of the tiles in row order:
+// a band of tile rows, so that a tile and its x and y neighbours, whose state planes overlap
+// in the halo, are read by one XCD's L2 close together.
 constexpr int SZ = 32, TXS = BX + 4, TYS = BY + 4;
 constexpr int SCELLS = TXS * TYS;                        // staged cells per plane
 constexpr int SPER = (SCELLS + BX * BY - 1) / (BX * BY);  // per thread
+
+__host__ __device__ __forceinline__ int stress_tiles(const Grid& G)
+{
+    return (((G.n[0] + 4 + BX - 1) / BX) * ((G.n[1] + 4 + BY - 1) / BY) + 7) & ~7;
+}
 
 template <class T>
 __global__ __launch_bounds__(BX * BY) void k_stress3d(const KConst* __restrict__ K, const double* __restrict__ Q,
@@ -103,10 +112,15 @@ __global__ __launch_bounds__(BX * BY) void k_stress3d(const KConst* __restrict__
     __shared__ T ring[2][3][TYS][TXS];
     const Grid& G = K->G;
     const int ex = G.n[0] + 4, ey = G.n[1] + 4, ez = G.n[2] + 4;
+    const int gx = (ex + BX - 1) / BX, per = stress_tiles(G);
+    const int seg = blockIdx.x / per, wg = blockIdx.x - seg * per;
+    const int r = (wg % 8) * (per / 8) + wg / 8;          // (workgroups go round-robin to the XCDs)
+    if (r >= gx * ((ey + BY - 1) / BY)) return;         // (padding: the whole block, before any barrier)
+    const int bx = r % gx, by = r / gx;
     const int tx = threadIdx.x & (BX - 1), ty = threadIdx.x / BX;
-    const int xi = blockIdx.x * BX + tx, yi = blockIdx.y * BY + ty;
+    const int xi = bx * BX + tx, yi = by * BY + ty;
     const bool out = xi < ex && yi < ey;
-    const int za = blockIdx.z * SZ, zb = min(za + SZ, ez) - 1;   // extended output planes
+    const int za = seg * SZ, zb = min(za + SZ, ez) - 1;   // extended output planes
     const int ka = za - 2, kb = zb - 2;                           // their cell indices
     const T inv12h = (T)K->inv12h, mu = (T)K->P.mu;
     const long long ne = (long long)ex * ey * ez;
@@ -119,8 +133,8 @@ __global__ __launch_bounds__(BX * BY) void k_stress3d(const KConst* __restrict__
     for (int m = 0; m < SPER; ++m) {
         const int c = threadIdx.x + m * BX * BY;
         const int ly = c / TXS, lx = c - ly * TXS;
-        ci[m] = blockIdx.x * BX + lx - 4;
-        cj[m] = blockIdx.y * BY + ly - 4;
+        ci[m] = bx * BX + lx - 4;
+        cj[m] = by * BY + ly - 4;
         cin[m] = c < SCELLS && ci[m] >= 0 && ci[m] < G.n[0] && cj[m] >= 0 && cj[m] < G.n[1];
     }
     auto prefetch = [&](int kf) {
@@ -729,7 +743,7 @@ int launch_stage3d(const KConst* K, const Grid& G, int scheme, int precision, in
     if (variables != 0 && precision != 0) return (int)hipErrorInvalidValue;
     const bool ch = variables != 0;
     const dim3 block(BX * BY);
-    const dim3 gs((G.n[0] + 4 + BX - 1) / BX, (G.n[1] + 4 + BY - 1) / BY, (G.n[2] + 4 + SZ - 1) / SZ);
+    const dim3 gs((unsigned)(stress_tiles(G) * ((G.n[2] + 4 + SZ - 1) / SZ)));
     const dim3 gr((G.n[0] + BX - 1) / BX, (G.n[1] + BY - 1) / BY, G.n[2]);
     if (precision == 1) {
         float* S = static_cast<float*>(stress);
