@@ -67,21 +67,6 @@ __device__ __forceinline__ T d1(T gm2, T gm1, T gp1, T gp2, T inv12h)
 // ---------------------------------------------------------------------------------------
 // Stress pass
 // ---------------------------------------------------------------------------------------
-template <class T>
-__device__ __forceinline__ void velocity(const KConst* K, const double* Q, long long step, int i, int j, int k,
-                                         T* u)
-{
-    constexpr bool F64 = std::is_same<T, double>::value;
-    double q[5];
-    cell_state(K, Q, step, i, j, k, q);
-    const double ir = rcp_nr(q[0]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double v = q[1 + a] * ir;
-        u[a] = F64 ? (T)v : (T)(v - K->P.prim_inf[1 + a]);
-    }
-}
-
 // The stress pass marches a 64 x 4 column tile of the extended grid up z over a segment of
 // SZ planes.  Each step stages the velocities of one front plane of the tile and its two-cell
 // x and y halo (every cell's velocity once, instead of once per neighbour that needs it) in
