@@ -378,15 +378,20 @@ const char* fsa_mb_last_error(const fsa_mb* mb);
 int32_t fsa_mb_block_info(const fsa_mb* mb, int32_t b, int32_t* first, int32_t* count, int32_t* halo_lo,
                           int32_t* halo_hi);
 /* Markers of the whole domain (HOST arrays as fsa_set_markers), shared out to the blocks
- * whose layers their supports reach; resets the penalty integral.  Synchronising. */
+ * whose layers their supports reach; resets the penalty integral.  Synchronising.
+ * FSA_EINVAL: a support leaves the grid (nothing changed).  After another error (a block's
+ * own rejection, e.g. more markers than its desc.max_markers) the markers are undefined:
+ * fsa_mb_rk3_steps, fsa_mb_marker_force and fsa_mb_set_marker_kinematics return FSA_ESTATE
+ * until a call of this function succeeds. */
 int32_t fsa_mb_set_markers(fsa_mb* mb, int32_t n, const double* X, const double* dV, const double* U,
                            int32_t motion, double omega);
 /* EXTERNAL markers: new positions X and velocities U (HOST [dim][n], U NULL: zero) for the
  * steps that follow, as fsa_set_marker_kinematics.  A block whose markers stay the same takes
  * the kinematics; one whose set changes is given its new markers with their penalty integrals
  * (read back from the blocks that held them: synchronising then).  FSA_ESTATE: the markers
- * are not EXTERNAL; FSA_EINVAL: a support leaves the grid (nothing changed).  After another
- * error the blocks' markers are undefined until fsa_mb_set_markers. */
+ * are not EXTERNAL, or undefined after a failed call; FSA_EINVAL: a support leaves the grid
+ * (nothing changed).  After another error the markers are undefined (as above) until
+ * fsa_mb_set_markers. */
 int32_t fsa_mb_set_marker_kinematics(fsa_mb* mb, const double* X, const double* U);
 /* The whole domain's state (DEVICE, [nq][cells] as fsa_rk3_step) into the blocks, halo
  * layers included; a fresh start: time, step and the penalty integral zero. */

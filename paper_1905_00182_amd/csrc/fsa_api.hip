@@ -1564,6 +1564,8 @@ struct fsa_mb {
     int motion = FSA_STATIC;
     double omega = 0.0;
     std::vector<double> dV;                     // every marker's quadrature weight
+    bool markers_bad = false;                   // a marker call failed part-way: the blocks' sets
+                                                // no longer match marker_of until fsa_mb_set_markers
     std::string err;
 };
 
@@ -1858,6 +1860,7 @@ int32_t fsa_mb_set_markers(fsa_mb* m, int32_t n, const double* X, const double* 
     if (motion < FSA_STATIC || motion > FSA_EXTERNAL) return mb_fail(m, FSA_EINVAL, "bad motion");
     std::vector<std::vector<int>> lists;
     if (int rc = mb_partition(m, n, X, lists)) return rc;
+    m->markers_bad = true;
     m->nm = n;
     m->motion = motion;
     m->omega = omega;
@@ -1873,12 +1876,14 @@ int32_t fsa_mb_set_markers(fsa_mb* m, int32_t n, const double* X, const double* 
         if (rc != FSA_OK) return mb_fail(m, rc, std::string("block marker set: ") + fsa_last_error(m->blk[b]));
     }
     mb_owners(m);
+    m->markers_bad = false;
     return FSA_OK;
 }
 
 int32_t fsa_mb_set_marker_kinematics(fsa_mb* m, const double* X, const double* U)
 {
     if (!m || !X) return FSA_EINVAL;
+    if (m->markers_bad) return mb_fail(m, FSA_ESTATE, "the markers are undefined after a failed call: set them again");
     if (m->nm == 0 || m->motion != FSA_EXTERNAL) return mb_fail(m, FSA_ESTATE, "markers are not EXTERNAL");
     const int n = m->nm, dim = m->whole.dim;
     std::vector<std::vector<int>> lists;
@@ -1899,6 +1904,7 @@ int32_t fsa_mb_set_marker_kinematics(fsa_mb* m, const double* X, const double* U
                 for (int d = 0; d < dim; ++d) xi[(size_t)d * n + old[i]] = xb[(size_t)d * old.size() + i];
         }
     }
+    m->markers_bad = true;
     for (int b = 0; b < m->nb; ++b) {
         std::vector<double> Xb, Ub;
         mb_slice(m, lists[b], n, X, Xb);
@@ -1922,6 +1928,7 @@ int32_t fsa_mb_set_marker_kinematics(fsa_mb* m, const double* X, const double* U
         if (rc != FSA_OK) return mb_fail(m, rc, std::string("block kinematics: ") + fsa_last_error(m->blk[b]));
     }
     mb_owners(m);
+    m->markers_bad = false;
     return FSA_OK;
 }
 
@@ -1978,6 +1985,7 @@ int32_t fsa_mb_rk3_steps(fsa_mb* m, double dt, int32_t nsteps)
     if (!m) return FSA_EINVAL;
     if (!(dt > 0.0) || !std::isfinite(dt)) return mb_fail(m, FSA_EINVAL, "dt must be positive");
     if (nsteps < 1) return mb_fail(m, FSA_EINVAL, "nsteps must be positive");
+    if (m->markers_bad) return mb_fail(m, FSA_ESTATE, "the markers are undefined after a failed call: set them again");
     static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
     static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
     std::vector<const double*> bufs(m->nb);
@@ -2023,6 +2031,7 @@ int32_t fsa_mb_rk3_steps(fsa_mb* m, double dt, int32_t nsteps)
 int32_t fsa_mb_marker_force(fsa_mb* m, double* h_F)
 {
     if (!m || !h_F) return FSA_EINVAL;
+    if (m->markers_bad) return mb_fail(m, FSA_ESTATE, "the markers are undefined after a failed call: set them again");
     const int dim = m->whole.dim;
     for (int b = 0; b < m->nb; ++b) {
         const int nbk = (int)m->marker_of[b].size();

@@ -170,3 +170,18 @@ def test_block_set_rejections(torch_cuda):
     with pytest.raises(fsa.FsaError) as e:
         m.set_markers(X + 10.0, case.markers["dV"])  # supports outside the grid
     assert e.value.code == fsa.EINVAL
+    # a block's own rejection part-way through (four copies of the markers: more than a block
+    # may hold) leaves the markers undefined: the calls that use them refuse until a set succeeds
+    dV = case.markers["dV"]
+    with pytest.raises(fsa.FsaError) as e:
+        m.set_markers(np.concatenate([X] * 4, axis=1), np.concatenate([dV] * 4), None, "external", 0.0)
+    assert e.value.code == fsa.EINVAL
+    m.scatter(torch_cuda.from_numpy(W.config2_state(case)).cuda())
+    for call in (m.marker_force, lambda: m.rk3_steps(case.dt, 1), lambda: m.set_marker_kinematics(X)):
+        with pytest.raises(fsa.FsaError) as e:
+            call()
+        assert e.value.code == fsa.ESTATE
+    m.set_markers(X, dV, None, "external", 0.0)
+    m.set_marker_kinematics(X)
+    m.rk3_steps(case.dt, 1)
+    assert np.isfinite(m.marker_force()).all()
