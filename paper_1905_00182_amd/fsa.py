@@ -635,7 +635,10 @@ class Solver:
             if params.dtype != t.bfloat16:
                 raise ValueError("a tensor of BF16 parameters must have dtype torch.bfloat16")
             params = params.detach().cpu().contiguous().view(t.int16).numpy().view(np.uint16)
-        p = np.ascontiguousarray(params, dtype=np.uint16)
+        p = np.asarray(params)
+        if p.dtype != np.uint16:      # (a cast would read values as bit patterns)
+            raise ValueError(f"BF16 parameters: a torch.bfloat16 tensor or uint16 bit patterns, not {p.dtype}")
+        p = np.ascontiguousarray(p)
         if p.shape != (MLP_NPARAM,):
             raise ValueError(f"the network has {MLP_NPARAM} parameters, not {p.shape}")
         self._check(lib().fsa_set_mlp(self.ctx, p.ctypes.data, MLP_NPARAM, conf_threshold))

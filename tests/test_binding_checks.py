@@ -74,3 +74,9 @@ def test_network_argument_checks():
         s._feats(f, meta((9,), torch.uint8))
     with pytest.raises(ValueError):
         s._feats(f, meta((10,), torch.float32))
+    # BF16 parameters: bit patterns or a bfloat16 tensor, the network's size
+    for bad in (np.zeros(fsa.MLP_NPARAM, dtype=np.float32), np.zeros(fsa.MLP_NPARAM, dtype=np.int64),
+                np.zeros(fsa.MLP_NPARAM - 1, dtype=np.uint16), torch.zeros(fsa.MLP_NPARAM, dtype=torch.float32),
+                torch.zeros(fsa.MLP_NPARAM + 1, dtype=torch.bfloat16)):
+        with pytest.raises(ValueError):
+            s.set_mlp_bf16(bad)
