@@ -375,18 +375,31 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
     const double alpha = __longlong_as_double((long long)abits[D]);
     // x faces: XCD bands as in the stage pass (within a plane, XCD x takes the tile rows of
     // band x), so the rows of neighbouring tiles are read by one XCD close together
-    int bx = blockIdx.x, by = blockIdx.y;
+    int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
     if (D == 0 && gridDim.y % 8 == 0) {
         const int r = blockIdx.y * gridDim.x + blockIdx.x;
         const int xcd = r % 8, slot = r / 8;
         bx = slot % gridDim.x;
         by = xcd * (gridDim.y / 8) + slot / gridDim.x;
     }
+    // characteristic-wise z faces: XCD x takes the y rows of band x, and within a row and x
+    // tile the z tiles one after another, so that the six planes two consecutive z tiles both
+    // stage are read by one XCD close together (the component-wise passes, which wait on
+    // memory more than they compute, run faster in launch order, neighbouring rows of the same
+    // planes together)
+    if (CH && D == 2 && gridDim.y % 8 == 0) {
+        const int r = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        const int xcd = r % 8, slot = r / 8;
+        bz = slot % gridDim.z;
+        const int t = slot / gridDim.z;
+        bx = t % gridDim.x;
+        by = xcd * (gridDim.y / 8) + t / gridDim.x;
+    }
     const int x0 = bx * FX - (D == 0 ? 3 : 0);
     const int fx = threadIdx.x % FX, fa = threadIdx.x / FX;
     const int xi = bx * FX + fx;
     const int yi = D == 2 ? by : by * FA + fa;
-    const int zi = D == 2 ? (int)blockIdx.z * FA + fa : (int)blockIdx.z;
+    const int zi = D == 2 ? bz * FA + fa : bz;
     const bool face_in = xi < G.n[0] + (D == 0) && yi < G.n[1] + (D == 1) && zi < G.n[2] + (D == 2);
     const int f = D == 0 ? xi : (D == 1 ? yi : zi);
     const long long nf = faces_of<D>(G);
@@ -401,7 +414,7 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
         for (int c = threadIdx.x; c < TA * TX; c += BX * BY) {
             const int ca = c / TX, cx = c - ca * TX;
             const int cj = D == 2 ? by : by * FA + ca - (D == 1 ? 3 : 0);
-            const int ck = D == 2 ? (int)blockIdx.z * FA + ca - 3 : (int)blockIdx.z;
+            const int ck = D == 2 ? bz * FA + ca - 3 : bz;
             double qc[5];
             cell_state(K, Q, step, x0 + cx, cj, ck, qc);   // (ghosts resolved by the boundary rules)
 #pragma unroll
@@ -425,7 +438,7 @@ __global__ __launch_bounds__(BX * BY) void k_faces3d(const KConst* __restrict__ 
         for (int c = threadIdx.x; c < TA * TX; c += BX * BY) {
             const int ca = c / TX, cx = c - ca * TX;
             const int cj = D == 2 ? by : by * FA + ca - (D == 1 ? 3 : 0);
-            const int ck = D == 2 ? (int)blockIdx.z * FA + ca - 3 : (int)blockIdx.z;
+            const int ck = D == 2 ? bz * FA + ca - 3 : bz;
             double qc[5], p, ud;
             T fpc[5], fmc[5];
             cell_state(K, Q, step, x0 + cx, cj, ck, qc);   // (ghosts resolved by the boundary rules)
