@@ -640,9 +640,8 @@ __global__ __launch_bounds__(BX * BY) void k_stage3d(const KConst* __restrict__ 
         }
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            // (the FP64 method's output streams past the caches like its buffers)
-            if constexpr (std::is_same<T, double>::value) __builtin_nontemporal_store(val[c], &A.out[c * G.ncell + o]);
-            else A.out[c * G.ncell + o] = val[c];
+            // (the output state streams past the caches: far larger than they are)
+            __builtin_nontemporal_store(val[c], &A.out[c * G.ncell + o]);
         }
         if (A.alpha_part && k >= A.arow0 && k < A.arow1) {
             const double ir = rcp_nr(val[0]);
